@@ -1,0 +1,173 @@
+/*
+ * pswfe — PSWF fast Ewald summation, long-range (Fourier-space) part, for AMD MI355X (gfx950).
+ *
+ * Method: Bostrom, Tornberg, af Klinteberg, "Fast Ewald summation using prolate spheroidal
+ * wave functions" (arXiv 2602.16591). The library evaluates, for n point charges rho_j at
+ * positions x_j in the periodic box [0, L)^3 (Sec. 2.1; charge neutral, Sec. 1),
+ *
+ *   phi_i = phi_i^far + phi_i^self         (Sec. 3.1; the real-space residual phi^local is
+ *                                           not part of this library)
+ *   F_i   = -rho_i grad phi_i^far          (Remark in Sec. 3.1, eq. force)
+ *   E     = 1/2 sum_i rho_i phi_i          (Remark in Sec. 3.1)
+ *
+ * with phi^far computed by the fast Fourier-space summation of Alg. 2 using the PSWF mollifier
+ * (Sec. 4.2) and the PSWF window (Sec. 4.3), and parameters from Alg. 3 (Sec. 6).
+ * Units: no Coulomb constant (Sec. 1, eq. potential1); phi is charge / length.
+ *
+ * Conventions for every entry point
+ *  - Return value: a pswfe_status; nothing is thrown across this interface.
+ *  - "device" pointers are HIP device allocations (or managed memory) owned by the caller;
+ *    the library never frees them. "host" pointers are ordinary CPU memory.
+ *  - Floating-point arrays are in the plan's precision: float for PSWFE_FP32, double for
+ *    PSWFE_FP64. The energy is always a double.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream). Every compute
+ *    entry point only enqueues work: it performs no allocation and no host synchronisation,
+ *    so it may be captured into a HIP graph. Calls on one plan must not overlap in time
+ *    (a plan owns one set of work buffers).
+ */
+#ifndef PSWFE_H
+#define PSWFE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PSWFE_OK = 0,
+  PSWFE_E_ARG = 1,        /* null pointer, n < 0, L <= 0, bad enum value, rc >= L/2 ...   */
+  PSWFE_E_EPS_RANGE = 2,  /* eps outside [1e-14, 0.1], or c_s / c_w beyond the PSWF range  */
+  PSWFE_E_GRID = 3,       /* m not an even 2,3,5,7-smooth size in [8, 512], or P > m, P > 32 */
+  PSWFE_E_ALLOC = 4,      /* device allocation failed (plan creation only)                 */
+  PSWFE_E_HIP = 5,        /* a HIP runtime call or kernel launch failed                    */
+  PSWFE_E_CAPACITY = 6,   /* n larger than the plan's n_max                                */
+  PSWFE_E_PREC = 7        /* unknown precision                                             */
+} pswfe_status;
+
+typedef enum {
+  PSWFE_TOL_REL = 0,      /* c_s = log(1/eps): relative error target (Sec. 6.2.1)           */
+  PSWFE_TOL_ABS = 1       /* c_s = W0(2 (B_s/eps)^2)/2: absolute RMS target (eq. cs_dimless) */
+} pswfe_tolmode;
+
+typedef enum { PSWFE_FP32 = 0, PSWFE_FP64 = 1 } pswfe_prec;
+
+/* Method parameters (Alg. 3). The first block is what the kernels use; the *_alg fields are
+ * the unrounded results of Alg. 3 steps 1-3, kept for reference. */
+typedef struct {
+  double L;          /* box side                                                           */
+  double eps;        /* requested tolerance                                                */
+  double rc;         /* cutoff radius = support of the mollifier (Sec. 4.2)                 */
+  double cs;         /* mollifier bandlimit, = pi rc m / L (eq. csrc)                        */
+  double cw;         /* window bandlimit,    = pi P / 2   (eq. cwP)                          */
+  double alpha;      /* window half width,   = P h / 2   (Sec. 6.3)                          */
+  double h;          /* grid spacing L / m                                                  */
+  double lambda0_s;  /* lambda_0(c_s), for the self term -2 rho / (rc lambda_0) (Sec. 3.1)  */
+  double cs_alg, cw_alg, alpha_alg;
+  int32_t m;         /* grid points per dimension (even, 2,3,5,7-smooth)                    */
+  int32_t P;         /* window support in grid points per dimension                         */
+  int32_t tol_mode;  /* pswfe_tolmode                                                       */
+  int32_t reserved;
+} pswfe_params;
+
+typedef struct pswfe_plan pswfe_plan;
+
+/* Alg. 3 (Sec. 6.4) with these readings: the W_{-1} branch for c_w; m rounded up to an even
+ * size with prime factors 2, 3, 5, 7; P from the final m; the kernels then use c_s = pi rc m/L,
+ * c_w = pi P / 2, alpha = P h / 2; A_s = 5 and A_s/A_w = 4 sqrt(5) / pi^{3/2}.
+ *   eps       tolerance, 1e-14 <= eps <= 0.1
+ *   L         box side (> 0)
+ *   rc        cutoff radius; <= 0 selects it from m (if m > 0) or else from n (64 neighbours)
+ *   m         prescribed grid size, or 0 to let Alg. 3 choose it
+ *   n         number of particles (used only by the default rc rule)
+ *   q_l2      ||rho||_2 (PSWFE_TOL_ABS only)
+ *   tol_mode  pswfe_tolmode
+ *   out       host pointer, written on success
+ * Host only; touches no GPU. */
+pswfe_status pswfe_choose_params(double eps, double L, double rc, int32_t m, int64_t n, double q_l2,
+                                 int32_t tol_mode, pswfe_params* out);
+
+/* Creates a plan: precomputes in float64 on the host the PSWF Legendre coefficients (App. B),
+ * the k-space scaling tables (eq. diag_scale, eq. MhatPSWF, Table 2), the piecewise-polynomial
+ * window (Remark after eq. force) and the FFT twiddles; allocates the device work buffers
+ * (grid, spectrum, particle bins) for up to n_max particles on the current HIP device.
+ *   p      host pointer to parameters (from pswfe_choose_params, or filled by the caller)
+ *   prec   pswfe_prec
+ *   n_max  largest n accepted by pswfe_compute (>= 0)
+ *   out    host pointer receiving the plan; NULL on failure. */
+pswfe_status pswfe_plan_create(const pswfe_params* p, int32_t prec, int64_t n_max, pswfe_plan** out);
+
+/* Frees the plan and its device buffers (synchronises the device first). NULL is a no-op. */
+pswfe_status pswfe_plan_destroy(pswfe_plan* plan);
+
+/* Full Alg. 2 plus self term and energy, in one stream:
+ *   pos     device, n x 3 (row-major x, y, z), any real values (wrapped mod L)
+ *   q       device, n charges (should sum to zero: the k = 0 mode is dropped, Sec. 3.1.2)
+ *   phi     device, n outputs phi_far + phi_self, or NULL to skip
+ *   force   device, n x 3 outputs -rho_i grad phi_far, or NULL to skip
+ *   energy  device, one double: 1/2 sum rho_i (phi_far + phi_self), or NULL to skip
+ *   stream  hipStream_t or NULL
+ * Outputs are in input order. n = 0 writes energy 0 and nothing else. */
+pswfe_status pswfe_compute(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi,
+                           void* force, double* energy, void* stream);
+
+/* As pswfe_compute, but `grad` receives grad phi_far (n x 3, not multiplied by -rho): the
+ * field needed by adjoints of losses that depend on phi (a second apply with charges g gives
+ * A g, and d/dx_i of g^T A q = g_i grad phi_i[q] + q_i grad phi_i[g], A symmetric, eq. matform). */
+pswfe_status pswfe_compute_grad(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi,
+                                void* grad, double* energy, void* stream);
+
+/* Alg. 2 step 1 alone (eq. spread_def): grid[(lz*m + ly)*m + lx] = sum_j q_j
+ * phitilde(x_j - h l) for the m^3 grid points, written to the device array `grid`
+ * (plan precision, m^3 entries, z slowest). */
+pswfe_status pswfe_spread(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* grid,
+                          void* stream);
+
+/* Alg. 2 steps 2-4 alone: b = F^{-1} C D F a (eq. matform) from the device grid `grid_in` to
+ * the device grid `grid_out` (both m^3, z slowest; may alias). */
+pswfe_status pswfe_transform(pswfe_plan* plan, const void* grid_in, void* grid_out, void* stream);
+
+/* Alg. 2 step 5 alone (eq. FastEwaldSteps34, eq. force) from the device grid `grid` (m^3):
+ * phi = interpolated values (no self term), grad = device n x 3 gradients; either may be NULL. */
+pswfe_status pswfe_interpolate(pswfe_plan* plan, int64_t n, const void* pos, const void* grid,
+                               void* phi, void* grad, void* stream);
+
+/* Host-only views of the float64 precompute, for verification (no GPU needed).
+ * pswfe_host_pswf: psi_0^c(x), d/dx psi_0^c(x) for |x| <= 1, lambda_0(c) and chi_0(c) (App. B);
+ *   any output pointer may be NULL.
+ * pswfe_host_tables: for parameters p and precision prec, fills (each may be NULL)
+ *   tm[0 .. 3(m/2)^2]   radial scaling T_M[|k|^2] = h^6 Mhat(k) / V in the band, 0 outside and at 0,
+ *   w[0 .. m/2]         1 / phihat_1(2 pi k / L)^2,
+ *   coef[0 .. P(deg+1)) window polynomial coefficients (piece j, power k at j*(deg+1)+k),
+ *   info[0..3]          deg, max fit error, max fit error of the derivative, self coefficient
+ *                       2 / (rc lambda_0(c_s));
+ *   the *_len arguments give the capacity of each array (in doubles); too small -> PSWFE_E_ARG. */
+pswfe_status pswfe_host_pswf(double c, double x, double* psi, double* dpsi, double* lambda0, double* chi0);
+pswfe_status pswfe_host_tables(const pswfe_params* p, int32_t prec, double* tm, int64_t tm_len, double* w,
+                               int64_t w_len, double* coef, int64_t coef_len, double* info);
+
+/* Instrumentation (not for hot loops): records a pair of HIP events on the compute stream
+ * around one pipeline stage of each following call on this plan, for up to max_calls calls.
+ *   stage: 0 binning, 1 spreading, 2 x R2C FFT, 3 y FFT, 4 z FFT + scaling + inverse z FFT,
+ *          5 inverse y FFT, 6 x C2R FFT, 7 interpolation, 8 the whole compute call; -1 turns
+ *          timing off and frees the events.
+ * pswfe_timing_enable synchronises the device and creates the events (host allocation).
+ * pswfe_timing_read waits for the last recorded event and returns the summed elapsed time (ms)
+ * and the number of timed calls since enable or the previous read, then resets the count. */
+pswfe_status pswfe_timing_enable(pswfe_plan* plan, int32_t stage, int32_t max_calls);
+pswfe_status pswfe_timing_read(pswfe_plan* plan, double* total_ms, int64_t* calls);
+
+/* Effective parameters of a plan (host copy). */
+pswfe_status pswfe_plan_params(const pswfe_plan* plan, pswfe_params* out);
+
+/* Static description of a string for a status code (never NULL). */
+const char* pswfe_status_str(pswfe_status s);
+
+/* Library version string, e.g. "pswfe 0.1 gfx950". */
+const char* pswfe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSWFE_H */

@@ -1,0 +1,266 @@
+"""pswfe: PSWF fast Ewald summation (long-range part) on AMD MI355X.
+
+Thin ctypes binding of the C-ABI declared in ``include/pswfe.h``; every step of the
+computation runs in the HIP library ``_lib/libpswfe.so``. PyTorch supplies device memory and
+streams only. There is no CPU fallback: without the built library, or with tensors that are
+not on a HIP device, calls raise.
+
+Method: Bostrom, Tornberg, af Klinteberg, arXiv 2602.16591 (Alg. 2 fast Fourier-space sum,
+Sec. 4 PSWF mollifier and window, Alg. 3 parameter selection).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libpswfe.so")
+
+OK, E_ARG, E_EPS_RANGE, E_GRID, E_ALLOC, E_HIP, E_CAPACITY, E_PREC = range(8)
+TOL_REL, TOL_ABS = 0, 1
+FP32, FP64 = 0, 1
+
+
+class PswfeError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {_lib().pswfe_status_str(status).decode()} (status {status})")
+
+
+class CParams(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_double), ("eps", ctypes.c_double), ("rc", ctypes.c_double),
+                ("cs", ctypes.c_double), ("cw", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("h", ctypes.c_double), ("lambda0_s", ctypes.c_double), ("cs_alg", ctypes.c_double),
+                ("cw_alg", ctypes.c_double), ("alpha_alg", ctypes.c_double), ("m", ctypes.c_int32),
+                ("P", ctypes.c_int32), ("tol_mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+# name -> (restype, argtypes); every symbol declared in include/pswfe.h
+_vp, _i64, _i32, _d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+_PPlan = ctypes.POINTER(ctypes.c_void_p)
+SIGNATURES = {
+    "pswfe_choose_params": (ctypes.c_int, [_d, _d, _d, _i32, _i64, _d, _i32, ctypes.POINTER(CParams)]),
+    "pswfe_plan_create": (ctypes.c_int, [ctypes.POINTER(CParams), _i32, _i64, _PPlan]),
+    "pswfe_plan_destroy": (ctypes.c_int, [_vp]),
+    "pswfe_compute": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "pswfe_compute_grad": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "pswfe_spread": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp]),
+    "pswfe_transform": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "pswfe_interpolate": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp]),
+    "pswfe_plan_params": (ctypes.c_int, [_vp, ctypes.POINTER(CParams)]),
+    "pswfe_host_pswf": (ctypes.c_int, [_d, _d, _vp, _vp, _vp, _vp]),
+    "pswfe_host_tables": (ctypes.c_int, [ctypes.POINTER(CParams), _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp]),
+    "pswfe_timing_enable": (ctypes.c_int, [_vp, _i32, _i32]),
+    "pswfe_timing_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "pswfe_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "pswfe_version": (ctypes.c_char_p, []),
+}
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2602_16591_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        raise PswfeError(status, where)
+
+
+def version() -> str:
+    return _lib().pswfe_version().decode()
+
+
+def choose_params(eps: float, L: float, *, rc: float = 0.0, m: int = 0, n: int = 0, q_l2: float = 0.0,
+                  tol_mode: int | str = TOL_REL) -> CParams:
+    """Alg. 3 parameters (host only)."""
+    mode = {"rel": TOL_REL, "abs": TOL_ABS}.get(tol_mode, tol_mode)
+    out = CParams()
+    _check(_lib().pswfe_choose_params(float(eps), float(L), float(rc), int(m), int(n), float(q_l2), int(mode),
+                                      ctypes.byref(out)), "pswfe_choose_params")
+    return out
+
+
+def host_pswf(c: float, x: float):
+    """(psi_0^c(x), psi_0^c'(x), lambda_0(c), chi_0(c)) from the library's float64 host code."""
+    out = (ctypes.c_double * 4)()
+    a = ctypes.addressof(out)
+    _check(_lib().pswfe_host_pswf(float(c), float(x), a, a + 8, a + 16, a + 24), "pswfe_host_pswf")
+    return tuple(out)
+
+
+def host_tables(params: CParams, prec: int | str = FP32):
+    """The plan's float64 host tables: dict(tm, w, coef (P, deg+1), deg, fit_err, fit_err_deriv, self_coef)."""
+    import numpy as np
+    prec = {"fp32": FP32, "fp64": FP64}.get(prec, prec)
+    m, P = params.m, params.P
+    tm = np.zeros(3 * (m // 2) ** 2 + 1)
+    w = np.zeros(m // 2 + 1)
+    coef = np.zeros(P * 40)
+    info = np.zeros(4)
+    _check(_lib().pswfe_host_tables(ctypes.byref(params), int(prec), tm.ctypes.data, tm.size, w.ctypes.data, w.size,
+                                    coef.ctypes.data, coef.size, info.ctypes.data), "pswfe_host_tables")
+    deg = int(info[0])
+    return dict(tm=tm, w=w, coef=coef[:P * (deg + 1)].reshape(P, deg + 1), deg=deg, fit_err=info[1],
+                fit_err_deriv=info[2], self_coef=info[3])
+
+
+def _ptr(t, dtype, shape_tail, name):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a torch tensor on a HIP device")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(t.shape[1:]) != shape_tail:
+        raise ValueError(f"{name} must have shape (n, {', '.join(map(str, shape_tail))})")
+    return t.data_ptr()
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """Device plan for one parameter set, precision and maximum particle count."""
+
+    def __init__(self, params: CParams, prec: int | str = FP32, n_max: int = 0):
+        import torch
+        self.prec = {"fp32": FP32, "fp64": FP64}.get(prec, prec)
+        self.dtype = torch.float32 if self.prec == FP32 else torch.float64
+        self.n_max = int(n_max)
+        self._h = ctypes.c_void_p()
+        _check(_lib().pswfe_plan_create(ctypes.byref(params), int(self.prec), self.n_max, ctypes.byref(self._h)),
+               "pswfe_plan_create")
+        p = CParams()
+        _check(_lib().pswfe_plan_params(self._h, ctypes.byref(p)), "pswfe_plan_params")
+        self.params = p
+
+    @property
+    def m(self) -> int:
+        return self.params.m
+
+    def close(self):
+        if self._h:
+            _lib().pswfe_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    STAGES = {"bin": 0, "spread": 1, "fft_x": 2, "fft_y": 3, "fft_z_scale": 4, "ifft_y": 5, "ifft_x": 6,
+              "gather": 7, "all": 8}
+
+    def timing_enable(self, stage: str | int | None, max_calls: int = 4096):
+        """Record HIP events around one pipeline stage of the following calls (None: off)."""
+        st = -1 if stage is None else self.STAGES.get(stage, stage)
+        _check(_lib().pswfe_timing_enable(self._h, int(st), int(max_calls)), "pswfe_timing_enable")
+
+    def timing_read(self):
+        """(total milliseconds, number of timed calls) since enable or the last read."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(_lib().pswfe_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)), "pswfe_timing_read")
+        return ms.value, n.value
+
+    def _n(self, pos):
+        n = int(pos.shape[0])
+        if n > self.n_max:
+            raise ValueError(f"n = {n} exceeds the plan's n_max = {self.n_max}")
+        return n
+
+    def compute(self, pos, q, *, phi=True, force=True, energy=True, grad=False, stream=None):
+        """phi_far + phi_self, forces -q grad phi_far (or grad phi_far with grad=True), energy.
+
+        Returns (phi, vec, energy) with None for outputs not requested; outputs are new tensors
+        unless tensors are passed in place of True."""
+        import torch
+        n = self._n(pos)
+        dev = pos.device
+        def out(spec, shape, dtype):
+            if isinstance(spec, torch.Tensor):
+                return spec
+            return torch.empty(shape, dtype=dtype, device=dev) if spec else None
+
+        phi_t = out(phi, (n,), self.dtype)
+        vec_t = out(force if not grad else grad, (n, 3), self.dtype)
+        e_t = out(energy, (1,), torch.float64)
+        fn = _lib().pswfe_compute_grad if grad else _lib().pswfe_compute
+        _check(fn(self._h, n, _ptr(pos, self.dtype, (3,), "pos"), _ptr(q, self.dtype, None, "q"),
+                  _ptr(phi_t, self.dtype, None, "phi"), _ptr(vec_t, self.dtype, (3,), "force"),
+                  _ptr(e_t, torch.float64, None, "energy"), _stream_ptr(stream)), "pswfe_compute")
+        return phi_t, vec_t, e_t
+
+    def spread(self, pos, q, grid=None, stream=None):
+        import torch
+        n = self._n(pos)
+        m = self.m
+        grid = torch.empty((m, m, m), dtype=self.dtype, device=pos.device) if grid is None else grid
+        _check(_lib().pswfe_spread(self._h, n, _ptr(pos, self.dtype, (3,), "pos"), _ptr(q, self.dtype, None, "q"),
+                                   _ptr(grid, self.dtype, None, "grid"), _stream_ptr(stream)), "pswfe_spread")
+        return grid
+
+    def transform(self, grid_in, grid_out=None, stream=None):
+        import torch
+        grid_out = torch.empty_like(grid_in) if grid_out is None else grid_out
+        if grid_in.numel() != self.m ** 3 or grid_out.numel() != self.m ** 3:
+            raise ValueError("grids must have m^3 entries")
+        _check(_lib().pswfe_transform(self._h, _ptr(grid_in, self.dtype, None, "grid_in"),
+                                      _ptr(grid_out, self.dtype, None, "grid_out"), _stream_ptr(stream)),
+               "pswfe_transform")
+        return grid_out
+
+    def interpolate(self, pos, grid, stream=None):
+        import torch
+        n = self._n(pos)
+        if grid.numel() != self.m ** 3:
+            raise ValueError("grid must have m^3 entries")
+        phi = torch.empty(n, dtype=self.dtype, device=pos.device)
+        g = torch.empty((n, 3), dtype=self.dtype, device=pos.device)
+        _check(_lib().pswfe_interpolate(self._h, n, _ptr(pos, self.dtype, (3,), "pos"),
+                                        _ptr(grid, self.dtype, None, "grid"), _ptr(phi, self.dtype, None, "phi"),
+                                        _ptr(g, self.dtype, (3,), "grad"), _stream_ptr(stream)), "pswfe_interpolate")
+        return phi, g
+
+
+@dataclass
+class LongRange:
+    """Convenience: choose parameters and build a plan for a given system shape."""
+    eps: float
+    L: float
+    n_max: int
+    prec: str = "fp32"
+    m: int = 0
+    rc: float = 0.0
+    tol_mode: str = "rel"
+    q_l2: float = 0.0
+
+    def __post_init__(self):
+        self.params = choose_params(self.eps, self.L, rc=self.rc, m=self.m, n=self.n_max, q_l2=self.q_l2,
+                                    tol_mode=self.tol_mode)
+        self.plan = Plan(self.params, self.prec, self.n_max)
+
+    def __call__(self, pos, q, **kw):
+        return self.plan.compute(pos, q, **kw)

@@ -1,0 +1,364 @@
+// Host float64 precompute: PSWF (App. B), Lambert W, Alg. 3, scaling and window tables.
+#include "host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+namespace pswfe {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Number of eigenvalues of the symmetric tridiagonal matrix (diag d, off-diagonal e) below x
+// (Sturm sequence count from the LDL^T pivots).
+int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (q < 0) ++cnt;
+  for (size_t i = 1; i < d.size(); ++i) {
+    if (q == 0.0) q = std::numeric_limits<double>::min();
+    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+// Solves (T - shift I) y = b in place for a symmetric tridiagonal T, Gaussian elimination
+// with partial pivoting (row interchanges create one extra superdiagonal).
+void tridiag_solve(const std::vector<double>& diag, const std::vector<double>& off, double shift,
+                   std::vector<double>* rhs) {
+  const int n = static_cast<int>(diag.size());
+  std::vector<double> dl(off), du(off), d(n), du2(std::max(n - 2, 0), 0.0);
+  std::vector<double>& b = *rhs;
+  const double tiny = 1e-300;
+  for (int i = 0; i < n; ++i) d[i] = diag[i] - shift;
+  for (int i = 0; i < n - 1; ++i) {
+    if (std::fabs(d[i]) >= std::fabs(dl[i])) {
+      if (d[i] == 0.0) d[i] = tiny;
+      const double f = dl[i] / d[i];
+      d[i + 1] -= f * du[i];
+      b[i + 1] -= f * b[i];
+    } else {
+      const double f = d[i] / dl[i];
+      d[i] = dl[i];
+      const double t = d[i + 1];
+      d[i + 1] = du[i] - f * t;
+      if (i < n - 2) {
+        du2[i] = du[i + 1];
+        du[i + 1] = -f * du2[i];
+      }
+      du[i] = t;
+      const double tb = b[i];
+      b[i] = b[i + 1];
+      b[i + 1] = tb - f * b[i + 1];
+    }
+  }
+  if (d[n - 1] == 0.0) d[n - 1] = tiny;
+  b[n - 1] /= d[n - 1];
+  if (n > 1) b[n - 2] = (b[n - 2] - du[n - 2] * b[n - 1]) / d[n - 2];
+  for (int i = n - 3; i >= 0; --i) b[i] = (b[i] - du[i] * b[i + 1] - du2[i] * b[i + 2]) / d[i];
+}
+
+}  // namespace
+
+Pswf::Pswf(double c_) : c(c_) {
+  const int K = std::max(40, static_cast<int>(1.5 * c) + 30);
+  std::vector<double> d(K), e(K - 1);
+  const double c2 = c * c;
+  for (int i = 0; i < K; ++i) {
+    const double n = 2.0 * i;
+    d[i] = n * (n + 1.0) + c2 * (2.0 * n * (n + 1.0) - 1.0) / ((2.0 * n + 3.0) * (2.0 * n - 1.0));
+    if (i < K - 1)
+      e[i] = c2 * (n + 1.0) * (n + 2.0) / ((2.0 * n + 3.0) * std::sqrt((2.0 * n + 1.0) * (2.0 * n + 5.0)));
+  }
+  // Gershgorin interval, then bisection on the Sturm count for the smallest eigenvalue.
+  double lo = d[0] - std::fabs(e[0]), hi = d[0] + std::fabs(e[0]);
+  for (int i = 1; i < K; ++i) {
+    const double r = std::fabs(e[i - 1]) + (i < K - 1 ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_count(d, e, mid) >= 1) hi = mid; else lo = mid;
+  }
+  chi0 = 0.5 * (lo + hi);
+  // Inverse iteration for the eigenvector (orthonormal Legendre basis).
+  std::vector<double> v(K, 1.0);
+  for (int it = 0; it < 4; ++it) {
+    tridiag_solve(d, e, chi0, &v);
+    double nrm = 0.0;
+    for (double x : v) nrm += x * x;
+    nrm = std::sqrt(nrm);
+    for (double& x : v) x /= nrm;
+  }
+  a.resize(K);
+  for (int i = 0; i < K; ++i) a[i] = v[i] * std::sqrt(2.0 * i + 0.5);  // Pbar_n = sqrt(n+1/2) P_n
+  psi_0 = psi(0.0);
+  if (psi_0 < 0) {
+    for (double& x : a) x = -x;
+    psi_0 = -psi_0;
+  }
+  psi_1 = psi(1.0);
+  lambda0 = 2.0 * a[0] / psi_0;  // int_{-1}^{1} P_0 = 2, other P_n integrate to 0
+}
+
+double Pswf::psi(double x) const {
+  // Legendre three-term recurrence, summing the even degrees.
+  double p0 = 1.0, p1 = x, s = a[0];
+  const int nmax = 2 * static_cast<int>(a.size()) - 2;
+  for (int n = 1; n < nmax; ++n) {
+    const double p2 = ((2.0 * n + 1.0) * x * p1 - n * p0) / (n + 1.0);
+    p0 = p1;
+    p1 = p2;
+    if ((n + 1) % 2 == 0) s += a[(n + 1) / 2] * p1;
+  }
+  return s;
+}
+
+double Pswf::dpsi(double x) const {
+  // P'_{n+1} = P'_{n-1} + (2n+1) P_n
+  double p0 = 1.0, p1 = x, d0 = 0.0, d1 = 1.0, s = 0.0;
+  const int nmax = 2 * static_cast<int>(a.size()) - 2;
+  for (int n = 1; n < nmax; ++n) {
+    const double p2 = ((2.0 * n + 1.0) * x * p1 - n * p0) / (n + 1.0);
+    const double d2 = d0 + (2.0 * n + 1.0) * p1;
+    p0 = p1;
+    p1 = p2;
+    d0 = d1;
+    d1 = d2;
+    if ((n + 1) % 2 == 0) s += a[(n + 1) / 2] * d1;
+  }
+  return s;
+}
+
+// Halley iteration on f(w) = w e^w - x.
+static double halley_w(double x, double w) {
+  for (int it = 0; it < 100; ++it) {
+    const double ew = std::exp(w);
+    const double f = w * ew - x;
+    const double fp = ew * (w + 1.0);
+    const double dw = f / (fp - (w + 2.0) * f / (2.0 * w + 2.0));
+    w -= dw;
+    if (std::fabs(dw) <= 1e-15 * (1.0 + std::fabs(w))) break;
+  }
+  return w;
+}
+
+double lambert_w0(double x) {
+  if (x == 0.0) return 0.0;
+  double w = x < 1.0 ? std::log1p(x) : std::log(x) - std::log(std::max(std::log(x), 1e-3));
+  if (x < -0.25) w = -1.0 + std::sqrt(2.0 * (1.0 + std::exp(1.0) * x));
+  return halley_w(x, w);
+}
+
+double lambert_wm1(double x) {
+  double w;
+  if (x > -0.25) {
+    const double l1 = std::log(-x);
+    w = l1 - std::log(-l1);
+  } else {
+    w = -1.0 - std::sqrt(std::max(0.0, 2.0 * (1.0 + std::exp(1.0) * x)));
+  }
+  return halley_w(x, w);
+}
+
+bool is_smooth_even(int m) {
+  if (m < 2 || (m & 1)) return false;
+  for (int p : {2, 3, 5, 7})
+    while (m % p == 0) m /= p;
+  return m == 1;
+}
+
+int next_smooth_even(int m) {
+  m = std::max(m, 2);
+  while (!is_smooth_even(m)) ++m;
+  return m;
+}
+
+namespace {
+constexpr double kAs = 5.0;  // split-model prefactor (Sec. 5.1.1)
+double as_over_aw() { return 4.0 * std::sqrt(5.0) / std::pow(kPi, 1.5); }  // Sec. 6.3
+
+double cs_of(double eps, double L, double rc, double q_l2, int tol_mode) {
+  if (tol_mode == 0) return std::log(1.0 / eps);
+  const double Bs = kAs * q_l2 * std::sqrt(rc) / std::sqrt(L * L * L);  // eq. cs_dimless
+  const double r = Bs / eps;
+  return 0.5 * lambert_w0(2.0 * r * r);
+}
+}  // namespace
+
+int choose_params(double eps, double L, double rc, int m, int64_t n, double q_l2, int tol_mode,
+                  Params* out) {
+  if (!out || !(L > 0.0) || !std::isfinite(L) || (tol_mode != 0 && tol_mode != 1)) return 1;
+  if (!(eps >= 1e-14 && eps <= 0.1)) return 2;
+  if (tol_mode == 1 && !(q_l2 > 0.0 && std::isfinite(q_l2))) return 1;
+  if (m > 0 && (!is_smooth_even(m) || m < 8 || m > 512)) return 3;
+  if (!(rc > 0.0)) {
+    if (m > 0) {
+      // eq. csrc solved for r_c at the prescribed m (fixed point: c_s depends on r_c in abs mode)
+      rc = L * std::log(1.0 / eps) / (kPi * m);
+      for (int it = 0; it < 200; ++it) {
+        const double r2 = L * cs_of(eps, L, rc, q_l2, tol_mode) / (kPi * m);
+        const bool done = std::fabs(r2 - rc) <= 1e-15 * rc;
+        rc = r2;
+        if (done) break;
+      }
+    } else {
+      if (n <= 0) return 1;
+      rc = L * std::cbrt(3.0 * 64.0 / (4.0 * kPi * static_cast<double>(n)));  // 64 neighbours
+    }
+  }
+  if (!(rc > 0.0) || !std::isfinite(rc)) return 1;
+  const double cs = cs_of(eps, L, rc, q_l2, tol_mode);                       // Alg. 3 step 1
+  const double Bw = as_over_aw() * std::sqrt(rc / L);
+  const double arg = -2.0 * Bw * Bw * std::exp(-2.0 * cs) / cs;
+  if (!(arg > -1.0 / std::exp(1.0) && arg < 0.0)) return 2;
+  const double cw = -0.5 * lambert_wm1(arg);                                  // step 2
+  const double alpha = rc * cw / cs;                                          // step 3
+  const int m_alg = static_cast<int>(std::ceil(L * cs / (kPi * rc) - 1e-9));  // step 4
+  int mm = m;
+  if (mm > 0) {
+    if (m_alg > mm) return 3;
+  } else {
+    mm = next_smooth_even(std::max(m_alg, 8));
+    if (mm > 512) return 3;
+  }
+  const int P = static_cast<int>(std::ceil(2.0 * alpha * mm / L - 1e-9));     // step 5
+  if (P < 2 || P > 32 || P > mm) return 3;
+  const double h = L / mm;
+  Params p{};
+  p.L = L;
+  p.eps = eps;
+  p.rc = rc;
+  p.cs = kPi * rc * mm / L;
+  p.cw = kPi * P / 2.0;
+  p.alpha = P * h / 2.0;
+  p.h = h;
+  p.cs_alg = cs;
+  p.cw_alg = cw;
+  p.alpha_alg = alpha;
+  p.m = mm;
+  p.P = P;
+  p.tol_mode = tol_mode;
+  if (p.cs > 40.0 || p.cw > 40.0) return 2;  // PSWF evaluation reaches machine precision (App. A)
+  p.lambda0_s = Pswf(p.cs).lambda0;
+  *out = p;
+  return 0;
+}
+
+namespace {
+
+// Chebyshev interpolation of f on [-1/2, 1/2] at deg+1 first-kind nodes, returned as monomial
+// coefficients in g (long double throughout).
+template <class F>
+std::vector<long double> cheb_fit_monomial(F f, int deg) {
+  const int N = deg + 1;
+  std::vector<long double> fx(N), ck(N, 0.0L);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < N; ++i) {
+    const long double th = pi * (i + 0.5L) / N;
+    fx[i] = f(0.5L * std::cos(th));
+  }
+  for (int k = 0; k < N; ++k) {
+    long double s = 0.0L;
+    for (int i = 0; i < N; ++i) s += fx[i] * std::cos(pi * k * (i + 0.5L) / N);
+    ck[k] = (k == 0 ? 1.0L : 2.0L) * s / N;
+  }
+  // sum_k ck T_k(2g): build T_k(2g) monomial coefficients by T_{k+1} = 4g T_k - T_{k-1}.
+  std::vector<long double> out(N, 0.0L), t0(N, 0.0L), t1(N, 0.0L), t2(N, 0.0L);
+  t0[0] = 1.0L;
+  if (N > 1) t1[1] = 2.0L;
+  for (int i = 0; i < N; ++i) out[i] += ck[0] * t0[i];
+  if (N > 1)
+    for (int i = 0; i < N; ++i) out[i] += ck[1] * t1[i];
+  for (int k = 2; k < N; ++k) {
+    for (int i = 0; i < N; ++i) t2[i] = (i > 0 ? 4.0L * t1[i - 1] : 0.0L) - t0[i];
+    for (int i = 0; i < N; ++i) out[i] += ck[k] * t2[i];
+    t0.swap(t1);
+    t1.swap(t2);
+  }
+  return out;
+}
+
+}  // namespace
+
+void build_tables(const Params& p, int deg, double fit_tol, Tables* t) {
+  const int m = p.m, P = p.P, half = m / 2;
+  const double L = p.L, h = p.h, V = L * L * L;
+  const Pswf ps(p.cs), pw(p.cw);
+  // Radial part of the scaling, T_M[k2] = h^6 Mhat(k) / V with Mhat(k) = L^2 gammahat / (pi |k|^2)
+  // (eq. Fsum) and gammahat(w) = psi_0^{cs}(r_c w / c_s) / psi_0^{cs}(0) in band
+  // (eq. PSWF_mollifier_ft); zero outside the band (|w| > c_s / r_c) and at k = 0.
+  const int k2max = 3 * half * half;
+  const double kband = p.cs * L / (2.0 * kPi * p.rc);
+  const double h6 = std::pow(h, 6);
+  t->tm.assign(k2max + 1, 0.0);
+  for (int k2 = 1; k2 <= k2max; ++k2) {
+    const double k = std::sqrt(static_cast<double>(k2));
+    if (k > kband * (1.0 + 1e-12)) continue;
+    const double s = std::min(1.0, p.rc * 2.0 * kPi * k / L / p.cs);
+    const double gh = ps.psi(s) / ps.psi_0;
+    t->tm[k2] = h6 / V * L * L / (kPi * k2) * gh;
+  }
+  // Window factor W[k] = 1 / phihat_1(2 pi k / L)^2, phihat_1(w) = alpha lambda_0 psi(alpha w/c_w)/psi(0)
+  // (Table 2), with alpha w / c_w = 2k/m.
+  t->w.assign(half + 1, 0.0);
+  for (int k = 0; k <= half; ++k) {
+    const double ph = p.alpha * pw.lambda0 * pw.psi(2.0 * k / m) / pw.psi_0;
+    t->w[k] = 1.0 / (ph * ph);
+  }
+  t->self_coef = 2.0 / (p.rc * ps.lambda0);
+  // Piecewise-polynomial window (Remark after eq. force): one polynomial per support point.
+  auto piece = [&](int j, long double g) -> long double {
+    const double s = 2.0 * (static_cast<double>(g) + 0.5 * (P - 1) - j) / P;
+    return static_cast<long double>(pw.psi(std::max(-1.0, std::min(1.0, s))) / pw.psi_0);
+  };
+  auto piece_d = [&](int j, double g) -> double {  // d/dg of phi_1(2(g + (P-1)/2 - j)/P)
+    const double s = 2.0 * (g + 0.5 * (P - 1) - j) / P;
+    return pw.dpsi(std::max(-1.0, std::min(1.0, s))) / pw.psi_0 * 2.0 / P;
+  };
+  double dmax = 0.0;
+  for (int j = 0; j < P; ++j)
+    for (int i = 0; i <= 32; ++i) dmax = std::max(dmax, std::fabs(piece_d(j, -0.5 + i / 32.0)));
+  const int dlo = deg > 0 ? deg : 4, dhi = deg > 0 ? deg : 28;
+  for (int dg = dlo; dg <= dhi; ++dg) {
+    std::vector<double> coef(static_cast<size_t>(P) * (dg + 1));
+    for (int j = 0; j < P; ++j) {
+      auto c = cheb_fit_monomial([&](long double g) { return piece(j, g); }, dg);
+      for (int k = 0; k <= dg; ++k) coef[j * (dg + 1) + k] = static_cast<double>(c[k]);
+    }
+    double err = 0.0, derr = 0.0;
+    for (int j = 0; j < P; ++j) {
+      const double* c = &coef[j * (dg + 1)];
+      for (int i = 0; i <= 96; ++i) {
+        const double g = -0.5 + i / 96.0;
+        double v = c[dg], dv = dg * c[dg];
+        for (int k = dg - 1; k >= 0; --k) v = v * g + c[k];
+        for (int k = dg - 1; k >= 1; --k) dv = dv * g + k * c[k];
+        err = std::max(err, std::fabs(v - static_cast<double>(piece(j, g))));
+        derr = std::max(derr, std::fabs(dv - piece_d(j, g)));
+      }
+    }
+    t->deg = dg;
+    t->coef.swap(coef);
+    t->fit_err = err;
+    t->fit_err_deriv = derr;
+    if (err <= fit_tol && derr <= fit_tol * dmax) break;
+  }
+}
+
+void twiddles(int N, int sign, std::vector<double>* out) {
+  out->resize(2 * static_cast<size_t>(N));
+  const long double twopi = 6.283185307179586476925286766559005768L;
+  for (int e = 0; e < N; ++e) {
+    const long double th = twopi * static_cast<long double>(e) / N;
+    (*out)[2 * e] = static_cast<double>(std::cos(th));
+    (*out)[2 * e + 1] = static_cast<double>(sign * std::sin(th));
+  }
+}
+
+}  // namespace pswfe

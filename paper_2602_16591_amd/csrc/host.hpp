@@ -1,0 +1,66 @@
+// Host-side float64 precompute for the PSWF fast Ewald plan: the PSWF itself (App. B),
+// Lambert W, parameter selection (Alg. 3) and the tables the kernels read.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace pswfe {
+
+// psi_0^c on [-1, 1] from its even Legendre expansion (eq. PSWFLegendre), with the
+// Legendre coefficients from the smallest eigenpair of the symmetric tridiagonal matrix
+// that the Sturm-Liouville equation (eq. ode) gives in the orthonormal Legendre basis,
+// found by Sturm bisection and inverse iteration (App. B.2).
+struct Pswf {
+  double c = 0.0;
+  double chi0 = 0.0;       // differential-equation eigenvalue (eq. ode)
+  double lambda0 = 0.0;    // integral-operator eigenvalue (eq. eigenvalueproblem)
+  double psi_0 = 0.0;      // psi_0^c(0)
+  double psi_1 = 0.0;      // psi_0^c(1)
+  std::vector<double> a;   // a[k]: coefficient of the Legendre polynomial P_{2k}
+
+  explicit Pswf(double c);
+  double psi(double x) const;   // |x| <= 1
+  double dpsi(double x) const;  // |x| <= 1
+};
+
+double lambert_w0(double x);   // principal branch, x >= -1/e
+double lambert_wm1(double x);  // lower branch, -1/e <= x < 0
+
+struct Params {
+  double L, eps, rc, cs, cw, alpha, h, lambda0_s;
+  double cs_alg, cw_alg, alpha_alg;
+  int m, P, tol_mode;
+};
+
+bool is_smooth_even(int m);
+int next_smooth_even(int m);
+
+// Alg. 3 with the rounding rules documented in pswfe.h. Returns 0 on success, else a
+// pswfe_status code.
+int choose_params(double eps, double L, double rc, int m, int64_t n, double q_l2, int tol_mode,
+                  Params* out);
+
+// Tables consumed by the kernels, all float64.
+struct Tables {
+  // Scaling s_k = T_M[|k|^2] * W[|k_x|] * W[|k_y|] * W[|k_z|] (Alg. 2 step 3 with the h^6 of the
+  // unnormalised DFT pair): T_M[k2] = h^6 Mhat(k) / V for 0 < |k| <= band edge, else 0;
+  // W[k] = 1 / phihat_1(2 pi k / L)^2 for 0 <= k <= m/2.
+  std::vector<double> tm;  // size 3 (m/2)^2 + 1
+  std::vector<double> w;   // size m/2 + 1
+  // Piecewise-polynomial window: for support point j = 0..P-1 and centred offset
+  // g in [-1/2, 1/2], phi_1(2 (g + (P-1)/2 - j) / P) ~ sum_k coef[j*(deg+1) + k] g^k.
+  int deg = 0;
+  std::vector<double> coef;     // P * (deg + 1)
+  double fit_err = 0.0;         // max |fit - phi_1| over all pieces (sampled)
+  double fit_err_deriv = 0.0;   // max |fit' - d phi_1/dg| over all pieces (sampled)
+  double self_coef = 0.0;       // 2 / (rc lambda_0(c_s))
+};
+
+// deg <= 0 picks the smallest degree in [4, 28] whose sampled error is below `fit_tol`.
+void build_tables(const Params& p, int deg, double fit_tol, Tables* t);
+
+// exp(sign * 2 pi i e / N) for e = 0..N-1, as interleaved (re, im) pairs, float64.
+void twiddles(int N, int sign, std::vector<double>* out);
+
+}  // namespace pswfe

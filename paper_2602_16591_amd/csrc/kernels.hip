@@ -1,0 +1,699 @@
+// HIP kernels for gfx950: binning, spreading (Alg. 2 step 1), smooth-size FFTs with the
+// k-space scaling fused between the forward and inverse z passes (steps 2-4), and
+// interpolation of potentials and gradients with the energy reduction (step 5, eq. force).
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <utility>
+
+namespace pswfe {
+namespace {
+
+template <class T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+template <class T> struct Cplx;
+template <> struct Cplx<float> { using type = float2; };
+template <> struct Cplx<double> { using type = double2; };
+
+template <class C> __device__ __forceinline__ C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <class C> __device__ __forceinline__ C cadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <class C> __device__ __forceinline__ C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <class C> __device__ __forceinline__ C cconj(C a) { C r; r.x = a.x; r.y = -a.y; return r; }
+
+__device__ __forceinline__ void atomic_add_global(float* p, float v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add_global(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+// Grid coordinate of x: cell c in [0, m) and fractional offset f with x/h = c + f (mod m).
+// The product x * (1/h) uses 1/h split into two words (ih_hi + ih_lo) and the exact product
+// error from an FMA, so f keeps the working precision's relative accuracy instead of losing
+// log2(m) bits to the integer part. Non-finite inputs map to cell 0 so every index derived
+// from the result stays inside the grid.
+template <class T>
+__device__ __forceinline__ int grid_coord(T x, T ih_hi, T ih_lo, T L, int m, T& f) {
+  T xr = x;
+  if (!(xr >= T(0) && xr < L)) {
+    xr = x - L * floor(x / L);
+    if (!(xr >= T(0) && xr < L)) xr = T(0);
+  }
+  const T p = xr * ih_hi;
+  const T lo = fma(xr, ih_lo, fma(xr, ih_hi, -p));
+  const T fl = floor(p);
+  int c = static_cast<int>(fl);
+  T fr = (p - fl) + lo;
+  if (fr < T(0)) {
+    fr += T(1);
+    c -= 1;
+  } else if (fr >= T(1)) {
+    fr -= T(1);
+    c += 1;
+  }
+  if (c < 0) c += m;
+  if (c >= m) c -= m;
+  if (!(fr >= T(0) && fr <= T(1))) fr = T(0);
+  f = fr;
+  return c;
+}
+
+// ------------------------------------------------------------------------------------
+// Binning: particles are grouped by tiles of B^3 grid cells (counting sort).
+// ------------------------------------------------------------------------------------
+template <class T>
+__global__ void k_bin_count(int64_t n, const T* __restrict__ pos, T ih_hi, T ih_lo, T L, int m, int B, int Tn,
+                            int* __restrict__ tile_count, int* __restrict__ tile_of, int* __restrict__ rank,
+                            double* __restrict__ energy) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i == 0 && energy) *energy = 0.0;
+  if (i >= n) return;
+  T f;
+  const int cx = grid_coord(pos[3 * i + 0], ih_hi, ih_lo, L, m, f);
+  const int cy = grid_coord(pos[3 * i + 1], ih_hi, ih_lo, L, m, f);
+  const int cz = grid_coord(pos[3 * i + 2], ih_hi, ih_lo, L, m, f);
+  const int tile = ((cz / B) * Tn + cy / B) * Tn + cx / B;
+  tile_of[i] = tile;
+  rank[i] = atomicAdd(&tile_count[tile], 1);
+}
+
+// Exclusive scan of the tile counts (one workgroup); resets the counts to zero.
+__global__ __launch_bounds__(1024) void k_scan(int ntiles, int* __restrict__ count, int* __restrict__ start) {
+  __shared__ int s_part[16];
+  __shared__ int s_carry;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) s_carry = 0;
+  __syncthreads();
+  for (int base = 0; base < ntiles; base += 4096) {
+    const int i0 = base + 4 * tid;
+    int v[4], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = (i0 + k < ntiles) ? count[i0 + k] : 0;
+      if (i0 + k < ntiles) count[i0 + k] = 0;
+      sum += v[k];
+    }
+    int x = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) s_part[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+      int p = lane < 16 ? s_part[lane] : 0;
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        const int y = __shfl_up(p, o, 64);
+        if (lane >= o) p += y;
+      }
+      if (lane < 16) s_part[lane] = p;
+    }
+    __syncthreads();
+    int excl = x - sum + (wid > 0 ? s_part[wid - 1] : 0) + s_carry;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (i0 + k < ntiles) start[i0 + k] = excl;
+      excl += v[k];
+    }
+    __syncthreads();
+    if (tid == 1023) s_carry = excl;
+    __syncthreads();
+  }
+  if (tid == 0) start[ntiles] = s_carry;
+}
+
+// Sorted record: (f_x, f_y, f_z, q) and the packed cell cx + m (cy + m cz).
+template <class T>
+__global__ void k_bin_scatter(int64_t n, const T* __restrict__ pos, const T* __restrict__ q, T ih_hi, T ih_lo, T L,
+                              int m, const int* __restrict__ tile_of, const int* __restrict__ rank,
+                              const int* __restrict__ tile_start, typename Vec4<T>::type* __restrict__ sorted,
+                              int* __restrict__ cells, int* __restrict__ perm) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const int dst = tile_start[tile_of[i]] + rank[i];
+  typename Vec4<T>::type r;
+  const int cx = grid_coord(pos[3 * i + 0], ih_hi, ih_lo, L, m, r.x);
+  const int cy = grid_coord(pos[3 * i + 1], ih_hi, ih_lo, L, m, r.y);
+  const int cz = grid_coord(pos[3 * i + 2], ih_hi, ih_lo, L, m, r.z);
+  r.w = q ? q[i] : T(0);
+  sorted[dst] = r;
+  cells[dst] = cx + m * (cy + m * cz);
+  perm[dst] = static_cast<int>(i);
+}
+
+// ------------------------------------------------------------------------------------
+// Window evaluation. For a particle at x/h = c + f (cell c, 0 <= f < 1) the support is the
+// P consecutive points starting at floor(c + f - P/2) + 1; point j sits at offset
+// u_j = g + (P-1)/2 - j with g in [-1/2, 1/2), and its window value phi_1(2 u_j / P) is the
+// polynomial `coef[j]` evaluated at g (Horner). `o` is the support start relative to the
+// tile origin T0 + 1 - ceil(P/2).
+// ------------------------------------------------------------------------------------
+template <class T, int P>
+__device__ __forceinline__ T centred_offset(T f, int c, int T0, int& o) {
+  if constexpr (P % 2 == 0) {
+    o = c - T0;
+    return f - T(0.5);
+  } else {
+    const int hh = f >= T(0.5) ? 1 : 0;
+    o = c - T0 + hh;
+    return f - static_cast<T>(hh);
+  }
+}
+
+template <class T, int P>
+__device__ __forceinline__ void window_values(T g, const T* __restrict__ coef, int deg, T* w) {
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const T* cj = coef + j * (deg + 1);
+    T v = cj[deg];
+    for (int k = deg - 1; k >= 0; --k) v = fma(v, g, cj[k]);
+    w[j] = v;
+  }
+}
+
+template <class T, int P>
+__device__ __forceinline__ void window_values_deriv(T g, const T* __restrict__ coef, int deg, T* w, T* dw) {
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const T* cj = coef + j * (deg + 1);
+    T v = cj[deg], dv = T(0);
+    for (int k = deg - 1; k >= 0; --k) {
+      dv = fma(dv, g, v);
+      v = fma(v, g, cj[k]);
+    }
+    w[j] = v;
+    dw[j] = dv;
+  }
+}
+
+__device__ __forceinline__ int wrap_index(int a, int m) {
+  int r = a % m;
+  return r < 0 ? r + m : r;
+}
+
+// ------------------------------------------------------------------------------------
+// Spreading (Alg. 2 step 1): one workgroup per tile accumulates the P^3 supports of its
+// particles into an LDS tile of S^3 points (S = B + 2 ceil(P/2) - 1) and adds the tile into
+// the HBM grid with atomics (a point is shared by at most the neighbouring tiles' halos).
+// The LDS tile is float64 in both precisions: on gfx950 LDS atomic adds on 64-bit floats run
+// about 20x faster than on 32-bit floats, and the accumulation gains precision.
+// ------------------------------------------------------------------------------------
+constexpr int kSpreadBatch = 16;
+
+template <class T, int P>
+__global__ __launch_bounds__(256) void k_spread(const typename Vec4<T>::type* __restrict__ sorted,
+                                                const int* __restrict__ cells,
+                                                const int* __restrict__ tile_start, const T* __restrict__ coef,
+                                                int deg, int m, int B, int Tn, int S, T* __restrict__ grid) {
+  extern __shared__ unsigned char smem_raw[];
+  double* acc = reinterpret_cast<double*>(smem_raw);
+  const int S3 = S * S * S;
+  T* W = reinterpret_cast<T*>(acc + S3);     // kSpreadBatch * 3 * P weights
+  T* Q = W + kSpreadBatch * 3 * P;           // kSpreadBatch charges
+  int* O = reinterpret_cast<int*>(Q + kSpreadBatch);  // kSpreadBatch * 3 support offsets
+  const int tile = blockIdx.x;
+  const int p0 = tile_start[tile], p1 = tile_start[tile + 1];
+  if (p0 == p1) return;
+  const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
+  const int T0[3] = {tx * B, ty * B, tz * B};
+  for (int i = threadIdx.x; i < S3; i += blockDim.x) acc[i] = 0.0;
+  __syncthreads();
+  for (int pb = p0; pb < p1; pb += kSpreadBatch) {
+    const int nb = min(kSpreadBatch, p1 - pb);
+    for (int e = threadIdx.x; e < nb * 3 * P; e += blockDim.x) {
+      const int p = e / (3 * P), r = e - p * 3 * P, d = r / P, j = r - d * P;
+      const auto rec = sorted[pb + p];
+      const T f = d == 0 ? rec.x : (d == 1 ? rec.y : rec.z);
+      const int cp = cells[pb + p];
+      const int c = d == 0 ? cp % m : (d == 1 ? (cp / m) % m : cp / (m * m));
+      int o;
+      const T g = centred_offset<T, P>(f, c, T0[d], o);
+      const T* cj = coef + j * (deg + 1);
+      T v = cj[deg];
+      for (int k = deg - 1; k >= 0; --k) v = fma(v, g, cj[k]);
+      W[(p * 3 + d) * P + j] = v;
+      if (j == 0) {
+        O[p * 3 + d] = o;
+        if (d == 0) Q[p] = rec.w;
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nb * P * P; e += blockDim.x) {
+      const int p = e / (P * P), r = e - p * P * P, jz = r / P, jy = r - jz * P;
+      const T wyz = Q[p] * W[(p * 3 + 2) * P + jz] * W[(p * 3 + 1) * P + jy];
+      const T* wx = W + (p * 3 + 0) * P;
+      double* row = acc + ((O[p * 3 + 2] + jz) * S + (O[p * 3 + 1] + jy)) * S + O[p * 3 + 0];
+#pragma unroll
+      for (int jx = 0; jx < P; ++jx) atomicAdd(row + jx, static_cast<double>(wyz * wx[jx]));
+    }
+    __syncthreads();
+  }
+  const int half = (P + 1) / 2;
+  const int Ox = T0[0] + 1 - half, Oy = T0[1] + 1 - half, Oz = T0[2] + 1 - half;
+  for (int i = threadIdx.x; i < S3; i += blockDim.x) {
+    const T v = static_cast<T>(acc[i]);
+    if (v == T(0)) continue;
+    const int ix = i % S, iy = (i / S) % S, iz = i / (S * S);
+    const int gx = wrap_index(Ox + ix, m), gy = wrap_index(Oy + iy, m), gz = wrap_index(Oz + iz, m);
+    atomic_add_global(grid + (static_cast<int64_t>(gz) * m + gy) * m + gx, v);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Interpolation (Alg. 2 step 5 and eq. force): one workgroup per tile stages the S^3 grid
+// values its particles touch in LDS; one thread per particle evaluates the tensor-product
+// sums as nested reductions (x, then y, then z) for phi and the three derivatives.
+// ------------------------------------------------------------------------------------
+template <class T, int P>
+__global__ __launch_bounds__(128) void k_gather(const typename Vec4<T>::type* __restrict__ sorted,
+                                                const int* __restrict__ cells,
+                                                const int* __restrict__ perm, const int* __restrict__ tile_start,
+                                                const T* __restrict__ coef, int deg, int m, int B, int Tn, int S,
+                                                const T* __restrict__ grid, T* __restrict__ phi, T* __restrict__ vec,
+                                                int vec_mode, T inv_h, double self_coef, int add_self,
+                                                double* __restrict__ energy) {
+  extern __shared__ unsigned char smem_raw[];
+  T* tb = reinterpret_cast<T*>(smem_raw);
+  __shared__ double s_red[4];
+  const int tile = blockIdx.x;
+  const int p0 = tile_start[tile], p1 = tile_start[tile + 1];
+  if (p0 == p1) return;
+  const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
+  const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
+  const int half = (P + 1) / 2;
+  const int Ox = T0x + 1 - half, Oy = T0y + 1 - half, Oz = T0z + 1 - half;
+  const int S3 = S * S * S;
+  for (int i = threadIdx.x; i < S3; i += blockDim.x) {
+    const int ix = i % S, iy = (i / S) % S, iz = i / (S * S);
+    const int gx = wrap_index(Ox + ix, m), gy = wrap_index(Oy + iy, m), gz = wrap_index(Oz + iz, m);
+    tb[i] = grid[(static_cast<int64_t>(gz) * m + gy) * m + gx];
+  }
+  __syncthreads();
+  double esum = 0.0;
+  for (int pi = p0 + threadIdx.x; pi < p1; pi += blockDim.x) {
+    const auto rec = sorted[pi];
+    const int cp = cells[pi];
+    T wx[P], dx[P], wy[P], dy[P], wz[P], dz[P];
+    int ox, oy, oz;
+    window_values_deriv<T, P>(centred_offset<T, P>(rec.x, cp % m, T0x, ox), coef, deg, wx, dx);
+    window_values_deriv<T, P>(centred_offset<T, P>(rec.y, (cp / m) % m, T0y, oy), coef, deg, wy, dy);
+    window_values_deriv<T, P>(centred_offset<T, P>(rec.z, cp / (m * m), T0z, oz), coef, deg, wz, dz);
+    T ph = T(0), gx = T(0), gy = T(0), gz = T(0);
+    for (int jz = 0; jz < P; ++jz) {
+      T ty_ = T(0), tdy = T(0), tdx = T(0);
+#pragma unroll
+      for (int jy = 0; jy < P; ++jy) {
+        const T* row = tb + ((oz + jz) * S + (oy + jy)) * S + ox;
+        T sx = T(0), sdx = T(0);
+#pragma unroll
+        for (int jx = 0; jx < P; ++jx) {
+          const T b = row[jx];
+          sx = fma(b, wx[jx], sx);
+          sdx = fma(b, dx[jx], sdx);
+        }
+        ty_ = fma(sx, wy[jy], ty_);
+        tdy = fma(sx, dy[jy], tdy);
+        tdx = fma(sdx, wy[jy], tdx);
+      }
+      // wz/dz indexed by a runtime jz: select from registers via a small unrolled search
+      T wzj = T(0), dzj = T(0);
+#pragma unroll
+      for (int j = 0; j < P; ++j)
+        if (j == jz) {
+          wzj = wz[j];
+          dzj = dz[j];
+        }
+      ph = fma(ty_, wzj, ph);
+      gz = fma(ty_, dzj, gz);
+      gy = fma(tdy, wzj, gy);
+      gx = fma(tdx, wzj, gx);
+    }
+    const int idx = perm[pi];
+    double phd = static_cast<double>(ph);
+    if (add_self) phd -= self_coef * static_cast<double>(rec.w);
+    if (phi) phi[idx] = static_cast<T>(phd);
+    if (vec) {
+      const T s = vec_mode == 0 ? -rec.w * inv_h : inv_h;
+      vec[3 * idx + 0] = s * gx;
+      vec[3 * idx + 1] = s * gy;
+      vec[3 * idx + 2] = s * gz;
+    }
+    esum += static_cast<double>(rec.w) * phd;
+  }
+  if (energy) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) esum += __shfl_xor(esum, o, 64);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = esum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) s += s_red[w];
+      unsafeAtomicAdd(energy, 0.5 * s);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// FFT: Stockham autosort passes in LDS over a batch of sequences. Stage with radix R and
+// current sub-length Ls: butterfly b (k = b mod Ls, j = b / Ls) reads x[b + t N/R],
+// multiplies by w_{R Ls}^{t k}, takes an R-point DFT, and writes y_u to j R Ls + u Ls + k.
+// The table `tw` holds exp(sign 2 pi i e / N), e = 0..N-1.
+// ------------------------------------------------------------------------------------
+template <class C, int R>
+__device__ __forceinline__ void butterfly(const C* __restrict__ in, int NR, C* __restrict__ out, int Ls, int k,
+                                          int twstep, const C* __restrict__ tw, int N) {
+  C a[R];
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    C x = in[t * NR];
+    if (t > 0) x = cmul(x, tw[t * k * twstep]);
+    a[t] = x;
+  }
+  if constexpr (R == 2) {
+    out[0] = cadd(a[0], a[1]);
+    out[Ls] = csub(a[0], a[1]);
+  } else if constexpr (R == 4) {
+    const C w = tw[N / 4];  // (0, +-1)
+    const C s02 = cadd(a[0], a[2]), d02 = csub(a[0], a[2]);
+    const C s13 = cadd(a[1], a[3]), d13 = csub(a[1], a[3]);
+    const C wd13 = cmul(w, d13);
+    out[0] = cadd(s02, s13);
+    out[Ls] = cadd(d02, wd13);
+    out[2 * Ls] = csub(s02, s13);
+    out[3 * Ls] = csub(d02, wd13);
+  } else {
+    C wr[R];
+#pragma unroll
+    for (int v = 0; v < R; ++v) wr[v] = tw[v * (N / R)];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      C y = a[0];
+#pragma unroll
+      for (int t = 1; t < R; ++t) {
+        const C p = cmul(a[t], wr[(t * u) % R]);
+        y.x += p.x;
+        y.y += p.y;
+      }
+      out[u * Ls] = y;
+    }
+  }
+}
+
+// Runs all stages; returns the buffer that holds the result (A or Bf).
+template <class C>
+__device__ C* fft_lds(C* A, C* Bf, int nseq, int ss, const FftPlan& pl, const C* __restrict__ tw) {
+  const int N = pl.N;
+  int Ls = 1;
+  C* src = A;
+  C* dst = Bf;
+  for (int st = 0; st < pl.nst; ++st) {
+    const int R = pl.radix[st];
+    const int NR = N / R;
+    const int twstep = N / (R * Ls);
+    for (int b = threadIdx.x; b < nseq * NR; b += blockDim.x) {
+      const int s = b / NR, bb = b - s * NR;
+      const int k = bb % Ls, j = bb / Ls;
+      const C* in = src + s * ss + bb;
+      C* out = dst + s * ss + j * R * Ls + k;
+      switch (R) {
+        case 2: butterfly<C, 2>(in, NR, out, Ls, k, twstep, tw, N); break;
+        case 3: butterfly<C, 3>(in, NR, out, Ls, k, twstep, tw, N); break;
+        case 4: butterfly<C, 4>(in, NR, out, Ls, k, twstep, tw, N); break;
+        case 5: butterfly<C, 5>(in, NR, out, Ls, k, twstep, tw, N); break;
+        case 7: butterfly<C, 7>(in, NR, out, Ls, k, twstep, tw, N); break;
+        default: butterfly<C, 8>(in, NR, out, Ls, k, twstep, tw, N); break;
+      }
+    }
+    __syncthreads();
+    C* tmp = src;
+    src = dst;
+    dst = tmp;
+    Ls *= R;
+  }
+  return src;
+}
+
+// x-direction real-to-complex FFT (sign +) of `nrows` rows of m reals via an m/2-point complex
+// FFT of (a_2j + i a_2j+1); writes X_k, k = 0..m/2, to spec. Optionally zeroes the input rows.
+template <class T>
+__global__ __launch_bounds__(256) void k_fft_x_r2c(const T* __restrict__ grid, T* zero_after, int m, int nrows,
+                                                   int rpb, FftPlan pl, const typename Cplx<T>::type* __restrict__ tw_half,
+                                                   const typename Cplx<T>::type* __restrict__ tw_full,
+                                                   typename Cplx<T>::type* __restrict__ spec) {
+  using C = typename Cplx<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  const int N = m / 2;
+  C* A = reinterpret_cast<C*>(smem_raw);
+  C* Bf = A + rpb * N;
+  const int row0 = blockIdx.x * rpb;
+  const int nr = min(rpb, nrows - row0);
+  const C* src = reinterpret_cast<const C*>(grid + static_cast<int64_t>(row0) * m);
+  C* zsrc = zero_after ? reinterpret_cast<C*>(zero_after + static_cast<int64_t>(row0) * m) : nullptr;
+  for (int e = threadIdx.x; e < nr * N; e += blockDim.x) {
+    A[e] = src[e];
+    if (zsrc) zsrc[e] = C{T(0), T(0)};
+  }
+  __syncthreads();
+  const C* Z = fft_lds(A, Bf, nr, N, pl, tw_half);
+  C* out = spec + static_cast<int64_t>(row0) * (N + 1);
+  for (int e = threadIdx.x; e < nr * (N + 1); e += blockDim.x) {
+    const int r = e / (N + 1), k = e - r * (N + 1);
+    const C zk = Z[r * N + (k == N ? 0 : k)];
+    const C zn = cconj(Z[r * N + (k == 0 ? 0 : N - k)]);
+    const C ev = C{T(0.5) * (zk.x + zn.x), T(0.5) * (zk.y + zn.y)};
+    const C dd = csub(zk, zn);
+    const C od = C{T(0.5) * dd.y, T(-0.5) * dd.x};  // (zk - zn) / (2i)
+    const C w = tw_full[k];
+    out[e] = cadd(ev, cmul(w, od));
+  }
+}
+
+// x-direction complex-to-real inverse FFT (sign -): from X_k, k = 0..m/2 (Hermitian), forms
+// Z_k = (X_k + conj X_{N-k}) + i w^{-k} (X_k - conj X_{N-k}), an m/2-point inverse FFT, and writes
+// a_2j = Re z_j, a_2j+1 = Im z_j.
+template <class T>
+__global__ __launch_bounds__(256) void k_fft_x_c2r(const typename Cplx<T>::type* __restrict__ spec, int m, int nrows,
+                                                   int rpb, FftPlan pl, const typename Cplx<T>::type* __restrict__ tw_half,
+                                                   const typename Cplx<T>::type* __restrict__ tw_full, T* __restrict__ grid) {
+  using C = typename Cplx<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  const int N = m / 2;
+  C* A = reinterpret_cast<C*>(smem_raw);   // rpb * (N + 1)
+  C* Bf = A + rpb * (N + 1);               // rpb * N
+  const int row0 = blockIdx.x * rpb;
+  const int nr = min(rpb, nrows - row0);
+  const C* in = spec + static_cast<int64_t>(row0) * (N + 1);
+  for (int e = threadIdx.x; e < nr * (N + 1); e += blockDim.x) A[e] = in[e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < nr * N; e += blockDim.x) {
+    const int r = e / N, k = e - r * N;
+    const C xk = A[r * (N + 1) + k];
+    const C xn = cconj(A[r * (N + 1) + N - k]);
+    const C s = cadd(xk, xn);
+    const C d = cmul(tw_full[k], csub(xk, xn));
+    Bf[e] = C{s.x - d.y, s.y + d.x};  // s + i d
+  }
+  __syncthreads();
+  const C* Z = fft_lds(Bf, A, nr, N, pl, tw_half);
+  C* dst = reinterpret_cast<C*>(grid + static_cast<int64_t>(row0) * m);
+  for (int e = threadIdx.x; e < nr * N; e += blockDim.x) dst[e] = Z[e];
+}
+
+// FFT along y or z of the half spectrum. Sequence c of a block is the column kx0 + c; its
+// element e sits at spec[outer * ostride + e * estride + kx0 + c]. With `scale`, the block
+// runs the forward transform along z, multiplies by s_k = T_M[|k|^2] W[|kx|] W[|ky|] W[|kz|]
+// (ky = outer), and runs the inverse transform along z (Alg. 2 steps 2-4 for this column).
+template <class T>
+__global__ __launch_bounds__(256) void k_fft_cols(typename Cplx<T>::type* __restrict__ spec, int m, int nx1,
+                                                  int64_t ostride, int64_t estride, int cpb, FftPlan pl,
+                                                  const typename Cplx<T>::type* __restrict__ tw, int scale,
+                                                  const typename Cplx<T>::type* __restrict__ tw_inv,
+                                                  const T* __restrict__ tm, const T* __restrict__ wk) {
+  using C = typename Cplx<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  const int ss = m + 1;  // padded sequence stride in LDS
+  C* A = reinterpret_cast<C*>(smem_raw);
+  C* Bf = A + cpb * ss;
+  const int kx0 = blockIdx.x * cpb;
+  const int outer = blockIdx.y;
+  const int nc = min(cpb, nx1 - kx0);
+  C* base = spec + outer * ostride + kx0;
+  for (int i = threadIdx.x; i < nc * m; i += blockDim.x) {
+    const int e = i / nc, c = i - e * nc;
+    A[c * ss + e] = base[e * estride + c];
+  }
+  __syncthreads();
+  C* R1 = fft_lds(A, Bf, nc, ss, pl, tw);
+  if (scale) {
+    const int ky = outer <= (m - 1) / 2 ? outer : m - outer;
+    for (int i = threadIdx.x; i < nc * m; i += blockDim.x) {
+      const int c = i / m, e = i - c * m;
+      const int kx = kx0 + c;
+      const int kz = e <= (m - 1) / 2 ? e : m - e;
+      const T s = tm[kx * kx + ky * ky + kz * kz] * wk[kx] * wk[ky] * wk[kz];
+      C v = R1[c * ss + e];
+      v.x *= s;
+      v.y *= s;
+      R1[c * ss + e] = v;
+    }
+    __syncthreads();
+    C* other = (R1 == A) ? Bf : A;
+    R1 = fft_lds(R1, other, nc, ss, pl, tw_inv);
+  }
+  for (int i = threadIdx.x; i < nc * m; i += blockDim.x) {
+    const int e = i / nc, c = i - e * nc;
+    base[e * estride + c] = R1[c * ss + e];
+  }
+}
+
+template <class T>
+__global__ void k_zero(T* __restrict__ p, int64_t count) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = T(0);
+}
+
+// ------------------------------------------------------------------------------------
+// Launch helpers
+// ------------------------------------------------------------------------------------
+inline unsigned blocks_for(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
+
+template <class T>
+hipError_t bin_impl(const DevPlan& d, int64_t n, const void* pos, const void* q, double* energy, hipStream_t st) {
+  const T ih_hi = static_cast<T>(d.inv_h_hi), ih_lo = static_cast<T>(d.inv_h_lo), L = static_cast<T>(d.L);
+  stage_begin(d, kStageBin, st);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_bin_count<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n,
+                       static_cast<const T*>(pos), ih_hi, ih_lo, L, d.m, d.B, d.Tn, d.tile_count, d.tile_of, d.rank,
+                       energy);
+  } else if (energy) {
+    hipLaunchKernelGGL(k_zero<double>, dim3(1), dim3(64), 0, st, energy, int64_t(1));
+  }
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d.ntiles, d.tile_count, d.tile_start);
+  if (n > 0)
+    hipLaunchKernelGGL(k_bin_scatter<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, static_cast<const T*>(pos),
+                       static_cast<const T*>(q), ih_hi, ih_lo, L, d.m, d.tile_of, d.rank, d.tile_start,
+                       static_cast<typename Vec4<T>::type*>(d.sorted), d.cells, d.perm);
+  stage_end(d, kStageBin, st);
+  return hipGetLastError();
+}
+
+template <class T, int P>
+hipError_t spread_impl(const DevPlan& d, void* grid, hipStream_t st) {
+  const size_t lds = sizeof(double) * static_cast<size_t>(d.S) * d.S * d.S +
+                     sizeof(T) * (kSpreadBatch * 3 * P + kSpreadBatch) + sizeof(int) * kSpreadBatch * 3;
+  stage_begin(d, kStageSpread, st);
+  hipLaunchKernelGGL((k_spread<T, P>), dim3(d.ntiles), dim3(256), lds, st,
+                     static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start,
+                     static_cast<const T*>(d.coef), d.deg, d.m, d.B, d.Tn, d.S, static_cast<T*>(grid));
+  stage_end(d, kStageSpread, st);
+  return hipGetLastError();
+}
+
+template <class T, int P>
+hipError_t gather_impl(const DevPlan& d, const void* grid, void* phi, void* vec, int vec_mode, bool add_self,
+                       double* energy, hipStream_t st) {
+  const size_t lds = sizeof(T) * static_cast<size_t>(d.S) * d.S * d.S;
+  stage_begin(d, kStageGather, st);
+  hipLaunchKernelGGL((k_gather<T, P>), dim3(d.ntiles), dim3(128), lds, st,
+                     static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.perm, d.tile_start,
+                     static_cast<const T*>(d.coef), d.deg, d.m, d.B, d.Tn, d.S, static_cast<const T*>(grid),
+                     static_cast<T*>(phi), static_cast<T*>(vec), vec_mode, static_cast<T>(d.inv_h), d.self_coef,
+                     add_self ? 1 : 0, energy);
+  stage_end(d, kStageGather, st);
+  return hipGetLastError();
+}
+
+template <class T, int P>
+hipError_t spread_dispatch(const DevPlan& d, void* grid, hipStream_t st) {
+  if (d.P == P) return spread_impl<T, P>(d, grid, st);
+  if constexpr (P < kPmax) return spread_dispatch<T, P + 1>(d, grid, st);
+  return hipErrorInvalidValue;
+}
+
+template <class T, int P>
+hipError_t gather_dispatch(const DevPlan& d, const void* grid, void* phi, void* vec, int vec_mode, bool add_self,
+                           double* energy, hipStream_t st) {
+  if (d.P == P) return gather_impl<T, P>(d, grid, phi, vec, vec_mode, add_self, energy, st);
+  if constexpr (P < kPmax) return gather_dispatch<T, P + 1>(d, grid, phi, vec, vec_mode, add_self, energy, st);
+  return hipErrorInvalidValue;
+}
+
+template <class T>
+hipError_t transform_impl(const DevPlan& d, const void* grid_in, void* grid_out, bool zero_input, hipStream_t st) {
+  using C = typename Cplx<T>::type;
+  const int m = d.m, N = m / 2, nx1 = N + 1, nrows = m * m;
+  C* spec = static_cast<C*>(d.spec);
+  const int rpb = d.rows_per_block, cpb = d.cols_per_block;
+  const size_t lds_x = sizeof(C) * 2 * static_cast<size_t>(rpb) * (N + 1);
+  const size_t lds_c = sizeof(C) * 2 * static_cast<size_t>(cpb) * (m + 1);
+  const C* twhp = static_cast<const C*>(d.tw_half_p);
+  const C* twhm = static_cast<const C*>(d.tw_half_m);
+  const C* twfp = static_cast<const C*>(d.tw_full_p);
+  const C* twfm = static_cast<const C*>(d.tw_full_m);
+  stage_begin(d, kStageFftX, st);
+  hipLaunchKernelGGL(k_fft_x_r2c<T>, dim3(blocks_for(nrows, rpb)), dim3(256), lds_x, st,
+                     static_cast<const T*>(grid_in), zero_input ? static_cast<T*>(const_cast<void*>(grid_in)) : nullptr,
+                     m, nrows, rpb, d.fft_half, twhp, twfp, spec);
+  stage_end(d, kStageFftX, st);
+  const dim3 gcols(blocks_for(nx1, cpb), m);
+  // y forward: outer = z plane, element stride nx1
+  stage_begin(d, kStageFftY, st);
+  hipLaunchKernelGGL(k_fft_cols<T>, gcols, dim3(256), lds_c, st, spec, m, nx1, int64_t(m) * nx1, int64_t(nx1), cpb,
+                     d.fft_full, twfp, 0, twfm, static_cast<const T*>(d.tm), static_cast<const T*>(d.wk));
+  stage_end(d, kStageFftY, st);
+  // z forward, scale, z inverse: outer = y row, element stride m * nx1
+  stage_begin(d, kStageFftZScale, st);
+  hipLaunchKernelGGL(k_fft_cols<T>, gcols, dim3(256), lds_c, st, spec, m, nx1, int64_t(nx1), int64_t(m) * nx1, cpb,
+                     d.fft_full, twfp, 1, twfm, static_cast<const T*>(d.tm), static_cast<const T*>(d.wk));
+  stage_end(d, kStageFftZScale, st);
+  // y inverse
+  stage_begin(d, kStageIfftY, st);
+  hipLaunchKernelGGL(k_fft_cols<T>, gcols, dim3(256), lds_c, st, spec, m, nx1, int64_t(m) * nx1, int64_t(nx1), cpb,
+                     d.fft_full, twfm, 0, twfm, static_cast<const T*>(d.tm), static_cast<const T*>(d.wk));
+  stage_end(d, kStageIfftY, st);
+  stage_begin(d, kStageIfftX, st);
+  hipLaunchKernelGGL(k_fft_x_c2r<T>, dim3(blocks_for(nrows, rpb)), dim3(256), lds_x, st,
+                     static_cast<const C*>(spec), m, nrows, rpb, d.fft_half, twhm, twfm, static_cast<T*>(grid_out));
+  stage_end(d, kStageIfftX, st);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_bin(const DevPlan& d, int64_t n, const void* pos, const void* q, double* energy, hipStream_t st) {
+  return d.prec == 0 ? bin_impl<float>(d, n, pos, q, energy, st) : bin_impl<double>(d, n, pos, q, energy, st);
+}
+
+hipError_t launch_spread(const DevPlan& d, void* grid, hipStream_t st) {
+  return d.prec == 0 ? spread_dispatch<float, kPmin>(d, grid, st) : spread_dispatch<double, kPmin>(d, grid, st);
+}
+
+hipError_t launch_zero(const DevPlan& d, void* buf, int64_t count, hipStream_t st) {
+  const unsigned nb = std::min<unsigned>(blocks_for(count, 256), 4096u);
+  if (d.prec == 0)
+    hipLaunchKernelGGL(k_zero<float>, dim3(std::max(nb, 1u)), dim3(256), 0, st, static_cast<float*>(buf), count);
+  else
+    hipLaunchKernelGGL(k_zero<double>, dim3(std::max(nb, 1u)), dim3(256), 0, st, static_cast<double*>(buf), count);
+  return hipGetLastError();
+}
+
+hipError_t launch_transform(const DevPlan& d, const void* grid_in, void* grid_out, bool zero_input, hipStream_t st) {
+  return d.prec == 0 ? transform_impl<float>(d, grid_in, grid_out, zero_input, st)
+                     : transform_impl<double>(d, grid_in, grid_out, zero_input, st);
+}
+
+hipError_t launch_gather(const DevPlan& d, int64_t n, const void* grid, void* phi, void* vec, int vec_mode,
+                         bool add_self, double* energy, hipStream_t st) {
+  (void)n;
+  return d.prec == 0 ? gather_dispatch<float, kPmin>(d, grid, phi, vec, vec_mode, add_self, energy, st)
+                     : gather_dispatch<double, kPmin>(d, grid, phi, vec, vec_mode, add_self, energy, st);
+}
+
+}  // namespace pswfe
