@@ -1,8 +1,8 @@
 """Benchmark: long-range PSWF fast Ewald (potentials + forces + energy) on one MI355X.
 
 Workload: water-like box of 10,000 rigid 3-site molecules (n = 30,000 charges, L = 6.688 nm,
-1 g/cm^3, SPC/E-like charges), eps = 1e-6 with the relative-tolerance parameters of Alg. 3 on a
-64^3 grid (P = 12). One step = one full pass of the pipeline (binning, spreading, FFT with fused
+1 g/cm^3, SPC/E-like charges), eps = 1e-6 absolute RMS with the parameters of Alg. 3 on a 64^3
+grid (P = 13). One step = one full pass of the pipeline (binning, spreading, FFT with fused
 scaling, inverse FFT, interpolation of phi and forces, self term and energy) on inputs resident
 in HBM. The headline value is the float32 path; the float64 path is timed on the same system.
 
@@ -59,9 +59,10 @@ def stage_work(stage: str, n: int, m: int, P: int, deg: int, elem: int):
 def cpu_baseline(x, q, L, eps, m):
     """The float64 oracle of the same computation (Alg. 2 in NumPy, oracle/fast.py) on the full
     system, single-threaded, timed on this host."""
+    import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import fast, params
-    p = params.choose(eps, L, m=m)
+    p = params.choose(eps, L, m=m, q_l2=float(np.linalg.norm(q)), tol_mode="abs")
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         fast.fast_longrange(x, q, p, grad=True)
@@ -92,7 +93,11 @@ def main():
     x, q, L = W.config("water_n30000")
     n = len(q)
     eps, m = 1e-6, 64
-    params = pw.choose_params(eps, L, m=m)
+    params = pw.choose_params(eps, L, m=m, q_l2=float(np.linalg.norm(q)), tol_mode="abs")
+    # both precisions see the same float32-representable inputs, so the float32/float64
+    # comparison below isolates arithmetic error from input quantisation
+    x = x.astype(np.float32).astype(np.float64)
+    q = q.astype(np.float32).astype(np.float64)
     P = params.P
     results = {}
     for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
@@ -148,19 +153,20 @@ def main():
     roof.update({"kernel": r["dom"], "avg_launch_us": r["dom_ms"] * 1e3, "work_per_launch": work})
     r64 = results["fp64"]
     phi_diff = float(np.linalg.norm(r["phi"] - r64["phi"]) / np.linalg.norm(r64["phi"]))
+    phi_abs = float(np.sqrt(np.mean((r["phi"] - r64["phi"]) ** 2)))
     F_diff = float(np.linalg.norm(r["F"] - r64["F"]) / np.linalg.norm(r64["F"]))
     out = {
         "metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["elapsed"] / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "water_box_n30000", "n": n, "L_nm": L, "eps": eps, "tol_mode": "rel", "m": m, "P": P,
+        "config": {"workload": "water_box_n30000", "n": n, "L_nm": L, "eps": eps, "tol_mode": "abs", "m": m, "P": P,
                    "rc_nm": params.rc, "parallelism": "single GPU"},
         "roofline": roof,
         "stage_us_fp32": {k: v * 1e3 for k, v in r["stage_ms"].items()},
         "fp64": {"value": n * args.steps / r64["elapsed"], "unit": "particles/s",
                  "ms_per_step": r64["elapsed"] / args.steps * 1e3,
                  "stage_us": {k: v * 1e3 for k, v in r64["stage_ms"].items()}},
-        "fp32_vs_fp64": {"phi_rel_l2": phi_diff, "force_rel_l2": F_diff,
+        "fp32_vs_fp64": {"phi_rel_l2": phi_diff, "phi_abs_rms": phi_abs, "force_rel_l2": F_diff,
                          "energy_rel": abs(r["E"] - r64["E"]) / abs(r64["E"])},
     }
     if not args.no_cpu_baseline:

@@ -97,6 +97,17 @@ pswfe_status pswfe_choose_params(double eps, double L, double rc, int32_t m, int
  *   out    host pointer receiving the plan; NULL on failure. */
 pswfe_status pswfe_plan_create(const pswfe_params* p, int32_t prec, int64_t n_max, pswfe_plan** out);
 
+/* As pswfe_plan_create with an explicit tile edge (in grid cells) for binning, spreading and
+ * interpolation: particles are processed per tile of tile^3 cells, each with an LDS copy of
+ * the grid points its supports touch. tile = 0 picks the default (8, reduced to fit the LDS
+ * limits and small grids); a tile that does not fit the LDS limits is reduced until it does.
+ * Used by the autotuner of the Python layer. tile < 0 or tile > m -> PSWFE_E_ARG. */
+pswfe_status pswfe_plan_create_tiled(const pswfe_params* p, int32_t prec, int64_t n_max, int32_t tile,
+                                     pswfe_plan** out);
+
+/* Tile edge a plan uses (0 for NULL). */
+int32_t pswfe_plan_tile(const pswfe_plan* plan);
+
 /* Frees the plan and its device buffers (synchronises the device first). NULL is a no-op. */
 pswfe_status pswfe_plan_destroy(pswfe_plan* plan);
 

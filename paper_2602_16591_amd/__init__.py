@@ -45,6 +45,8 @@ _PPlan = ctypes.POINTER(ctypes.c_void_p)
 SIGNATURES = {
     "pswfe_choose_params": (ctypes.c_int, [_d, _d, _d, _i32, _i64, _d, _i32, ctypes.POINTER(CParams)]),
     "pswfe_plan_create": (ctypes.c_int, [ctypes.POINTER(CParams), _i32, _i64, _PPlan]),
+    "pswfe_plan_create_tiled": (ctypes.c_int, [ctypes.POINTER(CParams), _i32, _i64, _i32, _PPlan]),
+    "pswfe_plan_tile": (ctypes.c_int32, [_vp]),
     "pswfe_plan_destroy": (ctypes.c_int, [_vp]),
     "pswfe_compute": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pswfe_compute_grad": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -144,14 +146,15 @@ def _stream_ptr(stream):
 class Plan:
     """Device plan for one parameter set, precision and maximum particle count."""
 
-    def __init__(self, params: CParams, prec: int | str = FP32, n_max: int = 0):
+    def __init__(self, params: CParams, prec: int | str = FP32, n_max: int = 0, tile: int = 0):
         import torch
         self.prec = {"fp32": FP32, "fp64": FP64}.get(prec, prec)
         self.dtype = torch.float32 if self.prec == FP32 else torch.float64
         self.n_max = int(n_max)
         self._h = ctypes.c_void_p()
-        _check(_lib().pswfe_plan_create(ctypes.byref(params), int(self.prec), self.n_max, ctypes.byref(self._h)),
-               "pswfe_plan_create")
+        _check(_lib().pswfe_plan_create_tiled(ctypes.byref(params), int(self.prec), self.n_max, int(tile),
+                                              ctypes.byref(self._h)), "pswfe_plan_create_tiled")
+        self.tile = int(_lib().pswfe_plan_tile(self._h))
         p = CParams()
         _check(_lib().pswfe_plan_params(self._h, ctypes.byref(p)), "pswfe_plan_params")
         self.params = p

@@ -56,25 +56,33 @@ pswfe::FftPlan make_fft_plan(int N) {
   return pl;
 }
 
-// Tile edge B for binning/spreading/gathering: the largest candidate that still yields at
-// least ~512 tiles (so the 256 CUs all get work) and whose LDS tile (float64 accumulators in
-// the spreading kernel) fits in 60 KiB.
-int choose_tile(int m, int P, int elem) {
-  if (const char* env = std::getenv("PSWFE_TILE")) {
-    const int b = std::atoi(env);
-    if (b >= 2 && b <= m) return b;
+// Tile edge B (cells) for binning, spreading and interpolation. The spreading tile holds
+// S^3 float64 accumulators (S = B + 2 ceil(P/2) - 1), at most 150 KiB; the interpolation tile
+// S^3 values of the plan precision plus the window records of 16 particles, at most 156 KiB.
+// Default: B = 8 (measured best on gfx950 for 64^3 and 128^3 grids with P = 12-18), reduced to
+// fit the LDS limits and to give at least 64 tiles on small grids.
+size_t gather_lds_bytes(int S, int P, int elem) {
+  return static_cast<size_t>(elem) * S * S * S + sizeof(double) * 16 * 6 * P;
+}
+
+bool tile_fits(int B, int P, int elem) {
+  const int S = B + 2 * ((P + 1) / 2) - 1;
+  return 8.0 * (static_cast<double>(S) * S * S + 16 * 3 * P) <= 150.0 * 1024 &&
+         gather_lds_bytes(S, P, elem) <= 156 * 1024;
+}
+
+int choose_tile(int m, int P, int requested, int elem) {
+  int B = requested;
+  if (B <= 0) {
+    if (const char* env = std::getenv("PSWFE_TILE")) B = std::atoi(env);
   }
-  const int half = (P + 1) / 2;
-  int best = 2;
-  for (int B : {2, 3, 4, 5, 6, 8, 10, 12, 16}) {
-    if (B > m) break;
-    const int S = B + 2 * half - 1;
-    const int Tn = (m + B - 1) / B;
-    if (static_cast<size_t>(S) * S * S * elem > 60 * 1024) break;
-    if (Tn * Tn * Tn < 512 && B > 2) break;
-    best = B;
+  if (B <= 0) {
+    B = 8;
+    while (B > 2 && (m + B - 1) / B < 4) --B;
   }
-  return best;
+  B = std::max(2, std::min(B, m));
+  while (B > 2 && !tile_fits(B, P, elem)) --B;
+  return B;
 }
 
 template <class T>
@@ -200,7 +208,14 @@ pswfe_status pswfe_plan_params(const pswfe_plan* plan, pswfe_params* out) {
   return PSWFE_OK;
 }
 
+int32_t pswfe_plan_tile(const pswfe_plan* plan) { return plan ? plan->d.B : 0; }
+
 pswfe_status pswfe_plan_create(const pswfe_params* pp, int32_t prec, int64_t n_max, pswfe_plan** out) {
+  return pswfe_plan_create_tiled(pp, prec, n_max, 0, out);
+}
+
+pswfe_status pswfe_plan_create_tiled(const pswfe_params* pp, int32_t prec, int64_t n_max, int32_t tile,
+                                     pswfe_plan** out) {
   if (!out) return PSWFE_E_ARG;
   *out = nullptr;
   if (!pp || n_max < 0 || n_max > (int64_t(1) << 31) - 1) return PSWFE_E_ARG;
@@ -222,7 +237,11 @@ pswfe_status pswfe_plan_create(const pswfe_params* pp, int32_t prec, int64_t n_m
   d.m = m;
   d.P = P;
   d.deg = plan->tab.deg;
-  d.B = choose_tile(m, P, 8);
+  if (tile < 0 || tile > m) {
+    delete plan;
+    return PSWFE_E_ARG;
+  }
+  d.B = choose_tile(m, P, tile, elem);
   d.Tn = (m + d.B - 1) / d.B;
   d.ntiles = d.Tn * d.Tn * d.Tn;
   d.S = d.B + 2 * ((P + 1) / 2) - 1;
@@ -271,7 +290,7 @@ pswfe_status pswfe_plan_create(const pswfe_params* pp, int32_t prec, int64_t n_m
   alloc(reinterpret_cast<void**>(&d.perm), sizeof(int) * nm);
   alloc(reinterpret_cast<void**>(&d.cells), sizeof(int) * nm);
   alloc(&d.sorted, size_t(4) * elem * nm);
-  alloc(&d.grid_a, elem * m3);
+  alloc(&d.grid_a, sizeof(double) * m3);
   alloc(&d.grid_b, elem * m3);
   alloc(&d.spec, size_t(2) * elem * nspec);
   if (st == PSWFE_OK) {
@@ -283,7 +302,7 @@ pswfe_status pswfe_plan_create(const pswfe_params* pp, int32_t prec, int64_t n_m
     auto up = [&](const std::vector<double>& v, void** dst) {
       if (st == PSWFE_OK) st = prec == PSWFE_FP32 ? upload<float>(v, dst) : upload<double>(v, dst);
     };
-    up(plan->tab.coef, &d.coef);
+    if (st == PSWFE_OK) st = upload<double>(plan->tab.coef, &d.coef);  // window polynomials: float64
     up(plan->tab.tm, &d.tm);
     up(plan->tab.w, &d.wk);
     up(twhp, &d.tw_half_p);
@@ -292,7 +311,8 @@ pswfe_status pswfe_plan_create(const pswfe_params* pp, int32_t prec, int64_t n_m
     up(twfm, &d.tw_full_m);
   }
   if (st == PSWFE_OK && (hipMemset(d.tile_count, 0, sizeof(int) * d.ntiles) != hipSuccess ||
-                         hipMemset(d.grid_a, 0, elem * m3) != hipSuccess || hipDeviceSynchronize() != hipSuccess))
+                         hipMemset(d.grid_a, 0, sizeof(double) * m3) != hipSuccess ||
+                         hipDeviceSynchronize() != hipSuccess))
     st = PSWFE_E_HIP;
   if (st != PSWFE_OK) {
     free_plan_buffers(d);
@@ -361,7 +381,7 @@ pswfe_status compute_impl(pswfe_plan* plan, int64_t n, const void* pos, const vo
   pswfe::stage_begin(d, pswfe::kStageAll, s);
   hipError_t e = pswfe::launch_bin(d, n, pos, q, energy, s);
   if (e == hipSuccess) e = pswfe::launch_spread(d, d.grid_a, s);
-  if (e == hipSuccess) e = pswfe::launch_transform(d, d.grid_a, d.grid_b, true, s);
+  if (e == hipSuccess) e = pswfe::launch_transform(d, d.grid_a, true, d.grid_b, true, s);
   if (e == hipSuccess && n > 0) e = pswfe::launch_gather(d, n, d.grid_b, phi, vec, vec_mode, true, energy, s);
   pswfe::stage_end(d, pswfe::kStageAll, s);
   return from_hip(e);
@@ -384,15 +404,16 @@ pswfe_status pswfe_spread(pswfe_plan* plan, int64_t n, const void* pos, const vo
   if (n > 0 && (!pos || !q)) return PSWFE_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const pswfe::DevPlan& d = plan->d;
-  hipError_t e = pswfe::launch_zero(d, grid, int64_t(d.m) * d.m * d.m, s);
-  if (e == hipSuccess) e = pswfe::launch_bin(d, n, pos, q, nullptr, s);
-  if (e == hipSuccess) e = pswfe::launch_spread(d, grid, s);
+  hipError_t e = pswfe::launch_bin(d, n, pos, q, nullptr, s);
+  if (e == hipSuccess) e = pswfe::launch_spread(d, d.grid_a, s);
+  if (e == hipSuccess) e = pswfe::launch_drain(d, grid, s);
   return from_hip(e);
 }
 
 pswfe_status pswfe_transform(pswfe_plan* plan, const void* grid_in, void* grid_out, void* stream) {
   if (!plan || !grid_in || !grid_out) return PSWFE_E_ARG;
-  return from_hip(pswfe::launch_transform(plan->d, grid_in, grid_out, false, static_cast<hipStream_t>(stream)));
+  return from_hip(pswfe::launch_transform(plan->d, grid_in, plan->d.prec == 1, grid_out, false,
+                                          static_cast<hipStream_t>(stream)));
 }
 
 pswfe_status pswfe_interpolate(pswfe_plan* plan, int64_t n, const void* pos, const void* grid, void* phi, void* grad,

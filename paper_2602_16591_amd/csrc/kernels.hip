@@ -35,9 +35,11 @@ __device__ __forceinline__ void atomic_add_global(double* p, double v) { unsafeA
 // The product x * (1/h) uses 1/h split into two words (ih_hi + ih_lo) and the exact product
 // error from an FMA, so f keeps the working precision's relative accuracy instead of losing
 // log2(m) bits to the integer part. Non-finite inputs map to cell 0 so every index derived
-// from the result stays inside the grid.
+// from the result stays inside the grid. Contraction is off here: fusing the rounded product
+// p into (p - floor(p)) would count its rounding error twice.
 template <class T>
 __device__ __forceinline__ int grid_coord(T x, T ih_hi, T ih_lo, T L, int m, T& f) {
+#pragma clang fp contract(off)
   T xr = x;
   if (!(xr >= T(0) && xr < L)) {
     xr = x - L * floor(x / L);
@@ -166,120 +168,124 @@ __device__ __forceinline__ T centred_offset(T f, int c, int T0, int& o) {
   }
 }
 
-template <class T, int P>
-__device__ __forceinline__ void window_values(T g, const T* __restrict__ coef, int deg, T* w) {
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    const T* cj = coef + j * (deg + 1);
-    T v = cj[deg];
-    for (int k = deg - 1; k >= 0; --k) v = fma(v, g, cj[k]);
-    w[j] = v;
-  }
-}
-
-template <class T, int P>
-__device__ __forceinline__ void window_values_deriv(T g, const T* __restrict__ coef, int deg, T* w, T* dw) {
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    const T* cj = coef + j * (deg + 1);
-    T v = cj[deg], dv = T(0);
-    for (int k = deg - 1; k >= 0; --k) {
-      dv = fma(dv, g, v);
-      v = fma(v, g, cj[k]);
-    }
-    w[j] = v;
-    dw[j] = dv;
-  }
-}
-
 __device__ __forceinline__ int wrap_index(int a, int m) {
   int r = a % m;
   return r < 0 ? r + m : r;
 }
 
 // ------------------------------------------------------------------------------------
-// Spreading (Alg. 2 step 1): one workgroup per tile accumulates the P^3 supports of its
-// particles into an LDS tile of S^3 points (S = B + 2 ceil(P/2) - 1) and adds the tile into
-// the HBM grid with atomics (a point is shared by at most the neighbouring tiles' halos).
-// The LDS tile is float64 in both precisions: on gfx950 LDS atomic adds on 64-bit floats run
-// about 20x faster than on 32-bit floats, and the accumulation gains precision.
+// Particle kernels. A workgroup (4 waves) owns one tile of B^3 cells and an LDS copy of the
+// S^3 grid points its particles' supports touch (S = B + 2 ceil(P/2) - 1). Each wave works on
+// 4 particles at a time, 16 lanes per particle: the 16 lanes evaluate the particle's 3P window
+// polynomials (Horner, float64) into a per-wave LDS record, then share the P^2 (y, z) lines of
+// its support, each lane running the x-direction of its lines. Lanes of a particle touch
+// distinct lines (stride S, odd in practice), so their LDS accesses do not conflict, and no
+// workgroup barrier is needed between particles.
+// Window values, products and sums are float64 in both precisions: on MI355X a float64 FMA
+// issues at the non-packed float32 rate, and float32 window values and products lose ~1e-6
+// relative on systems of neutral molecules, where the grid values are small sums of larger
+// terms of both signs.
 // ------------------------------------------------------------------------------------
-constexpr int kSpreadBatch = 16;
+constexpr int kLanesPerParticle = 16;
+constexpr int kSlotsPerBlock = 16;  // 4 waves x 4 particles
 
+// Per-wave ordering of LDS accesses between lanes (the record written by one lane is read by
+// other lanes of the same wave).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Spreading (Alg. 2 step 1): the tile accumulates q w_x w_y w_z over the supports with LDS
+// float64 atomic adds (on gfx950 about 20x the throughput of float32 LDS atomics), then adds
+// the tile into the float64 HBM grid with atomics (a point lies in the halos of up to
+// ceil(S/B)^3 tiles; their partial sums are larger than the total on systems of neutral
+// molecules, so they are added in float64 and rounded once, by the first FFT pass).
 template <class T, int P>
 __global__ __launch_bounds__(256) void k_spread(const typename Vec4<T>::type* __restrict__ sorted,
                                                 const int* __restrict__ cells,
-                                                const int* __restrict__ tile_start, const T* __restrict__ coef,
-                                                int deg, int m, int B, int Tn, int S, T* __restrict__ grid) {
+                                                const int* __restrict__ tile_start, const double* __restrict__ coef,
+                                                int deg, int m, int B, int Tn, int S, double* __restrict__ grid) {
+  constexpr int REC = 3 * P;  // window values of one particle: x, y, z
   extern __shared__ unsigned char smem_raw[];
   double* acc = reinterpret_cast<double*>(smem_raw);
   const int S3 = S * S * S;
-  T* W = reinterpret_cast<T*>(acc + S3);     // kSpreadBatch * 3 * P weights
-  T* Q = W + kSpreadBatch * 3 * P;           // kSpreadBatch charges
-  int* O = reinterpret_cast<int*>(Q + kSpreadBatch);  // kSpreadBatch * 3 support offsets
+  double* recs = acc + S3;    // kSlotsPerBlock * REC
   const int tile = blockIdx.x;
   const int p0 = tile_start[tile], p1 = tile_start[tile + 1];
   if (p0 == p1) return;
   const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
-  const int T0[3] = {tx * B, ty * B, tz * B};
+  const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
   for (int i = threadIdx.x; i < S3; i += blockDim.x) acc[i] = 0.0;
   __syncthreads();
-  for (int pb = p0; pb < p1; pb += kSpreadBatch) {
-    const int nb = min(kSpreadBatch, p1 - pb);
-    for (int e = threadIdx.x; e < nb * 3 * P; e += blockDim.x) {
-      const int p = e / (3 * P), r = e - p * 3 * P, d = r / P, j = r - d * P;
-      const auto rec = sorted[pb + p];
-      const T f = d == 0 ? rec.x : (d == 1 ? rec.y : rec.z);
-      const int cp = cells[pb + p];
-      const int c = d == 0 ? cp % m : (d == 1 ? (cp / m) % m : cp / (m * m));
-      int o;
-      const T g = centred_offset<T, P>(f, c, T0[d], o);
-      const T* cj = coef + j * (deg + 1);
-      T v = cj[deg];
-      for (int k = deg - 1; k >= 0; --k) v = fma(v, g, cj[k]);
-      W[(p * 3 + d) * P + j] = v;
-      if (j == 0) {
-        O[p * 3 + d] = o;
-        if (d == 0) Q[p] = rec.w;
+  const int lane = threadIdx.x & 63;
+  const int slot = threadIdx.x >> 4;            // 0..15
+  const int li = lane & (kLanesPerParticle - 1);
+  double* rec = recs + slot * REC;
+  const int nt = p1 - p0;
+  for (int base = 0; base < nt; base += kSlotsPerBlock) {
+    const int pi = p0 + base + slot;
+    const bool active = pi < p1;
+    const auto r = sorted[active ? pi : p0];
+    const int cp = cells[active ? pi : p0];
+    int o[3];
+    double g[3];
+    g[0] = static_cast<double>(centred_offset<T, P>(r.x, cp % m, T0x, o[0]));
+    g[1] = static_cast<double>(centred_offset<T, P>(r.y, (cp / m) % m, T0y, o[1]));
+    g[2] = static_cast<double>(centred_offset<T, P>(r.z, cp / (m * m), T0z, o[2]));
+    for (int c = li; c < REC; c += kLanesPerParticle) {
+      const int d = c / P, j = c - d * P;
+      const double* cj = coef + j * (deg + 1);
+      const double gd = d == 0 ? g[0] : (d == 1 ? g[1] : g[2]);
+      double v = cj[deg];
+      for (int k = deg - 1; k >= 0; --k) v = fma(v, gd, cj[k]);
+      rec[c] = v;
+    }
+    wave_lds_sync();
+    if (active) {
+      double wx[P];
+#pragma unroll
+      for (int j = 0; j < P; ++j) wx[j] = rec[j];
+      const double q = static_cast<double>(r.w);
+      for (int e = li; e < P * P; e += kLanesPerParticle) {
+        const int jz = e / P, jy = e - jz * P;
+        const double wyz = q * rec[P + jy] * rec[2 * P + jz];
+        double* row = acc + ((o[2] + jz) * S + (o[1] + jy)) * S + o[0];
+#pragma unroll
+        for (int jx = 0; jx < P; ++jx) atomicAdd(row + jx, wyz * wx[jx]);
       }
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nb * P * P; e += blockDim.x) {
-      const int p = e / (P * P), r = e - p * P * P, jz = r / P, jy = r - jz * P;
-      const T wyz = Q[p] * W[(p * 3 + 2) * P + jz] * W[(p * 3 + 1) * P + jy];
-      const T* wx = W + (p * 3 + 0) * P;
-      double* row = acc + ((O[p * 3 + 2] + jz) * S + (O[p * 3 + 1] + jy)) * S + O[p * 3 + 0];
-#pragma unroll
-      for (int jx = 0; jx < P; ++jx) atomicAdd(row + jx, static_cast<double>(wyz * wx[jx]));
-    }
-    __syncthreads();
+    wave_lds_sync();
   }
+  __syncthreads();
   const int half = (P + 1) / 2;
-  const int Ox = T0[0] + 1 - half, Oy = T0[1] + 1 - half, Oz = T0[2] + 1 - half;
+  const int Ox = T0x + 1 - half, Oy = T0y + 1 - half, Oz = T0z + 1 - half;
   for (int i = threadIdx.x; i < S3; i += blockDim.x) {
-    const T v = static_cast<T>(acc[i]);
-    if (v == T(0)) continue;
+    const double v = acc[i];
+    if (v == 0.0) continue;
     const int ix = i % S, iy = (i / S) % S, iz = i / (S * S);
     const int gx = wrap_index(Ox + ix, m), gy = wrap_index(Oy + iy, m), gz = wrap_index(Oz + iz, m);
     atomic_add_global(grid + (static_cast<int64_t>(gz) * m + gy) * m + gx, v);
   }
 }
 
-// ------------------------------------------------------------------------------------
-// Interpolation (Alg. 2 step 5 and eq. force): one workgroup per tile stages the S^3 grid
-// values its particles touch in LDS; one thread per particle evaluates the tensor-product
-// sums as nested reductions (x, then y, then z) for phi and the three derivatives.
-// ------------------------------------------------------------------------------------
+// Interpolation (Alg. 2 step 5 and eq. force): phi = sum b w_x w_y w_z and its gradient as
+// nested sums: each lane runs the x-sums of its lines for the value and the x-derivative,
+// weights them with the y/z windows and derivatives, and the 16 lanes of a particle reduce.
 template <class T, int P>
-__global__ __launch_bounds__(128) void k_gather(const typename Vec4<T>::type* __restrict__ sorted,
+__global__ __launch_bounds__(256) void k_gather(const typename Vec4<T>::type* __restrict__ sorted,
                                                 const int* __restrict__ cells,
                                                 const int* __restrict__ perm, const int* __restrict__ tile_start,
-                                                const T* __restrict__ coef, int deg, int m, int B, int Tn, int S,
+                                                const double* __restrict__ coef, int deg, int m, int B, int Tn, int S,
                                                 const T* __restrict__ grid, T* __restrict__ phi, T* __restrict__ vec,
-                                                int vec_mode, T inv_h, double self_coef, int add_self,
+                                                int vec_mode, double inv_h, double self_coef, int add_self,
                                                 double* __restrict__ energy) {
+  constexpr int REC = 6 * P;  // values x, y, z then derivatives x, y, z (d/dg)
   extern __shared__ unsigned char smem_raw[];
-  T* tb = reinterpret_cast<T*>(smem_raw);
+  const int S3 = S * S * S;
+  double* recs = reinterpret_cast<double*>(smem_raw);              // kSlotsPerBlock * REC
+  T* tb = reinterpret_cast<T*>(recs + kSlotsPerBlock * REC);
   __shared__ double s_red[4];
   const int tile = blockIdx.x;
   const int p0 = tile_start[tile], p1 = tile_start[tile + 1];
@@ -288,74 +294,96 @@ __global__ __launch_bounds__(128) void k_gather(const typename Vec4<T>::type* __
   const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
   const int half = (P + 1) / 2;
   const int Ox = T0x + 1 - half, Oy = T0y + 1 - half, Oz = T0z + 1 - half;
-  const int S3 = S * S * S;
   for (int i = threadIdx.x; i < S3; i += blockDim.x) {
     const int ix = i % S, iy = (i / S) % S, iz = i / (S * S);
     const int gx = wrap_index(Ox + ix, m), gy = wrap_index(Oy + iy, m), gz = wrap_index(Oz + iz, m);
     tb[i] = grid[(static_cast<int64_t>(gz) * m + gy) * m + gx];
   }
   __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int slot = threadIdx.x >> 4;
+  const int li = lane & (kLanesPerParticle - 1);
+  double* rec = recs + slot * REC;
+  const int nt = p1 - p0;
   double esum = 0.0;
-  for (int pi = p0 + threadIdx.x; pi < p1; pi += blockDim.x) {
-    const auto rec = sorted[pi];
-    const int cp = cells[pi];
-    T wx[P], dx[P], wy[P], dy[P], wz[P], dz[P];
-    int ox, oy, oz;
-    window_values_deriv<T, P>(centred_offset<T, P>(rec.x, cp % m, T0x, ox), coef, deg, wx, dx);
-    window_values_deriv<T, P>(centred_offset<T, P>(rec.y, (cp / m) % m, T0y, oy), coef, deg, wy, dy);
-    window_values_deriv<T, P>(centred_offset<T, P>(rec.z, cp / (m * m), T0z, oz), coef, deg, wz, dz);
-    T ph = T(0), gx = T(0), gy = T(0), gz = T(0);
-    for (int jz = 0; jz < P; ++jz) {
-      T ty_ = T(0), tdy = T(0), tdx = T(0);
+  for (int base = 0; base < nt; base += kSlotsPerBlock) {
+    const int pi = p0 + base + slot;
+    const bool active = pi < p1;
+    const auto r = sorted[active ? pi : p0];
+    const int cp = cells[active ? pi : p0];
+    int o[3];
+    double g[3];
+    g[0] = static_cast<double>(centred_offset<T, P>(r.x, cp % m, T0x, o[0]));
+    g[1] = static_cast<double>(centred_offset<T, P>(r.y, (cp / m) % m, T0y, o[1]));
+    g[2] = static_cast<double>(centred_offset<T, P>(r.z, cp / (m * m), T0z, o[2]));
+    for (int c = li; c < 3 * P; c += kLanesPerParticle) {
+      const int d = c / P, j = c - d * P;
+      const double* cj = coef + j * (deg + 1);
+      const double gd = d == 0 ? g[0] : (d == 1 ? g[1] : g[2]);
+      double v = cj[deg], dv = 0.0;
+      for (int k = deg - 1; k >= 0; --k) {
+        dv = fma(dv, gd, v);
+        v = fma(v, gd, cj[k]);
+      }
+      rec[c] = v;
+      rec[3 * P + c] = dv;
+    }
+    wave_lds_sync();
+    double ph = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    if (active) {
+      double wx[P], dx[P];
 #pragma unroll
-      for (int jy = 0; jy < P; ++jy) {
-        const T* row = tb + ((oz + jz) * S + (oy + jy)) * S + ox;
-        T sx = T(0), sdx = T(0);
+      for (int j = 0; j < P; ++j) {
+        wx[j] = rec[j];
+        dx[j] = rec[3 * P + j];
+      }
+      for (int e = li; e < P * P; e += kLanesPerParticle) {
+        const int jz = e / P, jy = e - jz * P;
+        const T* row = tb + ((o[2] + jz) * S + (o[1] + jy)) * S + o[0];
+        double sx = 0.0, sdx = 0.0;
 #pragma unroll
         for (int jx = 0; jx < P; ++jx) {
-          const T b = row[jx];
+          const double b = static_cast<double>(row[jx]);
           sx = fma(b, wx[jx], sx);
           sdx = fma(b, dx[jx], sdx);
         }
-        ty_ = fma(sx, wy[jy], ty_);
-        tdy = fma(sx, dy[jy], tdy);
-        tdx = fma(sdx, wy[jy], tdx);
+        const double wy = rec[P + jy], dy = rec[4 * P + jy], wz = rec[2 * P + jz], dz = rec[5 * P + jz];
+        const double wyz = wy * wz;
+        ph = fma(sx, wyz, ph);
+        gx = fma(sdx, wyz, gx);
+        gy = fma(sx, dy * wz, gy);
+        gz = fma(sx, wy * dz, gz);
       }
-      // wz/dz indexed by a runtime jz: select from registers via a small unrolled search
-      T wzj = T(0), dzj = T(0);
+    }
 #pragma unroll
-      for (int j = 0; j < P; ++j)
-        if (j == jz) {
-          wzj = wz[j];
-          dzj = dz[j];
-        }
-      ph = fma(ty_, wzj, ph);
-      gz = fma(ty_, dzj, gz);
-      gy = fma(tdy, wzj, gy);
-      gx = fma(tdx, wzj, gx);
+    for (int off = kLanesPerParticle / 2; off > 0; off >>= 1) {
+      ph += __shfl_xor(ph, off, kLanesPerParticle);
+      gx += __shfl_xor(gx, off, kLanesPerParticle);
+      gy += __shfl_xor(gy, off, kLanesPerParticle);
+      gz += __shfl_xor(gz, off, kLanesPerParticle);
     }
-    const int idx = perm[pi];
-    double phd = static_cast<double>(ph);
-    if (add_self) phd -= self_coef * static_cast<double>(rec.w);
-    if (phi) phi[idx] = static_cast<T>(phd);
-    if (vec) {
-      const T s = vec_mode == 0 ? -rec.w * inv_h : inv_h;
-      vec[3 * idx + 0] = s * gx;
-      vec[3 * idx + 1] = s * gy;
-      vec[3 * idx + 2] = s * gz;
+    if (active && li == 0) {
+      const int idx = perm[pi];
+      const double qd = static_cast<double>(r.w);
+      double phd = ph;
+      if (add_self) phd -= self_coef * qd;
+      if (phi) phi[idx] = static_cast<T>(phd);
+      if (vec) {
+        const double sc = vec_mode == 0 ? -qd * inv_h : inv_h;
+        vec[3 * idx + 0] = static_cast<T>(sc * gx);
+        vec[3 * idx + 1] = static_cast<T>(sc * gy);
+        vec[3 * idx + 2] = static_cast<T>(sc * gz);
+      }
+      esum += qd * phd;
     }
-    esum += static_cast<double>(rec.w) * phd;
+    wave_lds_sync();
   }
   if (energy) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) esum += __shfl_xor(esum, o, 64);
-    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = esum;
+    for (int off = 32; off > 0; off >>= 1) esum += __shfl_xor(esum, off, 64);
+    if (lane == 0) s_red[threadIdx.x >> 6] = esum;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-      for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) s += s_red[w];
-      unsafeAtomicAdd(energy, 0.5 * s);
-    }
+    if (threadIdx.x == 0) unsafeAtomicAdd(energy, 0.5 * (s_red[0] + s_red[1] + s_red[2] + s_red[3]));
   }
 }
 
@@ -441,8 +469,8 @@ __device__ C* fft_lds(C* A, C* Bf, int nseq, int ss, const FftPlan& pl, const C*
 
 // x-direction real-to-complex FFT (sign +) of `nrows` rows of m reals via an m/2-point complex
 // FFT of (a_2j + i a_2j+1); writes X_k, k = 0..m/2, to spec. Optionally zeroes the input rows.
-template <class T>
-__global__ __launch_bounds__(256) void k_fft_x_r2c(const T* __restrict__ grid, T* zero_after, int m, int nrows,
+template <class T, class TI>
+__global__ __launch_bounds__(256) void k_fft_x_r2c(const TI* __restrict__ grid, TI* zero_after, int m, int nrows,
                                                    int rpb, FftPlan pl, const typename Cplx<T>::type* __restrict__ tw_half,
                                                    const typename Cplx<T>::type* __restrict__ tw_full,
                                                    typename Cplx<T>::type* __restrict__ spec) {
@@ -453,11 +481,14 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(const T* __restrict__ grid, T
   C* Bf = A + rpb * N;
   const int row0 = blockIdx.x * rpb;
   const int nr = min(rpb, nrows - row0);
-  const C* src = reinterpret_cast<const C*>(grid + static_cast<int64_t>(row0) * m);
-  C* zsrc = zero_after ? reinterpret_cast<C*>(zero_after + static_cast<int64_t>(row0) * m) : nullptr;
+  const TI* src = grid + static_cast<int64_t>(row0) * m;
+  TI* zsrc = zero_after ? zero_after + static_cast<int64_t>(row0) * m : nullptr;
   for (int e = threadIdx.x; e < nr * N; e += blockDim.x) {
-    A[e] = src[e];
-    if (zsrc) zsrc[e] = C{T(0), T(0)};
+    A[e] = C{static_cast<T>(src[2 * e]), static_cast<T>(src[2 * e + 1])};
+    if (zsrc) {
+      zsrc[2 * e] = TI(0);
+      zsrc[2 * e + 1] = TI(0);
+    }
   }
   __syncthreads();
   const C* Z = fft_lds(A, Bf, nr, N, pl, tw_half);
@@ -586,12 +617,16 @@ hipError_t bin_impl(const DevPlan& d, int64_t n, const void* pos, const void* q,
 
 template <class T, int P>
 hipError_t spread_impl(const DevPlan& d, void* grid, hipStream_t st) {
-  const size_t lds = sizeof(double) * static_cast<size_t>(d.S) * d.S * d.S +
-                     sizeof(T) * (kSpreadBatch * 3 * P + kSpreadBatch) + sizeof(int) * kSpreadBatch * 3;
+  const size_t lds = sizeof(double) * (static_cast<size_t>(d.S) * d.S * d.S + kSlotsPerBlock * 3 * P);
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<T, P>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+  }
   stage_begin(d, kStageSpread, st);
   hipLaunchKernelGGL((k_spread<T, P>), dim3(d.ntiles), dim3(256), lds, st,
                      static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start,
-                     static_cast<const T*>(d.coef), d.deg, d.m, d.B, d.Tn, d.S, static_cast<T*>(grid));
+                     static_cast<const double*>(d.coef), d.deg, d.m, d.B, d.Tn, d.S, static_cast<double*>(grid));
   stage_end(d, kStageSpread, st);
   return hipGetLastError();
 }
@@ -599,12 +634,17 @@ hipError_t spread_impl(const DevPlan& d, void* grid, hipStream_t st) {
 template <class T, int P>
 hipError_t gather_impl(const DevPlan& d, const void* grid, void* phi, void* vec, int vec_mode, bool add_self,
                        double* energy, hipStream_t st) {
-  const size_t lds = sizeof(T) * static_cast<size_t>(d.S) * d.S * d.S;
+  const size_t lds = sizeof(double) * kSlotsPerBlock * 6 * P + sizeof(T) * static_cast<size_t>(d.S) * d.S * d.S;
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<T, P>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+  }
   stage_begin(d, kStageGather, st);
-  hipLaunchKernelGGL((k_gather<T, P>), dim3(d.ntiles), dim3(128), lds, st,
+  hipLaunchKernelGGL((k_gather<T, P>), dim3(d.ntiles), dim3(256), lds, st,
                      static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.perm, d.tile_start,
-                     static_cast<const T*>(d.coef), d.deg, d.m, d.B, d.Tn, d.S, static_cast<const T*>(grid),
-                     static_cast<T*>(phi), static_cast<T*>(vec), vec_mode, static_cast<T>(d.inv_h), d.self_coef,
+                     static_cast<const double*>(d.coef), d.deg, d.m, d.B, d.Tn, d.S, static_cast<const T*>(grid),
+                     static_cast<T*>(phi), static_cast<T*>(vec), vec_mode, d.inv_h, d.self_coef,
                      add_self ? 1 : 0, energy);
   stage_end(d, kStageGather, st);
   return hipGetLastError();
@@ -626,7 +666,8 @@ hipError_t gather_dispatch(const DevPlan& d, const void* grid, void* phi, void* 
 }
 
 template <class T>
-hipError_t transform_impl(const DevPlan& d, const void* grid_in, void* grid_out, bool zero_input, hipStream_t st) {
+hipError_t transform_impl(const DevPlan& d, const void* grid_in, bool in_f64, void* grid_out, bool zero_input,
+                          hipStream_t st) {
   using C = typename Cplx<T>::type;
   const int m = d.m, N = m / 2, nx1 = N + 1, nrows = m * m;
   C* spec = static_cast<C*>(d.spec);
@@ -638,9 +679,15 @@ hipError_t transform_impl(const DevPlan& d, const void* grid_in, void* grid_out,
   const C* twfp = static_cast<const C*>(d.tw_full_p);
   const C* twfm = static_cast<const C*>(d.tw_full_m);
   stage_begin(d, kStageFftX, st);
-  hipLaunchKernelGGL(k_fft_x_r2c<T>, dim3(blocks_for(nrows, rpb)), dim3(256), lds_x, st,
-                     static_cast<const T*>(grid_in), zero_input ? static_cast<T*>(const_cast<void*>(grid_in)) : nullptr,
-                     m, nrows, rpb, d.fft_half, twhp, twfp, spec);
+  if (in_f64)
+    hipLaunchKernelGGL((k_fft_x_r2c<T, double>), dim3(blocks_for(nrows, rpb)), dim3(256), lds_x, st,
+                       static_cast<const double*>(grid_in),
+                       zero_input ? static_cast<double*>(const_cast<void*>(grid_in)) : nullptr, m, nrows, rpb,
+                       d.fft_half, twhp, twfp, spec);
+  else
+    hipLaunchKernelGGL((k_fft_x_r2c<T, T>), dim3(blocks_for(nrows, rpb)), dim3(256), lds_x, st,
+                       static_cast<const T*>(grid_in), zero_input ? static_cast<T*>(const_cast<void*>(grid_in)) : nullptr,
+                       m, nrows, rpb, d.fft_half, twhp, twfp, spec);
   stage_end(d, kStageFftX, st);
   const dim3 gcols(blocks_for(nx1, cpb), m);
   // y forward: outer = z plane, element stride nx1
@@ -684,9 +731,32 @@ hipError_t launch_zero(const DevPlan& d, void* buf, int64_t count, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_transform(const DevPlan& d, const void* grid_in, void* grid_out, bool zero_input, hipStream_t st) {
-  return d.prec == 0 ? transform_impl<float>(d, grid_in, grid_out, zero_input, st)
-                     : transform_impl<double>(d, grid_in, grid_out, zero_input, st);
+hipError_t launch_transform(const DevPlan& d, const void* grid_in, bool in_f64, void* grid_out, bool zero_input,
+                            hipStream_t st) {
+  return d.prec == 0 ? transform_impl<float>(d, grid_in, in_f64, grid_out, zero_input, st)
+                     : transform_impl<double>(d, grid_in, true, grid_out, zero_input, st);
+}
+
+// Copies the float64 accumulation grid into a grid of the plan's precision and zeroes it.
+template <class T>
+__global__ void k_drain(double* __restrict__ acc, T* __restrict__ out, int64_t count) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    out[i] = static_cast<T>(acc[i]);
+    acc[i] = 0.0;
+  }
+}
+
+hipError_t launch_drain(const DevPlan& d, void* out, hipStream_t st) {
+  const int64_t count = static_cast<int64_t>(d.m) * d.m * d.m;
+  const unsigned nb = std::max(1u, std::min<unsigned>(blocks_for(count, 256), 4096u));
+  if (d.prec == 0)
+    hipLaunchKernelGGL(k_drain<float>, dim3(nb), dim3(256), 0, st, static_cast<double*>(d.grid_a),
+                       static_cast<float*>(out), count);
+  else
+    hipLaunchKernelGGL(k_drain<double>, dim3(nb), dim3(256), 0, st, static_cast<double*>(d.grid_a),
+                       static_cast<double*>(out), count);
+  return hipGetLastError();
 }
 
 hipError_t launch_gather(const DevPlan& d, int64_t n, const void* grid, void* phi, void* vec, int vec_mode,

@@ -53,7 +53,7 @@ struct DevPlan {
   void* sorted = nullptr;      // n_max x 4 T: (f_x, f_y, f_z, q), fractional cell offsets in [0, 1]
   int* cells = nullptr;        // n_max: packed cell cx + m (cy + m cz) of each sorted particle
   // grids
-  void* grid_a = nullptr;      // m^3 T, spread target; kept all-zero between calls
+  void* grid_a = nullptr;      // m^3 float64 spread target (both precisions); kept all-zero between calls
   void* grid_b = nullptr;      // m^3 T, transformed grid
   void* spec = nullptr;        // m * m * (m/2 + 1) complex T
   // tables (plan precision)
@@ -85,9 +85,13 @@ inline void stage_end(const DevPlan& d, int stage, hipStream_t st) {
 // Pipeline pieces (all enqueue on `stream`, return hipSuccess or the launch error).
 hipError_t launch_bin(const DevPlan& d, int64_t n, const void* pos, const void* q, double* energy_zero,
                       hipStream_t stream);
+// Spreads the binned particles into the float64 grid d.grid_a.
 hipError_t launch_spread(const DevPlan& d, void* grid, hipStream_t stream);
+// Copies d.grid_a into `out` (plan precision) and zeroes d.grid_a.
+hipError_t launch_drain(const DevPlan& d, void* out, hipStream_t stream);
 hipError_t launch_zero(const DevPlan& d, void* buf, int64_t count, hipStream_t stream);
-hipError_t launch_transform(const DevPlan& d, const void* grid_in, void* grid_out, bool zero_input,
+// grid_in is float64 when in_f64 (always for float64 plans), else the plan precision.
+hipError_t launch_transform(const DevPlan& d, const void* grid_in, bool in_f64, void* grid_out, bool zero_input,
                             hipStream_t stream);
 // vec_mode: 0 writes force -q grad(phi), 1 writes grad(phi). add_self adds -self_coef q to phi.
 hipError_t launch_gather(const DevPlan& d, int64_t n, const void* grid, void* phi, void* vec, int vec_mode,

@@ -82,8 +82,28 @@ def test_spread_matches_oracle(case, prec):
     g = plan.spread(tdev(x, prec), tdev(q, prec)).cpu().numpy()       # [z, y, x]
     a = fast.spread(np.mod(x, L), q, o).transpose(2, 1, 0)              # oracle [x, y, z] -> [z, y, x]
     A = fast.spread(np.mod(x, L), np.abs(q), o).transpose(2, 1, 0)      # sum of |terms|
-    tol = 4 * fit_tol(eps, prec) * A + 64 * U[prec] * A + 1e-300
+    # window values and sums are float64 on both paths; the float32 path rounds the grid values
+    # and the fractional offsets (x/h - floor(x/h), kept to the working precision relative to 1)
+    tol = 4 * fit_tol(eps, prec) * A + 8 * U[prec] * A + 1e-300
     assert np.all(np.abs(g - a) <= tol), float(np.max(np.abs(g - a) / (A + 1e-300)))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_single_charge_window_precision(prec):
+    """One unit charge far from the origin (x/h ~ m): every grid value of its support within a few
+    units of roundoff of the oracle's window product. Guards the compensated x/h of the binning
+    step (a fused multiply-add contracted into it once doubled the product's rounding error)."""
+    L = 6.688006779947665
+    c, o = both_params(1e-6, L, m=64)
+    plan = pw.Plan(c, prec, n_max=1)
+    rng = np.random.Generator(np.random.PCG64(11))
+    worst = 0.0
+    for _ in range(12):
+        x = rounded(L - rng.random((1, 3)) * 0.25 * L, prec)
+        g = plan.spread(tdev(x, prec), tdev(np.ones(1), prec)).cpu().numpy()
+        a = fast.spread(np.mod(x, L), np.ones(1), o).transpose(2, 1, 0)
+        worst = max(worst, float(np.max(np.abs(g - a))))
+    assert worst < (4 * fit_tol(1e-6, prec) + 8 * U[prec]), worst
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
