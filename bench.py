@@ -4,9 +4,10 @@ Workload: water-like box of 10,000 rigid 3-site molecules (n = 30,000 charges, L
 1 g/cm^3, SPC/E-like charges), eps = 1e-6 absolute RMS with the parameters of Alg. 3 on a 64^3
 grid (P = 13). One step = one full pass of the pipeline (binning, spreading, FFT with fused
 scaling, inverse FFT, interpolation of phi and forces, self term and energy) on inputs resident
-in HBM. The headline value is the float32 path; the float64 path is timed on the same system.
+in HBM. The headline value is the float32 path; the float64 path is timed on the same system,
+and a batch of 256 independent systems is timed batched (one HIP graph) and sequentially.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -72,12 +73,89 @@ def cpu_baseline(x, q, L, eps, m):
                       f"NumPy, phi and gradients) taking {dt:.2f} s on 1 thread"}
 
 
+def bench_ensemble(steps: int, warmup: int):
+    """Batched vs sequential: 256 independent neutral systems (n log-uniform in [500, 20000],
+    L uniform in [0.5, 2], uniform positions, +-1 charges), each with its own eps = 1e-6
+    parameters (Alg. 3, relative mode, 64-neighbour cutoff rule), float32, phi + forces +
+    energies. Batched: one plan over all systems, tiles from the autotuner, replayed as one HIP
+    graph (and, for reference, called eagerly). Sequential: one default plan per system, called
+    one after another."""
+    import numpy as np
+    import torch
+    import paper_2602_16591_amd as pw
+    import workloads as W
+    from paper_2602_16591_amd.autotune import autotune_batch
+
+    dev = torch.device("cuda:0")
+    ens = W.ensemble()
+    params = [pw.choose_params(1e-6, L, n=len(q)) for _, q, L in ens]
+    counts = [len(q) for _, q, _ in ens]
+    n_total = sum(counts)
+    X = torch.as_tensor(np.concatenate([x for x, _, _ in ens]), dtype=torch.float32, device=dev)
+    Q = torch.as_tensor(np.concatenate([q for _, q, _ in ens]), dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    plan, tiles, report = autotune_batch(params, counts, X, Q, "fp32", targets=(64, 256, 1024), reps=5)
+    tune_s = time.perf_counter() - t0
+    runner = plan.graph(X, Q)
+
+    def timed(fn, k):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / k
+
+    g_s = timed(runner, steps)
+    phi = torch.empty(n_total, dtype=torch.float32, device=dev)
+    F = torch.empty((n_total, 3), dtype=torch.float32, device=dev)
+    E = torch.empty(len(ens), dtype=torch.float64, device=dev)
+    e_s = timed(lambda: plan.compute(X, Q, phi=phi, force=F, energy=E), steps)
+    stage_ms = {}
+    for st in STAGES:
+        plan.timing_enable(st, 8)
+        for _ in range(4):
+            plan.compute(X, Q, phi=phi, force=F, energy=E)
+        ms, calls = plan.timing_read()
+        stage_ms[st] = ms / max(calls, 1)
+    plan.timing_enable(None)
+    singles = [pw.Plan(p, "fp32", n_max=c) for p, c in zip(params, counts)]
+    views = [(X[o:o + c], Q[o:o + c], phi[o:o + c], F[o:o + c], E[k:k + 1])
+             for k, (o, c) in enumerate(zip(plan.offsets, plan.counts))]
+
+    def sequential():
+        for sp, (x, q, ph, f, e) in zip(singles, views):
+            sp.compute(x, q, phi=ph, force=f, energy=e)
+
+    s_s = timed(sequential, max(2, steps // 4))
+    for sp in singles:
+        sp.close()
+    P_counts = {}
+    for p in params:
+        P_counts[p.P] = P_counts.get(p.P, 0) + 1
+    return {
+        "workload": "ensemble_256_systems", "n_total": n_total, "systems": len(ens),
+        "m_range": [min(p.m for p in params), max(p.m for p in params)], "P_counts": P_counts,
+        "batched_graph": {"value": n_total / g_s, "unit": "particles/s", "ms_per_step": g_s * 1e3},
+        "batched_eager": {"value": n_total / e_s, "unit": "particles/s", "ms_per_step": e_s * 1e3},
+        "sequential": {"value": n_total / s_s, "unit": "particles/s", "ms_per_step": s_s * 1e3,
+                       "plans": len(singles)},
+        "speedup_graph_vs_sequential": s_s / g_s,
+        "autotune": {"seconds": tune_s, "candidates": [{"target": t, "ms": ms} for t, _, ms in report],
+                     "tiles_hist": {str(b): tiles.count(b) for b in sorted(set(tiles))}},
+        "stage_us_batched": {k: v * 1e3 for k, v in stage_ms.items()},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-sequential ensemble")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the pipeline runs on a single MI355X; "
@@ -169,6 +247,8 @@ def main():
         "fp32_vs_fp64": {"phi_rel_l2": phi_diff, "phi_abs_rms": phi_abs, "force_rel_l2": F_diff,
                          "energy_rel": abs(r["E"] - r64["E"]) / abs(r64["E"])},
     }
+    if not args.no_batched:
+        out["batched"] = bench_ensemble(max(5, min(args.steps, 50)), max(2, min(args.warmup, 5)))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, q, L, eps, m)
     print(json.dumps(out), flush=True)

@@ -105,7 +105,7 @@ pswfe_status pswfe_plan_create(const pswfe_params* p, int32_t prec, int64_t n_ma
 pswfe_status pswfe_plan_create_tiled(const pswfe_params* p, int32_t prec, int64_t n_max, int32_t tile,
                                      pswfe_plan** out);
 
-/* Tile edge a plan uses (0 for NULL). */
+/* Tile edge a plan uses (system 0 of a batch; 0 for NULL). */
 int32_t pswfe_plan_tile(const pswfe_plan* plan);
 
 /* Frees the plan and its device buffers (synchronises the device first). NULL is a no-op. */
@@ -127,6 +127,48 @@ pswfe_status pswfe_compute(pswfe_plan* plan, int64_t n, const void* pos, const v
  * A g, and d/dx_i of g^T A q = g_i grad phi_i[q] + q_i grad phi_i[g], A symmetric, eq. matform). */
 pswfe_status pswfe_compute_grad(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi,
                                 void* grad, double* energy, void* stream);
+
+/* Batches of independent systems (each its own box, parameters and particles; Alg. 2 applied
+ * to each with its own parameters, as a single-system plan would). All systems share the
+ * precision. Binning and each FFT pass run as one kernel launch over all systems; spreading
+ * and interpolation run one launch per distinct window support P among the systems. A batch
+ * call therefore enqueues a fixed handful of launches, whatever the number of systems, and
+ * can be captured into one HIP graph.
+ *   nsys     number of systems, 1 <= nsys <= 2^20
+ *   params   host array of nsys parameter sets (pswfe_choose_params per system)
+ *   counts   host array of nsys particle counts (>= 0, sum < 2^31); fixed for the plan
+ *   prec     pswfe_prec
+ *   tiles    host array of nsys tile edges (as pswfe_plan_create_tiled; 0 = default: about 256
+ *            particles per tile on average), or NULL for all defaults
+ *   out      host pointer receiving the plan; NULL on failure.
+ * The particles of system s occupy the packed rows [offset_s, offset_s + counts[s]) of every
+ * particle array, offset_s = counts[0] + ... + counts[s-1]. */
+pswfe_status pswfe_batch_plan_create(int32_t nsys, const pswfe_params* params, const int64_t* counts,
+                                     int32_t prec, const int32_t* tiles, pswfe_plan** out);
+
+/* pswfe_compute for every system of a batch plan:
+ *   pos     device, N x 3 packed positions, N = sum of counts; system s's rows are wrapped mod L_s
+ *   q       device, N packed charges (each system should be neutral)
+ *   phi     device, N outputs (or NULL);  force: device, N x 3 outputs (or NULL)
+ *   energy  device, nsys doubles, energy of each system (or NULL)
+ * A plan from pswfe_plan_create is rejected (PSWFE_E_ARG), as are batch plans passed to the
+ * single-system entry points. */
+pswfe_status pswfe_batch_compute(pswfe_plan* plan, const void* pos, const void* q, void* phi, void* force,
+                                 double* energy, void* stream);
+
+/* As pswfe_batch_compute with grad phi_far (N x 3) in place of the forces (see
+ * pswfe_compute_grad). */
+pswfe_status pswfe_batch_compute_grad(pswfe_plan* plan, const void* pos, const void* q, void* phi, void* grad,
+                                      double* energy, void* stream);
+
+/* Number of systems of a plan (1 for single-system plans, 0 for NULL). */
+int32_t pswfe_plan_num_systems(const pswfe_plan* plan);
+
+/* Host description of system s of a plan: its parameters, the first packed row, the particle
+ * count (single-system plans: 0 and n_max) and the tile edge; any output may be NULL.
+ * s out of range -> PSWFE_E_ARG. */
+pswfe_status pswfe_plan_system(const pswfe_plan* plan, int32_t s, pswfe_params* params, int64_t* offset,
+                               int64_t* count, int32_t* tile);
 
 /* Alg. 2 step 1 alone (eq. spread_def): grid[(lz*m + ly)*m + lx] = sum_j q_j
  * phitilde(x_j - h l) for the m^3 grid points, written to the device array `grid`
@@ -168,7 +210,7 @@ pswfe_status pswfe_host_tables(const pswfe_params* p, int32_t prec, double* tm, 
 pswfe_status pswfe_timing_enable(pswfe_plan* plan, int32_t stage, int32_t max_calls);
 pswfe_status pswfe_timing_read(pswfe_plan* plan, double* total_ms, int64_t* calls);
 
-/* Effective parameters of a plan (host copy). */
+/* Effective parameters of a plan (host copy; system 0 of a batch). */
 pswfe_status pswfe_plan_params(const pswfe_plan* plan, pswfe_params* out);
 
 /* Static description of a string for a status code (never NULL). */

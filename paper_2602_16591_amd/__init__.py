@@ -54,6 +54,13 @@ SIGNATURES = {
     "pswfe_transform": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "pswfe_interpolate": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp]),
     "pswfe_plan_params": (ctypes.c_int, [_vp, ctypes.POINTER(CParams)]),
+    "pswfe_batch_plan_create": (ctypes.c_int, [_i32, ctypes.POINTER(CParams), ctypes.POINTER(ctypes.c_int64), _i32,
+                                               ctypes.POINTER(ctypes.c_int32), _PPlan]),
+    "pswfe_batch_compute": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "pswfe_batch_compute_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "pswfe_plan_num_systems": (ctypes.c_int32, [_vp]),
+    "pswfe_plan_system": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(CParams), ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
     "pswfe_host_pswf": (ctypes.c_int, [_d, _d, _vp, _vp, _vp, _vp]),
     "pswfe_host_tables": (ctypes.c_int, [ctypes.POINTER(CParams), _i32, _vp, _i64, _vp, _i64, _vp, _i64, _vp]),
     "pswfe_timing_enable": (ctypes.c_int, [_vp, _i32, _i32]),
@@ -137,31 +144,42 @@ def _ptr(t, dtype, shape_tail, name):
     return t.data_ptr()
 
 
+def _out(spec, shape, dtype, device):
+    """An output buffer: the tensor passed, a new tensor (True) or None (False/None)."""
+    import torch
+    if isinstance(spec, torch.Tensor):
+        return spec
+    return torch.empty(shape, dtype=dtype, device=device) if spec else None
+
+
 def _stream_ptr(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
 
 
-class Plan:
-    """Device plan for one parameter set, precision and maximum particle count."""
+def _prec(prec):
+    p = {"fp32": FP32, "fp64": FP64}.get(prec, prec)
+    if p not in (FP32, FP64):
+        raise ValueError(f"unknown precision {prec!r}")
+    return p
 
-    def __init__(self, params: CParams, prec: int | str = FP32, n_max: int = 0, tile: int = 0):
+
+class _PlanBase:
+    _h = ctypes.c_void_p()
+
+    def _init_common(self, prec):
         import torch
-        self.prec = {"fp32": FP32, "fp64": FP64}.get(prec, prec)
+        self.prec = _prec(prec)
         self.dtype = torch.float32 if self.prec == FP32 else torch.float64
-        self.n_max = int(n_max)
         self._h = ctypes.c_void_p()
-        _check(_lib().pswfe_plan_create_tiled(ctypes.byref(params), int(self.prec), self.n_max, int(tile),
-                                              ctypes.byref(self._h)), "pswfe_plan_create_tiled")
-        self.tile = int(_lib().pswfe_plan_tile(self._h))
-        p = CParams()
-        _check(_lib().pswfe_plan_params(self._h, ctypes.byref(p)), "pswfe_plan_params")
-        self.params = p
 
-    @property
-    def m(self) -> int:
-        return self.params.m
+    def system(self, s: int):
+        """(effective parameters, first packed row, particle count, tile edge) of system s."""
+        p, off, cnt, tile = CParams(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(_lib().pswfe_plan_system(self._h, int(s), ctypes.byref(p), ctypes.byref(off), ctypes.byref(cnt),
+                                        ctypes.byref(tile)), "pswfe_plan_system")
+        return p, off.value, cnt.value, tile.value
 
     def close(self):
         if self._h:
@@ -188,6 +206,29 @@ class Plan:
         _check(_lib().pswfe_timing_read(self._h, ctypes.byref(ms), ctypes.byref(n)), "pswfe_timing_read")
         return ms.value, n.value
 
+    def graph(self, pos, q, **kw):
+        """This plan's compute call on (pos, q) captured into a HIP graph; see CapturedCompute."""
+        from .graph import CapturedCompute
+        return CapturedCompute(self, pos, q, **kw)
+
+
+class Plan(_PlanBase):
+    """Device plan for one parameter set, precision and maximum particle count."""
+
+    def __init__(self, params: CParams, prec: int | str = FP32, n_max: int = 0, tile: int = 0):
+        self._init_common(prec)
+        self.n_max = int(n_max)
+        _check(_lib().pswfe_plan_create_tiled(ctypes.byref(params), int(self.prec), self.n_max, int(tile),
+                                              ctypes.byref(self._h)), "pswfe_plan_create_tiled")
+        self.tile = int(_lib().pswfe_plan_tile(self._h))
+        p = CParams()
+        _check(_lib().pswfe_plan_params(self._h, ctypes.byref(p)), "pswfe_plan_params")
+        self.params = p
+
+    @property
+    def m(self) -> int:
+        return self.params.m
+
     def _n(self, pos):
         n = int(pos.shape[0])
         if n > self.n_max:
@@ -201,15 +242,9 @@ class Plan:
         unless tensors are passed in place of True."""
         import torch
         n = self._n(pos)
-        dev = pos.device
-        def out(spec, shape, dtype):
-            if isinstance(spec, torch.Tensor):
-                return spec
-            return torch.empty(shape, dtype=dtype, device=dev) if spec else None
-
-        phi_t = out(phi, (n,), self.dtype)
-        vec_t = out(force if not grad else grad, (n, 3), self.dtype)
-        e_t = out(energy, (1,), torch.float64)
+        phi_t = _out(phi, (n,), self.dtype, pos.device)
+        vec_t = _out(force if not grad else grad, (n, 3), self.dtype, pos.device)
+        e_t = _out(energy, (1,), torch.float64, pos.device)
         fn = _lib().pswfe_compute_grad if grad else _lib().pswfe_compute
         _check(fn(self._h, n, _ptr(pos, self.dtype, (3,), "pos"), _ptr(q, self.dtype, None, "q"),
                   _ptr(phi_t, self.dtype, None, "phi"), _ptr(vec_t, self.dtype, (3,), "force"),
@@ -246,6 +281,53 @@ class Plan:
                                         _ptr(grid, self.dtype, None, "grid"), _ptr(phi, self.dtype, None, "phi"),
                                         _ptr(g, self.dtype, (3,), "grad"), _stream_ptr(stream)), "pswfe_interpolate")
         return phi, g
+
+
+class BatchPlan(_PlanBase):
+    """Device plan for a batch of independent systems (own box, parameters and particle count
+    each), run by one launch per pipeline stage. Particle arrays are packed: system s owns rows
+    offsets[s] .. offsets[s] + counts[s] - 1."""
+
+    def __init__(self, params, counts, prec: int | str = FP32, tiles=None):
+        self._init_common(prec)
+        params = list(params)
+        counts = [int(c) for c in counts]
+        ns = len(params)
+        if ns == 0 or len(counts) != ns or (tiles is not None and len(tiles) != ns):
+            raise ValueError("params, counts (and tiles) must be non-empty and of equal length")
+        arr = (CParams * ns)(*params)
+        cnt = (ctypes.c_int64 * ns)(*counts)
+        tl = (ctypes.c_int32 * ns)(*[int(t) for t in tiles]) if tiles is not None else None
+        _check(_lib().pswfe_batch_plan_create(ns, arr, cnt, int(self.prec), tl, ctypes.byref(self._h)),
+               "pswfe_batch_plan_create")
+        self.nsys = int(_lib().pswfe_plan_num_systems(self._h))
+        info = [self.system(s) for s in range(self.nsys)]
+        self.params = [i[0] for i in info]
+        self.offsets = [i[1] for i in info]
+        self.counts = [i[2] for i in info]
+        self.tiles = [i[3] for i in info]
+        self.n_total = sum(self.counts)
+        self.P = self.params[0].P
+
+    def compute(self, pos, q, *, phi=True, force=True, energy=True, grad=False, stream=None):
+        """Every system at once. pos (N, 3), q (N,) packed; returns (phi (N,), vec (N, 3),
+        energy (nsys,) float64) with None for outputs not requested (or the tensors passed)."""
+        import torch
+        if int(pos.shape[0]) != self.n_total or int(q.shape[0]) != self.n_total:
+            raise ValueError(f"packed arrays must have {self.n_total} rows")
+        n = self.n_total
+        phi_t = _out(phi, (n,), self.dtype, pos.device)
+        vec_t = _out(force if not grad else grad, (n, 3), self.dtype, pos.device)
+        e_t = _out(energy, (self.nsys,), torch.float64, pos.device)
+        fn = _lib().pswfe_batch_compute_grad if grad else _lib().pswfe_batch_compute
+        _check(fn(self._h, _ptr(pos, self.dtype, (3,), "pos"), _ptr(q, self.dtype, None, "q"),
+                  _ptr(phi_t, self.dtype, None, "phi"), _ptr(vec_t, self.dtype, (3,), "force"),
+                  _ptr(e_t, torch.float64, None, "energy"), _stream_ptr(stream)), "pswfe_batch_compute")
+        return phi_t, vec_t, e_t
+
+    def split(self, a):
+        """Per-system views of a packed array."""
+        return [a[o:o + c] for o, c in zip(self.offsets, self.counts)]
 
 
 @dataclass

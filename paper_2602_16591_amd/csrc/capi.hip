@@ -13,11 +13,14 @@
 #include "kernels.hpp"
 
 struct pswfe_plan {
-  pswfe::Params p;
-  pswfe::Tables tab;
+  std::vector<pswfe::Params> p;   // effective parameters of each system
+  std::vector<pswfe::Tables> tab; // host tables of each system
+  std::vector<int64_t> count;     // batch plans: particles of each system
+  bool batch = false;             // created by pswfe_batch_plan_create
   pswfe::DevPlan d;
   pswfe::StageTimer timer;
   int device = 0;
+  std::vector<void*> allocs;      // device allocations owned by the plan
 };
 
 namespace {
@@ -59,40 +62,43 @@ pswfe::FftPlan make_fft_plan(int N) {
 // Tile edge B (cells) for binning, spreading and interpolation. The spreading tile holds
 // S^3 float64 accumulators (S = B + 2 ceil(P/2) - 1), at most 150 KiB; the interpolation tile
 // S^3 values of the plan precision plus the window records of 16 particles, at most 156 KiB.
-// Default: B = 8 (measured best on gfx950 for 64^3 and 128^3 grids with P = 12-18), reduced to
-// fit the LDS limits and to give at least 64 tiles on small grids.
+size_t spread_lds_bytes(int S, int P) { return sizeof(double) * (static_cast<size_t>(S) * S * S + 16 * 3 * P); }
 size_t gather_lds_bytes(int S, int P, int elem) {
   return static_cast<size_t>(elem) * S * S * S + sizeof(double) * 16 * 6 * P;
 }
+int lds_edge(int B, int P) { return B + 2 * ((P + 1) / 2) - 1; }
 
 bool tile_fits(int B, int P, int elem) {
-  const int S = B + 2 * ((P + 1) / 2) - 1;
-  return 8.0 * (static_cast<double>(S) * S * S + 16 * 3 * P) <= 150.0 * 1024 &&
-         gather_lds_bytes(S, P, elem) <= 156 * 1024;
+  const int S = lds_edge(B, P);
+  return spread_lds_bytes(S, P) <= 150 * 1024 && gather_lds_bytes(S, P, elem) <= 156 * 1024;
 }
 
-int choose_tile(int m, int P, int requested, int elem) {
+// Single systems: B = 8 (measured best on gfx950 for 64^3 and 128^3 grids with P = 12-18),
+// reduced to give at least 4 tiles per dimension on small grids. Batches: the smallest B with
+// about 256 particles per tile on average (many small systems fill the chip together, so
+// tiles are sized for work per tile rather than tile count). Both are then reduced until
+// the LDS limits hold.
+int choose_tile(int m, int P, int requested, int elem, int64_t n_batch) {
   int B = requested;
-  if (B <= 0) {
+  if (B <= 0 && n_batch < 0) {
     if (const char* env = std::getenv("PSWFE_TILE")) B = std::atoi(env);
   }
   if (B <= 0) {
-    B = 8;
-    while (B > 2 && (m + B - 1) / B < 4) --B;
+    if (n_batch < 0) {
+      B = 8;
+      while (B > 2 && (m + B - 1) / B < 4) --B;
+    } else {
+      const double cells_per_tile = 256.0 * m * m * m / std::max<double>(static_cast<double>(n_batch), 1.0);
+      B = static_cast<int>(std::ceil(std::cbrt(cells_per_tile)));
+      B = std::max(4, B);
+    }
   }
   B = std::max(2, std::min(B, m));
   while (B > 2 && !tile_fits(B, P, elem)) --B;
   return B;
 }
 
-template <class T>
-pswfe_status upload(const std::vector<double>& src, void** dst) {
-  std::vector<T> tmp(src.begin(), src.end());
-  if (hipMalloc(dst, sizeof(T) * std::max<size_t>(tmp.size(), 1)) != hipSuccess) return PSWFE_E_ALLOC;
-  if (!tmp.empty() && hipMemcpy(*dst, tmp.data(), sizeof(T) * tmp.size(), hipMemcpyHostToDevice) != hipSuccess)
-    return PSWFE_E_HIP;
-  return PSWFE_OK;
-}
+double fit_tolerance(double eps, int prec) { return std::max(0.01 * eps, prec == PSWFE_FP32 ? 5e-9 : 1e-15); }
 
 void free_timer(pswfe::StageTimer& t) {
   if (t.ev) {
@@ -103,11 +109,263 @@ void free_timer(pswfe::StageTimer& t) {
   t = pswfe::StageTimer();
 }
 
-void free_plan_buffers(pswfe::DevPlan& d) {
-  void* bufs[] = {d.tile_count, d.tile_start, d.tile_of, d.rank, d.perm, d.cells, d.sorted, d.grid_a, d.grid_b, d.spec,
-                  d.coef, d.tm, d.wk, d.tw_half_p, d.tw_half_m, d.tw_full_p, d.tw_full_m};
-  for (void* b : bufs)
+void free_plan(pswfe_plan* plan) {
+  for (void* b : plan->allocs)
     if (b) (void)hipFree(b);
+  plan->allocs.clear();
+  delete plan;
+}
+
+pswfe_status params_from_c(const pswfe_params* pp, pswfe::Params* p) {
+  const int m = pp->m, P = pp->P;
+  if (!pswfe::is_smooth_even(m) || m < 8 || m > 512 || P < pswfe::kPmin || P > pswfe::kPmax || P > m)
+    return PSWFE_E_GRID;
+  if (!(pp->L > 0) || !(pp->rc > 0) || !(pp->cs > 0) || !(pp->cw > 0) || !(pp->alpha > 0) || !(pp->eps > 0))
+    return PSWFE_E_ARG;
+  if (pp->cs > 40.0 || pp->cw > 40.0) return PSWFE_E_EPS_RANGE;
+  p->L = pp->L;
+  p->eps = pp->eps;
+  p->rc = pp->rc;
+  p->cs = pp->cs;
+  p->cw = pp->cw;
+  p->alpha = pp->alpha;
+  p->h = pp->L / m;
+  p->cs_alg = pp->cs_alg;
+  p->cw_alg = pp->cw_alg;
+  p->alpha_alg = pp->alpha_alg;
+  p->m = m;
+  p->P = P;
+  p->tol_mode = pp->tol_mode;
+  p->lambda0_s = pswfe::Pswf(p->cs).lambda0;
+  return PSWFE_OK;
+}
+
+// Byte layout of one arena: sub-buffers at 256-byte aligned offsets.
+struct Arena {
+  size_t size = 0;
+  size_t take(size_t bytes) {
+    const size_t off = size;
+    size += (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+    return off;
+  }
+};
+
+template <class T>
+void put(std::vector<unsigned char>& img, size_t off, const std::vector<double>& v) {
+  for (size_t i = 0; i < v.size(); ++i) {
+    const T x = static_cast<T>(v[i]);
+    std::memcpy(img.data() + off + i * sizeof(T), &x, sizeof(T));
+  }
+}
+
+// Builds a plan over `ps.size()` systems. counts == NULL: single system taking up to n_max
+// particles per call; otherwise a batch with counts[s] particles in system s.
+pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, const int64_t* counts,
+                        const int32_t* tiles, pswfe_plan** out) {
+  const int nsys = static_cast<int>(ps.size());
+  const int elem = prec == PSWFE_FP32 ? 4 : 8;
+  const size_t celem = 2 * static_cast<size_t>(elem);
+  pswfe_plan* plan = new (std::nothrow) pswfe_plan();
+  if (!plan) return PSWFE_E_ALLOC;
+  plan->batch = counts != nullptr;
+  plan->p = ps;
+  plan->tab.resize(nsys);
+  (void)hipGetDevice(&plan->device);
+  pswfe::DevPlan& d = plan->d;
+  d.prec = prec;
+  d.nsys = nsys;
+  d.sys.resize(nsys);
+  std::vector<int> xblk_prefix(nsys + 1, 0), cblk_prefix(nsys + 1, 0);
+  std::vector<int64_t> part_prefix(nsys + 1, 0);
+  Arena work, tabs;
+  struct TabOff { size_t coef, tm, wk, twhp, twhm, twfp, twfm; };
+  struct WorkOff { size_t a, b, spec; };
+  std::vector<TabOff> toff(nsys);
+  std::vector<WorkOff> woff(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    const pswfe::Params& p = ps[s];
+    pswfe::Tables& t = plan->tab[s];
+    pswfe::build_tables(p, 0, fit_tolerance(p.eps, prec), &t);
+    pswfe::SysDesc& sd = d.sys[s];
+    const int m = p.m, N = m / 2, nx1 = N + 1;
+    if (counts) {
+      if (counts[s] < 0) {
+        free_plan(plan);
+        return PSWFE_E_ARG;
+      }
+      part_prefix[s + 1] = part_prefix[s] + counts[s];
+      plan->count.push_back(counts[s]);
+    }
+    const int req = tiles ? tiles[s] : 0;
+    if (req < 0 || req > m) {
+      free_plan(plan);
+      return PSWFE_E_ARG;
+    }
+    const int P = p.P;
+    sd.m = m;
+    sd.P = P;
+    sd.deg = t.deg;
+    sd.B = choose_tile(m, P, req, elem, counts ? counts[s] : -1);
+    sd.Tn = (m + sd.B - 1) / sd.B;
+    sd.S = lds_edge(sd.B, P);
+    sd.L = p.L;
+    sd.inv_h = m / p.L;
+    const long double ih = static_cast<long double>(m) / static_cast<long double>(p.L);
+    if (prec == PSWFE_FP32) {
+      const float hi = static_cast<float>(ih);
+      sd.ih_hi = hi;
+      sd.ih_lo = static_cast<float>(ih - static_cast<long double>(hi));
+    } else {
+      const double hi = static_cast<double>(ih);
+      sd.ih_hi = hi;
+      sd.ih_lo = static_cast<double>(ih - static_cast<long double>(hi));
+    }
+    sd.self_coef = t.self_coef;
+    sd.fh = make_fft_plan(N);
+    sd.ff = make_fft_plan(m);
+    if (sd.fh.nst < 0 || sd.ff.nst < 0) {
+      free_plan(plan);
+      return PSWFE_E_GRID;
+    }
+    int rpb = std::max(1, std::min(64, 2048 / nx1));
+    while (rpb > 1 && 2 * static_cast<size_t>(rpb) * nx1 * celem > 64 * 1024) --rpb;
+    int cmax = std::max(1, std::min(64, 2048 / (m + 1)));
+    while (cmax > 1 && 2 * static_cast<size_t>(cmax) * (m + 1) * celem > 64 * 1024) --cmax;
+    const int nxb = (nx1 + cmax - 1) / cmax;
+    sd.rows_per_block = rpb;
+    sd.cols_per_block = (nx1 + nxb - 1) / nxb;
+    sd.xblk_base = xblk_prefix[s];
+    sd.cblk_base = cblk_prefix[s];
+    sd.part_base = part_prefix[s];
+    xblk_prefix[s + 1] = xblk_prefix[s] + (m * m + rpb - 1) / rpb;
+    cblk_prefix[s + 1] = cblk_prefix[s] + ((nx1 + sd.cols_per_block - 1) / sd.cols_per_block) * m;
+    d.lds_x = std::max(d.lds_x, 2 * static_cast<size_t>(rpb) * nx1 * celem);
+    d.lds_c = std::max(d.lds_c, 2 * static_cast<size_t>(sd.cols_per_block) * (m + 1) * celem);
+    const size_t m3 = static_cast<size_t>(m) * m * m;
+    woff[s] = {work.take(sizeof(double) * m3), work.take(elem * m3),
+               work.take(celem * static_cast<size_t>(m) * m * nx1)};
+    toff[s] = {tabs.take(sizeof(double) * t.coef.size()), tabs.take(elem * t.tm.size()),
+               tabs.take(elem * t.w.size()), tabs.take(celem * N), tabs.take(celem * N), tabs.take(celem * m),
+               tabs.take(celem * m)};
+  }
+  // Global tile order: systems grouped by P (stable), so each P's tiles are one contiguous
+  // range covered by one launch of the particle kernels.
+  std::vector<int> order(nsys), tile_prefix(nsys + 1, 0);
+  for (int s = 0; s < nsys; ++s) order[s] = s;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return d.sys[a].P < d.sys[b].P; });
+  for (int k = 0; k < nsys; ++k) {
+    pswfe::SysDesc& sd = d.sys[order[k]];
+    sd.tile_base = tile_prefix[k];
+    tile_prefix[k + 1] = tile_prefix[k] + sd.Tn * sd.Tn * sd.Tn;
+    if (d.groups.empty() || d.groups.back().P != sd.P) {
+      pswfe::PGroup g;
+      g.P = sd.P;
+      g.tile_begin = tile_prefix[k];
+      d.groups.push_back(g);
+    }
+    pswfe::PGroup& g = d.groups.back();
+    g.tile_end = tile_prefix[k + 1];
+    g.lds_spread = std::max(g.lds_spread, spread_lds_bytes(sd.S, sd.P));
+    g.lds_gather = std::max(g.lds_gather, gather_lds_bytes(sd.S, sd.P, elem));
+  }
+  d.total_tiles = tile_prefix[nsys];
+  d.total_xblk = xblk_prefix[nsys];
+  d.total_cblk = cblk_prefix[nsys];
+  d.n_max = counts ? part_prefix[nsys] : n_max;
+  if (d.n_max > (int64_t(1) << 31) - 1) {
+    free_plan(plan);
+    return PSWFE_E_ARG;
+  }
+  if (!counts) part_prefix[1] = 0;  // unused: one system takes every particle of a call
+
+  pswfe_status st = PSWFE_OK;
+  auto alloc = [&](size_t bytes) -> void* {
+    void* ptr = nullptr;
+    if (st == PSWFE_OK && hipMalloc(&ptr, std::max<size_t>(bytes, 16)) != hipSuccess) {
+      st = PSWFE_E_ALLOC;
+      ptr = nullptr;
+    }
+    if (ptr) plan->allocs.push_back(ptr);
+    return ptr;
+  };
+  const size_t nm = static_cast<size_t>(std::max<int64_t>(d.n_max, 1));
+  unsigned char* work_dev = static_cast<unsigned char*>(alloc(work.size));
+  unsigned char* tab_dev = static_cast<unsigned char*>(alloc(tabs.size));
+  d.tile_count = static_cast<int*>(alloc(sizeof(int) * d.total_tiles));
+  d.tile_start = static_cast<int*>(alloc(sizeof(int) * (d.total_tiles + 1)));
+  d.tile_of = static_cast<int*>(alloc(sizeof(int) * nm));
+  d.rank = static_cast<int*>(alloc(sizeof(int) * nm));
+  d.perm = static_cast<int*>(alloc(sizeof(int) * nm));
+  d.cells = static_cast<int*>(alloc(sizeof(int) * nm));
+  d.sorted = alloc(4 * static_cast<size_t>(elem) * nm);
+  d.sys_dev = static_cast<pswfe::SysDesc*>(alloc(sizeof(pswfe::SysDesc) * nsys));
+  d.tile_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
+  d.tile_sys = static_cast<int*>(alloc(sizeof(int) * nsys));
+  d.xblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
+  d.cblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
+  d.part_prefix = static_cast<int64_t*>(alloc(sizeof(int64_t) * (nsys + 1)));
+  if (st != PSWFE_OK) {
+    free_plan(plan);
+    return st;
+  }
+  std::vector<unsigned char> img(tabs.size, 0);
+  for (int s = 0; s < nsys; ++s) {
+    pswfe::SysDesc& sd = d.sys[s];
+    const pswfe::Tables& t = plan->tab[s];
+    const int m = sd.m, N = m / 2;
+    sd.grid_a = reinterpret_cast<double*>(work_dev + woff[s].a);
+    sd.grid_b = work_dev + woff[s].b;
+    sd.spec = work_dev + woff[s].spec;
+    sd.coef = reinterpret_cast<const double*>(tab_dev + toff[s].coef);
+    sd.tm = tab_dev + toff[s].tm;
+    sd.wk = tab_dev + toff[s].wk;
+    sd.twhp = tab_dev + toff[s].twhp;
+    sd.twhm = tab_dev + toff[s].twhm;
+    sd.twfp = tab_dev + toff[s].twfp;
+    sd.twfm = tab_dev + toff[s].twfm;
+    std::vector<double> twhp, twhm, twfp, twfm;
+    pswfe::twiddles(N, +1, &twhp);
+    pswfe::twiddles(N, -1, &twhm);
+    pswfe::twiddles(m, +1, &twfp);
+    pswfe::twiddles(m, -1, &twfm);
+    put<double>(img, toff[s].coef, t.coef);  // window polynomials: float64 in both precisions
+    if (prec == PSWFE_FP32) {
+      put<float>(img, toff[s].tm, t.tm);
+      put<float>(img, toff[s].wk, t.w);
+      put<float>(img, toff[s].twhp, twhp);
+      put<float>(img, toff[s].twhm, twhm);
+      put<float>(img, toff[s].twfp, twfp);
+      put<float>(img, toff[s].twfm, twfm);
+    } else {
+      put<double>(img, toff[s].tm, t.tm);
+      put<double>(img, toff[s].wk, t.w);
+      put<double>(img, toff[s].twhp, twhp);
+      put<double>(img, toff[s].twhm, twhm);
+      put<double>(img, toff[s].twfp, twfp);
+      put<double>(img, toff[s].twfm, twfm);
+    }
+  }
+  // grid_a must start (and is kept) all-zero; the rest of the work arena needs no value.
+  bool ok = hipMemcpy(tab_dev, img.data(), tabs.size, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemset(work_dev, 0, work.size) == hipSuccess &&
+            hipMemset(d.tile_count, 0, sizeof(int) * d.total_tiles) == hipSuccess &&
+            hipMemcpy(d.sys_dev, d.sys.data(), sizeof(pswfe::SysDesc) * nsys, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(d.tile_prefix, tile_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
+                hipSuccess &&
+            hipMemcpy(d.tile_sys, order.data(), sizeof(int) * nsys, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(d.xblk_prefix, xblk_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
+                hipSuccess &&
+            hipMemcpy(d.cblk_prefix, cblk_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
+                hipSuccess &&
+            hipMemcpy(d.part_prefix, part_prefix.data(), sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice) ==
+                hipSuccess &&
+            pswfe::prepare_kernels(d) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    free_plan(plan);
+    return PSWFE_E_HIP;
+  }
+  *out = plan;
+  return PSWFE_OK;
 }
 
 }  // namespace
@@ -150,34 +408,6 @@ pswfe_status pswfe_host_pswf(double c, double x, double* psi, double* dpsi, doub
   return PSWFE_OK;
 }
 
-namespace {
-pswfe_status params_from_c(const pswfe_params* pp, pswfe::Params* p) {
-  const int m = pp->m, P = pp->P;
-  if (!pswfe::is_smooth_even(m) || m < 8 || m > 512 || P < pswfe::kPmin || P > pswfe::kPmax || P > m)
-    return PSWFE_E_GRID;
-  if (!(pp->L > 0) || !(pp->rc > 0) || !(pp->cs > 0) || !(pp->cw > 0) || !(pp->alpha > 0) || !(pp->eps > 0))
-    return PSWFE_E_ARG;
-  if (pp->cs > 40.0 || pp->cw > 40.0) return PSWFE_E_EPS_RANGE;
-  p->L = pp->L;
-  p->eps = pp->eps;
-  p->rc = pp->rc;
-  p->cs = pp->cs;
-  p->cw = pp->cw;
-  p->alpha = pp->alpha;
-  p->h = pp->L / m;
-  p->cs_alg = pp->cs_alg;
-  p->cw_alg = pp->cw_alg;
-  p->alpha_alg = pp->alpha_alg;
-  p->m = m;
-  p->P = P;
-  p->tol_mode = pp->tol_mode;
-  p->lambda0_s = pswfe::Pswf(p->cs).lambda0;
-  return PSWFE_OK;
-}
-
-double fit_tolerance(double eps, int prec) { return std::max(0.01 * eps, prec == PSWFE_FP32 ? 5e-9 : 1e-15); }
-}  // namespace
-
 pswfe_status pswfe_host_tables(const pswfe_params* pp, int32_t prec, double* tm, int64_t tm_len, double* w,
                                int64_t w_len, double* coef, int64_t coef_len, double* info) {
   if (!pp) return PSWFE_E_ARG;
@@ -204,11 +434,23 @@ pswfe_status pswfe_host_tables(const pswfe_params* pp, int32_t prec, double* tm,
 
 pswfe_status pswfe_plan_params(const pswfe_plan* plan, pswfe_params* out) {
   if (!plan || !out) return PSWFE_E_ARG;
-  to_c(plan->p, out);
+  to_c(plan->p[0], out);
   return PSWFE_OK;
 }
 
-int32_t pswfe_plan_tile(const pswfe_plan* plan) { return plan ? plan->d.B : 0; }
+int32_t pswfe_plan_tile(const pswfe_plan* plan) { return plan ? plan->d.sys[0].B : 0; }
+
+int32_t pswfe_plan_num_systems(const pswfe_plan* plan) { return plan ? plan->d.nsys : 0; }
+
+pswfe_status pswfe_plan_system(const pswfe_plan* plan, int32_t s, pswfe_params* params, int64_t* offset,
+                               int64_t* count, int32_t* tile) {
+  if (!plan || s < 0 || s >= plan->d.nsys) return PSWFE_E_ARG;
+  if (params) to_c(plan->p[s], params);
+  if (offset) *offset = plan->batch ? plan->d.sys[s].part_base : 0;
+  if (count) *count = plan->batch ? plan->count[s] : plan->d.n_max;
+  if (tile) *tile = plan->d.sys[s].B;
+  return PSWFE_OK;
+}
 
 pswfe_status pswfe_plan_create(const pswfe_params* pp, int32_t prec, int64_t n_max, pswfe_plan** out) {
   return pswfe_plan_create_tiled(pp, prec, n_max, 0, out);
@@ -220,115 +462,35 @@ pswfe_status pswfe_plan_create_tiled(const pswfe_params* pp, int32_t prec, int64
   *out = nullptr;
   if (!pp || n_max < 0 || n_max > (int64_t(1) << 31) - 1) return PSWFE_E_ARG;
   if (prec != PSWFE_FP32 && prec != PSWFE_FP64) return PSWFE_E_PREC;
-  pswfe::Params pcheck{};
-  const pswfe_status pst = params_from_c(pp, &pcheck);
-  if (pst != PSWFE_OK) return pst;
-  const int m = pp->m, P = pp->P;
-  pswfe_plan* plan = new (std::nothrow) pswfe_plan();
-  if (!plan) return PSWFE_E_ALLOC;
-  pswfe::Params& p = plan->p;
-  p = pcheck;
-  pswfe::build_tables(p, 0, fit_tolerance(p.eps, prec), &plan->tab);
-  (void)hipGetDevice(&plan->device);
+  std::vector<pswfe::Params> ps(1);
+  const pswfe_status st = params_from_c(pp, &ps[0]);
+  if (st != PSWFE_OK) return st;
+  return build_plan(ps, prec, n_max, nullptr, &tile, out);
+}
 
-  pswfe::DevPlan& d = plan->d;
-  const int elem = prec == PSWFE_FP32 ? 4 : 8;
-  d.prec = prec;
-  d.m = m;
-  d.P = P;
-  d.deg = plan->tab.deg;
-  if (tile < 0 || tile > m) {
-    delete plan;
-    return PSWFE_E_ARG;
+pswfe_status pswfe_batch_plan_create(int32_t nsys, const pswfe_params* params, const int64_t* counts, int32_t prec,
+                                     const int32_t* tiles, pswfe_plan** out) {
+  if (!out) return PSWFE_E_ARG;
+  *out = nullptr;
+  if (nsys < 1 || nsys > (1 << 20) || !params || !counts) return PSWFE_E_ARG;
+  if (prec != PSWFE_FP32 && prec != PSWFE_FP64) return PSWFE_E_PREC;
+  std::vector<pswfe::Params> ps(nsys);
+  int64_t total = 0;
+  for (int s = 0; s < nsys; ++s) {
+    const pswfe_status st = params_from_c(&params[s], &ps[s]);
+    if (st != PSWFE_OK) return st;
+    if (counts[s] < 0 || (tiles && (tiles[s] < 0 || tiles[s] > ps[s].m))) return PSWFE_E_ARG;
+    total += counts[s];
+    if (total > (int64_t(1) << 31) - 1) return PSWFE_E_ARG;
   }
-  d.B = choose_tile(m, P, tile, elem);
-  d.Tn = (m + d.B - 1) / d.B;
-  d.ntiles = d.Tn * d.Tn * d.Tn;
-  d.S = d.B + 2 * ((P + 1) / 2) - 1;
-  d.L = p.L;
-  d.h = p.h;
-  d.inv_h = m / p.L;
-  {
-    const long double ih = static_cast<long double>(m) / static_cast<long double>(p.L);
-    if (prec == PSWFE_FP32) {
-      const float hi = static_cast<float>(ih);
-      d.inv_h_hi = hi;
-      d.inv_h_lo = static_cast<float>(ih - static_cast<long double>(hi));
-    } else {
-      const double hi = static_cast<double>(ih);
-      d.inv_h_hi = hi;
-      d.inv_h_lo = static_cast<double>(ih - static_cast<long double>(hi));
-    }
-  }
-  d.self_coef = plan->tab.self_coef;
-  d.n_max = n_max;
-  d.fft_half = make_fft_plan(m / 2);
-  d.fft_full = make_fft_plan(m);
-  if (d.fft_half.nst < 0 || d.fft_full.nst < 0) {
-    delete plan;
-    return PSWFE_E_GRID;
-  }
-  const int N = m / 2;
-  d.rows_per_block = std::max(1, std::min(64, 2048 / (N + 1)));
-  while (d.rows_per_block > 1 && size_t(2) * d.rows_per_block * (N + 1) * 2 * elem > 64 * 1024) --d.rows_per_block;
-  int cmax = std::max(1, std::min(64, 2048 / (m + 1)));
-  while (cmax > 1 && size_t(2) * cmax * (m + 1) * 2 * elem > 64 * 1024) --cmax;
-  const int nblk = (N + 1 + cmax - 1) / cmax;
-  d.cols_per_block = (N + 1 + nblk - 1) / nblk;
-
-  const size_t m3 = size_t(m) * m * m;
-  const size_t nspec = size_t(m) * m * (N + 1);
-  const size_t nm = std::max<int64_t>(n_max, 1);
-  pswfe_status st = PSWFE_OK;
-  auto alloc = [&](void** ptr, size_t bytes) {
-    if (st == PSWFE_OK && hipMalloc(ptr, std::max<size_t>(bytes, 16)) != hipSuccess) st = PSWFE_E_ALLOC;
-  };
-  alloc(reinterpret_cast<void**>(&d.tile_count), sizeof(int) * d.ntiles);
-  alloc(reinterpret_cast<void**>(&d.tile_start), sizeof(int) * (d.ntiles + 1));
-  alloc(reinterpret_cast<void**>(&d.tile_of), sizeof(int) * nm);
-  alloc(reinterpret_cast<void**>(&d.rank), sizeof(int) * nm);
-  alloc(reinterpret_cast<void**>(&d.perm), sizeof(int) * nm);
-  alloc(reinterpret_cast<void**>(&d.cells), sizeof(int) * nm);
-  alloc(&d.sorted, size_t(4) * elem * nm);
-  alloc(&d.grid_a, sizeof(double) * m3);
-  alloc(&d.grid_b, elem * m3);
-  alloc(&d.spec, size_t(2) * elem * nspec);
-  if (st == PSWFE_OK) {
-    std::vector<double> twhp, twhm, twfp, twfm;
-    pswfe::twiddles(N, +1, &twhp);
-    pswfe::twiddles(N, -1, &twhm);
-    pswfe::twiddles(m, +1, &twfp);
-    pswfe::twiddles(m, -1, &twfm);
-    auto up = [&](const std::vector<double>& v, void** dst) {
-      if (st == PSWFE_OK) st = prec == PSWFE_FP32 ? upload<float>(v, dst) : upload<double>(v, dst);
-    };
-    if (st == PSWFE_OK) st = upload<double>(plan->tab.coef, &d.coef);  // window polynomials: float64
-    up(plan->tab.tm, &d.tm);
-    up(plan->tab.w, &d.wk);
-    up(twhp, &d.tw_half_p);
-    up(twhm, &d.tw_half_m);
-    up(twfp, &d.tw_full_p);
-    up(twfm, &d.tw_full_m);
-  }
-  if (st == PSWFE_OK && (hipMemset(d.tile_count, 0, sizeof(int) * d.ntiles) != hipSuccess ||
-                         hipMemset(d.grid_a, 0, sizeof(double) * m3) != hipSuccess ||
-                         hipDeviceSynchronize() != hipSuccess))
-    st = PSWFE_E_HIP;
-  if (st != PSWFE_OK) {
-    free_plan_buffers(d);
-    delete plan;
-    return st;
-  }
-  *out = plan;
-  return PSWFE_OK;
+  return build_plan(ps, prec, 0, counts, tiles, out);
 }
 
 pswfe_status pswfe_plan_destroy(pswfe_plan* plan) {
   if (!plan) return PSWFE_OK;
   (void)hipDeviceSynchronize();
   free_timer(plan->timer);
-  free_plan_buffers(plan->d);
-  delete plan;
+  free_plan(plan);
   return PSWFE_OK;
 }
 
@@ -371,20 +533,32 @@ pswfe_status pswfe_timing_read(pswfe_plan* plan, double* total_ms, int64_t* call
 }
 
 namespace {
-pswfe_status compute_impl(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi, void* vec,
-                          int vec_mode, double* energy, void* stream) {
-  if (!plan || n < 0) return PSWFE_E_ARG;
-  if (n > plan->d.n_max) return PSWFE_E_CAPACITY;
-  if (n > 0 && (!pos || !q)) return PSWFE_E_ARG;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const pswfe::DevPlan& d = plan->d;
+// Bin, spread, transform and gather over every system of the plan; n particles in all.
+hipError_t run_pipeline(const pswfe::DevPlan& d, int64_t n, const void* pos, const void* q, void* phi, void* vec,
+                        int vec_mode, double* energy, hipStream_t s) {
   pswfe::stage_begin(d, pswfe::kStageAll, s);
   hipError_t e = pswfe::launch_bin(d, n, pos, q, energy, s);
-  if (e == hipSuccess) e = pswfe::launch_spread(d, d.grid_a, s);
-  if (e == hipSuccess) e = pswfe::launch_transform(d, d.grid_a, true, d.grid_b, true, s);
-  if (e == hipSuccess && n > 0) e = pswfe::launch_gather(d, n, d.grid_b, phi, vec, vec_mode, true, energy, s);
+  if (e == hipSuccess) e = pswfe::launch_spread(d, s);
+  if (e == hipSuccess) e = pswfe::launch_transform(d, nullptr, nullptr, s);
+  if (e == hipSuccess && n > 0) e = pswfe::launch_gather(d, nullptr, phi, vec, vec_mode, true, energy, s);
   pswfe::stage_end(d, pswfe::kStageAll, s);
-  return from_hip(e);
+  return e;
+}
+
+pswfe_status compute_impl(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi, void* vec,
+                          int vec_mode, double* energy, void* stream) {
+  if (!plan || plan->batch || n < 0) return PSWFE_E_ARG;
+  if (n > plan->d.n_max) return PSWFE_E_CAPACITY;
+  if (n > 0 && (!pos || !q)) return PSWFE_E_ARG;
+  return from_hip(run_pipeline(plan->d, n, pos, q, phi, vec, vec_mode, energy, static_cast<hipStream_t>(stream)));
+}
+
+pswfe_status batch_impl(pswfe_plan* plan, const void* pos, const void* q, void* phi, void* vec, int vec_mode,
+                        double* energy, void* stream) {
+  if (!plan || !plan->batch) return PSWFE_E_ARG;
+  const int64_t n = plan->d.n_max;
+  if (n > 0 && (!pos || !q)) return PSWFE_E_ARG;
+  return from_hip(run_pipeline(plan->d, n, pos, q, phi, vec, vec_mode, energy, static_cast<hipStream_t>(stream)));
 }
 }  // namespace
 
@@ -398,33 +572,42 @@ pswfe_status pswfe_compute_grad(pswfe_plan* plan, int64_t n, const void* pos, co
   return compute_impl(plan, n, pos, q, phi, grad, 1, energy, stream);
 }
 
+pswfe_status pswfe_batch_compute(pswfe_plan* plan, const void* pos, const void* q, void* phi, void* force,
+                                 double* energy, void* stream) {
+  return batch_impl(plan, pos, q, phi, force, 0, energy, stream);
+}
+
+pswfe_status pswfe_batch_compute_grad(pswfe_plan* plan, const void* pos, const void* q, void* phi, void* grad,
+                                      double* energy, void* stream) {
+  return batch_impl(plan, pos, q, phi, grad, 1, energy, stream);
+}
+
 pswfe_status pswfe_spread(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* grid, void* stream) {
-  if (!plan || n < 0 || !grid) return PSWFE_E_ARG;
+  if (!plan || plan->batch || n < 0 || !grid) return PSWFE_E_ARG;
   if (n > plan->d.n_max) return PSWFE_E_CAPACITY;
   if (n > 0 && (!pos || !q)) return PSWFE_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const pswfe::DevPlan& d = plan->d;
   hipError_t e = pswfe::launch_bin(d, n, pos, q, nullptr, s);
-  if (e == hipSuccess) e = pswfe::launch_spread(d, d.grid_a, s);
+  if (e == hipSuccess) e = pswfe::launch_spread(d, s);
   if (e == hipSuccess) e = pswfe::launch_drain(d, grid, s);
   return from_hip(e);
 }
 
 pswfe_status pswfe_transform(pswfe_plan* plan, const void* grid_in, void* grid_out, void* stream) {
-  if (!plan || !grid_in || !grid_out) return PSWFE_E_ARG;
-  return from_hip(pswfe::launch_transform(plan->d, grid_in, plan->d.prec == 1, grid_out, false,
-                                          static_cast<hipStream_t>(stream)));
+  if (!plan || plan->batch || !grid_in || !grid_out) return PSWFE_E_ARG;
+  return from_hip(pswfe::launch_transform(plan->d, grid_in, grid_out, static_cast<hipStream_t>(stream)));
 }
 
 pswfe_status pswfe_interpolate(pswfe_plan* plan, int64_t n, const void* pos, const void* grid, void* phi, void* grad,
                                void* stream) {
-  if (!plan || n < 0 || !grid) return PSWFE_E_ARG;
+  if (!plan || plan->batch || n < 0 || !grid) return PSWFE_E_ARG;
   if (n > plan->d.n_max) return PSWFE_E_CAPACITY;
   if (n > 0 && !pos) return PSWFE_E_ARG;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const pswfe::DevPlan& d = plan->d;
   hipError_t e = pswfe::launch_bin(d, n, pos, nullptr, nullptr, s);
-  if (e == hipSuccess && n > 0) e = pswfe::launch_gather(d, n, grid, phi, grad, 1, false, nullptr, s);
+  if (e == hipSuccess && n > 0) e = pswfe::launch_gather(d, grid, phi, grad, 1, false, nullptr, s);
   return from_hip(e);
 }
 

@@ -1,6 +1,8 @@
 // HIP kernels for gfx950: binning, spreading (Alg. 2 step 1), smooth-size FFTs with the
 // k-space scaling fused between the forward and inverse z passes (steps 2-4), and
 // interpolation of potentials and gradients with the energy reduction (step 5, eq. force).
+// Each kernel covers every system of a batch in one launch: a workgroup (or, in binning, a
+// thread) looks up its system in a prefix table of the global index space it runs over.
 #include "kernels.hpp"
 
 #include <hip/hip_runtime.h>
@@ -30,6 +32,22 @@ template <class C> __device__ __forceinline__ C cconj(C a) { C r; r.x = a.x; r.y
 
 __device__ __forceinline__ void atomic_add_global(float* p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add_global(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+// System owning global item i: the largest s < nsys with prefix[s] <= i (prefix is
+// non-decreasing with prefix[0] = 0; an empty system repeats its successor's start and is
+// skipped).
+template <class I>
+__device__ __forceinline__ int find_sys(const I* __restrict__ prefix, int nsys, I i) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= i)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
 
 // Grid coordinate of x: cell c in [0, m) and fractional offset f with x/h = c + f (mod m).
 // The product x * (1/h) uses 1/h split into two words (ih_hi + ih_lo) and the exact product
@@ -65,20 +83,26 @@ __device__ __forceinline__ int grid_coord(T x, T ih_hi, T ih_lo, T L, int m, T& 
 }
 
 // ------------------------------------------------------------------------------------
-// Binning: particles are grouped by tiles of B^3 grid cells (counting sort).
+// Binning: particles are grouped by tiles of B^3 grid cells (counting sort over the global
+// tile index of the batch). Packed particle i belongs to the system whose range
+// [part_prefix[s], part_prefix[s+1]) holds it.
 // ------------------------------------------------------------------------------------
 template <class T>
-__global__ void k_bin_count(int64_t n, const T* __restrict__ pos, T ih_hi, T ih_lo, T L, int m, int B, int Tn,
+__global__ void k_bin_count(int64_t n, int nsys, const SysDesc* __restrict__ sys,
+                            const int64_t* __restrict__ part_prefix, const T* __restrict__ pos,
                             int* __restrict__ tile_count, int* __restrict__ tile_of, int* __restrict__ rank,
                             double* __restrict__ energy) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i == 0 && energy) *energy = 0.0;
+  if (energy && i < nsys) energy[i] = 0.0;
   if (i >= n) return;
+  const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
+  const T ih_hi = static_cast<T>(sd.ih_hi), ih_lo = static_cast<T>(sd.ih_lo), L = static_cast<T>(sd.L);
+  const int m = sd.m, B = sd.B, Tn = sd.Tn;
   T f;
   const int cx = grid_coord(pos[3 * i + 0], ih_hi, ih_lo, L, m, f);
   const int cy = grid_coord(pos[3 * i + 1], ih_hi, ih_lo, L, m, f);
   const int cz = grid_coord(pos[3 * i + 2], ih_hi, ih_lo, L, m, f);
-  const int tile = ((cz / B) * Tn + cy / B) * Tn + cx / B;
+  const int tile = sd.tile_base + ((cz / B) * Tn + cy / B) * Tn + cx / B;
   tile_of[i] = tile;
   rank[i] = atomicAdd(&tile_count[tile], 1);
 }
@@ -130,14 +154,18 @@ __global__ __launch_bounds__(1024) void k_scan(int ntiles, int* __restrict__ cou
   if (tid == 0) start[ntiles] = s_carry;
 }
 
-// Sorted record: (f_x, f_y, f_z, q) and the packed cell cx + m (cy + m cz).
+// Sorted record: (f_x, f_y, f_z, q) and the packed cell cx + m (cy + m cz) of its system.
 template <class T>
-__global__ void k_bin_scatter(int64_t n, const T* __restrict__ pos, const T* __restrict__ q, T ih_hi, T ih_lo, T L,
-                              int m, const int* __restrict__ tile_of, const int* __restrict__ rank,
+__global__ void k_bin_scatter(int64_t n, int nsys, const SysDesc* __restrict__ sys,
+                              const int64_t* __restrict__ part_prefix, const T* __restrict__ pos,
+                              const T* __restrict__ q, const int* __restrict__ tile_of, const int* __restrict__ rank,
                               const int* __restrict__ tile_start, typename Vec4<T>::type* __restrict__ sorted,
                               int* __restrict__ cells, int* __restrict__ perm) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
+  const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
+  const T ih_hi = static_cast<T>(sd.ih_hi), ih_lo = static_cast<T>(sd.ih_lo), L = static_cast<T>(sd.L);
+  const int m = sd.m;
   const int dst = tile_start[tile_of[i]] + rank[i];
   typename Vec4<T>::type r;
   const int cx = grid_coord(pos[3 * i + 0], ih_hi, ih_lo, L, m, r.x);
@@ -174,12 +202,12 @@ __device__ __forceinline__ int wrap_index(int a, int m) {
 }
 
 // ------------------------------------------------------------------------------------
-// Particle kernels. A workgroup (4 waves) owns one tile of B^3 cells and an LDS copy of the
-// S^3 grid points its particles' supports touch (S = B + 2 ceil(P/2) - 1). Each wave works on
-// 4 particles at a time, 16 lanes per particle: the 16 lanes evaluate the particle's 3P window
-// polynomials (Horner, float64) into a per-wave LDS record, then share the P^2 (y, z) lines of
-// its support, each lane running the x-direction of its lines. Lanes of a particle touch
-// distinct lines (stride S, odd in practice), so their LDS accesses do not conflict, and no
+// Particle kernels, one launch per window support P over the tiles of the systems with that
+// P. A workgroup (4 waves) owns one tile of B^3 cells of one system and an LDS copy of the S^3 grid points its particles' supports touch (S = B + 2 ceil(P/2) - 1).
+// Each wave works on 4 particles at a time, 16 lanes per particle: the 16 lanes evaluate the
+// particle's 3P window polynomials (Horner, float64) into a per-wave LDS record, then share
+// the P^2 (y, z) lines of its support, each lane running the x-direction of its lines. Lanes
+// of a particle touch distinct lines (stride S), so their LDS accesses do not conflict, and no
 // workgroup barrier is needed between particles.
 // Window values, products and sums are float64 in both precisions: on MI355X a float64 FMA
 // issues at the non-packed float32 rate, and float32 window values and products lose ~1e-6
@@ -199,22 +227,28 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Spreading (Alg. 2 step 1): the tile accumulates q w_x w_y w_z over the supports with LDS
 // float64 atomic adds (on gfx950 about 20x the throughput of float32 LDS atomics), then adds
-// the tile into the float64 HBM grid with atomics (a point lies in the halos of up to
-// ceil(S/B)^3 tiles; their partial sums are larger than the total on systems of neutral
+// the tile into its system's float64 HBM grid with atomics (a point lies in the halos of up
+// to ceil(S/B)^3 tiles; their partial sums are larger than the total on systems of neutral
 // molecules, so they are added in float64 and rounded once, by the first FFT pass).
 template <class T, int P>
 __global__ __launch_bounds__(256) void k_spread(const typename Vec4<T>::type* __restrict__ sorted,
-                                                const int* __restrict__ cells,
-                                                const int* __restrict__ tile_start, const double* __restrict__ coef,
-                                                int deg, int m, int B, int Tn, int S, double* __restrict__ grid) {
+                                                const int* __restrict__ cells, const int* __restrict__ tile_start,
+                                                int nsys, const SysDesc* __restrict__ sys,
+                                                const int* __restrict__ tile_prefix, const int* __restrict__ tile_sys,
+                                                int tile_offset) {
   constexpr int REC = 3 * P;  // window values of one particle: x, y, z
   extern __shared__ unsigned char smem_raw[];
+  const int gtile = tile_offset + static_cast<int>(blockIdx.x);
+  const int p0 = tile_start[gtile], p1 = tile_start[gtile + 1];
+  if (p0 == p1) return;
+  const SysDesc& sd = sys[tile_sys[find_sys(tile_prefix, nsys, gtile)]];
+  const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S, deg = sd.deg;
+  const double* __restrict__ coef = sd.coef;
+  double* __restrict__ grid = sd.grid_a;
   double* acc = reinterpret_cast<double*>(smem_raw);
   const int S3 = S * S * S;
   double* recs = acc + S3;    // kSlotsPerBlock * REC
-  const int tile = blockIdx.x;
-  const int p0 = tile_start[tile], p1 = tile_start[tile + 1];
-  if (p0 == p1) return;
+  const int tile = gtile - sd.tile_base;
   const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
   const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
   for (int i = threadIdx.x; i < S3; i += blockDim.x) acc[i] = 0.0;
@@ -273,23 +307,33 @@ __global__ __launch_bounds__(256) void k_spread(const typename Vec4<T>::type* __
 // Interpolation (Alg. 2 step 5 and eq. force): phi = sum b w_x w_y w_z and its gradient as
 // nested sums: each lane runs the x-sums of its lines for the value and the x-derivative,
 // weights them with the y/z windows and derivatives, and the 16 lanes of a particle reduce.
+// grid_override (single system) replaces the system's grid_b; energy holds one double per
+// system.
 template <class T, int P>
 __global__ __launch_bounds__(256) void k_gather(const typename Vec4<T>::type* __restrict__ sorted,
-                                                const int* __restrict__ cells,
-                                                const int* __restrict__ perm, const int* __restrict__ tile_start,
-                                                const double* __restrict__ coef, int deg, int m, int B, int Tn, int S,
-                                                const T* __restrict__ grid, T* __restrict__ phi, T* __restrict__ vec,
-                                                int vec_mode, double inv_h, double self_coef, int add_self,
+                                                const int* __restrict__ cells, const int* __restrict__ perm,
+                                                const int* __restrict__ tile_start, int nsys,
+                                                const SysDesc* __restrict__ sys, const int* __restrict__ tile_prefix,
+                                                const int* __restrict__ tile_sys, int tile_offset,
+                                                const T* __restrict__ grid_override, T* __restrict__ phi,
+                                                T* __restrict__ vec, int vec_mode, int add_self,
                                                 double* __restrict__ energy) {
   constexpr int REC = 6 * P;  // values x, y, z then derivatives x, y, z (d/dg)
   extern __shared__ unsigned char smem_raw[];
+  __shared__ double s_red[4];
+  const int gtile = tile_offset + static_cast<int>(blockIdx.x);
+  const int p0 = tile_start[gtile], p1 = tile_start[gtile + 1];
+  if (p0 == p1) return;
+  const int s = tile_sys[find_sys(tile_prefix, nsys, gtile)];
+  const SysDesc& sd = sys[s];
+  const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S, deg = sd.deg;
+  const double* __restrict__ coef = sd.coef;
+  const T* __restrict__ grid = grid_override ? grid_override : static_cast<const T*>(sd.grid_b);
+  const double inv_h = sd.inv_h, self_coef = sd.self_coef;
   const int S3 = S * S * S;
   double* recs = reinterpret_cast<double*>(smem_raw);              // kSlotsPerBlock * REC
   T* tb = reinterpret_cast<T*>(recs + kSlotsPerBlock * REC);
-  __shared__ double s_red[4];
-  const int tile = blockIdx.x;
-  const int p0 = tile_start[tile], p1 = tile_start[tile + 1];
-  if (p0 == p1) return;
+  const int tile = gtile - sd.tile_base;
   const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
   const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
   const int half = (P + 1) / 2;
@@ -383,7 +427,7 @@ __global__ __launch_bounds__(256) void k_gather(const typename Vec4<T>::type* __
     for (int off = 32; off > 0; off >>= 1) esum += __shfl_xor(esum, off, 64);
     if (lane == 0) s_red[threadIdx.x >> 6] = esum;
     __syncthreads();
-    if (threadIdx.x == 0) unsafeAtomicAdd(energy, 0.5 * (s_red[0] + s_red[1] + s_red[2] + s_red[3]));
+    if (threadIdx.x == 0) unsafeAtomicAdd(energy + s, 0.5 * (s_red[0] + s_red[1] + s_red[2] + s_red[3]));
   }
 }
 
@@ -467,22 +511,27 @@ __device__ C* fft_lds(C* A, C* Bf, int nseq, int ss, const FftPlan& pl, const C*
   return src;
 }
 
-// x-direction real-to-complex FFT (sign +) of `nrows` rows of m reals via an m/2-point complex
-// FFT of (a_2j + i a_2j+1); writes X_k, k = 0..m/2, to spec. Optionally zeroes the input rows.
+// x-direction real-to-complex FFT (sign +) of the m^2 rows of m reals of each system, via an
+// m/2-point complex FFT of (a_2j + i a_2j+1); writes X_k, k = 0..m/2, to the system's spectrum.
+// The input is the float64 grid_a (zeroed after it is read when zero_input is set) or, for a
+// single system, in_override.
 template <class T, class TI>
-__global__ __launch_bounds__(256) void k_fft_x_r2c(const TI* __restrict__ grid, TI* zero_after, int m, int nrows,
-                                                   int rpb, FftPlan pl, const typename Cplx<T>::type* __restrict__ tw_half,
-                                                   const typename Cplx<T>::type* __restrict__ tw_full,
-                                                   typename Cplx<T>::type* __restrict__ spec) {
+__global__ __launch_bounds__(256) void k_fft_x_r2c(int nsys, const SysDesc* __restrict__ sys,
+                                                   const int* __restrict__ xblk_prefix, const TI* in_override,
+                                                   int zero_input) {
   using C = typename Cplx<T>::type;
   extern __shared__ unsigned char smem_raw[];
-  const int N = m / 2;
+  const SysDesc& sd = sys[find_sys(xblk_prefix, nsys, static_cast<int>(blockIdx.x))];
+  const int m = sd.m, N = m / 2, nrows = m * m, rpb = sd.rows_per_block;
+  const C* __restrict__ tw_half = static_cast<const C*>(sd.twhp);
+  const C* __restrict__ tw_full = static_cast<const C*>(sd.twfp);
   C* A = reinterpret_cast<C*>(smem_raw);
   C* Bf = A + rpb * N;
-  const int row0 = blockIdx.x * rpb;
+  const int row0 = (static_cast<int>(blockIdx.x) - sd.xblk_base) * rpb;
   const int nr = min(rpb, nrows - row0);
+  const TI* grid = in_override ? in_override : reinterpret_cast<const TI*>(sd.grid_a);
   const TI* src = grid + static_cast<int64_t>(row0) * m;
-  TI* zsrc = zero_after ? zero_after + static_cast<int64_t>(row0) * m : nullptr;
+  TI* zsrc = zero_input ? const_cast<TI*>(src) : nullptr;
   for (int e = threadIdx.x; e < nr * N; e += blockDim.x) {
     A[e] = C{static_cast<T>(src[2 * e]), static_cast<T>(src[2 * e + 1])};
     if (zsrc) {
@@ -491,8 +540,8 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(const TI* __restrict__ grid, 
     }
   }
   __syncthreads();
-  const C* Z = fft_lds(A, Bf, nr, N, pl, tw_half);
-  C* out = spec + static_cast<int64_t>(row0) * (N + 1);
+  const C* Z = fft_lds(A, Bf, nr, N, sd.fh, tw_half);
+  C* out = static_cast<C*>(sd.spec) + static_cast<int64_t>(row0) * (N + 1);
   for (int e = threadIdx.x; e < nr * (N + 1); e += blockDim.x) {
     const int r = e / (N + 1), k = e - r * (N + 1);
     const C zk = Z[r * N + (k == N ? 0 : k)];
@@ -507,19 +556,21 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(const TI* __restrict__ grid, 
 
 // x-direction complex-to-real inverse FFT (sign -): from X_k, k = 0..m/2 (Hermitian), forms
 // Z_k = (X_k + conj X_{N-k}) + i w^{-k} (X_k - conj X_{N-k}), an m/2-point inverse FFT, and writes
-// a_2j = Re z_j, a_2j+1 = Im z_j.
+// a_2j = Re z_j, a_2j+1 = Im z_j to the system's grid_b (or, single system, out_override).
 template <class T>
-__global__ __launch_bounds__(256) void k_fft_x_c2r(const typename Cplx<T>::type* __restrict__ spec, int m, int nrows,
-                                                   int rpb, FftPlan pl, const typename Cplx<T>::type* __restrict__ tw_half,
-                                                   const typename Cplx<T>::type* __restrict__ tw_full, T* __restrict__ grid) {
+__global__ __launch_bounds__(256) void k_fft_x_c2r(int nsys, const SysDesc* __restrict__ sys,
+                                                   const int* __restrict__ xblk_prefix, T* out_override) {
   using C = typename Cplx<T>::type;
   extern __shared__ unsigned char smem_raw[];
-  const int N = m / 2;
+  const SysDesc& sd = sys[find_sys(xblk_prefix, nsys, static_cast<int>(blockIdx.x))];
+  const int m = sd.m, N = m / 2, nrows = m * m, rpb = sd.rows_per_block;
+  const C* __restrict__ tw_half = static_cast<const C*>(sd.twhm);
+  const C* __restrict__ tw_full = static_cast<const C*>(sd.twfm);
   C* A = reinterpret_cast<C*>(smem_raw);   // rpb * (N + 1)
   C* Bf = A + rpb * (N + 1);               // rpb * N
-  const int row0 = blockIdx.x * rpb;
+  const int row0 = (static_cast<int>(blockIdx.x) - sd.xblk_base) * rpb;
   const int nr = min(rpb, nrows - row0);
-  const C* in = spec + static_cast<int64_t>(row0) * (N + 1);
+  const C* in = static_cast<const C*>(sd.spec) + static_cast<int64_t>(row0) * (N + 1);
   for (int e = threadIdx.x; e < nr * (N + 1); e += blockDim.x) A[e] = in[e];
   __syncthreads();
   for (int e = threadIdx.x; e < nr * N; e += blockDim.x) {
@@ -531,210 +582,66 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(const typename Cplx<T>::type*
     Bf[e] = C{s.x - d.y, s.y + d.x};  // s + i d
   }
   __syncthreads();
-  const C* Z = fft_lds(Bf, A, nr, N, pl, tw_half);
+  const C* Z = fft_lds(Bf, A, nr, N, sd.fh, tw_half);
+  T* grid = out_override ? out_override : static_cast<T*>(sd.grid_b);
   C* dst = reinterpret_cast<C*>(grid + static_cast<int64_t>(row0) * m);
   for (int e = threadIdx.x; e < nr * N; e += blockDim.x) dst[e] = Z[e];
 }
 
-// FFT along y or z of the half spectrum. Sequence c of a block is the column kx0 + c; its
-// element e sits at spec[outer * ostride + e * estride + kx0 + c]. With `scale`, the block
-// runs the forward transform along z, multiplies by s_k = T_M[|k|^2] W[|kx|] W[|ky|] W[|kz|]
-// (ky = outer), and runs the inverse transform along z (Alg. 2 steps 2-4 for this column).
+// FFT along y or z of each system's half spectrum. A system's blocks are (outer, column
+// block) pairs; sequence c of a block is the column kx0 + c, whose element e sits at
+// spec[outer * ostride + e * estride + kx0 + c].
+//   mode 0: forward y (outer = z plane);  mode 2: inverse y;
+//   mode 1: forward z, multiply by s_k = T_M[|k|^2] W[|kx|] W[|ky|] W[|kz|] (ky = outer), inverse
+//           z (Alg. 2 steps 2-4 for this column; outer = y row).
 template <class T>
-__global__ __launch_bounds__(256) void k_fft_cols(typename Cplx<T>::type* __restrict__ spec, int m, int nx1,
-                                                  int64_t ostride, int64_t estride, int cpb, FftPlan pl,
-                                                  const typename Cplx<T>::type* __restrict__ tw, int scale,
-                                                  const typename Cplx<T>::type* __restrict__ tw_inv,
-                                                  const T* __restrict__ tm, const T* __restrict__ wk) {
+__global__ __launch_bounds__(256) void k_fft_cols(int nsys, const SysDesc* __restrict__ sys,
+                                                  const int* __restrict__ cblk_prefix, int mode) {
   using C = typename Cplx<T>::type;
   extern __shared__ unsigned char smem_raw[];
+  const SysDesc& sd = sys[find_sys(cblk_prefix, nsys, static_cast<int>(blockIdx.x))];
+  const int m = sd.m, nx1 = m / 2 + 1, cpb = sd.cols_per_block;
+  const int nxb = (nx1 + cpb - 1) / cpb;
+  const int lb = static_cast<int>(blockIdx.x) - sd.cblk_base;
+  const int outer = lb / nxb;
+  const int kx0 = (lb - outer * nxb) * cpb;
+  const int nc = min(cpb, nx1 - kx0);
+  const int64_t plane = static_cast<int64_t>(m) * nx1;
+  const int64_t ostride = mode == 1 ? int64_t(nx1) : plane;
+  const int64_t estride = mode == 1 ? plane : int64_t(nx1);
+  const C* __restrict__ tw = static_cast<const C*>(mode == 2 ? sd.twfm : sd.twfp);
   const int ss = m + 1;  // padded sequence stride in LDS
   C* A = reinterpret_cast<C*>(smem_raw);
   C* Bf = A + cpb * ss;
-  const int kx0 = blockIdx.x * cpb;
-  const int outer = blockIdx.y;
-  const int nc = min(cpb, nx1 - kx0);
-  C* base = spec + outer * ostride + kx0;
+  C* base = static_cast<C*>(sd.spec) + outer * ostride + kx0;
   for (int i = threadIdx.x; i < nc * m; i += blockDim.x) {
     const int e = i / nc, c = i - e * nc;
     A[c * ss + e] = base[e * estride + c];
   }
   __syncthreads();
-  C* R1 = fft_lds(A, Bf, nc, ss, pl, tw);
-  if (scale) {
+  C* R1 = fft_lds(A, Bf, nc, ss, sd.ff, tw);
+  if (mode == 1) {
+    const T* __restrict__ tm = static_cast<const T*>(sd.tm);
+    const T* __restrict__ wk = static_cast<const T*>(sd.wk);
     const int ky = outer <= (m - 1) / 2 ? outer : m - outer;
     for (int i = threadIdx.x; i < nc * m; i += blockDim.x) {
       const int c = i / m, e = i - c * m;
       const int kx = kx0 + c;
       const int kz = e <= (m - 1) / 2 ? e : m - e;
-      const T s = tm[kx * kx + ky * ky + kz * kz] * wk[kx] * wk[ky] * wk[kz];
+      const T sc = tm[kx * kx + ky * ky + kz * kz] * wk[kx] * wk[ky] * wk[kz];
       C v = R1[c * ss + e];
-      v.x *= s;
-      v.y *= s;
+      v.x *= sc;
+      v.y *= sc;
       R1[c * ss + e] = v;
     }
     __syncthreads();
     C* other = (R1 == A) ? Bf : A;
-    R1 = fft_lds(R1, other, nc, ss, pl, tw_inv);
+    R1 = fft_lds(R1, other, nc, ss, sd.ff, static_cast<const C*>(sd.twfm));
   }
   for (int i = threadIdx.x; i < nc * m; i += blockDim.x) {
     const int e = i / nc, c = i - e * nc;
     base[e * estride + c] = R1[c * ss + e];
   }
-}
-
-template <class T>
-__global__ void k_zero(T* __restrict__ p, int64_t count) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    p[i] = T(0);
-}
-
-// ------------------------------------------------------------------------------------
-// Launch helpers
-// ------------------------------------------------------------------------------------
-inline unsigned blocks_for(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
-
-template <class T>
-hipError_t bin_impl(const DevPlan& d, int64_t n, const void* pos, const void* q, double* energy, hipStream_t st) {
-  const T ih_hi = static_cast<T>(d.inv_h_hi), ih_lo = static_cast<T>(d.inv_h_lo), L = static_cast<T>(d.L);
-  stage_begin(d, kStageBin, st);
-  if (n > 0) {
-    hipLaunchKernelGGL(k_bin_count<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n,
-                       static_cast<const T*>(pos), ih_hi, ih_lo, L, d.m, d.B, d.Tn, d.tile_count, d.tile_of, d.rank,
-                       energy);
-  } else if (energy) {
-    hipLaunchKernelGGL(k_zero<double>, dim3(1), dim3(64), 0, st, energy, int64_t(1));
-  }
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d.ntiles, d.tile_count, d.tile_start);
-  if (n > 0)
-    hipLaunchKernelGGL(k_bin_scatter<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, static_cast<const T*>(pos),
-                       static_cast<const T*>(q), ih_hi, ih_lo, L, d.m, d.tile_of, d.rank, d.tile_start,
-                       static_cast<typename Vec4<T>::type*>(d.sorted), d.cells, d.perm);
-  stage_end(d, kStageBin, st);
-  return hipGetLastError();
-}
-
-template <class T, int P>
-hipError_t spread_impl(const DevPlan& d, void* grid, hipStream_t st) {
-  const size_t lds = sizeof(double) * (static_cast<size_t>(d.S) * d.S * d.S + kSlotsPerBlock * 3 * P);
-  if (lds > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<T, P>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    if (e != hipSuccess) return e;
-  }
-  stage_begin(d, kStageSpread, st);
-  hipLaunchKernelGGL((k_spread<T, P>), dim3(d.ntiles), dim3(256), lds, st,
-                     static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start,
-                     static_cast<const double*>(d.coef), d.deg, d.m, d.B, d.Tn, d.S, static_cast<double*>(grid));
-  stage_end(d, kStageSpread, st);
-  return hipGetLastError();
-}
-
-template <class T, int P>
-hipError_t gather_impl(const DevPlan& d, const void* grid, void* phi, void* vec, int vec_mode, bool add_self,
-                       double* energy, hipStream_t st) {
-  const size_t lds = sizeof(double) * kSlotsPerBlock * 6 * P + sizeof(T) * static_cast<size_t>(d.S) * d.S * d.S;
-  if (lds > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<T, P>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    if (e != hipSuccess) return e;
-  }
-  stage_begin(d, kStageGather, st);
-  hipLaunchKernelGGL((k_gather<T, P>), dim3(d.ntiles), dim3(256), lds, st,
-                     static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.perm, d.tile_start,
-                     static_cast<const double*>(d.coef), d.deg, d.m, d.B, d.Tn, d.S, static_cast<const T*>(grid),
-                     static_cast<T*>(phi), static_cast<T*>(vec), vec_mode, d.inv_h, d.self_coef,
-                     add_self ? 1 : 0, energy);
-  stage_end(d, kStageGather, st);
-  return hipGetLastError();
-}
-
-template <class T, int P>
-hipError_t spread_dispatch(const DevPlan& d, void* grid, hipStream_t st) {
-  if (d.P == P) return spread_impl<T, P>(d, grid, st);
-  if constexpr (P < kPmax) return spread_dispatch<T, P + 1>(d, grid, st);
-  return hipErrorInvalidValue;
-}
-
-template <class T, int P>
-hipError_t gather_dispatch(const DevPlan& d, const void* grid, void* phi, void* vec, int vec_mode, bool add_self,
-                           double* energy, hipStream_t st) {
-  if (d.P == P) return gather_impl<T, P>(d, grid, phi, vec, vec_mode, add_self, energy, st);
-  if constexpr (P < kPmax) return gather_dispatch<T, P + 1>(d, grid, phi, vec, vec_mode, add_self, energy, st);
-  return hipErrorInvalidValue;
-}
-
-template <class T>
-hipError_t transform_impl(const DevPlan& d, const void* grid_in, bool in_f64, void* grid_out, bool zero_input,
-                          hipStream_t st) {
-  using C = typename Cplx<T>::type;
-  const int m = d.m, N = m / 2, nx1 = N + 1, nrows = m * m;
-  C* spec = static_cast<C*>(d.spec);
-  const int rpb = d.rows_per_block, cpb = d.cols_per_block;
-  const size_t lds_x = sizeof(C) * 2 * static_cast<size_t>(rpb) * (N + 1);
-  const size_t lds_c = sizeof(C) * 2 * static_cast<size_t>(cpb) * (m + 1);
-  const C* twhp = static_cast<const C*>(d.tw_half_p);
-  const C* twhm = static_cast<const C*>(d.tw_half_m);
-  const C* twfp = static_cast<const C*>(d.tw_full_p);
-  const C* twfm = static_cast<const C*>(d.tw_full_m);
-  stage_begin(d, kStageFftX, st);
-  if (in_f64)
-    hipLaunchKernelGGL((k_fft_x_r2c<T, double>), dim3(blocks_for(nrows, rpb)), dim3(256), lds_x, st,
-                       static_cast<const double*>(grid_in),
-                       zero_input ? static_cast<double*>(const_cast<void*>(grid_in)) : nullptr, m, nrows, rpb,
-                       d.fft_half, twhp, twfp, spec);
-  else
-    hipLaunchKernelGGL((k_fft_x_r2c<T, T>), dim3(blocks_for(nrows, rpb)), dim3(256), lds_x, st,
-                       static_cast<const T*>(grid_in), zero_input ? static_cast<T*>(const_cast<void*>(grid_in)) : nullptr,
-                       m, nrows, rpb, d.fft_half, twhp, twfp, spec);
-  stage_end(d, kStageFftX, st);
-  const dim3 gcols(blocks_for(nx1, cpb), m);
-  // y forward: outer = z plane, element stride nx1
-  stage_begin(d, kStageFftY, st);
-  hipLaunchKernelGGL(k_fft_cols<T>, gcols, dim3(256), lds_c, st, spec, m, nx1, int64_t(m) * nx1, int64_t(nx1), cpb,
-                     d.fft_full, twfp, 0, twfm, static_cast<const T*>(d.tm), static_cast<const T*>(d.wk));
-  stage_end(d, kStageFftY, st);
-  // z forward, scale, z inverse: outer = y row, element stride m * nx1
-  stage_begin(d, kStageFftZScale, st);
-  hipLaunchKernelGGL(k_fft_cols<T>, gcols, dim3(256), lds_c, st, spec, m, nx1, int64_t(nx1), int64_t(m) * nx1, cpb,
-                     d.fft_full, twfp, 1, twfm, static_cast<const T*>(d.tm), static_cast<const T*>(d.wk));
-  stage_end(d, kStageFftZScale, st);
-  // y inverse
-  stage_begin(d, kStageIfftY, st);
-  hipLaunchKernelGGL(k_fft_cols<T>, gcols, dim3(256), lds_c, st, spec, m, nx1, int64_t(m) * nx1, int64_t(nx1), cpb,
-                     d.fft_full, twfm, 0, twfm, static_cast<const T*>(d.tm), static_cast<const T*>(d.wk));
-  stage_end(d, kStageIfftY, st);
-  stage_begin(d, kStageIfftX, st);
-  hipLaunchKernelGGL(k_fft_x_c2r<T>, dim3(blocks_for(nrows, rpb)), dim3(256), lds_x, st,
-                     static_cast<const C*>(spec), m, nrows, rpb, d.fft_half, twhm, twfm, static_cast<T*>(grid_out));
-  stage_end(d, kStageIfftX, st);
-  return hipGetLastError();
-}
-
-}  // namespace
-
-hipError_t launch_bin(const DevPlan& d, int64_t n, const void* pos, const void* q, double* energy, hipStream_t st) {
-  return d.prec == 0 ? bin_impl<float>(d, n, pos, q, energy, st) : bin_impl<double>(d, n, pos, q, energy, st);
-}
-
-hipError_t launch_spread(const DevPlan& d, void* grid, hipStream_t st) {
-  return d.prec == 0 ? spread_dispatch<float, kPmin>(d, grid, st) : spread_dispatch<double, kPmin>(d, grid, st);
-}
-
-hipError_t launch_zero(const DevPlan& d, void* buf, int64_t count, hipStream_t st) {
-  const unsigned nb = std::min<unsigned>(blocks_for(count, 256), 4096u);
-  if (d.prec == 0)
-    hipLaunchKernelGGL(k_zero<float>, dim3(std::max(nb, 1u)), dim3(256), 0, st, static_cast<float*>(buf), count);
-  else
-    hipLaunchKernelGGL(k_zero<double>, dim3(std::max(nb, 1u)), dim3(256), 0, st, static_cast<double*>(buf), count);
-  return hipGetLastError();
-}
-
-hipError_t launch_transform(const DevPlan& d, const void* grid_in, bool in_f64, void* grid_out, bool zero_input,
-                            hipStream_t st) {
-  return d.prec == 0 ? transform_impl<float>(d, grid_in, in_f64, grid_out, zero_input, st)
-                     : transform_impl<double>(d, grid_in, true, grid_out, zero_input, st);
 }
 
 // Copies the float64 accumulation grid into a grid of the plan's precision and zeroes it.
@@ -747,23 +654,166 @@ __global__ void k_drain(double* __restrict__ acc, T* __restrict__ out, int64_t c
   }
 }
 
-hipError_t launch_drain(const DevPlan& d, void* out, hipStream_t st) {
-  const int64_t count = static_cast<int64_t>(d.m) * d.m * d.m;
-  const unsigned nb = std::max(1u, std::min<unsigned>(blocks_for(count, 256), 4096u));
-  if (d.prec == 0)
-    hipLaunchKernelGGL(k_drain<float>, dim3(nb), dim3(256), 0, st, static_cast<double*>(d.grid_a),
-                       static_cast<float*>(out), count);
-  else
-    hipLaunchKernelGGL(k_drain<double>, dim3(nb), dim3(256), 0, st, static_cast<double*>(d.grid_a),
-                       static_cast<double*>(out), count);
+// ------------------------------------------------------------------------------------
+// Launch helpers
+// ------------------------------------------------------------------------------------
+inline unsigned blocks_for(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
+
+template <class T>
+hipError_t bin_impl(const DevPlan& d, int64_t n, const void* pos, const void* q, double* energy, hipStream_t st) {
+  stage_begin(d, kStageBin, st);
+  const int64_t nthreads = std::max<int64_t>(n, energy ? d.nsys : 0);
+  if (nthreads > 0)
+    hipLaunchKernelGGL(k_bin_count<T>, dim3(blocks_for(nthreads, 256)), dim3(256), 0, st, n, d.nsys, d.sys_dev,
+                       d.part_prefix, static_cast<const T*>(pos), d.tile_count, d.tile_of, d.rank, energy);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d.total_tiles, d.tile_count, d.tile_start);
+  if (n > 0)
+    hipLaunchKernelGGL(k_bin_scatter<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d.nsys, d.sys_dev,
+                       d.part_prefix, static_cast<const T*>(pos), static_cast<const T*>(q), d.tile_of, d.rank,
+                       d.tile_start, static_cast<typename Vec4<T>::type*>(d.sorted), d.cells, d.perm);
+  stage_end(d, kStageBin, st);
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const DevPlan& d, int64_t n, const void* grid, void* phi, void* vec, int vec_mode,
+template <class T, int P>
+hipError_t spread_impl(const DevPlan& d, const PGroup& g, hipStream_t st) {
+  hipLaunchKernelGGL((k_spread<T, P>), dim3(g.tile_end - g.tile_begin), dim3(256), g.lds_spread, st,
+                     static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start, d.nsys, d.sys_dev,
+                     d.tile_prefix, d.tile_sys, g.tile_begin);
+  return hipGetLastError();
+}
+
+template <class T, int P>
+hipError_t gather_impl(const DevPlan& d, const PGroup& g, const void* grid, void* phi, void* vec, int vec_mode,
+                       bool add_self, double* energy, hipStream_t st) {
+  hipLaunchKernelGGL((k_gather<T, P>), dim3(g.tile_end - g.tile_begin), dim3(256), g.lds_gather, st,
+                     static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.perm, d.tile_start, d.nsys,
+                     d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin, static_cast<const T*>(grid),
+                     static_cast<T*>(phi), static_cast<T*>(vec), vec_mode, add_self ? 1 : 0, energy);
+  return hipGetLastError();
+}
+
+// Raises the dynamic-LDS limit of the particle kernels of one P group where needed.
+template <class T, int P>
+hipError_t prepare_impl(const PGroup& g) {
+  if (g.lds_spread > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<T, P>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             static_cast<int>(g.lds_spread));
+    if (e != hipSuccess) return e;
+  }
+  if (g.lds_gather > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<T, P>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             static_cast<int>(g.lds_gather));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <class T, int P>
+hipError_t prepare_dispatch(const PGroup& g) {
+  if (g.P == P) return prepare_impl<T, P>(g);
+  if constexpr (P < kPmax) return prepare_dispatch<T, P + 1>(g);
+  return hipErrorInvalidValue;
+}
+
+template <class T, int P>
+hipError_t spread_dispatch(const DevPlan& d, const PGroup& g, hipStream_t st) {
+  if (g.P == P) return spread_impl<T, P>(d, g, st);
+  if constexpr (P < kPmax) return spread_dispatch<T, P + 1>(d, g, st);
+  return hipErrorInvalidValue;
+}
+
+template <class T, int P>
+hipError_t gather_dispatch(const DevPlan& d, const PGroup& g, const void* grid, void* phi, void* vec, int vec_mode,
+                           bool add_self, double* energy, hipStream_t st) {
+  if (g.P == P) return gather_impl<T, P>(d, g, grid, phi, vec, vec_mode, add_self, energy, st);
+  if constexpr (P < kPmax) return gather_dispatch<T, P + 1>(d, g, grid, phi, vec, vec_mode, add_self, energy, st);
+  return hipErrorInvalidValue;
+}
+
+template <class T>
+hipError_t transform_impl(const DevPlan& d, const void* in_override, void* out_override, hipStream_t st) {
+  stage_begin(d, kStageFftX, st);
+  if (in_override)
+    hipLaunchKernelGGL((k_fft_x_r2c<T, T>), dim3(d.total_xblk), dim3(256), d.lds_x, st, d.nsys, d.sys_dev,
+                       d.xblk_prefix, static_cast<const T*>(in_override), 0);
+  else
+    hipLaunchKernelGGL((k_fft_x_r2c<T, double>), dim3(d.total_xblk), dim3(256), d.lds_x, st, d.nsys, d.sys_dev,
+                       d.xblk_prefix, static_cast<const double*>(nullptr), 1);
+  stage_end(d, kStageFftX, st);
+  stage_begin(d, kStageFftY, st);
+  hipLaunchKernelGGL(k_fft_cols<T>, dim3(d.total_cblk), dim3(256), d.lds_c, st, d.nsys, d.sys_dev, d.cblk_prefix, 0);
+  stage_end(d, kStageFftY, st);
+  stage_begin(d, kStageFftZScale, st);
+  hipLaunchKernelGGL(k_fft_cols<T>, dim3(d.total_cblk), dim3(256), d.lds_c, st, d.nsys, d.sys_dev, d.cblk_prefix, 1);
+  stage_end(d, kStageFftZScale, st);
+  stage_begin(d, kStageIfftY, st);
+  hipLaunchKernelGGL(k_fft_cols<T>, dim3(d.total_cblk), dim3(256), d.lds_c, st, d.nsys, d.sys_dev, d.cblk_prefix, 2);
+  stage_end(d, kStageIfftY, st);
+  stage_begin(d, kStageIfftX, st);
+  hipLaunchKernelGGL(k_fft_x_c2r<T>, dim3(d.total_xblk), dim3(256), d.lds_x, st, d.nsys, d.sys_dev, d.xblk_prefix,
+                     static_cast<T*>(out_override));
+  stage_end(d, kStageIfftX, st);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t prepare_kernels(const DevPlan& d) {
+  for (const PGroup& g : d.groups) {
+    const hipError_t e = d.prec == 0 ? prepare_dispatch<float, kPmin>(g) : prepare_dispatch<double, kPmin>(g);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_bin(const DevPlan& d, int64_t n_total, const void* pos, const void* q, double* energy,
+                      hipStream_t st) {
+  return d.prec == 0 ? bin_impl<float>(d, n_total, pos, q, energy, st)
+                     : bin_impl<double>(d, n_total, pos, q, energy, st);
+}
+
+hipError_t launch_spread(const DevPlan& d, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  stage_begin(d, kStageSpread, st);
+  for (const PGroup& g : d.groups) {
+    e = d.prec == 0 ? spread_dispatch<float, kPmin>(d, g, st) : spread_dispatch<double, kPmin>(d, g, st);
+    if (e != hipSuccess) break;
+  }
+  stage_end(d, kStageSpread, st);
+  return e;
+}
+
+hipError_t launch_drain(const DevPlan& d, void* out, hipStream_t st) {
+  const SysDesc& s0 = d.sys[0];
+  const int64_t count = static_cast<int64_t>(s0.m) * s0.m * s0.m;
+  const unsigned nb = std::max(1u, std::min<unsigned>(blocks_for(count, 256), 4096u));
+  if (d.prec == 0)
+    hipLaunchKernelGGL(k_drain<float>, dim3(nb), dim3(256), 0, st, s0.grid_a, static_cast<float*>(out), count);
+  else
+    hipLaunchKernelGGL(k_drain<double>, dim3(nb), dim3(256), 0, st, s0.grid_a, static_cast<double*>(out), count);
+  return hipGetLastError();
+}
+
+hipError_t launch_transform(const DevPlan& d, const void* in_override, void* out_override, hipStream_t st) {
+  return d.prec == 0 ? transform_impl<float>(d, in_override, out_override, st)
+                     : transform_impl<double>(d, in_override, out_override, st);
+}
+
+hipError_t launch_gather(const DevPlan& d, const void* grid_override, void* phi, void* vec, int vec_mode,
                          bool add_self, double* energy, hipStream_t st) {
-  (void)n;
-  return d.prec == 0 ? gather_dispatch<float, kPmin>(d, grid, phi, vec, vec_mode, add_self, energy, st)
-                     : gather_dispatch<double, kPmin>(d, grid, phi, vec, vec_mode, add_self, energy, st);
+  hipError_t e = hipSuccess;
+  stage_begin(d, kStageGather, st);
+  for (const PGroup& g : d.groups) {
+    e = d.prec == 0
+            ? gather_dispatch<float, kPmin>(d, g, grid_override, phi, vec, vec_mode, add_self, energy, st)
+            : gather_dispatch<double, kPmin>(d, g, grid_override, phi, vec, vec_mode, add_self, energy, st);
+    if (e != hipSuccess) break;
+  }
+  stage_end(d, kStageGather, st);
+  return e;
 }
 
 }  // namespace pswfe

@@ -1,9 +1,15 @@
 // Device kernels of the PSWF fast Ewald pipeline (Alg. 2) and their launch helpers.
+//
+// Every launch covers a batch of independent systems (a single-system plan is a batch of one):
+// each system has a descriptor (grid size, tile geometry, tables, buffers) and owns a
+// contiguous range of the global tile, block and packed-particle index spaces; a workgroup
+// finds its system by binary search in a small prefix table.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace pswfe {
 
@@ -32,42 +38,64 @@ struct StageTimer {
   hipEvent_t* ev = nullptr;  // 2 * cap events: start, stop per call
 };
 
-// Everything a launch needs about a plan, in device terms. Pointers are device pointers in
-// the plan's precision T (real) or 2T (complex interleaved) unless stated.
-struct DevPlan {
-  int prec = 0;        // 0 float, 1 double
+// One system of a batch. Pointers are device pointers; real arrays are in the plan precision
+// unless stated.
+struct SysDesc {
   int m = 0, P = 0, deg = 0;
-  int B = 0;           // tile edge in grid cells (binning and spread/gather tiles)
-  int Tn = 0;          // tiles per dimension
-  int ntiles = 0;
-  int S = 0;           // LDS tile edge = B + 2 ceil(P/2) - 1
-  double L = 0, h = 0, inv_h = 0, self_coef = 0;
-  double inv_h_hi = 0, inv_h_lo = 0;  // m/L split into a working-precision word and its remainder
-  int64_t n_max = 0;
-  // binning
-  int* tile_count = nullptr;   // ntiles, kept all-zero between calls
-  int* tile_start = nullptr;   // ntiles + 1
+  int B = 0;                  // tile edge in grid cells
+  int Tn = 0;                 // tiles per dimension
+  int S = 0;                  // LDS tile edge = B + 2 ceil(P/2) - 1
+  int tile_base = 0;          // first global tile of this system
+  int rows_per_block = 1;     // x-direction FFT batching
+  int cols_per_block = 1;     // y/z-direction FFT batching
+  int xblk_base = 0;          // first block of this system in the x-direction FFT launches
+  int cblk_base = 0;          // first block in the y/z-direction FFT launches
+  int64_t part_base = 0;      // first packed particle of this system
+  double L = 0, inv_h = 0, ih_hi = 0, ih_lo = 0, self_coef = 0;
+  double* grid_a = nullptr;   // m^3 float64 spread target; kept all-zero between calls
+  void* grid_b = nullptr;     // m^3 transformed grid
+  void* spec = nullptr;       // m * m * (m/2 + 1) complex half spectrum
+  const double* coef = nullptr;  // P * (deg + 1) window polynomial coefficients (float64)
+  const void* tm = nullptr;   // 3 (m/2)^2 + 1 radial scaling table
+  const void* wk = nullptr;   // m/2 + 1 window factors
+  const void* twhp = nullptr; // exp(+2 pi i e / (m/2)), e < m/2
+  const void* twhm = nullptr; // exp(-2 pi i e / (m/2))
+  const void* twfp = nullptr; // exp(+2 pi i e / m), e < m
+  const void* twfm = nullptr; // exp(-2 pi i e / m)
+  FftPlan fh, ff;             // radix plans for lengths m/2 and m
+};
+
+// Systems sharing one window support P: their tiles form the contiguous global range
+// [tile_begin, tile_end), covered by one launch of each particle kernel (templated on P).
+struct PGroup {
+  int P = 0;
+  int tile_begin = 0, tile_end = 0;
+  size_t lds_spread = 0, lds_gather = 0;  // maxima over the group's systems
+};
+
+struct DevPlan {
+  int prec = 0;               // 0 float, 1 double
+  int nsys = 0;
+  int64_t n_max = 0;          // packed particles accepted (batch: exactly this many)
+  std::vector<SysDesc> sys;   // host copies of the descriptors
+  std::vector<PGroup> groups; // by increasing P
+  SysDesc* sys_dev = nullptr;
+  int* tile_prefix = nullptr;      // nsys + 1: tile ranges in global tile order (grouped by P)
+  int* tile_sys = nullptr;         // nsys: system owning the k-th tile range
+  int* xblk_prefix = nullptr;      // nsys + 1, in system order
+  int* cblk_prefix = nullptr;      // nsys + 1, in system order
+  int64_t* part_prefix = nullptr;  // nsys + 1 (batches; a single system takes n per call)
+  int total_tiles = 0, total_xblk = 0, total_cblk = 0;
+  size_t lds_x = 0, lds_c = 0;     // maxima over the systems
+  // binning, over all systems
+  int* tile_count = nullptr;   // total_tiles, kept all-zero between calls
+  int* tile_start = nullptr;   // total_tiles + 1
   int* tile_of = nullptr;      // n_max
   int* rank = nullptr;         // n_max
-  int* perm = nullptr;         // n_max: sorted slot -> input index
-  void* sorted = nullptr;      // n_max x 4 T: (f_x, f_y, f_z, q), fractional cell offsets in [0, 1]
+  int* perm = nullptr;         // n_max: sorted slot -> packed input index
   int* cells = nullptr;        // n_max: packed cell cx + m (cy + m cz) of each sorted particle
-  // grids
-  void* grid_a = nullptr;      // m^3 float64 spread target (both precisions); kept all-zero between calls
-  void* grid_b = nullptr;      // m^3 T, transformed grid
-  void* spec = nullptr;        // m * m * (m/2 + 1) complex T
-  // tables (plan precision)
-  void* coef = nullptr;        // P * (deg + 1) window polynomial coefficients
-  void* tm = nullptr;          // 3 (m/2)^2 + 1
-  void* wk = nullptr;          // m/2 + 1
-  void* tw_half_p = nullptr;   // N = m/2, exp(+2 pi i e / N)
-  void* tw_half_m = nullptr;   // N = m/2, exp(-2 pi i e / N)
-  void* tw_full_p = nullptr;   // N = m,   exp(+2 pi i e / N)
-  void* tw_full_m = nullptr;   // N = m,   exp(-2 pi i e / N)
-  FftPlan fft_half, fft_full;
+  void* sorted = nullptr;      // n_max x 4: (f_x, f_y, f_z, q), fractional cell offsets in [0, 1]
   StageTimer* timer = nullptr; // optional instrumentation
-  int rows_per_block = 1;      // x-direction R2C / C2R batching
-  int cols_per_block = 1;      // y/z-direction batching
 };
 
 inline void stage_begin(const DevPlan& d, int stage, hipStream_t st) {
@@ -82,19 +110,24 @@ inline void stage_end(const DevPlan& d, int stage, hipStream_t st) {
   }
 }
 
-// Pipeline pieces (all enqueue on `stream`, return hipSuccess or the launch error).
-hipError_t launch_bin(const DevPlan& d, int64_t n, const void* pos, const void* q, double* energy_zero,
+// One-time kernel attributes (dynamic LDS above 64 KiB); call at plan creation.
+hipError_t prepare_kernels(const DevPlan& d);
+
+// Pipeline pieces; all enqueue on `stream` and return hipSuccess or the launch error.
+// n_total: packed particles (a single system: its n). energy: nsys doubles zeroed here, or NULL.
+hipError_t launch_bin(const DevPlan& d, int64_t n_total, const void* pos, const void* q, double* energy,
                       hipStream_t stream);
-// Spreads the binned particles into the float64 grid d.grid_a.
-hipError_t launch_spread(const DevPlan& d, void* grid, hipStream_t stream);
-// Copies d.grid_a into `out` (plan precision) and zeroes d.grid_a.
+// Spreads the binned particles into each system's float64 grid_a.
+hipError_t launch_spread(const DevPlan& d, hipStream_t stream);
+// Copies grid_a of system 0 into `out` (plan precision) and zeroes it.
 hipError_t launch_drain(const DevPlan& d, void* out, hipStream_t stream);
-hipError_t launch_zero(const DevPlan& d, void* buf, int64_t count, hipStream_t stream);
-// grid_in is float64 when in_f64 (always for float64 plans), else the plan precision.
-hipError_t launch_transform(const DevPlan& d, const void* grid_in, bool in_f64, void* grid_out, bool zero_input,
-                            hipStream_t stream);
+// Steps 2-4 for every system, grid_a -> grid_b (grid_a zeroed after it is read). With
+// in_override / out_override (single system only) the input is the plan-precision grid
+// in_override (not modified) and the output goes to out_override.
+hipError_t launch_transform(const DevPlan& d, const void* in_override, void* out_override, hipStream_t stream);
 // vec_mode: 0 writes force -q grad(phi), 1 writes grad(phi). add_self adds -self_coef q to phi.
-hipError_t launch_gather(const DevPlan& d, int64_t n, const void* grid, void* phi, void* vec, int vec_mode,
+// grid_override (single system only) replaces grid_b. energy: nsys doubles, accumulated.
+hipError_t launch_gather(const DevPlan& d, const void* grid_override, void* phi, void* vec, int vec_mode,
                          bool add_self, double* energy, hipStream_t stream);
 
 }  // namespace pswfe

@@ -130,5 +130,31 @@ def test_status_codes():
     assert lib.pswfe_plan_create(ctypes.byref(bad), 0, 10, ctypes.byref(h)) == pw.E_GRID
     assert lib.pswfe_compute(None, 0, None, None, None, None, None, None) == pw.E_ARG
     assert lib.pswfe_plan_destroy(None) == pw.OK
+    # batch plans: argument checks happen before any device work
+    arr = (pw.CParams * 2)(p, p)
+    cnt = (ctypes.c_int64 * 2)(10, 20)
+    assert lib.pswfe_batch_plan_create(0, arr, cnt, 0, None, ctypes.byref(h)) == pw.E_ARG
+    assert lib.pswfe_batch_plan_create(2, arr, None, 0, None, ctypes.byref(h)) == pw.E_ARG
+    assert lib.pswfe_batch_plan_create(2, arr, cnt, 7, None, ctypes.byref(h)) == pw.E_PREC
+    assert lib.pswfe_batch_plan_create(2, (pw.CParams * 2)(p, bad), cnt, 0, None, ctypes.byref(h)) == pw.E_GRID
+    assert lib.pswfe_batch_plan_create(2, arr, (ctypes.c_int64 * 2)(10, -1), 0, None, ctypes.byref(h)) == pw.E_ARG
+    assert lib.pswfe_batch_plan_create(2, arr, (ctypes.c_int64 * 2)(2**30, 2**30), 0, None,
+                                       ctypes.byref(h)) == pw.E_ARG
+    assert lib.pswfe_batch_plan_create(2, arr, cnt, 0, (ctypes.c_int32 * 2)(8, 33), ctypes.byref(h)) == pw.E_ARG
+    assert lib.pswfe_batch_compute(None, None, None, None, None, None, None) == pw.E_ARG
+    assert lib.pswfe_batch_compute_grad(None, None, None, None, None, None, None) == pw.E_ARG
+    assert lib.pswfe_plan_num_systems(None) == 0
+    assert lib.pswfe_plan_system(None, 0, None, None, None, None) == pw.E_ARG
     for s in range(8):
         assert lib.pswfe_status_str(s)
+
+
+def test_tile_for_density():
+    from paper_2602_16591_amd.autotune import tile_for_density
+    # about `target` particles per tile: B^3 n / m^3 >= target with the smallest such B >= 4
+    for m, n, t in [(16, 500, 256), (50, 20000, 128), (32, 32768, 64), (48, 1000, 4096), (24, 10**6, 32)]:
+        b = tile_for_density(m, n, t)
+        assert 4 <= b <= m
+        if 4 < b < m:
+            assert b ** 3 * n / m ** 3 >= t - 1e-9 and (b - 1) ** 3 * n / m ** 3 < t
+    assert tile_for_density(16, 0, 256) == 8
