@@ -156,6 +156,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-sequential ensemble")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the measurement, copy a device buffer of this many MiB three times (a kernel of "
+                         "known traffic, to calibrate profiler byte counters); not part of the result")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the pipeline runs on a single MI355X; "
@@ -251,6 +254,13 @@ def main():
         out["batched"] = bench_ensemble(max(5, min(args.steps, 50)), max(2, min(args.warmup, 5)))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, q, L, eps, m)
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": src.numel() * 4, "bytes_written": dst.numel() * 4, "launches": 3}
     print(json.dumps(out), flush=True)
 
 

@@ -20,7 +20,7 @@ ARCH = os.environ.get("PSWFE_ARCH", "gfx950")
 SOURCES = ["host.cpp", "kernels.hip", "capi.hip"]
 
 HIP_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "../../include/pswfe.h"
@@ -62,15 +63,20 @@ pswfe::FftPlan make_fft_plan(int N) {
 // Tile edge B (cells) for binning, spreading and interpolation. The spreading tile holds
 // S^3 float64 accumulators (S = B + 2 ceil(P/2) - 1), at most 150 KiB; the interpolation tile
 // S^3 values of the plan precision plus the window records of 16 particles, at most 156 KiB.
-size_t spread_lds_bytes(int S, int P) { return sizeof(double) * (static_cast<size_t>(S) * S * S + 16 * 3 * P); }
-size_t gather_lds_bytes(int S, int P, int elem) {
-  return static_cast<size_t>(elem) * S * S * S + sizeof(double) * 16 * 6 * P;
+// Both also hold the P coefficient rows of the window polynomials (coef_stride(D) doubles each).
+size_t coef_lds_bytes(int P, int D) { return sizeof(double) * P * pswfe::coef_stride(D); }
+size_t spread_lds_bytes(int S, int P, int D) {
+  return sizeof(double) * (static_cast<size_t>(S) * S * S + 16 * 3 * P) + coef_lds_bytes(P, D);
+}
+size_t gather_lds_bytes(int S, int P, int D, int elem) {
+  return static_cast<size_t>(elem) * S * S * S + sizeof(double) * 16 * 6 * P + coef_lds_bytes(P, D);
 }
 int lds_edge(int B, int P) { return B + 2 * ((P + 1) / 2) - 1; }
 
 bool tile_fits(int B, int P, int elem) {
   const int S = lds_edge(B, P);
-  return spread_lds_bytes(S, P) <= 150 * 1024 && gather_lds_bytes(S, P, elem) <= 156 * 1024;
+  const int D = pswfe::kMaxDeg;  // whatever the degree, the tile fits
+  return spread_lds_bytes(S, P, D) <= 150 * 1024 && gather_lds_bytes(S, P, D, elem) <= 156 * 1024;
 }
 
 // Single systems: B = 8 (measured best on gfx950 for 64^3 and 128^3 grids with P = 12-18),
@@ -252,21 +258,24 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   // range covered by one launch of the particle kernels.
   std::vector<int> order(nsys), tile_prefix(nsys + 1, 0);
   for (int s = 0; s < nsys; ++s) order[s] = s;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return d.sys[a].P < d.sys[b].P; });
+  auto key = [&](int s) { return std::make_pair(d.sys[s].P, pswfe::degree_bucket(d.sys[s].deg)); };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
   for (int k = 0; k < nsys; ++k) {
     pswfe::SysDesc& sd = d.sys[order[k]];
+    const int D = pswfe::degree_bucket(sd.deg);
     sd.tile_base = tile_prefix[k];
     tile_prefix[k + 1] = tile_prefix[k] + sd.Tn * sd.Tn * sd.Tn;
-    if (d.groups.empty() || d.groups.back().P != sd.P) {
+    if (d.groups.empty() || d.groups.back().P != sd.P || d.groups.back().D != D) {
       pswfe::PGroup g;
       g.P = sd.P;
+      g.D = D;
       g.tile_begin = tile_prefix[k];
       d.groups.push_back(g);
     }
     pswfe::PGroup& g = d.groups.back();
     g.tile_end = tile_prefix[k + 1];
-    g.lds_spread = std::max(g.lds_spread, spread_lds_bytes(sd.S, sd.P));
-    g.lds_gather = std::max(g.lds_gather, gather_lds_bytes(sd.S, sd.P, elem));
+    g.lds_spread = std::max(g.lds_spread, spread_lds_bytes(sd.S, sd.P, D));
+    g.lds_gather = std::max(g.lds_gather, gather_lds_bytes(sd.S, sd.P, D, elem));
   }
   d.total_tiles = tile_prefix[nsys];
   d.total_xblk = xblk_prefix[nsys];

@@ -49,6 +49,12 @@ __device__ __forceinline__ int find_sys(const I* __restrict__ prefix, int nsys, 
   return lo;
 }
 
+// Cell coordinates (each < m <= 512) packed into 10-bit fields.
+__device__ __forceinline__ int pack_cell(int cx, int cy, int cz) { return cx | (cy << 10) | (cz << 20); }
+__device__ __forceinline__ int cell_x(int c) { return c & 1023; }
+__device__ __forceinline__ int cell_y(int c) { return (c >> 10) & 1023; }
+__device__ __forceinline__ int cell_z(int c) { return c >> 20; }
+
 // Grid coordinate of x: cell c in [0, m) and fractional offset f with x/h = c + f (mod m).
 // The product x * (1/h) uses 1/h split into two words (ih_hi + ih_lo) and the exact product
 // error from an FMA, so f keeps the working precision's relative accuracy instead of losing
@@ -154,7 +160,7 @@ __global__ __launch_bounds__(1024) void k_scan(int ntiles, int* __restrict__ cou
   if (tid == 0) start[ntiles] = s_carry;
 }
 
-// Sorted record: (f_x, f_y, f_z, q) and the packed cell cx + m (cy + m cz) of its system.
+// Sorted record: (f_x, f_y, f_z, q) and the packed cell of the particle in its system.
 template <class T>
 __global__ void k_bin_scatter(int64_t n, int nsys, const SysDesc* __restrict__ sys,
                               const int64_t* __restrict__ part_prefix, const T* __restrict__ pos,
@@ -173,7 +179,7 @@ __global__ void k_bin_scatter(int64_t n, int nsys, const SysDesc* __restrict__ s
   const int cz = grid_coord(pos[3 * i + 2], ih_hi, ih_lo, L, m, r.z);
   r.w = q ? q[i] : T(0);
   sorted[dst] = r;
-  cells[dst] = cx + m * (cy + m * cz);
+  cells[dst] = pack_cell(cx, cy, cz);
   perm[dst] = static_cast<int>(i);
 }
 
@@ -196,19 +202,65 @@ __device__ __forceinline__ T centred_offset(T f, int c, int T0, int& o) {
   }
 }
 
-__device__ __forceinline__ int wrap_index(int a, int m) {
-  int r = a % m;
-  return r < 0 ? r + m : r;
+// Periodic image of a grid index a in [-m, 3m) (the range of every halo index: a tile origin
+// is below m, tile edge and half support are at most m).
+__device__ __forceinline__ int fold_index(int a, int m) {
+  a += a < 0 ? m : 0;
+  a -= a >= m ? m : 0;
+  a -= a >= m ? m : 0;
+  return a;
+}
+
+// Walks the S^3 points of a tile's LDS block (x fastest) with a stride of one workgroup
+// (256 threads): load(k, lds_index, grid_index) for up to K points per thread, then use(...)
+// for the same points, so K independent memory accesses are in flight before their results
+// are needed. The (x, y, z) offsets advance by the stride's digits instead of being divided
+// out of the flat index.
+template <int K, class Load, class Use>
+__device__ __forceinline__ void walk_tile(int S, int m, int Ox, int Oy, int Oz, Load&& load, Use&& use) {
+  const int S2 = S * S, S3 = S2 * S;
+  const int sz = 256 / S2, sy = (256 - sz * S2) / S, sx = 256 - sz * S2 - sy * S;
+  const int t = threadIdx.x;
+  int iz = t / S2, iy = (t - iz * S2) / S, ix = t - iz * S2 - iy * S;
+  for (int base = t; base < S3; base += 256 * K) {
+    int li[K];
+    int64_t gi[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      li[k] = base + 256 * k;
+      gi[k] = (static_cast<int64_t>(fold_index(Oz + iz, m)) * m + fold_index(Oy + iy, m)) * m + fold_index(Ox + ix, m);
+      ix += sx;
+      if (ix >= S) {
+        ix -= S;
+        ++iy;
+      }
+      iy += sy;
+      if (iy >= S) {
+        iy -= S;
+        ++iz;
+      }
+      iz += sz;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (li[k] < S3) load(k, li[k], gi[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (li[k] < S3) use(k, li[k], gi[k]);
+  }
 }
 
 // ------------------------------------------------------------------------------------
-// Particle kernels, one launch per window support P over the tiles of the systems with that
-// P. A workgroup (4 waves) owns one tile of B^3 cells of one system and an LDS copy of the S^3 grid points its particles' supports touch (S = B + 2 ceil(P/2) - 1).
-// Each wave works on 4 particles at a time, 16 lanes per particle: the 16 lanes evaluate the
-// particle's 3P window polynomials (Horner, float64) into a per-wave LDS record, then share
-// the P^2 (y, z) lines of its support, each lane running the x-direction of its lines. Lanes
-// of a particle touch distinct lines (stride S), so their LDS accesses do not conflict, and no
-// workgroup barrier is needed between particles.
+// Particle kernels, one launch per (window support P, degree bucket D) over the tiles of the
+// systems in that group. A workgroup (4 waves) owns one tile of B^3 cells of one system and an
+// LDS copy of the S^3 grid points its particles' supports touch (S = B + 2 ceil(P/2) - 1).
+// Each wave works on 4 particles at a time, 16 lanes per particle:
+//  * lane j evaluates window piece j for the three coordinates at once (3 independent Horner
+//    chains, 6 with derivatives; pieces j and j + 16 when P > 16), the coefficients of piece j
+//    read from an LDS copy into registers, and writes the values to a per-slot LDS record;
+//  * the 16 lanes then share the P^2 (y, z) lines of the support, each lane running the
+//    x-direction of its lines. Lanes of a particle touch distinct lines (stride S), so their
+//    LDS accesses do not conflict, and no workgroup barrier is needed between particles.
 // Window values, products and sums are float64 in both precisions: on MI355X a float64 FMA
 // issues at the non-packed float32 rate, and float32 window values and products lose ~1e-6
 // relative on systems of neutral molecules, where the grid values are small sums of larger
@@ -225,32 +277,51 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Copies the window coefficients (P pieces of deg + 1 powers, float64) into LDS rows of
+// coef_stride(D) doubles, zero above deg.
+template <int P, int D>
+__device__ __forceinline__ void stage_coefficients(const double* __restrict__ coef, int deg, double* lcoef) {
+  constexpr int CS = coef_stride(D);
+  for (int i = threadIdx.x; i < P * CS; i += blockDim.x) {
+    const int j = i / CS, k = i - j * CS;
+    lcoef[i] = k <= deg ? coef[j * (deg + 1) + k] : 0.0;
+  }
+}
+
 // Spreading (Alg. 2 step 1): the tile accumulates q w_x w_y w_z over the supports with LDS
 // float64 atomic adds (on gfx950 about 20x the throughput of float32 LDS atomics), then adds
 // the tile into its system's float64 HBM grid with atomics (a point lies in the halos of up
 // to ceil(S/B)^3 tiles; their partial sums are larger than the total on systems of neutral
 // molecules, so they are added in float64 and rounded once, by the first FFT pass).
-template <class T, int P>
+// A lane reads the weights of up to kLineChunk lines and the x-window into registers before
+// issuing their atomics: LDS operations complete in order, so an LDS read between atomics
+// would wait for all of them.
+constexpr int kLineChunk = 12;
+
+template <class T, int P, int D>
 __global__ __launch_bounds__(256) void k_spread(const typename Vec4<T>::type* __restrict__ sorted,
                                                 const int* __restrict__ cells, const int* __restrict__ tile_start,
                                                 int nsys, const SysDesc* __restrict__ sys,
                                                 const int* __restrict__ tile_prefix, const int* __restrict__ tile_sys,
                                                 int tile_offset) {
   constexpr int REC = 3 * P;  // window values of one particle: x, y, z
+  constexpr int CS = coef_stride(D);
+  constexpr int NL = (P * P + kLanesPerParticle - 1) / kLanesPerParticle;  // lines per lane
   extern __shared__ unsigned char smem_raw[];
   const int gtile = tile_offset + static_cast<int>(blockIdx.x);
   const int p0 = tile_start[gtile], p1 = tile_start[gtile + 1];
   if (p0 == p1) return;
   const SysDesc& sd = sys[tile_sys[find_sys(tile_prefix, nsys, gtile)]];
-  const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S, deg = sd.deg;
-  const double* __restrict__ coef = sd.coef;
+  const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S;
   double* __restrict__ grid = sd.grid_a;
   double* acc = reinterpret_cast<double*>(smem_raw);
   const int S3 = S * S * S;
-  double* recs = acc + S3;    // kSlotsPerBlock * REC
+  double* recs = acc + S3;                           // kSlotsPerBlock * REC
+  double* lcoef = recs + kSlotsPerBlock * REC;       // P * CS
   const int tile = gtile - sd.tile_base;
   const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
   const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
+  stage_coefficients<P, D>(sd.coef, sd.deg, lcoef);
   for (int i = threadIdx.x; i < S3; i += blockDim.x) acc[i] = 0.0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -258,36 +329,63 @@ __global__ __launch_bounds__(256) void k_spread(const typename Vec4<T>::type* __
   const int li = lane & (kLanesPerParticle - 1);
   double* rec = recs + slot * REC;
   const int nt = p1 - p0;
+  // the record of the next round is loaded while this round's particle is spread
+  auto r_next = sorted[min(p0 + slot, p1 - 1)];
+  int c_next = cells[min(p0 + slot, p1 - 1)];
   for (int base = 0; base < nt; base += kSlotsPerBlock) {
     const int pi = p0 + base + slot;
     const bool active = pi < p1;
-    const auto r = sorted[active ? pi : p0];
-    const int cp = cells[active ? pi : p0];
+    const auto r = r_next;
+    const int cp = c_next;
+    r_next = sorted[min(pi + kSlotsPerBlock, p1 - 1)];
+    c_next = cells[min(pi + kSlotsPerBlock, p1 - 1)];
     int o[3];
     double g[3];
-    g[0] = static_cast<double>(centred_offset<T, P>(r.x, cp % m, T0x, o[0]));
-    g[1] = static_cast<double>(centred_offset<T, P>(r.y, (cp / m) % m, T0y, o[1]));
-    g[2] = static_cast<double>(centred_offset<T, P>(r.z, cp / (m * m), T0z, o[2]));
-    for (int c = li; c < REC; c += kLanesPerParticle) {
-      const int d = c / P, j = c - d * P;
-      const double* cj = coef + j * (deg + 1);
-      const double gd = d == 0 ? g[0] : (d == 1 ? g[1] : g[2]);
-      double v = cj[deg];
-      for (int k = deg - 1; k >= 0; --k) v = fma(v, gd, cj[k]);
-      rec[c] = v;
+    g[0] = static_cast<double>(centred_offset<T, P>(r.x, cell_x(cp), T0x, o[0]));
+    g[1] = static_cast<double>(centred_offset<T, P>(r.y, cell_y(cp), T0y, o[1]));
+    g[2] = static_cast<double>(centred_offset<T, P>(r.z, cell_z(cp), T0z, o[2]));
+#pragma unroll
+    for (int j = li; j < P; j += kLanesPerParticle) {
+      double c[D + 1];
+#pragma unroll
+      for (int k = 0; k <= D; ++k) c[k] = lcoef[j * CS + k];
+      double vx = c[D], vy = c[D], vz = c[D];
+#pragma unroll
+      for (int k = D - 1; k >= 0; --k) {
+        vx = fma(vx, g[0], c[k]);
+        vy = fma(vy, g[1], c[k]);
+        vz = fma(vz, g[2], c[k]);
+      }
+      rec[j] = vx;
+      rec[P + j] = vy;
+      rec[2 * P + j] = vz;
     }
     wave_lds_sync();
     if (active) {
+      const double q = static_cast<double>(r.w);
       double wx[P];
 #pragma unroll
       for (int j = 0; j < P; ++j) wx[j] = rec[j];
-      const double q = static_cast<double>(r.w);
-      for (int e = li; e < P * P; e += kLanesPerParticle) {
-        const int jz = e / P, jy = e - jz * P;
-        const double wyz = q * rec[P + jy] * rec[2 * P + jz];
-        double* row = acc + ((o[2] + jz) * S + (o[1] + jy)) * S + o[0];
 #pragma unroll
-        for (int jx = 0; jx < P; ++jx) atomicAdd(row + jx, wyz * wx[jx]);
+      for (int t0 = 0; t0 < NL; t0 += kLineChunk) {
+        double wl[kLineChunk];
+        int off[kLineChunk];
+#pragma unroll
+        for (int t = 0; t < kLineChunk; ++t) {
+          const int e = li + kLanesPerParticle * (t0 + t);
+          const int jz = e / P, jy = e - jz * P;
+          const bool ok = t0 + t < NL && e < P * P;
+          wl[t] = ok ? q * rec[P + jy] * rec[2 * P + jz] : 0.0;
+          off[t] = ok ? ((o[2] + jz) * S + (o[1] + jy)) * S + o[0] : -1;
+        }
+#pragma unroll
+        for (int t = 0; t < kLineChunk; ++t) {
+          if (off[t] >= 0) {
+            double* row = acc + off[t];
+#pragma unroll
+            for (int jx = 0; jx < P; ++jx) atomicAdd(row + jx, wl[t] * wx[jx]);
+          }
+        }
       }
     }
     wave_lds_sync();
@@ -295,13 +393,12 @@ __global__ __launch_bounds__(256) void k_spread(const typename Vec4<T>::type* __
   __syncthreads();
   const int half = (P + 1) / 2;
   const int Ox = T0x + 1 - half, Oy = T0y + 1 - half, Oz = T0z + 1 - half;
-  for (int i = threadIdx.x; i < S3; i += blockDim.x) {
-    const double v = acc[i];
-    if (v == 0.0) continue;
-    const int ix = i % S, iy = (i / S) % S, iz = i / (S * S);
-    const int gx = wrap_index(Ox + ix, m), gy = wrap_index(Oy + iy, m), gz = wrap_index(Oz + iz, m);
-    atomic_add_global(grid + (static_cast<int64_t>(gz) * m + gy) * m + gx, v);
-  }
+  double v[8];
+  walk_tile<8>(
+      S, m, Ox, Oy, Oz, [&](int k, int li_, int64_t) { v[k] = acc[li_]; },
+      [&](int k, int, int64_t gi) {
+        if (v[k] != 0.0) atomic_add_global(grid + gi, v[k]);
+      });
 }
 
 // Interpolation (Alg. 2 step 5 and eq. force): phi = sum b w_x w_y w_z and its gradient as
@@ -309,7 +406,7 @@ __global__ __launch_bounds__(256) void k_spread(const typename Vec4<T>::type* __
 // weights them with the y/z windows and derivatives, and the 16 lanes of a particle reduce.
 // grid_override (single system) replaces the system's grid_b; energy holds one double per
 // system.
-template <class T, int P>
+template <class T, int P, int D>
 __global__ __launch_bounds__(256) void k_gather(const typename Vec4<T>::type* __restrict__ sorted,
                                                 const int* __restrict__ cells, const int* __restrict__ perm,
                                                 const int* __restrict__ tile_start, int nsys,
@@ -319,6 +416,7 @@ __global__ __launch_bounds__(256) void k_gather(const typename Vec4<T>::type* __
                                                 T* __restrict__ vec, int vec_mode, int add_self,
                                                 double* __restrict__ energy) {
   constexpr int REC = 6 * P;  // values x, y, z then derivatives x, y, z (d/dg)
+  constexpr int CS = coef_stride(D);
   extern __shared__ unsigned char smem_raw[];
   __shared__ double s_red[4];
   const int gtile = tile_offset + static_cast<int>(blockIdx.x);
@@ -326,22 +424,23 @@ __global__ __launch_bounds__(256) void k_gather(const typename Vec4<T>::type* __
   if (p0 == p1) return;
   const int s = tile_sys[find_sys(tile_prefix, nsys, gtile)];
   const SysDesc& sd = sys[s];
-  const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S, deg = sd.deg;
-  const double* __restrict__ coef = sd.coef;
+  const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S;
   const T* __restrict__ grid = grid_override ? grid_override : static_cast<const T*>(sd.grid_b);
   const double inv_h = sd.inv_h, self_coef = sd.self_coef;
-  const int S3 = S * S * S;
   double* recs = reinterpret_cast<double*>(smem_raw);              // kSlotsPerBlock * REC
-  T* tb = reinterpret_cast<T*>(recs + kSlotsPerBlock * REC);
+  double* lcoef = recs + kSlotsPerBlock * REC;                     // P * CS
+  T* tb = reinterpret_cast<T*>(lcoef + P * CS);
   const int tile = gtile - sd.tile_base;
   const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
   const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
   const int half = (P + 1) / 2;
   const int Ox = T0x + 1 - half, Oy = T0y + 1 - half, Oz = T0z + 1 - half;
-  for (int i = threadIdx.x; i < S3; i += blockDim.x) {
-    const int ix = i % S, iy = (i / S) % S, iz = i / (S * S);
-    const int gx = wrap_index(Ox + ix, m), gy = wrap_index(Oy + iy, m), gz = wrap_index(Oz + iz, m);
-    tb[i] = grid[(static_cast<int64_t>(gz) * m + gy) * m + gx];
+  stage_coefficients<P, D>(sd.coef, sd.deg, lcoef);
+  {
+    T v[8];
+    walk_tile<8>(
+        S, m, Ox, Oy, Oz, [&](int k, int, int64_t gi) { v[k] = grid[gi]; },
+        [&](int k, int li_, int64_t) { tb[li_] = v[k]; });
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -350,27 +449,44 @@ __global__ __launch_bounds__(256) void k_gather(const typename Vec4<T>::type* __
   double* rec = recs + slot * REC;
   const int nt = p1 - p0;
   double esum = 0.0;
+  auto r_next = sorted[min(p0 + slot, p1 - 1)];
+  int c_next = cells[min(p0 + slot, p1 - 1)];
+  int i_next = perm[min(p0 + slot, p1 - 1)];
   for (int base = 0; base < nt; base += kSlotsPerBlock) {
     const int pi = p0 + base + slot;
     const bool active = pi < p1;
-    const auto r = sorted[active ? pi : p0];
-    const int cp = cells[active ? pi : p0];
+    const auto r = r_next;
+    const int cp = c_next;
+    const int idx = i_next;
+    r_next = sorted[min(pi + kSlotsPerBlock, p1 - 1)];
+    c_next = cells[min(pi + kSlotsPerBlock, p1 - 1)];
+    i_next = perm[min(pi + kSlotsPerBlock, p1 - 1)];
     int o[3];
     double g[3];
-    g[0] = static_cast<double>(centred_offset<T, P>(r.x, cp % m, T0x, o[0]));
-    g[1] = static_cast<double>(centred_offset<T, P>(r.y, (cp / m) % m, T0y, o[1]));
-    g[2] = static_cast<double>(centred_offset<T, P>(r.z, cp / (m * m), T0z, o[2]));
-    for (int c = li; c < 3 * P; c += kLanesPerParticle) {
-      const int d = c / P, j = c - d * P;
-      const double* cj = coef + j * (deg + 1);
-      const double gd = d == 0 ? g[0] : (d == 1 ? g[1] : g[2]);
-      double v = cj[deg], dv = 0.0;
-      for (int k = deg - 1; k >= 0; --k) {
-        dv = fma(dv, gd, v);
-        v = fma(v, gd, cj[k]);
+    g[0] = static_cast<double>(centred_offset<T, P>(r.x, cell_x(cp), T0x, o[0]));
+    g[1] = static_cast<double>(centred_offset<T, P>(r.y, cell_y(cp), T0y, o[1]));
+    g[2] = static_cast<double>(centred_offset<T, P>(r.z, cell_z(cp), T0z, o[2]));
+#pragma unroll
+    for (int j = li; j < P; j += kLanesPerParticle) {
+      double c[D + 1];
+#pragma unroll
+      for (int k = 0; k <= D; ++k) c[k] = lcoef[j * CS + k];
+      double v0 = c[D], v1 = c[D], v2 = c[D], d0 = 0.0, d1 = 0.0, d2 = 0.0;
+#pragma unroll
+      for (int k = D - 1; k >= 0; --k) {
+        d0 = fma(d0, g[0], v0);
+        d1 = fma(d1, g[1], v1);
+        d2 = fma(d2, g[2], v2);
+        v0 = fma(v0, g[0], c[k]);
+        v1 = fma(v1, g[1], c[k]);
+        v2 = fma(v2, g[2], c[k]);
       }
-      rec[c] = v;
-      rec[3 * P + c] = dv;
+      rec[j] = v0;
+      rec[P + j] = v1;
+      rec[2 * P + j] = v2;
+      rec[3 * P + j] = d0;
+      rec[4 * P + j] = d1;
+      rec[5 * P + j] = d2;
     }
     wave_lds_sync();
     double ph = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
@@ -381,16 +497,25 @@ __global__ __launch_bounds__(256) void k_gather(const typename Vec4<T>::type* __
         wx[j] = rec[j];
         dx[j] = rec[3 * P + j];
       }
+#pragma unroll 2
       for (int e = li; e < P * P; e += kLanesPerParticle) {
         const int jz = e / P, jy = e - jz * P;
         const T* row = tb + ((o[2] + jz) * S + (o[1] + jy)) * S + o[0];
-        double sx = 0.0, sdx = 0.0;
+        double sx0 = 0.0, sx1 = 0.0, sd0 = 0.0, sd1 = 0.0;
 #pragma unroll
-        for (int jx = 0; jx < P; ++jx) {
-          const double b = static_cast<double>(row[jx]);
-          sx = fma(b, wx[jx], sx);
-          sdx = fma(b, dx[jx], sdx);
+        for (int jx = 0; jx + 1 < P; jx += 2) {
+          const double b0 = static_cast<double>(row[jx]), b1 = static_cast<double>(row[jx + 1]);
+          sx0 = fma(b0, wx[jx], sx0);
+          sd0 = fma(b0, dx[jx], sd0);
+          sx1 = fma(b1, wx[jx + 1], sx1);
+          sd1 = fma(b1, dx[jx + 1], sd1);
         }
+        if constexpr (P % 2 == 1) {
+          const double b = static_cast<double>(row[P - 1]);
+          sx0 = fma(b, wx[P - 1], sx0);
+          sd0 = fma(b, dx[P - 1], sd0);
+        }
+        const double sx = sx0 + sx1, sdx = sd0 + sd1;
         const double wy = rec[P + jy], dy = rec[4 * P + jy], wz = rec[2 * P + jz], dz = rec[5 * P + jz];
         const double wyz = wy * wz;
         ph = fma(sx, wyz, ph);
@@ -407,7 +532,6 @@ __global__ __launch_bounds__(256) void k_gather(const typename Vec4<T>::type* __
       gz += __shfl_xor(gz, off, kLanesPerParticle);
     }
     if (active && li == 0) {
-      const int idx = perm[pi];
       const double qd = static_cast<double>(r.w);
       double phd = ph;
       if (add_self) phd -= self_coef * qd;
@@ -675,35 +799,35 @@ hipError_t bin_impl(const DevPlan& d, int64_t n, const void* pos, const void* q,
   return hipGetLastError();
 }
 
-template <class T, int P>
+template <class T, int P, int D>
 hipError_t spread_impl(const DevPlan& d, const PGroup& g, hipStream_t st) {
-  hipLaunchKernelGGL((k_spread<T, P>), dim3(g.tile_end - g.tile_begin), dim3(256), g.lds_spread, st,
+  hipLaunchKernelGGL((k_spread<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(256), g.lds_spread, st,
                      static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start, d.nsys, d.sys_dev,
                      d.tile_prefix, d.tile_sys, g.tile_begin);
   return hipGetLastError();
 }
 
-template <class T, int P>
+template <class T, int P, int D>
 hipError_t gather_impl(const DevPlan& d, const PGroup& g, const void* grid, void* phi, void* vec, int vec_mode,
                        bool add_self, double* energy, hipStream_t st) {
-  hipLaunchKernelGGL((k_gather<T, P>), dim3(g.tile_end - g.tile_begin), dim3(256), g.lds_gather, st,
+  hipLaunchKernelGGL((k_gather<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(256), g.lds_gather, st,
                      static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.perm, d.tile_start, d.nsys,
                      d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin, static_cast<const T*>(grid),
                      static_cast<T*>(phi), static_cast<T*>(vec), vec_mode, add_self ? 1 : 0, energy);
   return hipGetLastError();
 }
 
-// Raises the dynamic-LDS limit of the particle kernels of one P group where needed.
-template <class T, int P>
+// Raises the dynamic-LDS limit of the particle kernels of one group where needed.
+template <class T, int P, int D>
 hipError_t prepare_impl(const PGroup& g) {
   if (g.lds_spread > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<T, P>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<T, P, D>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
                                              static_cast<int>(g.lds_spread));
     if (e != hipSuccess) return e;
   }
   if (g.lds_gather > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<T, P>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<T, P, D>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
                                              static_cast<int>(g.lds_gather));
     if (e != hipSuccess) return e;
@@ -711,25 +835,16 @@ hipError_t prepare_impl(const PGroup& g) {
   return hipSuccess;
 }
 
-template <class T, int P>
-hipError_t prepare_dispatch(const PGroup& g) {
-  if (g.P == P) return prepare_impl<T, P>(g);
-  if constexpr (P < kPmax) return prepare_dispatch<T, P + 1>(g);
-  return hipErrorInvalidValue;
-}
-
-template <class T, int P>
-hipError_t spread_dispatch(const DevPlan& d, const PGroup& g, hipStream_t st) {
-  if (g.P == P) return spread_impl<T, P>(d, g, st);
-  if constexpr (P < kPmax) return spread_dispatch<T, P + 1>(d, g, st);
-  return hipErrorInvalidValue;
-}
-
-template <class T, int P>
-hipError_t gather_dispatch(const DevPlan& d, const PGroup& g, const void* grid, void* phi, void* vec, int vec_mode,
-                           bool add_self, double* energy, hipStream_t st) {
-  if (g.P == P) return gather_impl<T, P>(d, g, grid, phi, vec, vec_mode, add_self, energy, st);
-  if constexpr (P < kPmax) return gather_dispatch<T, P + 1>(d, g, grid, phi, vec, vec_mode, add_self, energy, st);
+// Calls f.template operator()<P, D>() for the group's (P, D); hipErrorInvalidValue if none.
+template <int P, class F>
+hipError_t with_group(const PGroup& g, F&& f) {
+  if (g.P == P) {
+    if (g.D == 11) return f.template operator()<P, 11>();
+    if (g.D == 17) return f.template operator()<P, 17>();
+    if (g.D == kMaxDeg) return f.template operator()<P, kMaxDeg>();
+    return hipErrorInvalidValue;
+  }
+  if constexpr (P < kPmax) return with_group<P + 1>(g, f);
   return hipErrorInvalidValue;
 }
 
@@ -763,7 +878,8 @@ hipError_t transform_impl(const DevPlan& d, const void* in_override, void* out_o
 
 hipError_t prepare_kernels(const DevPlan& d) {
   for (const PGroup& g : d.groups) {
-    const hipError_t e = d.prec == 0 ? prepare_dispatch<float, kPmin>(g) : prepare_dispatch<double, kPmin>(g);
+    const hipError_t e = d.prec == 0 ? with_group<kPmin>(g, [&]<int P, int D>() { return prepare_impl<float, P, D>(g); })
+                                     : with_group<kPmin>(g, [&]<int P, int D>() { return prepare_impl<double, P, D>(g); });
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -779,7 +895,8 @@ hipError_t launch_spread(const DevPlan& d, hipStream_t st) {
   hipError_t e = hipSuccess;
   stage_begin(d, kStageSpread, st);
   for (const PGroup& g : d.groups) {
-    e = d.prec == 0 ? spread_dispatch<float, kPmin>(d, g, st) : spread_dispatch<double, kPmin>(d, g, st);
+    e = d.prec == 0 ? with_group<kPmin>(g, [&]<int P, int D>() { return spread_impl<float, P, D>(d, g, st); })
+                    : with_group<kPmin>(g, [&]<int P, int D>() { return spread_impl<double, P, D>(d, g, st); });
     if (e != hipSuccess) break;
   }
   stage_end(d, kStageSpread, st);
@@ -807,9 +924,15 @@ hipError_t launch_gather(const DevPlan& d, const void* grid_override, void* phi,
   hipError_t e = hipSuccess;
   stage_begin(d, kStageGather, st);
   for (const PGroup& g : d.groups) {
-    e = d.prec == 0
-            ? gather_dispatch<float, kPmin>(d, g, grid_override, phi, vec, vec_mode, add_self, energy, st)
-            : gather_dispatch<double, kPmin>(d, g, grid_override, phi, vec, vec_mode, add_self, energy, st);
+    e = d.prec == 0 ? with_group<kPmin>(g,
+                                        [&]<int P, int D>() {
+                                          return gather_impl<float, P, D>(d, g, grid_override, phi, vec, vec_mode,
+                                                                          add_self, energy, st);
+                                        })
+                    : with_group<kPmin>(g, [&]<int P, int D>() {
+                        return gather_impl<double, P, D>(d, g, grid_override, phi, vec, vec_mode, add_self, energy,
+                                                         st);
+                      });
     if (e != hipSuccess) break;
   }
   stage_end(d, kStageGather, st);

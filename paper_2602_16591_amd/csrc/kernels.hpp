@@ -65,10 +65,19 @@ struct SysDesc {
   FftPlan fh, ff;             // radix plans for lengths m/2 and m
 };
 
-// Systems sharing one window support P: their tiles form the contiguous global range
-// [tile_begin, tile_end), covered by one launch of each particle kernel (templated on P).
+// Horner degree buckets of the particle kernels: a window polynomial of degree deg is
+// evaluated as one of degree D = degree_bucket(deg) >= deg whose extra leading coefficients are
+// zero (exact: the first Horner steps then produce zeros). Coefficient rows are staged in LDS
+// with an odd stride in doubles, so the 16 lanes of a particle read 16 rows without conflicts.
+inline int degree_bucket(int deg) { return deg <= 11 ? 11 : (deg <= 17 ? 17 : 28); }
+constexpr int coef_stride(int D) { return (D + 1) % 2 ? D + 1 : D + 2; }
+constexpr int kMaxDeg = 28;
+
+// Systems sharing one window support P and degree bucket D: their tiles form the contiguous
+// global range [tile_begin, tile_end), covered by one launch of each particle kernel
+// (templated on P and D).
 struct PGroup {
-  int P = 0;
+  int P = 0, D = 0;
   int tile_begin = 0, tile_end = 0;
   size_t lds_spread = 0, lds_gather = 0;  // maxima over the group's systems
 };
@@ -78,9 +87,9 @@ struct DevPlan {
   int nsys = 0;
   int64_t n_max = 0;          // packed particles accepted (batch: exactly this many)
   std::vector<SysDesc> sys;   // host copies of the descriptors
-  std::vector<PGroup> groups; // by increasing P
+  std::vector<PGroup> groups; // by increasing (P, D)
   SysDesc* sys_dev = nullptr;
-  int* tile_prefix = nullptr;      // nsys + 1: tile ranges in global tile order (grouped by P)
+  int* tile_prefix = nullptr;      // nsys + 1: tile ranges in global tile order (grouped by P, D)
   int* tile_sys = nullptr;         // nsys: system owning the k-th tile range
   int* xblk_prefix = nullptr;      // nsys + 1, in system order
   int* cblk_prefix = nullptr;      // nsys + 1, in system order
