@@ -57,6 +57,37 @@ def stage_work(stage: str, n: int, m: int, P: int, deg: int, elem: int):
     raise KeyError(stage)
 
 
+STAGE_KERNEL = {"spread": "k_spread", "gather": "k_gather", "fft_x": "k_fft_x_r2c", "fft_y": "k_fft_cols",
+                "fft_z_scale": "k_fft_cols", "ifft_y": "k_fft_cols", "ifft_x": "k_fft_x_c2r", "bin": "k_bin_count"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_water_box_n30000.md")
+
+
+def kernel_source_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2602_16591_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage: str, prec_ctype: str):
+    """HBM bytes per launch of the stage's kernel from the committed counter summary (FETCH_SIZE
+    and WRITE_SIZE runs, calibrated against a plain copy), or None when the summary is missing
+    or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            text = f.read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("kernel_source_sha256") != kernel_source_sha256():
+        return None
+    prefix = f"{STAGE_KERNEL[stage]}<{prec_ctype}"
+    hits = [v for k, v in blob.get("bytes_per_launch", {}).items() if k.startswith(prefix)]
+    return hits[0] if len(hits) == 1 else None
+
+
 def cpu_baseline(x, q, L, eps, m):
     """The float64 oracle of the same computation (Alg. 2 in NumPy, oracle/fast.py) on the full
     system, single-threaded, timed on this host."""
@@ -231,6 +262,7 @@ def main():
         achieved = work / secs / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
+    roof["traffic"] = measured_traffic(r["dom"], "float")
     roof.update({"kernel": r["dom"], "avg_launch_us": r["dom_ms"] * 1e3, "work_per_launch": work})
     r64 = results["fp64"]
     phi_diff = float(np.linalg.norm(r["phi"] - r64["phi"]) / np.linalg.norm(r64["phi"]))

@@ -297,11 +297,20 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     if (ptr) plan->allocs.push_back(ptr);
     return ptr;
   };
+  // sub-buckets per tile: at least 8 particles each on average, at most 16 per tile and
+  // 32768 counters in all (the scan runs in one workgroup)
+  {
+    const double per_tile = static_cast<double>(d.n_max) / std::max(d.total_tiles, 1);
+    while (d.sub_log2 < 4 && 8.0 * (1 << d.sub_log2) <= per_tile &&
+           (static_cast<int64_t>(d.total_tiles) << (d.sub_log2 + 1)) <= 32768)
+      ++d.sub_log2;
+  }
+  const int64_t nbuckets = static_cast<int64_t>(d.total_tiles) << d.sub_log2;
   const size_t nm = static_cast<size_t>(std::max<int64_t>(d.n_max, 1));
   unsigned char* work_dev = static_cast<unsigned char*>(alloc(work.size));
   unsigned char* tab_dev = static_cast<unsigned char*>(alloc(tabs.size));
-  d.tile_count = static_cast<int*>(alloc(sizeof(int) * d.total_tiles));
-  d.tile_start = static_cast<int*>(alloc(sizeof(int) * (d.total_tiles + 1)));
+  d.tile_count = static_cast<int*>(alloc(sizeof(int) * nbuckets));
+  d.tile_start = static_cast<int*>(alloc(sizeof(int) * (nbuckets + 1)));
   d.tile_of = static_cast<int*>(alloc(sizeof(int) * nm));
   d.rank = static_cast<int*>(alloc(sizeof(int) * nm));
   d.perm = static_cast<int*>(alloc(sizeof(int) * nm));
@@ -357,7 +366,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   // grid_a must start (and is kept) all-zero; the rest of the work arena needs no value.
   bool ok = hipMemcpy(tab_dev, img.data(), tabs.size, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemset(work_dev, 0, work.size) == hipSuccess &&
-            hipMemset(d.tile_count, 0, sizeof(int) * d.total_tiles) == hipSuccess &&
+            hipMemset(d.tile_count, 0, sizeof(int) * nbuckets) == hipSuccess &&
             hipMemcpy(d.sys_dev, d.sys.data(), sizeof(pswfe::SysDesc) * nsys, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(d.tile_prefix, tile_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
                 hipSuccess &&

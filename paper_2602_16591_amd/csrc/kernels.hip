@@ -90,12 +90,12 @@ __device__ __forceinline__ int grid_coord(T x, T ih_hi, T ih_lo, T L, int m, T& 
 
 // ------------------------------------------------------------------------------------
 // Binning: particles are grouped by tiles of B^3 grid cells (counting sort over the global
-// tile index of the batch). Packed particle i belongs to the system whose range
+// tile index of the batch, each tile split into sub-buckets). Packed particle i belongs to the system whose range
 // [part_prefix[s], part_prefix[s+1]) holds it.
 // ------------------------------------------------------------------------------------
 template <class T>
 __global__ void k_bin_count(int64_t n, int nsys, const SysDesc* __restrict__ sys,
-                            const int64_t* __restrict__ part_prefix, const T* __restrict__ pos,
+                            const int64_t* __restrict__ part_prefix, const T* __restrict__ pos, int sub_log2,
                             int* __restrict__ tile_count, int* __restrict__ tile_of, int* __restrict__ rank,
                             double* __restrict__ energy) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -109,8 +109,9 @@ __global__ void k_bin_count(int64_t n, int nsys, const SysDesc* __restrict__ sys
   const int cy = grid_coord(pos[3 * i + 1], ih_hi, ih_lo, L, m, f);
   const int cz = grid_coord(pos[3 * i + 2], ih_hi, ih_lo, L, m, f);
   const int tile = sd.tile_base + ((cz / B) * Tn + cy / B) * Tn + cx / B;
-  tile_of[i] = tile;
-  rank[i] = atomicAdd(&tile_count[tile], 1);
+  const int bucket = (tile << sub_log2) | static_cast<int>(i & ((1 << sub_log2) - 1));
+  tile_of[i] = bucket;
+  rank[i] = atomicAdd(&tile_count[bucket], 1);
 }
 
 // Exclusive scan of the tile counts (one workgroup); resets the counts to zero.
@@ -301,7 +302,7 @@ constexpr int kLineChunk = 12;
 template <class T, int P, int D>
 __global__ __launch_bounds__(256) void k_spread(const typename Vec4<T>::type* __restrict__ sorted,
                                                 const int* __restrict__ cells, const int* __restrict__ tile_start,
-                                                int nsys, const SysDesc* __restrict__ sys,
+                                                int sub_log2, int nsys, const SysDesc* __restrict__ sys,
                                                 const int* __restrict__ tile_prefix, const int* __restrict__ tile_sys,
                                                 int tile_offset) {
   constexpr int REC = 3 * P;  // window values of one particle: x, y, z
@@ -309,7 +310,7 @@ __global__ __launch_bounds__(256) void k_spread(const typename Vec4<T>::type* __
   constexpr int NL = (P * P + kLanesPerParticle - 1) / kLanesPerParticle;  // lines per lane
   extern __shared__ unsigned char smem_raw[];
   const int gtile = tile_offset + static_cast<int>(blockIdx.x);
-  const int p0 = tile_start[gtile], p1 = tile_start[gtile + 1];
+  const int p0 = tile_start[gtile << sub_log2], p1 = tile_start[(gtile + 1) << sub_log2];
   if (p0 == p1) return;
   const SysDesc& sd = sys[tile_sys[find_sys(tile_prefix, nsys, gtile)]];
   const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S;
@@ -409,7 +410,7 @@ __global__ __launch_bounds__(256) void k_spread(const typename Vec4<T>::type* __
 template <class T, int P, int D>
 __global__ __launch_bounds__(256) void k_gather(const typename Vec4<T>::type* __restrict__ sorted,
                                                 const int* __restrict__ cells, const int* __restrict__ perm,
-                                                const int* __restrict__ tile_start, int nsys,
+                                                const int* __restrict__ tile_start, int sub_log2, int nsys,
                                                 const SysDesc* __restrict__ sys, const int* __restrict__ tile_prefix,
                                                 const int* __restrict__ tile_sys, int tile_offset,
                                                 const T* __restrict__ grid_override, T* __restrict__ phi,
@@ -420,7 +421,7 @@ __global__ __launch_bounds__(256) void k_gather(const typename Vec4<T>::type* __
   extern __shared__ unsigned char smem_raw[];
   __shared__ double s_red[4];
   const int gtile = tile_offset + static_cast<int>(blockIdx.x);
-  const int p0 = tile_start[gtile], p1 = tile_start[gtile + 1];
+  const int p0 = tile_start[gtile << sub_log2], p1 = tile_start[(gtile + 1) << sub_log2];
   if (p0 == p1) return;
   const int s = tile_sys[find_sys(tile_prefix, nsys, gtile)];
   const SysDesc& sd = sys[s];
@@ -789,8 +790,9 @@ hipError_t bin_impl(const DevPlan& d, int64_t n, const void* pos, const void* q,
   const int64_t nthreads = std::max<int64_t>(n, energy ? d.nsys : 0);
   if (nthreads > 0)
     hipLaunchKernelGGL(k_bin_count<T>, dim3(blocks_for(nthreads, 256)), dim3(256), 0, st, n, d.nsys, d.sys_dev,
-                       d.part_prefix, static_cast<const T*>(pos), d.tile_count, d.tile_of, d.rank, energy);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d.total_tiles, d.tile_count, d.tile_start);
+                       d.part_prefix, static_cast<const T*>(pos), d.sub_log2, d.tile_count, d.tile_of, d.rank,
+                       energy);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d.total_tiles << d.sub_log2, d.tile_count, d.tile_start);
   if (n > 0)
     hipLaunchKernelGGL(k_bin_scatter<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d.nsys, d.sys_dev,
                        d.part_prefix, static_cast<const T*>(pos), static_cast<const T*>(q), d.tile_of, d.rank,
@@ -802,8 +804,8 @@ hipError_t bin_impl(const DevPlan& d, int64_t n, const void* pos, const void* q,
 template <class T, int P, int D>
 hipError_t spread_impl(const DevPlan& d, const PGroup& g, hipStream_t st) {
   hipLaunchKernelGGL((k_spread<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(256), g.lds_spread, st,
-                     static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start, d.nsys, d.sys_dev,
-                     d.tile_prefix, d.tile_sys, g.tile_begin);
+                     static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start, d.sub_log2, d.nsys,
+                     d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin);
   return hipGetLastError();
 }
 
@@ -811,8 +813,8 @@ template <class T, int P, int D>
 hipError_t gather_impl(const DevPlan& d, const PGroup& g, const void* grid, void* phi, void* vec, int vec_mode,
                        bool add_self, double* energy, hipStream_t st) {
   hipLaunchKernelGGL((k_gather<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(256), g.lds_gather, st,
-                     static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.perm, d.tile_start, d.nsys,
-                     d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin, static_cast<const T*>(grid),
+                     static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.perm, d.tile_start, d.sub_log2,
+                     d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin, static_cast<const T*>(grid),
                      static_cast<T*>(phi), static_cast<T*>(vec), vec_mode, add_self ? 1 : 0, energy);
   return hipGetLastError();
 }

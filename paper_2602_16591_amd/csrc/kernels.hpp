@@ -96,10 +96,13 @@ struct DevPlan {
   int64_t* part_prefix = nullptr;  // nsys + 1 (batches; a single system takes n per call)
   int total_tiles = 0, total_xblk = 0, total_cblk = 0;
   size_t lds_x = 0, lds_c = 0;     // maxima over the systems
-  // binning, over all systems
-  int* tile_count = nullptr;   // total_tiles, kept all-zero between calls
-  int* tile_start = nullptr;   // total_tiles + 1
-  int* tile_of = nullptr;      // n_max
+  // binning, over all systems. Each tile's counter is split into 2^sub_log2 sub-buckets
+  // (particle index mod 2^sub_log2), so fewer atomics queue on one address; a tile's
+  // particles stay contiguous: tile t owns [tile_start[t << sub_log2], tile_start[(t+1) << sub_log2]).
+  int sub_log2 = 0;
+  int* tile_count = nullptr;   // total_tiles << sub_log2, kept all-zero between calls
+  int* tile_start = nullptr;   // (total_tiles << sub_log2) + 1
+  int* tile_of = nullptr;      // n_max: bucket of each particle
   int* rank = nullptr;         // n_max
   int* perm = nullptr;         // n_max: sorted slot -> packed input index
   int* cells = nullptr;        // n_max: packed cell cx + m (cy + m cz) of each sorted particle
