@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <utility>
 #include <vector>
@@ -63,20 +64,45 @@ pswfe::FftPlan make_fft_plan(int N) {
 // Tile edge B (cells) for binning, spreading and interpolation. The spreading tile holds
 // S^3 float64 accumulators (S = B + 2 ceil(P/2) - 1), at most 150 KiB; the interpolation tile
 // S^3 values of the plan precision plus the window records of 16 particles, at most 156 KiB.
-// Both also hold the P coefficient rows of the window polynomials (coef_stride(D) doubles each).
+// Both also hold the P coefficient rows of the window polynomials (coef_stride(D) doubles each)
+// and one window record per particle slot (16 lanes each).
 size_t coef_lds_bytes(int P, int D) { return sizeof(double) * P * pswfe::coef_stride(D); }
-size_t spread_lds_bytes(int S, int P, int D) {
-  return sizeof(double) * (static_cast<size_t>(S) * S * S + 16 * 3 * P) + coef_lds_bytes(P, D);
+size_t spread_lds_bytes(int S, int P, int D, int threads) {
+  return sizeof(double) * (static_cast<size_t>(S) * S * S + (threads / 16) * 3 * P) + coef_lds_bytes(P, D);
 }
-size_t gather_lds_bytes(int S, int P, int D, int elem) {
-  return static_cast<size_t>(elem) * S * S * S + sizeof(double) * 16 * 6 * P + coef_lds_bytes(P, D);
+size_t gather_lds_bytes(int S, int P, int D, int elem, int threads) {
+  return static_cast<size_t>(elem) * S * S * S + sizeof(double) * (threads / 16) * 6 * P + coef_lds_bytes(P, D);
 }
 int lds_edge(int B, int P) { return B + 2 * ((P + 1) / 2) - 1; }
+constexpr size_t kLdsLimit = 160 * 1024;
 
 bool tile_fits(int B, int P, int elem) {
   const int S = lds_edge(B, P);
-  const int D = pswfe::kMaxDeg;  // whatever the degree, the tile fits
-  return spread_lds_bytes(S, P, D) <= 150 * 1024 && gather_lds_bytes(S, P, D, elem) <= 156 * 1024;
+  const int D = pswfe::kMaxDeg;  // whatever the degree, the tile fits with 256-thread workgroups
+  return spread_lds_bytes(S, P, D, 256) <= kLdsLimit && gather_lds_bytes(S, P, D, elem, 256) <= kLdsLimit;
+}
+
+// Workgroup size of a particle kernel: the most resident waves per compute unit (LDS and the
+// 16-wave budget of kernels near 128 VGPRs), larger workgroups on ties (more slots per tile).
+// PSWFE_PARTICLE_THREADS overrides it (if that fits).
+int particle_threads(int P, const std::function<size_t(int)>& lds_of) {
+  int best = 256, best_waves = 0;
+  const int tmax = pswfe::particle_max_threads_host(P);
+  for (int t = 256; t <= tmax; t *= 2) {
+    const size_t lds = lds_of(t);
+    if (lds > kLdsLimit) break;
+    const int blocks = static_cast<int>(kLdsLimit / std::max<size_t>(lds, 1));
+    const int waves = std::min(blocks * (t / 64), 16);
+    if (waves >= best_waves) {
+      best = t;
+      best_waves = waves;
+    }
+  }
+  if (const char* env = std::getenv("PSWFE_PARTICLE_THREADS")) {
+    const int t = std::atoi(env);
+    if ((t == 256 || t == 512 || t == 1024) && t <= tmax && lds_of(t) <= kLdsLimit) best = t;
+  }
+  return best;
 }
 
 // Single systems: B = 8 (measured best on gfx950 for 64^3 and 128^3 grids with P = 12-18),
@@ -183,6 +209,9 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   d.sys.resize(nsys);
   std::vector<int> xblk_prefix(nsys + 1, 0), cblk_prefix(nsys + 1, 0);
   std::vector<int64_t> part_prefix(nsys + 1, 0);
+  // complex values per FFT workgroup (measured on gfx950: 1024 on grids up to 96^3, 2048 above)
+  int fft_env = 0;
+  if (const char* env = std::getenv("PSWFE_FFT_ELEMS")) fft_env = std::max(64, std::min(4096, std::atoi(env)));
   Arena work, tabs;
   struct TabOff { size_t coef, tm, wk, twhp, twhm, twfp, twfm; };
   struct WorkOff { size_t a, b, spec; };
@@ -233,10 +262,13 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
       free_plan(plan);
       return PSWFE_E_GRID;
     }
-    int rpb = std::max(1, std::min(64, 2048 / nx1));
-    while (rpb > 1 && 2 * static_cast<size_t>(rpb) * nx1 * celem > 64 * 1024) --rpb;
-    int cmax = std::max(1, std::min(64, 2048 / (m + 1)));
-    while (cmax > 1 && 2 * static_cast<size_t>(cmax) * (m + 1) * celem > 64 * 1024) --cmax;
+    // FFT batching: about fft_elems complex values per workgroup, at most 64 KiB of LDS with
+    // the twiddle tables.
+    const int fft_elems = fft_env > 0 ? fft_env : (m <= 96 ? 1024 : 2048);
+    int rpb = std::max(1, std::min(64, fft_elems / nx1));
+    while (rpb > 1 && (2 * static_cast<size_t>(rpb) * nx1 + 2 * N + 1) * celem > 64 * 1024) --rpb;
+    int cmax = std::max(1, std::min(64, fft_elems / (m + 1)));
+    while (cmax > 1 && (2 * static_cast<size_t>(cmax) * (m + 1) + 2 * m) * celem > 64 * 1024) --cmax;
     const int nxb = (nx1 + cmax - 1) / cmax;
     sd.rows_per_block = rpb;
     sd.cols_per_block = (nx1 + nxb - 1) / nxb;
@@ -245,8 +277,9 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     sd.part_base = part_prefix[s];
     xblk_prefix[s + 1] = xblk_prefix[s] + (m * m + rpb - 1) / rpb;
     cblk_prefix[s + 1] = cblk_prefix[s] + ((nx1 + sd.cols_per_block - 1) / sd.cols_per_block) * m;
-    d.lds_x = std::max(d.lds_x, 2 * static_cast<size_t>(rpb) * nx1 * celem);
-    d.lds_c = std::max(d.lds_c, 2 * static_cast<size_t>(sd.cols_per_block) * (m + 1) * celem);
+    // data buffers plus the twiddle tables the kernels copy into LDS
+    d.lds_x = std::max(d.lds_x, (2 * static_cast<size_t>(rpb) * nx1 + 2 * N + 1) * celem);
+    d.lds_c = std::max(d.lds_c, (2 * static_cast<size_t>(sd.cols_per_block) * (m + 1) + 2 * m) * celem);
     const size_t m3 = static_cast<size_t>(m) * m * m;
     woff[s] = {work.take(sizeof(double) * m3), work.take(elem * m3),
                work.take(celem * static_cast<size_t>(m) * m * nx1)};
@@ -274,8 +307,14 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     }
     pswfe::PGroup& g = d.groups.back();
     g.tile_end = tile_prefix[k + 1];
-    g.lds_spread = std::max(g.lds_spread, spread_lds_bytes(sd.S, sd.P, D));
-    g.lds_gather = std::max(g.lds_gather, gather_lds_bytes(sd.S, sd.P, D, elem));
+    g.lds_spread = std::max<size_t>(g.lds_spread, lds_edge(sd.B, sd.P));  // largest S of the group, for now
+  }
+  for (pswfe::PGroup& g : d.groups) {
+    const int S = static_cast<int>(g.lds_spread), P = g.P, D = g.D;
+    g.spread_threads = particle_threads(P, [&](int t) { return spread_lds_bytes(S, P, D, t); });
+    g.gather_threads = particle_threads(P, [&](int t) { return gather_lds_bytes(S, P, D, elem, t); });
+    g.lds_spread = spread_lds_bytes(S, P, D, g.spread_threads);
+    g.lds_gather = gather_lds_bytes(S, P, D, elem, g.gather_threads);
   }
   d.total_tiles = tile_prefix[nsys];
   d.total_xblk = xblk_prefix[nsys];

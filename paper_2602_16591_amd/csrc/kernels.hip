@@ -212,23 +212,24 @@ __device__ __forceinline__ int fold_index(int a, int m) {
   return a;
 }
 
-// Walks the S^3 points of a tile's LDS block (x fastest) with a stride of one workgroup
-// (256 threads): load(k, lds_index, grid_index) for up to K points per thread, then use(...)
+// Walks the S^3 points of a tile's LDS block (x fastest) with a stride of one workgroup:
+// load(k, lds_index, grid_index) for up to K points per thread, then use(...)
 // for the same points, so K independent memory accesses are in flight before their results
 // are needed. The (x, y, z) offsets advance by the stride's digits instead of being divided
 // out of the flat index.
 template <int K, class Load, class Use>
 __device__ __forceinline__ void walk_tile(int S, int m, int Ox, int Oy, int Oz, Load&& load, Use&& use) {
   const int S2 = S * S, S3 = S2 * S;
-  const int sz = 256 / S2, sy = (256 - sz * S2) / S, sx = 256 - sz * S2 - sy * S;
+  const int nt = blockDim.x;
+  const int sz = nt / S2, sy = (nt - sz * S2) / S, sx = nt - sz * S2 - sy * S;
   const int t = threadIdx.x;
   int iz = t / S2, iy = (t - iz * S2) / S, ix = t - iz * S2 - iy * S;
-  for (int base = t; base < S3; base += 256 * K) {
+  for (int base = t; base < S3; base += nt * K) {
     int li[K];
     int64_t gi[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      li[k] = base + 256 * k;
+      li[k] = base + nt * k;
       gi[k] = (static_cast<int64_t>(fold_index(Oz + iz, m)) * m + fold_index(Oy + iy, m)) * m + fold_index(Ox + ix, m);
       ix += sx;
       if (ix >= S) {
@@ -268,7 +269,12 @@ __device__ __forceinline__ void walk_tile(int S, int m, int Ox, int Oy, int Oz, 
 // terms of both signs.
 // ------------------------------------------------------------------------------------
 constexpr int kLanesPerParticle = 16;
-constexpr int kSlotsPerBlock = 16;  // 4 waves x 4 particles
+
+// Workgroups of the particle kernels have 256, 512 or 1024 threads (4 particle slots per
+// wave); 1024 only where the kernel fits in 128 VGPRs (P <= 13), so that 16 waves can share
+// one compute unit's LDS tile.
+template <int P>
+constexpr int particle_max_threads() { return P <= 13 ? 1024 : 512; }
 
 // Per-wave ordering of LDS accesses between lanes (the record written by one lane is read by
 // other lanes of the same wave).
@@ -300,7 +306,7 @@ __device__ __forceinline__ void stage_coefficients(const double* __restrict__ co
 constexpr int kLineChunk = 12;
 
 template <class T, int P, int D>
-__global__ __launch_bounds__(256) void k_spread(const typename Vec4<T>::type* __restrict__ sorted,
+__global__ __launch_bounds__(particle_max_threads<P>()) void k_spread(const typename Vec4<T>::type* __restrict__ sorted,
                                                 const int* __restrict__ cells, const int* __restrict__ tile_start,
                                                 int sub_log2, int nsys, const SysDesc* __restrict__ sys,
                                                 const int* __restrict__ tile_prefix, const int* __restrict__ tile_sys,
@@ -317,8 +323,9 @@ __global__ __launch_bounds__(256) void k_spread(const typename Vec4<T>::type* __
   double* __restrict__ grid = sd.grid_a;
   double* acc = reinterpret_cast<double*>(smem_raw);
   const int S3 = S * S * S;
-  double* recs = acc + S3;                           // kSlotsPerBlock * REC
-  double* lcoef = recs + kSlotsPerBlock * REC;       // P * CS
+  const int nslots = blockDim.x / kLanesPerParticle;
+  double* recs = acc + S3;                           // nslots * REC
+  double* lcoef = recs + nslots * REC;               // P * CS
   const int tile = gtile - sd.tile_base;
   const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
   const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
@@ -326,27 +333,29 @@ __global__ __launch_bounds__(256) void k_spread(const typename Vec4<T>::type* __
   for (int i = threadIdx.x; i < S3; i += blockDim.x) acc[i] = 0.0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int slot = threadIdx.x >> 4;            // 0..15
+  const int slot = threadIdx.x >> 4;
   const int li = lane & (kLanesPerParticle - 1);
   double* rec = recs + slot * REC;
   const int nt = p1 - p0;
   // the record of the next round is loaded while this round's particle is spread
   auto r_next = sorted[min(p0 + slot, p1 - 1)];
   int c_next = cells[min(p0 + slot, p1 - 1)];
-  for (int base = 0; base < nt; base += kSlotsPerBlock) {
+  for (int base = 0; base < nt; base += nslots) {
     const int pi = p0 + base + slot;
     const bool active = pi < p1;
     const auto r = r_next;
     const int cp = c_next;
-    r_next = sorted[min(pi + kSlotsPerBlock, p1 - 1)];
-    c_next = cells[min(pi + kSlotsPerBlock, p1 - 1)];
+    r_next = sorted[min(pi + nslots, p1 - 1)];
+    c_next = cells[min(pi + nslots, p1 - 1)];
     int o[3];
     double g[3];
     g[0] = static_cast<double>(centred_offset<T, P>(r.x, cell_x(cp), T0x, o[0]));
     g[1] = static_cast<double>(centred_offset<T, P>(r.y, cell_y(cp), T0y, o[1]));
     g[2] = static_cast<double>(centred_offset<T, P>(r.z, cell_z(cp), T0z, o[2]));
 #pragma unroll
-    for (int j = li; j < P; j += kLanesPerParticle) {
+    for (int jj = 0; jj < (P + kLanesPerParticle - 1) / kLanesPerParticle; ++jj) {
+      const int j = li + kLanesPerParticle * jj;
+      if (j >= P) break;
       double c[D + 1];
 #pragma unroll
       for (int k = 0; k <= D; ++k) c[k] = lcoef[j * CS + k];
@@ -408,7 +417,7 @@ __global__ __launch_bounds__(256) void k_spread(const typename Vec4<T>::type* __
 // grid_override (single system) replaces the system's grid_b; energy holds one double per
 // system.
 template <class T, int P, int D>
-__global__ __launch_bounds__(256) void k_gather(const typename Vec4<T>::type* __restrict__ sorted,
+__global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const typename Vec4<T>::type* __restrict__ sorted,
                                                 const int* __restrict__ cells, const int* __restrict__ perm,
                                                 const int* __restrict__ tile_start, int sub_log2, int nsys,
                                                 const SysDesc* __restrict__ sys, const int* __restrict__ tile_prefix,
@@ -419,7 +428,7 @@ __global__ __launch_bounds__(256) void k_gather(const typename Vec4<T>::type* __
   constexpr int REC = 6 * P;  // values x, y, z then derivatives x, y, z (d/dg)
   constexpr int CS = coef_stride(D);
   extern __shared__ unsigned char smem_raw[];
-  __shared__ double s_red[4];
+  __shared__ double s_red[16];
   const int gtile = tile_offset + static_cast<int>(blockIdx.x);
   const int p0 = tile_start[gtile << sub_log2], p1 = tile_start[(gtile + 1) << sub_log2];
   if (p0 == p1) return;
@@ -428,8 +437,9 @@ __global__ __launch_bounds__(256) void k_gather(const typename Vec4<T>::type* __
   const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S;
   const T* __restrict__ grid = grid_override ? grid_override : static_cast<const T*>(sd.grid_b);
   const double inv_h = sd.inv_h, self_coef = sd.self_coef;
-  double* recs = reinterpret_cast<double*>(smem_raw);              // kSlotsPerBlock * REC
-  double* lcoef = recs + kSlotsPerBlock * REC;                     // P * CS
+  const int nslots = blockDim.x / kLanesPerParticle;
+  double* recs = reinterpret_cast<double*>(smem_raw);              // nslots * REC
+  double* lcoef = recs + nslots * REC;                             // P * CS
   T* tb = reinterpret_cast<T*>(lcoef + P * CS);
   const int tile = gtile - sd.tile_base;
   const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
@@ -453,22 +463,24 @@ __global__ __launch_bounds__(256) void k_gather(const typename Vec4<T>::type* __
   auto r_next = sorted[min(p0 + slot, p1 - 1)];
   int c_next = cells[min(p0 + slot, p1 - 1)];
   int i_next = perm[min(p0 + slot, p1 - 1)];
-  for (int base = 0; base < nt; base += kSlotsPerBlock) {
+  for (int base = 0; base < nt; base += nslots) {
     const int pi = p0 + base + slot;
     const bool active = pi < p1;
     const auto r = r_next;
     const int cp = c_next;
     const int idx = i_next;
-    r_next = sorted[min(pi + kSlotsPerBlock, p1 - 1)];
-    c_next = cells[min(pi + kSlotsPerBlock, p1 - 1)];
-    i_next = perm[min(pi + kSlotsPerBlock, p1 - 1)];
+    r_next = sorted[min(pi + nslots, p1 - 1)];
+    c_next = cells[min(pi + nslots, p1 - 1)];
+    i_next = perm[min(pi + nslots, p1 - 1)];
     int o[3];
     double g[3];
     g[0] = static_cast<double>(centred_offset<T, P>(r.x, cell_x(cp), T0x, o[0]));
     g[1] = static_cast<double>(centred_offset<T, P>(r.y, cell_y(cp), T0y, o[1]));
     g[2] = static_cast<double>(centred_offset<T, P>(r.z, cell_z(cp), T0z, o[2]));
 #pragma unroll
-    for (int j = li; j < P; j += kLanesPerParticle) {
+    for (int jj = 0; jj < (P + kLanesPerParticle - 1) / kLanesPerParticle; ++jj) {
+      const int j = li + kLanesPerParticle * jj;
+      if (j >= P) break;
       double c[D + 1];
 #pragma unroll
       for (int k = 0; k <= D; ++k) c[k] = lcoef[j * CS + k];
@@ -552,7 +564,11 @@ __global__ __launch_bounds__(256) void k_gather(const typename Vec4<T>::type* __
     for (int off = 32; off > 0; off >>= 1) esum += __shfl_xor(esum, off, 64);
     if (lane == 0) s_red[threadIdx.x >> 6] = esum;
     __syncthreads();
-    if (threadIdx.x == 0) unsafeAtomicAdd(energy + s, 0.5 * (s_red[0] + s_red[1] + s_red[2] + s_red[3]));
+    if (threadIdx.x == 0) {
+      double tot = 0.0;
+      for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) tot += s_red[w];
+      unsafeAtomicAdd(energy + s, 0.5 * tot);
+    }
   }
 }
 
@@ -636,6 +652,24 @@ __device__ C* fft_lds(C* A, C* Bf, int nseq, int ss, const FftPlan& pl, const C*
   return src;
 }
 
+// Copies count items from global memory into LDS with up to K loads per thread in flight:
+// v = load(i) for K indices, then store(i, v) for the same indices (the loads do not wait on
+// the stores, which go to another address space).
+template <int K, class Load, class Store>
+__device__ __forceinline__ void staged_copy(int count, Load&& load, Store&& store) {
+  using V = decltype(load(0));
+  const int nt = blockDim.x;
+  for (int base = threadIdx.x; base < count; base += nt * K) {
+    V v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (base + k * nt < count) v[k] = load(base + k * nt);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (base + k * nt < count) store(base + k * nt, v[k]);
+  }
+}
+
 // x-direction real-to-complex FFT (sign +) of the m^2 rows of m reals of each system, via an
 // m/2-point complex FFT of (a_2j + i a_2j+1); writes X_k, k = 0..m/2, to the system's spectrum.
 // The input is the float64 grid_a (zeroed after it is read when zero_input is set) or, for a
@@ -652,20 +686,28 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(int nsys, const SysDesc* __re
   const C* __restrict__ tw_full = static_cast<const C*>(sd.twfp);
   C* A = reinterpret_cast<C*>(smem_raw);
   C* Bf = A + rpb * N;
+  C* tw_h = Bf + rpb * N;          // N twiddles of the half-length FFT, then N + 1 of length m
+  C* tw_f = tw_h + N;
   const int row0 = (static_cast<int>(blockIdx.x) - sd.xblk_base) * rpb;
   const int nr = min(rpb, nrows - row0);
+  for (int e = threadIdx.x; e < 2 * N + 1; e += blockDim.x) {
+    if (e < N)
+      tw_h[e] = tw_half[e];
+    else
+      tw_f[e - N] = tw_full[e - N];
+  }
+  using CI = typename Cplx<TI>::type;  // a pair (a_2j, a_2j+1) of the input row, one vector load
   const TI* grid = in_override ? in_override : reinterpret_cast<const TI*>(sd.grid_a);
-  const TI* src = grid + static_cast<int64_t>(row0) * m;
-  TI* zsrc = zero_input ? const_cast<TI*>(src) : nullptr;
-  for (int e = threadIdx.x; e < nr * N; e += blockDim.x) {
-    A[e] = C{static_cast<T>(src[2 * e]), static_cast<T>(src[2 * e + 1])};
-    if (zsrc) {
-      zsrc[2 * e] = TI(0);
-      zsrc[2 * e + 1] = TI(0);
-    }
+  const CI* src = reinterpret_cast<const CI*>(grid + static_cast<int64_t>(row0) * m);
+  staged_copy<8>(
+      nr * N, [&](int e) { return src[e]; },
+      [&](int e, CI v) { A[e] = C{static_cast<T>(v.x), static_cast<T>(v.y)}; });
+  if (zero_input) {
+    CI* zsrc = const_cast<CI*>(src);
+    for (int e = threadIdx.x; e < nr * N; e += blockDim.x) zsrc[e] = CI{TI(0), TI(0)};
   }
   __syncthreads();
-  const C* Z = fft_lds(A, Bf, nr, N, sd.fh, tw_half);
+  const C* Z = fft_lds(A, Bf, nr, N, sd.fh, tw_h);
   C* out = static_cast<C*>(sd.spec) + static_cast<int64_t>(row0) * (N + 1);
   for (int e = threadIdx.x; e < nr * (N + 1); e += blockDim.x) {
     const int r = e / (N + 1), k = e - r * (N + 1);
@@ -674,7 +716,7 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(int nsys, const SysDesc* __re
     const C ev = C{T(0.5) * (zk.x + zn.x), T(0.5) * (zk.y + zn.y)};
     const C dd = csub(zk, zn);
     const C od = C{T(0.5) * dd.y, T(-0.5) * dd.x};  // (zk - zn) / (2i)
-    const C w = tw_full[k];
+    const C w = tw_f[k];
     out[e] = cadd(ev, cmul(w, od));
   }
 }
@@ -693,21 +735,30 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(int nsys, const SysDesc* __re
   const C* __restrict__ tw_full = static_cast<const C*>(sd.twfm);
   C* A = reinterpret_cast<C*>(smem_raw);   // rpb * (N + 1)
   C* Bf = A + rpb * (N + 1);               // rpb * N
+  C* tw_h = Bf + rpb * N;                  // N twiddles of the half-length FFT, then N of length m
+  C* tw_f = tw_h + N;
   const int row0 = (static_cast<int>(blockIdx.x) - sd.xblk_base) * rpb;
   const int nr = min(rpb, nrows - row0);
+  for (int e = threadIdx.x; e < 2 * N; e += blockDim.x) {
+    if (e < N)
+      tw_h[e] = tw_half[e];
+    else
+      tw_f[e - N] = tw_full[e - N];
+  }
   const C* in = static_cast<const C*>(sd.spec) + static_cast<int64_t>(row0) * (N + 1);
-  for (int e = threadIdx.x; e < nr * (N + 1); e += blockDim.x) A[e] = in[e];
+  staged_copy<8>(
+      nr * (N + 1), [&](int e) { return in[e]; }, [&](int e, C v) { A[e] = v; });
   __syncthreads();
   for (int e = threadIdx.x; e < nr * N; e += blockDim.x) {
     const int r = e / N, k = e - r * N;
     const C xk = A[r * (N + 1) + k];
     const C xn = cconj(A[r * (N + 1) + N - k]);
     const C s = cadd(xk, xn);
-    const C d = cmul(tw_full[k], csub(xk, xn));
+    const C d = cmul(tw_f[k], csub(xk, xn));
     Bf[e] = C{s.x - d.y, s.y + d.x};  // s + i d
   }
   __syncthreads();
-  const C* Z = fft_lds(Bf, A, nr, N, sd.fh, tw_half);
+  const C* Z = fft_lds(Bf, A, nr, N, sd.fh, tw_h);
   T* grid = out_override ? out_override : static_cast<T*>(sd.grid_b);
   C* dst = reinterpret_cast<C*>(grid + static_cast<int64_t>(row0) * m);
   for (int e = threadIdx.x; e < nr * N; e += blockDim.x) dst[e] = Z[e];
@@ -734,15 +785,33 @@ __global__ __launch_bounds__(256) void k_fft_cols(int nsys, const SysDesc* __res
   const int64_t plane = static_cast<int64_t>(m) * nx1;
   const int64_t ostride = mode == 1 ? int64_t(nx1) : plane;
   const int64_t estride = mode == 1 ? plane : int64_t(nx1);
-  const C* __restrict__ tw = static_cast<const C*>(mode == 2 ? sd.twfm : sd.twfp);
   const int ss = m + 1;  // padded sequence stride in LDS
   C* A = reinterpret_cast<C*>(smem_raw);
   C* Bf = A + cpb * ss;
-  C* base = static_cast<C*>(sd.spec) + outer * ostride + kx0;
-  for (int i = threadIdx.x; i < nc * m; i += blockDim.x) {
-    const int e = i / nc, c = i - e * nc;
-    A[c * ss + e] = base[e * estride + c];
+  C* tw_p = Bf + cpb * ss;  // twiddles of length m: sign + then sign -
+  C* tw_m = tw_p + m;
+  {
+    const C* __restrict__ gp = static_cast<const C*>(sd.twfp);
+    const C* __restrict__ gm = static_cast<const C*>(sd.twfm);
+    for (int e = threadIdx.x; e < 2 * m; e += blockDim.x) {
+      if (e < m)
+        tw_p[e] = gp[e];
+      else
+        tw_m[e - m] = gm[e - m];
+    }
   }
+  const C* tw = mode == 2 ? tw_m : tw_p;
+  C* base = static_cast<C*>(sd.spec) + outer * ostride + kx0;
+  staged_copy<8>(
+      nc * m,
+      [&](int i) {
+        const int e = i / nc, c = i - e * nc;
+        return base[e * estride + c];
+      },
+      [&](int i, C v) {
+        const int e = i / nc, c = i - e * nc;
+        A[c * ss + e] = v;
+      });
   __syncthreads();
   C* R1 = fft_lds(A, Bf, nc, ss, sd.ff, tw);
   if (mode == 1) {
@@ -761,7 +830,7 @@ __global__ __launch_bounds__(256) void k_fft_cols(int nsys, const SysDesc* __res
     }
     __syncthreads();
     C* other = (R1 == A) ? Bf : A;
-    R1 = fft_lds(R1, other, nc, ss, sd.ff, static_cast<const C*>(sd.twfm));
+    R1 = fft_lds(R1, other, nc, ss, sd.ff, tw_m);
   }
   for (int i = threadIdx.x; i < nc * m; i += blockDim.x) {
     const int e = i / nc, c = i - e * nc;
@@ -803,7 +872,7 @@ hipError_t bin_impl(const DevPlan& d, int64_t n, const void* pos, const void* q,
 
 template <class T, int P, int D>
 hipError_t spread_impl(const DevPlan& d, const PGroup& g, hipStream_t st) {
-  hipLaunchKernelGGL((k_spread<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(256), g.lds_spread, st,
+  hipLaunchKernelGGL((k_spread<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(g.spread_threads), g.lds_spread, st,
                      static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start, d.sub_log2, d.nsys,
                      d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin);
   return hipGetLastError();
@@ -812,7 +881,7 @@ hipError_t spread_impl(const DevPlan& d, const PGroup& g, hipStream_t st) {
 template <class T, int P, int D>
 hipError_t gather_impl(const DevPlan& d, const PGroup& g, const void* grid, void* phi, void* vec, int vec_mode,
                        bool add_self, double* energy, hipStream_t st) {
-  hipLaunchKernelGGL((k_gather<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(256), g.lds_gather, st,
+  hipLaunchKernelGGL((k_gather<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(g.gather_threads), g.lds_gather, st,
                      static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.perm, d.tile_start, d.sub_log2,
                      d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin, static_cast<const T*>(grid),
                      static_cast<T*>(phi), static_cast<T*>(vec), vec_mode, add_self ? 1 : 0, energy);

@@ -79,8 +79,12 @@ constexpr int kMaxDeg = 28;
 struct PGroup {
   int P = 0, D = 0;
   int tile_begin = 0, tile_end = 0;
+  int spread_threads = 256, gather_threads = 256;  // workgroup sizes (multiples of 64, <= 1024)
   size_t lds_spread = 0, lds_gather = 0;  // maxima over the group's systems
 };
+
+// Largest workgroup of the particle kernels for window support P (their launch bound).
+inline int particle_max_threads_host(int P) { return P <= 13 ? 1024 : 512; }
 
 struct DevPlan {
   int prec = 0;               // 0 float, 1 double
