@@ -7,6 +7,7 @@
 #include <cstring>
 #include <functional>
 #include <new>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -291,17 +292,25 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   // range covered by one launch of the particle kernels.
   std::vector<int> order(nsys), tile_prefix(nsys + 1, 0);
   for (int s = 0; s < nsys; ++s) order[s] = s;
-  auto key = [&](int s) { return std::make_pair(d.sys[s].P, pswfe::degree_bucket(d.sys[s].deg)); };
+  // spreading by columns where the tile edge allows it (PSWFE_SPREAD_COLUMNS=0 turns it off)
+  bool columns_ok = true;
+  if (const char* env = std::getenv("PSWFE_SPREAD_COLUMNS")) columns_ok = std::atoi(env) != 0;
+  auto cols = [&](int s) { return columns_ok && d.sys[s].B == pswfe::kColTileHost; };
+  auto key = [&](int s) {
+    return std::make_tuple(d.sys[s].P, pswfe::degree_bucket(d.sys[s].deg), cols(s) ? 1 : 0);
+  };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
   for (int k = 0; k < nsys; ++k) {
     pswfe::SysDesc& sd = d.sys[order[k]];
     const int D = pswfe::degree_bucket(sd.deg);
     sd.tile_base = tile_prefix[k];
     tile_prefix[k + 1] = tile_prefix[k] + sd.Tn * sd.Tn * sd.Tn;
-    if (d.groups.empty() || d.groups.back().P != sd.P || d.groups.back().D != D) {
+    if (d.groups.empty() || d.groups.back().P != sd.P || d.groups.back().D != D ||
+        d.groups.back().spread_columns != cols(order[k])) {
       pswfe::PGroup g;
       g.P = sd.P;
       g.D = D;
+      g.spread_columns = cols(order[k]);
       g.tile_begin = tile_prefix[k];
       d.groups.push_back(g);
     }
@@ -311,9 +320,10 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   }
   for (pswfe::PGroup& g : d.groups) {
     const int S = static_cast<int>(g.lds_spread), P = g.P, D = g.D;
-    g.spread_threads = particle_threads(P, [&](int t) { return spread_lds_bytes(S, P, D, t); });
+    g.spread_threads = g.spread_columns ? pswfe::col_threads_host(P)
+                                        : particle_threads(P, [&](int t) { return spread_lds_bytes(S, P, D, t); });
     g.gather_threads = particle_threads(P, [&](int t) { return gather_lds_bytes(S, P, D, elem, t); });
-    g.lds_spread = spread_lds_bytes(S, P, D, g.spread_threads);
+    g.lds_spread = g.spread_columns ? pswfe::col_lds_bytes(P, D) : spread_lds_bytes(S, P, D, g.spread_threads);
     g.lds_gather = gather_lds_bytes(S, P, D, elem, g.gather_threads);
   }
   d.total_tiles = tile_prefix[nsys];

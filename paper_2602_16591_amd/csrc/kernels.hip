@@ -411,6 +411,106 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_spread(const type
       });
 }
 
+// Spreading by columns, for tiles of edge kColTile (Alg. 2 step 1, same sums as k_spread).
+// Thread (ix, iz) of the S x S face of the tile's block owns the S points of its y-column in
+// registers. Particles are taken kColBatch at a time: their window values are written to LDS
+// as S-long arrays per dimension, zero outside the support (Horner runs once per value), and
+// every thread adds q w_x[ix] w_z[iz] w_y[iy] to its S points, skipping particles whose support
+// misses its column. The P^3 products of a particle become register FMAs instead of LDS
+// atomics (on gfx950 a float64 FMA costs far less issue time than a float64 LDS atomic);
+// the block then adds its S^3 points into the float64 grid with global atomics, lanes of
+// consecutive ix writing consecutive addresses.
+constexpr int kColTile = 8;
+constexpr int kColBatch = 32;
+template <int P>
+constexpr int col_edge() { return kColTile + 2 * ((P + 1) / 2) - 1; }
+template <int P>
+constexpr int col_threads() { return (col_edge<P>() * col_edge<P>() + 63) / 64 * 64; }
+
+template <class T, int P, int D>
+__global__ __launch_bounds__(col_threads<P>()) void k_spread_cols(
+    const typename Vec4<T>::type* __restrict__ sorted, const int* __restrict__ cells,
+    const int* __restrict__ tile_start, int sub_log2, int nsys, const SysDesc* __restrict__ sys,
+    const int* __restrict__ tile_prefix, const int* __restrict__ tile_sys, int tile_offset) {
+  constexpr int S = col_edge<P>();
+  constexpr int CS = coef_stride(D);
+  constexpr int RS = 3 * S;  // a particle's padded window values: x, y, z
+  extern __shared__ unsigned char smem_raw[];
+  const int gtile = tile_offset + static_cast<int>(blockIdx.x);
+  const int p0 = tile_start[gtile << sub_log2], p1 = tile_start[(gtile + 1) << sub_log2];
+  if (p0 == p1) return;
+  const SysDesc& sd = sys[tile_sys[find_sys(tile_prefix, nsys, gtile)]];
+  const int m = sd.m, Tn = sd.Tn;
+  double* __restrict__ grid = sd.grid_a;
+  double* lcoef = reinterpret_cast<double*>(smem_raw);  // P * CS
+  double* recs = lcoef + P * CS;                        // kColBatch * RS
+  double* pg = recs + kColBatch * RS;                   // kColBatch * 4: g_x, g_y, g_z, q
+  int* po = reinterpret_cast<int*>(pg + kColBatch * 4); // kColBatch * 4: o_x, o_y, o_z
+  const int tile = gtile - sd.tile_base;
+  const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
+  const int T0x = tx * kColTile, T0y = ty * kColTile, T0z = tz * kColTile;
+  stage_coefficients<P, D>(sd.coef, sd.deg, lcoef);
+  const int t = threadIdx.x;
+  const bool owner = t < S * S;
+  const int iz = t / S, ix = t - (t / S) * S;
+  double acc[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) acc[k] = 0.0;
+  for (int b0 = p0; b0 < p1; b0 += kColBatch) {
+    const int nb = min(kColBatch, p1 - b0);
+    if (t < nb) {
+      const auto r = sorted[b0 + t];
+      const int cp = cells[b0 + t];
+      int o0, o1, o2;
+      pg[4 * t + 0] = static_cast<double>(centred_offset<T, P>(r.x, cell_x(cp), T0x, o0));
+      pg[4 * t + 1] = static_cast<double>(centred_offset<T, P>(r.y, cell_y(cp), T0y, o1));
+      pg[4 * t + 2] = static_cast<double>(centred_offset<T, P>(r.z, cell_z(cp), T0z, o2));
+      pg[4 * t + 3] = static_cast<double>(r.w);
+      po[4 * t + 0] = o0;
+      po[4 * t + 1] = o1;
+      po[4 * t + 2] = o2;
+    }
+    __syncthreads();
+    for (int e = t; e < nb * RS; e += blockDim.x) {
+      const int k = e / RS, rr = e - k * RS, d = rr / S, i = rr - d * S;
+      const int j = i - po[4 * k + d];
+      double v = 0.0;
+      if (j >= 0 && j < P) {
+        const double g = pg[4 * k + d];
+        const double* c = lcoef + j * CS;
+        v = c[D];
+#pragma unroll
+        for (int kk = D - 1; kk >= 0; --kk) v = fma(v, g, c[kk]);
+      }
+      recs[e] = v;
+    }
+    __syncthreads();
+    if (owner) {
+      for (int k = 0; k < nb; ++k) {
+        const double* R = recs + k * RS;
+        const double tq = pg[4 * k + 3] * R[ix] * R[2 * S + iz];
+        if (tq != 0.0) {
+#pragma unroll
+          for (int iy = 0; iy < S; ++iy) acc[iy] = fma(tq, R[S + iy], acc[iy]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (owner) {
+    constexpr int half = (P + 1) / 2;
+    const int gx = fold_index(T0x + 1 - half + ix, m);
+    const int64_t gz = fold_index(T0z + 1 - half + iz, m);
+#pragma unroll
+    for (int iy = 0; iy < S; ++iy) {
+      if (acc[iy] != 0.0) {
+        const int gy = fold_index(T0y + 1 - half + iy, m);
+        atomic_add_global(grid + (gz * m + gy) * m + gx, acc[iy]);
+      }
+    }
+  }
+}
+
 // Interpolation (Alg. 2 step 5 and eq. force): phi = sum b w_x w_y w_z and its gradient as
 // nested sums: each lane runs the x-sums of its lines for the value and the x-derivative,
 // weights them with the y/z windows and derivatives, and the 16 lanes of a particle reduce.
@@ -872,9 +972,14 @@ hipError_t bin_impl(const DevPlan& d, int64_t n, const void* pos, const void* q,
 
 template <class T, int P, int D>
 hipError_t spread_impl(const DevPlan& d, const PGroup& g, hipStream_t st) {
-  hipLaunchKernelGGL((k_spread<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(g.spread_threads), g.lds_spread, st,
-                     static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start, d.sub_log2, d.nsys,
-                     d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin);
+  if (g.spread_columns)
+    hipLaunchKernelGGL((k_spread_cols<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(col_threads<P>()),
+                       g.lds_spread, st, static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start,
+                       d.sub_log2, d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin);
+  else
+    hipLaunchKernelGGL((k_spread<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(g.spread_threads), g.lds_spread,
+                       st, static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start, d.sub_log2,
+                       d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin);
   return hipGetLastError();
 }
 
@@ -892,9 +997,10 @@ hipError_t gather_impl(const DevPlan& d, const PGroup& g, const void* grid, void
 template <class T, int P, int D>
 hipError_t prepare_impl(const PGroup& g) {
   if (g.lds_spread > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spread<T, P, D>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             static_cast<int>(g.lds_spread));
+    const void* fn = g.spread_columns ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D>)
+                                      : reinterpret_cast<const void*>(&k_spread<T, P, D>);
+    const hipError_t e =
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(g.lds_spread));
     if (e != hipSuccess) return e;
   }
   if (g.lds_gather > 64 * 1024) {

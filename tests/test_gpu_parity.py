@@ -60,6 +60,29 @@ SMALL = [
 ]
 
 
+def covering_charge(x, q, o):
+    """Sum of |q_j| over the particles whose P^3 support holds each grid point ([z, y, x]).
+
+    Bounds the spreading error from the window fit: the fit error delta is absolute in window
+    value (at most 1), so a term q w_x w_y w_z is off by at most ~3 delta |q| wherever the
+    support reaches, however small the term itself is."""
+    idx, _, _ = fast.support(np.mod(x, o.L), o)
+    m, P = o.m, o.P
+    cov = np.zeros(m ** 3)
+    for jx in range(P):
+        for jy in range(P):
+            base = (idx[:, 0, jx] * m + idx[:, 1, jy]) * m
+            flat = (base[:, None] + idx[:, 2, :]).ravel()
+            cov += np.bincount(flat, weights=np.repeat(np.abs(q), P), minlength=m ** 3)
+    return cov.reshape(m, m, m).transpose(2, 1, 0)
+
+
+def spread_tol(x, q, o, eps, prec, A):
+    """Spreading tolerance: rounding relative to the sum of |terms| A, plus the window fit error
+    and the working-precision offset error (absolute in window value) times the covering charge."""
+    return 8 * U[prec] * A + (4 * fit_tol(eps, prec) + 8 * U[prec]) * covering_charge(x, q, o) + 1e-300
+
+
 def rounded(a, prec):
     """The values the device sees: inputs rounded to the working precision, as float64."""
     return np.asarray(a, dtype=np.float32 if prec == "fp32" else np.float64).astype(np.float64)
@@ -84,8 +107,45 @@ def test_spread_matches_oracle(case, prec):
     A = fast.spread(np.mod(x, L), np.abs(q), o).transpose(2, 1, 0)      # sum of |terms|
     # window values and sums are float64 on both paths; the float32 path rounds the grid values
     # and the fractional offsets (x/h - floor(x/h), kept to the working precision relative to 1)
-    tol = 4 * fit_tol(eps, prec) * A + 8 * U[prec] * A + 1e-300
-    assert np.all(np.abs(g - a) <= tol), float(np.max(np.abs(g - a) / (A + 1e-300)))
+    tol = spread_tol(x, q, o, eps, prec, A)
+    assert np.all(np.abs(g - a) <= tol), float(np.max(np.abs(g - a) / tol))
+
+
+SPREAD_KERNEL_CASES = [
+    # (name, generator, eps, params kwargs, tile): tile 8 can run either spreading kernel
+    ("uniform_m32_P11_tile8", lambda: W.uniform_pm1(700, seed=21), 1e-6, dict(m=32), 8),
+    ("paper_abs_m36_P14_tile8", lambda: W.paper_default(900, seed=22, L=1.4), 1e-6, dict(rc=0.22, tol_mode="abs"), 8),
+    ("clustered_m24_tile8", lambda: W.clustered(800, seed=23, L=0.9), 1e-6, dict(m=24), 8),
+    ("high_precision_m48_tile8", lambda: W.uniform_pm1(500, seed=24), 1e-10, dict(m=48), 8),
+    ("uniform_m30_tile6", lambda: W.uniform_pm1(600, seed=25, L=1.3), 1e-6, dict(m=30), 6),
+]
+
+
+@pytest.mark.parametrize("columns", ["1", "0"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", SPREAD_KERNEL_CASES, ids=[c[0] for c in SPREAD_KERNEL_CASES])
+def test_both_spreading_kernels_match_oracle(case, prec, columns, monkeypatch):
+    """Spreading by LDS atomics (any tile) and by register columns (tiles of edge 8): the grid
+    against the oracle's spreading, and the whole pipeline against Alg. 2 in float64."""
+    _, gen, eps, kw, tile = case
+    if prec == "fp32" and eps < 1e-6:
+        pytest.skip("fp32 path is for eps >= 1e-6")
+    monkeypatch.setenv("PSWFE_SPREAD_COLUMNS", columns)
+    x, q, L, kw = _sys(gen, eps, kw, prec)
+    c, o = both_params(eps, L, **kw)
+    plan = pw.Plan(c, prec, n_max=len(q), tile=tile)
+    assert plan.tile == tile
+    g = plan.spread(tdev(x, prec), tdev(q, prec)).cpu().numpy()
+    a = fast.spread(np.mod(x, L), q, o).transpose(2, 1, 0)
+    A = fast.spread(np.mod(x, L), np.abs(q), o).transpose(2, 1, 0)
+    tol = spread_tol(x, q, o, eps, prec, A)
+    assert np.all(np.abs(g - a) <= tol), float(np.max(np.abs(g - a) / tol))
+    phi, F, E = plan.compute(tdev(x, prec), tdev(q, prec))
+    rphi, rg = fast.fast_longrange(x, q, o)
+    far = rphi - direct.self_term(q, o.rc, o.cs)
+    tol_phi = (1e-11 if prec == "fp64" else 2e-6) + 10 * fit_tol(eps, prec)
+    assert np.linalg.norm(phi.cpu().numpy() - rphi) / np.linalg.norm(far) < tol_phi
+    assert rel_l2(F.cpu().numpy(), direct.forces(q, rg)) < (1e-10 if prec == "fp64" else 2e-5) + 100 * fit_tol(eps, prec)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
