@@ -99,9 +99,10 @@ pswfe_status pswfe_plan_create(const pswfe_params* p, int32_t prec, int64_t n_ma
 
 /* As pswfe_plan_create with an explicit tile edge (in grid cells) for binning, spreading and
  * interpolation: particles are processed per tile of tile^3 cells, each with an LDS copy of
- * the grid points its supports touch. tile = 0 picks the default (8, reduced to fit the LDS
- * limits and small grids); a tile that does not fit the LDS limits is reduced until it does.
- * Used by the autotuner of the Python layer. tile < 0 or tile > m -> PSWFE_E_ARG. */
+ * the grid points its supports touch (tiles of edge 8 spread by register columns, others by
+ * LDS atomics). tile = 0 picks the default (8, reduced to fit the LDS limits and small grids);
+ * a tile that does not fit the LDS limits is reduced until it does. Used by the autotuner of
+ * the Python layer. tile < 0 or tile > m -> PSWFE_E_ARG. */
 pswfe_status pswfe_plan_create_tiled(const pswfe_params* p, int32_t prec, int64_t n_max, int32_t tile,
                                      pswfe_plan** out);
 
@@ -138,8 +139,8 @@ pswfe_status pswfe_compute_grad(pswfe_plan* plan, int64_t n, const void* pos, co
  *   params   host array of nsys parameter sets (pswfe_choose_params per system)
  *   counts   host array of nsys particle counts (>= 0, sum < 2^31); fixed for the plan
  *   prec     pswfe_prec
- *   tiles    host array of nsys tile edges (as pswfe_plan_create_tiled; 0 = default: about 256
- *            particles per tile on average), or NULL for all defaults
+ *   tiles    host array of nsys tile edges (as pswfe_plan_create_tiled; 0 = default: 8, reduced
+ *            to fit the LDS limits), or NULL for all defaults
  *   out      host pointer receiving the plan; NULL on failure.
  * The particles of system s occupy the packed rows [offset_s, offset_s + counts[s]) of every
  * particle array, offset_s = counts[0] + ... + counts[s-1]. */

@@ -17,7 +17,7 @@ import os
 
 from . import BatchPlan, Plan, _prec
 
-DENSITY_TARGETS = (32, 64, 128, 256, 512, 1024, 4096)
+DENSITY_TARGETS = (None, 32, 64, 128, 256, 1024)  # None: tile edge 8 everywhere (spreading by columns)
 SINGLE_TILES = (4, 5, 6, 7, 8, 9, 10, 12)
 
 
@@ -69,9 +69,10 @@ def _key(kind, prec, params, counts):
 def autotune_batch(params, counts, pos, q, prec="fp32", targets=DENSITY_TARGETS, reps: int = 10, cache=None,
                    **compute_kw):
     """Picks per-system tile edges for a batch. Each candidate is a particles-per-tile target
-    turned into one edge per system (tile_for_density); the candidate with the fastest graph
-    replay wins. Returns (BatchPlan with the chosen tiles, tiles, report) where report lists
-    (target, tiles, ms) per candidate (empty when the cache answered)."""
+    turned into one edge per system (tile_for_density), or None for edge 8 everywhere (where
+    spreading runs by register columns); the candidate with the fastest graph replay wins.
+    Returns (BatchPlan with the chosen tiles, tiles, report) where report lists (target, tiles,
+    ms) per candidate (empty when the cache answered)."""
     params, counts = list(params), [int(c) for c in counts]
     table = _load(cache)
     key = _key("batch", prec, params, counts)
@@ -82,7 +83,7 @@ def autotune_batch(params, counts, pos, q, prec="fp32", targets=DENSITY_TARGETS,
     report, best = [], None
     seen = set()
     for t in targets:
-        tiles = [tile_for_density(p.m, c, t) for p, c in zip(params, counts)]
+        tiles = [min(8, p.m) if t is None else tile_for_density(p.m, c, t) for p, c in zip(params, counts)]
         if tuple(tiles) in seen:
             continue
         seen.add(tuple(tiles))

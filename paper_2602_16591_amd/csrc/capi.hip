@@ -106,11 +106,11 @@ int particle_threads(int P, const std::function<size_t(int)>& lds_of) {
   return best;
 }
 
-// Single systems: B = 8 (measured best on gfx950 for 64^3 and 128^3 grids with P = 12-18),
-// reduced to give at least 4 tiles per dimension on small grids. Batches: the smallest B with
-// about 256 particles per tile on average (many small systems fill the chip together, so
-// tiles are sized for work per tile rather than tile count). Both are then reduced until
-// the LDS limits hold.
+// Single systems: B = 8 (measured best on gfx950 for 64^3 and 128^3 grids with P = 12-18;
+// spreading then runs by register columns), reduced to give at least 4 tiles per dimension on
+// small grids. Batches: B = 8 (measured best on a 256-system ensemble of 16^3-50^3 grids;
+// many small systems fill the chip together). Both are then reduced until the LDS limits
+// hold.
 int choose_tile(int m, int P, int requested, int elem, int64_t n_batch) {
   int B = requested;
   if (B <= 0 && n_batch < 0) {
@@ -121,9 +121,7 @@ int choose_tile(int m, int P, int requested, int elem, int64_t n_batch) {
       B = 8;
       while (B > 2 && (m + B - 1) / B < 4) --B;
     } else {
-      const double cells_per_tile = 256.0 * m * m * m / std::max<double>(static_cast<double>(n_batch), 1.0);
-      B = static_cast<int>(std::ceil(std::cbrt(cells_per_tile)));
-      B = std::max(4, B);
+      B = 8;
     }
   }
   B = std::max(2, std::min(B, m));

@@ -456,11 +456,18 @@ __global__ __launch_bounds__(col_threads<P>()) void k_spread_cols(
   double acc[S];
 #pragma unroll
   for (int k = 0; k < S; ++k) acc[k] = 0.0;
+  // the records of the next batch are loaded while this batch is accumulated
+  auto r_next = sorted[min(p0 + t, p1 - 1)];
+  int c_next = cells[min(p0 + t, p1 - 1)];
   for (int b0 = p0; b0 < p1; b0 += kColBatch) {
     const int nb = min(kColBatch, p1 - b0);
+    const auto r = r_next;
+    const int cp = c_next;
+    if (t < kColBatch) {
+      r_next = sorted[min(b0 + kColBatch + t, p1 - 1)];
+      c_next = cells[min(b0 + kColBatch + t, p1 - 1)];
+    }
     if (t < nb) {
-      const auto r = sorted[b0 + t];
-      const int cp = cells[b0 + t];
       int o0, o1, o2;
       pg[4 * t + 0] = static_cast<double>(centred_offset<T, P>(r.x, cell_x(cp), T0x, o0));
       pg[4 * t + 1] = static_cast<double>(centred_offset<T, P>(r.y, cell_y(cp), T0y, o1));

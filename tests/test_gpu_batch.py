@@ -170,7 +170,7 @@ def test_autotuner_picks_a_measured_plan():
     counts = [len(s[1]) for s in systems]
     pos, q = pack([(s[0], s[1]) for s in systems], prec)
     cache = {}
-    plan, tiles, report = autotune_batch(params, counts, pos, q, prec, targets=(16, 256, 4096), reps=3, cache=cache)
+    plan, tiles, report = autotune_batch(params, counts, pos, q, prec, targets=(None, 16, 256), reps=3, cache=cache)
     assert report and plan.tiles == tiles and min(r[2] for r in report) == cache[next(iter(cache))]["ms"]
     ref = pw.BatchPlan(params, counts, prec)
     a, b = plan.compute(pos, q)[0], ref.compute(pos, q)[0]
