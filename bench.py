@@ -57,8 +57,9 @@ def stage_work(stage: str, n: int, m: int, P: int, deg: int, elem: int):
     raise KeyError(stage)
 
 
-STAGE_KERNEL = {"spread": "k_spread", "gather": "k_gather", "fft_x": "k_fft_x_r2c", "fft_y": "k_fft_cols",
-                "fft_z_scale": "k_fft_cols", "ifft_y": "k_fft_cols", "ifft_x": "k_fft_x_c2r", "bin": "k_bin_count"}
+STAGE_KERNEL = {"spread": ("k_spread", "k_spread_cols"), "gather": ("k_gather",), "fft_x": ("k_fft_x_r2c",),
+                "fft_y": ("k_fft_cols",), "fft_z_scale": ("k_fft_cols",), "ifft_y": ("k_fft_cols",),
+                "ifft_x": ("k_fft_x_c2r",), "bin": ("k_bin_count",)}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_water_box_n30000.md")
 
 
@@ -83,8 +84,8 @@ def measured_traffic(stage: str, prec_ctype: str):
         return None
     if blob.get("kernel_source_sha256") != kernel_source_sha256():
         return None
-    prefix = f"{STAGE_KERNEL[stage]}<{prec_ctype}"
-    hits = [v for k, v in blob.get("bytes_per_launch", {}).items() if k.startswith(prefix)]
+    prefixes = tuple(f"{name}<{prec_ctype}" for name in STAGE_KERNEL[stage])
+    hits = [v for k, v in blob.get("bytes_per_launch", {}).items() if k.startswith(prefixes)]
     return hits[0] if len(hits) == 1 else None
 
 
