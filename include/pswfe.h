@@ -52,6 +52,13 @@ typedef enum {
 
 typedef enum { PSWFE_FP32 = 0, PSWFE_FP64 = 1 } pswfe_prec;
 
+/* Flags of the *_ex compute entry points (bitwise or). */
+typedef enum {
+  PSWFE_VEC_GRAD = 1,  /* the vector output is grad phi (not the force -rho grad phi)          */
+  PSWFE_TOTAL = 2      /* add the real-space residual: phi, forces and energy of the full Ewald
+                          sum phi_far + phi_local + phi_self (Sec. 3.1, eq. Ewald split)       */
+} pswfe_flags;
+
 /* Method parameters (Alg. 3). The first block is what the kernels use; the *_alg fields are
  * the unrounded results of Alg. 3 steps 1-3, kept for reference. */
 typedef struct {
@@ -129,6 +136,31 @@ pswfe_status pswfe_compute(pswfe_plan* plan, int64_t n, const void* pos, const v
 pswfe_status pswfe_compute_grad(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi,
                                 void* grad, double* energy, void* stream);
 
+/* pswfe_compute / pswfe_compute_grad with flags (pswfe_flags). With PSWFE_TOTAL the outputs are
+ * the full Ewald potential, force and energy: the real-space residual
+ *   phi_local,i = sum'_j rho_j R(|x_i - x_j|),  R(r) = (1 - Phi(r)) / r for r < r_c, 0 beyond
+ * (Sec. 3.1.1, eq. R; minimum image, self pair excluded) is added to phi_far + phi_self, its
+ * force -rho_i grad phi_local,i to the force and 1/2 sum rho_i phi_local,i to the energy.
+ * R is evaluated from a float64 polynomial fit of Phi(r)/r in r^2 (relative error below 1e-15);
+ * pairs are found in cells of edge L / floor(L / r_c) >= r_c (every pair of the system when
+ * L < 3 r_c). PSWFE_TOTAL needs r_c < L/2 for every system (else PSWFE_E_ARG); unknown flag
+ * bits -> PSWFE_E_ARG. */
+pswfe_status pswfe_compute_ex(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi, void* vec,
+                              double* energy, int32_t flags, void* stream);
+
+/* The real-space residual alone (Sec. 3.1.1): phi_local (n), its force -rho grad phi_local (or,
+ * with PSWFE_VEC_GRAD, grad phi_local; n x 3) and energy 1/2 sum rho_i phi_local,i (one double
+ * per system), written to the device outputs (any may be NULL). Single-system plans take
+ * n <= n_max particles; batch plans exactly the packed total (else PSWFE_E_ARG). */
+pswfe_status pswfe_local(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi, void* vec,
+                         double* energy, int32_t flags, void* stream);
+
+/* Host view of the residual the kernels evaluate, for verification: R(r_i) and R'(r_i)/r_i for
+ * count radii (0 outside (0, r_c)); info[0..2] = polynomial degree, fit error (relative to
+ * Phi(r)/r at 0), K = 2 / (lambda_0 psi_0(0) r_c). Any output may be NULL. */
+pswfe_status pswfe_host_local(const pswfe_params* p, int64_t count, const double* r, double* R, double* dRr,
+                              double* info);
+
 /* Batches of independent systems (each its own box, parameters and particles; Alg. 2 applied
  * to each with its own parameters, as a single-system plan would). All systems share the
  * precision. Binning and each FFT pass run as one kernel launch over all systems; spreading
@@ -161,6 +193,10 @@ pswfe_status pswfe_batch_compute(pswfe_plan* plan, const void* pos, const void* 
  * pswfe_compute_grad). */
 pswfe_status pswfe_batch_compute_grad(pswfe_plan* plan, const void* pos, const void* q, void* phi, void* grad,
                                       double* energy, void* stream);
+
+/* pswfe_batch_compute with flags, as pswfe_compute_ex. */
+pswfe_status pswfe_batch_compute_ex(pswfe_plan* plan, const void* pos, const void* q, void* phi, void* vec,
+                                    double* energy, int32_t flags, void* stream);
 
 /* Number of systems of a plan (1 for single-system plans, 0 for NULL). */
 int32_t pswfe_plan_num_systems(const pswfe_plan* plan);
@@ -203,8 +239,8 @@ pswfe_status pswfe_host_tables(const pswfe_params* p, int32_t prec, double* tm, 
 /* Instrumentation (not for hot loops): records a pair of HIP events on the compute stream
  * around one pipeline stage of each following call on this plan, for up to max_calls calls.
  *   stage: 0 binning, 1 spreading, 2 x R2C FFT, 3 y FFT, 4 z FFT + scaling + inverse z FFT,
- *          5 inverse y FFT, 6 x C2R FFT, 7 interpolation, 8 the whole compute call; -1 turns
- *          timing off and frees the events.
+ *          5 inverse y FFT, 6 x C2R FFT, 7 interpolation, 8 the whole compute call,
+ *          9 the real-space residual; -1 turns timing off and frees the events.
  * pswfe_timing_enable synchronises the device and creates the events (host allocation).
  * pswfe_timing_read waits for the last recorded event and returns the summed elapsed time (ms)
  * and the number of timed calls since enable or the previous read, then resets the count. */

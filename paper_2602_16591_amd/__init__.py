@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libpswfe.so")
 OK, E_ARG, E_EPS_RANGE, E_GRID, E_ALLOC, E_HIP, E_CAPACITY, E_PREC = range(8)
 TOL_REL, TOL_ABS = 0, 1
 FP32, FP64 = 0, 1
+VEC_GRAD, TOTAL = 1, 2
 
 
 class PswfeError(RuntimeError):
@@ -59,6 +60,10 @@ SIGNATURES = {
     "pswfe_batch_compute": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pswfe_batch_compute_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pswfe_plan_num_systems": (ctypes.c_int32, [_vp]),
+    "pswfe_compute_ex": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "pswfe_batch_compute_ex": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "pswfe_local": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "pswfe_host_local": (ctypes.c_int, [ctypes.POINTER(CParams), _i64, _vp, _vp, _vp, _vp]),
     "pswfe_plan_system": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(CParams), ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
     "pswfe_host_pswf": (ctypes.c_int, [_d, _d, _vp, _vp, _vp, _vp]),
@@ -129,6 +134,17 @@ def host_tables(params: CParams, prec: int | str = FP32):
                 fit_err_deriv=info[2], self_coef=info[3])
 
 
+def host_local(params: CParams, r):
+    """The real-space residual the kernels evaluate, on the host: (R(r), R'(r)/r, info) for
+    radii r (float64 array); info = (degree, fit error, K)."""
+    import numpy as np
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    R, dRr, info = np.zeros_like(r), np.zeros_like(r), np.zeros(3)
+    _check(_lib().pswfe_host_local(ctypes.byref(params), r.size, r.ctypes.data, R.ctypes.data, dRr.ctypes.data,
+                                   info.ctypes.data), "pswfe_host_local")
+    return R, dRr, dict(deg=int(info[0]), fit_err=info[1], K=info[2])
+
+
 def _ptr(t, dtype, shape_tail, name):
     import torch
     if t is None:
@@ -193,7 +209,7 @@ class _PlanBase:
             pass
 
     STAGES = {"bin": 0, "spread": 1, "fft_x": 2, "fft_y": 3, "fft_z_scale": 4, "ifft_y": 5, "ifft_x": 6,
-              "gather": 7, "all": 8}
+              "gather": 7, "all": 8, "local": 9}
 
     def timing_enable(self, stage: str | int | None, max_calls: int = 4096):
         """Record HIP events around one pipeline stage of the following calls (None: off)."""
@@ -235,8 +251,9 @@ class Plan(_PlanBase):
             raise ValueError(f"n = {n} exceeds the plan's n_max = {self.n_max}")
         return n
 
-    def compute(self, pos, q, *, phi=True, force=True, energy=True, grad=False, stream=None):
-        """phi_far + phi_self, forces -q grad phi_far (or grad phi_far with grad=True), energy.
+    def compute(self, pos, q, *, phi=True, force=True, energy=True, grad=False, total=False, stream=None):
+        """phi_far + phi_self, forces -q grad phi_far (or grad phi_far with grad=True), energy;
+        with total=True the real-space residual is included (the full Ewald sum).
 
         Returns (phi, vec, energy) with None for outputs not requested; outputs are new tensors
         unless tensors are passed in place of True."""
@@ -245,10 +262,24 @@ class Plan(_PlanBase):
         phi_t = _out(phi, (n,), self.dtype, pos.device)
         vec_t = _out(force if not grad else grad, (n, 3), self.dtype, pos.device)
         e_t = _out(energy, (1,), torch.float64, pos.device)
-        fn = _lib().pswfe_compute_grad if grad else _lib().pswfe_compute
-        _check(fn(self._h, n, _ptr(pos, self.dtype, (3,), "pos"), _ptr(q, self.dtype, None, "q"),
-                  _ptr(phi_t, self.dtype, None, "phi"), _ptr(vec_t, self.dtype, (3,), "force"),
-                  _ptr(e_t, torch.float64, None, "energy"), _stream_ptr(stream)), "pswfe_compute")
+        flags = (VEC_GRAD if grad else 0) | (TOTAL if total else 0)
+        _check(_lib().pswfe_compute_ex(self._h, n, _ptr(pos, self.dtype, (3,), "pos"), _ptr(q, self.dtype, None, "q"),
+                                       _ptr(phi_t, self.dtype, None, "phi"), _ptr(vec_t, self.dtype, (3,), "force"),
+                                       _ptr(e_t, torch.float64, None, "energy"), flags, _stream_ptr(stream)),
+               "pswfe_compute_ex")
+        return phi_t, vec_t, e_t
+
+    def local(self, pos, q, *, phi=True, force=True, energy=True, grad=False, stream=None):
+        """The real-space residual alone: (phi_local, force or grad, energy)."""
+        import torch
+        n = self._n(pos)
+        phi_t = _out(phi, (n,), self.dtype, pos.device)
+        vec_t = _out(force if not grad else grad, (n, 3), self.dtype, pos.device)
+        e_t = _out(energy, (1,), torch.float64, pos.device)
+        _check(_lib().pswfe_local(self._h, n, _ptr(pos, self.dtype, (3,), "pos"), _ptr(q, self.dtype, None, "q"),
+                                  _ptr(phi_t, self.dtype, None, "phi"), _ptr(vec_t, self.dtype, (3,), "force"),
+                                  _ptr(e_t, torch.float64, None, "energy"), VEC_GRAD if grad else 0,
+                                  _stream_ptr(stream)), "pswfe_local")
         return phi_t, vec_t, e_t
 
     def spread(self, pos, q, grid=None, stream=None):
@@ -309,9 +340,10 @@ class BatchPlan(_PlanBase):
         self.n_total = sum(self.counts)
         self.P = self.params[0].P
 
-    def compute(self, pos, q, *, phi=True, force=True, energy=True, grad=False, stream=None):
+    def compute(self, pos, q, *, phi=True, force=True, energy=True, grad=False, total=False, stream=None):
         """Every system at once. pos (N, 3), q (N,) packed; returns (phi (N,), vec (N, 3),
-        energy (nsys,) float64) with None for outputs not requested (or the tensors passed)."""
+        energy (nsys,) float64) with None for outputs not requested (or the tensors passed);
+        total=True includes the real-space residual."""
         import torch
         if int(pos.shape[0]) != self.n_total or int(q.shape[0]) != self.n_total:
             raise ValueError(f"packed arrays must have {self.n_total} rows")
@@ -319,10 +351,12 @@ class BatchPlan(_PlanBase):
         phi_t = _out(phi, (n,), self.dtype, pos.device)
         vec_t = _out(force if not grad else grad, (n, 3), self.dtype, pos.device)
         e_t = _out(energy, (self.nsys,), torch.float64, pos.device)
-        fn = _lib().pswfe_batch_compute_grad if grad else _lib().pswfe_batch_compute
-        _check(fn(self._h, _ptr(pos, self.dtype, (3,), "pos"), _ptr(q, self.dtype, None, "q"),
-                  _ptr(phi_t, self.dtype, None, "phi"), _ptr(vec_t, self.dtype, (3,), "force"),
-                  _ptr(e_t, torch.float64, None, "energy"), _stream_ptr(stream)), "pswfe_batch_compute")
+        flags = (VEC_GRAD if grad else 0) | (TOTAL if total else 0)
+        _check(_lib().pswfe_batch_compute_ex(self._h, _ptr(pos, self.dtype, (3,), "pos"),
+                                             _ptr(q, self.dtype, None, "q"), _ptr(phi_t, self.dtype, None, "phi"),
+                                             _ptr(vec_t, self.dtype, (3,), "force"),
+                                             _ptr(e_t, torch.float64, None, "energy"), flags, _stream_ptr(stream)),
+               "pswfe_batch_compute_ex")
         return phi_t, vec_t, e_t
 
     def split(self, a):

@@ -19,14 +19,15 @@ from __future__ import annotations
 
 import torch
 
-from . import Plan
+from . import BatchPlan, Plan
 
 
 class _LongRange(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, pos, q, plan):
-        phi, gphi, E = plan.compute(pos, q, phi=True, grad=True, energy=True)
+    def forward(ctx, pos, q, plan, total=False):
+        phi, gphi, E = plan.compute(pos, q, phi=True, grad=True, energy=True, total=total)
         ctx.plan = plan
+        ctx.total = total
         ctx.save_for_backward(pos, q, phi, gphi)
         return E, phi
 
@@ -40,18 +41,58 @@ class _LongRange(torch.autograd.Function):
         dx = (ge * q)[:, None] * gphi
         if gphi_out is not None and bool(torch.any(gphi_out != 0)):
             g = gphi_out.to(dt).contiguous()
+            psi, gpsi, _ = plan.compute(pos, g, phi=True, grad=True, energy=False, total=ctx.total)
+            dq = dq + psi
+            dx = dx + g[:, None] * gphi + q[:, None] * gpsi
+        return (dx if ctx.needs_input_grad[0] else None, dq if ctx.needs_input_grad[1] else None, None, None)
+
+
+def energy_and_potential(pos: torch.Tensor, q: torch.Tensor, plan: Plan, total: bool = False):
+    """Long-range energy E (float64 tensor of shape (1,)) and potentials phi (plan precision),
+    differentiable with respect to positions and charges. total=True differentiates the full
+    Ewald sum (the real-space residual R is symmetric in the pair too, so the same adjoint
+    holds)."""
+    return _LongRange.apply(pos, q, plan, total)
+
+
+def energy(pos: torch.Tensor, q: torch.Tensor, plan: Plan, total: bool = False) -> torch.Tensor:
+    """Long-range (or, with total=True, full Ewald) energy, differentiable with respect to
+    positions and charges."""
+    return _LongRange.apply(pos, q, plan, total)[0]
+
+
+class _BatchLongRange(torch.autograd.Function):
+    """The same adjoint for a batch of independent systems: A is block diagonal (one block per
+    system), so the energy gradient of system s reaches only its own particles."""
+
+    @staticmethod
+    def forward(ctx, pos, q, plan):
+        phi, gphi, E = plan.compute(pos, q, phi=True, grad=True, energy=True)
+        ctx.plan = plan
+        ctx.save_for_backward(pos, q, phi, gphi)
+        return E, phi
+
+    @staticmethod
+    def backward(ctx, gE, gphi_out):
+        pos, q, phi, gphi = ctx.saved_tensors
+        plan = ctx.plan
+        dt = phi.dtype
+        counts = torch.as_tensor(plan.counts, device=phi.device)
+        if gE is None:
+            ge = torch.zeros_like(phi)
+        else:
+            ge = torch.repeat_interleave(gE.to(dt), counts, output_size=phi.shape[0])
+        dq = ge * phi
+        dx = (ge * q)[:, None] * gphi
+        if gphi_out is not None and bool(torch.any(gphi_out != 0)):
+            g = gphi_out.to(dt).contiguous()
             psi, gpsi, _ = plan.compute(pos, g, phi=True, grad=True, energy=False)
             dq = dq + psi
             dx = dx + g[:, None] * gphi + q[:, None] * gpsi
         return (dx if ctx.needs_input_grad[0] else None, dq if ctx.needs_input_grad[1] else None, None)
 
 
-def energy_and_potential(pos: torch.Tensor, q: torch.Tensor, plan: Plan):
-    """Long-range energy E (float64 tensor of shape (1,)) and potentials phi (plan precision),
-    differentiable with respect to positions and charges."""
-    return _LongRange.apply(pos, q, plan)
-
-
-def energy(pos: torch.Tensor, q: torch.Tensor, plan: Plan) -> torch.Tensor:
-    """Long-range energy, differentiable with respect to positions and charges."""
-    return _LongRange.apply(pos, q, plan)[0]
+def batch_energy_and_potential(pos: torch.Tensor, q: torch.Tensor, plan: BatchPlan):
+    """Energies of every system (float64, shape (nsys,)) and packed potentials, differentiable
+    with respect to the packed positions and charges."""
+    return _BatchLongRange.apply(pos, q, plan)

@@ -18,6 +18,8 @@
 struct pswfe_plan {
   std::vector<pswfe::Params> p;   // effective parameters of each system
   std::vector<pswfe::Tables> tab; // host tables of each system
+  std::vector<pswfe::LocalTable> ltab;  // real-space residual tables
+  bool local_ok = true;           // every system has r_c < L/2 (minimum image)
   std::vector<int64_t> count;     // batch plans: particles of each system
   bool batch = false;             // created by pswfe_batch_plan_create
   pswfe::DevPlan d;
@@ -201,6 +203,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   plan->batch = counts != nullptr;
   plan->p = ps;
   plan->tab.resize(nsys);
+  plan->ltab.resize(nsys);
   (void)hipGetDevice(&plan->device);
   pswfe::DevPlan& d = plan->d;
   d.prec = prec;
@@ -212,7 +215,8 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   int fft_env = 0;
   if (const char* env = std::getenv("PSWFE_FFT_ELEMS")) fft_env = std::max(64, std::min(4096, std::atoi(env)));
   Arena work, tabs;
-  struct TabOff { size_t coef, tm, wk, twhp, twhm, twfp, twfm; };
+  struct TabOff { size_t coef, tm, wk, twhp, twhm, twfp, twfm, lcoef; };
+  int cell_prefix = 0;
   struct WorkOff { size_t a, b, spec; };
   std::vector<TabOff> toff(nsys);
   std::vector<WorkOff> woff(nsys);
@@ -220,6 +224,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     const pswfe::Params& p = ps[s];
     pswfe::Tables& t = plan->tab[s];
     pswfe::build_tables(p, 0, fit_tolerance(p.eps, prec), &t);
+    pswfe::build_local_table(p, &plan->ltab[s]);
     pswfe::SysDesc& sd = d.sys[s];
     const int m = p.m, N = m / 2, nx1 = N + 1;
     if (counts) {
@@ -282,9 +287,18 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     const size_t m3 = static_cast<size_t>(m) * m * m;
     woff[s] = {work.take(sizeof(double) * m3), work.take(elem * m3),
                work.take(celem * static_cast<size_t>(m) * m * nx1)};
+    // real-space cells of edge L / nc >= r_c (at most 128 per dimension)
+    sd.rc = p.rc;
+    sd.lK = plan->ltab[s].K;
+    sd.ldeg = plan->ltab[s].deg;
+    sd.nc = std::max(1, std::min(128, static_cast<int>(std::floor(p.L / p.rc))));
+    if (sd.nc < 3) sd.nc = 1;
+    sd.cell_base = cell_prefix;
+    cell_prefix += sd.nc * sd.nc * sd.nc;
+    if (!(p.rc < 0.5 * p.L)) plan->local_ok = false;
     toff[s] = {tabs.take(sizeof(double) * t.coef.size()), tabs.take(elem * t.tm.size()),
                tabs.take(elem * t.w.size()), tabs.take(celem * N), tabs.take(celem * N), tabs.take(celem * m),
-               tabs.take(celem * m)};
+               tabs.take(celem * m), tabs.take(sizeof(double) * plan->ltab[s].coef.size())};
   }
   // Global tile order: systems grouped by P (stable), so each P's tiles are one contiguous
   // range covered by one launch of the particle kernels.
@@ -366,6 +380,13 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   d.sys_dev = static_cast<pswfe::SysDesc*>(alloc(sizeof(pswfe::SysDesc) * nsys));
   d.tile_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
   d.tile_sys = static_cast<int*>(alloc(sizeof(int) * nsys));
+  d.total_cells = cell_prefix;
+  d.cell_count = static_cast<int*>(alloc(sizeof(int) * d.total_cells));
+  d.cell_start = static_cast<int*>(alloc(sizeof(int) * (d.total_cells + 1)));
+  d.cell_of = static_cast<int*>(alloc(sizeof(int) * nm));
+  d.cell_rank = static_cast<int*>(alloc(sizeof(int) * nm));
+  d.lsorted = static_cast<double*>(alloc(sizeof(double) * 4 * nm));
+  d.lperm = static_cast<int*>(alloc(sizeof(int) * nm));
   d.xblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
   d.cblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
   d.part_prefix = static_cast<int64_t*>(alloc(sizeof(int64_t) * (nsys + 1)));
@@ -388,6 +409,8 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     sd.twhm = tab_dev + toff[s].twhm;
     sd.twfp = tab_dev + toff[s].twfp;
     sd.twfm = tab_dev + toff[s].twfm;
+    sd.lcoef = reinterpret_cast<const double*>(tab_dev + toff[s].lcoef);
+    put<double>(img, toff[s].lcoef, plan->ltab[s].coef);
     std::vector<double> twhp, twhm, twfp, twfm;
     pswfe::twiddles(N, +1, &twhp);
     pswfe::twiddles(N, -1, &twhm);
@@ -414,6 +437,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   bool ok = hipMemcpy(tab_dev, img.data(), tabs.size, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemset(work_dev, 0, work.size) == hipSuccess &&
             hipMemset(d.tile_count, 0, sizeof(int) * nbuckets) == hipSuccess &&
+            hipMemset(d.cell_count, 0, sizeof(int) * d.total_cells) == hipSuccess &&
             hipMemcpy(d.sys_dev, d.sys.data(), sizeof(pswfe::SysDesc) * nsys, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(d.tile_prefix, tile_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
                 hipSuccess &&
@@ -598,32 +622,40 @@ pswfe_status pswfe_timing_read(pswfe_plan* plan, double* total_ms, int64_t* call
 }
 
 namespace {
-// Bin, spread, transform and gather over every system of the plan; n particles in all.
+// Bin, spread, transform and gather over every system of the plan; n particles in all; with
+// `total`, the real-space residual is added.
 hipError_t run_pipeline(const pswfe::DevPlan& d, int64_t n, const void* pos, const void* q, void* phi, void* vec,
-                        int vec_mode, double* energy, hipStream_t s) {
+                        int vec_mode, double* energy, bool total, hipStream_t s) {
   pswfe::stage_begin(d, pswfe::kStageAll, s);
   hipError_t e = pswfe::launch_bin(d, n, pos, q, energy, s);
   if (e == hipSuccess) e = pswfe::launch_spread(d, s);
   if (e == hipSuccess) e = pswfe::launch_transform(d, nullptr, nullptr, s);
   if (e == hipSuccess && n > 0) e = pswfe::launch_gather(d, nullptr, phi, vec, vec_mode, true, energy, s);
+  if (e == hipSuccess && total) e = pswfe::launch_local(d, n, pos, q, phi, vec, vec_mode, energy, true, s);
   pswfe::stage_end(d, pswfe::kStageAll, s);
   return e;
 }
 
+constexpr int32_t kKnownFlags = PSWFE_VEC_GRAD | PSWFE_TOTAL;
+
 pswfe_status compute_impl(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi, void* vec,
-                          int vec_mode, double* energy, void* stream) {
-  if (!plan || plan->batch || n < 0) return PSWFE_E_ARG;
+                          int32_t flags, double* energy, void* stream) {
+  if (!plan || plan->batch || n < 0 || (flags & ~kKnownFlags)) return PSWFE_E_ARG;
+  if ((flags & PSWFE_TOTAL) && !plan->local_ok) return PSWFE_E_ARG;
   if (n > plan->d.n_max) return PSWFE_E_CAPACITY;
   if (n > 0 && (!pos || !q)) return PSWFE_E_ARG;
-  return from_hip(run_pipeline(plan->d, n, pos, q, phi, vec, vec_mode, energy, static_cast<hipStream_t>(stream)));
+  return from_hip(run_pipeline(plan->d, n, pos, q, phi, vec, (flags & PSWFE_VEC_GRAD) ? 1 : 0, energy,
+                               (flags & PSWFE_TOTAL) != 0, static_cast<hipStream_t>(stream)));
 }
 
-pswfe_status batch_impl(pswfe_plan* plan, const void* pos, const void* q, void* phi, void* vec, int vec_mode,
+pswfe_status batch_impl(pswfe_plan* plan, const void* pos, const void* q, void* phi, void* vec, int32_t flags,
                         double* energy, void* stream) {
-  if (!plan || !plan->batch) return PSWFE_E_ARG;
+  if (!plan || !plan->batch || (flags & ~kKnownFlags)) return PSWFE_E_ARG;
+  if ((flags & PSWFE_TOTAL) && !plan->local_ok) return PSWFE_E_ARG;
   const int64_t n = plan->d.n_max;
   if (n > 0 && (!pos || !q)) return PSWFE_E_ARG;
-  return from_hip(run_pipeline(plan->d, n, pos, q, phi, vec, vec_mode, energy, static_cast<hipStream_t>(stream)));
+  return from_hip(run_pipeline(plan->d, n, pos, q, phi, vec, (flags & PSWFE_VEC_GRAD) ? 1 : 0, energy,
+                               (flags & PSWFE_TOTAL) != 0, static_cast<hipStream_t>(stream)));
 }
 }  // namespace
 
@@ -634,7 +666,12 @@ pswfe_status pswfe_compute(pswfe_plan* plan, int64_t n, const void* pos, const v
 
 pswfe_status pswfe_compute_grad(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi, void* grad,
                                 double* energy, void* stream) {
-  return compute_impl(plan, n, pos, q, phi, grad, 1, energy, stream);
+  return compute_impl(plan, n, pos, q, phi, grad, PSWFE_VEC_GRAD, energy, stream);
+}
+
+pswfe_status pswfe_compute_ex(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi, void* vec,
+                              double* energy, int32_t flags, void* stream) {
+  return compute_impl(plan, n, pos, q, phi, vec, flags, energy, stream);
 }
 
 pswfe_status pswfe_batch_compute(pswfe_plan* plan, const void* pos, const void* q, void* phi, void* force,
@@ -644,7 +681,53 @@ pswfe_status pswfe_batch_compute(pswfe_plan* plan, const void* pos, const void* 
 
 pswfe_status pswfe_batch_compute_grad(pswfe_plan* plan, const void* pos, const void* q, void* phi, void* grad,
                                       double* energy, void* stream) {
-  return batch_impl(plan, pos, q, phi, grad, 1, energy, stream);
+  return batch_impl(plan, pos, q, phi, grad, PSWFE_VEC_GRAD, energy, stream);
+}
+
+pswfe_status pswfe_batch_compute_ex(pswfe_plan* plan, const void* pos, const void* q, void* phi, void* vec,
+                                    double* energy, int32_t flags, void* stream) {
+  return batch_impl(plan, pos, q, phi, vec, flags, energy, stream);
+}
+
+pswfe_status pswfe_local(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi, void* vec,
+                         double* energy, int32_t flags, void* stream) {
+  if (!plan || n < 0 || (flags & ~PSWFE_VEC_GRAD) || !plan->local_ok) return PSWFE_E_ARG;
+  if (plan->batch ? n != plan->d.n_max : n > plan->d.n_max) return plan->batch ? PSWFE_E_ARG : PSWFE_E_CAPACITY;
+  if (n > 0 && (!pos || !q)) return PSWFE_E_ARG;
+  return from_hip(pswfe::launch_local(plan->d, n, pos, q, phi, vec, (flags & PSWFE_VEC_GRAD) ? 1 : 0, energy, false,
+                                      static_cast<hipStream_t>(stream)));
+}
+
+pswfe_status pswfe_host_local(const pswfe_params* pp, int64_t count, const double* r, double* R, double* dRr,
+                              double* info) {
+  if (!pp || count < 0 || (count > 0 && !r)) return PSWFE_E_ARG;
+  pswfe::Params p{};
+  const pswfe_status st = params_from_c(pp, &p);
+  if (st != PSWFE_OK) return st;
+  pswfe::LocalTable t;
+  pswfe::build_local_table(p, &t);
+  for (int64_t i = 0; i < count; ++i) {
+    const double ri = r[i];
+    double Ri = 0.0, dRi = 0.0;
+    if (ri > 0.0 && ri < p.rc) {
+      const double g = ri * ri / (p.rc * p.rc) - 0.5;
+      double G = t.coef[t.deg], dG = 0.0;
+      for (int k = t.deg - 1; k >= 0; --k) {
+        dG = dG * g + G;
+        G = G * g + t.coef[k];
+      }
+      Ri = 1.0 / ri - t.K * G;
+      dRi = -1.0 / (ri * ri * ri) - 2.0 * t.K / (p.rc * p.rc) * dG;
+    }
+    if (R) R[i] = Ri;
+    if (dRr) dRr[i] = dRi;
+  }
+  if (info) {
+    info[0] = t.deg;
+    info[1] = t.fit_err;
+    info[2] = t.K;
+  }
+  return PSWFE_OK;
 }
 
 pswfe_status pswfe_spread(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* grid, void* stream) {

@@ -135,6 +135,22 @@ double Pswf::dpsi(double x) const {
   return s;
 }
 
+double Pswf::ipsi(double x) const {
+  // int_0^x P_0 = x; int_0^x P_n = (P_{n+1}(x) - P_{n-1}(x)) / (2n + 1) for even n >= 2
+  // (both values vanish at 0 for odd indices).
+  const int nmax = 2 * static_cast<int>(a.size());
+  std::vector<double> P(static_cast<size_t>(nmax) + 1);
+  P[0] = 1.0;
+  if (nmax >= 1) P[1] = x;
+  for (int n = 1; n < nmax; ++n) P[n + 1] = ((2.0 * n + 1.0) * x * P[n] - n * P[n - 1]) / (n + 1.0);
+  double s = a[0] * x;
+  for (size_t k = 1; k < a.size(); ++k) {
+    const int n = 2 * static_cast<int>(k);
+    s += a[k] * (P[n + 1] - P[n - 1]) / (2.0 * n + 1.0);
+  }
+  return s;
+}
+
 // Halley iteration on f(w) = w e^w - x.
 static double halley_w(double x, double w) {
   for (int it = 0; it < 100; ++it) {
@@ -348,6 +364,35 @@ void build_tables(const Params& p, int deg, double fit_tol, Tables* t) {
     t->fit_err = err;
     t->fit_err_deriv = derr;
     if (err <= fit_tol && derr <= fit_tol * dmax) break;
+  }
+}
+
+void build_local_table(const Params& p, LocalTable* t) {
+  const Pswf ps(p.cs);
+  t->K = 2.0 / (ps.lambda0 * ps.psi_0 * p.rc);
+  // G(t^2) = I(t) / t, with G(0) = psi_0(0)
+  auto G = [&](long double g) -> long double {
+    const double s = std::max(0.0, std::min(1.0, static_cast<double>(g) + 0.5));
+    const double tt = std::sqrt(s);
+    if (tt < 1e-8) return static_cast<long double>(ps.psi_0);
+    return static_cast<long double>(ps.ipsi(tt) / tt);
+  };
+  const double gmax = static_cast<double>(G(-0.5L));
+  for (int dg = 6; dg <= 40; ++dg) {
+    auto c = cheb_fit_monomial(G, dg);
+    std::vector<double> coef(dg + 1);
+    for (int k = 0; k <= dg; ++k) coef[k] = static_cast<double>(c[k]);
+    double err = 0.0;
+    for (int i = 0; i <= 256; ++i) {
+      const double g = -0.5 + i / 256.0;
+      double v = coef[dg];
+      for (int k = dg - 1; k >= 0; --k) v = v * g + coef[k];
+      err = std::max(err, std::fabs(v - static_cast<double>(G(g))) / std::fabs(gmax));
+    }
+    t->deg = dg;
+    t->coef.swap(coef);
+    t->fit_err = err;
+    if (err <= 1e-15) break;
   }
 }
 

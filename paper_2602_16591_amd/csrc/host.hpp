@@ -22,6 +22,7 @@ struct Pswf {
   explicit Pswf(double c);
   double psi(double x) const;   // |x| <= 1
   double dpsi(double x) const;  // |x| <= 1
+  double ipsi(double x) const;  // int_0^x psi_0, |x| <= 1
 };
 
 double lambert_w0(double x);   // principal branch, x >= -1/e
@@ -59,6 +60,18 @@ struct Tables {
 
 // deg <= 0 picks the smallest degree in [4, 28] whose sampled error is below `fit_tol`.
 void build_tables(const Params& p, int deg, double fit_tol, Tables* t);
+
+// Real-space residual R(r) = (1 - Phi(r)) / r for r < r_c (Sec. 3.1.1, eq. R). With
+// Phi(r) = 2 I(r/r_c) / (lambda_0 psi_0(0)), I(t) = int_0^t psi_0 (eq. Phi_cs), the smooth part
+// M(r) = Phi(r)/r = K G(r^2/r_c^2) with K = 2 / (lambda_0 psi_0(0) r_c) and G(t^2) = I(t)/t,
+// an even function of t. G is fitted as a polynomial in g = r^2/r_c^2 - 1/2 on [-1/2, 1/2].
+struct LocalTable {
+  int deg = 0;
+  std::vector<double> coef;  // deg + 1 monomial coefficients in g
+  double K = 0.0;
+  double fit_err = 0.0;      // max |fit - G| / max |G| (sampled)
+};
+void build_local_table(const Params& p, LocalTable* t);
 
 // exp(sign * 2 pi i e / N) for e = 0..N-1, as interleaved (re, im) pairs, float64.
 void twiddles(int N, int sign, std::vector<double>* out);

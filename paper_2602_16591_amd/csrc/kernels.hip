@@ -680,6 +680,151 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
 }
 
 // ------------------------------------------------------------------------------------
+// Real-space residual (Sec. 3.1.1, eq. R): phi_local,i = sum'_j q_j R(|x_i - x_j|) over the
+// pairs closer than r_c (minimum image, r_c < L/2), with R(r) = 1/r - K G(r^2/r_c^2 - 1/2), and
+// its gradient sum'_j q_j R'(r)/r (x_i - x_j). Particles are sorted by cells of edge L/nc >= r_c,
+// so a particle's pairs lie in its 27 neighbour cells (every pair of the system when nc < 3).
+// Positions are wrapped and differenced in float64, and all sums are float64.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ double wrap_pos(double x, double L) {
+  const double xr = x - L * floor(x / L);
+  return (xr >= 0.0 && xr < L) ? xr : 0.0;  // rounding up to L, or a non-finite input
+}
+
+__device__ __forceinline__ int cell_of_pos(double xr, double scale, int nc) {
+  const int c = static_cast<int>(xr * scale);
+  return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+template <class T>
+__global__ void k_cell_count(int64_t n, int nsys, const SysDesc* __restrict__ sys,
+                             const int64_t* __restrict__ part_prefix, const T* __restrict__ pos,
+                             int* __restrict__ cell_count, int* __restrict__ cell_of, int* __restrict__ cell_rank,
+                             double* __restrict__ energy) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (energy && i < nsys) energy[i] = 0.0;
+  if (i >= n) return;
+  const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
+  const double L = sd.L, sc = sd.nc / sd.L;
+  const int nc = sd.nc;
+  const int cx = cell_of_pos(wrap_pos(static_cast<double>(pos[3 * i + 0]), L), sc, nc);
+  const int cy = cell_of_pos(wrap_pos(static_cast<double>(pos[3 * i + 1]), L), sc, nc);
+  const int cz = cell_of_pos(wrap_pos(static_cast<double>(pos[3 * i + 2]), L), sc, nc);
+  const int cell = sd.cell_base + (cz * nc + cy) * nc + cx;
+  cell_of[i] = cell;
+  cell_rank[i] = atomicAdd(&cell_count[cell], 1);
+}
+
+template <class T>
+__global__ void k_cell_scatter(int64_t n, int nsys, const SysDesc* __restrict__ sys,
+                               const int64_t* __restrict__ part_prefix, const T* __restrict__ pos,
+                               const T* __restrict__ q, const int* __restrict__ cell_of,
+                               const int* __restrict__ cell_rank, const int* __restrict__ cell_start,
+                               double4* __restrict__ lsorted, int* __restrict__ lperm) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
+  const double L = sd.L;
+  const int dst = cell_start[cell_of[i]] + cell_rank[i];
+  lsorted[dst] = make_double4(wrap_pos(static_cast<double>(pos[3 * i + 0]), L),
+                              wrap_pos(static_cast<double>(pos[3 * i + 1]), L),
+                              wrap_pos(static_cast<double>(pos[3 * i + 2]), L), static_cast<double>(q[i]));
+  lperm[dst] = static_cast<int>(i);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_local(int64_t n, int nsys, const SysDesc* __restrict__ sys,
+                                               const int64_t* __restrict__ part_prefix,
+                                               const double4* __restrict__ lsorted, const int* __restrict__ lperm,
+                                               const int* __restrict__ cell_start, T* __restrict__ phi,
+                                               T* __restrict__ vec, int vec_mode, int accumulate,
+                                               double* __restrict__ energy) {
+  __shared__ double s_red[4];
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const bool valid = i < n;
+  const int s = nsys == 1 ? 0 : find_sys(part_prefix, nsys, valid ? i : n - 1);
+  double ph = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0, qi = 0.0;
+  if (valid) {
+    const SysDesc& sd = sys[s];
+    const double4 xi = lsorted[i];
+    qi = xi.w;
+    const double L = sd.L, rc2 = sd.rc * sd.rc, inv_rc2 = 1.0 / rc2, K = sd.lK;
+    const double* __restrict__ c = sd.lcoef;
+    const int deg = sd.ldeg;
+    auto pair = [&](int64_t j) {
+      if (j == i) return;
+      const double4 xj = lsorted[j];
+      double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+      dx -= L * rint(dx / L);
+      dy -= L * rint(dy / L);
+      dz -= L * rint(dz / L);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (!(r2 < rc2) || r2 == 0.0) return;  // beyond the cutoff, or coincident positions
+      const double rinv = 1.0 / sqrt(r2);
+      const double g = r2 * inv_rc2 - 0.5;
+      double G = c[deg], dG = 0.0;
+      for (int k = deg - 1; k >= 0; --k) {
+        dG = fma(dG, g, G);
+        G = fma(G, g, c[k]);
+      }
+      const double R = rinv - K * G;                                  // eq. R
+      const double dRr = -rinv * rinv * rinv - 2.0 * K * inv_rc2 * dG;  // R'(r) / r
+      ph = fma(xj.w, R, ph);
+      const double f = xj.w * dRr;
+      g0 = fma(f, dx, g0);
+      g1 = fma(f, dy, g1);
+      g2 = fma(f, dz, g2);
+    };
+    const int nc = sd.nc;
+    if (nc >= 3) {
+      const double sc = nc / L;
+      const int cx = cell_of_pos(xi.x, sc, nc), cy = cell_of_pos(xi.y, sc, nc), cz = cell_of_pos(xi.z, sc, nc);
+      for (int dz2 = -1; dz2 <= 1; ++dz2) {
+        const int z = cz + dz2 < 0 ? cz + dz2 + nc : (cz + dz2 >= nc ? cz + dz2 - nc : cz + dz2);
+        for (int dy2 = -1; dy2 <= 1; ++dy2) {
+          const int y = cy + dy2 < 0 ? cy + dy2 + nc : (cy + dy2 >= nc ? cy + dy2 - nc : cy + dy2);
+          for (int dx2 = -1; dx2 <= 1; ++dx2) {
+            const int x = cx + dx2 < 0 ? cx + dx2 + nc : (cx + dx2 >= nc ? cx + dx2 - nc : cx + dx2);
+            const int cell = sd.cell_base + (z * nc + y) * nc + x;
+            const int j1 = cell_start[cell + 1];
+            for (int j = cell_start[cell]; j < j1; ++j) pair(j);
+          }
+        }
+      }
+    } else {
+      const int64_t j0 = nsys == 1 ? 0 : part_prefix[s], j1 = nsys == 1 ? n : part_prefix[s + 1];
+      for (int64_t j = j0; j < j1; ++j) pair(j);
+    }
+    const int idx = lperm[i];
+    if (phi) phi[idx] = static_cast<T>(accumulate ? static_cast<double>(phi[idx]) + ph : ph);
+    if (vec) {
+      const double sc = vec_mode == 0 ? -qi : 1.0;
+      const double v[3] = {sc * g0, sc * g1, sc * g2};
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        vec[3 * idx + d] = static_cast<T>(accumulate ? static_cast<double>(vec[3 * idx + d]) + v[d] : v[d]);
+    }
+  }
+  if (energy) {
+    // one atomic per workgroup when its particles belong to one system, else one per particle
+    const int64_t i0 = blockIdx.x * static_cast<int64_t>(blockDim.x);
+    const int64_t ilast = min(i0 + static_cast<int64_t>(blockDim.x) - 1, n - 1);
+    const int s_first = nsys == 1 ? 0 : find_sys(part_prefix, nsys, i0);
+    const int s_last = nsys == 1 ? 0 : find_sys(part_prefix, nsys, ilast);
+    double e = 0.5 * qi * ph;
+    if (s_first == s_last) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+      if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = e;
+      __syncthreads();
+      if (threadIdx.x == 0) unsafeAtomicAdd(energy + s_first, s_red[0] + s_red[1] + s_red[2] + s_red[3]);
+    } else if (valid) {
+      unsafeAtomicAdd(energy + s, e);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
 // FFT: Stockham autosort passes in LDS over a batch of sequences. Stage with radix R and
 // current sub-length Ls: butterfly b (k = b mod Ls, j = b / Ls) reads x[b + t N/R],
 // multiplies by w_{R Ls}^{t k}, takes an R-point DFT, and writes y_u to j R Ls + u Ls + k.
@@ -1096,6 +1241,34 @@ hipError_t launch_drain(const DevPlan& d, void* out, hipStream_t st) {
   else
     hipLaunchKernelGGL(k_drain<double>, dim3(nb), dim3(256), 0, st, s0.grid_a, static_cast<double*>(out), count);
   return hipGetLastError();
+}
+
+template <class T>
+hipError_t local_impl(const DevPlan& d, int64_t n, const void* pos, const void* q, void* phi, void* vec, int vec_mode,
+                      double* energy, bool accumulate, hipStream_t st) {
+  stage_begin(d, kStageLocal, st);
+  const int64_t nthreads = std::max<int64_t>(n, (energy && !accumulate) ? d.nsys : 0);
+  if (nthreads > 0)
+    hipLaunchKernelGGL(k_cell_count<T>, dim3(blocks_for(nthreads, 256)), dim3(256), 0, st, n, d.nsys, d.sys_dev,
+                       d.part_prefix, static_cast<const T*>(pos), d.cell_count, d.cell_of, d.cell_rank,
+                       accumulate ? nullptr : energy);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d.total_cells, d.cell_count, d.cell_start);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_cell_scatter<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d.nsys, d.sys_dev,
+                       d.part_prefix, static_cast<const T*>(pos), static_cast<const T*>(q), d.cell_of, d.cell_rank,
+                       d.cell_start, reinterpret_cast<double4*>(d.lsorted), d.lperm);
+    hipLaunchKernelGGL(k_local<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d.nsys, d.sys_dev, d.part_prefix,
+                       reinterpret_cast<const double4*>(d.lsorted), d.lperm, d.cell_start, static_cast<T*>(phi),
+                       static_cast<T*>(vec), vec_mode, accumulate ? 1 : 0, energy);
+  }
+  stage_end(d, kStageLocal, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_local(const DevPlan& d, int64_t n_total, const void* pos, const void* q, void* phi, void* vec,
+                        int vec_mode, double* energy, bool accumulate, hipStream_t st) {
+  return d.prec == 0 ? local_impl<float>(d, n_total, pos, q, phi, vec, vec_mode, energy, accumulate, st)
+                     : local_impl<double>(d, n_total, pos, q, phi, vec, vec_mode, energy, accumulate, st);
 }
 
 hipError_t launch_transform(const DevPlan& d, const void* in_override, void* out_override, hipStream_t st) {

@@ -27,7 +27,7 @@ struct FftPlan {
 // Pipeline stages, for event-based timing of one stage at a time.
 enum Stage {
   kStageBin = 0, kStageSpread = 1, kStageFftX = 2, kStageFftY = 3, kStageFftZScale = 4, kStageIfftY = 5,
-  kStageIfftX = 6, kStageGather = 7, kStageAll = 8, kNumStages = 9
+  kStageIfftX = 6, kStageGather = 7, kStageAll = 8, kStageLocal = 9, kNumStages = 10
 };
 
 // HIP events recorded around one stage of successive calls (owned by the plan).
@@ -63,6 +63,13 @@ struct SysDesc {
   const void* twfp = nullptr; // exp(+2 pi i e / m), e < m
   const void* twfm = nullptr; // exp(-2 pi i e / m)
   FftPlan fh, ff;             // radix plans for lengths m/2 and m
+  // real-space residual (Sec. 3.1.1): cells of edge L / nc >= r_c (nc >= 3), or every pair of
+  // the system when nc < 3
+  int nc = 1;                 // cells per dimension
+  int cell_base = 0;          // first global cell of this system
+  int ldeg = 0;               // degree of the residual polynomial G
+  double rc = 0, lK = 0;      // cutoff and K of R(r) = 1/r - K G(r^2/r_c^2 - 1/2)
+  const double* lcoef = nullptr;  // ldeg + 1 coefficients of G (float64)
 };
 
 // Horner degree buckets of the particle kernels: a window polynomial of degree deg is
@@ -123,6 +130,14 @@ struct DevPlan {
   int* perm = nullptr;         // n_max: sorted slot -> packed input index
   int* cells = nullptr;        // n_max: packed cell cx + m (cy + m cz) of each sorted particle
   void* sorted = nullptr;      // n_max x 4: (f_x, f_y, f_z, q), fractional cell offsets in [0, 1]
+  // real-space cell list, over all systems
+  int total_cells = 0;
+  int* cell_count = nullptr;   // total_cells, kept all-zero between calls
+  int* cell_start = nullptr;   // total_cells + 1
+  int* cell_of = nullptr;      // n_max
+  int* cell_rank = nullptr;    // n_max
+  double* lsorted = nullptr;   // n_max x 4: wrapped position (float64) and charge, by cell
+  int* lperm = nullptr;        // n_max: cell-sorted slot -> packed input index
   StageTimer* timer = nullptr; // optional instrumentation
 };
 
@@ -157,5 +172,10 @@ hipError_t launch_transform(const DevPlan& d, const void* in_override, void* out
 // grid_override (single system only) replaces grid_b. energy: nsys doubles, accumulated.
 hipError_t launch_gather(const DevPlan& d, const void* grid_override, void* phi, void* vec, int vec_mode,
                          bool add_self, double* energy, hipStream_t stream);
+// Real-space residual of every system: cell binning, then phi_local, its gradient term and
+// energy, added to phi / vec / energy when accumulate is set, else written (energy zeroed
+// first). vec_mode as in launch_gather.
+hipError_t launch_local(const DevPlan& d, int64_t n_total, const void* pos, const void* q, void* phi, void* vec,
+                        int vec_mode, double* energy, bool accumulate, hipStream_t stream);
 
 }  // namespace pswfe

@@ -158,3 +158,25 @@ def test_tile_for_density():
         if 4 < b < m:
             assert b ** 3 * n / m ** 3 >= t - 1e-9 and (b - 1) ** 3 * n / m ** 3 < t
     assert tile_for_density(16, 0, 256) == 8
+
+
+@pytest.mark.parametrize("eps,m,L", [(1e-6, 32, 1.0), (1e-10, 48, 2.0), (1e-4, 20, 0.7), (1e-12, 64, 1.0)])
+def test_host_residual_matches_oracle(eps, m, L):
+    """The real-space residual the kernels evaluate, R(r) = (1 - Phi(r))/r (eq. R), and R'(r)/r,
+    from the library's float64 fit, against the oracle's split function (Legendre series and
+    its quadrature-free integral): relative to 1/r, and R(r_c) = 0 where Phi reaches 1."""
+    from oracle import params as oparams
+    from oracle.pswf import split_function, split_function_deriv
+    c = pw.choose_params(eps, L, m=m)
+    o = oparams.choose(eps, L, m=m)
+    r = np.linspace(1e-4, 1.0, 4001) * o.rc
+    R, dRr, info = pw.host_local(c, r)
+    ps = PSWF(o.cs)
+    Phi = split_function(r, o.rc, ps)
+    Rref = (1.0 - Phi) / r
+    dRref = (-split_function_deriv(r, o.rc, ps) / r - (1.0 - Phi) / r ** 2) / r
+    assert info["fit_err"] <= 1e-15
+    assert np.max(np.abs(R - Rref) * r) < 2e-15
+    assert np.max(np.abs(dRr - dRref) * r ** 3) < 2e-12   # derivative of a degree <= 40 fit
+    assert abs(pw.host_local(c, np.array([o.rc * (1 - 1e-12)]))[0][0]) < 1e-9 / o.rc
+    assert pw.host_local(c, np.array([o.rc, 1.5 * o.rc, 0.0]))[0].tolist() == [0.0, 0.0, 0.0]

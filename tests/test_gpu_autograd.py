@@ -129,3 +129,55 @@ def test_general_loss_adjoint(prec):
     assert len(errs) > 40
     tol = 1e-6 if prec == "fp64" else 3e-5
     assert np.sqrt(np.mean(np.square(errs))) < tol * np.sqrt(np.mean(gx ** 2))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_adjoint_matches_single_systems(prec):
+    """A batch of three systems with L = sum_s c_s E_s + sum_i w_i phi_i: the batched adjoint
+    against each system's own single-plan adjoint, and the charge gradients against central
+    differences of the float64 batch (L is quadratic in q)."""
+    systems = [W.uniform_pm1(400, seed=31, L=1.0), W.uniform_pm1(600, seed=32, L=1.5),
+               W.paper_default(500, seed=33, L=0.8)]
+    grids = [24, 30, 20]
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    params = [pw.choose_params(1e-6, L, m=m) for (_, _, L), m in zip(systems, grids)]
+    counts = [len(q) for _, q, _ in systems]
+    x = np.concatenate([s[0] for s in systems]).astype(np.float32).astype(np.float64)
+    q = np.concatenate([s[1] for s in systems])
+    rng = np.random.Generator(np.random.PCG64(34))
+    w = rng.standard_normal(len(q))
+    cs = np.array([0.7, -1.3, 2.1])
+    plan = pw.BatchPlan(params, counts, prec)
+    X = torch.tensor(x, dtype=dt, device=dev(), requires_grad=True)
+    Q = torch.tensor(q, dtype=dt, device=dev(), requires_grad=True)
+    E, phi = ag.batch_energy_and_potential(X, Q, plan)
+    loss = (torch.tensor(w, dtype=dt, device=dev()) * phi).sum() + (torch.tensor(cs, device=dev()) * E).sum().to(dt)
+    loss.backward()
+    gx, gq = X.grad.double().cpu().numpy(), Q.grad.double().cpu().numpy()
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    for s, (o, n) in enumerate(zip(plan.offsets, plan.counts)):
+        sp = pw.Plan(params[s], prec, n_max=n)
+        Xs = torch.tensor(x[o:o + n], dtype=dt, device=dev(), requires_grad=True)
+        Qs = torch.tensor(q[o:o + n], dtype=dt, device=dev(), requires_grad=True)
+        Es, phis = ag.energy_and_potential(Xs, Qs, sp)
+        ls = (torch.tensor(w[o:o + n], dtype=dt, device=dev()) * phis).sum() + cs[s] * Es.to(dt).sum()
+        ls.backward()
+        rx, rq = Xs.grad.double().cpu().numpy(), Qs.grad.double().cpu().numpy()
+        assert np.linalg.norm(gx[o:o + n] - rx) <= tol * np.linalg.norm(rx)
+        assert np.linalg.norm(gq[o:o + n] - rq) <= tol * np.linalg.norm(rq)
+    p64 = pw.BatchPlan(params, counts, "fp64")
+    X64 = torch.tensor(x, dtype=torch.float64, device=dev())
+    W64 = torch.tensor(w, dtype=torch.float64, device=dev())
+    C64 = torch.tensor(cs, dtype=torch.float64, device=dev())
+
+    def L_of(Qv):
+        ph, _, En = p64.compute(X64, Qv, force=False)
+        return float((W64 * ph).sum().cpu()) + float((C64 * En).sum().cpu())
+
+    Q64 = torch.tensor(q, dtype=torch.float64, device=dev())
+    for i in [5, counts[0] + 7, counts[0] + counts[1] + 11]:
+        Qp, Qm = Q64.clone(), Q64.clone()
+        Qp[i] += 1e-3
+        Qm[i] -= 1e-3
+        fd = (L_of(Qp) - L_of(Qm)) / 2e-3
+        assert abs(fd - gq[i]) < (1e-8 if prec == "fp64" else 3e-5) * np.max(np.abs(gq))
