@@ -217,6 +217,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   Arena work, tabs;
   struct TabOff { size_t coef, tm, wk, twhp, twhm, twfp, twfm, lcoef; };
   int cell_prefix = 0;
+  std::vector<int> cell_prefix_v(nsys + 1, 0);
   struct WorkOff { size_t a, b, spec; };
   std::vector<TabOff> toff(nsys);
   std::vector<WorkOff> woff(nsys);
@@ -295,6 +296,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     if (sd.nc < 3) sd.nc = 1;
     sd.cell_base = cell_prefix;
     cell_prefix += sd.nc * sd.nc * sd.nc;
+    cell_prefix_v[s + 1] = cell_prefix;
     if (!(p.rc < 0.5 * p.L)) plan->local_ok = false;
     toff[s] = {tabs.take(sizeof(double) * t.coef.size()), tabs.take(elem * t.tm.size()),
                tabs.take(elem * t.w.size()), tabs.take(celem * N), tabs.take(celem * N), tabs.take(celem * m),
@@ -381,6 +383,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   d.tile_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
   d.tile_sys = static_cast<int*>(alloc(sizeof(int) * nsys));
   d.total_cells = cell_prefix;
+  d.cell_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
   d.cell_count = static_cast<int*>(alloc(sizeof(int) * d.total_cells));
   d.cell_start = static_cast<int*>(alloc(sizeof(int) * (d.total_cells + 1)));
   d.cell_of = static_cast<int*>(alloc(sizeof(int) * nm));
@@ -442,6 +445,8 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
             hipMemcpy(d.tile_prefix, tile_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
                 hipSuccess &&
             hipMemcpy(d.tile_sys, order.data(), sizeof(int) * nsys, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(d.cell_prefix, cell_prefix_v.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
+                hipSuccess &&
             hipMemcpy(d.xblk_prefix, xblk_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
                 hipSuccess &&
             hipMemcpy(d.cblk_prefix, cblk_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==

@@ -732,94 +732,148 @@ __global__ void k_cell_scatter(int64_t n, int nsys, const SysDesc* __restrict__ 
   lperm[dst] = static_cast<int>(i);
 }
 
+// One workgroup per cell: the particles of the 27 neighbour cells (of the whole system when
+// nc < 3) are staged in LDS, kLocalChunk at a time, and each target particle of the cell is
+// handled by kLocalLanes lanes that split the sources and reduce with shuffles. The residual's
+// polynomial coefficients are held in registers, and no division or memory access other than
+// LDS reads sits in the pair loop.
+constexpr int kLocalThreads = 128;
+constexpr int kLocalLanes = 8;
+constexpr int kLocalChunk = 1024;
+constexpr int kLocalDeg = 24;  // the residual polynomial G, zero-padded to this degree
+
 template <class T>
-__global__ __launch_bounds__(256) void k_local(int64_t n, int nsys, const SysDesc* __restrict__ sys,
-                                               const int64_t* __restrict__ part_prefix,
-                                               const double4* __restrict__ lsorted, const int* __restrict__ lperm,
-                                               const int* __restrict__ cell_start, T* __restrict__ phi,
-                                               T* __restrict__ vec, int vec_mode, int accumulate,
-                                               double* __restrict__ energy) {
-  __shared__ double s_red[4];
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  const bool valid = i < n;
-  const int s = nsys == 1 ? 0 : find_sys(part_prefix, nsys, valid ? i : n - 1);
-  double ph = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0, qi = 0.0;
-  if (valid) {
-    const SysDesc& sd = sys[s];
-    const double4 xi = lsorted[i];
-    qi = xi.w;
-    const double L = sd.L, rc2 = sd.rc * sd.rc, inv_rc2 = 1.0 / rc2, K = sd.lK;
-    const double* __restrict__ c = sd.lcoef;
-    const int deg = sd.ldeg;
-    auto pair = [&](int64_t j) {
-      if (j == i) return;
-      const double4 xj = lsorted[j];
-      double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-      dx -= L * rint(dx / L);
-      dy -= L * rint(dy / L);
-      dz -= L * rint(dz / L);
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      if (!(r2 < rc2) || r2 == 0.0) return;  // beyond the cutoff, or coincident positions
-      const double rinv = 1.0 / sqrt(r2);
-      const double g = r2 * inv_rc2 - 0.5;
-      double G = c[deg], dG = 0.0;
-      for (int k = deg - 1; k >= 0; --k) {
-        dG = fma(dG, g, G);
-        G = fma(G, g, c[k]);
-      }
-      const double R = rinv - K * G;                                  // eq. R
-      const double dRr = -rinv * rinv * rinv - 2.0 * K * inv_rc2 * dG;  // R'(r) / r
-      ph = fma(xj.w, R, ph);
-      const double f = xj.w * dRr;
-      g0 = fma(f, dx, g0);
-      g1 = fma(f, dy, g1);
-      g2 = fma(f, dz, g2);
-    };
-    const int nc = sd.nc;
+__global__ __launch_bounds__(kLocalThreads) void k_local(int nsys, const SysDesc* __restrict__ sys,
+                                                         const int* __restrict__ cell_prefix,
+                                                         const double4* __restrict__ lsorted,
+                                                         const int* __restrict__ lperm,
+                                                         const int* __restrict__ cell_start, T* __restrict__ phi,
+                                                         T* __restrict__ vec, int vec_mode, int accumulate,
+                                                         double* __restrict__ energy) {
+  __shared__ double4 src[kLocalChunk];
+  __shared__ int src_id[kLocalChunk];
+  __shared__ int nb_begin[27], nb_off[28];
+  __shared__ double s_red[kLocalThreads / 64];
+  const int gcell = blockIdx.x;
+  const int t0 = cell_start[gcell], t1 = cell_start[gcell + 1];
+  if (t0 == t1) return;
+  const int s = find_sys(cell_prefix, nsys, gcell);
+  const SysDesc& sd = sys[s];
+  const int nc = sd.nc;
+  const double L = sd.L, inv_L = 1.0 / sd.L, rc2 = sd.rc * sd.rc, inv_rc2 = 1.0 / rc2, K = sd.lK;
+  double cr[kLocalDeg + 1];
+#pragma unroll
+  for (int k = 0; k <= kLocalDeg; ++k) cr[k] = k <= sd.ldeg ? sd.lcoef[k] : 0.0;
+  const int tid = threadIdx.x;
+  // source ranges: the 27 neighbour cells (distinct, as nc >= 3), or the system's one cell
+  if (tid < 27) {
+    int b = 0, e = 0;
     if (nc >= 3) {
-      const double sc = nc / L;
-      const int cx = cell_of_pos(xi.x, sc, nc), cy = cell_of_pos(xi.y, sc, nc), cz = cell_of_pos(xi.z, sc, nc);
-      for (int dz2 = -1; dz2 <= 1; ++dz2) {
-        const int z = cz + dz2 < 0 ? cz + dz2 + nc : (cz + dz2 >= nc ? cz + dz2 - nc : cz + dz2);
-        for (int dy2 = -1; dy2 <= 1; ++dy2) {
-          const int y = cy + dy2 < 0 ? cy + dy2 + nc : (cy + dy2 >= nc ? cy + dy2 - nc : cy + dy2);
-          for (int dx2 = -1; dx2 <= 1; ++dx2) {
-            const int x = cx + dx2 < 0 ? cx + dx2 + nc : (cx + dx2 >= nc ? cx + dx2 - nc : cx + dx2);
-            const int cell = sd.cell_base + (z * nc + y) * nc + x;
-            const int j1 = cell_start[cell + 1];
-            for (int j = cell_start[cell]; j < j1; ++j) pair(j);
+      const int lc = gcell - sd.cell_base;
+      const int cx = lc % nc, cy = (lc / nc) % nc, cz = lc / (nc * nc);
+      const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = tid / 9 - 1;
+      const int x = (cx + dx + nc) % nc, y = (cy + dy + nc) % nc, z = (cz + dz + nc) % nc;
+      const int cell = sd.cell_base + (z * nc + y) * nc + x;
+      b = cell_start[cell];
+      e = cell_start[cell + 1];
+    } else if (tid == 0) {
+      b = t0;
+      e = t1;
+    }
+    nb_begin[tid] = b;
+    nb_off[tid + 1] = e - b;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    nb_off[0] = 0;
+    for (int k = 0; k < 27; ++k) nb_off[k + 1] += nb_off[k];
+  }
+  __syncthreads();
+  const int ns = nb_off[27];
+  const int grp = tid / kLocalLanes, lane = tid % kLocalLanes;
+  constexpr int kTargetsPerPass = kLocalThreads / kLocalLanes;
+  double esum = 0.0;
+  for (int tb = t0; tb < t1; tb += kTargetsPerPass) {
+    const int ti = tb + grp;
+    const bool tvalid = ti < t1;
+    const double4 xi = lsorted[tvalid ? ti : t0];
+    double ph = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    for (int c0 = 0; c0 < ns; c0 += kLocalChunk) {
+      const int nchunk = min(kLocalChunk, ns - c0);
+      __syncthreads();
+      for (int k = tid; k < nchunk; k += kLocalThreads) {
+        const int gk = c0 + k;
+        int lo = 0, hi = 26;  // the neighbour cell holding source gk: largest cc with nb_off[cc] <= gk
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (nb_off[mid] <= gk)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        const int j = nb_begin[lo] + (gk - nb_off[lo]);
+        src[k] = lsorted[j];
+        src_id[k] = j;
+      }
+      __syncthreads();
+      if (tvalid) {
+        for (int k = lane; k < nchunk; k += kLocalLanes) {
+          if (src_id[k] == ti) continue;
+          const double4 xj = src[k];
+          double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
+          dx -= L * rint(dx * inv_L);  // minimum image (|dx| < L; pairs near L/2 lie beyond r_c)
+          dy -= L * rint(dy * inv_L);
+          dz -= L * rint(dz * inv_L);
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (!(r2 < rc2) || r2 == 0.0) continue;  // beyond the cutoff, or coincident positions
+          const double rinv = rsqrt(r2);
+          const double g = r2 * inv_rc2 - 0.5;
+          double G = cr[kLocalDeg], dG = 0.0;
+#pragma unroll
+          for (int kk = kLocalDeg - 1; kk >= 0; --kk) {
+            dG = fma(dG, g, G);
+            G = fma(G, g, cr[kk]);
           }
+          const double R = rinv - K * G;                                  // eq. R
+          const double dRr = -rinv * rinv * rinv - 2.0 * K * inv_rc2 * dG;  // R'(r) / r
+          ph = fma(xj.w, R, ph);
+          const double f = xj.w * dRr;
+          g0 = fma(f, dx, g0);
+          g1 = fma(f, dy, g1);
+          g2 = fma(f, dz, g2);
         }
       }
-    } else {
-      const int64_t j0 = nsys == 1 ? 0 : part_prefix[s], j1 = nsys == 1 ? n : part_prefix[s + 1];
-      for (int64_t j = j0; j < j1; ++j) pair(j);
     }
-    const int idx = lperm[i];
-    if (phi) phi[idx] = static_cast<T>(accumulate ? static_cast<double>(phi[idx]) + ph : ph);
-    if (vec) {
-      const double sc = vec_mode == 0 ? -qi : 1.0;
-      const double v[3] = {sc * g0, sc * g1, sc * g2};
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
-        vec[3 * idx + d] = static_cast<T>(accumulate ? static_cast<double>(vec[3 * idx + d]) + v[d] : v[d]);
+    for (int off = kLocalLanes / 2; off > 0; off >>= 1) {
+      ph += __shfl_xor(ph, off, kLocalLanes);
+      g0 += __shfl_xor(g0, off, kLocalLanes);
+      g1 += __shfl_xor(g1, off, kLocalLanes);
+      g2 += __shfl_xor(g2, off, kLocalLanes);
+    }
+    if (tvalid && lane == 0) {
+      const int idx = lperm[ti];
+      const double qi = xi.w;
+      if (phi) phi[idx] = static_cast<T>(accumulate ? static_cast<double>(phi[idx]) + ph : ph);
+      if (vec) {
+        const double sc = vec_mode == 0 ? -qi : 1.0;
+        const double v[3] = {sc * g0, sc * g1, sc * g2};
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+          vec[3 * idx + d] = static_cast<T>(accumulate ? static_cast<double>(vec[3 * idx + d]) + v[d] : v[d]);
+      }
+      esum += 0.5 * qi * ph;
     }
   }
   if (energy) {
-    // one atomic per workgroup when its particles belong to one system, else one per particle
-    const int64_t i0 = blockIdx.x * static_cast<int64_t>(blockDim.x);
-    const int64_t ilast = min(i0 + static_cast<int64_t>(blockDim.x) - 1, n - 1);
-    const int s_first = nsys == 1 ? 0 : find_sys(part_prefix, nsys, i0);
-    const int s_last = nsys == 1 ? 0 : find_sys(part_prefix, nsys, ilast);
-    double e = 0.5 * qi * ph;
-    if (s_first == s_last) {
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
-      if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = e;
-      __syncthreads();
-      if (threadIdx.x == 0) unsafeAtomicAdd(energy + s_first, s_red[0] + s_red[1] + s_red[2] + s_red[3]);
-    } else if (valid) {
-      unsafeAtomicAdd(energy + s, e);
+    for (int off = 32; off > 0; off >>= 1) esum += __shfl_xor(esum, off, 64);
+    if ((tid & 63) == 0) s_red[tid >> 6] = esum;
+    __syncthreads();
+    if (tid == 0) {
+      double tot = 0.0;
+      for (int w = 0; w < kLocalThreads / 64; ++w) tot += s_red[w];
+      unsafeAtomicAdd(energy + s, tot);
     }
   }
 }
@@ -1257,9 +1311,9 @@ hipError_t local_impl(const DevPlan& d, int64_t n, const void* pos, const void* 
     hipLaunchKernelGGL(k_cell_scatter<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d.nsys, d.sys_dev,
                        d.part_prefix, static_cast<const T*>(pos), static_cast<const T*>(q), d.cell_of, d.cell_rank,
                        d.cell_start, reinterpret_cast<double4*>(d.lsorted), d.lperm);
-    hipLaunchKernelGGL(k_local<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d.nsys, d.sys_dev, d.part_prefix,
-                       reinterpret_cast<const double4*>(d.lsorted), d.lperm, d.cell_start, static_cast<T*>(phi),
-                       static_cast<T*>(vec), vec_mode, accumulate ? 1 : 0, energy);
+    hipLaunchKernelGGL(k_local<T>, dim3(d.total_cells), dim3(kLocalThreads), 0, st, d.nsys, d.sys_dev,
+                       d.cell_prefix, reinterpret_cast<const double4*>(d.lsorted), d.lperm, d.cell_start,
+                       static_cast<T*>(phi), static_cast<T*>(vec), vec_mode, accumulate ? 1 : 0, energy);
   }
   stage_end(d, kStageLocal, st);
   return hipGetLastError();

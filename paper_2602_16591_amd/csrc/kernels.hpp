@@ -63,8 +63,8 @@ struct SysDesc {
   const void* twfp = nullptr; // exp(+2 pi i e / m), e < m
   const void* twfm = nullptr; // exp(-2 pi i e / m)
   FftPlan fh, ff;             // radix plans for lengths m/2 and m
-  // real-space residual (Sec. 3.1.1): cells of edge L / nc >= r_c (nc >= 3), or every pair of
-  // the system when nc < 3
+  // real-space residual (Sec. 3.1.1): cells of edge L / nc >= r_c (nc >= 3), or one cell
+  // holding the whole system when nc < 3
   int nc = 1;                 // cells per dimension
   int cell_base = 0;          // first global cell of this system
   int ldeg = 0;               // degree of the residual polynomial G
@@ -132,6 +132,7 @@ struct DevPlan {
   void* sorted = nullptr;      // n_max x 4: (f_x, f_y, f_z, q), fractional cell offsets in [0, 1]
   // real-space cell list, over all systems
   int total_cells = 0;
+  int* cell_prefix = nullptr;  // nsys + 1: first global cell of each system
   int* cell_count = nullptr;   // total_cells, kept all-zero between calls
   int* cell_start = nullptr;   // total_cells + 1
   int* cell_of = nullptr;      // n_max
