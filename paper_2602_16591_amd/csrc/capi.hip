@@ -309,10 +309,8 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   // spreading by columns where the tile edge allows it (PSWFE_SPREAD_COLUMNS=0 turns it off)
   bool columns_ok = true;
   if (const char* env = std::getenv("PSWFE_SPREAD_COLUMNS")) columns_ok = std::atoi(env) != 0;
-  auto cols = [&](int s) { return columns_ok && d.sys[s].B == pswfe::kColTileHost; };
-  auto key = [&](int s) {
-    return std::make_tuple(d.sys[s].P, pswfe::degree_bucket(d.sys[s].deg), cols(s) ? 1 : 0);
-  };
+  auto cols = [&](int s) { return columns_ok && pswfe::col_tile_ok(d.sys[s].B) ? d.sys[s].B : 0; };
+  auto key = [&](int s) { return std::make_tuple(d.sys[s].P, pswfe::degree_bucket(d.sys[s].deg), cols(s)); };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
   for (int k = 0; k < nsys; ++k) {
     pswfe::SysDesc& sd = d.sys[order[k]];
@@ -320,11 +318,11 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     sd.tile_base = tile_prefix[k];
     tile_prefix[k + 1] = tile_prefix[k] + sd.Tn * sd.Tn * sd.Tn;
     if (d.groups.empty() || d.groups.back().P != sd.P || d.groups.back().D != D ||
-        d.groups.back().spread_columns != cols(order[k])) {
+        d.groups.back().col_tile != cols(order[k])) {
       pswfe::PGroup g;
       g.P = sd.P;
       g.D = D;
-      g.spread_columns = cols(order[k]);
+      g.col_tile = cols(order[k]);
       g.tile_begin = tile_prefix[k];
       d.groups.push_back(g);
     }
@@ -334,10 +332,10 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   }
   for (pswfe::PGroup& g : d.groups) {
     const int S = static_cast<int>(g.lds_spread), P = g.P, D = g.D;
-    g.spread_threads = g.spread_columns ? pswfe::col_threads_host(P)
-                                        : particle_threads(P, [&](int t) { return spread_lds_bytes(S, P, D, t); });
+    g.spread_threads = g.col_tile ? pswfe::col_threads_host(P, g.col_tile)
+                                  : particle_threads(P, [&](int t) { return spread_lds_bytes(S, P, D, t); });
     g.gather_threads = particle_threads(P, [&](int t) { return gather_lds_bytes(S, P, D, elem, t); });
-    g.lds_spread = g.spread_columns ? pswfe::col_lds_bytes(P, D) : spread_lds_bytes(S, P, D, g.spread_threads);
+    g.lds_spread = g.col_tile ? pswfe::col_lds_bytes(P, D, g.col_tile) : spread_lds_bytes(S, P, D, g.spread_threads);
     g.lds_gather = gather_lds_bytes(S, P, D, elem, g.gather_threads);
   }
   d.total_tiles = tile_prefix[nsys];

@@ -411,7 +411,7 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_spread(const type
       });
 }
 
-// Spreading by columns, for tiles of edge kColTile (Alg. 2 step 1, same sums as k_spread).
+// Spreading by columns, for tiles of edge B = 4, 6 or 8 (Alg. 2 step 1, same sums as k_spread).
 // Thread (ix, iz) of the S x S face of the tile's block owns the S points of its y-column in
 // registers. Particles are taken kColBatch at a time: their window values are written to LDS
 // as S-long arrays per dimension, zero outside the support (Horner runs once per value), and
@@ -420,19 +420,18 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_spread(const type
 // atomics (on gfx950 a float64 FMA costs far less issue time than a float64 LDS atomic);
 // the block then adds its S^3 points into the float64 grid with global atomics, lanes of
 // consecutive ix writing consecutive addresses.
-constexpr int kColTile = 8;
 constexpr int kColBatch = 32;
-template <int P>
-constexpr int col_edge() { return kColTile + 2 * ((P + 1) / 2) - 1; }
-template <int P>
-constexpr int col_threads() { return (col_edge<P>() * col_edge<P>() + 63) / 64 * 64; }
+template <int P, int B>
+constexpr int col_edge() { return B + 2 * ((P + 1) / 2) - 1; }
+template <int P, int B>
+constexpr int col_threads() { return (col_edge<P, B>() * col_edge<P, B>() + 63) / 64 * 64; }
 
-template <class T, int P, int D>
-__global__ __launch_bounds__(col_threads<P>()) void k_spread_cols(
+template <class T, int P, int D, int B>
+__global__ __launch_bounds__((col_threads<P, B>())) void k_spread_cols(
     const typename Vec4<T>::type* __restrict__ sorted, const int* __restrict__ cells,
     const int* __restrict__ tile_start, int sub_log2, int nsys, const SysDesc* __restrict__ sys,
     const int* __restrict__ tile_prefix, const int* __restrict__ tile_sys, int tile_offset) {
-  constexpr int S = col_edge<P>();
+  constexpr int S = col_edge<P, B>();
   constexpr int CS = coef_stride(D);
   constexpr int RS = 3 * S;  // a particle's padded window values: x, y, z
   extern __shared__ unsigned char smem_raw[];
@@ -448,7 +447,7 @@ __global__ __launch_bounds__(col_threads<P>()) void k_spread_cols(
   int* po = reinterpret_cast<int*>(pg + kColBatch * 4); // kColBatch * 4: o_x, o_y, o_z
   const int tile = gtile - sd.tile_base;
   const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
-  const int T0x = tx * kColTile, T0y = ty * kColTile, T0z = tz * kColTile;
+  const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
   stage_coefficients<P, D>(sd.coef, sd.deg, lcoef);
   const int t = threadIdx.x;
   const bool owner = t < S * S;
@@ -1178,10 +1177,17 @@ hipError_t bin_impl(const DevPlan& d, int64_t n, const void* pos, const void* q,
 
 template <class T, int P, int D>
 hipError_t spread_impl(const DevPlan& d, const PGroup& g, hipStream_t st) {
-  if (g.spread_columns)
-    hipLaunchKernelGGL((k_spread_cols<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(col_threads<P>()),
-                       g.lds_spread, st, static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start,
-                       d.sub_log2, d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin);
+  auto cols = [&](auto kern, int threads) {
+    hipLaunchKernelGGL(kern, dim3(g.tile_end - g.tile_begin), dim3(threads), g.lds_spread, st,
+                       static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start, d.sub_log2, d.nsys,
+                       d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin);
+  };
+  if (g.col_tile == 4)
+    cols(k_spread_cols<T, P, D, 4>, col_threads<P, 4>());
+  else if (g.col_tile == 6)
+    cols(k_spread_cols<T, P, D, 6>, col_threads<P, 6>());
+  else if (g.col_tile == 8)
+    cols(k_spread_cols<T, P, D, 8>, col_threads<P, 8>());
   else
     hipLaunchKernelGGL((k_spread<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(g.spread_threads), g.lds_spread,
                        st, static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start, d.sub_log2,
@@ -1203,8 +1209,10 @@ hipError_t gather_impl(const DevPlan& d, const PGroup& g, const void* grid, void
 template <class T, int P, int D>
 hipError_t prepare_impl(const PGroup& g) {
   if (g.lds_spread > 64 * 1024) {
-    const void* fn = g.spread_columns ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D>)
-                                      : reinterpret_cast<const void*>(&k_spread<T, P, D>);
+    const void* fn = g.col_tile == 4   ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 4>)
+                     : g.col_tile == 6 ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 6>)
+                     : g.col_tile == 8 ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 8>)
+                                       : reinterpret_cast<const void*>(&k_spread<T, P, D>);
     const hipError_t e =
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(g.lds_spread));
     if (e != hipSuccess) return e;

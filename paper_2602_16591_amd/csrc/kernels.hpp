@@ -87,20 +87,21 @@ struct PGroup {
   int P = 0, D = 0;
   int tile_begin = 0, tile_end = 0;
   int spread_threads = 256, gather_threads = 256;  // workgroup sizes (multiples of 64, <= 1024)
-  bool spread_columns = false;  // spreading by register columns (every tile of edge kColTileHost)
+  int col_tile = 0;  // spreading by register columns when the group's tiles all have this edge (4, 6, 8)
   size_t lds_spread = 0, lds_gather = 0;  // maxima over the group's systems
 };
 
 // Largest workgroup of the particle kernels for window support P (their launch bound).
 inline int particle_max_threads_host(int P) { return P <= 13 ? 1024 : 512; }
 
-// Spreading by columns: tile edge, particles per batch, block edge S, workgroup size and LDS.
-constexpr int kColTileHost = 8;
+// Spreading by columns: tile edges served, particles per batch, block edge S, workgroup size
+// and LDS.
+inline bool col_tile_ok(int B) { return B == 4 || B == 6 || B == 8; }
 constexpr int kColBatchHost = 32;
-inline int col_edge_host(int P) { return kColTileHost + 2 * ((P + 1) / 2) - 1; }
-inline int col_threads_host(int P) { return (col_edge_host(P) * col_edge_host(P) + 63) / 64 * 64; }
-inline size_t col_lds_bytes(int P, int D) {
-  const int S = col_edge_host(P);
+inline int col_edge_host(int P, int B) { return B + 2 * ((P + 1) / 2) - 1; }
+inline int col_threads_host(int P, int B) { return (col_edge_host(P, B) * col_edge_host(P, B) + 63) / 64 * 64; }
+inline size_t col_lds_bytes(int P, int D, int B) {
+  const int S = col_edge_host(P, B);
   return sizeof(double) * (static_cast<size_t>(P) * coef_stride(D) + kColBatchHost * (3 * S + 4)) +
          sizeof(int) * kColBatchHost * 4;
 }
