@@ -5,9 +5,11 @@ Usage: python -m paper_2602_16591_amd.build   (or call build()).
 from __future__ import annotations
 
 import os
+import re
 import shutil
 import subprocess
 import sys
+import tempfile
 import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -18,6 +20,20 @@ LIB = os.path.join(OUT_DIR, "libpswfe.so")
 ARCH = os.environ.get("PSWFE_ARCH", "gfx950")
 
 SOURCES = ["host.cpp", "kernels.hip", "capi.hip"]
+# particles.hip is compiled once per (precision, P range) listed in kernels.hpp
+PARTICLE_SOURCE = "particles.hip"
+
+
+def particle_instances() -> list[tuple[int, int, int]]:
+    """(prec, lo, hi) of every particle-kernel instance, from PSWFE_PARTICLE_INSTANCES."""
+    with open(os.path.join(CSRC, "kernels.hpp")) as f:
+        text = f.read()
+    body = text.split("#define PSWFE_PARTICLE_INSTANCES(X)", 1)[1].split("\n\n", 1)[0]
+    inst = [tuple(int(v) for v in t) for t in re.findall(r"X\((\d+), (\d+), (\d+)\)", body)]
+    if not inst:
+        raise RuntimeError("no particle-kernel instances found in kernels.hpp")
+    return inst
+
 
 HIP_FLAGS = [
     "-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",
@@ -34,31 +50,55 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = True, jobs: int = 3) -> str:
+def build(verbose: bool = True, jobs: int | None = None) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     cc = hipcc()
-    objs, procs = [], []
+    jobs = jobs or max(1, min(16, os.cpu_count() or 1))
+    units = [(src, os.path.splitext(src)[0] + ".o", []) for src in SOURCES]
+    for prec, lo, hi in particle_instances():
+        units.append((PARTICLE_SOURCE, f"particles_{prec}_{lo}.o",
+                      [f"-DPSWFE_PREC={prec}", f"-DPSWFE_PLO={lo}", f"-DPSWFE_PHI={hi}"]))
+    # longest compiles first
+    units.sort(key=lambda u: 0 if u[0] == PARTICLE_SOURCE else 1)
+    objs, running, failed = [], [], []
     t0 = time.time()
-    for src in SOURCES:
-        obj = os.path.join(OUT_DIR, os.path.splitext(src)[0] + ".o")
+
+    def reap(block: bool) -> None:
+        for item in list(running):
+            name, proc, log = item
+            if block or proc.poll() is not None:
+                proc.wait()
+                running.remove(item)
+                log.seek(0)
+                msg = log.read().decode(errors="replace").strip()
+                log.close()
+                if proc.returncode != 0:
+                    failed.append((name, msg))
+                elif verbose and msg:
+                    print(msg)
+                if block:
+                    return
+
+    for src, obj_name, defs in units:
+        obj = os.path.join(OUT_DIR, obj_name)
         lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "c++"]
-        cmd = [cc, *HIP_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj,
+        cmd = [cc, *HIP_FLAGS, *defs, *lang, "-c", os.path.join(CSRC, src), "-o", obj,
                f"-I{os.path.join(ROOT, 'include')}"]
         if src.endswith(".cpp"):
             cmd = [c for c in cmd if not c.startswith("--offload-arch")]
-        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        while len(running) >= jobs:
+            reap(block=False)
+            if len(running) >= jobs:
+                time.sleep(0.2)
+        log = tempfile.TemporaryFile()   # compiler output, read when the job ends
+        running.append((obj_name, subprocess.Popen(cmd, stdout=log, stderr=subprocess.STDOUT), log))
         objs.append(obj)
-        if len([p for _, p in procs if p.poll() is None]) >= jobs:
-            procs[0][1].wait()
-    for src, p in procs:
-        out, _ = p.communicate()
-        if p.returncode != 0:
-            sys.stderr.write(out.decode(errors="replace"))
-            raise RuntimeError(f"compiling {src} failed")
-        if verbose and out:
-            msg = out.decode(errors="replace").strip()
-            if msg:
-                print(msg)
+    while running:
+        reap(block=True)
+    if failed:
+        for name, msg in failed:
+            sys.stderr.write(f"--- {name}\n{msg}\n")
+        raise RuntimeError("compiling " + ", ".join(n for n, _ in failed) + " failed")
     tmp = LIB + ".tmp"
     cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     subprocess.run(cmd, check=True)

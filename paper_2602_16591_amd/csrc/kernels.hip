@@ -3,7 +3,7 @@
 // interpolation of potentials and gradients with the energy reduction (step 5, eq. force).
 // Each kernel covers every system of a batch in one launch: a workgroup (or, in binning, a
 // thread) looks up its system in a prefix table of the global index space it runs over.
-#include "kernels.hpp"
+#include "device_common.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -12,82 +12,6 @@
 
 namespace pswfe {
 namespace {
-
-template <class T> struct Vec4;
-template <> struct Vec4<float> { using type = float4; };
-template <> struct Vec4<double> { using type = double4; };
-template <class T> struct Cplx;
-template <> struct Cplx<float> { using type = float2; };
-template <> struct Cplx<double> { using type = double2; };
-
-template <class C> __device__ __forceinline__ C cmul(C a, C b) {
-  C r;
-  r.x = a.x * b.x - a.y * b.y;
-  r.y = a.x * b.y + a.y * b.x;
-  return r;
-}
-template <class C> __device__ __forceinline__ C cadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
-template <class C> __device__ __forceinline__ C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
-template <class C> __device__ __forceinline__ C cconj(C a) { C r; r.x = a.x; r.y = -a.y; return r; }
-
-__device__ __forceinline__ void atomic_add_global(float* p, float v) { unsafeAtomicAdd(p, v); }
-__device__ __forceinline__ void atomic_add_global(double* p, double v) { unsafeAtomicAdd(p, v); }
-
-// System owning global item i: the largest s < nsys with prefix[s] <= i (prefix is
-// non-decreasing with prefix[0] = 0; an empty system repeats its successor's start and is
-// skipped).
-template <class I>
-__device__ __forceinline__ int find_sys(const I* __restrict__ prefix, int nsys, I i) {
-  int lo = 0, hi = nsys - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (prefix[mid] <= i)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
-
-// Cell coordinates (each < m <= 512) packed into 10-bit fields.
-__device__ __forceinline__ int pack_cell(int cx, int cy, int cz) { return cx | (cy << 10) | (cz << 20); }
-__device__ __forceinline__ int cell_x(int c) { return c & 1023; }
-__device__ __forceinline__ int cell_y(int c) { return (c >> 10) & 1023; }
-__device__ __forceinline__ int cell_z(int c) { return c >> 20; }
-
-// Grid coordinate of x: cell c in [0, m) and fractional offset f with x/h = c + f (mod m).
-// The product x * (1/h) uses 1/h split into two words (ih_hi + ih_lo) and the exact product
-// error from an FMA, so f keeps the working precision's relative accuracy instead of losing
-// log2(m) bits to the integer part. Non-finite inputs map to cell 0 so every index derived
-// from the result stays inside the grid. Contraction is off here: fusing the rounded product
-// p into (p - floor(p)) would count its rounding error twice.
-template <class T>
-__device__ __forceinline__ int grid_coord(T x, T ih_hi, T ih_lo, T L, int m, T& f) {
-#pragma clang fp contract(off)
-  T xr = x;
-  if (!(xr >= T(0) && xr < L)) {
-    xr = x - L * floor(x / L);
-    if (!(xr >= T(0) && xr < L)) xr = T(0);
-  }
-  const T p = xr * ih_hi;
-  const T lo = fma(xr, ih_lo, fma(xr, ih_hi, -p));
-  const T fl = floor(p);
-  int c = static_cast<int>(fl);
-  T fr = (p - fl) + lo;
-  if (fr < T(0)) {
-    fr += T(1);
-    c -= 1;
-  } else if (fr >= T(1)) {
-    fr -= T(1);
-    c += 1;
-  }
-  if (c < 0) c += m;
-  if (c >= m) c -= m;
-  if (!(fr >= T(0) && fr <= T(1))) fr = T(0);
-  f = fr;
-  return c;
-}
-
 // ------------------------------------------------------------------------------------
 // Binning: particles are grouped by tiles of B^3 grid cells (counting sort over the global
 // tile index of the batch, each tile split into sub-buckets). Packed particle i belongs to the system whose range
@@ -182,500 +106,6 @@ __global__ void k_bin_scatter(int64_t n, int nsys, const SysDesc* __restrict__ s
   sorted[dst] = r;
   cells[dst] = pack_cell(cx, cy, cz);
   perm[dst] = static_cast<int>(i);
-}
-
-// ------------------------------------------------------------------------------------
-// Window evaluation. For a particle at x/h = c + f (cell c, 0 <= f < 1) the support is the
-// P consecutive points starting at floor(c + f - P/2) + 1; point j sits at offset
-// u_j = g + (P-1)/2 - j with g in [-1/2, 1/2), and its window value phi_1(2 u_j / P) is the
-// polynomial `coef[j]` evaluated at g (Horner). `o` is the support start relative to the
-// tile origin T0 + 1 - ceil(P/2).
-// ------------------------------------------------------------------------------------
-template <class T, int P>
-__device__ __forceinline__ T centred_offset(T f, int c, int T0, int& o) {
-  if constexpr (P % 2 == 0) {
-    o = c - T0;
-    return f - T(0.5);
-  } else {
-    const int hh = f >= T(0.5) ? 1 : 0;
-    o = c - T0 + hh;
-    return f - static_cast<T>(hh);
-  }
-}
-
-// Periodic image of a grid index a in [-m, 3m) (the range of every halo index: a tile origin
-// is below m, tile edge and half support are at most m).
-__device__ __forceinline__ int fold_index(int a, int m) {
-  a += a < 0 ? m : 0;
-  a -= a >= m ? m : 0;
-  a -= a >= m ? m : 0;
-  return a;
-}
-
-// Walks the S^3 points of a tile's LDS block (x fastest) with a stride of one workgroup:
-// load(k, lds_index, grid_index) for up to K points per thread, then use(...)
-// for the same points, so K independent memory accesses are in flight before their results
-// are needed. The (x, y, z) offsets advance by the stride's digits instead of being divided
-// out of the flat index.
-template <int K, class Load, class Use>
-__device__ __forceinline__ void walk_tile(int S, int m, int Ox, int Oy, int Oz, Load&& load, Use&& use) {
-  const int S2 = S * S, S3 = S2 * S;
-  const int nt = blockDim.x;
-  const int sz = nt / S2, sy = (nt - sz * S2) / S, sx = nt - sz * S2 - sy * S;
-  const int t = threadIdx.x;
-  int iz = t / S2, iy = (t - iz * S2) / S, ix = t - iz * S2 - iy * S;
-  for (int base = t; base < S3; base += nt * K) {
-    int li[K];
-    int64_t gi[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      li[k] = base + nt * k;
-      gi[k] = (static_cast<int64_t>(fold_index(Oz + iz, m)) * m + fold_index(Oy + iy, m)) * m + fold_index(Ox + ix, m);
-      ix += sx;
-      if (ix >= S) {
-        ix -= S;
-        ++iy;
-      }
-      iy += sy;
-      if (iy >= S) {
-        iy -= S;
-        ++iz;
-      }
-      iz += sz;
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (li[k] < S3) load(k, li[k], gi[k]);
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (li[k] < S3) use(k, li[k], gi[k]);
-  }
-}
-
-// ------------------------------------------------------------------------------------
-// Particle kernels, one launch per (window support P, degree bucket D) over the tiles of the
-// systems in that group. A workgroup (4 waves) owns one tile of B^3 cells of one system and an
-// LDS copy of the S^3 grid points its particles' supports touch (S = B + 2 ceil(P/2) - 1).
-// Each wave works on 4 particles at a time, 16 lanes per particle:
-//  * lane j evaluates window piece j for the three coordinates at once (3 independent Horner
-//    chains, 6 with derivatives; pieces j and j + 16 when P > 16), the coefficients of piece j
-//    read from an LDS copy into registers, and writes the values to a per-slot LDS record;
-//  * the 16 lanes then share the P^2 (y, z) lines of the support, each lane running the
-//    x-direction of its lines. Lanes of a particle touch distinct lines (stride S), so their
-//    LDS accesses do not conflict, and no workgroup barrier is needed between particles.
-// Window values, products and sums are float64 in both precisions: on MI355X a float64 FMA
-// issues at the non-packed float32 rate, and float32 window values and products lose ~1e-6
-// relative on systems of neutral molecules, where the grid values are small sums of larger
-// terms of both signs.
-// ------------------------------------------------------------------------------------
-constexpr int kLanesPerParticle = 16;
-
-// Workgroups of the particle kernels have 256, 512 or 1024 threads (4 particle slots per
-// wave); 1024 only where the kernel fits in 128 VGPRs (P <= 13), so that 16 waves can share
-// one compute unit's LDS tile.
-template <int P>
-constexpr int particle_max_threads() { return P <= 13 ? 1024 : 512; }
-
-// Per-wave ordering of LDS accesses between lanes (the record written by one lane is read by
-// other lanes of the same wave).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Copies the window coefficients (P pieces of deg + 1 powers, float64) into LDS rows of
-// coef_stride(D) doubles, zero above deg.
-template <int P, int D>
-__device__ __forceinline__ void stage_coefficients(const double* __restrict__ coef, int deg, double* lcoef) {
-  constexpr int CS = coef_stride(D);
-  for (int i = threadIdx.x; i < P * CS; i += blockDim.x) {
-    const int j = i / CS, k = i - j * CS;
-    lcoef[i] = k <= deg ? coef[j * (deg + 1) + k] : 0.0;
-  }
-}
-
-// Spreading (Alg. 2 step 1): the tile accumulates q w_x w_y w_z over the supports with LDS
-// float64 atomic adds (on gfx950 about 20x the throughput of float32 LDS atomics), then adds
-// the tile into its system's float64 HBM grid with atomics (a point lies in the halos of up
-// to ceil(S/B)^3 tiles; their partial sums are larger than the total on systems of neutral
-// molecules, so they are added in float64 and rounded once, by the first FFT pass).
-// A lane reads the weights of up to kLineChunk lines and the x-window into registers before
-// issuing their atomics: LDS operations complete in order, so an LDS read between atomics
-// would wait for all of them.
-constexpr int kLineChunk = 12;
-
-template <class T, int P, int D>
-__global__ __launch_bounds__(particle_max_threads<P>()) void k_spread(const typename Vec4<T>::type* __restrict__ sorted,
-                                                const int* __restrict__ cells, const int* __restrict__ tile_start,
-                                                int sub_log2, int nsys, const SysDesc* __restrict__ sys,
-                                                const int* __restrict__ tile_prefix, const int* __restrict__ tile_sys,
-                                                int tile_offset) {
-  constexpr int REC = 3 * P;  // window values of one particle: x, y, z
-  constexpr int CS = coef_stride(D);
-  constexpr int NL = (P * P + kLanesPerParticle - 1) / kLanesPerParticle;  // lines per lane
-  extern __shared__ unsigned char smem_raw[];
-  const int gtile = tile_offset + static_cast<int>(blockIdx.x);
-  const int p0 = tile_start[gtile << sub_log2], p1 = tile_start[(gtile + 1) << sub_log2];
-  if (p0 == p1) return;
-  const SysDesc& sd = sys[tile_sys[find_sys(tile_prefix, nsys, gtile)]];
-  const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S;
-  double* __restrict__ grid = sd.grid_a;
-  double* acc = reinterpret_cast<double*>(smem_raw);
-  const int S3 = S * S * S;
-  const int nslots = blockDim.x / kLanesPerParticle;
-  double* recs = acc + S3;                           // nslots * REC
-  double* lcoef = recs + nslots * REC;               // P * CS
-  const int tile = gtile - sd.tile_base;
-  const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
-  const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
-  stage_coefficients<P, D>(sd.coef, sd.deg, lcoef);
-  for (int i = threadIdx.x; i < S3; i += blockDim.x) acc[i] = 0.0;
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int slot = threadIdx.x >> 4;
-  const int li = lane & (kLanesPerParticle - 1);
-  double* rec = recs + slot * REC;
-  const int nt = p1 - p0;
-  // the record of the next round is loaded while this round's particle is spread
-  auto r_next = sorted[min(p0 + slot, p1 - 1)];
-  int c_next = cells[min(p0 + slot, p1 - 1)];
-  for (int base = 0; base < nt; base += nslots) {
-    const int pi = p0 + base + slot;
-    const bool active = pi < p1;
-    const auto r = r_next;
-    const int cp = c_next;
-    r_next = sorted[min(pi + nslots, p1 - 1)];
-    c_next = cells[min(pi + nslots, p1 - 1)];
-    int o[3];
-    double g[3];
-    g[0] = static_cast<double>(centred_offset<T, P>(r.x, cell_x(cp), T0x, o[0]));
-    g[1] = static_cast<double>(centred_offset<T, P>(r.y, cell_y(cp), T0y, o[1]));
-    g[2] = static_cast<double>(centred_offset<T, P>(r.z, cell_z(cp), T0z, o[2]));
-#pragma unroll
-    for (int jj = 0; jj < (P + kLanesPerParticle - 1) / kLanesPerParticle; ++jj) {
-      const int j = li + kLanesPerParticle * jj;
-      if (j >= P) break;
-      double c[D + 1];
-#pragma unroll
-      for (int k = 0; k <= D; ++k) c[k] = lcoef[j * CS + k];
-      double vx = c[D], vy = c[D], vz = c[D];
-#pragma unroll
-      for (int k = D - 1; k >= 0; --k) {
-        vx = fma(vx, g[0], c[k]);
-        vy = fma(vy, g[1], c[k]);
-        vz = fma(vz, g[2], c[k]);
-      }
-      rec[j] = vx;
-      rec[P + j] = vy;
-      rec[2 * P + j] = vz;
-    }
-    wave_lds_sync();
-    if (active) {
-      const double q = static_cast<double>(r.w);
-      double wx[P];
-#pragma unroll
-      for (int j = 0; j < P; ++j) wx[j] = rec[j];
-#pragma unroll
-      for (int t0 = 0; t0 < NL; t0 += kLineChunk) {
-        double wl[kLineChunk];
-        int off[kLineChunk];
-#pragma unroll
-        for (int t = 0; t < kLineChunk; ++t) {
-          const int e = li + kLanesPerParticle * (t0 + t);
-          const int jz = e / P, jy = e - jz * P;
-          const bool ok = t0 + t < NL && e < P * P;
-          wl[t] = ok ? q * rec[P + jy] * rec[2 * P + jz] : 0.0;
-          off[t] = ok ? ((o[2] + jz) * S + (o[1] + jy)) * S + o[0] : -1;
-        }
-#pragma unroll
-        for (int t = 0; t < kLineChunk; ++t) {
-          if (off[t] >= 0) {
-            double* row = acc + off[t];
-#pragma unroll
-            for (int jx = 0; jx < P; ++jx) atomicAdd(row + jx, wl[t] * wx[jx]);
-          }
-        }
-      }
-    }
-    wave_lds_sync();
-  }
-  __syncthreads();
-  const int half = (P + 1) / 2;
-  const int Ox = T0x + 1 - half, Oy = T0y + 1 - half, Oz = T0z + 1 - half;
-  double v[8];
-  walk_tile<8>(
-      S, m, Ox, Oy, Oz, [&](int k, int li_, int64_t) { v[k] = acc[li_]; },
-      [&](int k, int, int64_t gi) {
-        if (v[k] != 0.0) atomic_add_global(grid + gi, v[k]);
-      });
-}
-
-// Spreading by columns, for tiles of edge B = 4, 6 or 8 (Alg. 2 step 1, same sums as k_spread).
-// Thread (ix, iz) of the S x S face of the tile's block owns the S points of its y-column in
-// registers. Particles are taken kColBatch at a time: their window values are written to LDS
-// as S-long arrays per dimension, zero outside the support (Horner runs once per value), and
-// every thread adds q w_x[ix] w_z[iz] w_y[iy] to its S points, skipping particles whose support
-// misses its column. The P^3 products of a particle become register FMAs instead of LDS
-// atomics (on gfx950 a float64 FMA costs far less issue time than a float64 LDS atomic);
-// the block then adds its S^3 points into the float64 grid with global atomics, lanes of
-// consecutive ix writing consecutive addresses.
-constexpr int kColBatch = 32;
-template <int P, int B>
-constexpr int col_edge() { return B + 2 * ((P + 1) / 2) - 1; }
-template <int P, int B>
-constexpr int col_threads() { return (col_edge<P, B>() * col_edge<P, B>() + 63) / 64 * 64; }
-
-template <class T, int P, int D, int B>
-__global__ __launch_bounds__((col_threads<P, B>())) void k_spread_cols(
-    const typename Vec4<T>::type* __restrict__ sorted, const int* __restrict__ cells,
-    const int* __restrict__ tile_start, int sub_log2, int nsys, const SysDesc* __restrict__ sys,
-    const int* __restrict__ tile_prefix, const int* __restrict__ tile_sys, int tile_offset) {
-  constexpr int S = col_edge<P, B>();
-  constexpr int CS = coef_stride(D);
-  constexpr int RS = 3 * S;  // a particle's padded window values: x, y, z
-  extern __shared__ unsigned char smem_raw[];
-  const int gtile = tile_offset + static_cast<int>(blockIdx.x);
-  const int p0 = tile_start[gtile << sub_log2], p1 = tile_start[(gtile + 1) << sub_log2];
-  if (p0 == p1) return;
-  const SysDesc& sd = sys[tile_sys[find_sys(tile_prefix, nsys, gtile)]];
-  const int m = sd.m, Tn = sd.Tn;
-  double* __restrict__ grid = sd.grid_a;
-  double* lcoef = reinterpret_cast<double*>(smem_raw);  // P * CS
-  double* recs = lcoef + P * CS;                        // kColBatch * RS
-  double* pg = recs + kColBatch * RS;                   // kColBatch * 4: g_x, g_y, g_z, q
-  int* po = reinterpret_cast<int*>(pg + kColBatch * 4); // kColBatch * 4: o_x, o_y, o_z
-  const int tile = gtile - sd.tile_base;
-  const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
-  const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
-  stage_coefficients<P, D>(sd.coef, sd.deg, lcoef);
-  const int t = threadIdx.x;
-  const bool owner = t < S * S;
-  const int iz = t / S, ix = t - (t / S) * S;
-  double acc[S];
-#pragma unroll
-  for (int k = 0; k < S; ++k) acc[k] = 0.0;
-  // the records of the next batch are loaded while this batch is accumulated
-  auto r_next = sorted[min(p0 + t, p1 - 1)];
-  int c_next = cells[min(p0 + t, p1 - 1)];
-  for (int b0 = p0; b0 < p1; b0 += kColBatch) {
-    const int nb = min(kColBatch, p1 - b0);
-    const auto r = r_next;
-    const int cp = c_next;
-    if (t < kColBatch) {
-      r_next = sorted[min(b0 + kColBatch + t, p1 - 1)];
-      c_next = cells[min(b0 + kColBatch + t, p1 - 1)];
-    }
-    if (t < nb) {
-      int o0, o1, o2;
-      pg[4 * t + 0] = static_cast<double>(centred_offset<T, P>(r.x, cell_x(cp), T0x, o0));
-      pg[4 * t + 1] = static_cast<double>(centred_offset<T, P>(r.y, cell_y(cp), T0y, o1));
-      pg[4 * t + 2] = static_cast<double>(centred_offset<T, P>(r.z, cell_z(cp), T0z, o2));
-      pg[4 * t + 3] = static_cast<double>(r.w);
-      po[4 * t + 0] = o0;
-      po[4 * t + 1] = o1;
-      po[4 * t + 2] = o2;
-    }
-    __syncthreads();
-    for (int e = t; e < nb * RS; e += blockDim.x) {
-      const int k = e / RS, rr = e - k * RS, d = rr / S, i = rr - d * S;
-      const int j = i - po[4 * k + d];
-      double v = 0.0;
-      if (j >= 0 && j < P) {
-        const double g = pg[4 * k + d];
-        const double* c = lcoef + j * CS;
-        v = c[D];
-#pragma unroll
-        for (int kk = D - 1; kk >= 0; --kk) v = fma(v, g, c[kk]);
-      }
-      recs[e] = v;
-    }
-    __syncthreads();
-    if (owner) {
-      for (int k = 0; k < nb; ++k) {
-        const double* R = recs + k * RS;
-        const double tq = pg[4 * k + 3] * R[ix] * R[2 * S + iz];
-        if (tq != 0.0) {
-#pragma unroll
-          for (int iy = 0; iy < S; ++iy) acc[iy] = fma(tq, R[S + iy], acc[iy]);
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if (owner) {
-    constexpr int half = (P + 1) / 2;
-    const int gx = fold_index(T0x + 1 - half + ix, m);
-    const int64_t gz = fold_index(T0z + 1 - half + iz, m);
-#pragma unroll
-    for (int iy = 0; iy < S; ++iy) {
-      if (acc[iy] != 0.0) {
-        const int gy = fold_index(T0y + 1 - half + iy, m);
-        atomic_add_global(grid + (gz * m + gy) * m + gx, acc[iy]);
-      }
-    }
-  }
-}
-
-// Interpolation (Alg. 2 step 5 and eq. force): phi = sum b w_x w_y w_z and its gradient as
-// nested sums: each lane runs the x-sums of its lines for the value and the x-derivative,
-// weights them with the y/z windows and derivatives, and the 16 lanes of a particle reduce.
-// grid_override (single system) replaces the system's grid_b; energy holds one double per
-// system.
-template <class T, int P, int D>
-__global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const typename Vec4<T>::type* __restrict__ sorted,
-                                                const int* __restrict__ cells, const int* __restrict__ perm,
-                                                const int* __restrict__ tile_start, int sub_log2, int nsys,
-                                                const SysDesc* __restrict__ sys, const int* __restrict__ tile_prefix,
-                                                const int* __restrict__ tile_sys, int tile_offset,
-                                                const T* __restrict__ grid_override, T* __restrict__ phi,
-                                                T* __restrict__ vec, int vec_mode, int add_self,
-                                                double* __restrict__ energy) {
-  constexpr int REC = 6 * P;  // values x, y, z then derivatives x, y, z (d/dg)
-  constexpr int CS = coef_stride(D);
-  extern __shared__ unsigned char smem_raw[];
-  __shared__ double s_red[16];
-  const int gtile = tile_offset + static_cast<int>(blockIdx.x);
-  const int p0 = tile_start[gtile << sub_log2], p1 = tile_start[(gtile + 1) << sub_log2];
-  if (p0 == p1) return;
-  const int s = tile_sys[find_sys(tile_prefix, nsys, gtile)];
-  const SysDesc& sd = sys[s];
-  const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S;
-  const T* __restrict__ grid = grid_override ? grid_override : static_cast<const T*>(sd.grid_b);
-  const double inv_h = sd.inv_h, self_coef = sd.self_coef;
-  const int nslots = blockDim.x / kLanesPerParticle;
-  double* recs = reinterpret_cast<double*>(smem_raw);              // nslots * REC
-  double* lcoef = recs + nslots * REC;                             // P * CS
-  T* tb = reinterpret_cast<T*>(lcoef + P * CS);
-  const int tile = gtile - sd.tile_base;
-  const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
-  const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
-  const int half = (P + 1) / 2;
-  const int Ox = T0x + 1 - half, Oy = T0y + 1 - half, Oz = T0z + 1 - half;
-  stage_coefficients<P, D>(sd.coef, sd.deg, lcoef);
-  {
-    T v[8];
-    walk_tile<8>(
-        S, m, Ox, Oy, Oz, [&](int k, int, int64_t gi) { v[k] = grid[gi]; },
-        [&](int k, int li_, int64_t) { tb[li_] = v[k]; });
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int slot = threadIdx.x >> 4;
-  const int li = lane & (kLanesPerParticle - 1);
-  double* rec = recs + slot * REC;
-  const int nt = p1 - p0;
-  double esum = 0.0;
-  auto r_next = sorted[min(p0 + slot, p1 - 1)];
-  int c_next = cells[min(p0 + slot, p1 - 1)];
-  int i_next = perm[min(p0 + slot, p1 - 1)];
-  for (int base = 0; base < nt; base += nslots) {
-    const int pi = p0 + base + slot;
-    const bool active = pi < p1;
-    const auto r = r_next;
-    const int cp = c_next;
-    const int idx = i_next;
-    r_next = sorted[min(pi + nslots, p1 - 1)];
-    c_next = cells[min(pi + nslots, p1 - 1)];
-    i_next = perm[min(pi + nslots, p1 - 1)];
-    int o[3];
-    double g[3];
-    g[0] = static_cast<double>(centred_offset<T, P>(r.x, cell_x(cp), T0x, o[0]));
-    g[1] = static_cast<double>(centred_offset<T, P>(r.y, cell_y(cp), T0y, o[1]));
-    g[2] = static_cast<double>(centred_offset<T, P>(r.z, cell_z(cp), T0z, o[2]));
-#pragma unroll
-    for (int jj = 0; jj < (P + kLanesPerParticle - 1) / kLanesPerParticle; ++jj) {
-      const int j = li + kLanesPerParticle * jj;
-      if (j >= P) break;
-      double c[D + 1];
-#pragma unroll
-      for (int k = 0; k <= D; ++k) c[k] = lcoef[j * CS + k];
-      double v0 = c[D], v1 = c[D], v2 = c[D], d0 = 0.0, d1 = 0.0, d2 = 0.0;
-#pragma unroll
-      for (int k = D - 1; k >= 0; --k) {
-        d0 = fma(d0, g[0], v0);
-        d1 = fma(d1, g[1], v1);
-        d2 = fma(d2, g[2], v2);
-        v0 = fma(v0, g[0], c[k]);
-        v1 = fma(v1, g[1], c[k]);
-        v2 = fma(v2, g[2], c[k]);
-      }
-      rec[j] = v0;
-      rec[P + j] = v1;
-      rec[2 * P + j] = v2;
-      rec[3 * P + j] = d0;
-      rec[4 * P + j] = d1;
-      rec[5 * P + j] = d2;
-    }
-    wave_lds_sync();
-    double ph = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-    if (active) {
-      double wx[P], dx[P];
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        wx[j] = rec[j];
-        dx[j] = rec[3 * P + j];
-      }
-#pragma unroll 2
-      for (int e = li; e < P * P; e += kLanesPerParticle) {
-        const int jz = e / P, jy = e - jz * P;
-        const T* row = tb + ((o[2] + jz) * S + (o[1] + jy)) * S + o[0];
-        double sx0 = 0.0, sx1 = 0.0, sd0 = 0.0, sd1 = 0.0;
-#pragma unroll
-        for (int jx = 0; jx + 1 < P; jx += 2) {
-          const double b0 = static_cast<double>(row[jx]), b1 = static_cast<double>(row[jx + 1]);
-          sx0 = fma(b0, wx[jx], sx0);
-          sd0 = fma(b0, dx[jx], sd0);
-          sx1 = fma(b1, wx[jx + 1], sx1);
-          sd1 = fma(b1, dx[jx + 1], sd1);
-        }
-        if constexpr (P % 2 == 1) {
-          const double b = static_cast<double>(row[P - 1]);
-          sx0 = fma(b, wx[P - 1], sx0);
-          sd0 = fma(b, dx[P - 1], sd0);
-        }
-        const double sx = sx0 + sx1, sdx = sd0 + sd1;
-        const double wy = rec[P + jy], dy = rec[4 * P + jy], wz = rec[2 * P + jz], dz = rec[5 * P + jz];
-        const double wyz = wy * wz;
-        ph = fma(sx, wyz, ph);
-        gx = fma(sdx, wyz, gx);
-        gy = fma(sx, dy * wz, gy);
-        gz = fma(sx, wy * dz, gz);
-      }
-    }
-#pragma unroll
-    for (int off = kLanesPerParticle / 2; off > 0; off >>= 1) {
-      ph += __shfl_xor(ph, off, kLanesPerParticle);
-      gx += __shfl_xor(gx, off, kLanesPerParticle);
-      gy += __shfl_xor(gy, off, kLanesPerParticle);
-      gz += __shfl_xor(gz, off, kLanesPerParticle);
-    }
-    if (active && li == 0) {
-      const double qd = static_cast<double>(r.w);
-      double phd = ph;
-      if (add_self) phd -= self_coef * qd;
-      if (phi) phi[idx] = static_cast<T>(phd);
-      if (vec) {
-        const double sc = vec_mode == 0 ? -qd * inv_h : inv_h;
-        vec[3 * idx + 0] = static_cast<T>(sc * gx);
-        vec[3 * idx + 1] = static_cast<T>(sc * gy);
-        vec[3 * idx + 2] = static_cast<T>(sc * gz);
-      }
-      esum += qd * phd;
-    }
-    wave_lds_sync();
-  }
-  if (energy) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) esum += __shfl_xor(esum, off, 64);
-    if (lane == 0) s_red[threadIdx.x >> 6] = esum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double tot = 0.0;
-      for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) tot += s_red[w];
-      unsafeAtomicAdd(energy + s, 0.5 * tot);
-    }
-  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -905,6 +335,29 @@ __device__ __forceinline__ void butterfly(const C* __restrict__ in, int NR, C* _
     out[Ls] = cadd(d02, wd13);
     out[2 * Ls] = csub(s02, s13);
     out[3 * Ls] = csub(d02, wd13);
+  } else if constexpr (R == 8) {
+    // y_u = sum_t a_t w^{t u}, w = tw[N/8]: split t into t and t + 4 (w^4 = -1), then two
+    // 4-point DFTs with w^2 = tw[N/4] = +-i: even u from a_t + a_{t+4}, odd u from
+    // (a_t - a_{t+4}) w^t.
+    const C w8 = tw[N / 8], w4 = tw[N / 4];
+    const C w83 = cmul(w8, w4);
+    const C b0 = cadd(a[0], a[4]), b1 = cadd(a[1], a[5]), b2 = cadd(a[2], a[6]), b3 = cadd(a[3], a[7]);
+    const C c0 = csub(a[0], a[4]), c1 = cmul(csub(a[1], a[5]), w8), c2 = cmul(csub(a[2], a[6]), w4),
+            c3 = cmul(csub(a[3], a[7]), w83);
+    {
+      const C s02 = cadd(b0, b2), d02 = csub(b0, b2), s13 = cadd(b1, b3), d13 = cmul(csub(b1, b3), w4);
+      out[0] = cadd(s02, s13);
+      out[4 * Ls] = csub(s02, s13);
+      out[2 * Ls] = cadd(d02, d13);
+      out[6 * Ls] = csub(d02, d13);
+    }
+    {
+      const C s02 = cadd(c0, c2), d02 = csub(c0, c2), s13 = cadd(c1, c3), d13 = cmul(csub(c1, c3), w4);
+      out[Ls] = cadd(s02, s13);
+      out[5 * Ls] = csub(s02, s13);
+      out[3 * Ls] = cadd(d02, d13);
+      out[7 * Ls] = csub(d02, d13);
+    }
   } else {
     C wr[R];
 #pragma unroll
@@ -1175,70 +628,6 @@ hipError_t bin_impl(const DevPlan& d, int64_t n, const void* pos, const void* q,
   return hipGetLastError();
 }
 
-template <class T, int P, int D>
-hipError_t spread_impl(const DevPlan& d, const PGroup& g, hipStream_t st) {
-  auto cols = [&](auto kern, int threads) {
-    hipLaunchKernelGGL(kern, dim3(g.tile_end - g.tile_begin), dim3(threads), g.lds_spread, st,
-                       static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start, d.sub_log2, d.nsys,
-                       d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin);
-  };
-  if (g.col_tile == 4)
-    cols(k_spread_cols<T, P, D, 4>, col_threads<P, 4>());
-  else if (g.col_tile == 6)
-    cols(k_spread_cols<T, P, D, 6>, col_threads<P, 6>());
-  else if (g.col_tile == 8)
-    cols(k_spread_cols<T, P, D, 8>, col_threads<P, 8>());
-  else
-    hipLaunchKernelGGL((k_spread<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(g.spread_threads), g.lds_spread,
-                       st, static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start, d.sub_log2,
-                       d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin);
-  return hipGetLastError();
-}
-
-template <class T, int P, int D>
-hipError_t gather_impl(const DevPlan& d, const PGroup& g, const void* grid, void* phi, void* vec, int vec_mode,
-                       bool add_self, double* energy, hipStream_t st) {
-  hipLaunchKernelGGL((k_gather<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(g.gather_threads), g.lds_gather, st,
-                     static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.perm, d.tile_start, d.sub_log2,
-                     d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin, static_cast<const T*>(grid),
-                     static_cast<T*>(phi), static_cast<T*>(vec), vec_mode, add_self ? 1 : 0, energy);
-  return hipGetLastError();
-}
-
-// Raises the dynamic-LDS limit of the particle kernels of one group where needed.
-template <class T, int P, int D>
-hipError_t prepare_impl(const PGroup& g) {
-  if (g.lds_spread > 64 * 1024) {
-    const void* fn = g.col_tile == 4   ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 4>)
-                     : g.col_tile == 6 ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 6>)
-                     : g.col_tile == 8 ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 8>)
-                                       : reinterpret_cast<const void*>(&k_spread<T, P, D>);
-    const hipError_t e =
-        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(g.lds_spread));
-    if (e != hipSuccess) return e;
-  }
-  if (g.lds_gather > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<T, P, D>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             static_cast<int>(g.lds_gather));
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
-// Calls f.template operator()<P, D>() for the group's (P, D); hipErrorInvalidValue if none.
-template <int P, class F>
-hipError_t with_group(const PGroup& g, F&& f) {
-  if (g.P == P) {
-    if (g.D == 11) return f.template operator()<P, 11>();
-    if (g.D == 17) return f.template operator()<P, 17>();
-    if (g.D == kMaxDeg) return f.template operator()<P, kMaxDeg>();
-    return hipErrorInvalidValue;
-  }
-  if constexpr (P < kPmax) return with_group<P + 1>(g, f);
-  return hipErrorInvalidValue;
-}
-
 template <class T>
 hipError_t transform_impl(const DevPlan& d, const void* in_override, void* out_override, hipStream_t st) {
   stage_begin(d, kStageFftX, st);
@@ -1265,12 +654,31 @@ hipError_t transform_impl(const DevPlan& d, const void* in_override, void* out_o
   return hipGetLastError();
 }
 
+// Particle-kernel instance covering (precision, P).
+struct ParticleFns {
+  int prec, lo, hi;
+  hipError_t (*prepare)(const PGroup&);
+  hipError_t (*spread)(const DevPlan&, const PGroup&, hipStream_t);
+  hipError_t (*gather)(const DevPlan&, const PGroup&, const void*, void*, void*, int, bool, double*, hipStream_t);
+};
+
+#define PSWFE_PARTICLE_ENTRY(prec, lo, hi) \
+  {prec, lo, hi, particles_prepare_##prec##_##lo, particles_spread_##prec##_##lo, particles_gather_##prec##_##lo},
+constexpr ParticleFns kParticleFns[] = {PSWFE_PARTICLE_INSTANCES(PSWFE_PARTICLE_ENTRY)};
+#undef PSWFE_PARTICLE_ENTRY
+
+const ParticleFns* particle_fns(int prec, int P) {
+  for (const ParticleFns& f : kParticleFns)
+    if (f.prec == prec && f.lo <= P && P <= f.hi) return &f;
+  return nullptr;
+}
+
 }  // namespace
 
 hipError_t prepare_kernels(const DevPlan& d) {
   for (const PGroup& g : d.groups) {
-    const hipError_t e = d.prec == 0 ? with_group<kPmin>(g, [&]<int P, int D>() { return prepare_impl<float, P, D>(g); })
-                                     : with_group<kPmin>(g, [&]<int P, int D>() { return prepare_impl<double, P, D>(g); });
+    const ParticleFns* f = particle_fns(d.prec, g.P);
+    const hipError_t e = f ? f->prepare(g) : hipErrorInvalidValue;
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1286,8 +694,8 @@ hipError_t launch_spread(const DevPlan& d, hipStream_t st) {
   hipError_t e = hipSuccess;
   stage_begin(d, kStageSpread, st);
   for (const PGroup& g : d.groups) {
-    e = d.prec == 0 ? with_group<kPmin>(g, [&]<int P, int D>() { return spread_impl<float, P, D>(d, g, st); })
-                    : with_group<kPmin>(g, [&]<int P, int D>() { return spread_impl<double, P, D>(d, g, st); });
+    const ParticleFns* f = particle_fns(d.prec, g.P);
+    e = f ? f->spread(d, g, st) : hipErrorInvalidValue;
     if (e != hipSuccess) break;
   }
   stage_end(d, kStageSpread, st);
@@ -1343,15 +751,8 @@ hipError_t launch_gather(const DevPlan& d, const void* grid_override, void* phi,
   hipError_t e = hipSuccess;
   stage_begin(d, kStageGather, st);
   for (const PGroup& g : d.groups) {
-    e = d.prec == 0 ? with_group<kPmin>(g,
-                                        [&]<int P, int D>() {
-                                          return gather_impl<float, P, D>(d, g, grid_override, phi, vec, vec_mode,
-                                                                          add_self, energy, st);
-                                        })
-                    : with_group<kPmin>(g, [&]<int P, int D>() {
-                        return gather_impl<double, P, D>(d, g, grid_override, phi, vec, vec_mode, add_self, energy,
-                                                         st);
-                      });
+    const ParticleFns* f = particle_fns(d.prec, g.P);
+    e = f ? f->gather(d, g, grid_override, phi, vec, vec_mode, add_self, energy, st) : hipErrorInvalidValue;
     if (e != hipSuccess) break;
   }
   stage_end(d, kStageGather, st);

@@ -155,6 +155,23 @@ inline void stage_end(const DevPlan& d, int stage, hipStream_t st) {
   }
 }
 
+// The particle kernels (spreading, interpolation) are compiled from one source once per
+// precision (0 float, 1 double) and range [lo, hi] of window supports P, so that their many
+// template instances build in parallel. Each instance defines the three functions below with
+// the suffix _<prec>_<lo>; the ranges cover [kPmin, kPmax] without overlap.
+#define PSWFE_PARTICLE_INSTANCES(X) \
+  X(0, 3, 8) X(0, 9, 12) X(0, 13, 16) X(0, 17, 20) X(0, 21, 24) \
+  X(1, 3, 8) X(1, 9, 12) X(1, 13, 16) X(1, 17, 20) X(1, 21, 24)
+
+#define PSWFE_PARTICLE_DECLARE(prec, lo, hi)                                                              \
+  hipError_t particles_prepare_##prec##_##lo(const PGroup& g);                                            \
+  hipError_t particles_spread_##prec##_##lo(const DevPlan& d, const PGroup& g, hipStream_t st);           \
+  hipError_t particles_gather_##prec##_##lo(const DevPlan& d, const PGroup& g, const void* grid, void* phi, \
+                                            void* vec, int vec_mode, bool add_self, double* energy,       \
+                                            hipStream_t st);
+PSWFE_PARTICLE_INSTANCES(PSWFE_PARTICLE_DECLARE)
+#undef PSWFE_PARTICLE_DECLARE
+
 // One-time kernel attributes (dynamic LDS above 64 KiB); call at plan creation.
 hipError_t prepare_kernels(const DevPlan& d);
 
