@@ -61,12 +61,14 @@ STAGE_KERNEL = {"spread": ("k_spread", "k_spread_cols"), "gather": ("k_gather",)
                 "fft_y": ("k_fft_cols",), "fft_z_scale": ("k_fft_cols",), "ifft_y": ("k_fft_cols",),
                 "ifft_x": ("k_fft_x_c2r",), "bin": ("k_bin_count",)}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_water_box_n30000.md")
+# the device code whose counters the traffic file holds; any change voids them
+KERNEL_SOURCES = ("kernels.hip", "kernels.hpp", "particles.hip", "device_common.hpp")
 
 
 def kernel_source_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.hpp"):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2602_16591_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
