@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace pswfe {
@@ -28,8 +30,50 @@ template <class C> __device__ __forceinline__ C cadd(C a, C b) { C r; r.x = a.x 
 template <class C> __device__ __forceinline__ C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
 template <class C> __device__ __forceinline__ C cconj(C a) { C r; r.x = a.x; r.y = -a.y; return r; }
 
-__device__ __forceinline__ void atomic_add_global(float* p, float v) { unsafeAtomicAdd(p, v); }
-__device__ __forceinline__ void atomic_add_global(double* p, double v) { unsafeAtomicAdd(p, v); }
+// Global-address-space view of a device pointer taken from a descriptor: loads through it
+// compile to global_load (the compiler cannot infer the address space of a pointer read from
+// memory, and flat loads also count against the LDS wait counter).
+template <class T>
+using global_ptr = const __attribute__((address_space(1))) T*;
+template <class T>
+using global_mut_ptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ global_ptr<T> as_global(const T* p) {
+  return (global_ptr<T>)p;
+}
+template <class T>
+__device__ __forceinline__ global_mut_ptr<T> as_global_mut(T* p) {
+  return (global_mut_ptr<T>)p;
+}
+
+// Loads and stores of two-element vectors (float2, double2) in global memory through the
+// compiler's native vector type (the HIP vector classes cannot be accessed through a
+// global-address-space pointer).
+template <class V>
+__device__ __forceinline__ V gload(const V* p) {
+  using E = std::remove_cv_t<std::remove_reference_t<decltype(V{}.x)>>;
+  typedef E N __attribute__((ext_vector_type(2)));
+  const N n = *((const __attribute__((address_space(1))) N*)p);
+  return V{n.x, n.y};
+}
+template <class V>
+__device__ __forceinline__ void gstore(V* p, const V& v) {
+  using E = std::remove_cv_t<std::remove_reference_t<decltype(V{}.x)>>;
+  typedef E N __attribute__((ext_vector_type(2)));
+  N n;
+  n.x = v.x;
+  n.y = v.y;
+  *((__attribute__((address_space(1))) N*)p) = n;
+}
+
+// Atomic adds into device (HBM) memory; the result is not used, so the non-returning global
+// form is emitted.
+__device__ __forceinline__ void atomic_add_global(float* p, float v) {
+  (void)__builtin_amdgcn_global_atomic_fadd_f32((__attribute__((address_space(1))) float*)p, v);
+}
+__device__ __forceinline__ void atomic_add_global(double* p, double v) {
+  (void)__builtin_amdgcn_global_atomic_fadd_f64((__attribute__((address_space(1))) double*)p, v);
+}
 
 // System owning global item i: the largest s < nsys with prefix[s] <= i (prefix is
 // non-decreasing with prefix[0] = 0; an empty system repeats its successor's start and is

@@ -191,8 +191,9 @@ __global__ __launch_bounds__(kLocalThreads) void k_local(int nsys, const SysDesc
   const int nc = sd.nc;
   const double L = sd.L, inv_L = 1.0 / sd.L, rc2 = sd.rc * sd.rc, inv_rc2 = 1.0 / rc2, K = sd.lK;
   double cr[kLocalDeg + 1];
+  const global_ptr<double> lcoef = as_global(sd.lcoef);
 #pragma unroll
-  for (int k = 0; k <= kLocalDeg; ++k) cr[k] = k <= sd.ldeg ? sd.lcoef[k] : 0.0;
+  for (int k = 0; k <= kLocalDeg; ++k) cr[k] = k <= sd.ldeg ? lcoef[k] : 0.0;
   const int tid = threadIdx.x;
   // source ranges: the 27 neighbour cells (distinct, as nc >= 3), or the system's one cell
   if (tid < 27) {
@@ -378,7 +379,7 @@ __device__ __forceinline__ void butterfly(const C* __restrict__ in, int NR, C* _
 
 // Runs all stages; returns the buffer that holds the result (A or Bf).
 template <class C>
-__device__ C* fft_lds(C* A, C* Bf, int nseq, int ss, const FftPlan& pl, const C* __restrict__ tw) {
+__device__ __forceinline__ C* fft_lds(C* A, C* Bf, int nseq, int ss, const FftPlan& pl, const C* __restrict__ tw) {
   const int N = pl.N;
   int Ls = 1;
   C* src = A;
@@ -450,19 +451,19 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(int nsys, const SysDesc* __re
   const int nr = min(rpb, nrows - row0);
   for (int e = threadIdx.x; e < 2 * N + 1; e += blockDim.x) {
     if (e < N)
-      tw_h[e] = tw_half[e];
+      tw_h[e] = gload(tw_half + e);
     else
-      tw_f[e - N] = tw_full[e - N];
+      tw_f[e - N] = gload(tw_full + (e - N));
   }
   using CI = typename Cplx<TI>::type;  // a pair (a_2j, a_2j+1) of the input row, one vector load
   const TI* grid = in_override ? in_override : reinterpret_cast<const TI*>(sd.grid_a);
   const CI* src = reinterpret_cast<const CI*>(grid + static_cast<int64_t>(row0) * m);
   staged_copy<8>(
-      nr * N, [&](int e) { return src[e]; },
+      nr * N, [&](int e) { return gload(src + e); },
       [&](int e, CI v) { A[e] = C{static_cast<T>(v.x), static_cast<T>(v.y)}; });
   if (zero_input) {
     CI* zsrc = const_cast<CI*>(src);
-    for (int e = threadIdx.x; e < nr * N; e += blockDim.x) zsrc[e] = CI{TI(0), TI(0)};
+    for (int e = threadIdx.x; e < nr * N; e += blockDim.x) gstore(zsrc + e, CI{TI(0), TI(0)});
   }
   __syncthreads();
   const C* Z = fft_lds(A, Bf, nr, N, sd.fh, tw_h);
@@ -475,7 +476,7 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(int nsys, const SysDesc* __re
     const C dd = csub(zk, zn);
     const C od = C{T(0.5) * dd.y, T(-0.5) * dd.x};  // (zk - zn) / (2i)
     const C w = tw_f[k];
-    out[e] = cadd(ev, cmul(w, od));
+    gstore(out + e, cadd(ev, cmul(w, od)));
   }
 }
 
@@ -499,13 +500,13 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(int nsys, const SysDesc* __re
   const int nr = min(rpb, nrows - row0);
   for (int e = threadIdx.x; e < 2 * N; e += blockDim.x) {
     if (e < N)
-      tw_h[e] = tw_half[e];
+      tw_h[e] = gload(tw_half + e);
     else
-      tw_f[e - N] = tw_full[e - N];
+      tw_f[e - N] = gload(tw_full + (e - N));
   }
   const C* in = static_cast<const C*>(sd.spec) + static_cast<int64_t>(row0) * (N + 1);
   staged_copy<8>(
-      nr * (N + 1), [&](int e) { return in[e]; }, [&](int e, C v) { A[e] = v; });
+      nr * (N + 1), [&](int e) { return gload(in + e); }, [&](int e, C v) { A[e] = v; });
   __syncthreads();
   for (int e = threadIdx.x; e < nr * N; e += blockDim.x) {
     const int r = e / N, k = e - r * N;
@@ -519,7 +520,7 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(int nsys, const SysDesc* __re
   const C* Z = fft_lds(Bf, A, nr, N, sd.fh, tw_h);
   T* grid = out_override ? out_override : static_cast<T*>(sd.grid_b);
   C* dst = reinterpret_cast<C*>(grid + static_cast<int64_t>(row0) * m);
-  for (int e = threadIdx.x; e < nr * N; e += blockDim.x) dst[e] = Z[e];
+  for (int e = threadIdx.x; e < nr * N; e += blockDim.x) gstore(dst + e, Z[e]);
 }
 
 // FFT along y or z of each system's half spectrum. A system's blocks are (outer, column
@@ -553,9 +554,9 @@ __global__ __launch_bounds__(256) void k_fft_cols(int nsys, const SysDesc* __res
     const C* __restrict__ gm = static_cast<const C*>(sd.twfm);
     for (int e = threadIdx.x; e < 2 * m; e += blockDim.x) {
       if (e < m)
-        tw_p[e] = gp[e];
+        tw_p[e] = gload(gp + e);
       else
-        tw_m[e - m] = gm[e - m];
+        tw_m[e - m] = gload(gm + (e - m));
     }
   }
   const C* tw = mode == 2 ? tw_m : tw_p;
@@ -564,7 +565,7 @@ __global__ __launch_bounds__(256) void k_fft_cols(int nsys, const SysDesc* __res
       nc * m,
       [&](int i) {
         const int e = i / nc, c = i - e * nc;
-        return base[e * estride + c];
+        return gload(base + e * estride + c);
       },
       [&](int i, C v) {
         const int e = i / nc, c = i - e * nc;
@@ -573,8 +574,8 @@ __global__ __launch_bounds__(256) void k_fft_cols(int nsys, const SysDesc* __res
   __syncthreads();
   C* R1 = fft_lds(A, Bf, nc, ss, sd.ff, tw);
   if (mode == 1) {
-    const T* __restrict__ tm = static_cast<const T*>(sd.tm);
-    const T* __restrict__ wk = static_cast<const T*>(sd.wk);
+    const auto tm = as_global(static_cast<const T*>(sd.tm));
+    const auto wk = as_global(static_cast<const T*>(sd.wk));
     const int ky = outer <= (m - 1) / 2 ? outer : m - outer;
     for (int i = threadIdx.x; i < nc * m; i += blockDim.x) {
       const int c = i / m, e = i - c * m;
@@ -592,7 +593,7 @@ __global__ __launch_bounds__(256) void k_fft_cols(int nsys, const SysDesc* __res
   }
   for (int i = threadIdx.x; i < nc * m; i += blockDim.x) {
     const int e = i / nc, c = i - e * nc;
-    base[e * estride + c] = R1[c * ss + e];
+    gstore(base + e * estride + c, R1[c * ss + e]);
   }
 }
 

@@ -59,9 +59,10 @@ __device__ __forceinline__ void wave_lds_sync() {
 template <int P, int D>
 __device__ __forceinline__ void stage_coefficients(const double* __restrict__ coef, int deg, double* lcoef) {
   constexpr int CS = coef_stride(D);
+  const global_ptr<double> gcoef = as_global(coef);
   for (int i = threadIdx.x; i < P * CS; i += blockDim.x) {
     const int j = i / CS, k = i - j * CS;
-    lcoef[i] = k <= deg ? coef[j * (deg + 1) + k] : 0.0;
+    lcoef[i] = k <= deg ? gcoef[j * (deg + 1) + k] : 0.0;
   }
 }
 
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
   const int s = tile_sys[find_sys(tile_prefix, nsys, gtile)];
   const SysDesc& sd = sys[s];
   const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S;
-  const T* __restrict__ grid = grid_override ? grid_override : static_cast<const T*>(sd.grid_b);
+  const global_ptr<T> grid = as_global(grid_override ? grid_override : static_cast<const T*>(sd.grid_b));
   const double inv_h = sd.inv_h, self_coef = sd.self_coef;
   const int nslots = blockDim.x / kLanesPerParticle;
   double* recs = reinterpret_cast<double*>(smem_raw);              // nslots * REC
