@@ -59,6 +59,20 @@ typedef enum {
                           sum phi_far + phi_local + phi_self (Sec. 3.1, eq. Ewald split)       */
 } pswfe_flags;
 
+/* Kernel split (Sec. 3.1) and window (Table 2). The method of the paper is PSWF/PSWF; the
+ * other choices are the configurations it is compared with (Sec. 4.3.1, Sec. 7.3.1-7.4) and run
+ * through the same pipeline (parameters from pswfe_variant_params). */
+typedef enum {
+  PSWFE_SPLIT_PSWF = 0,   /* PSWF mollifier (Sec. 4.2), band limited to c_s / r_c             */
+  PSWFE_SPLIT_GAUSS = 1   /* Gaussian mollifier (Example 1), sigma = r_c / sqrt(c_s)          */
+} pswfe_split;
+
+typedef enum {
+  PSWFE_WINDOW_PSWF = 0,    /* psi_0^{c_w}(x / alpha) / psi_0^{c_w}(0) (Sec. 4.3)             */
+  PSWFE_WINDOW_GAUSS = 1,   /* exp(-c_g (x / alpha)^2) on |x| <= alpha, free-space transform */
+  PSWFE_WINDOW_BSPLINE = 2  /* cardinal B-spline B_P(x / h), SPME scaling (Sec. 7.1)          */
+} pswfe_window;
+
 /* Method parameters (Alg. 3). The first block is what the kernels use; the *_alg fields are
  * the unrounded results of Alg. 3 steps 1-3, kept for reference. */
 typedef struct {
@@ -74,7 +88,10 @@ typedef struct {
   int32_t m;         /* grid points per dimension (even, 2,3,5,7-smooth)                    */
   int32_t P;         /* window support in grid points per dimension                         */
   int32_t tol_mode;  /* pswfe_tolmode                                                       */
-  int32_t reserved;
+  int32_t split;     /* pswfe_split (PSWFE_SPLIT_PSWF from pswfe_choose_params)              */
+  int32_t window;    /* pswfe_window (PSWFE_WINDOW_PSWF from pswfe_choose_params)            */
+  int32_t reserved;  /* 0                                                                    */
+  double cg;         /* Gaussian window shape c_g (PSWFE_WINDOW_GAUSS only)                  */
 } pswfe_params;
 
 typedef struct pswfe_plan pswfe_plan;
@@ -93,6 +110,26 @@ typedef struct pswfe_plan pswfe_plan;
  * Host only; touches no GPU. */
 pswfe_status pswfe_choose_params(double eps, double L, double rc, int32_t m, int64_t n, double q_l2,
                                  int32_t tol_mode, pswfe_params* out);
+
+/* Parameters of a comparison configuration (Sec. 7.3.1-7.4): the split and the window are
+ * chosen independently and the grid size m and support P are given (the paper's comparisons
+ * search them for each tolerance). Fills h = L/m, alpha = P h / 2, c_w = pi P / 2, lambda_0(c_s)
+ * and the *_alg fields (= the used values).
+ *   split, window  pswfe_split, pswfe_window
+ *   L, rc          box side, cutoff radius (rc < L/2)
+ *   cs             PSWF split: bandlimit c_s (band edge c_s / r_c, modes |k| <= c_s L/(2 pi r_c));
+ *                  Gaussian split: (r_c / sigma)^2 (eq. directsumexample), modes |k| <= m/2
+ *   m, P           grid size (even, 2,3,5,7-smooth, 8..512) and support (3..24, P <= m)
+ *   cg             Gaussian window shape; <= 0 selects 0.8 pi P / 2 (ignored for other windows)
+ *   eps            tolerance the window polynomials are fitted to (as for pswfe_choose_params)
+ *   out            host pointer, written on success
+ * Returns PSWFE_E_ARG for an unknown split or window or a non-positive length, PSWFE_E_GRID
+ * for m or P out of range, PSWFE_E_EPS_RANGE for c_s > 40 or eps outside [1e-14, 0.1].
+ * Plans made from these parameters compute phi_far + phi_self, forces and energy as usual; the
+ * real-space residual (PSWFE_TOTAL, pswfe_local) is available for the PSWF split only. Host
+ * only. */
+pswfe_status pswfe_variant_params(int32_t split, int32_t window, double L, double rc, double cs, int32_t m,
+                                  int32_t P, double cg, double eps, pswfe_params* out);
 
 /* Creates a plan: precomputes in float64 on the host the PSWF Legendre coefficients (App. B),
  * the k-space scaling tables (eq. diag_scale, eq. MhatPSWF, Table 2), the piecewise-polynomial
@@ -143,21 +180,23 @@ pswfe_status pswfe_compute_grad(pswfe_plan* plan, int64_t n, const void* pos, co
  * force -rho_i grad phi_local,i to the force and 1/2 sum rho_i phi_local,i to the energy.
  * R is evaluated from a float64 polynomial fit of Phi(r)/r in r^2 (relative error below 1e-15);
  * pairs are found in cells of edge L / floor(L / r_c) >= r_c (every pair of the system when
- * L < 3 r_c). PSWFE_TOTAL needs r_c < L/2 for every system (else PSWFE_E_ARG); unknown flag
- * bits -> PSWFE_E_ARG. */
+ * L < 3 r_c). PSWFE_TOTAL needs r_c < L/2 and the PSWF split for every system (else
+ * PSWFE_E_ARG); unknown flag bits -> PSWFE_E_ARG. */
 pswfe_status pswfe_compute_ex(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi, void* vec,
                               double* energy, int32_t flags, void* stream);
 
 /* The real-space residual alone (Sec. 3.1.1): phi_local (n), its force -rho grad phi_local (or,
  * with PSWFE_VEC_GRAD, grad phi_local; n x 3) and energy 1/2 sum rho_i phi_local,i (one double
  * per system), written to the device outputs (any may be NULL). Single-system plans take
- * n <= n_max particles; batch plans exactly the packed total (else PSWFE_E_ARG). */
+ * n <= n_max particles; batch plans exactly the packed total (else PSWFE_E_ARG). PSWF split
+ * only (else PSWFE_E_ARG). */
 pswfe_status pswfe_local(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi, void* vec,
                          double* energy, int32_t flags, void* stream);
 
 /* Host view of the residual the kernels evaluate, for verification: R(r_i) and R'(r_i)/r_i for
  * count radii (0 outside (0, r_c)); info[0..2] = polynomial degree, fit error (relative to
- * Phi(r)/r at 0), K = 2 / (lambda_0 psi_0(0) r_c). Any output may be NULL. */
+ * Phi(r)/r at 0), K = 2 / (lambda_0 psi_0(0) r_c). Any output may be NULL. PSWF split only
+ * (else PSWFE_E_ARG). */
 pswfe_status pswfe_host_local(const pswfe_params* p, int64_t count, const double* r, double* R, double* dRr,
                               double* info);
 

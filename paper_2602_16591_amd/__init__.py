@@ -34,7 +34,8 @@ class CParams(ctypes.Structure):
                 ("cs", ctypes.c_double), ("cw", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("h", ctypes.c_double), ("lambda0_s", ctypes.c_double), ("cs_alg", ctypes.c_double),
                 ("cw_alg", ctypes.c_double), ("alpha_alg", ctypes.c_double), ("m", ctypes.c_int32),
-                ("P", ctypes.c_int32), ("tol_mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("P", ctypes.c_int32), ("tol_mode", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("window", ctypes.c_int32), ("reserved", ctypes.c_int32), ("cg", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -45,6 +46,7 @@ _vp, _i64, _i32, _d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_
 _PPlan = ctypes.POINTER(ctypes.c_void_p)
 SIGNATURES = {
     "pswfe_choose_params": (ctypes.c_int, [_d, _d, _d, _i32, _i64, _d, _i32, ctypes.POINTER(CParams)]),
+    "pswfe_variant_params": (ctypes.c_int, [_i32, _i32, _d, _d, _d, _i32, _i32, _d, _d, ctypes.POINTER(CParams)]),
     "pswfe_plan_create": (ctypes.c_int, [ctypes.POINTER(CParams), _i32, _i64, _PPlan]),
     "pswfe_plan_create_tiled": (ctypes.c_int, [ctypes.POINTER(CParams), _i32, _i64, _i32, _PPlan]),
     "pswfe_plan_tile": (ctypes.c_int32, [_vp]),
@@ -107,6 +109,21 @@ def choose_params(eps: float, L: float, *, rc: float = 0.0, m: int = 0, n: int =
     out = CParams()
     _check(_lib().pswfe_choose_params(float(eps), float(L), float(rc), int(m), int(n), float(q_l2), int(mode),
                                       ctypes.byref(out)), "pswfe_choose_params")
+    return out
+
+
+SPLITS = {"pswf": 0, "gauss": 1}
+WINDOWS = {"pswf": 0, "gauss": 1, "bspline": 2}
+
+
+def variant_params(split: int | str, window: int | str, L: float, rc: float, cs: float, m: int, P: int, *,
+                   cg: float = 0.0, eps: float = 1e-6) -> CParams:
+    """Parameters of a comparison configuration (split "pswf" | "gauss", window "pswf" | "gauss" |
+    "bspline") with a given grid size m and support P (host only)."""
+    out = CParams()
+    _check(_lib().pswfe_variant_params(int(SPLITS.get(split, split)), int(WINDOWS.get(window, window)), float(L),
+                                       float(rc), float(cs), int(m), int(P), float(cg), float(eps),
+                                       ctypes.byref(out)), "pswfe_variant_params")
     return out
 
 

@@ -47,7 +47,10 @@ void to_c(const pswfe::Params& p, pswfe_params* o) {
   o->m = p.m;
   o->P = p.P;
   o->tol_mode = p.tol_mode;
+  o->split = p.split;
+  o->window = p.window;
   o->reserved = 0;
+  o->cg = p.cg;
 }
 
 pswfe::FftPlan make_fft_plan(int N) {
@@ -157,7 +160,14 @@ pswfe_status params_from_c(const pswfe_params* pp, pswfe::Params* p) {
     return PSWFE_E_GRID;
   if (!(pp->L > 0) || !(pp->rc > 0) || !(pp->cs > 0) || !(pp->cw > 0) || !(pp->alpha > 0) || !(pp->eps > 0))
     return PSWFE_E_ARG;
-  if (pp->cs > 40.0 || pp->cw > 40.0) return PSWFE_E_EPS_RANGE;
+  if (pp->split != PSWFE_SPLIT_PSWF && pp->split != PSWFE_SPLIT_GAUSS) return PSWFE_E_ARG;
+  if (pp->window != PSWFE_WINDOW_PSWF && pp->window != PSWFE_WINDOW_GAUSS && pp->window != PSWFE_WINDOW_BSPLINE)
+    return PSWFE_E_ARG;
+  if (pp->window == PSWFE_WINDOW_GAUSS && !(pp->cg > 0)) return PSWFE_E_ARG;
+  if (pp->cs > 40.0 || (pp->window == PSWFE_WINDOW_PSWF && pp->cw > 40.0)) return PSWFE_E_EPS_RANGE;
+  p->split = pp->split;
+  p->window = pp->window;
+  p->cg = pp->cg;
   p->L = pp->L;
   p->eps = pp->eps;
   p->rc = pp->rc;
@@ -227,7 +237,12 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     const pswfe::Params& p = ps[s];
     pswfe::Tables& t = plan->tab[s];
     pswfe::build_tables(p, 0, fit_tolerance(p.eps, prec), &t);
-    pswfe::build_local_table(p, &plan->ltab[s]);
+    if (p.split == pswfe::kSplitPswf) {
+      pswfe::build_local_table(p, &plan->ltab[s]);
+    } else {
+      plan->ltab[s].coef.assign(1, 0.0);  // no residual for the Gaussian split (never launched)
+      plan->local_ok = false;
+    }
     pswfe::SysDesc& sd = d.sys[s];
     const int m = p.m, N = m / 2, nx1 = N + 1;
     if (counts) {
@@ -492,6 +507,38 @@ pswfe_status pswfe_choose_params(double eps, double L, double rc, int32_t m, int
   return PSWFE_OK;
 }
 
+pswfe_status pswfe_variant_params(int32_t split, int32_t window, double L, double rc, double cs, int32_t m,
+                                  int32_t P, double cg, double eps, pswfe_params* out) {
+  if (!out) return PSWFE_E_ARG;
+  if (split != PSWFE_SPLIT_PSWF && split != PSWFE_SPLIT_GAUSS) return PSWFE_E_ARG;
+  if (window != PSWFE_WINDOW_PSWF && window != PSWFE_WINDOW_GAUSS && window != PSWFE_WINDOW_BSPLINE)
+    return PSWFE_E_ARG;
+  if (!(L > 0) || !std::isfinite(L) || !(rc > 0) || !(rc < 0.5 * L) || !(cs > 0)) return PSWFE_E_ARG;
+  if (!pswfe::is_smooth_even(m) || m < 8 || m > 512 || P < pswfe::kPmin || P > pswfe::kPmax || P > m)
+    return PSWFE_E_GRID;
+  if (cs > 40.0 || !(eps >= 1e-14 && eps <= 0.1)) return PSWFE_E_EPS_RANGE;
+  pswfe::Params p{};
+  p.L = L;
+  p.eps = eps;
+  p.rc = rc;
+  p.cs = cs;
+  p.m = m;
+  p.P = P;
+  p.h = L / m;
+  p.alpha = 0.5 * P * p.h;
+  p.cw = 0.5 * 3.14159265358979323846 * P;
+  p.cs_alg = p.cs;
+  p.cw_alg = p.cw;
+  p.alpha_alg = p.alpha;
+  p.tol_mode = PSWFE_TOL_REL;
+  p.lambda0_s = pswfe::Pswf(cs).lambda0;
+  p.split = split;
+  p.window = window;
+  p.cg = window == PSWFE_WINDOW_GAUSS ? (cg > 0 ? cg : pswfe::default_gauss_shape(P)) : 0.0;
+  to_c(p, out);
+  return PSWFE_OK;
+}
+
 pswfe_status pswfe_host_pswf(double c, double x, double* psi, double* dpsi, double* lambda0, double* chi0) {
   if (!(c > 0.0) || c > 60.0 || !(x >= -1.0 && x <= 1.0)) return PSWFE_E_ARG;
   const pswfe::Pswf f(c);
@@ -709,6 +756,7 @@ pswfe_status pswfe_host_local(const pswfe_params* pp, int64_t count, const doubl
   pswfe::Params p{};
   const pswfe_status st = params_from_c(pp, &p);
   if (st != PSWFE_OK) return st;
+  if (p.split != pswfe::kSplitPswf) return PSWFE_E_ARG;
   pswfe::LocalTable t;
   pswfe::build_local_table(p, &t);
   for (int64_t i = 0; i < count; ++i) {

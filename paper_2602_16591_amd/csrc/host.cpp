@@ -302,40 +302,113 @@ std::vector<long double> cheb_fit_monomial(F f, int deg) {
 
 }  // namespace
 
+double default_gauss_shape(int P) { return 0.8 * kPi * P / 2.0; }
+
+// Values M_{k+1}(t + r), r = 0..k, of the uniform B-spline of order k + 1 on [0, k + 1) at the
+// points t + r, 0 <= t < 1, built up from M_1 = 1 on [0, 1) with
+// M_{k+1}(y) = (y M_k(y) + (k + 1 - y) M_k(y - 1)) / k (the convolution with the unit box).
+static void bspline_row(int order, long double t, long double* v) {
+  v[0] = 1.0L;
+  for (int k = 1; k < order; ++k) {
+    v[k] = 0.0L;
+    for (int r = k; r >= 0; --r) {
+      const long double y = t + r;
+      const long double a = r <= k - 1 ? y * v[r] : 0.0L;
+      const long double b = r >= 1 ? (k + 1 - y) * v[r - 1] : 0.0L;
+      v[r] = (a + b) / k;
+    }
+  }
+}
+
+long double bspline(int P, long double x) {
+  const long double y = x + 0.5L * P;  // B_P(x) = M_P(x + P/2)
+  if (!(y >= 0.0L && y < P)) return 0.0L;
+  const int i = std::min(P - 1, static_cast<int>(std::floor(y)));
+  long double v[64];
+  bspline_row(P, y - i, v);
+  return v[i];
+}
+
+long double bspline_deriv(int P, long double x) {
+  // d/dy M_P(y) = M_{P-1}(y) - M_{P-1}(y - 1)
+  const long double y = x + 0.5L * P;
+  if (!(y >= 0.0L && y < P) || P < 2) return 0.0L;
+  const int i = std::min(P - 1, static_cast<int>(std::floor(y)));
+  long double v[64];
+  bspline_row(P - 1, y - i, v);
+  const long double a = i <= P - 2 ? v[i] : 0.0L;
+  const long double b = i >= 1 ? v[i - 1] : 0.0L;
+  return a - b;
+}
+
 void build_tables(const Params& p, int deg, double fit_tol, Tables* t) {
   const int m = p.m, P = p.P, half = m / 2;
   const double L = p.L, h = p.h, V = L * L * L;
-  const Pswf ps(p.cs), pw(p.cw);
+  const bool gsplit = p.split == kSplitGauss;
+  const Pswf ps(p.cs), pw(p.window == kWindowPswf ? p.cw : 1.0);
+  const double sigma = p.rc / std::sqrt(p.cs);  // Gaussian split width, c_s = (r_c / sigma)^2
   // Radial part of the scaling, T_M[k2] = h^6 Mhat(k) / V with Mhat(k) = L^2 gammahat / (pi |k|^2)
-  // (eq. Fsum) and gammahat(w) = psi_0^{cs}(r_c w / c_s) / psi_0^{cs}(0) in band
-  // (eq. PSWF_mollifier_ft); zero outside the band (|w| > c_s / r_c) and at k = 0.
+  // (eq. Fsum). PSWF split: gammahat(w) = psi_0^{cs}(r_c w / c_s) / psi_0^{cs}(0) in band
+  // (eq. PSWF_mollifier_ft), zero outside the band (|w| > c_s / r_c). Gaussian split (Example 1):
+  // gammahat(w) = exp(-sigma^2 w^2 / 4) for |k| <= m/2. Zero at k = 0.
   const int k2max = 3 * half * half;
-  const double kband = p.cs * L / (2.0 * kPi * p.rc);
+  const double kband = gsplit ? 0.5 * m : p.cs * L / (2.0 * kPi * p.rc);
   const double h6 = std::pow(h, 6);
   t->tm.assign(k2max + 1, 0.0);
   for (int k2 = 1; k2 <= k2max; ++k2) {
     const double k = std::sqrt(static_cast<double>(k2));
     if (k > kband * (1.0 + 1e-12)) continue;
-    const double s = std::min(1.0, p.rc * 2.0 * kPi * k / L / p.cs);
-    const double gh = ps.psi(s) / ps.psi_0;
+    const double w = 2.0 * kPi * k / L;
+    double gh;
+    if (gsplit) {
+      gh = std::exp(-0.25 * sigma * sigma * w * w);
+    } else {
+      const double s = std::min(1.0, p.rc * w / p.cs);
+      gh = ps.psi(s) / ps.psi_0;
+    }
     t->tm[k2] = h6 / V * L * L / (kPi * k2) * gh;
   }
-  // Window factor W[k] = 1 / phihat_1(2 pi k / L)^2, phihat_1(w) = alpha lambda_0 psi(alpha w/c_w)/psi(0)
-  // (Table 2), with alpha w / c_w = 2k/m.
+  // Window factor W[k] = 1 / phihat_1(2 pi k / L)^2 (Table 2):
+  //  PSWF: alpha lambda_0 psi(alpha w / c_w) / psi(0), with alpha w / c_w = 2k/m;
+  //  Gaussian: the free-space transform alpha sqrt(pi / c_g) exp(-w^2 alpha^2 / (4 c_g));
+  //  B-spline: h sum_j B_P(j) cos(2 pi k j / m), the periodised transform sum_p h B_P^(h w + 2 pi p)
+  //  by Poisson summation (the SPME scaling).
   t->w.assign(half + 1, 0.0);
   for (int k = 0; k <= half; ++k) {
-    const double ph = p.alpha * pw.lambda0 * pw.psi(2.0 * k / m) / pw.psi_0;
+    const double w = 2.0 * kPi * k / L;
+    double ph = 0.0;
+    if (p.window == kWindowPswf) {
+      ph = p.alpha * pw.lambda0 * pw.psi(2.0 * k / m) / pw.psi_0;
+    } else if (p.window == kWindowGauss) {
+      ph = p.alpha * std::sqrt(kPi / p.cg) * std::exp(-w * w * p.alpha * p.alpha / (4.0 * p.cg));
+    } else {
+      long double acc = 0.0L;
+      for (int j = -(P / 2); j <= P / 2; ++j)
+        acc += bspline(P, static_cast<long double>(j)) * std::cos(2.0L * static_cast<long double>(kPi) * k * j / m);
+      ph = h * static_cast<double>(acc);
+    }
     t->w[k] = 1.0 / (ph * ph);
   }
-  t->self_coef = 2.0 / (p.rc * ps.lambda0);
-  // Piecewise-polynomial window (Remark after eq. force): one polynomial per support point.
+  t->self_coef = gsplit ? 2.0 / (std::sqrt(kPi) * sigma) : 2.0 / (p.rc * ps.lambda0);
+  // Piecewise-polynomial window (Remark after eq. force): one polynomial per support point, in
+  // the offset g; the window at x = s alpha with s = 2 (g + (P-1)/2 - j) / P.
+  auto window_at = [&](long double s) -> long double {
+    s = std::max(-1.0L, std::min(1.0L, s));
+    if (p.window == kWindowPswf) return static_cast<long double>(pw.psi(static_cast<double>(s)) / pw.psi_0);
+    if (p.window == kWindowGauss) return std::exp(-static_cast<long double>(p.cg) * s * s);
+    return bspline(P, 0.5L * P * s);  // x / h = s P / 2
+  };
+  auto window_ds = [&](long double s) -> long double {  // d/ds
+    s = std::max(-1.0L, std::min(1.0L, s));
+    if (p.window == kWindowPswf) return static_cast<long double>(pw.dpsi(static_cast<double>(s)) / pw.psi_0);
+    if (p.window == kWindowGauss) return -2.0L * p.cg * s * std::exp(-static_cast<long double>(p.cg) * s * s);
+    return 0.5L * P * bspline_deriv(P, 0.5L * P * s);
+  };
   auto piece = [&](int j, long double g) -> long double {
-    const double s = 2.0 * (static_cast<double>(g) + 0.5 * (P - 1) - j) / P;
-    return static_cast<long double>(pw.psi(std::max(-1.0, std::min(1.0, s))) / pw.psi_0);
+    return window_at(2.0L * (g + 0.5L * (P - 1) - j) / P);
   };
   auto piece_d = [&](int j, double g) -> double {  // d/dg of phi_1(2(g + (P-1)/2 - j)/P)
-    const double s = 2.0 * (g + 0.5 * (P - 1) - j) / P;
-    return pw.dpsi(std::max(-1.0, std::min(1.0, s))) / pw.psi_0 * 2.0 / P;
+    return static_cast<double>(window_ds(2.0L * (g + 0.5L * (P - 1) - j) / P) * 2.0L / P);
   };
   double dmax = 0.0;
   for (int j = 0; j < P; ++j)

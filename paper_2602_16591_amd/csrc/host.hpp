@@ -28,11 +28,29 @@ struct Pswf {
 double lambert_w0(double x);   // principal branch, x >= -1/e
 double lambert_wm1(double x);  // lower branch, -1/e <= x < 0
 
+// Kernel split and window (Sec. 4.2, 4.3; the comparison configurations of Sec. 4.3.1 and
+// Sec. 7.3.1-7.4 use the Gaussian split of Example 1 and the Gaussian and B-spline windows of
+// Table 2).
+enum Split { kSplitPswf = 0, kSplitGauss = 1 };
+enum Window { kWindowPswf = 0, kWindowGauss = 1, kWindowBspline = 2 };
+
 struct Params {
   double L, eps, rc, cs, cw, alpha, h, lambda0_s;
   double cs_alg, cw_alg, alpha_alg;
   int m, P, tol_mode;
+  int split = kSplitPswf;    // for the Gaussian split, cs = (rc / sigma)^2
+  int window = kWindowPswf;
+  double cg = 0.0;           // Gaussian window shape: exp(-cg (x/alpha)^2)
 };
+
+// Default Gaussian window shape for support P: 0.8 times c_w = pi P / 2 (the ratio that gave
+// the smallest errors at the grid sizes and supports of Table 3's Gaussian/Gaussian column).
+double default_gauss_shape(int P);
+
+// Centred cardinal B-spline B_P(x) (Table 2) and its derivative, by the Cox-de Boor
+// recurrence of the uniform spline on the piece that contains x.
+long double bspline(int P, long double x);
+long double bspline_deriv(int P, long double x);
 
 bool is_smooth_even(int m);
 int next_smooth_even(int m);
@@ -45,17 +63,20 @@ int choose_params(double eps, double L, double rc, int m, int64_t n, double q_l2
 // Tables consumed by the kernels, all float64.
 struct Tables {
   // Scaling s_k = T_M[|k|^2] * W[|k_x|] * W[|k_y|] * W[|k_z|] (Alg. 2 step 3 with the h^6 of the
-  // unnormalised DFT pair): T_M[k2] = h^6 Mhat(k) / V for 0 < |k| <= band edge, else 0;
-  // W[k] = 1 / phihat_1(2 pi k / L)^2 for 0 <= k <= m/2.
+  // unnormalised DFT pair): T_M[k2] = h^6 Mhat(k) / V for 0 < |k| <= band edge, else 0 (the
+  // PSWF split's band edge c_s L / (2 pi r_c); m/2 for the Gaussian split, which has no band);
+  // W[k] = 1 / phihat_1(2 pi k / L)^2 for 0 <= k <= m/2, with phihat_1 the window's transform
+  // (for the B-spline window, the SPME form: the transform of its integer samples).
   std::vector<double> tm;  // size 3 (m/2)^2 + 1
   std::vector<double> w;   // size m/2 + 1
   // Piecewise-polynomial window: for support point j = 0..P-1 and centred offset
-  // g in [-1/2, 1/2], phi_1(2 (g + (P-1)/2 - j) / P) ~ sum_k coef[j*(deg+1) + k] g^k.
+  // g in [-1/2, 1/2], phi_1(2 (g + (P-1)/2 - j) / P) ~ sum_k coef[j*(deg+1) + k] g^k, with
+  // phi_1(s) the window at x = s alpha.
   int deg = 0;
   std::vector<double> coef;     // P * (deg + 1)
   double fit_err = 0.0;         // max |fit - phi_1| over all pieces (sampled)
   double fit_err_deriv = 0.0;   // max |fit' - d phi_1/dg| over all pieces (sampled)
-  double self_coef = 0.0;       // 2 / (rc lambda_0(c_s))
+  double self_coef = 0.0;       // lim_{r->0} M(r): 2 / (rc lambda_0(c_s)), or 2 / (sqrt(pi) sigma)
 };
 
 // deg <= 0 picks the smallest degree in [4, 28] whose sampled error is below `fit_tol`.
