@@ -8,6 +8,7 @@ in HBM. The headline value is the float32 path; the float64 path is timed on the
 and a batch of 256 independent systems is timed batched (one HIP graph) and sequentially.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
+                       [--no-comparison]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -184,6 +185,66 @@ def bench_ensemble(steps: int, warmup: int):
     }
 
 
+# Comparison configurations at the paper's resolutions (split, window, eps, m from the table, P):
+# Table 3 at eps = 1e-6 (PSWF/PSWF, Gaussian/PSWF, Gaussian/Gaussian) and Table 4 at eps = 1e-5
+# (B-spline windows of order 4, 6, 8 with the PSWF and the Gaussian split; PSWF/PSWF from Table 3).
+COMPARISON = [
+    ("PP", "pswf", "pswf", 1e-6, 42, 10), ("GP", "gauss", "pswf", 1e-6, 79, 10),
+    ("GG", "gauss", "gauss", 1e-6, 80, 15),
+    ("PP", "pswf", "pswf", 1e-5, 35, 9),
+    ("PB4", "pswf", "bspline", 1e-5, 154, 4), ("PB6", "pswf", "bspline", 1e-5, 66, 6),
+    ("PB8", "pswf", "bspline", 1e-5, 49, 8),
+    ("GB4", "gauss", "bspline", 1e-5, 230, 4), ("GB6", "gauss", "bspline", 1e-5, 101, 6),
+    ("GB8", "gauss", "bspline", 1e-5, 78, 8),
+]
+
+
+def bench_comparison(steps: int, warmup: int, n: int = 100_000):
+    """MI355X time of the paper's split/window configurations at equal accuracy: the grid sizes
+    and supports of Tables 3 and 4 (m rounded up to an FFT size), n uniform particles with
+    N(0,1) charges shifted to neutrality in the unit box, r_c = 0.1 (the tables' setup, with
+    more particles), float32, phi + forces + energy, one graph replay per step."""
+    import numpy as np
+    import torch
+    import paper_2602_16591_amd as pw
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    x, q, L = W.paper_default(n, seed=W.SEED_BASE + 7)
+    X = torch.as_tensor(x, dtype=torch.float32, device=dev)
+    Q = torch.as_tensor(q, dtype=torch.float32, device=dev)
+    rows = []
+    for name, split, window, eps, m_tab, P in COMPARISON:
+        m = m_tab
+        while True:   # next even size with prime factors 2, 3, 5, 7
+            r = m
+            for f in (2, 3, 5, 7):
+                while r % f == 0:
+                    r //= f
+            if r == 1 and m % 2 == 0:
+                break
+            m += 1
+        c = pw.variant_params(split, window, L, 0.1, math.log(1.0 / eps), m, P, eps=eps)
+        plan = pw.Plan(c, "fp32", n_max=n)
+        runner = plan.graph(X, Q)
+        for _ in range(warmup):
+            runner()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            runner()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) / steps * 1e3
+        rows.append({"config": name, "split": split, "window": window, "eps": eps, "m_table": m_tab, "m": m,
+                     "P": P, "ms_per_step": ms})
+        del runner
+        plan.close()
+    ref = {eps: next(r["ms_per_step"] for r in rows if r["config"] == "PP" and r["eps"] == eps) for eps in (1e-6, 1e-5)}
+    for r in rows:
+        r["time_vs_PP"] = r["ms_per_step"] / ref[r["eps"]]
+    return {"workload": f"uniform_n{n}_unit_box_rc0.1", "prec": "fp32", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +252,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-sequential ensemble")
+    ap.add_argument("--no-comparison", action="store_true",
+                    help="skip the split/window comparison at the paper's resolutions")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the measurement, copy a device buffer of this many MiB three times (a kernel of "
                          "known traffic, to calibrate profiler byte counters); not part of the result")
@@ -312,6 +375,8 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = bench_ensemble(max(5, min(args.steps, 50)), max(2, min(args.warmup, 5)))
+    if not args.no_comparison:
+        out["comparison"] = bench_comparison(max(5, min(args.steps, 30)), max(2, min(args.warmup, 5)))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, q, L, eps, m)
     if args.copy_mib > 0:

@@ -329,6 +329,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   auto cols = [&](int s) { return columns_ok && pswfe::col_tile_ok(d.sys[s].B) ? d.sys[s].B : 0; };
   auto key = [&](int s) { return std::make_tuple(d.sys[s].P, pswfe::degree_bucket(d.sys[s].deg), cols(s)); };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
+  std::vector<int64_t> group_particles;
   for (int k = 0; k < nsys; ++k) {
     pswfe::SysDesc& sd = d.sys[order[k]];
     const int D = pswfe::degree_bucket(sd.deg);
@@ -342,10 +343,26 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
       g.col_tile = cols(order[k]);
       g.tile_begin = tile_prefix[k];
       d.groups.push_back(g);
+      group_particles.push_back(0);
     }
     pswfe::PGroup& g = d.groups.back();
     g.tile_end = tile_prefix[k + 1];
+    group_particles.back() += counts ? counts[order[k]] : n_max;
     g.lds_spread = std::max<size_t>(g.lds_spread, lds_edge(sd.B, sd.P));  // largest S of the group, for now
+  }
+  // Dense tiles are shared by several workgroups, each taking a slice of the tile's particles,
+  // when a group has too few tiles to fill the GPU: up to about 1024 workgroups per launch, with
+  // at least 32 particles (on average) per workgroup and at most 16 workgroups per tile.
+  // PSWFE_TILE_PARTS overrides it.
+  int parts_env = 0;
+  if (const char* env = std::getenv("PSWFE_TILE_PARTS")) parts_env = std::max(1, std::min(16, std::atoi(env)));
+  for (size_t gi = 0; gi < d.groups.size(); ++gi) {
+    pswfe::PGroup& g = d.groups[gi];
+    const int64_t tiles = g.tile_end - g.tile_begin;
+    const int64_t per_tile = group_particles[gi] / std::max<int64_t>(tiles, 1);
+    int64_t parts = 1;
+    if (tiles < 1024) parts = std::min<int64_t>((1024 + tiles - 1) / tiles, std::max<int64_t>(1, per_tile / 32));
+    g.parts = parts_env ? parts_env : static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(16, parts)));
   }
   for (pswfe::PGroup& g : d.groups) {
     const int S = static_cast<int>(g.lds_spread), P = g.P, D = g.D;

@@ -88,6 +88,7 @@ struct PGroup {
   int tile_begin = 0, tile_end = 0;
   int spread_threads = 256, gather_threads = 256;  // workgroup sizes (multiples of 64, <= 1024)
   int col_tile = 0;  // spreading by register columns when the group's tiles all have this edge (4, 6, 8)
+  int parts = 1;     // workgroups per tile, each taking an equal slice of the tile's particles
   size_t lds_spread = 0, lds_gather = 0;  // maxima over the group's systems
 };
 

@@ -54,6 +54,17 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Particles [p0, p1) of part `part` of `parts` equal slices of tile gtile's bin: a dense tile
+// is shared by several workgroups (each spreading into its own partial block, or interpolating
+// its own particles), so that small grids with many particles per tile still fill the GPU.
+__device__ __forceinline__ void tile_slice(const int* __restrict__ tile_start, int gtile, int sub_log2, int part,
+                                           int parts, int& p0, int& p1) {
+  const int a = tile_start[gtile << sub_log2], b = tile_start[(gtile + 1) << sub_log2];
+  const int64_t nt = b - a;
+  p0 = a + static_cast<int>(nt * part / parts);
+  p1 = a + static_cast<int>(nt * (part + 1) / parts);
+}
+
 // Copies the window coefficients (P pieces of deg + 1 powers, float64) into LDS rows of
 // coef_stride(D) doubles, zero above deg.
 template <int P, int D>
@@ -81,13 +92,14 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_spread(const type
                                                 const int* __restrict__ cells, const int* __restrict__ tile_start,
                                                 int sub_log2, int nsys, const SysDesc* __restrict__ sys,
                                                 const int* __restrict__ tile_prefix, const int* __restrict__ tile_sys,
-                                                int tile_offset) {
+                                                int tile_offset, int parts) {
   constexpr int REC = 3 * P;  // window values of one particle: x, y, z
   constexpr int CS = coef_stride(D);
   constexpr int NL = (P * P + kLanesPerParticle - 1) / kLanesPerParticle;  // lines per lane
   extern __shared__ unsigned char smem_raw[];
-  const int gtile = tile_offset + static_cast<int>(blockIdx.x);
-  const int p0 = tile_start[gtile << sub_log2], p1 = tile_start[(gtile + 1) << sub_log2];
+  const int gtile = tile_offset + static_cast<int>(blockIdx.x) / parts;
+  int p0, p1;
+  tile_slice(tile_start, gtile, sub_log2, static_cast<int>(blockIdx.x) % parts, parts, p0, p1);
   if (p0 == p1) return;
   const SysDesc& sd = sys[tile_sys[find_sys(tile_prefix, nsys, gtile)]];
   const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S;
@@ -201,13 +213,14 @@ template <class T, int P, int D, int B>
 __global__ __launch_bounds__((col_threads<P, B>())) void k_spread_cols(
     const typename Vec4<T>::type* __restrict__ sorted, const int* __restrict__ cells,
     const int* __restrict__ tile_start, int sub_log2, int nsys, const SysDesc* __restrict__ sys,
-    const int* __restrict__ tile_prefix, const int* __restrict__ tile_sys, int tile_offset) {
+    const int* __restrict__ tile_prefix, const int* __restrict__ tile_sys, int tile_offset, int parts) {
   constexpr int S = col_edge<P, B>();
   constexpr int CS = coef_stride(D);
   constexpr int RS = 3 * S;  // a particle's padded window values: x, y, z
   extern __shared__ unsigned char smem_raw[];
-  const int gtile = tile_offset + static_cast<int>(blockIdx.x);
-  const int p0 = tile_start[gtile << sub_log2], p1 = tile_start[(gtile + 1) << sub_log2];
+  const int gtile = tile_offset + static_cast<int>(blockIdx.x) / parts;
+  int p0, p1;
+  tile_slice(tile_start, gtile, sub_log2, static_cast<int>(blockIdx.x) % parts, parts, p0, p1);
   if (p0 == p1) return;
   const SysDesc& sd = sys[tile_sys[find_sys(tile_prefix, nsys, gtile)]];
   const int m = sd.m, Tn = sd.Tn;
@@ -298,7 +311,7 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
                                                 const int* __restrict__ cells, const int* __restrict__ perm,
                                                 const int* __restrict__ tile_start, int sub_log2, int nsys,
                                                 const SysDesc* __restrict__ sys, const int* __restrict__ tile_prefix,
-                                                const int* __restrict__ tile_sys, int tile_offset,
+                                                const int* __restrict__ tile_sys, int tile_offset, int parts,
                                                 const T* __restrict__ grid_override, T* __restrict__ phi,
                                                 T* __restrict__ vec, int vec_mode, int add_self,
                                                 double* __restrict__ energy) {
@@ -306,8 +319,9 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
   constexpr int CS = coef_stride(D);
   extern __shared__ unsigned char smem_raw[];
   __shared__ double s_red[16];
-  const int gtile = tile_offset + static_cast<int>(blockIdx.x);
-  const int p0 = tile_start[gtile << sub_log2], p1 = tile_start[(gtile + 1) << sub_log2];
+  const int gtile = tile_offset + static_cast<int>(blockIdx.x) / parts;
+  int p0, p1;
+  tile_slice(tile_start, gtile, sub_log2, static_cast<int>(blockIdx.x) % parts, parts, p0, p1);
   if (p0 == p1) return;
   const int s = tile_sys[find_sys(tile_prefix, nsys, gtile)];
   const SysDesc& sd = sys[s];
@@ -452,9 +466,9 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
 template <class T, int P, int D>
 hipError_t spread_impl(const DevPlan& d, const PGroup& g, hipStream_t st) {
   auto cols = [&](auto kern, int threads) {
-    hipLaunchKernelGGL(kern, dim3(g.tile_end - g.tile_begin), dim3(threads), g.lds_spread, st,
+    hipLaunchKernelGGL(kern, dim3((g.tile_end - g.tile_begin) * g.parts), dim3(threads), g.lds_spread, st,
                        static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start, d.sub_log2, d.nsys,
-                       d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin);
+                       d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin, g.parts);
   };
   if (g.col_tile == 4)
     cols(k_spread_cols<T, P, D, 4>, col_threads<P, 4>());
@@ -463,18 +477,19 @@ hipError_t spread_impl(const DevPlan& d, const PGroup& g, hipStream_t st) {
   else if (g.col_tile == 8)
     cols(k_spread_cols<T, P, D, 8>, col_threads<P, 8>());
   else
-    hipLaunchKernelGGL((k_spread<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(g.spread_threads), g.lds_spread,
-                       st, static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start, d.sub_log2,
-                       d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin);
+    hipLaunchKernelGGL((k_spread<T, P, D>), dim3((g.tile_end - g.tile_begin) * g.parts), dim3(g.spread_threads),
+                       g.lds_spread, st, static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start,
+                       d.sub_log2, d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin, g.parts);
   return hipGetLastError();
 }
 
 template <class T, int P, int D>
 hipError_t gather_impl(const DevPlan& d, const PGroup& g, const void* grid, void* phi, void* vec, int vec_mode,
                        bool add_self, double* energy, hipStream_t st) {
-  hipLaunchKernelGGL((k_gather<T, P, D>), dim3(g.tile_end - g.tile_begin), dim3(g.gather_threads), g.lds_gather, st,
-                     static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.perm, d.tile_start, d.sub_log2,
-                     d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin, static_cast<const T*>(grid),
+  hipLaunchKernelGGL((k_gather<T, P, D>), dim3((g.tile_end - g.tile_begin) * g.parts), dim3(g.gather_threads),
+                     g.lds_gather, st, static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.perm,
+                     d.tile_start, d.sub_log2, d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin, g.parts,
+                     static_cast<const T*>(grid),
                      static_cast<T*>(phi), static_cast<T*>(vec), vec_mode, add_self ? 1 : 0, energy);
   return hipGetLastError();
 }

@@ -148,6 +148,41 @@ def test_both_spreading_kernels_match_oracle(case, prec, columns, monkeypatch):
     assert rel_l2(F.cpu().numpy(), direct.forces(q, rg)) < (1e-10 if prec == "fp64" else 2e-5) + 100 * fit_tol(eps, prec)
 
 
+DENSE_CASES = [
+    # (name, generator, eps, params kwargs, tile): many particles per tile, few tiles
+    ("dense_m24_tile8_cols", lambda: W.uniform_pm1(24000, seed=26), 1e-6, dict(m=24), 8),
+    ("dense_m20_tile5_lds", lambda: W.paper_default(9000, seed=27, L=1.1), 1e-6, dict(m=20), 5),
+]
+
+
+@pytest.mark.parametrize("parts", ["auto", "1", "3", "16"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", DENSE_CASES, ids=[c[0] for c in DENSE_CASES])
+def test_dense_tiles_shared_by_workgroups(case, prec, parts, monkeypatch):
+    """Dense tiles split over several workgroups (each spreading its slice of the tile's
+    particles into its own partial block, or interpolating its slice): the same results as the
+    oracle, whatever the number of parts (automatic: 1024 / tiles, here 2 to 16)."""
+    _, gen, eps, kw, tile = case
+    if parts != "auto":
+        monkeypatch.setenv("PSWFE_TILE_PARTS", parts)
+    x, q, L, kw = _sys(gen, eps, kw, prec)
+    c, o = both_params(eps, L, **kw)
+    plan = pw.Plan(c, prec, n_max=len(q), tile=tile)
+    assert plan.tile == tile
+    g = plan.spread(tdev(x, prec), tdev(q, prec)).cpu().numpy()
+    a = fast.spread(np.mod(x, L), q, o).transpose(2, 1, 0)
+    A = fast.spread(np.mod(x, L), np.abs(q), o).transpose(2, 1, 0)
+    assert np.all(np.abs(g - a) <= spread_tol(x, q, o, eps, prec, A))
+    phi, F, E = plan.compute(tdev(x, prec), tdev(q, prec))
+    rphi, rg = fast.fast_longrange(x, q, o)
+    far = rphi - direct.self_term(q, o.rc, o.cs)
+    tol_phi = (1e-11 if prec == "fp64" else 2e-6) + 10 * fit_tol(eps, prec)
+    assert np.linalg.norm(phi.cpu().numpy() - rphi) / np.linalg.norm(far) < tol_phi
+    assert rel_l2(F.cpu().numpy(), direct.forces(q, rg)) < (1e-10 if prec == "fp64" else 2e-5) + 100 * fit_tol(eps, prec)
+    Eref = 0.5 * float(q @ rphi)
+    assert abs(float(E.cpu()[0]) - Eref) <= tol_phi * 0.5 * float(np.abs(q) @ np.abs(far)) + 1e-12 * abs(Eref)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_single_charge_window_precision(prec):
     """One unit charge far from the origin (x/h ~ m): every grid value of its support within a few
