@@ -221,7 +221,14 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   d.prec = prec;
   d.nsys = nsys;
   d.sys.resize(nsys);
-  std::vector<int> xblk_prefix(nsys + 1, 0), cblk_prefix(nsys + 1, 0);
+  std::vector<int> xblk_prefix(nsys + 1, 0), cblk_prefix(nsys + 1, 0), pblk_prefix(nsys + 1, 0);
+  // x and y FFTs fused per z-plane (PSWFE_PLANE_FFT=1) when every system's plane (two padded
+  // copies of its half spectrum plus twiddles) fits in LDS. Off by default: measured on MI355X,
+  // one workgroup per plane (64-128 of them) costs as much as the two separate passes it saves a
+  // launch over (water box 64^3: 135.5 against 136.0 us per step in float32, 153.9 against 152.7
+  // in float64; 128^3 float32: 3.6 us slower).
+  bool plane_ok = false;
+  if (const char* env = std::getenv("PSWFE_PLANE_FFT")) plane_ok = std::atoi(env) != 0;
   std::vector<int64_t> part_prefix(nsys + 1, 0);
   // complex values per FFT workgroup (measured on gfx950: 1024 on grids up to 96^3, 2048 above)
   int fft_env = 0;
@@ -295,6 +302,13 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     sd.rows_per_block = rpb;
     sd.cols_per_block = (nx1 + nxb - 1) / nxb;
     sd.xblk_base = xblk_prefix[s];
+    sd.pblk_base = pblk_prefix[s];
+    pblk_prefix[s + 1] = pblk_prefix[s] + m;
+    {
+      const size_t lds_plane = (2 * static_cast<size_t>(nx1) * (m + 1) + N + m) * celem;
+      d.lds_p = std::max(d.lds_p, lds_plane);
+      if (lds_plane > kLdsLimit) plane_ok = false;
+    }
     sd.cblk_base = cblk_prefix[s];
     sd.part_base = part_prefix[s];
     xblk_prefix[s + 1] = xblk_prefix[s] + (m * m + rpb - 1) / rpb;
@@ -374,6 +388,8 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   }
   d.total_tiles = tile_prefix[nsys];
   d.total_xblk = xblk_prefix[nsys];
+  d.total_pblk = pblk_prefix[nsys];
+  d.plane_fft = plane_ok ? 1 : 0;
   d.total_cblk = cblk_prefix[nsys];
   d.n_max = counts ? part_prefix[nsys] : n_max;
   if (d.n_max > (int64_t(1) << 31) - 1) {
@@ -423,6 +439,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   d.lsorted = static_cast<double*>(alloc(sizeof(double) * 4 * nm));
   d.lperm = static_cast<int*>(alloc(sizeof(int) * nm));
   d.xblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
+  d.pblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
   d.cblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
   d.part_prefix = static_cast<int64_t*>(alloc(sizeof(int64_t) * (nsys + 1)));
   if (st != PSWFE_OK) {
@@ -480,6 +497,8 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
             hipMemcpy(d.cell_prefix, cell_prefix_v.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
                 hipSuccess &&
             hipMemcpy(d.xblk_prefix, xblk_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
+                hipSuccess &&
+            hipMemcpy(d.pblk_prefix, pblk_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
                 hipSuccess &&
             hipMemcpy(d.cblk_prefix, cblk_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
                 hipSuccess &&

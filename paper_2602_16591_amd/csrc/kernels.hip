@@ -523,6 +523,118 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(int nsys, const SysDesc* __re
   for (int e = threadIdx.x; e < nr * N; e += blockDim.x) gstore(dst + e, Z[e]);
 }
 
+// Forward x and y FFTs of one z-plane per workgroup (used when a plane fits in LDS): the m
+// rows' real-to-complex FFTs as in k_fft_x_r2c, their half spectra written transposed into LDS
+// (column kx of length m, padded stride m + 1), the y FFT of those m/2 + 1 columns, and the
+// result stored to the spectrum in the layout k_fft_cols reads. One launch instead of two, and
+// the plane does not travel through HBM in between.
+template <class T, class TI>
+__global__ __launch_bounds__(256) void k_fft_plane_fwd(int nsys, const SysDesc* __restrict__ sys,
+                                                       const int* __restrict__ pblk_prefix, const TI* in_override,
+                                                       int zero_input) {
+  using C = typename Cplx<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  const SysDesc& sd = sys[find_sys(pblk_prefix, nsys, static_cast<int>(blockIdx.x))];
+  const int m = sd.m, N = m / 2, nx1 = N + 1, ss = m + 1;
+  const int z = static_cast<int>(blockIdx.x) - sd.pblk_base;
+  C* U = reinterpret_cast<C*>(smem_raw);  // nx1 * ss each
+  C* V = U + nx1 * ss;
+  C* tw_h = V + nx1 * ss;  // N twiddles of the half-length FFT, then m of length m (sign +)
+  C* tw_f = tw_h + N;
+  {
+    const C* __restrict__ tw_half = static_cast<const C*>(sd.twhp);
+    const C* __restrict__ tw_full = static_cast<const C*>(sd.twfp);
+    for (int e = threadIdx.x; e < N + m; e += blockDim.x) {
+      if (e < N)
+        tw_h[e] = gload(tw_half + e);
+      else
+        tw_f[e - N] = gload(tw_full + (e - N));
+    }
+  }
+  using CI = typename Cplx<TI>::type;
+  const TI* grid = in_override ? in_override : reinterpret_cast<const TI*>(sd.grid_a);
+  const CI* src = reinterpret_cast<const CI*>(grid + static_cast<int64_t>(z) * m * m);
+  staged_copy<8>(
+      m * N, [&](int e) { return gload(src + e); },
+      [&](int e, CI v) { U[e] = C{static_cast<T>(v.x), static_cast<T>(v.y)}; });
+  if (zero_input) {
+    CI* zsrc = const_cast<CI*>(src);
+    for (int e = threadIdx.x; e < m * N; e += blockDim.x) gstore(zsrc + e, CI{TI(0), TI(0)});
+  }
+  __syncthreads();
+  const C* Z = fft_lds(U, V, m, N, sd.fh, tw_h);  // rows y = 0..m-1, N points each
+  C* Tc = (Z == U) ? V : U;
+  for (int e = threadIdx.x; e < m * nx1; e += blockDim.x) {
+    const int y = e / nx1, k = e - y * nx1;
+    const C zk = Z[y * N + (k == N ? 0 : k)];
+    const C zn = cconj(Z[y * N + (k == 0 ? 0 : N - k)]);
+    const C ev = C{T(0.5) * (zk.x + zn.x), T(0.5) * (zk.y + zn.y)};
+    const C dd = csub(zk, zn);
+    const C od = C{T(0.5) * dd.y, T(-0.5) * dd.x};
+    Tc[k * ss + y] = cadd(ev, cmul(tw_f[k], od));
+  }
+  __syncthreads();
+  C* other = (Tc == U) ? V : U;
+  const C* R = fft_lds(Tc, other, nx1, ss, sd.ff, tw_f);
+  C* out = static_cast<C*>(sd.spec) + static_cast<int64_t>(z) * m * nx1;
+  for (int e = threadIdx.x; e < m * nx1; e += blockDim.x) {
+    const int y = e / nx1, k = e - y * nx1;
+    gstore(out + e, R[k * ss + y]);
+  }
+}
+
+// Inverse y and x FFTs of one z-plane per workgroup, the mirror of k_fft_plane_fwd: the plane's
+// half spectrum loaded transposed, the inverse y FFT of its m/2 + 1 columns, then the
+// complex-to-real inverse x FFT of its m rows as in k_fft_x_c2r, written to grid_b (or, single
+// system, out_override).
+template <class T>
+__global__ __launch_bounds__(256) void k_fft_plane_inv(int nsys, const SysDesc* __restrict__ sys,
+                                                       const int* __restrict__ pblk_prefix, T* out_override) {
+  using C = typename Cplx<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  const SysDesc& sd = sys[find_sys(pblk_prefix, nsys, static_cast<int>(blockIdx.x))];
+  const int m = sd.m, N = m / 2, nx1 = N + 1, ss = m + 1;
+  const int z = static_cast<int>(blockIdx.x) - sd.pblk_base;
+  C* U = reinterpret_cast<C*>(smem_raw);
+  C* V = U + nx1 * ss;
+  C* tw_h = V + nx1 * ss;  // N twiddles of the half-length FFT, then m of length m (sign -)
+  C* tw_f = tw_h + N;
+  {
+    const C* __restrict__ tw_half = static_cast<const C*>(sd.twhm);
+    const C* __restrict__ tw_full = static_cast<const C*>(sd.twfm);
+    for (int e = threadIdx.x; e < N + m; e += blockDim.x) {
+      if (e < N)
+        tw_h[e] = gload(tw_half + e);
+      else
+        tw_f[e - N] = gload(tw_full + (e - N));
+    }
+  }
+  const C* in = static_cast<const C*>(sd.spec) + static_cast<int64_t>(z) * m * nx1;
+  staged_copy<8>(
+      m * nx1, [&](int e) { return gload(in + e); },
+      [&](int e, C v) {
+        const int y = e / nx1, k = e - y * nx1;
+        U[k * ss + y] = v;
+      });
+  __syncthreads();
+  const C* R = fft_lds(U, V, nx1, ss, sd.ff, tw_f);  // inverse y of each column kx
+  C* W = (R == U) ? V : U;
+  for (int e = threadIdx.x; e < m * N; e += blockDim.x) {
+    const int y = e / N, k = e - y * N;
+    const C xk = R[k * ss + y];
+    const C xn = cconj(R[(N - k) * ss + y]);
+    const C s = cadd(xk, xn);
+    const C d = cmul(tw_f[k], csub(xk, xn));
+    W[e] = C{s.x - d.y, s.y + d.x};  // s + i d
+  }
+  __syncthreads();
+  C* other = (W == U) ? V : U;
+  const C* Z = fft_lds(W, other, m, N, sd.fh, tw_h);
+  T* grid = out_override ? out_override : static_cast<T*>(sd.grid_b);
+  C* dst = reinterpret_cast<C*>(grid + static_cast<int64_t>(z) * m * m);
+  for (int e = threadIdx.x; e < m * N; e += blockDim.x) gstore(dst + e, Z[e]);
+}
+
 // FFT along y or z of each system's half spectrum. A system's blocks are (outer, column
 // block) pairs; sequence c of a block is the column kx0 + c, whose element e sits at
 // spec[outer * ostride + e * estride + kx0 + c].
@@ -631,6 +743,29 @@ hipError_t bin_impl(const DevPlan& d, int64_t n, const void* pos, const void* q,
 
 template <class T>
 hipError_t transform_impl(const DevPlan& d, const void* in_override, void* out_override, hipStream_t st) {
+  if (d.plane_fft) {
+    stage_begin(d, kStageFftX, st);
+    if (in_override)
+      hipLaunchKernelGGL((k_fft_plane_fwd<T, T>), dim3(d.total_pblk), dim3(256), d.lds_p, st, d.nsys, d.sys_dev,
+                         d.pblk_prefix, static_cast<const T*>(in_override), 0);
+    else
+      hipLaunchKernelGGL((k_fft_plane_fwd<T, double>), dim3(d.total_pblk), dim3(256), d.lds_p, st, d.nsys,
+                         d.sys_dev, d.pblk_prefix, static_cast<const double*>(nullptr), 1);
+    stage_end(d, kStageFftX, st);
+    stage_begin(d, kStageFftY, st);  // fused into the x stage: recorded as an empty stage
+    stage_end(d, kStageFftY, st);
+    stage_begin(d, kStageFftZScale, st);
+    hipLaunchKernelGGL(k_fft_cols<T>, dim3(d.total_cblk), dim3(256), d.lds_c, st, d.nsys, d.sys_dev, d.cblk_prefix,
+                       1);
+    stage_end(d, kStageFftZScale, st);
+    stage_begin(d, kStageIfftY, st);  // fused into the inverse x stage
+    stage_end(d, kStageIfftY, st);
+    stage_begin(d, kStageIfftX, st);
+    hipLaunchKernelGGL(k_fft_plane_inv<T>, dim3(d.total_pblk), dim3(256), d.lds_p, st, d.nsys, d.sys_dev,
+                       d.pblk_prefix, static_cast<T*>(out_override));
+    stage_end(d, kStageIfftX, st);
+    return hipGetLastError();
+  }
   stage_begin(d, kStageFftX, st);
   if (in_override)
     hipLaunchKernelGGL((k_fft_x_r2c<T, T>), dim3(d.total_xblk), dim3(256), d.lds_x, st, d.nsys, d.sys_dev,
@@ -677,6 +812,31 @@ const ParticleFns* particle_fns(int prec, int P) {
 }  // namespace
 
 hipError_t prepare_kernels(const DevPlan& d) {
+  if (d.plane_fft && d.lds_p > 64 * 1024) {
+    hipError_t e;
+    if (d.prec == 0)
+      e = [&] {
+        hipError_t r = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_plane_fwd<float, float>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(d.lds_p));
+        if (r == hipSuccess)
+          r = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_plane_fwd<float, double>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(d.lds_p));
+        if (r == hipSuccess)
+          r = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_plane_inv<float>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(d.lds_p));
+        return r;
+      }();
+    else
+      e = [&] {
+        hipError_t r = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_plane_fwd<double, double>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(d.lds_p));
+        if (r == hipSuccess)
+          r = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_plane_inv<double>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(d.lds_p));
+        return r;
+      }();
+    if (e != hipSuccess) return e;
+  }
   for (const PGroup& g : d.groups) {
     const ParticleFns* f = particle_fns(d.prec, g.P);
     const hipError_t e = f ? f->prepare(g) : hipErrorInvalidValue;

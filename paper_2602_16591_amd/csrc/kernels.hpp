@@ -49,6 +49,7 @@ struct SysDesc {
   int rows_per_block = 1;     // x-direction FFT batching
   int cols_per_block = 1;     // y/z-direction FFT batching
   int xblk_base = 0;          // first block of this system in the x-direction FFT launches
+  int pblk_base = 0;          // first block (z-plane) of this system in the plane FFT launches
   int cblk_base = 0;          // first block in the y/z-direction FFT launches
   int64_t part_base = 0;      // first packed particle of this system
   double L = 0, inv_h = 0, ih_hi = 0, ih_lo = 0, self_coef = 0;
@@ -117,6 +118,10 @@ struct DevPlan {
   int* tile_prefix = nullptr;      // nsys + 1: tile ranges in global tile order (grouped by P, D)
   int* tile_sys = nullptr;         // nsys: system owning the k-th tile range
   int* xblk_prefix = nullptr;      // nsys + 1, in system order
+  int* pblk_prefix = nullptr;      // nsys + 1: z-planes, for the plane FFT kernels
+  int plane_fft = 0;               // x and y FFTs fused per z-plane (every system's plane fits in LDS)
+  int total_pblk = 0;
+  size_t lds_p = 0;                // LDS of the plane FFT kernels
   int* cblk_prefix = nullptr;      // nsys + 1, in system order
   int64_t* part_prefix = nullptr;  // nsys + 1 (batches; a single system takes n per call)
   int total_tiles = 0, total_xblk = 0, total_cblk = 0;
