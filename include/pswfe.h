@@ -92,6 +92,11 @@ typedef struct {
   int32_t window;    /* pswfe_window (PSWFE_WINDOW_PSWF from pswfe_choose_params)            */
   int32_t reserved;  /* 0                                                                    */
   double cg;         /* Gaussian window shape c_g (PSWFE_WINDOW_GAUSS only)                  */
+  /* Cuboid boxes [0, L) x [0, Ly) x [0, Lz) (Sec. 6.1, remark on cuboid domains): sides and grid
+   * sizes along y and z; 0 means equal to L and m (a cube). Grid spacings h_d = L_d / m_d; L, m,
+   * h and alpha above are the x values; the window has the same P and c_w along every axis. */
+  double Ly, Lz;
+  int32_t my, mz;
 } pswfe_params;
 
 typedef struct pswfe_plan pswfe_plan;
@@ -110,6 +115,15 @@ typedef struct pswfe_plan pswfe_plan;
  * Host only; touches no GPU. */
 pswfe_status pswfe_choose_params(double eps, double L, double rc, int32_t m, int64_t n, double q_l2,
                                  int32_t tol_mode, pswfe_params* out);
+
+/* Alg. 3 for a cuboid box [0, Lx) x [0, Ly) x [0, Lz) (Sec. 6.1, remark on cuboid domains): the
+ * parameters of the cube of side L_min = min(Lx, Ly, Lz) with the same particle density and
+ * charge density (n and ||rho||^2 scaled by L_min^3 / (Lx Ly Lz)) fix r_c, c_s, c_w and P and the
+ * spacing h = L_min / m; then m_d is the smallest even 2,3,5,7-smooth size with L_d / m_d <= h.
+ * Arguments as for pswfe_choose_params (m: prescribed grid size along the shortest side, or 0).
+ * With Lx = Ly = Lz this is pswfe_choose_params. Host only. */
+pswfe_status pswfe_choose_params_box(double eps, double Lx, double Ly, double Lz, double rc, int32_t m, int64_t n,
+                                     double q_l2, int32_t tol_mode, pswfe_params* out);
 
 /* Parameters of a comparison configuration (Sec. 7.3.1-7.4): the split and the window are
  * chosen independently and the grid size m and support P are given (the paper's comparisons
@@ -247,16 +261,16 @@ pswfe_status pswfe_plan_system(const pswfe_plan* plan, int32_t s, pswfe_params* 
                                int64_t* count, int32_t* tile);
 
 /* Alg. 2 step 1 alone (eq. spread_def): grid[(lz*m + ly)*m + lx] = sum_j q_j
- * phitilde(x_j - h l) for the m^3 grid points, written to the device array `grid`
- * (plan precision, m^3 entries, z slowest). */
+ * phitilde(x_j - h l) for the m x my x mz grid points (m^3 for a cube), written to the device
+ * array `grid` (plan precision, x fastest, z slowest). */
 pswfe_status pswfe_spread(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* grid,
                           void* stream);
 
 /* Alg. 2 steps 2-4 alone: b = F^{-1} C D F a (eq. matform) from the device grid `grid_in` to
- * the device grid `grid_out` (both m^3, z slowest; may alias). */
+ * the device grid `grid_out` (both m x my x mz, z slowest; may alias). */
 pswfe_status pswfe_transform(pswfe_plan* plan, const void* grid_in, void* grid_out, void* stream);
 
-/* Alg. 2 step 5 alone (eq. FastEwaldSteps34, eq. force) from the device grid `grid` (m^3):
+/* Alg. 2 step 5 alone (eq. FastEwaldSteps34, eq. force) from the device grid `grid` (m x my x mz):
  * phi = interpolated values (no self term), grad = device n x 3 gradients; either may be NULL. */
 pswfe_status pswfe_interpolate(pswfe_plan* plan, int64_t n, const void* pos, const void* grid,
                                void* phi, void* grad, void* stream);

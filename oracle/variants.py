@@ -23,6 +23,9 @@ The paper compares its PSWF split and PSWF window with the classical alternative
 
 Alg. 2 is then the same five steps as ``fast.fast_longrange``:
     s_k = h^6 Mhat(k) / (V prod_d phihat_d(k_d)^2),
+in a cuboid box [0, L) x [0, Ly) x [0, Lz) with m x my x mz grid points (Sec. 6.1, remark on cuboid
+domains; h^6 becomes prod_d h_d^2, and the window has the same P and c_w in grid units along each
+axis, alpha_d = P h_d / 2),
 with the modes outside a ball set to zero: the PSWF split's band |k| <= c_s L / (2 pi r_c), as
 in ``fast.scaling``; for the Gaussian split, which has no band, |k| <= m/2 (beyond it the
 corners of the grid's cube of modes multiply rounding errors by up to 1/phihat^2 in all three
@@ -36,7 +39,6 @@ from dataclasses import dataclass
 import numpy as np
 
 from .pswf import PSWF, gammahat, window_1d, window_1d_deriv, window_hat_1d
-from .direct import structure_factor, _exp_tables
 
 SPLITS = ("pswf", "gauss")
 WINDOWS = ("pswf", "gauss", "bspline")
@@ -52,6 +54,22 @@ class VariantParams:
     split: str = "pswf"
     window: str = "pswf"
     cg: float = 0.0    # Gaussian window shape (window == "gauss")
+    Ly: float | None = None   # cuboid sides and grid sizes along y and z (None: the x values)
+    Lz: float | None = None
+    my: int | None = None
+    mz: int | None = None
+
+    @property
+    def sides(self):
+        return (self.L, self.Ly or self.L, self.Lz or self.L)
+
+    @property
+    def grids(self):
+        return (self.m, self.my or self.m, self.mz or self.m)
+
+    @property
+    def hs(self):
+        return tuple(Ld / md for Ld, md in zip(self.sides, self.grids))
 
     @property
     def h(self) -> float:
@@ -136,30 +154,34 @@ def gauss_window_hat(omega, alpha: float, cg: float):
     return alpha * math.sqrt(math.pi / cg) * np.exp(-w * w * alpha * alpha / (4.0 * cg))
 
 
-def window_values(d, vp: VariantParams):
-    """Window and its x-derivative at offsets d = x - h l (any shape)."""
+def window_values(d, vp: VariantParams, axis: int = 0):
+    """Window along `axis` and its derivative at offsets d = x - h_d l (any shape)."""
+    h = vp.hs[axis]
+    alpha = vp.P * h / 2.0
     if vp.window == "pswf":
         pw = PSWF(vp.cw)
-        s = d / vp.alpha
-        return window_1d(s, pw), window_1d_deriv(s, pw) / vp.alpha
+        s = d / alpha
+        return window_1d(s, pw), window_1d_deriv(s, pw) / alpha
     if vp.window == "gauss":
-        s = d / vp.alpha
-        return gauss_window(s, vp.cg), gauss_window_deriv(s, vp.cg) / vp.alpha
+        s = d / alpha
+        return gauss_window(s, vp.cg), gauss_window_deriv(s, vp.cg) / alpha
     if vp.window == "bspline":
-        u = d / vp.h
-        return bspline(u, vp.P), bspline_deriv(u, vp.P) / vp.h
+        u = d / h
+        return bspline(u, vp.P), bspline_deriv(u, vp.P) / h
     raise ValueError(vp.window)
 
 
-def window_hat(k, vp: VariantParams):
-    """phihat_d at integer wave numbers k (the deconvolution factor of each dimension)."""
-    omega = 2.0 * math.pi * np.asarray(k, dtype=np.float64) / vp.L
+def window_hat(k, vp: VariantParams, axis: int = 0):
+    """phihat_d at integer wave numbers k along `axis` (the deconvolution factor of that axis)."""
+    L, m, h = vp.sides[axis], vp.grids[axis], vp.hs[axis]
+    alpha = vp.P * h / 2.0
+    omega = 2.0 * math.pi * np.asarray(k, dtype=np.float64) / L
     if vp.window == "pswf":
-        return window_hat_1d(omega, vp.alpha, PSWF(vp.cw))
+        return window_hat_1d(omega, alpha, PSWF(vp.cw))
     if vp.window == "gauss":
-        return gauss_window_hat(omega, vp.alpha, vp.cg)
+        return gauss_window_hat(omega, alpha, vp.cg)
     if vp.window == "bspline":
-        return vp.h * spme_factor(k, vp.m, vp.P)
+        return h * spme_factor(k, m, vp.P)
     raise ValueError(vp.window)
 
 
@@ -187,10 +209,18 @@ def self_coefficient(vp: VariantParams) -> float:
 
 
 def band_edge(vp: VariantParams) -> float:
-    """Largest |k| kept: the PSWF split's band edge c_s L / (2 pi r_c), or m/2 for the Gaussian split."""
+    """Largest |k| kept (cubes): the PSWF split's band edge c_s L / (2 pi r_c), or m/2 for the Gaussian split."""
     if vp.split == "pswf":
         return vp.cs * vp.L / (2.0 * math.pi * vp.rc)
     return vp.m / 2.0
+
+
+def band_omega(vp: VariantParams) -> float:
+    """Largest |w| kept: c_s / r_c for the PSWF split; pi / max_d h_d (the Nyquist frequency of the
+    coarsest axis, m/2 modes on a cube) for the Gaussian split."""
+    if vp.split == "pswf":
+        return vp.cs / vp.rc
+    return math.pi / max(vp.hs)
 
 
 # ---------------------------------------------------------------------------------------
@@ -203,53 +233,73 @@ def kvec(m: int) -> np.ndarray:
 
 
 def support(x, vp: VariantParams):
-    """Per particle and dimension: the P grid indices (mod m) l = floor(x/h - P/2) + 1 + j and the
-    window values and derivatives at x - h l."""
-    t = x / vp.h
-    start = np.floor(t - vp.P / 2.0).astype(np.int64) + 1
-    l = start[:, :, None] + np.arange(vp.P)[None, None, :]
-    w, dw = window_values(x[:, :, None] - vp.h * l, vp)
-    return np.mod(l, vp.m), w, dw
+    """Per particle and dimension: the P grid indices (mod m_d) l = floor(x/h_d - P/2) + 1 + j
+    and the window values and derivatives at x - h_d l."""
+    n = x.shape[0]
+    idx = np.empty((n, 3, vp.P), dtype=np.int64)
+    w = np.empty((n, 3, vp.P))
+    dw = np.empty((n, 3, vp.P))
+    for d in range(3):
+        h, m = vp.hs[d], vp.grids[d]
+        start = np.floor(x[:, d] / h - vp.P / 2.0).astype(np.int64) + 1
+        l = start[:, None] + np.arange(vp.P)[None, :]
+        w[:, d], dw[:, d] = window_values(x[:, d][:, None] - h * l, vp, d)
+        idx[:, d] = np.mod(l, m)
+    return idx, w, dw
 
 
 def scaling(vp: VariantParams) -> np.ndarray:
-    m, L, h = vp.m, vp.L, vp.h
-    k = kvec(m)
-    k2 = k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2
-    kn = np.sqrt(np.arange(int(k2.max()) + 1, dtype=np.float64))
-    mt = np.zeros(kn.size)
-    mt[1:] = mhat(2.0 * math.pi * kn[1:] / L, vp)
-    ph = window_hat(k, vp)
-    phihat = ph[:, None, None] * ph[None, :, None] * ph[None, None, :]
-    s = h ** 6 * mt[k2] / (L ** 3 * phihat ** 2)
-    s[0, 0, 0] = 0.0
-    kb = band_edge(vp)
-    s[k2 > kb * kb * (1.0 + 1e-12)] = 0.0
+    """s_k on the (m, my, mz) FFT bins: prod_d h_d^2 Mhat(|w|) / (V prod_d phihat_d^2), zero outside
+    the band and at k = 0. For cubes the band is the |k| ball of ``band_edge``."""
+    mx, my, mz = vp.grids
+    Lx, Ly, Lz = vp.sides
+    ks = [kvec(mm) for mm in vp.grids]
+    w2 = ((2 * math.pi * ks[0] / Lx) ** 2)[:, None, None] + ((2 * math.pi * ks[1] / Ly) ** 2)[None, :, None] \
+        + ((2 * math.pi * ks[2] / Lz) ** 2)[None, None, :]
+    pref = np.prod(np.square(vp.hs)) / (Lx * Ly * Lz)
+    cube = vp.sides[1] == vp.L and vp.sides[2] == vp.L and vp.grids[1] == vp.m and vp.grids[2] == vp.m
+    if cube:   # exactly the cube's |k| ball (the same test as before, in integers)
+        k2 = ks[0][:, None, None] ** 2 + ks[1][None, :, None] ** 2 + ks[2][None, None, :] ** 2
+        kb = band_edge(vp)
+        keep = (k2 > 0) & (k2 <= kb * kb * (1.0 + 1e-12))
+        kn = np.sqrt(np.arange(int(k2.max()) + 1, dtype=np.float64))
+        mt = np.zeros(kn.size)
+        mt[1:] = mhat(2.0 * math.pi * kn[1:] / vp.L, vp)
+        M = mt[k2]
+    else:
+        wb = band_omega(vp)
+        keep = (w2 > 0) & (w2 <= wb * wb * (1.0 + 1e-12))
+        M = np.zeros(w2.shape)
+        M[keep] = mhat(np.sqrt(w2[keep]), vp)
+    ph = [window_hat(ks[d], vp, d) for d in range(3)]
+    phihat = ph[0][:, None, None] * ph[1][None, :, None] * ph[2][None, None, :]
+    s = np.where(keep, pref * M / phihat ** 2, 0.0)
     return s
 
 
 def fast_variant(x, q, vp: VariantParams, grad: bool = True):
     """phi_far + phi_self (and grad phi_far) by the five steps of Alg. 2 with the chosen split
     and window, float64."""
-    x = np.mod(np.asarray(x, dtype=np.float64), vp.L)
+    x = np.mod(np.asarray(x, dtype=np.float64), np.asarray(vp.sides))
     q = np.asarray(q, dtype=np.float64)
-    m, P = vp.m, vp.P
+    mx, my, mz = vp.grids
+    P = vp.P
     idx, w, dw = support(x, vp)
-    a = np.zeros(m ** 3)                                       # step 1
+    a = np.zeros(mx * my * mz)                                 # step 1
     for jx in range(P):
         for jy in range(P):
             wxy = q * w[:, 0, jx] * w[:, 1, jy]
-            base = (idx[:, 0, jx] * m + idx[:, 1, jy]) * m
+            base = (idx[:, 0, jx] * my + idx[:, 1, jy]) * mz
             flat = (base[:, None] + idx[:, 2, :]).ravel()
-            a += np.bincount(flat, weights=(wxy[:, None] * w[:, 2, :]).ravel(), minlength=m ** 3)
-    ahat = np.fft.ifftn(a.reshape(m, m, m)) * m ** 3          # step 2 (e^{+})
-    b = np.fft.fftn(scaling(vp) * ahat).real.reshape(-1)      # steps 3-4 (e^{-})
+            a += np.bincount(flat, weights=(wxy[:, None] * w[:, 2, :]).ravel(), minlength=mx * my * mz)
+    ahat = np.fft.ifftn(a.reshape(mx, my, mz)) * (mx * my * mz)  # step 2 (e^{+})
+    b = np.fft.fftn(scaling(vp) * ahat).real.reshape(-1)        # steps 3-4 (e^{-})
     n = x.shape[0]
     phi = np.zeros(n)
     g = np.zeros((n, 3)) if grad else None
     for jx in range(P):                                        # step 5
         for jy in range(P):
-            base = (idx[:, 0, jx] * m + idx[:, 1, jy]) * m
+            base = (idx[:, 0, jx] * my + idx[:, 1, jy]) * mz
             vals = b[base[:, None] + idx[:, 2, :]]
             sz = np.einsum("np,np->n", vals, w[:, 2, :])
             phi += w[:, 0, jx] * w[:, 1, jy] * sz
@@ -262,31 +312,40 @@ def fast_variant(x, q, vp: VariantParams, grad: bool = True):
     return phi, g
 
 
-def far_direct_variant(x, q, vp: VariantParams, K: int, grad: bool = False):
-    """The split's Fourier series summed directly over 0 < |k| <= K (Alg. 1), plus the self
-    term: the reference the comparisons measure errors against (``reference_modes`` gives a K
-    whose neglected tail is far below the errors measured)."""
-    x = np.mod(np.asarray(x, dtype=np.float64), vp.L)
+def far_direct_variant(x, q, vp: VariantParams, K: int, grad: bool = False, chunk: int = 2048):
+    """The split's Fourier series summed directly over 0 < |w| <= 2 pi K / L_min (Alg. 1), plus the
+    self term: the reference the comparisons measure errors against (``reference_modes`` gives a
+    K whose neglected tail is far below the errors measured). On a cube: 0 < |k| <= K."""
+    x = np.mod(np.asarray(x, dtype=np.float64), np.asarray(vp.sides))
     q = np.asarray(q, dtype=np.float64)
-    L = vp.L
-    a = np.arange(-K, K + 1)
-    k2 = a[:, None, None] ** 2 + a[None, :, None] ** 2 + a[None, None, :] ** 2
-    keep = (k2 > 0) & (k2 <= K * K)
-    kn = np.sqrt(np.arange(K * K + 1, dtype=np.float64))
-    mt = np.zeros(kn.size)
-    mt[1:] = mhat(2.0 * math.pi * kn[1:] / L, vp)
-    B = np.where(keep, mt[np.minimum(k2, K * K)], 0.0) * structure_factor(x, q, L, K) / L ** 3
-    ex, ey, ez = [t.conj() for t in _exp_tables(x, L, K)]
+    Ls = vp.sides
+    wK = 2.0 * math.pi * K / min(Ls)
+    Kd = [int(math.ceil(wK * Ld / (2.0 * math.pi) * (1.0 + 1e-12))) for Ld in Ls]
+    ax = [np.arange(-k, k + 1) for k in Kd]
+    wd = [2.0 * math.pi * a / Ld for a, Ld in zip(ax, Ls)]
+    w2 = wd[0][:, None, None] ** 2 + wd[1][None, :, None] ** 2 + wd[2][None, None, :] ** 2
+    keep = (w2 > 0) & (w2 <= wK * wK * (1.0 + 1e-12))
+    M = np.zeros(w2.shape)
+    M[keep] = mhat(np.sqrt(w2[keep]), vp)
+    # rhohat(k) = sum_j q_j e^{+i w.x_j}, per-axis exponential tables, summed in chunks
+    rho = np.zeros(w2.shape, dtype=np.complex128)
+    for s0 in range(0, x.shape[0], chunk):
+        e = [np.exp(1j * np.multiply.outer(x[s0:s0 + chunk, d], wd[d])) for d in range(3)]
+        qq = q[s0:s0 + chunk]
+        for ia in range(len(ax[0])):
+            A = (qq * e[0][:, ia])[:, None] * e[1]
+            rho[ia] += A.T @ e[2]
+    B = M * rho / (Ls[0] * Ls[1] * Ls[2])
+    ex, ey, ez = [np.exp(-1j * np.multiply.outer(x[:, d], wd[d])) for d in range(3)]
     t1 = np.einsum("abc,tc->tab", B, ez, optimize=True)
     t2 = np.einsum("tab,tb->ta", t1, ey)
     phi = np.einsum("ta,ta->t", t2, ex).real - self_coefficient(vp) * q
     g = None
     if grad:
-        ik = -1j * 2.0 * math.pi / L * a
         g = np.zeros((x.shape[0], 3))
-        g[:, 0] = np.einsum("ta,ta->t", t2 * ik[None, :], ex).real
-        g[:, 1] = np.einsum("ta,ta->t", np.einsum("tab,tb->ta", t1, ey * ik[None, :]), ex).real
-        t1z = np.einsum("abc,tc->tab", B * ik[None, None, :], ez, optimize=True)
+        g[:, 0] = np.einsum("ta,ta->t", t2 * (-1j * wd[0])[None, :], ex).real
+        g[:, 1] = np.einsum("ta,ta->t", np.einsum("tab,tb->ta", t1, ey * (-1j * wd[1])[None, :]), ex).real
+        t1z = np.einsum("abc,tc->tab", B * (-1j * wd[2])[None, None, :], ez, optimize=True)
         g[:, 2] = np.einsum("ta,ta->t", np.einsum("tab,tb->ta", t1z, ey), ex).real
     return phi, g
 
@@ -295,7 +354,29 @@ def reference_modes(vp: VariantParams, tail: float = 1e-16) -> int:
     """K for ``far_direct_variant``: for the PSWF split 4.7 times the band edge (as route R1 of
     ``direct``: the split's out-of-band tail decays slowly); for the Gaussian split the |k| at
     which exp(-sigma^2 w^2 / 4) falls below `tail`."""
+    Lmin = min(vp.sides)
     if vp.split == "pswf":
-        return int(math.ceil(4.7 * vp.cs * vp.L / (2.0 * math.pi * vp.rc)))
+        return int(math.ceil(4.7 * vp.cs * Lmin / (2.0 * math.pi * vp.rc)))
     w = 2.0 * math.sqrt(math.log(1.0 / tail)) / vp.sigma
-    return int(math.ceil(w * vp.L / (2.0 * math.pi)))
+    return int(math.ceil(w * Lmin / (2.0 * math.pi)))
+
+
+def box_params(eps: float, sides, rc: float, tol_mode: str = "rel", q_l2: float = 0.0, n: int = 0,
+               m: int | None = None):
+    """Parameters for a cuboid box (Sec. 6.1, remark on cuboid domains): the cube of side
+    L_min = min(sides) with the same particle and charge densities (n and ||rho||^2 scaled by
+    L_min^3 / V) is parameterised by Alg. 3 (oracle/params.py), giving r_c, c_s, P and
+    h = L_min / m; each axis then takes the smallest even 2,3,5,7-smooth m_d with L_d / m_d <= h."""
+    from . import params as oparams
+    Lx, Ly, Lz = (float(v) for v in sides)
+    Lmin = min(Lx, Ly, Lz)
+    ratio = Lmin ** 3 / (Lx * Ly * Lz)
+    kw = dict(rc=rc, tol_mode=tol_mode)
+    if tol_mode == "abs":
+        kw["q_l2"] = q_l2 * math.sqrt(ratio)
+    if m is not None:
+        kw["m"] = m
+    p = oparams.choose(eps, Lmin, **kw)
+    h = Lmin / p.m
+    ms = [oparams.next_smooth_even(int(math.ceil(Ld / h - 1e-9))) for Ld in (Lx, Ly, Lz)]
+    return VariantParams(Lx, p.rc, p.cs, ms[0], p.P, Ly=Ly, Lz=Lz, my=ms[1], mz=ms[2])

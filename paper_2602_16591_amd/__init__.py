@@ -11,6 +11,7 @@ Sec. 4 PSWF mollifier and window, Alg. 3 parameter selection).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass
 
@@ -35,7 +36,8 @@ class CParams(ctypes.Structure):
                 ("h", ctypes.c_double), ("lambda0_s", ctypes.c_double), ("cs_alg", ctypes.c_double),
                 ("cw_alg", ctypes.c_double), ("alpha_alg", ctypes.c_double), ("m", ctypes.c_int32),
                 ("P", ctypes.c_int32), ("tol_mode", ctypes.c_int32), ("split", ctypes.c_int32),
-                ("window", ctypes.c_int32), ("reserved", ctypes.c_int32), ("cg", ctypes.c_double)]
+                ("window", ctypes.c_int32), ("reserved", ctypes.c_int32), ("cg", ctypes.c_double),
+                ("Ly", ctypes.c_double), ("Lz", ctypes.c_double), ("my", ctypes.c_int32), ("mz", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -46,6 +48,7 @@ _vp, _i64, _i32, _d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_
 _PPlan = ctypes.POINTER(ctypes.c_void_p)
 SIGNATURES = {
     "pswfe_choose_params": (ctypes.c_int, [_d, _d, _d, _i32, _i64, _d, _i32, ctypes.POINTER(CParams)]),
+    "pswfe_choose_params_box": (ctypes.c_int, [_d, _d, _d, _d, _d, _i32, _i64, _d, _i32, ctypes.POINTER(CParams)]),
     "pswfe_variant_params": (ctypes.c_int, [_i32, _i32, _d, _d, _d, _i32, _i32, _d, _d, ctypes.POINTER(CParams)]),
     "pswfe_plan_create": (ctypes.c_int, [ctypes.POINTER(CParams), _i32, _i64, _PPlan]),
     "pswfe_plan_create_tiled": (ctypes.c_int, [ctypes.POINTER(CParams), _i32, _i64, _i32, _PPlan]),
@@ -109,6 +112,17 @@ def choose_params(eps: float, L: float, *, rc: float = 0.0, m: int = 0, n: int =
     out = CParams()
     _check(_lib().pswfe_choose_params(float(eps), float(L), float(rc), int(m), int(n), float(q_l2), int(mode),
                                       ctypes.byref(out)), "pswfe_choose_params")
+    return out
+
+
+def choose_params_box(eps: float, box, *, rc: float = 0.0, m: int = 0, n: int = 0, q_l2: float = 0.0,
+                      tol_mode: int | str = TOL_REL) -> CParams:
+    """Alg. 3 for a cuboid box (Lx, Ly, Lz) (host only); m is the grid size along the shortest side."""
+    Lx, Ly, Lz = (float(v) for v in box)
+    mode = {"rel": TOL_REL, "abs": TOL_ABS}.get(tol_mode, tol_mode)
+    out = CParams()
+    _check(_lib().pswfe_choose_params_box(float(eps), Lx, Ly, Lz, float(rc), int(m), int(n), float(q_l2), int(mode),
+                                          ctypes.byref(out)), "pswfe_choose_params_box")
     return out
 
 
@@ -262,6 +276,12 @@ class Plan(_PlanBase):
     def m(self) -> int:
         return self.params.m
 
+    @property
+    def grid_shape(self):
+        """(mz, my, m): the grids' layout, x fastest (a cube: (m, m, m))."""
+        p = self.params
+        return (p.mz or p.m, p.my or p.m, p.m)
+
     def _n(self, pos):
         n = int(pos.shape[0])
         if n > self.n_max:
@@ -302,8 +322,7 @@ class Plan(_PlanBase):
     def spread(self, pos, q, grid=None, stream=None):
         import torch
         n = self._n(pos)
-        m = self.m
-        grid = torch.empty((m, m, m), dtype=self.dtype, device=pos.device) if grid is None else grid
+        grid = torch.empty(self.grid_shape, dtype=self.dtype, device=pos.device) if grid is None else grid
         _check(_lib().pswfe_spread(self._h, n, _ptr(pos, self.dtype, (3,), "pos"), _ptr(q, self.dtype, None, "q"),
                                    _ptr(grid, self.dtype, None, "grid"), _stream_ptr(stream)), "pswfe_spread")
         return grid
@@ -311,8 +330,9 @@ class Plan(_PlanBase):
     def transform(self, grid_in, grid_out=None, stream=None):
         import torch
         grid_out = torch.empty_like(grid_in) if grid_out is None else grid_out
-        if grid_in.numel() != self.m ** 3 or grid_out.numel() != self.m ** 3:
-            raise ValueError("grids must have m^3 entries")
+        size = math.prod(self.grid_shape)
+        if grid_in.numel() != size or grid_out.numel() != size:
+            raise ValueError(f"grids must have {size} entries")
         _check(_lib().pswfe_transform(self._h, _ptr(grid_in, self.dtype, None, "grid_in"),
                                       _ptr(grid_out, self.dtype, None, "grid_out"), _stream_ptr(stream)),
                "pswfe_transform")
@@ -321,8 +341,8 @@ class Plan(_PlanBase):
     def interpolate(self, pos, grid, stream=None):
         import torch
         n = self._n(pos)
-        if grid.numel() != self.m ** 3:
-            raise ValueError("grid must have m^3 entries")
+        if grid.numel() != math.prod(self.grid_shape):
+            raise ValueError(f"grid must have {math.prod(self.grid_shape)} entries")
         phi = torch.empty(n, dtype=self.dtype, device=pos.device)
         g = torch.empty((n, 3), dtype=self.dtype, device=pos.device)
         _check(_lib().pswfe_interpolate(self._h, n, _ptr(pos, self.dtype, (3,), "pos"),

@@ -51,6 +51,10 @@ void to_c(const pswfe::Params& p, pswfe_params* o) {
   o->window = p.window;
   o->reserved = 0;
   o->cg = p.cg;
+  o->Ly = p.side(1);
+  o->Lz = p.side(2);
+  o->my = p.grid(1);
+  o->mz = p.grid(2);
 }
 
 pswfe::FftPlan make_fft_plan(int N) {
@@ -156,8 +160,11 @@ void free_plan(pswfe_plan* plan) {
 
 pswfe_status params_from_c(const pswfe_params* pp, pswfe::Params* p) {
   const int m = pp->m, P = pp->P;
-  if (!pswfe::is_smooth_even(m) || m < 8 || m > 512 || P < pswfe::kPmin || P > pswfe::kPmax || P > m)
-    return PSWFE_E_GRID;
+  const int my = pp->my > 0 ? pp->my : m, mz = pp->mz > 0 ? pp->mz : m;
+  for (int md : {m, my, mz})
+    if (!pswfe::is_smooth_even(md) || md < 8 || md > 512 || P > md) return PSWFE_E_GRID;
+  if (pp->my < 0 || pp->mz < 0 || P < pswfe::kPmin || P > pswfe::kPmax) return PSWFE_E_GRID;
+  if (pp->Ly < 0 || pp->Lz < 0 || !std::isfinite(pp->Ly) || !std::isfinite(pp->Lz)) return PSWFE_E_ARG;
   if (!(pp->L > 0) || !(pp->rc > 0) || !(pp->cs > 0) || !(pp->cw > 0) || !(pp->alpha > 0) || !(pp->eps > 0))
     return PSWFE_E_ARG;
   if (pp->split != PSWFE_SPLIT_PSWF && pp->split != PSWFE_SPLIT_GAUSS) return PSWFE_E_ARG;
@@ -168,6 +175,10 @@ pswfe_status params_from_c(const pswfe_params* pp, pswfe::Params* p) {
   p->split = pp->split;
   p->window = pp->window;
   p->cg = pp->cg;
+  p->Ly = pp->Ly > 0 ? pp->Ly : pp->L;
+  p->Lz = pp->Lz > 0 ? pp->Lz : pp->L;
+  p->my = my;
+  p->mz = mz;
   p->L = pp->L;
   p->eps = pp->eps;
   p->rc = pp->rc;
@@ -222,6 +233,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   d.nsys = nsys;
   d.sys.resize(nsys);
   std::vector<int> xblk_prefix(nsys + 1, 0), cblk_prefix(nsys + 1, 0), pblk_prefix(nsys + 1, 0);
+  std::vector<int> zblk_prefix(nsys + 1, 0);
   // x and y FFTs fused per z-plane (PSWFE_PLANE_FFT=1) when every system's plane (two padded
   // copies of its half spectrum plus twiddles) fits in LDS. Off by default: measured on MI355X,
   // one workgroup per plane (64-128 of them) costs as much as the two separate passes it saves a
@@ -234,7 +246,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   int fft_env = 0;
   if (const char* env = std::getenv("PSWFE_FFT_ELEMS")) fft_env = std::max(64, std::min(4096, std::atoi(env)));
   Arena work, tabs;
-  struct TabOff { size_t coef, tm, wk, twhp, twhm, twfp, twfm, lcoef; };
+  struct TabOff { size_t coef, tm, wk, wky, wkz, twhp, twhm, twfp, twfm, twyp, twym, twzp, twzm, lcoef, rpoly; };
   int cell_prefix = 0;
   std::vector<int> cell_prefix_v(nsys + 1, 0);
   struct WorkOff { size_t a, b, spec; };
@@ -251,7 +263,8 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
       plan->local_ok = false;
     }
     pswfe::SysDesc& sd = d.sys[s];
-    const int m = p.m, N = m / 2, nx1 = N + 1;
+    const int m = p.m, N = m / 2, nx1 = N + 1, my = p.grid(1), mz = p.grid(2);
+    const int mmin = std::min(m, std::min(my, mz)), mlen = std::max(my, mz);
     if (counts) {
       if (counts[s] < 0) {
         free_plan(plan);
@@ -261,33 +274,56 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
       plan->count.push_back(counts[s]);
     }
     const int req = tiles ? tiles[s] : 0;
-    if (req < 0 || req > m) {
+    if (req < 0 || req > mmin) {
       free_plan(plan);
       return PSWFE_E_ARG;
     }
     const int P = p.P;
     sd.m = m;
+    sd.my = my;
+    sd.mz = mz;
     sd.P = P;
     sd.deg = t.deg;
-    sd.B = choose_tile(m, P, req, elem, counts ? counts[s] : -1);
+    sd.B = choose_tile(mmin, P, req, elem, counts ? counts[s] : -1);
     sd.Tn = (m + sd.B - 1) / sd.B;
+    sd.Tny = (my + sd.B - 1) / sd.B;
+    sd.Tnz = (mz + sd.B - 1) / sd.B;
     sd.S = lds_edge(sd.B, P);
-    sd.L = p.L;
-    sd.inv_h = m / p.L;
-    const long double ih = static_cast<long double>(m) / static_cast<long double>(p.L);
-    if (prec == PSWFE_FP32) {
-      const float hi = static_cast<float>(ih);
-      sd.ih_hi = hi;
-      sd.ih_lo = static_cast<float>(ih - static_cast<long double>(hi));
-    } else {
-      const double hi = static_cast<double>(ih);
-      sd.ih_hi = hi;
-      sd.ih_lo = static_cast<double>(ih - static_cast<long double>(hi));
-    }
+    sd.L = p.side(0);
+    sd.Ly = p.side(1);
+    sd.Lz = p.side(2);
+    // 1/h_d split into a high and a low word of the plan precision (exact product error)
+    auto inv_spacing = [&](int md, double Ld, double* inv, double* hi_out, double* lo_out) {
+      *inv = md / Ld;
+      const long double ih = static_cast<long double>(md) / static_cast<long double>(Ld);
+      if (prec == PSWFE_FP32) {
+        const float hi = static_cast<float>(ih);
+        *hi_out = hi;
+        *lo_out = static_cast<float>(ih - static_cast<long double>(hi));
+      } else {
+        const double hi = static_cast<double>(ih);
+        *hi_out = hi;
+        *lo_out = static_cast<double>(ih - static_cast<long double>(hi));
+      }
+    };
+    inv_spacing(m, sd.L, &sd.inv_h, &sd.ih_hi, &sd.ih_lo);
+    inv_spacing(my, sd.Ly, &sd.inv_hy, &sd.ihy_hi, &sd.ihy_lo);
+    inv_spacing(mz, sd.Lz, &sd.inv_hz, &sd.ihz_hi, &sd.ihz_lo);
     sd.self_coef = t.self_coef;
+    sd.radial = t.radial;
+    sd.rleg_n = t.radial == 1 ? static_cast<int>(t.rpoly.size()) - 1 : 0;
+    sd.w2x = (2.0 * M_PI / sd.L) * (2.0 * M_PI / sd.L);
+    sd.w2y = (2.0 * M_PI / sd.Ly) * (2.0 * M_PI / sd.Ly);
+    sd.w2z = (2.0 * M_PI / sd.Lz) * (2.0 * M_PI / sd.Lz);
+    sd.rscale = t.rscale;
+    sd.rpref = t.rpref;
+    sd.rband2 = t.rband2;
+    sd.rsig2 = t.rsig2;
     sd.fh = make_fft_plan(N);
     sd.ff = make_fft_plan(m);
-    if (sd.fh.nst < 0 || sd.ff.nst < 0) {
+    sd.ffy = make_fft_plan(my);
+    sd.ffz = make_fft_plan(mz);
+    if (sd.fh.nst < 0 || sd.ff.nst < 0 || sd.ffy.nst < 0 || sd.ffz.nst < 0) {
       free_plan(plan);
       return PSWFE_E_GRID;
     }
@@ -296,8 +332,8 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     const int fft_elems = fft_env > 0 ? fft_env : (m <= 96 ? 1024 : 2048);
     int rpb = std::max(1, std::min(64, fft_elems / nx1));
     while (rpb > 1 && (2 * static_cast<size_t>(rpb) * nx1 + 2 * N + 1) * celem > 64 * 1024) --rpb;
-    int cmax = std::max(1, std::min(64, fft_elems / (m + 1)));
-    while (cmax > 1 && (2 * static_cast<size_t>(cmax) * (m + 1) + 2 * m) * celem > 64 * 1024) --cmax;
+    int cmax = std::max(1, std::min(64, fft_elems / (mlen + 1)));
+    while (cmax > 1 && (2 * static_cast<size_t>(cmax) * (mlen + 1) + 2 * mlen) * celem > 64 * 1024) --cmax;
     const int nxb = (nx1 + cmax - 1) / cmax;
     sd.rows_per_block = rpb;
     sd.cols_per_block = (nx1 + nxb - 1) / nxb;
@@ -307,31 +343,40 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     {
       const size_t lds_plane = (2 * static_cast<size_t>(nx1) * (m + 1) + N + m) * celem;
       d.lds_p = std::max(d.lds_p, lds_plane);
-      if (lds_plane > kLdsLimit) plane_ok = false;
+      if (lds_plane > kLdsLimit || !p.cubic()) plane_ok = false;
     }
     sd.cblk_base = cblk_prefix[s];
+    sd.zblk_base = zblk_prefix[s];
     sd.part_base = part_prefix[s];
-    xblk_prefix[s + 1] = xblk_prefix[s] + (m * m + rpb - 1) / rpb;
-    cblk_prefix[s + 1] = cblk_prefix[s] + ((nx1 + sd.cols_per_block - 1) / sd.cols_per_block) * m;
+    const int ncb = (nx1 + sd.cols_per_block - 1) / sd.cols_per_block;
+    xblk_prefix[s + 1] = xblk_prefix[s] + (my * mz + rpb - 1) / rpb;
+    cblk_prefix[s + 1] = cblk_prefix[s] + ncb * mz;  // y passes: one row of blocks per z plane
+    zblk_prefix[s + 1] = zblk_prefix[s] + ncb * my;  // z pass: one per y row
     // data buffers plus the twiddle tables the kernels copy into LDS
     d.lds_x = std::max(d.lds_x, (2 * static_cast<size_t>(rpb) * nx1 + 2 * N + 1) * celem);
-    d.lds_c = std::max(d.lds_c, (2 * static_cast<size_t>(sd.cols_per_block) * (m + 1) + 2 * m) * celem);
-    const size_t m3 = static_cast<size_t>(m) * m * m;
+    d.lds_c = std::max(d.lds_c, (2 * static_cast<size_t>(sd.cols_per_block) * (mlen + 1) + 2 * mlen) * celem);
+    const size_t m3 = static_cast<size_t>(m) * my * mz;
     woff[s] = {work.take(sizeof(double) * m3), work.take(elem * m3),
-               work.take(celem * static_cast<size_t>(m) * m * nx1)};
-    // real-space cells of edge L / nc >= r_c (at most 128 per dimension)
+               work.take(celem * static_cast<size_t>(mz) * my * nx1)};
+    // real-space cells of edge L_d / nc_d >= r_c (at most 128 per dimension); one cell holding
+    // the whole system when any dimension has fewer than 3
     sd.rc = p.rc;
     sd.lK = plan->ltab[s].K;
     sd.ldeg = plan->ltab[s].deg;
-    sd.nc = std::max(1, std::min(128, static_cast<int>(std::floor(p.L / p.rc))));
-    if (sd.nc < 3) sd.nc = 1;
+    sd.nc = std::max(1, std::min(128, static_cast<int>(std::floor(sd.L / p.rc))));
+    sd.ncy = std::max(1, std::min(128, static_cast<int>(std::floor(sd.Ly / p.rc))));
+    sd.ncz = std::max(1, std::min(128, static_cast<int>(std::floor(sd.Lz / p.rc))));
+    if (sd.nc < 3 || sd.ncy < 3 || sd.ncz < 3) sd.nc = sd.ncy = sd.ncz = 1;
     sd.cell_base = cell_prefix;
-    cell_prefix += sd.nc * sd.nc * sd.nc;
+    cell_prefix += sd.nc * sd.ncy * sd.ncz;
     cell_prefix_v[s + 1] = cell_prefix;
-    if (!(p.rc < 0.5 * p.L)) plan->local_ok = false;
+    if (!(p.rc < 0.5 * std::min(sd.L, std::min(sd.Ly, sd.Lz)))) plan->local_ok = false;
     toff[s] = {tabs.take(sizeof(double) * t.coef.size()), tabs.take(elem * t.tm.size()),
-               tabs.take(elem * t.w.size()), tabs.take(celem * N), tabs.take(celem * N), tabs.take(celem * m),
-               tabs.take(celem * m), tabs.take(sizeof(double) * plan->ltab[s].coef.size())};
+               tabs.take(elem * t.w.size()), tabs.take(elem * t.wy.size()), tabs.take(elem * t.wz.size()),
+               tabs.take(celem * N), tabs.take(celem * N), tabs.take(celem * m), tabs.take(celem * m),
+               tabs.take(celem * my), tabs.take(celem * my), tabs.take(celem * mz), tabs.take(celem * mz),
+               tabs.take(sizeof(double) * plan->ltab[s].coef.size()),
+               tabs.take(sizeof(double) * std::max<size_t>(1, t.rpoly.size()))};
   }
   // Global tile order: systems grouped by P (stable), so each P's tiles are one contiguous
   // range covered by one launch of the particle kernels.
@@ -348,7 +393,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     pswfe::SysDesc& sd = d.sys[order[k]];
     const int D = pswfe::degree_bucket(sd.deg);
     sd.tile_base = tile_prefix[k];
-    tile_prefix[k + 1] = tile_prefix[k] + sd.Tn * sd.Tn * sd.Tn;
+    tile_prefix[k + 1] = tile_prefix[k] + sd.Tn * sd.Tny * sd.Tnz;
     if (d.groups.empty() || d.groups.back().P != sd.P || d.groups.back().D != D ||
         d.groups.back().col_tile != cols(order[k])) {
       pswfe::PGroup g;
@@ -389,6 +434,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   d.total_tiles = tile_prefix[nsys];
   d.total_xblk = xblk_prefix[nsys];
   d.total_pblk = pblk_prefix[nsys];
+  d.total_zblk = zblk_prefix[nsys];
   d.plane_fft = plane_ok ? 1 : 0;
   d.total_cblk = cblk_prefix[nsys];
   d.n_max = counts ? part_prefix[nsys] : n_max;
@@ -440,6 +486,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   d.lperm = static_cast<int*>(alloc(sizeof(int) * nm));
   d.xblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
   d.pblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
+  d.zblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
   d.cblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
   d.part_prefix = static_cast<int64_t*>(alloc(sizeof(int64_t) * (nsys + 1)));
   if (st != PSWFE_OK) {
@@ -457,33 +504,48 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     sd.coef = reinterpret_cast<const double*>(tab_dev + toff[s].coef);
     sd.tm = tab_dev + toff[s].tm;
     sd.wk = tab_dev + toff[s].wk;
+    sd.wky = tab_dev + toff[s].wky;
+    sd.wkz = tab_dev + toff[s].wkz;
     sd.twhp = tab_dev + toff[s].twhp;
     sd.twhm = tab_dev + toff[s].twhm;
     sd.twfp = tab_dev + toff[s].twfp;
     sd.twfm = tab_dev + toff[s].twfm;
+    sd.twyp = tab_dev + toff[s].twyp;
+    sd.twym = tab_dev + toff[s].twym;
+    sd.twzp = tab_dev + toff[s].twzp;
+    sd.twzm = tab_dev + toff[s].twzm;
     sd.lcoef = reinterpret_cast<const double*>(tab_dev + toff[s].lcoef);
+    sd.rleg = reinterpret_cast<const double*>(tab_dev + toff[s].rpoly);
     put<double>(img, toff[s].lcoef, plan->ltab[s].coef);
-    std::vector<double> twhp, twhm, twfp, twfm;
+    put<double>(img, toff[s].rpoly, t.rpoly.empty() ? std::vector<double>(1, 0.0) : t.rpoly);
+    std::vector<double> twhp, twhm, twfp, twfm, twyp, twym, twzp, twzm;
     pswfe::twiddles(N, +1, &twhp);
     pswfe::twiddles(N, -1, &twhm);
     pswfe::twiddles(m, +1, &twfp);
     pswfe::twiddles(m, -1, &twfm);
+    pswfe::twiddles(sd.my, +1, &twyp);
+    pswfe::twiddles(sd.my, -1, &twym);
+    pswfe::twiddles(sd.mz, +1, &twzp);
+    pswfe::twiddles(sd.mz, -1, &twzm);
     put<double>(img, toff[s].coef, t.coef);  // window polynomials: float64 in both precisions
-    if (prec == PSWFE_FP32) {
-      put<float>(img, toff[s].tm, t.tm);
-      put<float>(img, toff[s].wk, t.w);
-      put<float>(img, toff[s].twhp, twhp);
-      put<float>(img, toff[s].twhm, twhm);
-      put<float>(img, toff[s].twfp, twfp);
-      put<float>(img, toff[s].twfm, twfm);
-    } else {
-      put<double>(img, toff[s].tm, t.tm);
-      put<double>(img, toff[s].wk, t.w);
-      put<double>(img, toff[s].twhp, twhp);
-      put<double>(img, toff[s].twhm, twhm);
-      put<double>(img, toff[s].twfp, twfp);
-      put<double>(img, toff[s].twfm, twfm);
-    }
+    auto put_real = [&](size_t off, const std::vector<double>& v) {
+      if (prec == PSWFE_FP32)
+        put<float>(img, off, v);
+      else
+        put<double>(img, off, v);
+    };
+    put_real(toff[s].tm, t.tm);
+    put_real(toff[s].wk, t.w);
+    put_real(toff[s].wky, t.wy);
+    put_real(toff[s].wkz, t.wz);
+    put_real(toff[s].twhp, twhp);
+    put_real(toff[s].twhm, twhm);
+    put_real(toff[s].twfp, twfp);
+    put_real(toff[s].twfm, twfm);
+    put_real(toff[s].twyp, twyp);
+    put_real(toff[s].twym, twym);
+    put_real(toff[s].twzp, twzp);
+    put_real(toff[s].twzm, twzm);
   }
   // grid_a must start (and is kept) all-zero; the rest of the work arena needs no value.
   bool ok = hipMemcpy(tab_dev, img.data(), tabs.size, hipMemcpyHostToDevice) == hipSuccess &&
@@ -499,6 +561,8 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
             hipMemcpy(d.xblk_prefix, xblk_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
                 hipSuccess &&
             hipMemcpy(d.pblk_prefix, pblk_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
+                hipSuccess &&
+            hipMemcpy(d.zblk_prefix, zblk_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
                 hipSuccess &&
             hipMemcpy(d.cblk_prefix, cblk_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
                 hipSuccess &&
@@ -538,6 +602,16 @@ pswfe_status pswfe_choose_params(double eps, double L, double rc, int32_t m, int
   if (!out) return PSWFE_E_ARG;
   pswfe::Params p{};
   const int rcode = pswfe::choose_params(eps, L, rc, m, n, q_l2, tol_mode, &p);
+  if (rcode != 0) return static_cast<pswfe_status>(rcode);
+  to_c(p, out);
+  return PSWFE_OK;
+}
+
+pswfe_status pswfe_choose_params_box(double eps, double Lx, double Ly, double Lz, double rc, int32_t m, int64_t n,
+                                     double q_l2, int32_t tol_mode, pswfe_params* out) {
+  if (!out) return PSWFE_E_ARG;
+  pswfe::Params p{};
+  const int rcode = pswfe::choose_params_box(eps, Lx, Ly, Lz, rc, m, n, q_l2, tol_mode, &p);
   if (rcode != 0) return static_cast<pswfe_status>(rcode);
   to_c(p, out);
   return PSWFE_OK;

@@ -164,7 +164,8 @@ __device__ __forceinline__ int fold_index(int a, int m) {
 // are needed. The (x, y, z) offsets advance by the stride's digits instead of being divided
 // out of the flat index.
 template <int K, class Load, class Use>
-__device__ __forceinline__ void walk_tile(int S, int m, int Ox, int Oy, int Oz, Load&& load, Use&& use) {
+__device__ __forceinline__ void walk_tile(int S, int m, int my, int mz, int Ox, int Oy, int Oz, Load&& load,
+                                          Use&& use) {
   const int S2 = S * S, S3 = S2 * S;
   const int nt = blockDim.x;
   const int sz = nt / S2, sy = (nt - sz * S2) / S, sx = nt - sz * S2 - sy * S;
@@ -176,7 +177,7 @@ __device__ __forceinline__ void walk_tile(int S, int m, int Ox, int Oy, int Oz, 
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       li[k] = base + nt * k;
-      gi[k] = (static_cast<int64_t>(fold_index(Oz + iz, m)) * m + fold_index(Oy + iy, m)) * m + fold_index(Ox + ix, m);
+      gi[k] = (static_cast<int64_t>(fold_index(Oz + iz, mz)) * my + fold_index(Oy + iy, my)) * m + fold_index(Ox + ix, m);
       ix += sx;
       if (ix >= S) {
         ix -= S;

@@ -302,6 +302,34 @@ std::vector<long double> cheb_fit_monomial(F f, int deg) {
 
 }  // namespace
 
+int choose_params_box(double eps, double Lx, double Ly, double Lz, double rc, int m, int64_t n, double q_l2,
+                      int tol_mode, Params* out) {
+  if (!out || !(Lx > 0.0) || !(Ly > 0.0) || !(Lz > 0.0) || !std::isfinite(Lx) || !std::isfinite(Ly) ||
+      !std::isfinite(Lz))
+    return 1;
+  const double Lmin = std::min(Lx, std::min(Ly, Lz));
+  const double ratio = Lmin * Lmin * Lmin / (Lx * Ly * Lz);  // volume of the cube / volume of the box
+  const int64_t n_cube = n > 0 ? std::max<int64_t>(1, static_cast<int64_t>(std::llround(n * ratio))) : n;
+  const int rcode = choose_params(eps, Lmin, rc, m, n_cube, q_l2 * std::sqrt(ratio), tol_mode, out);
+  if (rcode != 0) return rcode;
+  const double h = Lmin / out->m;
+  const double Ls[3] = {Lx, Ly, Lz};
+  int ms[3];
+  for (int d = 0; d < 3; ++d) {
+    ms[d] = next_smooth_even(static_cast<int>(std::ceil(Ls[d] / h - 1e-9)));
+    if (ms[d] > 512) return 3;
+  }
+  out->L = Lx;
+  out->Ly = Ly;
+  out->Lz = Lz;
+  out->m = ms[0];
+  out->my = ms[1];
+  out->mz = ms[2];
+  out->h = Lx / ms[0];
+  out->alpha = 0.5 * out->P * out->h;
+  return 0;
+}
+
 double default_gauss_shape(int P) { return 0.8 * kPi * P / 2.0; }
 
 // Values M_{k+1}(t + r), r = 0..k, of the uniform B-spline of order k + 1 on [0, k + 1) at the
@@ -373,21 +401,67 @@ void build_tables(const Params& p, int deg, double fit_tol, Tables* t) {
   //  Gaussian: the free-space transform alpha sqrt(pi / c_g) exp(-w^2 alpha^2 / (4 c_g));
   //  B-spline: h sum_j B_P(j) cos(2 pi k j / m), the periodised transform sum_p h B_P^(h w + 2 pi p)
   //  by Poisson summation (the SPME scaling).
-  t->w.assign(half + 1, 0.0);
-  for (int k = 0; k <= half; ++k) {
-    const double w = 2.0 * kPi * k / L;
-    double ph = 0.0;
-    if (p.window == kWindowPswf) {
-      ph = p.alpha * pw.lambda0 * pw.psi(2.0 * k / m) / pw.psi_0;
-    } else if (p.window == kWindowGauss) {
-      ph = p.alpha * std::sqrt(kPi / p.cg) * std::exp(-w * w * p.alpha * p.alpha / (4.0 * p.cg));
-    } else {
-      long double acc = 0.0L;
-      for (int j = -(P / 2); j <= P / 2; ++j)
-        acc += bspline(P, static_cast<long double>(j)) * std::cos(2.0L * static_cast<long double>(kPi) * k * j / m);
-      ph = h * static_cast<double>(acc);
+  // One table per dimension d, with m_d, L_d, h_d = L_d / m_d and alpha_d = P h_d / 2 (on a
+  // cuboid the window has the same P and c_w in grid units along every dimension).
+  auto window_factors = [&](int d, std::vector<double>* out) {
+    const int md = p.grid(d);
+    const double Ld = p.side(d), hd = Ld / md, ad = 0.5 * P * hd;
+    out->assign(md / 2 + 1, 0.0);
+    for (int k = 0; k <= md / 2; ++k) {
+      const double w = 2.0 * kPi * k / Ld;
+      double ph = 0.0;
+      if (p.window == kWindowPswf) {
+        ph = ad * pw.lambda0 * pw.psi(2.0 * k / md) / pw.psi_0;
+      } else if (p.window == kWindowGauss) {
+        ph = ad * std::sqrt(kPi / p.cg) * std::exp(-w * w * ad * ad / (4.0 * p.cg));
+      } else {
+        long double acc = 0.0L;
+        for (int j = -(P / 2); j <= P / 2; ++j)
+          acc += bspline(P, static_cast<long double>(j)) * std::cos(2.0L * static_cast<long double>(kPi) * k * j / md);
+        ph = hd * static_cast<double>(acc);
+      }
+      (*out)[k] = 1.0 / (ph * ph);
     }
-    t->w[k] = 1.0 / (ph * ph);
+  };
+  window_factors(0, &t->w);
+  window_factors(1, &t->wy);
+  window_factors(2, &t->wz);
+  // Cuboids: the radial factor is evaluated per mode on the GPU (|w|^2 is no integer function of
+  // |k|^2 when the L_d / m_d or m_d differ).
+  t->radial = 0;
+  if (!p.cubic()) {
+    const double hx = p.side(0) / p.grid(0), hy = p.side(1) / p.grid(1), hz = p.side(2) / p.grid(2);
+    const double vol = p.side(0) * p.side(1) * p.side(2);
+    t->rpref = 4.0 * kPi * hx * hx * hy * hy * hz * hz / vol;
+    if (gsplit) {
+      t->radial = 2;
+      const double wmax = kPi / std::max(hx, std::max(hy, hz));  // |k_d| <= m_d / 2 on the coarsest axis
+      t->rband2 = wmax * wmax;
+      t->rsig2 = 0.25 * sigma * sigma;
+    } else {
+      t->radial = 1;
+      t->rband2 = (p.cs / p.rc) * (p.cs / p.rc);
+      t->rscale = (p.rc / p.cs) * (p.rc / p.cs);
+      // psi_0(x) / psi_0(0) as a polynomial in u = x^2 - 1/2 on x in [0, 1]
+      auto G = [&](long double u) -> long double {
+        const double x = std::sqrt(std::max(0.0, std::min(1.0, static_cast<double>(u) + 0.5)));
+        return static_cast<long double>(ps.psi(x) / ps.psi_0);
+      };
+      for (int dg = 8; dg <= 48; ++dg) {
+        auto c = cheb_fit_monomial(G, dg);
+        std::vector<double> coef(dg + 1);
+        for (int k = 0; k <= dg; ++k) coef[k] = static_cast<double>(c[k]);
+        double err = 0.0;
+        for (int i = 0; i <= 256; ++i) {
+          const double u = -0.5 + i / 256.0;
+          double v = coef[dg];
+          for (int k = dg - 1; k >= 0; --k) v = v * u + coef[k];
+          err = std::max(err, std::fabs(v - static_cast<double>(G(u))));
+        }
+        t->rpoly.swap(coef);
+        if (err <= 1e-15) break;
+      }
+    }
   }
   t->self_coef = gsplit ? 2.0 / (std::sqrt(kPi) * sigma) : 2.0 / (p.rc * ps.lambda0);
   // Piecewise-polynomial window (Remark after eq. force): one polynomial per support point, in

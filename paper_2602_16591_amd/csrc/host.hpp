@@ -41,6 +41,13 @@ struct Params {
   int split = kSplitPswf;    // for the Gaussian split, cs = (rc / sigma)^2
   int window = kWindowPswf;
   double cg = 0.0;           // Gaussian window shape: exp(-cg (x/alpha)^2)
+  // Cuboid boxes (Sec. 6.1): sides L (x), Ly, Lz and grid sizes m (x), my, mz; 0 means equal to
+  // the x value. Grid spacings h_d = L_d / m_d; L, h and alpha above are the x values.
+  double Ly = 0.0, Lz = 0.0;
+  int my = 0, mz = 0;
+  double side(int d) const { return d == 0 ? L : (d == 1 ? (Ly > 0 ? Ly : L) : (Lz > 0 ? Lz : L)); }
+  int grid(int d) const { return d == 0 ? m : (d == 1 ? (my > 0 ? my : m) : (mz > 0 ? mz : m)); }
+  bool cubic() const { return side(1) == L && side(2) == L && grid(1) == m && grid(2) == m; }
 };
 
 // Default Gaussian window shape for support P: 0.8 times c_w = pi P / 2 (the ratio that gave
@@ -60,6 +67,12 @@ int next_smooth_even(int m);
 int choose_params(double eps, double L, double rc, int m, int64_t n, double q_l2, int tol_mode,
                   Params* out);
 
+// Alg. 3 for a cuboid box: the cube of side L_min with the same particle and charge densities
+// fixes r_c, c_s, c_w, P and h = L_min / m; m_d is then the smallest even 2,3,5,7-smooth size
+// with L_d / m_d <= h (Sec. 6.1, remark on cuboid domains).
+int choose_params_box(double eps, double Lx, double Ly, double Lz, double rc, int m, int64_t n, double q_l2,
+                      int tol_mode, Params* out);
+
 // Tables consumed by the kernels, all float64.
 struct Tables {
   // Scaling s_k = T_M[|k|^2] * W[|k_x|] * W[|k_y|] * W[|k_z|] (Alg. 2 step 3 with the h^6 of the
@@ -67,8 +80,16 @@ struct Tables {
   // PSWF split's band edge c_s L / (2 pi r_c); m/2 for the Gaussian split, which has no band);
   // W[k] = 1 / phihat_1(2 pi k / L)^2 for 0 <= k <= m/2, with phihat_1 the window's transform
   // (for the B-spline window, the SPME form: the transform of its integer samples).
-  std::vector<double> tm;  // size 3 (m/2)^2 + 1
+  std::vector<double> tm;  // size 3 (m/2)^2 + 1 (cubes only)
   std::vector<double> w;   // size m/2 + 1
+  std::vector<double> wy, wz;  // the window factors along y and z (my/2 + 1, mz/2 + 1)
+  // Cuboids: the radial factor per mode, 4 pi prod_d h_d^2 / V * gammahat(|w|) / |w|^2 for
+  // |w|^2 <= rband2, with gammahat the Gaussian exp(-rsig2 |w|^2) (radial 2) or, for the PSWF
+  // split (radial 1), the polynomial rpoly in u = rscale |w|^2 - 1/2 (psi_0(r_c |w| / c_s) /
+  // psi_0(0), fitted to 1e-15 relative).
+  int radial = 0;
+  std::vector<double> rpoly;
+  double rscale = 0.0, rpref = 0.0, rband2 = 0.0, rsig2 = 0.0;
   // Piecewise-polynomial window: for support point j = 0..P-1 and centred offset
   // g in [-1/2, 1/2], phi_1(2 (g + (P-1)/2 - j) / P) ~ sum_k coef[j*(deg+1) + k] g^k, with
   // phi_1(s) the window at x = s alpha.

@@ -26,13 +26,12 @@ __global__ void k_bin_count(int64_t n, int nsys, const SysDesc* __restrict__ sys
   if (energy && i < nsys) energy[i] = 0.0;
   if (i >= n) return;
   const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
-  const T ih_hi = static_cast<T>(sd.ih_hi), ih_lo = static_cast<T>(sd.ih_lo), L = static_cast<T>(sd.L);
-  const int m = sd.m, B = sd.B, Tn = sd.Tn;
+  const int B = sd.B;
   T f;
-  const int cx = grid_coord(pos[3 * i + 0], ih_hi, ih_lo, L, m, f);
-  const int cy = grid_coord(pos[3 * i + 1], ih_hi, ih_lo, L, m, f);
-  const int cz = grid_coord(pos[3 * i + 2], ih_hi, ih_lo, L, m, f);
-  const int tile = sd.tile_base + ((cz / B) * Tn + cy / B) * Tn + cx / B;
+  const int cx = grid_coord(pos[3 * i + 0], T(sd.ih_hi), T(sd.ih_lo), T(sd.L), sd.m, f);
+  const int cy = grid_coord(pos[3 * i + 1], T(sd.ihy_hi), T(sd.ihy_lo), T(sd.Ly), sd.my, f);
+  const int cz = grid_coord(pos[3 * i + 2], T(sd.ihz_hi), T(sd.ihz_lo), T(sd.Lz), sd.mz, f);
+  const int tile = sd.tile_base + ((cz / B) * sd.Tny + cy / B) * sd.Tn + cx / B;
   const int bucket = (tile << sub_log2) | static_cast<int>(i & ((1 << sub_log2) - 1));
   tile_of[i] = bucket;
   rank[i] = atomicAdd(&tile_count[bucket], 1);
@@ -95,13 +94,11 @@ __global__ void k_bin_scatter(int64_t n, int nsys, const SysDesc* __restrict__ s
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
   const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
-  const T ih_hi = static_cast<T>(sd.ih_hi), ih_lo = static_cast<T>(sd.ih_lo), L = static_cast<T>(sd.L);
-  const int m = sd.m;
   const int dst = tile_start[tile_of[i]] + rank[i];
   typename Vec4<T>::type r;
-  const int cx = grid_coord(pos[3 * i + 0], ih_hi, ih_lo, L, m, r.x);
-  const int cy = grid_coord(pos[3 * i + 1], ih_hi, ih_lo, L, m, r.y);
-  const int cz = grid_coord(pos[3 * i + 2], ih_hi, ih_lo, L, m, r.z);
+  const int cx = grid_coord(pos[3 * i + 0], T(sd.ih_hi), T(sd.ih_lo), T(sd.L), sd.m, r.x);
+  const int cy = grid_coord(pos[3 * i + 1], T(sd.ihy_hi), T(sd.ihy_lo), T(sd.Ly), sd.my, r.y);
+  const int cz = grid_coord(pos[3 * i + 2], T(sd.ihz_hi), T(sd.ihz_lo), T(sd.Lz), sd.mz, r.z);
   r.w = q ? q[i] : T(0);
   sorted[dst] = r;
   cells[dst] = pack_cell(cx, cy, cz);
@@ -134,12 +131,10 @@ __global__ void k_cell_count(int64_t n, int nsys, const SysDesc* __restrict__ sy
   if (energy && i < nsys) energy[i] = 0.0;
   if (i >= n) return;
   const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
-  const double L = sd.L, sc = sd.nc / sd.L;
-  const int nc = sd.nc;
-  const int cx = cell_of_pos(wrap_pos(static_cast<double>(pos[3 * i + 0]), L), sc, nc);
-  const int cy = cell_of_pos(wrap_pos(static_cast<double>(pos[3 * i + 1]), L), sc, nc);
-  const int cz = cell_of_pos(wrap_pos(static_cast<double>(pos[3 * i + 2]), L), sc, nc);
-  const int cell = sd.cell_base + (cz * nc + cy) * nc + cx;
+  const int cx = cell_of_pos(wrap_pos(static_cast<double>(pos[3 * i + 0]), sd.L), sd.nc / sd.L, sd.nc);
+  const int cy = cell_of_pos(wrap_pos(static_cast<double>(pos[3 * i + 1]), sd.Ly), sd.ncy / sd.Ly, sd.ncy);
+  const int cz = cell_of_pos(wrap_pos(static_cast<double>(pos[3 * i + 2]), sd.Lz), sd.ncz / sd.Lz, sd.ncz);
+  const int cell = sd.cell_base + (cz * sd.ncy + cy) * sd.nc + cx;
   cell_of[i] = cell;
   cell_rank[i] = atomicAdd(&cell_count[cell], 1);
 }
@@ -153,11 +148,10 @@ __global__ void k_cell_scatter(int64_t n, int nsys, const SysDesc* __restrict__ 
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= n) return;
   const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
-  const double L = sd.L;
   const int dst = cell_start[cell_of[i]] + cell_rank[i];
-  lsorted[dst] = make_double4(wrap_pos(static_cast<double>(pos[3 * i + 0]), L),
-                              wrap_pos(static_cast<double>(pos[3 * i + 1]), L),
-                              wrap_pos(static_cast<double>(pos[3 * i + 2]), L), static_cast<double>(q[i]));
+  lsorted[dst] = make_double4(wrap_pos(static_cast<double>(pos[3 * i + 0]), sd.L),
+                              wrap_pos(static_cast<double>(pos[3 * i + 1]), sd.Ly),
+                              wrap_pos(static_cast<double>(pos[3 * i + 2]), sd.Lz), static_cast<double>(q[i]));
   lperm[dst] = static_cast<int>(i);
 }
 
@@ -188,22 +182,23 @@ __global__ __launch_bounds__(kLocalThreads) void k_local(int nsys, const SysDesc
   if (t0 == t1) return;
   const int s = find_sys(cell_prefix, nsys, gcell);
   const SysDesc& sd = sys[s];
-  const int nc = sd.nc;
-  const double L = sd.L, inv_L = 1.0 / sd.L, rc2 = sd.rc * sd.rc, inv_rc2 = 1.0 / rc2, K = sd.lK;
+  const int nc = sd.nc, ncy = sd.ncy, ncz = sd.ncz;
+  const double Lx = sd.L, Ly = sd.Ly, Lz = sd.Lz, inv_Lx = 1.0 / Lx, inv_Ly = 1.0 / Ly, inv_Lz = 1.0 / Lz;
+  const double rc2 = sd.rc * sd.rc, inv_rc2 = 1.0 / rc2, K = sd.lK;
   double cr[kLocalDeg + 1];
   const global_ptr<double> lcoef = as_global(sd.lcoef);
 #pragma unroll
   for (int k = 0; k <= kLocalDeg; ++k) cr[k] = k <= sd.ldeg ? lcoef[k] : 0.0;
   const int tid = threadIdx.x;
-  // source ranges: the 27 neighbour cells (distinct, as nc >= 3), or the system's one cell
+  // source ranges: the 27 neighbour cells (distinct, as every nc >= 3), or the system's one cell
   if (tid < 27) {
     int b = 0, e = 0;
     if (nc >= 3) {
       const int lc = gcell - sd.cell_base;
-      const int cx = lc % nc, cy = (lc / nc) % nc, cz = lc / (nc * nc);
+      const int cx = lc % nc, cy = (lc / nc) % ncy, cz = lc / (nc * ncy);
       const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = tid / 9 - 1;
-      const int x = (cx + dx + nc) % nc, y = (cy + dy + nc) % nc, z = (cz + dz + nc) % nc;
-      const int cell = sd.cell_base + (z * nc + y) * nc + x;
+      const int x = (cx + dx + nc) % nc, y = (cy + dy + ncy) % ncy, z = (cz + dz + ncz) % ncz;
+      const int cell = sd.cell_base + (z * ncy + y) * nc + x;
       b = cell_start[cell];
       e = cell_start[cell + 1];
     } else if (tid == 0) {
@@ -251,9 +246,9 @@ __global__ __launch_bounds__(kLocalThreads) void k_local(int nsys, const SysDesc
           if (src_id[k] == ti) continue;
           const double4 xj = src[k];
           double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
-          dx -= L * rint(dx * inv_L);  // minimum image (|dx| < L; pairs near L/2 lie beyond r_c)
-          dy -= L * rint(dy * inv_L);
-          dz -= L * rint(dz * inv_L);
+          dx -= Lx * rint(dx * inv_Lx);  // minimum image (pairs near L/2 lie beyond r_c)
+          dy -= Ly * rint(dy * inv_Ly);
+          dz -= Lz * rint(dz * inv_Lz);
           const double r2 = dx * dx + dy * dy + dz * dz;
           if (!(r2 < rc2) || r2 == 0.0) continue;  // beyond the cutoff, or coincident positions
           const double rinv = rsqrt(r2);
@@ -440,7 +435,7 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(int nsys, const SysDesc* __re
   using C = typename Cplx<T>::type;
   extern __shared__ unsigned char smem_raw[];
   const SysDesc& sd = sys[find_sys(xblk_prefix, nsys, static_cast<int>(blockIdx.x))];
-  const int m = sd.m, N = m / 2, nrows = m * m, rpb = sd.rows_per_block;
+  const int m = sd.m, N = m / 2, nrows = sd.my * sd.mz, rpb = sd.rows_per_block;
   const C* __restrict__ tw_half = static_cast<const C*>(sd.twhp);
   const C* __restrict__ tw_full = static_cast<const C*>(sd.twfp);
   C* A = reinterpret_cast<C*>(smem_raw);
@@ -489,7 +484,7 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(int nsys, const SysDesc* __re
   using C = typename Cplx<T>::type;
   extern __shared__ unsigned char smem_raw[];
   const SysDesc& sd = sys[find_sys(xblk_prefix, nsys, static_cast<int>(blockIdx.x))];
-  const int m = sd.m, N = m / 2, nrows = m * m, rpb = sd.rows_per_block;
+  const int m = sd.m, N = m / 2, nrows = sd.my * sd.mz, rpb = sd.rows_per_block;
   const C* __restrict__ tw_half = static_cast<const C*>(sd.twhm);
   const C* __restrict__ tw_full = static_cast<const C*>(sd.twfm);
   C* A = reinterpret_cast<C*>(smem_raw);   // rpb * (N + 1)
@@ -635,46 +630,66 @@ __global__ __launch_bounds__(256) void k_fft_plane_inv(int nsys, const SysDesc* 
   for (int e = threadIdx.x; e < m * N; e += blockDim.x) gstore(dst + e, Z[e]);
 }
 
-// FFT along y or z of each system's half spectrum. A system's blocks are (outer, column
-// block) pairs; sequence c of a block is the column kx0 + c, whose element e sits at
-// spec[outer * ostride + e * estride + kx0 + c].
-//   mode 0: forward y (outer = z plane);  mode 2: inverse y;
-//   mode 1: forward z, multiply by s_k = T_M[|k|^2] W[|kx|] W[|ky|] W[|kz|] (ky = outer), inverse
-//           z (Alg. 2 steps 2-4 for this column; outer = y row).
+// Radial factor of the scaling at |w|^2 = w2 for systems without a T_M table (cuboids):
+// 4 pi prod_d h_d^2 / V * gammahat(|w|) / |w|^2 inside the band, 0 outside and at w = 0.
+// PSWF split: gammahat = psi_0^{c_s}(r_c |w| / c_s) / psi_0^{c_s}(0), a polynomial in
+// u = (r_c |w| / c_s)^2 - 1/2; Gaussian split: exp(-sigma^2 |w|^2 / 4).
+__device__ __forceinline__ double radial_factor(const SysDesc& sd, double w2) {
+  if (!(w2 > 0.0) || w2 > sd.rband2) return 0.0;
+  double g;
+  if (sd.radial == 2) {
+    g = exp(-sd.rsig2 * w2);
+  } else {
+    const global_ptr<double> c = as_global(sd.rleg);
+    const double u = sd.rscale * w2 - 0.5;
+    g = c[sd.rleg_n];
+    for (int k = sd.rleg_n - 1; k >= 0; --k) g = fma(g, u, c[k]);
+  }
+  return sd.rpref * g / w2;
+}
+
+// FFT along y or z of each system's half spectrum (mz planes of my rows of m/2 + 1 complex
+// values). A system's blocks are (outer, column block) pairs; sequence c of a block is the
+// column kx0 + c, whose element e sits at spec[outer * ostride + e * estride + kx0 + c].
+//   mode 0: forward y (outer = z plane; length my);  mode 2: inverse y;
+//   mode 1: forward z (outer = y row; length mz), multiply by
+//           s_k = T_M(|k|) W[|kx|] Wy[|ky|] Wz[|kz|], inverse z (Alg. 2 steps 2-4 for this column).
 template <class T>
 __global__ __launch_bounds__(256) void k_fft_cols(int nsys, const SysDesc* __restrict__ sys,
                                                   const int* __restrict__ cblk_prefix, int mode) {
   using C = typename Cplx<T>::type;
   extern __shared__ unsigned char smem_raw[];
   const SysDesc& sd = sys[find_sys(cblk_prefix, nsys, static_cast<int>(blockIdx.x))];
-  const int m = sd.m, nx1 = m / 2 + 1, cpb = sd.cols_per_block;
+  const int m = sd.m, my = sd.my, mz = sd.mz, nx1 = m / 2 + 1, cpb = sd.cols_per_block;
+  const int len = mode == 1 ? mz : my;
   const int nxb = (nx1 + cpb - 1) / cpb;
-  const int lb = static_cast<int>(blockIdx.x) - sd.cblk_base;
+  const int lb = static_cast<int>(blockIdx.x) - (mode == 1 ? sd.zblk_base : sd.cblk_base);
   const int outer = lb / nxb;
   const int kx0 = (lb - outer * nxb) * cpb;
   const int nc = min(cpb, nx1 - kx0);
-  const int64_t plane = static_cast<int64_t>(m) * nx1;
+  const int64_t plane = static_cast<int64_t>(my) * nx1;
   const int64_t ostride = mode == 1 ? int64_t(nx1) : plane;
   const int64_t estride = mode == 1 ? plane : int64_t(nx1);
-  const int ss = m + 1;  // padded sequence stride in LDS
+  const int ss = len + 1;  // padded sequence stride in LDS
+  const FftPlan& pl = mode == 1 ? sd.ffz : sd.ffy;
   C* A = reinterpret_cast<C*>(smem_raw);
   C* Bf = A + cpb * ss;
-  C* tw_p = Bf + cpb * ss;  // twiddles of length m: sign + then sign -
-  C* tw_m = tw_p + m;
+  C* tw_p = Bf + cpb * ss;  // twiddles of length len: sign + then sign -
+  C* tw_m = tw_p + len;
   {
-    const C* __restrict__ gp = static_cast<const C*>(sd.twfp);
-    const C* __restrict__ gm = static_cast<const C*>(sd.twfm);
-    for (int e = threadIdx.x; e < 2 * m; e += blockDim.x) {
-      if (e < m)
+    const C* __restrict__ gp = static_cast<const C*>(mode == 1 ? sd.twzp : sd.twyp);
+    const C* __restrict__ gm = static_cast<const C*>(mode == 1 ? sd.twzm : sd.twym);
+    for (int e = threadIdx.x; e < 2 * len; e += blockDim.x) {
+      if (e < len)
         tw_p[e] = gload(gp + e);
       else
-        tw_m[e - m] = gload(gm + (e - m));
+        tw_m[e - len] = gload(gm + (e - len));
     }
   }
   const C* tw = mode == 2 ? tw_m : tw_p;
   C* base = static_cast<C*>(sd.spec) + outer * ostride + kx0;
   staged_copy<8>(
-      nc * m,
+      nc * len,
       [&](int i) {
         const int e = i / nc, c = i - e * nc;
         return gload(base + e * estride + c);
@@ -684,16 +699,23 @@ __global__ __launch_bounds__(256) void k_fft_cols(int nsys, const SysDesc* __res
         A[c * ss + e] = v;
       });
   __syncthreads();
-  C* R1 = fft_lds(A, Bf, nc, ss, sd.ff, tw);
+  C* R1 = fft_lds(A, Bf, nc, ss, pl, tw);
   if (mode == 1) {
-    const auto tm = as_global(static_cast<const T*>(sd.tm));
     const auto wk = as_global(static_cast<const T*>(sd.wk));
-    const int ky = outer <= (m - 1) / 2 ? outer : m - outer;
-    for (int i = threadIdx.x; i < nc * m; i += blockDim.x) {
-      const int c = i / m, e = i - c * m;
+    const auto wky = as_global(static_cast<const T*>(sd.wky));
+    const auto wkz = as_global(static_cast<const T*>(sd.wkz));
+    const int ky = outer <= (my - 1) / 2 ? outer : my - outer;
+    for (int i = threadIdx.x; i < nc * mz; i += blockDim.x) {
+      const int c = i / mz, e = i - c * mz;
       const int kx = kx0 + c;
-      const int kz = e <= (m - 1) / 2 ? e : m - e;
-      const T sc = tm[kx * kx + ky * ky + kz * kz] * wk[kx] * wk[ky] * wk[kz];
+      const int kz = e <= (mz - 1) / 2 ? e : mz - e;
+      T rad;
+      if (sd.radial == 0) {
+        rad = as_global(static_cast<const T*>(sd.tm))[kx * kx + ky * ky + kz * kz];
+      } else {
+        rad = static_cast<T>(radial_factor(sd, sd.w2x * kx * kx + sd.w2y * ky * ky + sd.w2z * kz * kz));
+      }
+      const T sc = rad * wk[kx] * wky[ky] * wkz[kz];
       C v = R1[c * ss + e];
       v.x *= sc;
       v.y *= sc;
@@ -701,9 +723,9 @@ __global__ __launch_bounds__(256) void k_fft_cols(int nsys, const SysDesc* __res
     }
     __syncthreads();
     C* other = (R1 == A) ? Bf : A;
-    R1 = fft_lds(R1, other, nc, ss, sd.ff, tw_m);
+    R1 = fft_lds(R1, other, nc, ss, pl, tw_m);
   }
-  for (int i = threadIdx.x; i < nc * m; i += blockDim.x) {
+  for (int i = threadIdx.x; i < nc * len; i += blockDim.x) {
     const int e = i / nc, c = i - e * nc;
     gstore(base + e * estride + c, R1[c * ss + e]);
   }
@@ -755,7 +777,7 @@ hipError_t transform_impl(const DevPlan& d, const void* in_override, void* out_o
     stage_begin(d, kStageFftY, st);  // fused into the x stage: recorded as an empty stage
     stage_end(d, kStageFftY, st);
     stage_begin(d, kStageFftZScale, st);
-    hipLaunchKernelGGL(k_fft_cols<T>, dim3(d.total_cblk), dim3(256), d.lds_c, st, d.nsys, d.sys_dev, d.cblk_prefix,
+    hipLaunchKernelGGL(k_fft_cols<T>, dim3(d.total_zblk), dim3(256), d.lds_c, st, d.nsys, d.sys_dev, d.zblk_prefix,
                        1);
     stage_end(d, kStageFftZScale, st);
     stage_begin(d, kStageIfftY, st);  // fused into the inverse x stage
@@ -778,7 +800,7 @@ hipError_t transform_impl(const DevPlan& d, const void* in_override, void* out_o
   hipLaunchKernelGGL(k_fft_cols<T>, dim3(d.total_cblk), dim3(256), d.lds_c, st, d.nsys, d.sys_dev, d.cblk_prefix, 0);
   stage_end(d, kStageFftY, st);
   stage_begin(d, kStageFftZScale, st);
-  hipLaunchKernelGGL(k_fft_cols<T>, dim3(d.total_cblk), dim3(256), d.lds_c, st, d.nsys, d.sys_dev, d.cblk_prefix, 1);
+  hipLaunchKernelGGL(k_fft_cols<T>, dim3(d.total_zblk), dim3(256), d.lds_c, st, d.nsys, d.sys_dev, d.zblk_prefix, 1);
   stage_end(d, kStageFftZScale, st);
   stage_begin(d, kStageIfftY, st);
   hipLaunchKernelGGL(k_fft_cols<T>, dim3(d.total_cblk), dim3(256), d.lds_c, st, d.nsys, d.sys_dev, d.cblk_prefix, 2);
@@ -865,7 +887,7 @@ hipError_t launch_spread(const DevPlan& d, hipStream_t st) {
 
 hipError_t launch_drain(const DevPlan& d, void* out, hipStream_t st) {
   const SysDesc& s0 = d.sys[0];
-  const int64_t count = static_cast<int64_t>(s0.m) * s0.m * s0.m;
+  const int64_t count = static_cast<int64_t>(s0.m) * s0.my * s0.mz;
   const unsigned nb = std::max(1u, std::min<unsigned>(blocks_for(count, 256), 4096u));
   if (d.prec == 0)
     hipLaunchKernelGGL(k_drain<float>, dim3(nb), dim3(256), 0, st, s0.grid_a, static_cast<float*>(out), count);

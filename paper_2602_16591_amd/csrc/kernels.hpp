@@ -40,33 +40,54 @@ struct StageTimer {
 
 // One system of a batch. Pointers are device pointers; real arrays are in the plan precision
 // unless stated.
+// Boxes are cuboids [0, L) x [0, Ly) x [0, Lz) with m x my x mz grid points (a cube has equal
+// sizes; the cuboid remark of Sec. 6.1); x fields keep the unsuffixed names.
 struct SysDesc {
-  int m = 0, P = 0, deg = 0;
+  int m = 0, P = 0, deg = 0;  // m: grid points along x
+  int my = 0, mz = 0;         // grid points along y and z
   int B = 0;                  // tile edge in grid cells
-  int Tn = 0;                 // tiles per dimension
+  int Tn = 0;                 // tiles along x
+  int Tny = 0, Tnz = 0;       // tiles along y and z
   int S = 0;                  // LDS tile edge = B + 2 ceil(P/2) - 1
   int tile_base = 0;          // first global tile of this system
   int rows_per_block = 1;     // x-direction FFT batching
   int cols_per_block = 1;     // y/z-direction FFT batching
   int xblk_base = 0;          // first block of this system in the x-direction FFT launches
   int pblk_base = 0;          // first block (z-plane) of this system in the plane FFT launches
-  int cblk_base = 0;          // first block in the y/z-direction FFT launches
+  int cblk_base = 0;          // first block in the y-direction FFT launches
+  int zblk_base = 0;          // first block in the z-direction FFT launch
   int64_t part_base = 0;      // first packed particle of this system
-  double L = 0, inv_h = 0, ih_hi = 0, ih_lo = 0, self_coef = 0;
-  double* grid_a = nullptr;   // m^3 float64 spread target; kept all-zero between calls
-  void* grid_b = nullptr;     // m^3 transformed grid
-  void* spec = nullptr;       // m * m * (m/2 + 1) complex half spectrum
+  double L = 0, inv_h = 0, ih_hi = 0, ih_lo = 0, self_coef = 0;  // x: box side, 1/h (split in two)
+  double Ly = 0, inv_hy = 0, ihy_hi = 0, ihy_lo = 0;
+  double Lz = 0, inv_hz = 0, ihz_hi = 0, ihz_lo = 0;
+  double* grid_a = nullptr;   // mz * my * m float64 spread target; kept all-zero between calls
+  void* grid_b = nullptr;     // mz * my * m transformed grid
+  void* spec = nullptr;       // mz * my * (m/2 + 1) complex half spectrum
   const double* coef = nullptr;  // P * (deg + 1) window polynomial coefficients (float64)
-  const void* tm = nullptr;   // 3 (m/2)^2 + 1 radial scaling table
-  const void* wk = nullptr;   // m/2 + 1 window factors
+  // radial scaling: radial == 0, a table T_M[|k|^2] over 3 (m/2)^2 + 1 entries (cubes); else the
+  // factor is evaluated per mode from |w|^2 = w2x kx^2 + w2y ky^2 + w2z kz^2 (radial == 1: PSWF
+  // split, Legendre series of psi_0^{c_s}; radial == 2: Gaussian split)
+  const void* tm = nullptr;
+  int radial = 0, rleg_n = 0;
+  const double* rleg = nullptr;  // Legendre coefficients of P_0, P_2, ... of psi_0^{c_s}
+  double w2x = 0, w2y = 0, w2z = 0, rscale = 0, rpref = 0, rband2 = 0, rsig2 = 0;
+  const void* wk = nullptr;   // m/2 + 1 window factors (x), then my/2 + 1 (y), mz/2 + 1 (z)
+  const void* wky = nullptr;
+  const void* wkz = nullptr;
   const void* twhp = nullptr; // exp(+2 pi i e / (m/2)), e < m/2
   const void* twhm = nullptr; // exp(-2 pi i e / (m/2))
   const void* twfp = nullptr; // exp(+2 pi i e / m), e < m
   const void* twfm = nullptr; // exp(-2 pi i e / m)
+  const void* twyp = nullptr; // the same for lengths my and mz
+  const void* twym = nullptr;
+  const void* twzp = nullptr;
+  const void* twzm = nullptr;
   FftPlan fh, ff;             // radix plans for lengths m/2 and m
+  FftPlan ffy, ffz;           // lengths my and mz
   // real-space residual (Sec. 3.1.1): cells of edge L / nc >= r_c (nc >= 3), or one cell
   // holding the whole system when nc < 3
-  int nc = 1;                 // cells per dimension
+  int nc = 1;                 // cells along x
+  int ncy = 1, ncz = 1;       // along y and z
   int cell_base = 0;          // first global cell of this system
   int ldeg = 0;               // degree of the residual polynomial G
   double rc = 0, lK = 0;      // cutoff and K of R(r) = 1/r - K G(r^2/r_c^2 - 1/2)
@@ -118,6 +139,8 @@ struct DevPlan {
   int* tile_prefix = nullptr;      // nsys + 1: tile ranges in global tile order (grouped by P, D)
   int* tile_sys = nullptr;         // nsys: system owning the k-th tile range
   int* xblk_prefix = nullptr;      // nsys + 1, in system order
+  int* zblk_prefix = nullptr;      // nsys + 1: blocks of the z-direction pass
+  int total_zblk = 0;
   int* pblk_prefix = nullptr;      // nsys + 1: z-planes, for the plane FFT kernels
   int plane_fft = 0;               // x and y FFTs fused per z-plane (every system's plane fits in LDS)
   int total_pblk = 0;

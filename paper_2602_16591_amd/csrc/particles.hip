@@ -110,7 +110,7 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_spread(const type
   double* recs = acc + S3;                           // nslots * REC
   double* lcoef = recs + nslots * REC;               // P * CS
   const int tile = gtile - sd.tile_base;
-  const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
+  const int tx = tile % Tn, ty = (tile / Tn) % sd.Tny, tz = tile / (Tn * sd.Tny);
   const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
   stage_coefficients<P, D>(sd.coef, sd.deg, lcoef);
   for (int i = threadIdx.x; i < S3; i += blockDim.x) acc[i] = 0.0;
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_spread(const type
   const int Ox = T0x + 1 - half, Oy = T0y + 1 - half, Oz = T0z + 1 - half;
   double v[8];
   walk_tile<8>(
-      S, m, Ox, Oy, Oz, [&](int k, int li_, int64_t) { v[k] = acc[li_]; },
+      S, m, sd.my, sd.mz, Ox, Oy, Oz, [&](int k, int li_, int64_t) { v[k] = acc[li_]; },
       [&](int k, int, int64_t gi) {
         if (v[k] != 0.0) atomic_add_global(grid + gi, v[k]);
       });
@@ -230,7 +230,7 @@ __global__ __launch_bounds__((col_threads<P, B>())) void k_spread_cols(
   double* pg = recs + kColBatch * RS;                   // kColBatch * 4: g_x, g_y, g_z, q
   int* po = reinterpret_cast<int*>(pg + kColBatch * 4); // kColBatch * 4: o_x, o_y, o_z
   const int tile = gtile - sd.tile_base;
-  const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
+  const int tx = tile % Tn, ty = (tile / Tn) % sd.Tny, tz = tile / (Tn * sd.Tny);
   const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
   stage_coefficients<P, D>(sd.coef, sd.deg, lcoef);
   const int t = threadIdx.x;
@@ -289,13 +289,14 @@ __global__ __launch_bounds__((col_threads<P, B>())) void k_spread_cols(
   }
   if (owner) {
     constexpr int half = (P + 1) / 2;
+    const int my = sd.my;
     const int gx = fold_index(T0x + 1 - half + ix, m);
-    const int64_t gz = fold_index(T0z + 1 - half + iz, m);
+    const int64_t gz = fold_index(T0z + 1 - half + iz, sd.mz);
 #pragma unroll
     for (int iy = 0; iy < S; ++iy) {
       if (acc[iy] != 0.0) {
-        const int gy = fold_index(T0y + 1 - half + iy, m);
-        atomic_add_global(grid + (gz * m + gy) * m + gx, acc[iy]);
+        const int gy = fold_index(T0y + 1 - half + iy, my);
+        atomic_add_global(grid + (gz * my + gy) * m + gx, acc[iy]);
       }
     }
   }
@@ -327,13 +328,13 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
   const SysDesc& sd = sys[s];
   const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S;
   const global_ptr<T> grid = as_global(grid_override ? grid_override : static_cast<const T*>(sd.grid_b));
-  const double inv_h = sd.inv_h, self_coef = sd.self_coef;
+  const double inv_hx = sd.inv_h, inv_hy = sd.inv_hy, inv_hz = sd.inv_hz, self_coef = sd.self_coef;
   const int nslots = blockDim.x / kLanesPerParticle;
   double* recs = reinterpret_cast<double*>(smem_raw);              // nslots * REC
   double* lcoef = recs + nslots * REC;                             // P * CS
   T* tb = reinterpret_cast<T*>(lcoef + P * CS);
   const int tile = gtile - sd.tile_base;
-  const int tx = tile % Tn, ty = (tile / Tn) % Tn, tz = tile / (Tn * Tn);
+  const int tx = tile % Tn, ty = (tile / Tn) % sd.Tny, tz = tile / (Tn * sd.Tny);
   const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
   const int half = (P + 1) / 2;
   const int Ox = T0x + 1 - half, Oy = T0y + 1 - half, Oz = T0z + 1 - half;
@@ -341,7 +342,7 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
   {
     T v[8];
     walk_tile<8>(
-        S, m, Ox, Oy, Oz, [&](int k, int, int64_t gi) { v[k] = grid[gi]; },
+        S, m, sd.my, sd.mz, Ox, Oy, Oz, [&](int k, int, int64_t gi) { v[k] = grid[gi]; },
         [&](int k, int li_, int64_t) { tb[li_] = v[k]; });
   }
   __syncthreads();
@@ -441,10 +442,10 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
       if (add_self) phd -= self_coef * qd;
       if (phi) phi[idx] = static_cast<T>(phd);
       if (vec) {
-        const double sc = vec_mode == 0 ? -qd * inv_h : inv_h;
-        vec[3 * idx + 0] = static_cast<T>(sc * gx);
-        vec[3 * idx + 1] = static_cast<T>(sc * gy);
-        vec[3 * idx + 2] = static_cast<T>(sc * gz);
+        const double sc = vec_mode == 0 ? -qd : 1.0;  // d/dx_d = (1 / h_d) d/dg_d
+        vec[3 * idx + 0] = static_cast<T>(sc * inv_hx * gx);
+        vec[3 * idx + 1] = static_cast<T>(sc * inv_hy * gy);
+        vec[3 * idx + 2] = static_cast<T>(sc * inv_hz * gz);
       }
       esum += qd * phd;
     }
