@@ -242,7 +242,26 @@ def bench_comparison(steps: int, warmup: int, n: int = 100_000):
     ref = {eps: next(r["ms_per_step"] for r in rows if r["config"] == "PP" and r["eps"] == eps) for eps in (1e-6, 1e-5)}
     for r in rows:
         r["time_vs_PP"] = r["ms_per_step"] / ref[r["eps"]]
-    return {"workload": f"uniform_n{n}_unit_box_rc0.1", "prec": "fp32", "rows": rows}
+    # oversampled grids: Alg. 3 parameters (eps = 1e-6, r_c = 0.1) on grids sigma times finer with
+    # the smaller support they allow
+    over = []
+    base = pw.choose_params(1e-6, L, rc=0.1)
+    for sigma in (1.0, 1.5, 2.0):
+        c = pw.oversample_params(base, sigma)
+        plan = pw.Plan(c, "fp32", n_max=n)
+        runner = plan.graph(X, Q)
+        for _ in range(warmup):
+            runner()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            runner()
+        torch.cuda.synchronize()
+        over.append({"sigma": sigma, "m": c.m, "P": c.P, "cw": c.cw,
+                     "ms_per_step": (time.perf_counter() - t) / steps * 1e3})
+        del runner
+        plan.close()
+    return {"workload": f"uniform_n{n}_unit_box_rc0.1", "prec": "fp32", "rows": rows, "oversampled_eps1e-6": over}
 
 
 def main():

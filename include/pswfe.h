@@ -125,6 +125,17 @@ pswfe_status pswfe_choose_params(double eps, double L, double rc, int32_t m, int
 pswfe_status pswfe_choose_params_box(double eps, double Lx, double Ly, double Lz, double rc, int32_t m, int64_t n,
                                      double q_l2, int32_t tol_mode, pswfe_params* out);
 
+/* Oversampled grid for PSWF/PSWF parameters (from pswfe_choose_params[_box]): each m_d becomes the
+ * smallest even 2,3,5,7-smooth size >= sigma m_d; with the effective factor sigma' = min_d
+ * m_d / (2 k_band,d), k_band,d = c_s L_d / (2 pi r_c), the window bandlimit becomes
+ * c_w = pi P (1 - 1/(2 sigma')) (the gap between the band edge and its first alias, times alpha)
+ * and P the smallest support with c_w >= the base's c_w (pi P / 2 from Alg. 3), so P shrinks by
+ * about 1 / (2 - 1/sigma'); sigma = 1 returns the base grid and support. The split
+ * (r_c, c_s) is unchanged. The paper names oversampling as future work; the reading is stated in
+ * the design notes and pinned against the direct sum. sigma in [1, 4]; PSWFE_E_ARG for other
+ * splits or windows, PSWFE_E_GRID if a size would exceed 512. Host only. */
+pswfe_status pswfe_oversample_params(const pswfe_params* base, double sigma, pswfe_params* out);
+
 /* Parameters of a comparison configuration (Sec. 7.3.1-7.4): the split and the window are
  * chosen independently and the grid size m and support P are given (the paper's comparisons
  * search them for each tolerance). Fills h = L/m, alpha = P h / 2, c_w = pi P / 2, lambda_0(c_s)

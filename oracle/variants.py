@@ -54,6 +54,7 @@ class VariantParams:
     split: str = "pswf"
     window: str = "pswf"
     cg: float = 0.0    # Gaussian window shape (window == "gauss")
+    cw_window: float = 0.0    # PSWF window bandlimit; 0: pi P / 2 (eq. cwP)
     Ly: float | None = None   # cuboid sides and grid sizes along y and z (None: the x values)
     Lz: float | None = None
     my: int | None = None
@@ -81,7 +82,7 @@ class VariantParams:
 
     @property
     def cw(self) -> float:
-        return math.pi * self.P / 2.0
+        return self.cw_window if self.cw_window > 0 else math.pi * self.P / 2.0
 
     @property
     def sigma(self) -> float:
@@ -380,3 +381,18 @@ def box_params(eps: float, sides, rc: float, tol_mode: str = "rel", q_l2: float 
     h = Lmin / p.m
     ms = [oparams.next_smooth_even(int(math.ceil(Ld / h - 1e-9))) for Ld in (Lx, Ly, Lz)]
     return VariantParams(Lx, p.rc, p.cs, ms[0], p.P, Ly=Ly, Lz=Lz, my=ms[1], mz=ms[2])
+
+
+def oversample(p, sigma: float) -> VariantParams:
+    """PSWF/PSWF on a grid oversampled by sigma (a reading: the paper names oversampling as future
+    work). m' is the smallest even 2,3,5,7-smooth size >= sigma m; with sigma' = m' / (2 k_band),
+    k_band = c_s L / (2 pi r_c) modes, the band edge's first alias lies 2 pi / h - c_s / r_c away,
+    i.e. pi P (1 - 1/(2 sigma')) / alpha; that is taken as the window bandlimit c_w, and P as the
+    smallest support whose c_w reaches the base's c_w = pi P / 2 (Alg. 3). `p` is an
+    oracle/params.py parameter set for a cube."""
+    from . import params as oparams
+    m2 = oparams.next_smooth_even(int(math.ceil(sigma * p.m - 1e-9)))
+    kband = p.cs * p.L / (2.0 * math.pi * p.rc)
+    shrink = math.pi * (1.0 - 1.0 / (2.0 * max(1.0, m2 / (2.0 * kband))))
+    P = max(3, int(math.ceil(p.cw / shrink - 1e-9)))
+    return VariantParams(p.L, p.rc, p.cs, m2, P, cw_window=shrink * P)

@@ -49,6 +49,7 @@ _PPlan = ctypes.POINTER(ctypes.c_void_p)
 SIGNATURES = {
     "pswfe_choose_params": (ctypes.c_int, [_d, _d, _d, _i32, _i64, _d, _i32, ctypes.POINTER(CParams)]),
     "pswfe_choose_params_box": (ctypes.c_int, [_d, _d, _d, _d, _d, _i32, _i64, _d, _i32, ctypes.POINTER(CParams)]),
+    "pswfe_oversample_params": (ctypes.c_int, [ctypes.POINTER(CParams), _d, ctypes.POINTER(CParams)]),
     "pswfe_variant_params": (ctypes.c_int, [_i32, _i32, _d, _d, _d, _i32, _i32, _d, _d, ctypes.POINTER(CParams)]),
     "pswfe_plan_create": (ctypes.c_int, [ctypes.POINTER(CParams), _i32, _i64, _PPlan]),
     "pswfe_plan_create_tiled": (ctypes.c_int, [ctypes.POINTER(CParams), _i32, _i64, _i32, _PPlan]),
@@ -123,6 +124,15 @@ def choose_params_box(eps: float, box, *, rc: float = 0.0, m: int = 0, n: int = 
     out = CParams()
     _check(_lib().pswfe_choose_params_box(float(eps), Lx, Ly, Lz, float(rc), int(m), int(n), float(q_l2), int(mode),
                                           ctypes.byref(out)), "pswfe_choose_params_box")
+    return out
+
+
+def oversample_params(params: CParams, sigma: float) -> CParams:
+    """PSWF/PSWF parameters on a grid oversampled by sigma, with the smaller support it allows
+    (host only)."""
+    out = CParams()
+    _check(_lib().pswfe_oversample_params(ctypes.byref(params), float(sigma), ctypes.byref(out)),
+           "pswfe_oversample_params")
     return out
 
 

@@ -172,6 +172,9 @@ pswfe_status params_from_c(const pswfe_params* pp, pswfe::Params* p) {
     return PSWFE_E_ARG;
   if (pp->window == PSWFE_WINDOW_GAUSS && !(pp->cg > 0)) return PSWFE_E_ARG;
   if (pp->cs > 40.0 || (pp->window == PSWFE_WINDOW_PSWF && pp->cw > 40.0)) return PSWFE_E_EPS_RANGE;
+  // the window transform of Table 2 holds inside the window's band: alpha w <= c_w on the grid
+  if (pp->window == PSWFE_WINDOW_PSWF && pp->cw < 0.5 * 3.14159265358979323846 * P * (1.0 - 1e-12))
+    return PSWFE_E_ARG;
   p->split = pp->split;
   p->window = pp->window;
   p->cg = pp->cg;
@@ -613,6 +616,20 @@ pswfe_status pswfe_choose_params_box(double eps, double Lx, double Ly, double Lz
   pswfe::Params p{};
   const int rcode = pswfe::choose_params_box(eps, Lx, Ly, Lz, rc, m, n, q_l2, tol_mode, &p);
   if (rcode != 0) return static_cast<pswfe_status>(rcode);
+  to_c(p, out);
+  return PSWFE_OK;
+}
+
+pswfe_status pswfe_oversample_params(const pswfe_params* base, double sigma, pswfe_params* out) {
+  if (!base || !out) return PSWFE_E_ARG;
+  pswfe::Params b{};
+  const pswfe_status st = params_from_c(base, &b);
+  if (st != PSWFE_OK) return st;
+  pswfe::Params p{};
+  const int rcode = pswfe::oversample_params(b, sigma, &p);
+  if (rcode == 3) return PSWFE_E_GRID;
+  if (rcode != 0) return PSWFE_E_ARG;
+  if (p.cw > 40.0) return PSWFE_E_EPS_RANGE;
   to_c(p, out);
   return PSWFE_OK;
 }

@@ -330,6 +330,28 @@ int choose_params_box(double eps, double Lx, double Ly, double Lz, double rc, in
   return 0;
 }
 
+int oversample_params(const Params& base, double sigma, Params* out) {
+  if (!out || !(sigma >= 1.0) || sigma > 4.0 || base.split != kSplitPswf || base.window != kWindowPswf) return 1;
+  Params p = base;
+  double sig_eff = 1e300;
+  for (int d = 0; d < 3; ++d) {
+    const int md = next_smooth_even(static_cast<int>(std::ceil(sigma * base.grid(d) - 1e-9)));
+    if (md > 512) return 3;
+    (d == 0 ? p.m : (d == 1 ? p.my : p.mz)) = md;
+    const double kband = base.cs * base.side(d) / (2.0 * kPi * base.rc);  // band edge in modes
+    sig_eff = std::min(sig_eff, md / (2.0 * kband));
+  }
+  const double shrink = kPi * (1.0 - 1.0 / (2.0 * std::max(1.0, sig_eff)));
+  const double cw_need = base.cw;  // the base grid's window bandlimit (pi P / 2 from Alg. 3)
+  p.P = std::max(kPminHost, static_cast<int>(std::ceil(cw_need / shrink - 1e-9)));
+  p.cw = shrink * p.P;
+  p.h = p.L / p.m;
+  p.alpha = 0.5 * p.P * p.h;
+  p.alpha_alg = p.alpha;
+  *out = p;
+  return 0;
+}
+
 double default_gauss_shape(int P) { return 0.8 * kPi * P / 2.0; }
 
 // Values M_{k+1}(t + r), r = 0..k, of the uniform B-spline of order k + 1 on [0, k + 1) at the
@@ -411,7 +433,8 @@ void build_tables(const Params& p, int deg, double fit_tol, Tables* t) {
       const double w = 2.0 * kPi * k / Ld;
       double ph = 0.0;
       if (p.window == kWindowPswf) {
-        ph = ad * pw.lambda0 * pw.psi(2.0 * k / md) / pw.psi_0;
+        // alpha_d w / c_w = pi P k / (m_d c_w): 2k/m_d for c_w = pi P / 2, less on oversampled grids
+        ph = ad * pw.lambda0 * pw.psi(std::min(1.0, kPi * P * k / (md * p.cw))) / pw.psi_0;
       } else if (p.window == kWindowGauss) {
         ph = ad * std::sqrt(kPi / p.cg) * std::exp(-w * w * ad * ad / (4.0 * p.cg));
       } else {

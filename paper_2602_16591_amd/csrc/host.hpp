@@ -73,6 +73,16 @@ int choose_params(double eps, double L, double rc, int m, int64_t n, double q_l2
 int choose_params_box(double eps, double Lx, double Ly, double Lz, double rc, int m, int64_t n, double q_l2,
                       int tol_mode, Params* out);
 
+// Oversampled grid (the paper leaves oversampling to future work; see the design notes): every
+// m_d becomes the smallest FFT size >= sigma m_d, and with the effective factor
+// sigma' = min_d m_d / (2 x band edge in modes) the PSWF window bandlimit is
+// c_w = pi P (1 - 1/(2 sigma')), the distance from the band edge to its first alias in units of
+// 1/alpha; P is the smallest support whose c_w reaches base's c_w (pi P / 2 from Alg. 3), so
+// P shrinks by about 1 / (2 - 1/sigma'). sigma = 1 returns base's grid and support. PSWF split
+// and window only; 1 <= sigma <= 4.
+constexpr int kPminHost = 3;
+int oversample_params(const Params& base, double sigma, Params* out);
+
 // Tables consumed by the kernels, all float64.
 struct Tables {
   // Scaling s_k = T_M[|k|^2] * W[|k_x|] * W[|k_y|] * W[|k_z|] (Alg. 2 step 3 with the h^6 of the

@@ -94,3 +94,30 @@ def test_gaussian_split_has_no_residual():
     with pytest.raises(pw.PswfeError) as ei:
         plan.compute(tdev(x, "fp64"), tdev(q, "fp64"), total=True)
     assert ei.value.status == pw.E_ARG
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("sigma", [1.5, 2.0])
+def test_oversampled_grid_matches_oracle(sigma, prec):
+    """A grid oversampled by sigma with the smaller support it allows (pswfe_oversample_params):
+    element-wise parity with the oracle's Alg. 2 on the same parameters, and the tolerance met
+    against the direct sum."""
+    from oracle import params as oparams
+    eps = 1e-6
+    x, q, L = W.paper_default(1500, seed=63)
+    if prec == "fp32":
+        x, q = x.astype(np.float32).astype(np.float64), q.astype(np.float32).astype(np.float64)
+    c = pw.oversample_params(pw.choose_params(eps, L, rc=0.1), sigma)
+    vp = V.oversample(oparams.choose(eps, L, rc=0.1), sigma)
+    assert (c.m, c.P) == (vp.m, vp.P) and abs(c.cw - vp.cw) < 1e-12 * vp.cw
+    plan = pw.Plan(c, prec, n_max=len(q))
+    phi, F, _ = plan.compute(tdev(x, prec), tdev(q, prec))
+    rphi, rg = V.fast_variant(x, q, vp)
+    far = rphi + V.self_coefficient(vp) * q
+    tol_phi = (1e-11 if prec == "fp64" else 2e-6) + 10 * fit_tol(eps, prec)
+    assert np.linalg.norm(phi.double().cpu().numpy() - rphi) / np.linalg.norm(far) < tol_phi
+    rF = direct.forces(q, rg)
+    tol_F = (1e-10 if prec == "fp64" else 2e-5) + 100 * fit_tol(eps, prec)
+    assert np.linalg.norm(F.double().cpu().numpy() - rF) / np.linalg.norm(rF) < tol_F
+    ref, _ = direct.longrange_r2(x, q, L, c.rc, c.cs, grad=False)
+    assert np.linalg.norm(phi.double().cpu().numpy() - ref) / np.linalg.norm(far) < eps
