@@ -3,15 +3,18 @@
  *
  * Method: Bostrom, Tornberg, af Klinteberg, "Fast Ewald summation using prolate spheroidal
  * wave functions" (arXiv 2602.16591). The library evaluates, for n point charges rho_j at
- * positions x_j in the periodic box [0, L)^3 (Sec. 2.1; charge neutral, Sec. 1),
+ * positions x_j in the periodic box [0, L)^3 (Sec. 2.1; charge neutral, Sec. 1), or a cuboid
+ * [0, L) x [0, Ly) x [0, Lz) (Sec. 6.1, remark on cuboid domains),
  *
- *   phi_i = phi_i^far + phi_i^self         (Sec. 3.1; the real-space residual phi^local is
- *                                           not part of this library)
- *   F_i   = -rho_i grad phi_i^far          (Remark in Sec. 3.1, eq. force)
+ *   phi_i = phi_i^far + phi_i^self         (Sec. 3.1), plus on request the real-space residual
+ *                                           phi_i^local (Sec. 3.1.1): the full Ewald sum
+ *   F_i   = -rho_i grad phi_i              (Remark in Sec. 3.1, eq. force)
  *   E     = 1/2 sum_i rho_i phi_i          (Remark in Sec. 3.1)
  *
  * with phi^far computed by the fast Fourier-space summation of Alg. 2 using the PSWF mollifier
- * (Sec. 4.2) and the PSWF window (Sec. 4.3), and parameters from Alg. 3 (Sec. 6).
+ * (Sec. 4.2) and the PSWF window (Sec. 4.3), and parameters from Alg. 3 (Sec. 6). The Gaussian
+ * split and the Gaussian and B-spline windows the paper compares with (Sec. 4.3.1, Sec. 7.3.1-7.4)
+ * run through the same pipeline (pswfe_variant_params).
  * Units: no Coulomb constant (Sec. 1, eq. potential1); phi is charge / length.
  *
  * Conventions for every entry point
