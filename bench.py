@@ -75,21 +75,80 @@ def kernel_source_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(stage: str, prec_ctype: str):
-    """HBM bytes per launch of the stage's kernel from the committed counter summary (FETCH_SIZE
-    and WRITE_SIZE runs, calibrated against a plain copy), or None when the summary is missing
-    or was taken on other kernel sources."""
+LDS_FILE = os.path.join(ROOT, "profiles", "lds_water_box_n30000.md")
+
+
+def _profile_blob(path):
+    """The machine-readable block of a committed counter summary, or None when it is missing or
+    was taken on other kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             text = f.read()
         blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
         return None
-    if blob.get("kernel_source_sha256") != kernel_source_sha256():
-        return None
+    return blob if blob.get("kernel_source_sha256") == kernel_source_sha256() else None
+
+
+def _stage_kernels(blob_keys, stage: str, prec_ctype: str):
     prefixes = tuple(f"{name}<{prec_ctype}" for name in STAGE_KERNEL[stage])
-    hits = [v for k, v in blob.get("bytes_per_launch", {}).items() if k.startswith(prefixes)]
-    return hits[0] if len(hits) == 1 else None
+    hits = [k for k in blob_keys if k.startswith(prefixes)]
+    if stage == "bin":   # the counting sort is three launches: count, scan, scatter
+        hits += [k for k in blob_keys if k == "k_scan" or k.startswith(f"k_bin_scatter<{prec_ctype}")]
+    return hits
+
+
+def measured_traffic(stage: str, prec_ctype: str):
+    """HBM bytes per launch of the stage's kernel(s) from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE runs, calibrated against a plain copy), or None when the summary
+    is missing or was taken on other kernel sources."""
+    blob = _profile_blob(TRAFFIC_FILE)
+    if blob is None:
+        return None
+    per = blob.get("bytes_per_launch", {})
+    hits = _stage_kernels(per.keys(), stage, prec_ctype)
+    if not hits or (stage != "bin" and len(hits) != 1):
+        return None
+    return sum(per[k] for k in hits)
+
+
+def measured_lds(stage: str, prec_ctype: str):
+    """LDS instructions and LDS bank-conflict cycles per launch of the stage's kernel(s) from the
+    committed counter summary, or None."""
+    blob = _profile_blob(LDS_FILE)
+    if blob is None:
+        return None
+    per = blob.get("per_launch", {})
+    hits = _stage_kernels(per.keys(), stage, prec_ctype)
+    if not hits or (stage != "bin" and len(hits) != 1):
+        return None
+    return {c: sum(per[k][c] for k in hits) for c in ("lds_instr", "lds_bank_conflict_cycles", "valu_instr")}
+
+
+def kernel_rooflines(stage_ms: dict, n: int, m: int, P: int, deg: int, elem: int, prec_ctype: str):
+    """Per stage: event-timed duration, the algorithmic work and its roofline fraction, the HBM
+    traffic the counters measured (GB/s against 8 TB/s) and the LDS bank-conflict share of the
+    compute units' cycles (2.4 GHz x 256 CUs)."""
+    out = {}
+    for st in STAGES:
+        us = stage_ms[st] * 1e3
+        kind, work = stage_work(st, n, m, P, deg, elem)
+        row = {"us": us}
+        if kind == "alu":
+            peak = PEAK_FP64_TFLOPS
+            row.update({"bound": "alu", "flops": work, "tflops": work / us * 1e-6, "frac_fp64_peak": work / us * 1e-6 / peak})
+        else:
+            row.update({"bound": "hbm", "algorithmic_bytes": work, "gbs": work / us * 1e-3,
+                        "frac_hbm_peak": work / us * 1e-3 / PEAK_HBM_GBS})
+        t = measured_traffic(st, prec_ctype)
+        if t is not None:
+            row.update({"measured_bytes": t, "measured_gbs": t / us * 1e-3, "measured_frac_hbm_peak": t / us * 1e-3 / PEAK_HBM_GBS})
+        lds = measured_lds(st, prec_ctype)
+        if lds is not None:
+            row.update({"lds_instr": lds["lds_instr"],
+                        "lds_conflict_share": lds["lds_bank_conflict_cycles"] / (us * 2400.0 * 256)})
+        out[st] = row
+    return out
 
 
 def cpu_baseline(x, q, L, eps, m):
@@ -387,6 +446,8 @@ def main():
         "fp64": {"value": n * args.steps / r64["elapsed"], "unit": "particles/s",
                  "ms_per_step": r64["elapsed"] / args.steps * 1e3,
                  "stage_us": {k: v * 1e3 for k, v in r64["stage_ms"].items()}},
+        "kernels_fp32": kernel_rooflines(r["stage_ms"], n, m, P, r["deg"], r["elem"], "float"),
+        "kernels_fp64": kernel_rooflines(r64["stage_ms"], n, m, P, r64["deg"], r64["elem"], "double"),
         "fp32_vs_fp64": {"phi_rel_l2": phi_diff, "phi_abs_rms": phi_abs, "force_rel_l2": F_diff,
                          "energy_rel": abs(r["E"] - r64["E"]) / abs(r64["E"])},
         "total_ewald": {"note": "phi_far + phi_local + phi_self (real-space residual on the GPU), same workload",
