@@ -247,7 +247,13 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   std::vector<int64_t> part_prefix(nsys + 1, 0);
   // complex values per FFT workgroup (measured on gfx950: 1024 on grids up to 96^3, 2048 above)
   int fft_env = 0;
-  if (const char* env = std::getenv("PSWFE_FFT_ELEMS")) fft_env = std::max(64, std::min(4096, std::atoi(env)));
+  if (const char* env = std::getenv("PSWFE_FFT_ELEMS")) fft_env = std::max(64, std::min(8192, std::atoi(env)));
+  // LDS per FFT workgroup (PSWFE_FFT_LDS_KIB overrides, up to 160). Larger blocks measured slower
+  // on MI355X: 160 KiB with 4096 complex values per workgroup took the 216^3 float64 z pass from
+  // 139 to 179 us and the water-box step from 138 to 150 us.
+  size_t fft_lds_cap = 64 * 1024;
+  if (const char* env = std::getenv("PSWFE_FFT_LDS_KIB"))
+    fft_lds_cap = static_cast<size_t>(std::max(16, std::min(160, std::atoi(env)))) * 1024;
   Arena work, tabs;
   struct TabOff { size_t coef, tm, wk, wky, wkz, twhp, twhm, twfp, twfm, twyp, twym, twzp, twzm, lcoef, rpoly; };
   int cell_prefix = 0;
@@ -334,9 +340,9 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     // the twiddle tables.
     const int fft_elems = fft_env > 0 ? fft_env : (m <= 96 ? 1024 : 2048);
     int rpb = std::max(1, std::min(64, fft_elems / nx1));
-    while (rpb > 1 && (2 * static_cast<size_t>(rpb) * nx1 + 2 * N + 1) * celem > 64 * 1024) --rpb;
+    while (rpb > 1 && (2 * static_cast<size_t>(rpb) * nx1 + 2 * N + 1) * celem > fft_lds_cap) --rpb;
     int cmax = std::max(1, std::min(64, fft_elems / (mlen + 1)));
-    while (cmax > 1 && (2 * static_cast<size_t>(cmax) * (mlen + 1) + 2 * mlen) * celem > 64 * 1024) --cmax;
+    while (cmax > 1 && (2 * static_cast<size_t>(cmax) * (mlen + 1) + 2 * mlen) * celem > fft_lds_cap) --cmax;
     const int nxb = (nx1 + cmax - 1) / cmax;
     sd.rows_per_block = rpb;
     sd.cols_per_block = (nx1 + nxb - 1) / nxb;

@@ -833,7 +833,25 @@ const ParticleFns* particle_fns(int prec, int P) {
 
 }  // namespace
 
+template <class T>
+hipError_t raise_fft_lds(const DevPlan& d) {
+  auto set = [](const void* f, size_t bytes) {
+    return bytes > 64 * 1024
+               ? hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes))
+               : hipSuccess;
+  };
+  hipError_t e = set(reinterpret_cast<const void*>(&k_fft_x_r2c<T, T>), d.lds_x);
+  if (e == hipSuccess) e = set(reinterpret_cast<const void*>(&k_fft_x_r2c<T, double>), d.lds_x);
+  if (e == hipSuccess) e = set(reinterpret_cast<const void*>(&k_fft_x_c2r<T>), d.lds_x);
+  if (e == hipSuccess) e = set(reinterpret_cast<const void*>(&k_fft_cols<T>), d.lds_c);
+  return e;
+}
+
 hipError_t prepare_kernels(const DevPlan& d) {
+  {
+    const hipError_t e = d.prec == 0 ? raise_fft_lds<float>(d) : raise_fft_lds<double>(d);
+    if (e != hipSuccess) return e;
+  }
   if (d.plane_fft && d.lds_p > 64 * 1024) {
     hipError_t e;
     if (d.prec == 0)
