@@ -142,6 +142,11 @@ int choose_tile(int m, int P, int requested, int elem, int64_t n_batch) {
 
 double fit_tolerance(double eps, int prec) { return std::max(0.01 * eps, prec == PSWFE_FP32 ? 5e-9 : 1e-15); }
 
+// Relative accuracy of the residual polynomial G. The residual is exact up to rounding (it does
+// not depend on eps), so this is set by the output precision: 1e-10 lies far below float32's
+// unit roundoff of 6e-8 and lets float32 plans run about half the Horner steps.
+double local_fit_tolerance(int prec) { return prec == PSWFE_FP32 ? 1e-10 : 1e-15; }
+
 void free_timer(pswfe::StageTimer& t) {
   if (t.ev) {
     for (int i = 0; i < 2 * t.cap; ++i)
@@ -266,7 +271,8 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     pswfe::Tables& t = plan->tab[s];
     pswfe::build_tables(p, 0, fit_tolerance(p.eps, prec), &t);
     if (p.split == pswfe::kSplitPswf) {
-      pswfe::build_local_table(p, &plan->ltab[s]);
+      pswfe::build_local_table(p, local_fit_tolerance(prec), &plan->ltab[s]);
+      d.local_deg = std::max(d.local_deg, plan->ltab[s].deg);
     } else {
       plan->ltab[s].coef.assign(1, 0.0);  // no residual for the Gaussian split (never launched)
       plan->local_ok = false;
@@ -891,7 +897,7 @@ pswfe_status pswfe_host_local(const pswfe_params* pp, int64_t count, const doubl
   if (st != PSWFE_OK) return st;
   if (p.split != pswfe::kSplitPswf) return PSWFE_E_ARG;
   pswfe::LocalTable t;
-  pswfe::build_local_table(p, &t);
+  pswfe::build_local_table(p, local_fit_tolerance(PSWFE_FP64), &t);
   for (int64_t i = 0; i < count; ++i) {
     const double ri = r[i];
     double Ri = 0.0, dRi = 0.0;

@@ -537,11 +537,12 @@ void build_tables(const Params& p, int deg, double fit_tol, Tables* t) {
   }
 }
 
-// The kernels evaluate the residual polynomial with this many powers in registers; the fit
-// stops there (its sampled relative error is ~1e-15 by degree 20 at every supported c_s).
+// The kernels evaluate the residual polynomial with at most this many powers in registers; the
+// fit stops there (its sampled relative error reaches 1e-15 by degree 20 at every supported c_s,
+// 1e-10 by degree 12 for c_s up to 16).
 constexpr int kLocalMaxDeg = 24;
 
-void build_local_table(const Params& p, LocalTable* t) {
+void build_local_table(const Params& p, double fit_tol, LocalTable* t) {
   const Pswf ps(p.cs);
   t->K = 2.0 / (ps.lambda0 * ps.psi_0 * p.rc);
   // G(t^2) = I(t) / t, with G(0) = psi_0(0)
@@ -566,7 +567,7 @@ void build_local_table(const Params& p, LocalTable* t) {
     t->deg = dg;
     t->coef.swap(coef);
     t->fit_err = err;
-    if (err <= 1e-15) break;
+    if (err <= fit_tol) break;
   }
 }
 

@@ -123,7 +123,8 @@ struct LocalTable {
   double K = 0.0;
   double fit_err = 0.0;      // max |fit - G| / max |G| (sampled)
 };
-void build_local_table(const Params& p, LocalTable* t);
+// Fits G to relative accuracy fit_tol (the lowest degree from 6 up that reaches it, at most 24).
+void build_local_table(const Params& p, double fit_tol, LocalTable* t);
 
 // exp(sign * 2 pi i e / N) for e = 0..N-1, as interleaved (re, im) pairs, float64.
 void twiddles(int N, int sign, std::vector<double>* out);

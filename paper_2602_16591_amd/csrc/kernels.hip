@@ -163,9 +163,8 @@ __global__ void k_cell_scatter(int64_t n, int nsys, const SysDesc* __restrict__ 
 constexpr int kLocalThreads = 128;
 constexpr int kLocalLanes = 8;
 constexpr int kLocalChunk = 1024;
-constexpr int kLocalDeg = 24;  // the residual polynomial G, zero-padded to this degree
-
-template <class T>
+// DEG: the residual polynomial G, zero-padded to this degree (an instance per 12, 16, 20, 24)
+template <class T, int DEG>
 __global__ __launch_bounds__(kLocalThreads) void k_local(int nsys, const SysDesc* __restrict__ sys,
                                                          const int* __restrict__ cell_prefix,
                                                          const double4* __restrict__ lsorted,
@@ -185,10 +184,10 @@ __global__ __launch_bounds__(kLocalThreads) void k_local(int nsys, const SysDesc
   const int nc = sd.nc, ncy = sd.ncy, ncz = sd.ncz;
   const double Lx = sd.L, Ly = sd.Ly, Lz = sd.Lz, inv_Lx = 1.0 / Lx, inv_Ly = 1.0 / Ly, inv_Lz = 1.0 / Lz;
   const double rc2 = sd.rc * sd.rc, inv_rc2 = 1.0 / rc2, K = sd.lK;
-  double cr[kLocalDeg + 1];
+  double cr[DEG + 1];
   const global_ptr<double> lcoef = as_global(sd.lcoef);
 #pragma unroll
-  for (int k = 0; k <= kLocalDeg; ++k) cr[k] = k <= sd.ldeg ? lcoef[k] : 0.0;
+  for (int k = 0; k <= DEG; ++k) cr[k] = k <= sd.ldeg ? lcoef[k] : 0.0;
   const int tid = threadIdx.x;
   // source ranges: the 27 neighbour cells (distinct, as every nc >= 3), or the system's one cell
   if (tid < 27) {
@@ -253,9 +252,9 @@ __global__ __launch_bounds__(kLocalThreads) void k_local(int nsys, const SysDesc
           if (!(r2 < rc2) || r2 == 0.0) continue;  // beyond the cutoff, or coincident positions
           const double rinv = rsqrt(r2);
           const double g = r2 * inv_rc2 - 0.5;
-          double G = cr[kLocalDeg], dG = 0.0;
+          double G = cr[DEG], dG = 0.0;
 #pragma unroll
-          for (int kk = kLocalDeg - 1; kk >= 0; --kk) {
+          for (int kk = DEG - 1; kk >= 0; --kk) {
             dG = fma(dG, g, G);
             G = fma(G, g, cr[kk]);
           }
@@ -928,9 +927,11 @@ hipError_t local_impl(const DevPlan& d, int64_t n, const void* pos, const void* 
     hipLaunchKernelGGL(k_cell_scatter<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d.nsys, d.sys_dev,
                        d.part_prefix, static_cast<const T*>(pos), static_cast<const T*>(q), d.cell_of, d.cell_rank,
                        d.cell_start, reinterpret_cast<double4*>(d.lsorted), d.lperm);
-    hipLaunchKernelGGL(k_local<T>, dim3(d.total_cells), dim3(kLocalThreads), 0, st, d.nsys, d.sys_dev,
-                       d.cell_prefix, reinterpret_cast<const double4*>(d.lsorted), d.lperm, d.cell_start,
-                       static_cast<T*>(phi), static_cast<T*>(vec), vec_mode, accumulate ? 1 : 0, energy);
+    auto kern = d.local_deg <= 12 ? k_local<T, 12> : d.local_deg <= 16 ? k_local<T, 16>
+              : d.local_deg <= 20 ? k_local<T, 20> : k_local<T, 24>;
+    hipLaunchKernelGGL(kern, dim3(d.total_cells), dim3(kLocalThreads), 0, st, d.nsys, d.sys_dev, d.cell_prefix,
+                       reinterpret_cast<const double4*>(d.lsorted), d.lperm, d.cell_start, static_cast<T*>(phi),
+                       static_cast<T*>(vec), vec_mode, accumulate ? 1 : 0, energy);
   }
   stage_end(d, kStageLocal, st);
   return hipGetLastError();

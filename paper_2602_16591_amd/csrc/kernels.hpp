@@ -169,6 +169,7 @@ struct DevPlan {
   int* cell_rank = nullptr;    // n_max
   double* lsorted = nullptr;   // n_max x 4: wrapped position (float64) and charge, by cell
   int* lperm = nullptr;        // n_max: cell-sorted slot -> packed input index
+  int local_deg = 0;           // highest residual polynomial degree over the systems
   StageTimer* timer = nullptr; // optional instrumentation
 };
 
