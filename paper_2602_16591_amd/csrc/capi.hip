@@ -438,12 +438,20 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     if (tiles < 1024) parts = std::min<int64_t>((1024 + tiles - 1) / tiles, std::max<int64_t>(1, per_tile / 32));
     g.parts = parts_env ? parts_env : static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(16, parts)));
   }
+  // the matrix-core form rather than y-columns for the tile edges 4, 6, 8 (PSWFE_SPREAD_MFMA=0
+  // turns it off)
+  bool mfma_ok = true;
+  if (const char* env = std::getenv("PSWFE_SPREAD_MFMA")) mfma_ok = std::atoi(env) != 0;
   for (pswfe::PGroup& g : d.groups) {
     const int S = static_cast<int>(g.lds_spread), P = g.P, D = g.D;
-    g.spread_threads = g.col_tile ? pswfe::col_threads_host(P, g.col_tile)
-                                  : particle_threads(P, [&](int t) { return spread_lds_bytes(S, P, D, t); }, true);
+    g.mfma = g.col_tile && mfma_ok ? 1 : 0;
+    g.spread_threads = g.mfma       ? pswfe::mfma_threads_host(P, g.col_tile)
+                       : g.col_tile ? pswfe::col_threads_host(P, g.col_tile)
+                                    : particle_threads(P, [&](int t) { return spread_lds_bytes(S, P, D, t); }, true);
     g.gather_threads = particle_threads(P, [&](int t) { return gather_lds_bytes(S, P, D, elem, t); }, false);
-    g.lds_spread = g.col_tile ? pswfe::col_lds_bytes(P, D, g.col_tile) : spread_lds_bytes(S, P, D, g.spread_threads);
+    g.lds_spread = g.mfma       ? pswfe::mfma_lds_bytes(P, D, g.col_tile)
+                   : g.col_tile ? pswfe::col_lds_bytes(P, D, g.col_tile)
+                                : spread_lds_bytes(S, P, D, g.spread_threads);
     g.lds_gather = gather_lds_bytes(S, P, D, elem, g.gather_threads);
   }
   d.total_tiles = tile_prefix[nsys];

@@ -32,7 +32,10 @@ __global__ void k_bin_count(int64_t n, int nsys, const SysDesc* __restrict__ sys
   const int cy = grid_coord(pos[3 * i + 1], T(sd.ihy_hi), T(sd.ihy_lo), T(sd.Ly), sd.my, f);
   const int cz = grid_coord(pos[3 * i + 2], T(sd.ihz_hi), T(sd.ihz_lo), T(sd.Lz), sd.mz, f);
   const int tile = sd.tile_base + ((cz / B) * sd.Tny + cy / B) * sd.Tn + cx / B;
-  const int bucket = (tile << sub_log2) | static_cast<int>(i & ((1 << sub_log2) - 1));
+  // sub-bucket: the z-cell within the tile, so a tile's particles come out ordered by z (the
+  // slices of a tile shared by several workgroups then cover narrow z-ranges, and their partial
+  // blocks flush fewer nonzero points)
+  const int bucket = (tile << sub_log2) | (((cz % B) << sub_log2) / B);
   tile_of[i] = bucket;
   rank[i] = atomicAdd(&tile_count[bucket], 1);
 }

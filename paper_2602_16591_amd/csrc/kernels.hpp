@@ -8,6 +8,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <vector>
 
@@ -109,7 +110,8 @@ struct PGroup {
   int P = 0, D = 0;
   int tile_begin = 0, tile_end = 0;
   int spread_threads = 256, gather_threads = 256;  // workgroup sizes (multiples of 64, <= 1024)
-  int col_tile = 0;  // spreading by register columns when the group's tiles all have this edge (4, 6, 8)
+  int col_tile = 0;  // spreading in registers when the group's tiles all have this edge (4, 6, 8)
+  int mfma = 0;      // ... as a matrix product on the matrix cores (k_spread_mfma) rather than by y-columns
   int parts = 1;     // workgroups per tile, each taking an equal slice of the tile's particles
   size_t lds_spread = 0, lds_gather = 0;  // maxima over the group's systems
 };
@@ -123,6 +125,16 @@ inline bool col_tile_ok(int B) { return B == 4 || B == 6 || B == 8; }
 constexpr int kColBatchHost = 32;
 inline int col_edge_host(int P, int B) { return B + 2 * ((P + 1) / 2) - 1; }
 inline int col_threads_host(int P, int B) { return (col_edge_host(P, B) * col_edge_host(P, B) + 63) / 64 * 64; }
+inline int mfma_threads_host(int P, int B) {
+  const int S = col_edge_host(P, B), pieces = (S * S + 15) / 16;
+  return 64 * ((pieces + 3) / 4);
+}
+inline size_t mfma_lds_bytes(int P, int D, int B) {
+  const size_t S = static_cast<size_t>(col_edge_host(P, B));
+  const size_t batch = sizeof(double) * (static_cast<size_t>(P) * coef_stride(D) + kColBatchHost * (3 * S + 4)) +
+                       sizeof(int) * kColBatchHost * 4;
+  return std::max(batch, sizeof(double) * S * S * S);  // the records, then the block
+}
 inline size_t col_lds_bytes(int P, int D, int B) {
   const int S = col_edge_host(P, B);
   return sizeof(double) * (static_cast<size_t>(P) * coef_stride(D) + kColBatchHost * (3 * S + 4)) +
@@ -149,9 +161,10 @@ struct DevPlan {
   int64_t* part_prefix = nullptr;  // nsys + 1 (batches; a single system takes n per call)
   int total_tiles = 0, total_xblk = 0, total_cblk = 0;
   size_t lds_x = 0, lds_c = 0;     // maxima over the systems
-  // binning, over all systems. Each tile's counter is split into 2^sub_log2 sub-buckets
-  // (particle index mod 2^sub_log2), so fewer atomics queue on one address; a tile's
-  // particles stay contiguous: tile t owns [tile_start[t << sub_log2], tile_start[(t+1) << sub_log2]).
+  // binning, over all systems. Each tile's counter is split into 2^sub_log2 sub-buckets by
+  // the particle's z-cell within the tile, so fewer atomics queue on one address and a tile's
+  // particles come out ordered by z; a tile's particles stay contiguous: tile t owns
+  // [tile_start[t << sub_log2], tile_start[(t+1) << sub_log2]).
   int sub_log2 = 0;
   int* tile_count = nullptr;   // total_tiles << sub_log2, kept all-zero between calls
   int* tile_start = nullptr;   // (total_tiles << sub_log2) + 1

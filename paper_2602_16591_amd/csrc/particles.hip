@@ -302,6 +302,166 @@ __global__ __launch_bounds__((col_threads<P, B>())) void k_spread_cols(
   }
 }
 
+// Spreading as a matrix product on the matrix cores, for tile edges 4, 6 and 8 (Alg. 2 step 1,
+// same sums as k_spread). Over a tile's particles the S^3 block is
+//   C[(z, y), x] = sum_p U[(z, y), p] V[p, x],  U = q_p w_z,p[z] w_y,p[y],  V = w_x,p[x],
+// a product of an S^2 x K and a K x S matrix (K = the tile's particles). The block is cut into
+// 16 x 16 pieces of C held in the accumulators of v_mfma_f64_16x16x4f64, kMfmaPieces row
+// pieces (all column pieces) per wave; each instruction takes 4 particles. Particles are taken
+// kColBatch at a time: their window values are written to LDS as S-long arrays per dimension
+// (zero outside the support, the z-values multiplied by the charge); per 4 particles a lane
+// reads one value of V per column piece and two of U per row piece. The block is then written
+// to LDS and added to the grid with lanes of consecutive x on consecutive addresses.
+// Accumulator layout of the instruction: item r of lane l holds row l / 16 + 4 r, column l % 16;
+// operand a of lane l is A[l % 16][l / 16], operand b is B[l / 16][l % 16].
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+constexpr int kMfmaPieces = 4;
+template <int P, int B>
+constexpr int mfma_row_pieces() { return (col_edge<P, B>() * col_edge<P, B>() + 15) / 16; }
+template <int P, int B>
+constexpr int mfma_col_pieces() { return (col_edge<P, B>() + 15) / 16; }
+template <int P, int B>
+constexpr int mfma_threads() { return 64 * ((mfma_row_pieces<P, B>() + kMfmaPieces - 1) / kMfmaPieces); }
+
+template <class T, int P, int D, int B>
+__global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
+    const typename Vec4<T>::type* __restrict__ sorted, const int* __restrict__ cells,
+    const int* __restrict__ tile_start, int sub_log2, int nsys, const SysDesc* __restrict__ sys,
+    const int* __restrict__ tile_prefix, const int* __restrict__ tile_sys, int tile_offset, int parts) {
+  constexpr int S = col_edge<P, B>();
+  constexpr int MR = mfma_row_pieces<P, B>();
+  constexpr int NC = mfma_col_pieces<P, B>();
+  constexpr int CS = coef_stride(D);
+  constexpr int RS = 3 * S;
+  extern __shared__ unsigned char smem_raw[];
+  const int gtile = tile_offset + static_cast<int>(blockIdx.x) / parts;
+  int p0, p1;
+  tile_slice(tile_start, gtile, sub_log2, static_cast<int>(blockIdx.x) % parts, parts, p0, p1);
+  if (p0 == p1) return;
+  const SysDesc& sd = sys[tile_sys[find_sys(tile_prefix, nsys, gtile)]];
+  const int m = sd.m, Tn = sd.Tn;
+  double* __restrict__ grid = sd.grid_a;
+  double* lcoef = reinterpret_cast<double*>(smem_raw);  // P * CS
+  double* recs = lcoef + P * CS;                        // kColBatch * RS
+  double* pg = recs + kColBatch * RS;                   // kColBatch * 4: g_x, g_y, g_z, q
+  int* po = reinterpret_cast<int*>(pg + kColBatch * 4); // kColBatch * 4: o_x, o_y, o_z
+  const int tile = gtile - sd.tile_base;
+  const int tx = tile % Tn, ty = (tile / Tn) % sd.Tny, tz = tile / (Tn * sd.Tny);
+  const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
+  stage_coefficients<P, D>(sd.coef, sd.deg, lcoef);
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  // this lane's rows of U (one per row piece) and columns of V (one per column piece)
+  int zo[kMfmaPieces], yo[kMfmaPieces];
+  double rmask[kMfmaPieces];
+#pragma unroll
+  for (int u = 0; u < kMfmaPieces; ++u) {
+    const int row = (wave * kMfmaPieces + u) * 16 + lr;
+    const bool ok = row < S * S;
+    zo[u] = 2 * S + (ok ? row / S : 0);
+    yo[u] = S + (ok ? row % S : 0);
+    rmask[u] = ok ? 1.0 : 0.0;
+  }
+  int xo[NC];
+  double cmask[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int x = c * 16 + lr;
+    xo[c] = x < S ? x : 0;
+    cmask[c] = x < S ? 1.0 : 0.0;
+  }
+  mfma_d4 acc[kMfmaPieces][NC];
+#pragma unroll
+  for (int u = 0; u < kMfmaPieces; ++u)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[u][c] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+  auto r_next = sorted[min(p0 + t, p1 - 1)];
+  int c_next = cells[min(p0 + t, p1 - 1)];
+  for (int b0 = p0; b0 < p1; b0 += kColBatch) {
+    const int nb = min(kColBatch, p1 - b0);
+    const auto r = r_next;
+    const int cp = c_next;
+    if (t < kColBatch) {
+      r_next = sorted[min(b0 + kColBatch + t, p1 - 1)];
+      c_next = cells[min(b0 + kColBatch + t, p1 - 1)];
+    }
+    if (t < nb) {
+      int o0, o1, o2;
+      pg[4 * t + 0] = static_cast<double>(centred_offset<T, P>(r.x, cell_x(cp), T0x, o0));
+      pg[4 * t + 1] = static_cast<double>(centred_offset<T, P>(r.y, cell_y(cp), T0y, o1));
+      pg[4 * t + 2] = static_cast<double>(centred_offset<T, P>(r.z, cell_z(cp), T0z, o2));
+      pg[4 * t + 3] = static_cast<double>(r.w);
+      po[4 * t + 0] = o0;
+      po[4 * t + 1] = o1;
+      po[4 * t + 2] = o2;
+    }
+    __syncthreads();
+    const int nb4 = (nb + 3) & ~3;  // whole groups of 4 particles; the padding records are zero
+    // the P window values of each particle and dimension (Horner), then the S - P zeros around
+    // them, so that no lane runs Horner for a zero
+    for (int e = t; e < nb4 * 3 * P; e += blockDim.x) {
+      const int k = e / (3 * P), rr = e - k * (3 * P), d = rr / P, j = rr - d * P;
+      double v = 0.0;
+      if (k < nb) {
+        const double g = pg[4 * k + d];
+        const double* c = lcoef + j * CS;
+        v = c[D];
+#pragma unroll
+        for (int kk = D - 1; kk >= 0; --kk) v = fma(v, g, c[kk]);
+        if (d == 2) v *= pg[4 * k + 3];
+      }
+      recs[k * RS + d * S + (k < nb ? po[4 * k + d] : 0) + j] = v;
+    }
+    for (int e = t; e < nb4 * 3 * (S - P); e += blockDim.x) {
+      const int k = e / (3 * (S - P)), rr = e - k * (3 * (S - P)), d = rr / (S - P), jj = rr - d * (S - P);
+      const int o = k < nb ? po[4 * k + d] : 0;
+      recs[k * RS + d * S + (jj < o ? jj : jj + P)] = 0.0;
+    }
+    __syncthreads();
+    for (int k4 = 0; k4 < nb4; k4 += 4) {
+      const double* R = recs + (k4 + lk) * RS;
+      // every piece takes every group: skipping the pieces outside the group's z-range (the
+      // particles are ordered by z) measured slower, as the branches break up the chain of
+      // matrix instructions
+      double bv[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) bv[c] = R[xo[c]] * cmask[c];
+#pragma unroll
+      for (int u = 0; u < kMfmaPieces; ++u) {
+        if (wave * kMfmaPieces + u < MR) {
+          const double av = R[zo[u]] * R[yo[u]] * rmask[u];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc[u][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[c], acc[u][c], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double* blk = reinterpret_cast<double*>(smem_raw);  // S^3, over the coefficients and records
+#pragma unroll
+  for (int u = 0; u < kMfmaPieces; ++u) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int x = c * 16 + lr;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = (wave * kMfmaPieces + u) * 16 + lk + 4 * q;
+        if (row < S * S && x < S) blk[row * S + x] = acc[u][c][q];
+      }
+    }
+  }
+  __syncthreads();
+  constexpr int half = (P + 1) / 2;
+  double v[8];
+  walk_tile<8>(
+      S, m, sd.my, sd.mz, T0x + 1 - half, T0y + 1 - half, T0z + 1 - half,
+      [&](int k, int li_, int64_t) { v[k] = blk[li_]; },
+      [&](int k, int, int64_t gi) {
+        if (v[k] != 0.0) atomic_add_global(grid + gi, v[k]);
+      });
+}
+
 // Interpolation (Alg. 2 step 5 and eq. force): phi = sum b w_x w_y w_z and its gradient as
 // nested sums: each lane runs the x-sums of its lines for the value and the x-derivative,
 // weights them with the y/z windows and derivatives, and the 16 lanes of a particle reduce.
@@ -471,7 +631,13 @@ hipError_t spread_impl(const DevPlan& d, const PGroup& g, hipStream_t st) {
                        static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start, d.sub_log2, d.nsys,
                        d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin, g.parts);
   };
-  if (g.col_tile == 4)
+  if (g.mfma && g.col_tile == 4)
+    cols(k_spread_mfma<T, P, D, 4>, mfma_threads<P, 4>());
+  else if (g.mfma && g.col_tile == 6)
+    cols(k_spread_mfma<T, P, D, 6>, mfma_threads<P, 6>());
+  else if (g.mfma && g.col_tile == 8)
+    cols(k_spread_mfma<T, P, D, 8>, mfma_threads<P, 8>());
+  else if (g.col_tile == 4)
     cols(k_spread_cols<T, P, D, 4>, col_threads<P, 4>());
   else if (g.col_tile == 6)
     cols(k_spread_cols<T, P, D, 6>, col_threads<P, 6>());
@@ -499,10 +665,13 @@ hipError_t gather_impl(const DevPlan& d, const PGroup& g, const void* grid, void
 template <class T, int P, int D>
 hipError_t prepare_impl(const PGroup& g) {
   if (g.lds_spread > 64 * 1024) {
-    const void* fn = g.col_tile == 4   ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 4>)
-                     : g.col_tile == 6 ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 6>)
-                     : g.col_tile == 8 ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 8>)
-                                       : reinterpret_cast<const void*>(&k_spread<T, P, D>);
+    const void* fn = g.mfma && g.col_tile == 4 ? reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 4>)
+                     : g.mfma && g.col_tile == 6 ? reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 6>)
+                     : g.mfma && g.col_tile == 8 ? reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 8>)
+                     : g.col_tile == 4             ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 4>)
+                     : g.col_tile == 6             ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 6>)
+                     : g.col_tile == 8             ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 8>)
+                                                   : reinterpret_cast<const void*>(&k_spread<T, P, D>);
     const hipError_t e =
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(g.lds_spread));
     if (e != hipSuccess) return e;

@@ -121,16 +121,22 @@ SPREAD_KERNEL_CASES = [
 ]
 
 
-@pytest.mark.parametrize("columns", ["1", "0"])
+SPREAD_KERNELS = {"mfma": ("1", "1"), "columns": ("1", "0"), "lds": ("0", "0")}
+
+
+@pytest.mark.parametrize("kernel", list(SPREAD_KERNELS))
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", SPREAD_KERNEL_CASES, ids=[c[0] for c in SPREAD_KERNEL_CASES])
-def test_both_spreading_kernels_match_oracle(case, prec, columns, monkeypatch):
-    """Spreading by LDS atomics (any tile) and by register columns (tiles of edge 8): the grid
-    against the oracle's spreading, and the whole pipeline against Alg. 2 in float64."""
+def test_every_spreading_kernel_matches_oracle(case, prec, kernel, monkeypatch):
+    """Spreading by LDS atomics (any tile), by register columns and as a matrix product on the
+    matrix cores (tiles of edge 4, 6, 8): the grid against the oracle's spreading, and the whole
+    pipeline against Alg. 2 in float64."""
     _, gen, eps, kw, tile = case
     if prec == "fp32" and eps < 1e-6:
         pytest.skip("fp32 path is for eps >= 1e-6")
+    columns, mfma = SPREAD_KERNELS[kernel]
     monkeypatch.setenv("PSWFE_SPREAD_COLUMNS", columns)
+    monkeypatch.setenv("PSWFE_SPREAD_MFMA", mfma)
     x, q, L, kw = _sys(gen, eps, kw, prec)
     c, o = both_params(eps, L, **kw)
     plan = pw.Plan(c, prec, n_max=len(q), tile=tile)
@@ -149,9 +155,10 @@ def test_both_spreading_kernels_match_oracle(case, prec, columns, monkeypatch):
 
 
 DENSE_CASES = [
-    # (name, generator, eps, params kwargs, tile): many particles per tile, few tiles
-    ("dense_m24_tile8_cols", lambda: W.uniform_pm1(24000, seed=26), 1e-6, dict(m=24), 8),
-    ("dense_m20_tile5_lds", lambda: W.paper_default(9000, seed=27, L=1.1), 1e-6, dict(m=20), 5),
+    # (name, generator, eps, params kwargs, tile, spreading kernel): many particles per tile, few tiles
+    ("dense_m24_tile8_mfma", lambda: W.uniform_pm1(24000, seed=26), 1e-6, dict(m=24), 8, "mfma"),
+    ("dense_m24_tile8_cols", lambda: W.uniform_pm1(24000, seed=26), 1e-6, dict(m=24), 8, "columns"),
+    ("dense_m20_tile5_lds", lambda: W.paper_default(9000, seed=27, L=1.1), 1e-6, dict(m=20), 5, "lds"),
 ]
 
 
@@ -162,7 +169,10 @@ def test_dense_tiles_shared_by_workgroups(case, prec, parts, monkeypatch):
     """Dense tiles split over several workgroups (each spreading its slice of the tile's
     particles into its own partial block, or interpolating its slice): the same results as the
     oracle, whatever the number of parts (automatic: 1024 / tiles, here 2 to 16)."""
-    _, gen, eps, kw, tile = case
+    _, gen, eps, kw, tile, kernel = case
+    columns, mfma = SPREAD_KERNELS[kernel]
+    monkeypatch.setenv("PSWFE_SPREAD_COLUMNS", columns)
+    monkeypatch.setenv("PSWFE_SPREAD_MFMA", mfma)
     if parts != "auto":
         monkeypatch.setenv("PSWFE_TILE_PARTS", parts)
     x, q, L, kw = _sys(gen, eps, kw, prec)
