@@ -500,6 +500,12 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   d.tile_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
   d.tile_sys = static_cast<int*>(alloc(sizeof(int) * nsys));
   d.total_cells = cell_prefix;
+  // residual workgroup size: 512 threads (PSWFE_LOCAL_THREADS=128 or 256 overrides)
+  d.local_threads = 512;
+  if (const char* env = std::getenv("PSWFE_LOCAL_THREADS")) {
+    const int v = std::atoi(env);
+    if (v == 128 || v == 256) d.local_threads = v;
+  }
   d.cell_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
   d.cell_count = static_cast<int*>(alloc(sizeof(int) * d.total_cells));
   d.cell_start = static_cast<int*>(alloc(sizeof(int) * (d.total_cells + 1)));

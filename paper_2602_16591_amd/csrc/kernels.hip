@@ -163,12 +163,15 @@ __global__ void k_cell_scatter(int64_t n, int nsys, const SysDesc* __restrict__ 
 // handled by kLocalLanes lanes that split the sources and reduce with shuffles. The residual's
 // polynomial coefficients are held in registers, and no division or memory access other than
 // LDS reads sits in the pair loop.
-constexpr int kLocalThreads = 128;
+// Workgroups of NT = 512 threads (128 and 256 on request): the kernel is latency-bound, and
+// measured on MI355X more waves per cell beat the lanes they leave idle (a water-box cell of
+// ~17 particles fills 17 of 64 target slots): 112 / 84 / 80 us for NT = 128 / 256 / 512, and
+// 3.4 / 2.6 / 2.4 ms at n = 1e6.
 constexpr int kLocalLanes = 8;
 constexpr int kLocalChunk = 1024;
 // DEG: the residual polynomial G, zero-padded to this degree (an instance per 12, 16, 20, 24)
-template <class T, int DEG>
-__global__ __launch_bounds__(kLocalThreads) void k_local(int nsys, const SysDesc* __restrict__ sys,
+template <class T, int DEG, int NT>
+__global__ __launch_bounds__(NT) void k_local(int nsys, const SysDesc* __restrict__ sys,
                                                          const int* __restrict__ cell_prefix,
                                                          const double4* __restrict__ lsorted,
                                                          const int* __restrict__ lperm,
@@ -178,7 +181,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_local(int nsys, const SysDesc
   __shared__ double4 src[kLocalChunk];
   __shared__ int src_id[kLocalChunk];
   __shared__ int nb_begin[27], nb_off[28];
-  __shared__ double s_red[kLocalThreads / 64];
+  __shared__ double s_red[NT / 64];
   const int gcell = blockIdx.x;
   const int t0 = cell_start[gcell], t1 = cell_start[gcell + 1];
   if (t0 == t1) return;
@@ -218,7 +221,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_local(int nsys, const SysDesc
   __syncthreads();
   const int ns = nb_off[27];
   const int grp = tid / kLocalLanes, lane = tid % kLocalLanes;
-  constexpr int kTargetsPerPass = kLocalThreads / kLocalLanes;
+  constexpr int kTargetsPerPass = NT / kLocalLanes;
   double esum = 0.0;
   for (int tb = t0; tb < t1; tb += kTargetsPerPass) {
     const int ti = tb + grp;
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_local(int nsys, const SysDesc
     for (int c0 = 0; c0 < ns; c0 += kLocalChunk) {
       const int nchunk = min(kLocalChunk, ns - c0);
       __syncthreads();
-      for (int k = tid; k < nchunk; k += kLocalThreads) {
+      for (int k = tid; k < nchunk; k += NT) {
         const int gk = c0 + k;
         int lo = 0, hi = 26;  // the neighbour cell holding source gk: largest cc with nb_off[cc] <= gk
         while (lo < hi) {
@@ -299,7 +302,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_local(int nsys, const SysDesc
     __syncthreads();
     if (tid == 0) {
       double tot = 0.0;
-      for (int w = 0; w < kLocalThreads / 64; ++w) tot += s_red[w];
+      for (int w = 0; w < NT / 64; ++w) tot += s_red[w];
       unsafeAtomicAdd(energy + s, tot);
     }
   }
@@ -930,11 +933,27 @@ hipError_t local_impl(const DevPlan& d, int64_t n, const void* pos, const void* 
     hipLaunchKernelGGL(k_cell_scatter<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d.nsys, d.sys_dev,
                        d.part_prefix, static_cast<const T*>(pos), static_cast<const T*>(q), d.cell_of, d.cell_rank,
                        d.cell_start, reinterpret_cast<double4*>(d.lsorted), d.lperm);
-    auto kern = d.local_deg <= 12 ? k_local<T, 12> : d.local_deg <= 16 ? k_local<T, 16>
-              : d.local_deg <= 20 ? k_local<T, 20> : k_local<T, 24>;
-    hipLaunchKernelGGL(kern, dim3(d.total_cells), dim3(kLocalThreads), 0, st, d.nsys, d.sys_dev, d.cell_prefix,
-                       reinterpret_cast<const double4*>(d.lsorted), d.lperm, d.cell_start, static_cast<T*>(phi),
-                       static_cast<T*>(vec), vec_mode, accumulate ? 1 : 0, energy);
+    const auto launch = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(d.total_cells), dim3(d.local_threads), 0, st, d.nsys, d.sys_dev, d.cell_prefix,
+                         reinterpret_cast<const double4*>(d.lsorted), d.lperm, d.cell_start, static_cast<T*>(phi),
+                         static_cast<T*>(vec), vec_mode, accumulate ? 1 : 0, energy);
+    };
+    const auto by_threads = [&]<int DEG>() {
+      if (d.local_threads == 128)
+        launch(k_local<T, DEG, 128>);
+      else if (d.local_threads == 256)
+        launch(k_local<T, DEG, 256>);
+      else
+        launch(k_local<T, DEG, 512>);
+    };
+    if (d.local_deg <= 12)
+      by_threads.template operator()<12>();
+    else if (d.local_deg <= 16)
+      by_threads.template operator()<16>();
+    else if (d.local_deg <= 20)
+      by_threads.template operator()<20>();
+    else
+      by_threads.template operator()<24>();
   }
   stage_end(d, kStageLocal, st);
   return hipGetLastError();

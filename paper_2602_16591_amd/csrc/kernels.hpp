@@ -183,6 +183,7 @@ struct DevPlan {
   double* lsorted = nullptr;   // n_max x 4: wrapped position (float64) and charge, by cell
   int* lperm = nullptr;        // n_max: cell-sorted slot -> packed input index
   int local_deg = 0;           // highest residual polynomial degree over the systems
+  int local_threads = 512;     // residual workgroup size (128, 256, 512)
   StageTimer* timer = nullptr; // optional instrumentation
 };
 

@@ -77,6 +77,23 @@ def test_local_matches_oracle(case, prec):
     assert rel_l2(G.cpu().numpy(), rg) < 10 * tol
 
 
+@pytest.mark.parametrize("threads", ["128", "256", "default"])
+def test_local_workgroup_sizes_match_oracle(threads, monkeypatch):
+    """Every residual workgroup size (16, 32 or 64 targets per pass; cells of ~32 particles take
+    one to two passes) gives the oracle's pair sum."""
+    if threads != "default":
+        monkeypatch.setenv("PSWFE_LOCAL_THREADS", threads)
+    x, q, L = W.uniform_pm1(4000, seed=45)
+    c = pw.choose_params(1e-6, L, m=24)
+    o = oparams.choose(1e-6, L, m=24)
+    plan = pw.Plan(c, "fp64", n_max=len(q))
+    phi, F, E = plan.local(tdev(x, "fp64"), tdev(q, "fp64"))
+    rphi, rg = direct.local_direct(x, q, L, o.rc, o.cs)
+    assert rel_l2(phi.cpu().numpy(), rphi) < 1e-12
+    assert rel_l2(F.cpu().numpy(), direct.forces(q, rg)) < 1e-11
+    assert abs(float(E.cpu()[0]) - 0.5 * float(np.dot(q, rphi))) <= 1e-12 * 0.5 * float(np.abs(q) @ np.abs(rphi))
+
+
 def test_total_matches_gaussian_ewald():
     """phi_far + phi_local + phi_self at eps = 1e-10 against the classical Gaussian split
     converged to ~1e-14 (Example 1): the total does not depend on the split."""
