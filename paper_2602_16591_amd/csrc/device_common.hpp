@@ -132,21 +132,24 @@ __device__ __forceinline__ int grid_coord(T x, T ih_hi, T ih_lo, T L, int m, T& 
 
 // ------------------------------------------------------------------------------------
 // Window evaluation. For a particle at x/h = c + f (cell c, 0 <= f < 1) the support is the
-// P consecutive points starting at floor(c + f - P/2) + 1; point j sits at offset
-// u_j = g + (P-1)/2 - j with g in [-1/2, 1/2), and its window value phi_1(2 u_j / P) is the
-// polynomial `coef[j]` evaluated at g (Horner). `o` is the support start relative to the
-// tile origin T0 + 1 - ceil(P/2).
+// P consecutive points starting at floor(c + f - P/2) + 1 = a + 1 - ceil(P/2), with the anchor
+// a = c for even P and the nearest grid point a = c + [f >= 1/2] (mod m) for odd P; point j sits
+// at offset u_j = g + (P-1)/2 - j with g = f - 1/2 (even P) or f - [f >= 1/2] (odd P), g in
+// [-1/2, 1/2), and its window value phi_1(2 u_j / P) is the polynomial `coef[j]` evaluated at g
+// (Horner). Binning sorts particles by the tile of their anchor and stores (g, anchor), so the
+// support starts at o = a - T0 from the tile's halo origin T0 + 1 - ceil(P/2), with o in
+// [0, B - 1]: the halo block has edge S = B + P - 1.
 // ------------------------------------------------------------------------------------
-template <class T, int P>
-__device__ __forceinline__ T centred_offset(T f, int c, int T0, int& o) {
-  if constexpr (P % 2 == 0) {
-    o = c - T0;
-    return f - T(0.5);
-  } else {
-    const int hh = f >= T(0.5) ? 1 : 0;
-    o = c - T0 + hh;
-    return f - static_cast<T>(hh);
+template <class T>
+__device__ __forceinline__ int support_anchor(int c, T f, int P, int m, T& g) {
+  if (P % 2 == 0) {
+    g = f - T(0.5);
+    return c;
   }
+  const int hh = f >= T(0.5) ? 1 : 0;
+  g = f - static_cast<T>(hh);
+  const int a = c + hh;
+  return a >= m ? a - m : a;
 }
 
 // Periodic image of a grid index a in [-m, 3m) (the range of every halo index: a tile origin

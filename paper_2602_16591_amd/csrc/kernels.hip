@@ -27,10 +27,13 @@ __global__ void k_bin_count(int64_t n, int nsys, const SysDesc* __restrict__ sys
   if (i >= n) return;
   const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
   const int B = sd.B;
-  T f;
-  const int cx = grid_coord(pos[3 * i + 0], T(sd.ih_hi), T(sd.ih_lo), T(sd.L), sd.m, f);
-  const int cy = grid_coord(pos[3 * i + 1], T(sd.ihy_hi), T(sd.ihy_lo), T(sd.Ly), sd.my, f);
-  const int cz = grid_coord(pos[3 * i + 2], T(sd.ihz_hi), T(sd.ihz_lo), T(sd.Lz), sd.mz, f);
+  T f[3], g;
+  const int c0 = grid_coord(pos[3 * i + 0], T(sd.ih_hi), T(sd.ih_lo), T(sd.L), sd.m, f[0]);
+  const int c1 = grid_coord(pos[3 * i + 1], T(sd.ihy_hi), T(sd.ihy_lo), T(sd.Ly), sd.my, f[1]);
+  const int c2 = grid_coord(pos[3 * i + 2], T(sd.ihz_hi), T(sd.ihz_lo), T(sd.Lz), sd.mz, f[2]);
+  const int cx = support_anchor(c0, f[0], sd.P, sd.m, g);
+  const int cy = support_anchor(c1, f[1], sd.P, sd.my, g);
+  const int cz = support_anchor(c2, f[2], sd.P, sd.mz, g);
   const int tile = sd.tile_base + ((cz / B) * sd.Tny + cy / B) * sd.Tn + cx / B;
   // sub-bucket: the z-cell within the tile, so a tile's particles come out ordered by z (the
   // slices of a tile shared by several workgroups then cover narrow z-ranges, and their partial
@@ -87,7 +90,8 @@ __global__ __launch_bounds__(1024) void k_scan(int ntiles, int* __restrict__ cou
   if (tid == 0) start[ntiles] = s_carry;
 }
 
-// Sorted record: (f_x, f_y, f_z, q) and the packed cell of the particle in its system.
+// Sorted record: (g_x, g_y, g_z, q), the centred offsets from the support anchors, and the
+// packed anchor of the particle in its system.
 template <class T>
 __global__ void k_bin_scatter(int64_t n, int nsys, const SysDesc* __restrict__ sys,
                               const int64_t* __restrict__ part_prefix, const T* __restrict__ pos,
@@ -99,9 +103,13 @@ __global__ void k_bin_scatter(int64_t n, int nsys, const SysDesc* __restrict__ s
   const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
   const int dst = tile_start[tile_of[i]] + rank[i];
   typename Vec4<T>::type r;
-  const int cx = grid_coord(pos[3 * i + 0], T(sd.ih_hi), T(sd.ih_lo), T(sd.L), sd.m, r.x);
-  const int cy = grid_coord(pos[3 * i + 1], T(sd.ihy_hi), T(sd.ihy_lo), T(sd.Ly), sd.my, r.y);
-  const int cz = grid_coord(pos[3 * i + 2], T(sd.ihz_hi), T(sd.ihz_lo), T(sd.Lz), sd.mz, r.z);
+  T f[3];
+  const int c0 = grid_coord(pos[3 * i + 0], T(sd.ih_hi), T(sd.ih_lo), T(sd.L), sd.m, f[0]);
+  const int c1 = grid_coord(pos[3 * i + 1], T(sd.ihy_hi), T(sd.ihy_lo), T(sd.Ly), sd.my, f[1]);
+  const int c2 = grid_coord(pos[3 * i + 2], T(sd.ihz_hi), T(sd.ihz_lo), T(sd.Lz), sd.mz, f[2]);
+  const int cx = support_anchor(c0, f[0], sd.P, sd.m, r.x);
+  const int cy = support_anchor(c1, f[1], sd.P, sd.my, r.y);
+  const int cz = support_anchor(c2, f[2], sd.P, sd.mz, r.z);
   r.w = q ? q[i] : T(0);
   sorted[dst] = r;
   cells[dst] = pack_cell(cx, cy, cz);

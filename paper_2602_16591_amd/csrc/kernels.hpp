@@ -49,7 +49,7 @@ struct SysDesc {
   int B = 0;                  // tile edge in grid cells
   int Tn = 0;                 // tiles along x
   int Tny = 0, Tnz = 0;       // tiles along y and z
-  int S = 0;                  // LDS tile edge = B + 2 ceil(P/2) - 1
+  int S = 0;                  // LDS tile edge = (B + P - 1) rounded up to odd
   int tile_base = 0;          // first global tile of this system
   int rows_per_block = 1;     // x-direction FFT batching
   int cols_per_block = 1;     // y/z-direction FFT batching
@@ -123,7 +123,7 @@ inline int particle_max_threads_host(int P) { return P <= 13 ? 1024 : 512; }
 // and LDS.
 inline bool col_tile_ok(int B) { return B == 4 || B == 6 || B == 8; }
 constexpr int kColBatchHost = 32;
-inline int col_edge_host(int P, int B) { return B + 2 * ((P + 1) / 2) - 1; }
+inline int col_edge_host(int P, int B) { return B + P - 1; }
 inline int col_threads_host(int P, int B) { return (col_edge_host(P, B) * col_edge_host(P, B) + 63) / 64 * 64; }
 inline int mfma_threads_host(int P, int B) {
   const int S = col_edge_host(P, B), pieces = (S * S + 15) / 16;

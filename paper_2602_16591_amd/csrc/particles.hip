@@ -25,7 +25,7 @@ namespace {
 // ------------------------------------------------------------------------------------
 // Particle kernels, one launch per (window support P, degree bucket D) over the tiles of the
 // systems in that group. A workgroup (4 waves) owns one tile of B^3 cells of one system and an
-// LDS copy of the S^3 grid points its particles' supports touch (S = B + 2 ceil(P/2) - 1).
+// LDS copy of the S^3 grid points its particles' supports touch (S = B + P - 1, rounded up to odd).
 // Each wave works on 4 particles at a time, 16 lanes per particle:
 //  * lane j evaluates window piece j for the three coordinates at once (3 independent Horner
 //    chains, 6 with derivatives; pieces j and j + 16 when P > 16), the coefficients of piece j
@@ -132,9 +132,12 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_spread(const type
     c_next = cells[min(pi + nslots, p1 - 1)];
     int o[3];
     double g[3];
-    g[0] = static_cast<double>(centred_offset<T, P>(r.x, cell_x(cp), T0x, o[0]));
-    g[1] = static_cast<double>(centred_offset<T, P>(r.y, cell_y(cp), T0y, o[1]));
-    g[2] = static_cast<double>(centred_offset<T, P>(r.z, cell_z(cp), T0z, o[2]));
+    g[0] = static_cast<double>(r.x);
+    o[0] = cell_x(cp) - T0x;
+    g[1] = static_cast<double>(r.y);
+    o[1] = cell_y(cp) - T0y;
+    g[2] = static_cast<double>(r.z);
+    o[2] = cell_z(cp) - T0z;
 #pragma unroll
     for (int jj = 0; jj < (P + kLanesPerParticle - 1) / kLanesPerParticle; ++jj) {
       const int j = li + kLanesPerParticle * jj;
@@ -205,7 +208,7 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_spread(const type
 // consecutive ix writing consecutive addresses.
 constexpr int kColBatch = 32;
 template <int P, int B>
-constexpr int col_edge() { return B + 2 * ((P + 1) / 2) - 1; }
+constexpr int col_edge() { return B + P - 1; }
 template <int P, int B>
 constexpr int col_threads() { return (col_edge<P, B>() * col_edge<P, B>() + 63) / 64 * 64; }
 
@@ -252,9 +255,12 @@ __global__ __launch_bounds__((col_threads<P, B>())) void k_spread_cols(
     }
     if (t < nb) {
       int o0, o1, o2;
-      pg[4 * t + 0] = static_cast<double>(centred_offset<T, P>(r.x, cell_x(cp), T0x, o0));
-      pg[4 * t + 1] = static_cast<double>(centred_offset<T, P>(r.y, cell_y(cp), T0y, o1));
-      pg[4 * t + 2] = static_cast<double>(centred_offset<T, P>(r.z, cell_z(cp), T0z, o2));
+      pg[4 * t + 0] = static_cast<double>(r.x);
+      o0 = cell_x(cp) - T0x;
+      pg[4 * t + 1] = static_cast<double>(r.y);
+      o1 = cell_y(cp) - T0y;
+      pg[4 * t + 2] = static_cast<double>(r.z);
+      o2 = cell_z(cp) - T0z;
       pg[4 * t + 3] = static_cast<double>(r.w);
       po[4 * t + 0] = o0;
       po[4 * t + 1] = o1;
@@ -388,9 +394,12 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
     }
     if (t < nb) {
       int o0, o1, o2;
-      pg[4 * t + 0] = static_cast<double>(centred_offset<T, P>(r.x, cell_x(cp), T0x, o0));
-      pg[4 * t + 1] = static_cast<double>(centred_offset<T, P>(r.y, cell_y(cp), T0y, o1));
-      pg[4 * t + 2] = static_cast<double>(centred_offset<T, P>(r.z, cell_z(cp), T0z, o2));
+      pg[4 * t + 0] = static_cast<double>(r.x);
+      o0 = cell_x(cp) - T0x;
+      pg[4 * t + 1] = static_cast<double>(r.y);
+      o1 = cell_y(cp) - T0y;
+      pg[4 * t + 2] = static_cast<double>(r.z);
+      o2 = cell_z(cp) - T0z;
       pg[4 * t + 3] = static_cast<double>(r.w);
       po[4 * t + 0] = o0;
       po[4 * t + 1] = o1;
@@ -526,9 +535,12 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
     i_next = perm[min(pi + nslots, p1 - 1)];
     int o[3];
     double g[3];
-    g[0] = static_cast<double>(centred_offset<T, P>(r.x, cell_x(cp), T0x, o[0]));
-    g[1] = static_cast<double>(centred_offset<T, P>(r.y, cell_y(cp), T0y, o[1]));
-    g[2] = static_cast<double>(centred_offset<T, P>(r.z, cell_z(cp), T0z, o[2]));
+    g[0] = static_cast<double>(r.x);
+    o[0] = cell_x(cp) - T0x;
+    g[1] = static_cast<double>(r.y);
+    o[1] = cell_y(cp) - T0y;
+    g[2] = static_cast<double>(r.z);
+    o[2] = cell_z(cp) - T0z;
 #pragma unroll
     for (int jj = 0; jj < (P + kLanesPerParticle - 1) / kLanesPerParticle; ++jj) {
       const int j = li + kLanesPerParticle * jj;
