@@ -828,7 +828,7 @@ hipError_t transform_impl(const DevPlan& d, const void* in_override, void* out_o
 // Particle-kernel instance covering (precision, P).
 struct ParticleFns {
   int prec, lo, hi;
-  hipError_t (*prepare)(const PGroup&);
+  hipError_t (*prepare)(PGroup&);
   hipError_t (*spread)(const DevPlan&, const PGroup&, hipStream_t);
   hipError_t (*gather)(const DevPlan&, const PGroup&, const void*, void*, void*, int, bool, double*, hipStream_t);
 };
@@ -860,7 +860,7 @@ hipError_t raise_fft_lds(const DevPlan& d) {
   return e;
 }
 
-hipError_t prepare_kernels(const DevPlan& d) {
+hipError_t prepare_kernels(DevPlan& d) {
   {
     const hipError_t e = d.prec == 0 ? raise_fft_lds<float>(d) : raise_fft_lds<double>(d);
     if (e != hipSuccess) return e;
@@ -890,7 +890,7 @@ hipError_t prepare_kernels(const DevPlan& d) {
       }();
     if (e != hipSuccess) return e;
   }
-  for (const PGroup& g : d.groups) {
+  for (PGroup& g : d.groups) {
     const ParticleFns* f = particle_fns(d.prec, g.P);
     const hipError_t e = f ? f->prepare(g) : hipErrorInvalidValue;
     if (e != hipSuccess) return e;

@@ -113,6 +113,7 @@ struct PGroup {
   int col_tile = 0;  // spreading in registers when the group's tiles all have this edge (4, 6, 8)
   int mfma = 0;      // ... as a matrix product on the matrix cores (k_spread_mfma) rather than by y-columns
   int parts = 1;     // workgroups per tile, each taking an equal slice of the tile's particles
+  int xcd_spread = 0, xcd_gather = 0;  // XCD-aware tile order (set at plan creation)
   size_t lds_spread = 0, lds_gather = 0;  // maxima over the group's systems
 };
 
@@ -208,7 +209,7 @@ inline void stage_end(const DevPlan& d, int stage, hipStream_t st) {
   X(1, 3, 8) X(1, 9, 12) X(1, 13, 16) X(1, 17, 20) X(1, 21, 24)
 
 #define PSWFE_PARTICLE_DECLARE(prec, lo, hi)                                                              \
-  hipError_t particles_prepare_##prec##_##lo(const PGroup& g);                                            \
+  hipError_t particles_prepare_##prec##_##lo(PGroup& g);                                                  \
   hipError_t particles_spread_##prec##_##lo(const DevPlan& d, const PGroup& g, hipStream_t st);           \
   hipError_t particles_gather_##prec##_##lo(const DevPlan& d, const PGroup& g, const void* grid, void* phi, \
                                             void* vec, int vec_mode, bool add_self, double* energy,       \
@@ -216,8 +217,9 @@ inline void stage_end(const DevPlan& d, int stage, hipStream_t st) {
 PSWFE_PARTICLE_INSTANCES(PSWFE_PARTICLE_DECLARE)
 #undef PSWFE_PARTICLE_DECLARE
 
-// One-time kernel attributes (dynamic LDS above 64 KiB); call at plan creation.
-hipError_t prepare_kernels(const DevPlan& d);
+// One-time kernel attributes (dynamic LDS above 64 KiB) and launch choices that depend on
+// occupancy; call at plan creation.
+hipError_t prepare_kernels(DevPlan& d);
 
 // Pipeline pieces; all enqueue on `stream` and return hipSuccess or the launch error.
 // n_total: packed particles (a single system: its n). energy: nsys doubles zeroed here, or NULL.

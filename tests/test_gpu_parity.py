@@ -154,6 +154,25 @@ def test_every_spreading_kernel_matches_oracle(case, prec, kernel, monkeypatch):
     assert rel_l2(F.cpu().numpy(), direct.forces(q, rg)) < (1e-10 if prec == "fp64" else 2e-5) + 100 * fit_tol(eps, prec)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_xcd_tile_order_gives_the_same_results(prec, monkeypatch):
+    """The XCD-aware order of tiles over workgroups (on when a launch's grid is resident at
+    once) only permutes the work: the same potentials and forces as the plain order, to
+    rounding (the grid's atomic sums are added in another order)."""
+    x, q, L = W.uniform_pm1(3000, seed=29)
+    c = pw.choose_params(1e-6, L, m=32)
+    out = {}
+    for order in ("1", "0"):
+        monkeypatch.setenv("PSWFE_XCD_ORDER", order)
+        plan = pw.Plan(c, prec, n_max=len(q), tile=4)
+        phi, F, E = plan.compute(tdev(x, prec), tdev(q, prec))
+        out[order] = (phi.cpu().numpy().astype(np.float64), F.cpu().numpy().astype(np.float64), float(E.cpu()[0]))
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert rel_l2(out["1"][0], out["0"][0]) < tol
+    assert rel_l2(out["1"][1], out["0"][1]) < tol
+    assert abs(out["1"][2] - out["0"][2]) <= tol * abs(out["0"][2])
+
+
 DENSE_CASES = [
     # (name, generator, eps, params kwargs, tile, spreading kernel): many particles per tile, few tiles
     ("dense_m24_tile8_mfma", lambda: W.uniform_pm1(24000, seed=26), 1e-6, dict(m=24), 8, "mfma"),
