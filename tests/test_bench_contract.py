@@ -1,0 +1,69 @@
+"""Host-side pieces of bench.py: the one-GPU guard, the algorithmic work behind the roofline
+figures, and the rule that counter summaries count only for the kernel sources they were taken
+on. No GPU is used."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_spread_and_gather_work_per_launch():
+    # water box: n = 30,000, P = 13, deg = 9
+    n, P, deg = 30000, 13, 9
+    kind, flops = bench.stage_work("spread", n, 64, P, deg, 4)
+    assert kind == "mfma"
+    assert flops == n * (3 * P * 2 * deg + 2 * P * P + 2 * P ** 3) == 163_020_000
+    kind, flops = bench.stage_work("gather", n, 64, P, deg, 4)
+    assert kind == "alu"
+    assert flops == n * (6 * P * 2 * deg + 4 * P ** 3 + 6 * P * P + 8 * P)
+
+
+@pytest.mark.parametrize("elem", [4, 8])
+def test_fft_pass_bytes(elem):
+    m = 64
+    real, half = m ** 3 * elem, m * m * (m // 2 + 1) * 2 * elem
+    assert bench.stage_work("fft_x", 1, m, 13, 9, elem) == ("hbm", real + half)
+    assert bench.stage_work("ifft_x", 1, m, 13, 9, elem) == ("hbm", half + real)
+    for st in ("fft_y", "fft_z_scale", "ifft_y"):
+        assert bench.stage_work(st, 1, m, 13, 9, elem) == ("hbm", 2 * half)
+
+
+def _summary(tmp_path, sha):
+    blob = {"kernel_source_sha256": sha, "bytes_per_launch": {"k_spread_mfma<float, 13, 11, 8>": 41_000_000}}
+    p = tmp_path / "summary.md"
+    p.write_text("# summary\n\n```json\n" + json.dumps(blob) + "\n```\n")
+    return str(p)
+
+
+def test_counter_summaries_apply_only_to_their_kernel_sources(tmp_path, monkeypatch):
+    current = bench.kernel_source_sha256()
+    assert len(current) == 64
+    assert bench._profile_blob(_summary(tmp_path, current)) is not None
+    assert bench._profile_blob(_summary(tmp_path, "0" * 64)) is None
+    assert bench._profile_blob(str(tmp_path / "missing.md")) is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", _summary(tmp_path, current))
+    assert bench.measured_traffic("spread", "float") == 41_000_000
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", _summary(tmp_path, "0" * 64))
+    assert bench.measured_traffic("spread", "float") is None
+
+
+def test_roofline_fractions_are_fractions():
+    stage_ms = {st: 0.05 for st in bench.STAGES}
+    rows = bench.kernel_rooflines(stage_ms, 30000, 64, 13, 9, 4, "float")
+    for st, row in rows.items():
+        frac = row.get("frac_fp64_peak", row.get("frac_hbm_peak"))
+        assert frac is not None and 0.0 < frac < 1.0, (st, row)
