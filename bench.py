@@ -63,16 +63,25 @@ STAGE_KERNEL = {"spread": ("k_spread", "k_spread_cols", "k_spread_mfma"), "gathe
                 "fft_y": ("k_fft_cols",), "fft_z_scale": ("k_fft_cols",), "ifft_y": ("k_fft_cols",),
                 "ifft_x": ("k_fft_x_c2r",), "bin": ("k_bin_count",)}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_water_box_n30000.md")
-# the device code whose counters the traffic file holds; any change voids them
+# the device code whose counters the traffic file holds; any change to the code voids them
 KERNEL_SOURCES = ("kernels.hip", "kernels.hpp", "particles.hip", "device_common.hpp")
+
+
+def code_only(text: str) -> str:
+    """C++ source with comments removed and every run of blank space made one space (string
+    and character literals kept), so that editing a comment leaves the hash unchanged."""
+    import re
+    token = re.compile(r'"(?:\\.|[^"\\])*"|\'(?:\\.|[^\'\\])*\'|//[^\n]*|/\*.*?\*/', re.S)
+    stripped = token.sub(lambda m: " " if m.group(0).startswith("/") else m.group(0), text)
+    return " ".join(stripped.split())
 
 
 def kernel_source_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2602_16591_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2602_16591_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_only(fh.read()).encode())
     return h.hexdigest()
 
 

@@ -122,7 +122,7 @@ int particle_threads(int P, const std::function<size_t(int)>& lds_of, bool large
 }
 
 // Single systems: B = 8 (measured best on gfx950 for 64^3 and 128^3 grids with P = 12-18;
-// spreading then runs by register columns), reduced to give at least 4 tiles per dimension on
+// spreading then runs on the matrix cores), reduced to give at least 4 tiles per dimension on
 // small grids. Batches: B = 8 (measured best on a 256-system ensemble of 16^3-50^3 grids;
 // many small systems fill the chip together). Both are then reduced until the LDS limits
 // hold.
@@ -401,7 +401,8 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   // range covered by one launch of the particle kernels.
   std::vector<int> order(nsys), tile_prefix(nsys + 1, 0);
   for (int s = 0; s < nsys; ++s) order[s] = s;
-  // spreading by columns where the tile edge allows it (PSWFE_SPREAD_COLUMNS=0 turns it off)
+  // spreading in registers (matrix cores or y-columns) where the tile edge allows it
+  // (PSWFE_SPREAD_COLUMNS=0 turns it off: LDS atomics for every edge)
   bool columns_ok = true;
   if (const char* env = std::getenv("PSWFE_SPREAD_COLUMNS")) columns_ok = std::atoi(env) != 0;
   auto cols = [&](int s) { return columns_ok && pswfe::col_tile_ok(d.sys[s].B) ? d.sys[s].B : 0; };

@@ -1,6 +1,7 @@
 // Particle kernels of the PSWF fast Ewald pipeline for one precision and one range of window
-// supports: spreading (Alg. 2 step 1) by LDS atomics or by register columns, interpolation of
-// potentials and gradients with the energy reduction (Alg. 2 step 5, eq. force). The build
+// supports: spreading (Alg. 2 step 1) as a matrix product on the matrix cores, by register
+// columns or by LDS atomics, and interpolation of potentials and gradients with the energy
+// reduction (Alg. 2 step 5, eq. force). The build
 // compiles this file once per (precision, P range), so the many template instances of these
 // kernels compile in parallel; PSWFE_PREC (0 float, 1 double), PSWFE_PLO and PSWFE_PHI select
 // the instance.
