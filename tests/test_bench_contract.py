@@ -67,3 +67,12 @@ def test_roofline_fractions_are_fractions():
     for st, row in rows.items():
         frac = row.get("frac_fp64_peak", row.get("frac_hbm_peak"))
         assert frac is not None and 0.0 < frac < 1.0, (st, row)
+
+
+def test_kernel_hash_ignores_comments_but_not_code():
+    src = 'int f(int a) {  // twice\n  /* returns\n     double */ return 2 * a; }\nconst char* s = "// kept";\n'
+    same = 'int f(int a) { return 2 * a; } // reworded\nconst char* s = "// kept";'
+    other = 'int f(int a) { return 3 * a; }\nconst char* s = "// kept";'
+    assert bench.code_only(src) == bench.code_only(same)
+    assert bench.code_only(src) != bench.code_only(other)
+    assert '"// kept"' in bench.code_only(src)
