@@ -88,14 +88,16 @@ def kernel_source_sha256() -> str:
 LDS_FILE = os.path.join(ROOT, "profiles", "lds_water_box_n30000.md")
 
 
-def _profile_blob(path):
-    """The machine-readable block of a committed counter summary, or None when it is missing or
-    was taken on other kernel sources."""
+def _profile_blob(path, workload: str = "water_box_n30000"):
+    """The machine-readable block of a committed counter summary, or None when it is missing,
+    was taken on other kernel code or on another workload."""
     try:
         with open(path) as f:
             text = f.read()
         blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("workload", "water_box_n30000") != workload:
         return None
     return blob if blob.get("kernel_source_sha256") == kernel_source_sha256() else None
 
@@ -108,11 +110,11 @@ def _stage_kernels(blob_keys, stage: str, prec_ctype: str):
     return hits
 
 
-def measured_traffic(stage: str, prec_ctype: str):
+def measured_traffic(stage: str, prec_ctype: str, workload: str = "water_box_n30000"):
     """HBM bytes per launch of the stage's kernel(s) from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE runs, calibrated against a plain copy), or None when the summary
     is missing or was taken on other kernel sources."""
-    blob = _profile_blob(TRAFFIC_FILE)
+    blob = _profile_blob(TRAFFIC_FILE, workload)
     if blob is None:
         return None
     per = blob.get("bytes_per_launch", {})
@@ -122,10 +124,10 @@ def measured_traffic(stage: str, prec_ctype: str):
     return sum(per[k] for k in hits)
 
 
-def measured_lds(stage: str, prec_ctype: str):
+def measured_lds(stage: str, prec_ctype: str, workload: str = "water_box_n30000"):
     """LDS instructions and LDS bank-conflict cycles per launch of the stage's kernel(s) from the
     committed counter summary, or None."""
-    blob = _profile_blob(LDS_FILE)
+    blob = _profile_blob(LDS_FILE, workload)
     if blob is None:
         return None
     per = blob.get("per_launch", {})
@@ -135,7 +137,8 @@ def measured_lds(stage: str, prec_ctype: str):
     return {c: sum(per[k][c] for k in hits) for c in ("lds_instr", "lds_bank_conflict_cycles", "valu_instr")}
 
 
-def kernel_rooflines(stage_ms: dict, n: int, m: int, P: int, deg: int, elem: int, prec_ctype: str):
+def kernel_rooflines(stage_ms: dict, n: int, m: int, P: int, deg: int, elem: int, prec_ctype: str,
+                     workload: str = "water_box_n30000"):
     """Per stage: event-timed duration, the algorithmic work and its roofline fraction, the HBM
     traffic the counters measured (GB/s against 8 TB/s) and the LDS bank-conflict share of the
     compute units' cycles (2.4 GHz x 256 CUs)."""
@@ -150,10 +153,10 @@ def kernel_rooflines(stage_ms: dict, n: int, m: int, P: int, deg: int, elem: int
         else:
             row.update({"bound": "hbm", "algorithmic_bytes": work, "gbs": work / us * 1e-3,
                         "frac_hbm_peak": work / us * 1e-3 / PEAK_HBM_GBS})
-        t = measured_traffic(st, prec_ctype)
+        t = measured_traffic(st, prec_ctype, workload)
         if t is not None:
             row.update({"measured_bytes": t, "measured_gbs": t / us * 1e-3, "measured_frac_hbm_peak": t / us * 1e-3 / PEAK_HBM_GBS})
-        lds = measured_lds(st, prec_ctype)
+        lds = measured_lds(st, prec_ctype, workload)
         if lds is not None:
             row.update({"lds_instr": lds["lds_instr"],
                         "lds_conflict_share": lds["lds_bank_conflict_cycles"] / (us * 2400.0 * 256)})
@@ -161,20 +164,26 @@ def kernel_rooflines(stage_ms: dict, n: int, m: int, P: int, deg: int, elem: int
     return out
 
 
-def cpu_baseline(x, q, L, eps, m):
-    """The float64 oracle of the same computation (Alg. 2 in NumPy, oracle/fast.py) on the full
-    system, single-threaded, timed on this host."""
+def cpu_baseline(x, q, L, eps, m, tol_mode="abs", sample=None, label="full water box"):
+    """The float64 oracle of the same computation (Alg. 2 in NumPy, oracle/fast.py), single-
+    threaded, timed on this host: on the full system, or on its first `sample` particles with
+    the full system's parameters (grid and window), when the whole would take minutes."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import fast, params
-    p = params.choose(eps, L, m=m, q_l2=float(np.linalg.norm(q)), tol_mode="abs")
+    if tol_mode == "abs":
+        p = params.choose(eps, L, m=m, q_l2=float(np.linalg.norm(q)), tol_mode="abs")
+    else:
+        p = params.choose(eps, L, m=m)
+    xs, qs = (x, q) if sample is None else (x[:sample], q[:sample])
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        fast.fast_longrange(x, q, p, grad=True)
+        fast.fast_longrange(xs, qs, p, grad=True)
         dt = time.perf_counter() - t0
-    return {"value": len(q) / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": f"full water box (n={len(q)}), one evaluation of oracle/fast.py (Alg. 2, float64 "
-                      f"NumPy, phi and gradients) taking {dt:.2f} s on 1 thread"}
+    what = f"{label} (n={len(qs)})" if sample is None else f"first {len(qs)} of the n={len(q)} {label} particles, same m and P"
+    return {"value": len(qs) / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": f"{what}, one evaluation of oracle/fast.py (Alg. 2, float64 NumPy, phi and gradients) "
+                      f"taking {dt:.2f} s on 1 thread"}
 
 
 def bench_ensemble(steps: int, warmup: int):
@@ -336,6 +345,9 @@ def bench_comparison(steps: int, warmup: int, n: int = 100_000):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=("water_box_n30000", "uniform_n1e6"), default="water_box_n30000",
+                    help="water box (default, the headline) or n = 1e6 uniform (float32 at eps 1e-6 on 128^3, "
+                         "float64 at eps 1e-10 with the same r_c)")
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -357,10 +369,18 @@ def main():
     import workloads as W
 
     dev = torch.device("cuda:0")
-    x, q, L = W.config("water_n30000")
+    water = args.workload == "water_box_n30000"
+    if water:
+        x, q, L = W.config("water_n30000")
+        eps, m = 1e-6, 64
+        params = pw.choose_params(eps, L, m=m, q_l2=float(np.linalg.norm(q)), tol_mode="abs")
+        params_of = {"fp32": params, "fp64": params}
+    else:
+        x, q, L = W.config("uniform_n1e6")
+        eps, m = 1e-6, 128
+        params = pw.choose_params(eps, L, m=m)
+        params_of = {"fp32": params, "fp64": pw.choose_params(1e-10, L, rc=params.rc)}
     n = len(q)
-    eps, m = 1e-6, 64
-    params = pw.choose_params(eps, L, m=m, q_l2=float(np.linalg.norm(q)), tol_mode="abs")
     # both precisions see the same float32-representable inputs, so the float32/float64
     # comparison below isolates arithmetic error from input quantisation
     x = x.astype(np.float32).astype(np.float64)
@@ -368,7 +388,7 @@ def main():
     P = params.P
     results = {}
     for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
-        plan = pw.Plan(params, prec, n_max=n)
+        plan = pw.Plan(params_of[prec], prec, n_max=n)
         X = torch.as_tensor(x, dtype=dt, device=dev).contiguous()
         Q = torch.as_tensor(q, dtype=dt, device=dev).contiguous()
         phi = torch.empty(n, dtype=dt, device=dev)
@@ -402,7 +422,10 @@ def main():
         plan.timing_enable(None)
         results[prec] = dict(elapsed=elapsed, dom=dom, dom_ms=dom_ms_total / max(dom_calls, 1), stage_ms=stage_ms,
                              phi=phi.double().cpu().numpy(), F=F.double().cpu().numpy(), E=float(E.cpu()[0]),
-                             deg=pw.host_tables(params, prec)["deg"], elem=4 if prec == "fp32" else 8)
+                             deg=pw.host_tables(params_of[prec], prec)["deg"], elem=4 if prec == "fp32" else 8)
+        if not water:
+            plan.close()
+            continue
         # the full Ewald sum (real-space residual added), same inputs, outside the headline
         def step_total():
             plan.compute(X, Q, phi=phi, force=F, energy=E, total=True)
@@ -440,36 +463,48 @@ def main():
         achieved = work / secs / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-    roof["traffic"] = measured_traffic(r["dom"], "float")
+    roof["traffic"] = measured_traffic(r["dom"], "float", args.workload)
     roof.update({"kernel": r["dom"], "avg_launch_us": r["dom_ms"] * 1e3, "work_per_launch": work})
     r64 = results["fp64"]
-    phi_diff = float(np.linalg.norm(r["phi"] - r64["phi"]) / np.linalg.norm(r64["phi"]))
-    phi_abs = float(np.sqrt(np.mean((r["phi"] - r64["phi"]) ** 2)))
-    F_diff = float(np.linalg.norm(r["F"] - r64["F"]) / np.linalg.norm(r64["F"]))
+    p64 = params_of["fp64"]
+    if water:
+        config = {"workload": "water_box_n30000", "n": n, "L_nm": L, "eps": eps, "tol_mode": "abs", "m": m, "P": P,
+                  "rc_nm": params.rc, "parallelism": "single GPU"}
+    else:
+        config = {"workload": "uniform_n1e6", "n": n, "L": L, "eps": eps, "tol_mode": "rel", "m": m, "P": P,
+                  "rc": params.rc, "fp64": {"eps": 1e-10, "m": p64.m, "P": p64.P}, "parallelism": "single GPU"}
     out = {
         "metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["elapsed"] / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "water_box_n30000", "n": n, "L_nm": L, "eps": eps, "tol_mode": "abs", "m": m, "P": P,
-                   "rc_nm": params.rc, "parallelism": "single GPU"},
+        "config": config,
         "roofline": roof,
         "stage_us_fp32": {k: v * 1e3 for k, v in r["stage_ms"].items()},
         "fp64": {"value": n * args.steps / r64["elapsed"], "unit": "particles/s",
                  "ms_per_step": r64["elapsed"] / args.steps * 1e3,
                  "stage_us": {k: v * 1e3 for k, v in r64["stage_ms"].items()}},
-        "kernels_fp32": kernel_rooflines(r["stage_ms"], n, m, P, r["deg"], r["elem"], "float"),
-        "kernels_fp64": kernel_rooflines(r64["stage_ms"], n, m, P, r64["deg"], r64["elem"], "double"),
-        "fp32_vs_fp64": {"phi_rel_l2": phi_diff, "phi_abs_rms": phi_abs, "force_rel_l2": F_diff,
-                         "energy_rel": abs(r["E"] - r64["E"]) / abs(r64["E"])},
-        "total_ewald": {"note": "phi_far + phi_local + phi_self (real-space residual on the GPU), same workload",
-                        "fp32": results["fp32_total"], "fp64": results["fp64_total"]},
+        "kernels_fp32": kernel_rooflines(r["stage_ms"], n, m, P, r["deg"], r["elem"], "float", args.workload),
+        "kernels_fp64": kernel_rooflines(r64["stage_ms"], n, p64.m, p64.P, r64["deg"], r64["elem"], "double",
+                                         args.workload),
     }
+    if water:
+        phi_diff = float(np.linalg.norm(r["phi"] - r64["phi"]) / np.linalg.norm(r64["phi"]))
+        phi_abs = float(np.sqrt(np.mean((r["phi"] - r64["phi"]) ** 2)))
+        F_diff = float(np.linalg.norm(r["F"] - r64["F"]) / np.linalg.norm(r64["F"]))
+        out["fp32_vs_fp64"] = {"phi_rel_l2": phi_diff, "phi_abs_rms": phi_abs, "force_rel_l2": F_diff,
+                               "energy_rel": abs(r["E"] - r64["E"]) / abs(r64["E"])}
+        out["total_ewald"] = {"note": "phi_far + phi_local + phi_self (real-space residual on the GPU), same workload",
+                              "fp32": results["fp32_total"], "fp64": results["fp64_total"]}
     if not args.no_batched:
         out["batched"] = bench_ensemble(max(5, min(args.steps, 50)), max(2, min(args.warmup, 5)))
     if not args.no_comparison:
         out["comparison"] = bench_comparison(max(5, min(args.steps, 30)), max(2, min(args.warmup, 5)))
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(x, q, L, eps, m)
+        if water:
+            out["cpu_baseline"] = cpu_baseline(x, q, L, eps, m)
+        else:
+            out["cpu_baseline"] = cpu_baseline(x, q, L, eps, m, tol_mode="rel", sample=200_000,
+                                               label="uniform")
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -13,12 +13,23 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
-def test_more_than_one_gpu_is_refused_with_a_message():
-    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+@pytest.mark.parametrize("extra", [[], ["--workload", "uniform_n1e6"]])
+def test_more_than_one_gpu_is_refused_with_a_message(extra):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2", *extra], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_water_box_counter_summaries_are_not_used_for_other_workloads(tmp_path, monkeypatch):
+    blob = {"kernel_source_sha256": bench.kernel_source_sha256(), "workload": "water_box_n30000",
+            "bytes_per_launch": {"k_spread_mfma<float, 13, 11, 8>": 41_000_000}}
+    p = tmp_path / "summary.md"
+    p.write_text("```json\n" + json.dumps(blob) + "\n```\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(p))
+    assert bench.measured_traffic("spread", "float") == 41_000_000
+    assert bench.measured_traffic("spread", "float", "uniform_n1e6") is None
 
 
 def test_spread_and_gather_work_per_launch():
