@@ -168,13 +168,14 @@ __global__ void k_cell_scatter(int64_t n, int nsys, const SysDesc* __restrict__ 
 
 // One workgroup per cell: the particles of the 27 neighbour cells (of the whole system when
 // nc < 3) are staged in LDS, kLocalChunk at a time, and each target particle of the cell is
-// handled by kLocalLanes lanes that split the sources and reduce with shuffles. The residual's
-// polynomial coefficients are held in registers, and no division or memory access other than
-// LDS reads sits in the pair loop.
+// handled by L lanes that split the sources and reduce with shuffles, L = NT / (the cell's
+// target count rounded up to a power of 2), between kLocalLanes and 64: the lanes a small cell
+// would leave idle shorten its targets' source loops instead. The residual's polynomial
+// coefficients are held in registers, and no division or memory access other than LDS reads
+// sits in the pair loop.
 // Workgroups of NT = 512 threads (128 and 256 on request): the kernel is latency-bound, and
-// measured on MI355X more waves per cell beat the lanes they leave idle (a water-box cell of
-// ~17 particles fills 17 of 64 target slots): 112 / 84 / 80 us for NT = 128 / 256 / 512, and
-// 3.4 / 2.6 / 2.4 ms at n = 1e6.
+// measured on MI355X more waves per cell pay (with 8 lanes per target: 112 / 84 / 80 us for
+// NT = 128 / 256 / 512 on the water box, and 3.4 / 2.6 / 2.4 ms at n = 1e6).
 constexpr int kLocalLanes = 8;
 constexpr int kLocalChunk = 1024;
 // DEG: the residual polynomial G, zero-padded to this degree (an instance per 12, 16, 20, 24)
@@ -228,10 +229,13 @@ __global__ __launch_bounds__(NT) void k_local(int nsys, const SysDesc* __restric
   }
   __syncthreads();
   const int ns = nb_off[27];
-  const int grp = tid / kLocalLanes, lane = tid % kLocalLanes;
-  constexpr int kTargetsPerPass = NT / kLocalLanes;
+  int lanes = NT;  // lanes per target (a power of 2, 8..64), the same for the whole workgroup
+  for (int pw = 1; pw < t1 - t0 && lanes > kLocalLanes; pw <<= 1) lanes >>= 1;
+  lanes = min(lanes, 64);
+  const int grp = tid / lanes, lane = tid % lanes;
+  const int targets_per_pass = NT / lanes;
   double esum = 0.0;
-  for (int tb = t0; tb < t1; tb += kTargetsPerPass) {
+  for (int tb = t0; tb < t1; tb += targets_per_pass) {
     const int ti = tb + grp;
     const bool tvalid = ti < t1;
     const double4 xi = lsorted[tvalid ? ti : t0];
@@ -255,7 +259,7 @@ __global__ __launch_bounds__(NT) void k_local(int nsys, const SysDesc* __restric
       }
       __syncthreads();
       if (tvalid) {
-        for (int k = lane; k < nchunk; k += kLocalLanes) {
+        for (int k = lane; k < nchunk; k += lanes) {
           if (src_id[k] == ti) continue;
           const double4 xj = src[k];
           double dx = xi.x - xj.x, dy = xi.y - xj.y, dz = xi.z - xj.z;
@@ -282,12 +286,11 @@ __global__ __launch_bounds__(NT) void k_local(int nsys, const SysDesc* __restric
         }
       }
     }
-#pragma unroll
-    for (int off = kLocalLanes / 2; off > 0; off >>= 1) {
-      ph += __shfl_xor(ph, off, kLocalLanes);
-      g0 += __shfl_xor(g0, off, kLocalLanes);
-      g1 += __shfl_xor(g1, off, kLocalLanes);
-      g2 += __shfl_xor(g2, off, kLocalLanes);
+    for (int off = lanes / 2; off > 0; off >>= 1) {  // within the aligned group of `lanes` lanes
+      ph += __shfl_xor(ph, off);
+      g0 += __shfl_xor(g0, off);
+      g1 += __shfl_xor(g1, off);
+      g2 += __shfl_xor(g2, off);
     }
     if (tvalid && lane == 0) {
       const int idx = lperm[ti];
