@@ -206,10 +206,14 @@ pswfe_status pswfe_compute_grad(pswfe_plan* plan, int64_t n, const void* pos, co
  *   phi_local,i = sum'_j rho_j R(|x_i - x_j|),  R(r) = (1 - Phi(r)) / r for r < r_c, 0 beyond
  * (Sec. 3.1.1, eq. R; minimum image, self pair excluded) is added to phi_far + phi_self, its
  * force -rho_i grad phi_local,i to the force and 1/2 sum rho_i phi_local,i to the energy.
- * R is evaluated from a float64 polynomial fit of Phi(r)/r in r^2 (relative error below 1e-15);
- * pairs are found in cells of edge L / floor(L / r_c) >= r_c (every pair of the system when
- * L < 3 r_c). PSWFE_TOTAL needs r_c < L/2 and the PSWF split for every system (else
- * PSWFE_E_ARG); unknown flag bits -> PSWFE_E_ARG. */
+ * R is evaluated from a float64 polynomial fit of Phi(r)/r in r^2 (relative error below 1e-15
+ * in float64 plans, 1e-10 in float32 plans); pairs are found in cells of edge
+ * L / floor(L / r_c) >= r_c (every pair of the system when L < 3 r_c). The residual runs on a
+ * stream the plan owns, started by an event recorded on `stream` and joined back to `stream`
+ * before interpolation, so the call stays ordered on `stream` (and can be captured into a HIP
+ * graph from it); as for every call, calls on one plan must not run concurrently.
+ * PSWFE_TOTAL needs r_c < L/2 and the PSWF split for every system (else PSWFE_E_ARG); unknown
+ * flag bits -> PSWFE_E_ARG. */
 pswfe_status pswfe_compute_ex(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi, void* vec,
                               double* energy, int32_t flags, void* stream);
 

@@ -26,6 +26,14 @@ struct pswfe_plan {
   pswfe::StageTimer timer;
   int device = 0;
   std::vector<void*> allocs;      // device allocations owned by the plan
+  // The real-space residual of PSWFE_TOTAL calls runs on a stream of its own, forked from and
+  // joined back to the caller's stream with events, while binning, spreading and the FFT run on
+  // the caller's; interpolation then adds its float64 results (phi_d, vec_d).
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  double* phi_d = nullptr;        // n_max
+  double* vec_d = nullptr;        // n_max x 3
+  bool overlap = true;            // PSWFE_LOCAL_OVERLAP=0: residual after the long-range part, same stream
 };
 
 namespace {
@@ -161,6 +169,9 @@ void free_timer(pswfe::StageTimer& t) {
 }
 
 void free_plan(pswfe_plan* plan) {
+  if (plan->side) (void)hipStreamDestroy(plan->side);
+  if (plan->ev_fork) (void)hipEventDestroy(plan->ev_fork);
+  if (plan->ev_join) (void)hipEventDestroy(plan->ev_join);
   for (void* b : plan->allocs)
     if (b) (void)hipFree(b);
   plan->allocs.clear();
@@ -603,9 +614,22 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
             hipMemcpy(d.part_prefix, part_prefix.data(), sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice) ==
                 hipSuccess &&
             pswfe::prepare_kernels(d) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+  if (ok && plan->local_ok) {
+    if (const char* env = std::getenv("PSWFE_LOCAL_OVERLAP")) plan->overlap = std::atoi(env) != 0;
+    if (plan->overlap) {
+      // default priority (a stream of another priority is never used here)
+      ok = hipStreamCreateWithFlags(&plan->side, hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&plan->ev_fork, hipEventDisableTiming) == hipSuccess &&
+           hipEventCreateWithFlags(&plan->ev_join, hipEventDisableTiming) == hipSuccess;
+      plan->phi_d = static_cast<double*>(alloc(sizeof(double) * nm));
+      plan->vec_d = static_cast<double*>(alloc(sizeof(double) * 3 * nm));
+      ok = ok && st == PSWFE_OK;
+    }
+  }
   if (!ok) {
+    const pswfe_status fail = st != PSWFE_OK ? st : PSWFE_E_HIP;
     free_plan(plan);
-    return PSWFE_E_HIP;
+    return fail;
   }
   *out = plan;
   return PSWFE_OK;
@@ -833,15 +857,31 @@ pswfe_status pswfe_timing_read(pswfe_plan* plan, double* total_ms, int64_t* call
 
 namespace {
 // Bin, spread, transform and gather over every system of the plan; n particles in all; with
-// `total`, the real-space residual is added.
-hipError_t run_pipeline(const pswfe::DevPlan& d, int64_t n, const void* pos, const void* q, void* phi, void* vec,
+// `total`, the real-space residual is added: computed on the plan's side stream while the
+// long-range part runs, and added by the interpolation (or, without the side stream, computed
+// after it and accumulated).
+hipError_t run_pipeline(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi, void* vec,
                         int vec_mode, double* energy, bool total, hipStream_t s) {
+  const pswfe::DevPlan& d = plan->d;
+  const bool fork = total && n > 0 && plan->side;
   pswfe::stage_begin(d, pswfe::kStageAll, s);
-  hipError_t e = pswfe::launch_bin(d, n, pos, q, energy, s);
+  hipError_t e = hipSuccess;
+  if (fork) {
+    e = hipEventRecord(plan->ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(plan->side, plan->ev_fork, 0);
+    if (e == hipSuccess)
+      e = pswfe::launch_local(d, n, pos, q, nullptr, nullptr, vec_mode, nullptr, false, plan->side, plan->phi_d,
+                              vec ? plan->vec_d : nullptr);
+    if (e == hipSuccess) e = hipEventRecord(plan->ev_join, plan->side);
+  }
+  if (e == hipSuccess) e = pswfe::launch_bin(d, n, pos, q, energy, s);
   if (e == hipSuccess) e = pswfe::launch_spread(d, s);
   if (e == hipSuccess) e = pswfe::launch_transform(d, nullptr, nullptr, s);
-  if (e == hipSuccess && n > 0) e = pswfe::launch_gather(d, nullptr, phi, vec, vec_mode, true, energy, s);
-  if (e == hipSuccess && total) e = pswfe::launch_local(d, n, pos, q, phi, vec, vec_mode, energy, true, s);
+  if (e == hipSuccess && fork) e = hipStreamWaitEvent(s, plan->ev_join, 0);
+  if (e == hipSuccess && n > 0)
+    e = pswfe::launch_gather(d, nullptr, phi, vec, vec_mode, true, energy, s, fork ? plan->phi_d : nullptr,
+                             fork && vec ? plan->vec_d : nullptr);
+  if (e == hipSuccess && total && !fork) e = pswfe::launch_local(d, n, pos, q, phi, vec, vec_mode, energy, true, s);
   pswfe::stage_end(d, pswfe::kStageAll, s);
   return e;
 }
@@ -854,7 +894,7 @@ pswfe_status compute_impl(pswfe_plan* plan, int64_t n, const void* pos, const vo
   if ((flags & PSWFE_TOTAL) && !plan->local_ok) return PSWFE_E_ARG;
   if (n > plan->d.n_max) return PSWFE_E_CAPACITY;
   if (n > 0 && (!pos || !q)) return PSWFE_E_ARG;
-  return from_hip(run_pipeline(plan->d, n, pos, q, phi, vec, (flags & PSWFE_VEC_GRAD) ? 1 : 0, energy,
+  return from_hip(run_pipeline(plan, n, pos, q, phi, vec, (flags & PSWFE_VEC_GRAD) ? 1 : 0, energy,
                                (flags & PSWFE_TOTAL) != 0, static_cast<hipStream_t>(stream)));
 }
 
@@ -864,7 +904,7 @@ pswfe_status batch_impl(pswfe_plan* plan, const void* pos, const void* q, void* 
   if ((flags & PSWFE_TOTAL) && !plan->local_ok) return PSWFE_E_ARG;
   const int64_t n = plan->d.n_max;
   if (n > 0 && (!pos || !q)) return PSWFE_E_ARG;
-  return from_hip(run_pipeline(plan->d, n, pos, q, phi, vec, (flags & PSWFE_VEC_GRAD) ? 1 : 0, energy,
+  return from_hip(run_pipeline(plan, n, pos, q, phi, vec, (flags & PSWFE_VEC_GRAD) ? 1 : 0, energy,
                                (flags & PSWFE_TOTAL) != 0, static_cast<hipStream_t>(stream)));
 }
 }  // namespace

@@ -186,7 +186,8 @@ __global__ __launch_bounds__(NT) void k_local(int nsys, const SysDesc* __restric
                                                          const int* __restrict__ lperm,
                                                          const int* __restrict__ cell_start, T* __restrict__ phi,
                                                          T* __restrict__ vec, int vec_mode, int accumulate,
-                                                         double* __restrict__ energy) {
+                                                         double* __restrict__ energy, double* __restrict__ phi_d,
+                                                         double* __restrict__ vec_d) {
   __shared__ double4 src[kLocalChunk];
   __shared__ int src_id[kLocalChunk];
   __shared__ int nb_begin[27], nb_off[28];
@@ -295,13 +296,21 @@ __global__ __launch_bounds__(NT) void k_local(int nsys, const SysDesc* __restric
     if (tvalid && lane == 0) {
       const int idx = lperm[ti];
       const double qi = xi.w;
-      if (phi) phi[idx] = static_cast<T>(accumulate ? static_cast<double>(phi[idx]) + ph : ph);
-      if (vec) {
-        const double sc = vec_mode == 0 ? -qi : 1.0;
-        const double v[3] = {sc * g0, sc * g1, sc * g2};
+      const double sc = vec_mode == 0 ? -qi : 1.0;
+      const double v[3] = {sc * g0, sc * g1, sc * g2};
+      if (phi_d) {  // float64 terms for the interpolation to add
+        phi_d[idx] = ph;
+        if (vec_d) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-          vec[3 * idx + d] = static_cast<T>(accumulate ? static_cast<double>(vec[3 * idx + d]) + v[d] : v[d]);
+          for (int d = 0; d < 3; ++d) vec_d[3 * idx + d] = v[d];
+        }
+      } else {
+        if (phi) phi[idx] = static_cast<T>(accumulate ? static_cast<double>(phi[idx]) + ph : ph);
+        if (vec) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            vec[3 * idx + d] = static_cast<T>(accumulate ? static_cast<double>(vec[3 * idx + d]) + v[d] : v[d]);
+        }
       }
       esum += 0.5 * qi * ph;
     }
@@ -833,7 +842,8 @@ struct ParticleFns {
   int prec, lo, hi;
   hipError_t (*prepare)(PGroup&);
   hipError_t (*spread)(const DevPlan&, const PGroup&, hipStream_t);
-  hipError_t (*gather)(const DevPlan&, const PGroup&, const void*, void*, void*, int, bool, double*, hipStream_t);
+  hipError_t (*gather)(const DevPlan&, const PGroup&, const void*, void*, void*, int, bool, double*, const double*,
+                       const double*, hipStream_t);
 };
 
 #define PSWFE_PARTICLE_ENTRY(prec, lo, hi) \
@@ -932,7 +942,7 @@ hipError_t launch_drain(const DevPlan& d, void* out, hipStream_t st) {
 
 template <class T>
 hipError_t local_impl(const DevPlan& d, int64_t n, const void* pos, const void* q, void* phi, void* vec, int vec_mode,
-                      double* energy, bool accumulate, hipStream_t st) {
+                      double* energy, bool accumulate, hipStream_t st, double* phi_d, double* vec_d) {
   stage_begin(d, kStageLocal, st);
   const int64_t nthreads = std::max<int64_t>(n, (energy && !accumulate) ? d.nsys : 0);
   if (nthreads > 0)
@@ -947,7 +957,7 @@ hipError_t local_impl(const DevPlan& d, int64_t n, const void* pos, const void* 
     const auto launch = [&](auto kern) {
       hipLaunchKernelGGL(kern, dim3(d.total_cells), dim3(d.local_threads), 0, st, d.nsys, d.sys_dev, d.cell_prefix,
                          reinterpret_cast<const double4*>(d.lsorted), d.lperm, d.cell_start, static_cast<T*>(phi),
-                         static_cast<T*>(vec), vec_mode, accumulate ? 1 : 0, energy);
+                         static_cast<T*>(vec), vec_mode, accumulate ? 1 : 0, energy, phi_d, vec_d);
     };
     const auto by_threads = [&]<int DEG>() {
       if (d.local_threads == 128)
@@ -971,9 +981,9 @@ hipError_t local_impl(const DevPlan& d, int64_t n, const void* pos, const void* 
 }
 
 hipError_t launch_local(const DevPlan& d, int64_t n_total, const void* pos, const void* q, void* phi, void* vec,
-                        int vec_mode, double* energy, bool accumulate, hipStream_t st) {
-  return d.prec == 0 ? local_impl<float>(d, n_total, pos, q, phi, vec, vec_mode, energy, accumulate, st)
-                     : local_impl<double>(d, n_total, pos, q, phi, vec, vec_mode, energy, accumulate, st);
+                        int vec_mode, double* energy, bool accumulate, hipStream_t st, double* phi_d, double* vec_d) {
+  return d.prec == 0 ? local_impl<float>(d, n_total, pos, q, phi, vec, vec_mode, energy, accumulate, st, phi_d, vec_d)
+                     : local_impl<double>(d, n_total, pos, q, phi, vec, vec_mode, energy, accumulate, st, phi_d, vec_d);
 }
 
 hipError_t launch_transform(const DevPlan& d, const void* in_override, void* out_override, hipStream_t st) {
@@ -982,12 +992,13 @@ hipError_t launch_transform(const DevPlan& d, const void* in_override, void* out
 }
 
 hipError_t launch_gather(const DevPlan& d, const void* grid_override, void* phi, void* vec, int vec_mode,
-                         bool add_self, double* energy, hipStream_t st) {
+                         bool add_self, double* energy, hipStream_t st, const double* phi_add, const double* vec_add) {
   hipError_t e = hipSuccess;
   stage_begin(d, kStageGather, st);
   for (const PGroup& g : d.groups) {
     const ParticleFns* f = particle_fns(d.prec, g.P);
-    e = f ? f->gather(d, g, grid_override, phi, vec, vec_mode, add_self, energy, st) : hipErrorInvalidValue;
+    e = f ? f->gather(d, g, grid_override, phi, vec, vec_mode, add_self, energy, phi_add, vec_add, st)
+          : hipErrorInvalidValue;
     if (e != hipSuccess) break;
   }
   stage_end(d, kStageGather, st);

@@ -213,7 +213,7 @@ inline void stage_end(const DevPlan& d, int stage, hipStream_t st) {
   hipError_t particles_spread_##prec##_##lo(const DevPlan& d, const PGroup& g, hipStream_t st);           \
   hipError_t particles_gather_##prec##_##lo(const DevPlan& d, const PGroup& g, const void* grid, void* phi, \
                                             void* vec, int vec_mode, bool add_self, double* energy,       \
-                                            hipStream_t st);
+                                            const double* phi_add, const double* vec_add, hipStream_t st);
 PSWFE_PARTICLE_INSTANCES(PSWFE_PARTICLE_DECLARE)
 #undef PSWFE_PARTICLE_DECLARE
 
@@ -235,12 +235,17 @@ hipError_t launch_drain(const DevPlan& d, void* out, hipStream_t stream);
 hipError_t launch_transform(const DevPlan& d, const void* in_override, void* out_override, hipStream_t stream);
 // vec_mode: 0 writes force -q grad(phi), 1 writes grad(phi). add_self adds -self_coef q to phi.
 // grid_override (single system only) replaces grid_b. energy: nsys doubles, accumulated.
+// phi_add / vec_add (nullable, float64, n and n x 3 in input order) are added to each particle's
+// potential and vec term before they are rounded and before the energy sum.
 hipError_t launch_gather(const DevPlan& d, const void* grid_override, void* phi, void* vec, int vec_mode,
-                         bool add_self, double* energy, hipStream_t stream);
+                         bool add_self, double* energy, hipStream_t stream, const double* phi_add = nullptr,
+                         const double* vec_add = nullptr);
 // Real-space residual of every system: cell binning, then phi_local, its gradient term and
 // energy, added to phi / vec / energy when accumulate is set, else written (energy zeroed
-// first). vec_mode as in launch_gather.
+// first). vec_mode as in launch_gather. With phi_d set, phi_local and the vec term (if vec_d)
+// are written to these float64 arrays instead, and phi, vec, energy are not touched.
 hipError_t launch_local(const DevPlan& d, int64_t n_total, const void* pos, const void* q, void* phi, void* vec,
-                        int vec_mode, double* energy, bool accumulate, hipStream_t stream);
+                        int vec_mode, double* energy, bool accumulate, hipStream_t stream, double* phi_d = nullptr,
+                        double* vec_d = nullptr);
 
 }  // namespace pswfe

@@ -501,7 +501,8 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
                                                 const int* __restrict__ tile_sys, int tile_offset, int parts, int xcd,
                                                 const T* __restrict__ grid_override, T* __restrict__ phi,
                                                 T* __restrict__ vec, int vec_mode, int add_self,
-                                                double* __restrict__ energy) {
+                                                double* __restrict__ energy, const double* __restrict__ phi_add,
+                                                const double* __restrict__ vec_add) {
   constexpr int REC = 6 * P;  // values x, y, z then derivatives x, y, z (d/dg)
   constexpr int CS = coef_stride(D);
   extern __shared__ unsigned char smem_raw[];
@@ -630,12 +631,19 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
       const double qd = static_cast<double>(r.w);
       double phd = ph;
       if (add_self) phd -= self_coef * qd;
+      if (phi_add) phd += phi_add[idx];  // the real-space residual, computed alongside (float64)
       if (phi) phi[idx] = static_cast<T>(phd);
       if (vec) {
         const double sc = vec_mode == 0 ? -qd : 1.0;  // d/dx_d = (1 / h_d) d/dg_d
-        vec[3 * idx + 0] = static_cast<T>(sc * inv_hx * gx);
-        vec[3 * idx + 1] = static_cast<T>(sc * inv_hy * gy);
-        vec[3 * idx + 2] = static_cast<T>(sc * inv_hz * gz);
+        double v0 = sc * inv_hx * gx, v1 = sc * inv_hy * gy, v2 = sc * inv_hz * gz;
+        if (vec_add) {
+          v0 += vec_add[3 * idx + 0];
+          v1 += vec_add[3 * idx + 1];
+          v2 += vec_add[3 * idx + 2];
+        }
+        vec[3 * idx + 0] = static_cast<T>(v0);
+        vec[3 * idx + 1] = static_cast<T>(v1);
+        vec[3 * idx + 2] = static_cast<T>(v2);
       }
       esum += qd * phd;
     }
@@ -683,12 +691,13 @@ hipError_t spread_impl(const DevPlan& d, const PGroup& g, hipStream_t st) {
 
 template <class T, int P, int D>
 hipError_t gather_impl(const DevPlan& d, const PGroup& g, const void* grid, void* phi, void* vec, int vec_mode,
-                       bool add_self, double* energy, hipStream_t st) {
+                       bool add_self, double* energy, const double* phi_add, const double* vec_add,
+                       hipStream_t st) {
   hipLaunchKernelGGL((k_gather<T, P, D>), dim3((g.tile_end - g.tile_begin) * g.parts), dim3(g.gather_threads),
                      g.lds_gather, st, static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.perm,
                      d.tile_start, d.sub_log2, d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin, g.parts,
                      g.xcd_gather, static_cast<const T*>(grid),
-                     static_cast<T*>(phi), static_cast<T*>(vec), vec_mode, add_self ? 1 : 0, energy);
+                     static_cast<T*>(phi), static_cast<T*>(vec), vec_mode, add_self ? 1 : 0, energy, phi_add, vec_add);
   return hipGetLastError();
 }
 
@@ -765,9 +774,10 @@ hipError_t PSWFE_PARTICLE_FN(spread)(const DevPlan& d, const PGroup& g, hipStrea
 }
 
 hipError_t PSWFE_PARTICLE_FN(gather)(const DevPlan& d, const PGroup& g, const void* grid, void* phi, void* vec,
-                                     int vec_mode, bool add_self, double* energy, hipStream_t st) {
+                                     int vec_mode, bool add_self, double* energy, const double* phi_add,
+                                     const double* vec_add, hipStream_t st) {
   return with_group<PSWFE_PLO>(g, [&]<int P, int D>() {
-    return gather_impl<Real, P, D>(d, g, grid, phi, vec, vec_mode, add_self, energy, st);
+    return gather_impl<Real, P, D>(d, g, grid, phi, vec, vec_mode, add_self, energy, phi_add, vec_add, st);
   });
 }
 

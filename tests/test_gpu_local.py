@@ -204,3 +204,63 @@ def test_water_box_total_potential(prec):
     ref, gref = direct.total_potential(x, q, L, target_idx=idx, rc_o=0.3 * L, cs_o=30.0)
     err = phi.double().cpu().numpy()[idx] - ref
     assert np.sqrt(np.mean(err ** 2)) < 1.5 * eps
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_overlapped_residual_matches_sequential(prec, monkeypatch):
+    """The residual computed on the plan's side stream, alongside the long-range part, and added
+    by the interpolation in float64 gives the results of computing it afterwards on the caller's
+    stream (one rounding instead of two; energies within rounding)."""
+    x, q, L = W.uniform_pm1(3000, seed=47)
+    x, q = rounded(x, prec), rounded(q, prec)
+    c = pw.choose_params(1e-6, L, m=32)
+    out = {}
+    for overlap in ("1", "0"):
+        monkeypatch.setenv("PSWFE_LOCAL_OVERLAP", overlap)
+        plan = pw.Plan(c, prec, n_max=len(q))
+        phi, F, E = plan.compute(tdev(x, prec), tdev(q, prec), total=True)
+        _, G, _ = plan.compute(tdev(x, prec), tdev(q, prec), total=True, grad=True)
+        out[overlap] = [a.double().cpu().numpy() for a in (phi, F, G, E)]
+        plan.close()
+    tol = 1e-13 if prec == "fp64" else 2e-7
+    for a, b in zip(out["1"][:3], out["0"][:3]):
+        assert rel_l2(a, b) < tol
+    assert abs(out["1"][3][0] - out["0"][3][0]) <= tol * abs(out["0"][3][0])
+    # batch plans take the same path
+    monkeypatch.setenv("PSWFE_LOCAL_OVERLAP", "1")
+    bplan = pw.BatchPlan([c, c], [len(q), len(q)], prec)
+    X2 = tdev(np.concatenate([x, x]), prec)
+    Q2 = tdev(np.concatenate([q, -q]), prec)
+    bphi, bF, bE = bplan.compute(X2, Q2, total=True)
+    bphi = bphi.double().cpu().numpy()
+    assert rel_l2(bphi[:len(q)], out["0"][0]) < 10 * tol
+    assert rel_l2(bphi[len(q):], -out["0"][0]) < 10 * tol
+    assert np.allclose(bE.cpu().numpy(), out["0"][3][0], rtol=10 * tol, atol=0)
+
+
+def test_graph_replay_of_the_total_sum():
+    """A captured graph of the full Ewald sum (the residual forked to the side stream and joined
+    back inside the capture) replays to the eager results, with eager work between replays and
+    new inputs."""
+    prec = "fp32"
+    x, q, L = W.uniform_pm1(4000, seed=48)
+    c = pw.choose_params(1e-6, L, m=32)
+    plan = pw.Plan(c, prec, n_max=len(q))
+    X, Q = tdev(x, prec), tdev(q, prec)
+    e_phi, e_F, e_E = plan.compute(X, Q, total=True)
+    torch.cuda.synchronize()
+    runner = plan.graph(X, Q, total=True)
+    other = pw.Plan(c, prec, n_max=len(q))
+    for _ in range(4):
+        phi, F, E = runner()
+        torch.cuda.synchronize()
+        assert torch.allclose(phi, e_phi, rtol=0, atol=1e-6 * float(e_phi.abs().max()))
+        assert torch.allclose(F, e_F, rtol=0, atol=1e-6 * float(e_F.abs().max()))
+        assert torch.allclose(E, e_E, rtol=1e-6, atol=1e-12)
+        other.compute(X, Q, total=True)
+        _ = (X * 2).sum()
+        torch.cuda.synchronize()
+    phi2, F2, E2 = runner(q=-Q)
+    torch.cuda.synchronize()
+    assert torch.allclose(phi2, -e_phi, rtol=0, atol=1e-6 * float(e_phi.abs().max()))
+    assert torch.allclose(E2, e_E, rtol=1e-6, atol=1e-12)
