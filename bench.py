@@ -63,6 +63,7 @@ STAGE_KERNEL = {"spread": ("k_spread", "k_spread_cols", "k_spread_mfma"), "gathe
                 "fft_y": ("k_fft_cols",), "fft_z_scale": ("k_fft_cols",), "ifft_y": ("k_fft_cols",),
                 "ifft_x": ("k_fft_x_c2r",), "bin": ("k_bin_count",)}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_water_box_n30000.md")
+TRAFFIC_FILE_N1E6 = os.path.join(ROOT, "profiles", "traffic_uniform_n1e6.md")
 # the device code whose counters the traffic file holds; any change to the code voids them
 KERNEL_SOURCES = ("kernels.hip", "kernels.hpp", "particles.hip", "device_common.hpp")
 
@@ -114,7 +115,7 @@ def measured_traffic(stage: str, prec_ctype: str, workload: str = "water_box_n30
     """HBM bytes per launch of the stage's kernel(s) from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE runs, calibrated against a plain copy), or None when the summary
     is missing or was taken on other kernel sources."""
-    blob = _profile_blob(TRAFFIC_FILE, workload)
+    blob = _profile_blob(TRAFFIC_FILE_N1E6 if workload == "uniform_n1e6" else TRAFFIC_FILE, workload)
     if blob is None:
         return None
     per = blob.get("bytes_per_launch", {})
