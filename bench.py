@@ -26,7 +26,6 @@ if ROOT not in sys.path:
 
 METRIC = "long-range particles/s (φ+forces) at ε=1e-6 FP32 vs FP64; % HBM roofline"
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_TFLOPS = 157.3   # packed float32 vector FMA: 256 CU x 4 SIMD x 16 lanes x 2 x 2 flops x 2.4 GHz
 PEAK_FP64_TFLOPS = 78.6    # float64 vector FMA (256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz); the float64 MFMA peak is the same
 STAGES = ["bin", "spread", "fft_x", "fft_y", "fft_z_scale", "ifft_y", "ifft_x", "gather"]
 
