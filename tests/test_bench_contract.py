@@ -28,6 +28,7 @@ def test_water_box_counter_summaries_are_not_used_for_other_workloads(tmp_path, 
     p = tmp_path / "summary.md"
     p.write_text("```json\n" + json.dumps(blob) + "\n```\n")
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(p))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE_N1E6", str(p))   # a water-box summary where the n = 1e6 one belongs
     assert bench.measured_traffic("spread", "float") == 41_000_000
     assert bench.measured_traffic("spread", "float", "uniform_n1e6") is None
 
