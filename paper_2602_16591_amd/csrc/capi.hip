@@ -364,9 +364,16 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     while (rpb > 1 && (2 * static_cast<size_t>(rpb) * nx1 + 2 * N + 1) * celem > fft_lds_cap) --rpb;
     int cmax = std::max(1, std::min(64, fft_elems / (mlen + 1)));
     while (cmax > 1 && (2 * static_cast<size_t>(cmax) * (mlen + 1) + 2 * mlen) * celem > fft_lds_cap) --cmax;
-    const int nxb = (nx1 + cmax - 1) / cmax;
+    // Spectrum rows padded to 128 bytes, and column blocks of whole 128-byte segments (16
+    // float32 or 8 float64 complex values), so that a column pass reads each line once: blocks
+    // of other widths start inside lines and read about twice the bytes (measured at 128^3).
+    const int spec_align = static_cast<int>(128 / celem);
+    sd.spec_pitch = (nx1 + spec_align - 1) / spec_align * spec_align;
+    int cpb = cmax >= spec_align ? cmax / spec_align * spec_align : spec_align;
+    while (cpb > 1 && (2 * static_cast<size_t>(cpb) * (mlen + 1) + 2 * mlen) * celem > fft_lds_cap)
+      cpb = cpb > spec_align ? cpb - spec_align : cpb - 1;
     sd.rows_per_block = rpb;
-    sd.cols_per_block = (nx1 + nxb - 1) / nxb;
+    sd.cols_per_block = cpb;
     sd.xblk_base = xblk_prefix[s];
     sd.pblk_base = pblk_prefix[s];
     pblk_prefix[s + 1] = pblk_prefix[s] + m;
@@ -387,7 +394,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     d.lds_c = std::max(d.lds_c, (2 * static_cast<size_t>(sd.cols_per_block) * (mlen + 1) + 2 * mlen) * celem);
     const size_t m3 = static_cast<size_t>(m) * my * mz;
     woff[s] = {work.take(sizeof(double) * m3), work.take(elem * m3),
-               work.take(celem * static_cast<size_t>(mz) * my * nx1)};
+               work.take(celem * static_cast<size_t>(mz) * my * sd.spec_pitch)};
     // real-space cells of edge L_d / nc_d >= r_c (at most 128 per dimension); one cell holding
     // the whole system when any dimension has fewer than 3
     sd.rc = p.rc;

@@ -487,7 +487,8 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(int nsys, const SysDesc* __re
   }
   __syncthreads();
   const C* Z = fft_lds(A, Bf, nr, N, sd.fh, tw_h);
-  C* out = static_cast<C*>(sd.spec) + static_cast<int64_t>(row0) * (N + 1);
+  const int sp = sd.spec_pitch;
+  C* out = static_cast<C*>(sd.spec) + static_cast<int64_t>(row0) * sp;
   for (int e = threadIdx.x; e < nr * (N + 1); e += blockDim.x) {
     const int r = e / (N + 1), k = e - r * (N + 1);
     const C zk = Z[r * N + (k == N ? 0 : k)];
@@ -496,7 +497,7 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(int nsys, const SysDesc* __re
     const C dd = csub(zk, zn);
     const C od = C{T(0.5) * dd.y, T(-0.5) * dd.x};  // (zk - zn) / (2i)
     const C w = tw_f[k];
-    gstore(out + e, cadd(ev, cmul(w, od)));
+    gstore(out + r * sp + k, cadd(ev, cmul(w, od)));
   }
 }
 
@@ -524,9 +525,15 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(int nsys, const SysDesc* __re
     else
       tw_f[e - N] = gload(tw_full + (e - N));
   }
-  const C* in = static_cast<const C*>(sd.spec) + static_cast<int64_t>(row0) * (N + 1);
+  const int sp = sd.spec_pitch;
+  const C* in = static_cast<const C*>(sd.spec) + static_cast<int64_t>(row0) * sp;
   staged_copy<8>(
-      nr * (N + 1), [&](int e) { return gload(in + e); }, [&](int e, C v) { A[e] = v; });
+      nr * (N + 1),
+      [&](int e) {
+        const int r = e / (N + 1), k = e - r * (N + 1);
+        return gload(in + r * sp + k);
+      },
+      [&](int e, C v) { A[e] = v; });
   __syncthreads();
   for (int e = threadIdx.x; e < nr * N; e += blockDim.x) {
     const int r = e / N, k = e - r * N;
@@ -596,10 +603,11 @@ __global__ __launch_bounds__(256) void k_fft_plane_fwd(int nsys, const SysDesc* 
   __syncthreads();
   C* other = (Tc == U) ? V : U;
   const C* R = fft_lds(Tc, other, nx1, ss, sd.ff, tw_f);
-  C* out = static_cast<C*>(sd.spec) + static_cast<int64_t>(z) * m * nx1;
+  const int sp = sd.spec_pitch;
+  C* out = static_cast<C*>(sd.spec) + static_cast<int64_t>(z) * m * sp;
   for (int e = threadIdx.x; e < m * nx1; e += blockDim.x) {
     const int y = e / nx1, k = e - y * nx1;
-    gstore(out + e, R[k * ss + y]);
+    gstore(out + y * sp + k, R[k * ss + y]);
   }
 }
 
@@ -629,9 +637,14 @@ __global__ __launch_bounds__(256) void k_fft_plane_inv(int nsys, const SysDesc* 
         tw_f[e - N] = gload(tw_full + (e - N));
     }
   }
-  const C* in = static_cast<const C*>(sd.spec) + static_cast<int64_t>(z) * m * nx1;
+  const int sp = sd.spec_pitch;
+  const C* in = static_cast<const C*>(sd.spec) + static_cast<int64_t>(z) * m * sp;
   staged_copy<8>(
-      m * nx1, [&](int e) { return gload(in + e); },
+      m * nx1,
+      [&](int e) {
+        const int y = e / nx1, k = e - y * nx1;
+        return gload(in + y * sp + k);
+      },
       [&](int e, C v) {
         const int y = e / nx1, k = e - y * nx1;
         U[k * ss + y] = v;
@@ -692,9 +705,9 @@ __global__ __launch_bounds__(256) void k_fft_cols(int nsys, const SysDesc* __res
   const int outer = lb / nxb;
   const int kx0 = (lb - outer * nxb) * cpb;
   const int nc = min(cpb, nx1 - kx0);
-  const int64_t plane = static_cast<int64_t>(my) * nx1;
-  const int64_t ostride = mode == 1 ? int64_t(nx1) : plane;
-  const int64_t estride = mode == 1 ? plane : int64_t(nx1);
+  const int64_t plane = static_cast<int64_t>(my) * sd.spec_pitch;
+  const int64_t ostride = mode == 1 ? int64_t(sd.spec_pitch) : plane;
+  const int64_t estride = mode == 1 ? plane : int64_t(sd.spec_pitch);
   const int ss = len + 1;  // padded sequence stride in LDS
   const FftPlan& pl = mode == 1 ? sd.ffz : sd.ffy;
   C* A = reinterpret_cast<C*>(smem_raw);

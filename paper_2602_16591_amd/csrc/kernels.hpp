@@ -52,7 +52,8 @@ struct SysDesc {
   int S = 0;                  // LDS tile edge = (B + P - 1) rounded up to odd
   int tile_base = 0;          // first global tile of this system
   int rows_per_block = 1;     // x-direction FFT batching
-  int cols_per_block = 1;     // y/z-direction FFT batching
+  int cols_per_block = 1;     // y/z-direction FFT batching (a multiple of spec_align where nx1 allows)
+  int spec_pitch = 0;         // complex values per spectrum row: nx1 = m/2 + 1 rounded up to 128 bytes
   int xblk_base = 0;          // first block of this system in the x-direction FFT launches
   int pblk_base = 0;          // first block (z-plane) of this system in the plane FFT launches
   int cblk_base = 0;          // first block in the y-direction FFT launches
