@@ -162,7 +162,10 @@ pswfe_status pswfe_variant_params(int32_t split, int32_t window, double L, doubl
 /* Creates a plan: precomputes in float64 on the host the PSWF Legendre coefficients (App. B),
  * the k-space scaling tables (eq. diag_scale, eq. MhatPSWF, Table 2), the piecewise-polynomial
  * window (Remark after eq. force) and the FFT twiddles; allocates the device work buffers
- * (grid, spectrum, particle bins) for up to n_max particles on the current HIP device.
+ * (grid, spectrum, particle bins) for up to n_max particles on the current HIP device, and, when
+ * the real-space residual is available, a stream of default priority, two events and 32 bytes
+ * of float64 scratch per particle for PSWFE_TOTAL calls. Everything is released by
+ * pswfe_plan_destroy.
  *   p      host pointer to parameters (from pswfe_choose_params, or filled by the caller)
  *   prec   pswfe_prec
  *   n_max  largest n accepted by pswfe_compute (>= 0)
