@@ -19,13 +19,21 @@
  *
  * Conventions for every entry point
  *  - Return value: a pswfe_status; nothing is thrown across this interface.
- *  - "device" pointers are HIP device allocations (or managed memory) owned by the caller;
- *    the library never frees them. "host" pointers are ordinary CPU memory.
+ *  - "device" pointers are coarse-grained HIP device allocations (hipMalloc, or the storage of
+ *    a torch tensor on the GPU) owned by the caller; the library never frees them. Managed or
+ *    fine-grained memory is not supported: outputs are summed with hardware float64 atomics,
+ *    which are defined on coarse-grained memory only. "host" pointers are ordinary CPU memory.
+ *  - Inputs are not validated on the device unless PSWFE_CHECK_INPUT is passed (see pswfe_flags).
+ *    Without it, a particle with a non-finite position is given a NaN charge, so it poisons the
+ *    outputs it reaches (for the long-range part, every output and the energy of its system)
+ *    instead of being moved silently into the box, as a non-finite charge does; and a system
+ *    whose charges do not sum to zero carries the uniform neutralising background implied by
+ *    dropping the k = 0 mode (Sec. 3.1.2).
  *  - Floating-point arrays are in the plan's precision: float for PSWFE_FP32, double for
  *    PSWFE_FP64. The energy is always a double.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream). Every compute
- *    entry point only enqueues work: it performs no allocation and no host synchronisation,
- *    so it may be captured into a HIP graph. Calls on one plan must not overlap in time
+ *    entry point only enqueues work: it performs no allocation and no host synchronisation
+ *    (except with PSWFE_CHECK_INPUT), so it may be captured into a HIP graph. Calls on one plan must not overlap in time
  *    (a plan owns one set of work buffers).
  */
 #ifndef PSWFE_H
@@ -45,7 +53,9 @@ typedef enum {
   PSWFE_E_ALLOC = 4,      /* device allocation failed (plan creation only)                 */
   PSWFE_E_HIP = 5,        /* a HIP runtime call or kernel launch failed                    */
   PSWFE_E_CAPACITY = 6,   /* n larger than the plan's n_max                                */
-  PSWFE_E_PREC = 7        /* unknown precision                                             */
+  PSWFE_E_PREC = 7,       /* unknown precision                                             */
+  PSWFE_E_NONNEUTRAL = 8, /* PSWFE_CHECK_INPUT: |sum q| > 1e-6 sum |q| in some system          */
+  PSWFE_E_NONFINITE = 9   /* PSWFE_CHECK_INPUT: a position or charge is NaN or infinite        */
 } pswfe_status;
 
 typedef enum {
@@ -58,8 +68,15 @@ typedef enum { PSWFE_FP32 = 0, PSWFE_FP64 = 1 } pswfe_prec;
 /* Flags of the *_ex compute entry points (bitwise or). */
 typedef enum {
   PSWFE_VEC_GRAD = 1,  /* the vector output is grad phi (not the force -rho grad phi)          */
-  PSWFE_TOTAL = 2      /* add the real-space residual: phi, forces and energy of the full Ewald
+  PSWFE_TOTAL = 2,     /* add the real-space residual: phi, forces and energy of the full Ewald
                           sum phi_far + phi_local + phi_self (Sec. 3.1, eq. Ewald split)       */
+  PSWFE_CHECK_INPUT = 4 /* before any other work, sum each system's charges and |charges| in
+                          float64 and count non-finite positions and charges on the device, wait
+                          for the result on the host, and return PSWFE_E_NONFINITE or
+                          PSWFE_E_NONNEUTRAL (|sum q| > 1e-6 sum |q|; the k = 0 mode is dropped,
+                          Sec. 3.1.2) without computing anything. The call then synchronises
+                          `stream`, so it cannot be captured into a HIP graph: under capture it
+                          returns PSWFE_E_ARG. Outputs are untouched when a check fails.       */
 } pswfe_flags;
 
 /* Kernel split (Sec. 3.1) and window (Table 2). The method of the paper is PSWF/PSWF; the

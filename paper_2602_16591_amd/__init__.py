@@ -18,10 +18,10 @@ from dataclasses import dataclass
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libpswfe.so")
 
-OK, E_ARG, E_EPS_RANGE, E_GRID, E_ALLOC, E_HIP, E_CAPACITY, E_PREC = range(8)
+OK, E_ARG, E_EPS_RANGE, E_GRID, E_ALLOC, E_HIP, E_CAPACITY, E_PREC, E_NONNEUTRAL, E_NONFINITE = range(10)
 TOL_REL, TOL_ABS = 0, 1
 FP32, FP64 = 0, 1
-VEC_GRAD, TOTAL = 1, 2
+VEC_GRAD, TOTAL, CHECK_INPUT = 1, 2, 4
 
 
 class PswfeError(RuntimeError):
@@ -201,6 +201,18 @@ def _ptr(t, dtype, shape_tail, name):
     return t.data_ptr()
 
 
+def _expect_shapes(**named):
+    """Raises ValueError unless every tensor given (name=(tensor, shape)) has exactly that shape:
+    the kernels index every array up to n (or the number of systems), so a short buffer would be
+    read or written out of bounds. Checked before any pointer is passed to the library."""
+    for name, (t, shape) in named.items():
+        if t is None:
+            continue
+        got = tuple(getattr(t, "shape", ()))
+        if got != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {got}")
+
+
 def _out(spec, shape, dtype, device):
     """An output buffer: the tensor passed, a new tensor (True) or None (False/None)."""
     import torch
@@ -298,9 +310,12 @@ class Plan(_PlanBase):
             raise ValueError(f"n = {n} exceeds the plan's n_max = {self.n_max}")
         return n
 
-    def compute(self, pos, q, *, phi=True, force=True, energy=True, grad=False, total=False, stream=None):
+    def compute(self, pos, q, *, phi=True, force=True, energy=True, grad=False, total=False, check=False,
+                stream=None):
         """phi_far + phi_self, forces -q grad phi_far (or grad phi_far with grad=True), energy;
-        with total=True the real-space residual is included (the full Ewald sum).
+        with total=True the real-space residual is included (the full Ewald sum). check=True
+        first checks on the device that the charges sum to zero and every input is finite
+        (PswfeError E_NONNEUTRAL / E_NONFINITE; synchronises the stream, not capturable).
 
         Returns (phi, vec, energy) with None for outputs not requested; outputs are new tensors
         unless tensors are passed in place of True."""
@@ -309,7 +324,8 @@ class Plan(_PlanBase):
         phi_t = _out(phi, (n,), self.dtype, pos.device)
         vec_t = _out(force if not grad else grad, (n, 3), self.dtype, pos.device)
         e_t = _out(energy, (1,), torch.float64, pos.device)
-        flags = (VEC_GRAD if grad else 0) | (TOTAL if total else 0)
+        _expect_shapes(pos=(pos, (n, 3)), q=(q, (n,)), phi=(phi_t, (n,)), force=(vec_t, (n, 3)), energy=(e_t, (1,)))
+        flags = (VEC_GRAD if grad else 0) | (TOTAL if total else 0) | (CHECK_INPUT if check else 0)
         _check(_lib().pswfe_compute_ex(self._h, n, _ptr(pos, self.dtype, (3,), "pos"), _ptr(q, self.dtype, None, "q"),
                                        _ptr(phi_t, self.dtype, None, "phi"), _ptr(vec_t, self.dtype, (3,), "force"),
                                        _ptr(e_t, torch.float64, None, "energy"), flags, _stream_ptr(stream)),
@@ -323,6 +339,7 @@ class Plan(_PlanBase):
         phi_t = _out(phi, (n,), self.dtype, pos.device)
         vec_t = _out(force if not grad else grad, (n, 3), self.dtype, pos.device)
         e_t = _out(energy, (1,), torch.float64, pos.device)
+        _expect_shapes(pos=(pos, (n, 3)), q=(q, (n,)), phi=(phi_t, (n,)), force=(vec_t, (n, 3)), energy=(e_t, (1,)))
         _check(_lib().pswfe_local(self._h, n, _ptr(pos, self.dtype, (3,), "pos"), _ptr(q, self.dtype, None, "q"),
                                   _ptr(phi_t, self.dtype, None, "phi"), _ptr(vec_t, self.dtype, (3,), "force"),
                                   _ptr(e_t, torch.float64, None, "energy"), VEC_GRAD if grad else 0,
@@ -333,6 +350,9 @@ class Plan(_PlanBase):
         import torch
         n = self._n(pos)
         grid = torch.empty(self.grid_shape, dtype=self.dtype, device=pos.device) if grid is None else grid
+        _expect_shapes(pos=(pos, (n, 3)), q=(q, (n,)))
+        if grid.numel() != math.prod(self.grid_shape):
+            raise ValueError(f"grid must have {math.prod(self.grid_shape)} entries")
         _check(_lib().pswfe_spread(self._h, n, _ptr(pos, self.dtype, (3,), "pos"), _ptr(q, self.dtype, None, "q"),
                                    _ptr(grid, self.dtype, None, "grid"), _stream_ptr(stream)), "pswfe_spread")
         return grid
@@ -351,6 +371,7 @@ class Plan(_PlanBase):
     def interpolate(self, pos, grid, stream=None):
         import torch
         n = self._n(pos)
+        _expect_shapes(pos=(pos, (n, 3)))
         if grid.numel() != math.prod(self.grid_shape):
             raise ValueError(f"grid must have {math.prod(self.grid_shape)} entries")
         phi = torch.empty(n, dtype=self.dtype, device=pos.device)
@@ -387,18 +408,19 @@ class BatchPlan(_PlanBase):
         self.n_total = sum(self.counts)
         self.P = self.params[0].P
 
-    def compute(self, pos, q, *, phi=True, force=True, energy=True, grad=False, total=False, stream=None):
+    def compute(self, pos, q, *, phi=True, force=True, energy=True, grad=False, total=False, check=False,
+                stream=None):
         """Every system at once. pos (N, 3), q (N,) packed; returns (phi (N,), vec (N, 3),
         energy (nsys,) float64) with None for outputs not requested (or the tensors passed);
-        total=True includes the real-space residual."""
+        total=True includes the real-space residual; check=True as for Plan.compute, per system."""
         import torch
-        if int(pos.shape[0]) != self.n_total or int(q.shape[0]) != self.n_total:
-            raise ValueError(f"packed arrays must have {self.n_total} rows")
         n = self.n_total
+        _expect_shapes(pos=(pos, (n, 3)), q=(q, (n,)))
         phi_t = _out(phi, (n,), self.dtype, pos.device)
         vec_t = _out(force if not grad else grad, (n, 3), self.dtype, pos.device)
         e_t = _out(energy, (self.nsys,), torch.float64, pos.device)
-        flags = (VEC_GRAD if grad else 0) | (TOTAL if total else 0)
+        _expect_shapes(phi=(phi_t, (n,)), force=(vec_t, (n, 3)), energy=(e_t, (self.nsys,)))
+        flags = (VEC_GRAD if grad else 0) | (TOTAL if total else 0) | (CHECK_INPUT if check else 0)
         _check(_lib().pswfe_batch_compute_ex(self._h, _ptr(pos, self.dtype, (3,), "pos"),
                                              _ptr(q, self.dtype, None, "q"), _ptr(phi_t, self.dtype, None, "phi"),
                                              _ptr(vec_t, self.dtype, (3,), "force"),

@@ -541,6 +541,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   d.zblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
   d.cblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
   d.part_prefix = static_cast<int64_t*>(alloc(sizeof(int64_t) * (nsys + 1)));
+  d.check = static_cast<double*>(alloc(sizeof(double) * 3 * nsys));
   if (st != PSWFE_OK) {
     free_plan(plan);
     return st;
@@ -656,6 +657,8 @@ const char* pswfe_status_str(pswfe_status s) {
     case PSWFE_E_HIP: return "HIP runtime error";
     case PSWFE_E_CAPACITY: return "more particles than the plan's n_max";
     case PSWFE_E_PREC: return "unknown precision";
+    case PSWFE_E_NONNEUTRAL: return "charges do not sum to zero";
+    case PSWFE_E_NONFINITE: return "a position or charge is not finite";
   }
   return "unknown status";
 }
@@ -873,18 +876,25 @@ hipError_t run_pipeline(pswfe_plan* plan, int64_t n, const void* pos, const void
   const bool fork = total && n > 0 && plan->side;
   pswfe::stage_begin(d, pswfe::kStageAll, s);
   hipError_t e = hipSuccess;
+  bool forked = false;  // the side stream waits on the caller's: it must be joined back, whatever fails
   if (fork) {
     e = hipEventRecord(plan->ev_fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(plan->side, plan->ev_fork, 0);
+    forked = e == hipSuccess;
     if (e == hipSuccess)
       e = pswfe::launch_local(d, n, pos, q, nullptr, nullptr, vec_mode, nullptr, false, plan->side, plan->phi_d,
                               vec ? plan->vec_d : nullptr);
-    if (e == hipSuccess) e = hipEventRecord(plan->ev_join, plan->side);
   }
   if (e == hipSuccess) e = pswfe::launch_bin(d, n, pos, q, energy, s);
   if (e == hipSuccess) e = pswfe::launch_spread(d, s);
   if (e == hipSuccess) e = pswfe::launch_transform(d, nullptr, nullptr, s);
-  if (e == hipSuccess && fork) e = hipStreamWaitEvent(s, plan->ev_join, 0);
+  if (forked) {
+    // join before returning, also after a failed launch, keeping the first error: the residual
+    // reads the caller's inputs and writes plan scratch, and a capture must not end unjoined
+    hipError_t j = hipEventRecord(plan->ev_join, plan->side);
+    if (j == hipSuccess) j = hipStreamWaitEvent(s, plan->ev_join, 0);
+    if (e == hipSuccess) e = j;
+  }
   if (e == hipSuccess && n > 0)
     e = pswfe::launch_gather(d, nullptr, phi, vec, vec_mode, true, energy, s, fork ? plan->phi_d : nullptr,
                              fork && vec ? plan->vec_d : nullptr);
@@ -893,7 +903,29 @@ hipError_t run_pipeline(pswfe_plan* plan, int64_t n, const void* pos, const void
   return e;
 }
 
-constexpr int32_t kKnownFlags = PSWFE_VEC_GRAD | PSWFE_TOTAL;
+constexpr int32_t kKnownFlags = PSWFE_VEC_GRAD | PSWFE_TOTAL | PSWFE_CHECK_INPUT;
+
+// Relative charge imbalance above which PSWFE_CHECK_INPUT reports a system as non-neutral.
+constexpr double kNeutralTol = 1e-6;
+
+// PSWFE_CHECK_INPUT: per-system charge sums and non-finite counts on the device, read back with
+// a synchronisation of `s` (refused while `s` is being captured).
+pswfe_status check_input(pswfe_plan* plan, int64_t n, const void* pos, const void* q, hipStream_t s) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess) return PSWFE_E_HIP;
+  if (cap != hipStreamCaptureStatusNone) return PSWFE_E_ARG;
+  const pswfe::DevPlan& d = plan->d;
+  std::vector<double> h(3 * static_cast<size_t>(d.nsys), 0.0);
+  hipError_t e = pswfe::launch_check(d, n, pos, q, d.check, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d.check, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return PSWFE_E_HIP;
+  for (int k = 0; k < d.nsys; ++k)
+    if (h[3 * k + 2] > 0.0) return PSWFE_E_NONFINITE;
+  for (int k = 0; k < d.nsys; ++k)
+    if (std::fabs(h[3 * k]) > kNeutralTol * h[3 * k + 1]) return PSWFE_E_NONNEUTRAL;
+  return PSWFE_OK;
+}
 
 pswfe_status compute_impl(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi, void* vec,
                           int32_t flags, double* energy, void* stream) {
@@ -901,6 +933,10 @@ pswfe_status compute_impl(pswfe_plan* plan, int64_t n, const void* pos, const vo
   if ((flags & PSWFE_TOTAL) && !plan->local_ok) return PSWFE_E_ARG;
   if (n > plan->d.n_max) return PSWFE_E_CAPACITY;
   if (n > 0 && (!pos || !q)) return PSWFE_E_ARG;
+  if (flags & PSWFE_CHECK_INPUT) {
+    const pswfe_status c = check_input(plan, n, pos, q, static_cast<hipStream_t>(stream));
+    if (c != PSWFE_OK) return c;
+  }
   return from_hip(run_pipeline(plan, n, pos, q, phi, vec, (flags & PSWFE_VEC_GRAD) ? 1 : 0, energy,
                                (flags & PSWFE_TOTAL) != 0, static_cast<hipStream_t>(stream)));
 }
@@ -911,6 +947,10 @@ pswfe_status batch_impl(pswfe_plan* plan, const void* pos, const void* q, void* 
   if ((flags & PSWFE_TOTAL) && !plan->local_ok) return PSWFE_E_ARG;
   const int64_t n = plan->d.n_max;
   if (n > 0 && (!pos || !q)) return PSWFE_E_ARG;
+  if (flags & PSWFE_CHECK_INPUT) {
+    const pswfe_status c = check_input(plan, n, pos, q, static_cast<hipStream_t>(stream));
+    if (c != PSWFE_OK) return c;
+  }
   return from_hip(run_pipeline(plan, n, pos, q, phi, vec, (flags & PSWFE_VEC_GRAD) ? 1 : 0, energy,
                                (flags & PSWFE_TOTAL) != 0, static_cast<hipStream_t>(stream)));
 }

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <limits>
 #include <utility>
 
 namespace pswfe {
@@ -111,9 +112,58 @@ __global__ void k_bin_scatter(int64_t n, int nsys, const SysDesc* __restrict__ s
   const int cy = support_anchor(c1, f[1], sd.P, sd.my, r.y);
   const int cz = support_anchor(c2, f[2], sd.P, sd.mz, r.z);
   r.w = q ? q[i] : T(0);
+  // a non-finite position is moved to cell 0 by grid_coord; its NaN charge poisons the outputs
+  // instead (spreading adds NaN into the grid, interpolation returns NaN for it)
+  if (!(isfinite(pos[3 * i + 0]) && isfinite(pos[3 * i + 1]) && isfinite(pos[3 * i + 2])))
+    r.w = std::numeric_limits<T>::quiet_NaN();
   sorted[dst] = r;
   cells[dst] = pack_cell(cx, cy, cz);
   perm[dst] = static_cast<int>(i);
+}
+
+// Input check (PSWFE_CHECK_INPUT): per system s, out[3 s] = sum q, out[3 s + 1] = sum |q| (float64)
+// and out[3 s + 2] = the number of particles with a non-finite position or charge; out is
+// zeroed by k_zero first. A wave whose particles all belong to one system adds its reduced sums
+// with one atomic each; a wave spanning systems adds per particle.
+__global__ void k_zero(double* __restrict__ out, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = 0.0;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_check_input(int64_t n, int nsys, const int64_t* __restrict__ part_prefix,
+                                                     const T* __restrict__ pos, const T* __restrict__ q,
+                                                     double* __restrict__ out) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  const bool valid = i < n;
+  const int64_t ic = valid ? i : n - 1;
+  const int s = nsys == 1 ? 0 : find_sys(part_prefix, nsys, ic);
+  double v = 0.0, a = 0.0, bad = 0.0;
+  if (valid) {
+    const T qi = q[i];
+    const bool finite = isfinite(pos[3 * i + 0]) && isfinite(pos[3 * i + 1]) && isfinite(pos[3 * i + 2]) && isfinite(qi);
+    v = finite ? static_cast<double>(qi) : 0.0;
+    a = finite ? fabs(static_cast<double>(qi)) : 0.0;
+    bad = finite ? 0.0 : 1.0;
+  }
+  const int s0 = __shfl(s, 0, 64);
+  if (__all(s == s0)) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      v += __shfl_xor(v, off, 64);
+      a += __shfl_xor(a, off, 64);
+      bad += __shfl_xor(bad, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicAdd(out + 3 * s0, v);
+      atomicAdd(out + 3 * s0 + 1, a);
+      atomicAdd(out + 3 * s0 + 2, bad);
+    }
+  } else if (valid) {
+    atomicAdd(out + 3 * s, v);
+    atomicAdd(out + 3 * s + 1, a);
+    atomicAdd(out + 3 * s + 2, bad);
+  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -160,9 +210,11 @@ __global__ void k_cell_scatter(int64_t n, int nsys, const SysDesc* __restrict__ 
   if (i >= n) return;
   const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
   const int dst = cell_start[cell_of[i]] + cell_rank[i];
+  const bool finite = isfinite(pos[3 * i + 0]) && isfinite(pos[3 * i + 1]) && isfinite(pos[3 * i + 2]);
   lsorted[dst] = make_double4(wrap_pos(static_cast<double>(pos[3 * i + 0]), sd.L),
                               wrap_pos(static_cast<double>(pos[3 * i + 1]), sd.Ly),
-                              wrap_pos(static_cast<double>(pos[3 * i + 2]), sd.Lz), static_cast<double>(q[i]));
+                              wrap_pos(static_cast<double>(pos[3 * i + 2]), sd.Lz),
+                              finite ? static_cast<double>(q[i]) : std::numeric_limits<double>::quiet_NaN());
   lperm[dst] = static_cast<int>(i);
 }
 
@@ -323,7 +375,7 @@ __global__ __launch_bounds__(NT) void k_local(int nsys, const SysDesc* __restric
     if (tid == 0) {
       double tot = 0.0;
       for (int w = 0; w < NT / 64; ++w) tot += s_red[w];
-      unsafeAtomicAdd(energy + s, tot);
+      safeAtomicAdd(energy + s, tot);  // caller's memory: the CAS form
     }
   }
 }
@@ -922,6 +974,21 @@ hipError_t prepare_kernels(DevPlan& d) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_check(const DevPlan& d, int64_t n_total, const void* pos, const void* q, double* out,
+                        hipStream_t st) {
+  const int count = 3 * d.nsys;
+  hipLaunchKernelGGL(k_zero, dim3(blocks_for(count, 256)), dim3(256), 0, st, out, count);
+  if (n_total > 0) {
+    if (d.prec == 0)
+      hipLaunchKernelGGL(k_check_input<float>, dim3(blocks_for(n_total, 256)), dim3(256), 0, st, n_total, d.nsys,
+                         d.part_prefix, static_cast<const float*>(pos), static_cast<const float*>(q), out);
+    else
+      hipLaunchKernelGGL(k_check_input<double>, dim3(blocks_for(n_total, 256)), dim3(256), 0, st, n_total, d.nsys,
+                         d.part_prefix, static_cast<const double*>(pos), static_cast<const double*>(q), out);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_bin(const DevPlan& d, int64_t n_total, const void* pos, const void* q, double* energy,

@@ -187,6 +187,7 @@ struct DevPlan {
   int local_deg = 0;           // highest residual polynomial degree over the systems
   int local_threads = 512;     // residual workgroup size (128, 256, 512)
   StageTimer* timer = nullptr; // optional instrumentation
+  double* check = nullptr;     // 3 nsys doubles: results of the input check
 };
 
 inline void stage_begin(const DevPlan& d, int stage, hipStream_t st) {
@@ -226,6 +227,10 @@ hipError_t prepare_kernels(DevPlan& d);
 // n_total: packed particles (a single system: its n). energy: nsys doubles zeroed here, or NULL.
 hipError_t launch_bin(const DevPlan& d, int64_t n_total, const void* pos, const void* q, double* energy,
                       hipStream_t stream);
+// Input check: per system s, out[3 s .. 3 s + 2] = (sum q, sum |q|, number of particles with a
+// non-finite position or charge), float64; out holds 3 nsys doubles (zeroed here).
+hipError_t launch_check(const DevPlan& d, int64_t n_total, const void* pos, const void* q, double* out,
+                        hipStream_t stream);
 // Spreads the binned particles into each system's float64 grid_a.
 hipError_t launch_spread(const DevPlan& d, hipStream_t stream);
 // Copies grid_a of system 0 into `out` (plan precision) and zeroes it.

@@ -629,6 +629,7 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
     }
     if (active && li == 0) {
       const double qd = static_cast<double>(r.w);
+      if (qd != qd) ph = gx = gy = gz = qd;  // binning marks a non-finite position with a NaN charge
       double phd = ph;
       if (add_self) phd -= self_coef * qd;
       if (phi_add) phd += phi_add[idx];  // the real-space residual, computed alongside (float64)
@@ -657,7 +658,7 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
     if (threadIdx.x == 0) {
       double tot = 0.0;
       for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) tot += s_red[w];
-      unsafeAtomicAdd(energy + s, 0.5 * tot);
+      safeAtomicAdd(energy + s, 0.5 * tot);  // caller's memory: the CAS form
     }
   }
 }

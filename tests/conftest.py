@@ -26,3 +26,15 @@ def read_table(name):
                 continue
             rows.append(line.split())
     return rows
+
+
+def pytest_terminal_summary(terminalreporter):
+    """Largest per-particle err/tol ratio of every element-wise parity check that ran."""
+    import sys
+    mod = sys.modules.get("elementwise")
+    ratios = getattr(mod, "RATIOS", None) if mod else None
+    if not ratios:
+        return
+    terminalreporter.write_sep("-", "element-wise parity: largest err/tol per check")
+    for name, r in ratios:
+        terminalreporter.write_line(f"{r:9.3g}  {name}")

@@ -145,8 +145,10 @@ def test_status_codes():
     assert lib.pswfe_batch_compute_grad(None, None, None, None, None, None, None) == pw.E_ARG
     assert lib.pswfe_plan_num_systems(None) == 0
     assert lib.pswfe_plan_system(None, 0, None, None, None, None) == pw.E_ARG
-    for s in range(8):
-        assert lib.pswfe_status_str(s)
+    for s in range(10):
+        assert lib.pswfe_status_str(s) and lib.pswfe_status_str(s) != b"unknown status"
+    assert (pw.E_NONNEUTRAL, pw.E_NONFINITE, pw.CHECK_INPUT) == (8, 9, 4)
+    assert lib.pswfe_compute_ex(None, 0, None, None, None, None, None, 8, None) == pw.E_ARG
 
 
 def test_tile_for_density():

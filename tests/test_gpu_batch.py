@@ -12,6 +12,7 @@
 import numpy as np
 import pytest
 
+import elementwise as EW
 import workloads as W
 from oracle import direct, fast, params as oparams
 
@@ -47,14 +48,18 @@ def pack(systems, prec):
             torch.as_tensor(rounded(q, prec), dtype=dt(prec), device=d))
 
 
-def check_vs_oracle(x, q, o, phi, F, E, eps, prec):
-    """The compute parity bar of the single-system tests, for one system."""
+def check_vs_oracle(x, q, o, phi, F, E, eps, prec, c=None, name="batch"):
+    """The compute parity bar of the single-system tests, for one system: norms, and with the
+    library parameters c the per-particle bounds of tests/elementwise.py."""
     if len(q) == 0:
         assert E == 0.0
         return
-    rphi, rg = fast.fast_longrange(x, q, o)
+    rphi, rg, grids = fast.fast_longrange(x, q, o, return_grids=True)
     rF = direct.forces(q, rg)
     far = rphi - direct.self_term(q, o.rc, o.cs)
+    if c is not None and len(q) > 1:
+        EW.check(name, phi, F, q, rphi, rg, far, grids["b"], np.mod(x, o.L), o, pw.host_tables(c, prec)["coef"],
+                 eps, prec)
     tol_phi = (1e-11 if prec == "fp64" else 2e-6) + 10 * fit_tol(eps, prec)
     tol_F = (1e-10 if prec == "fp64" else 2e-5) + 100 * fit_tol(eps, prec)
     scale = max(np.linalg.norm(far), 1e-300)
@@ -107,7 +112,7 @@ def test_mixed_batch_matches_oracle_and_sequential(prec):
     E = E.cpu().numpy()
     phis, Fs = plan.split(phi.cpu().numpy()), plan.split(F.cpu().numpy())
     for k, (x, qq, L, eps, c, o) in enumerate(systems):
-        check_vs_oracle(x, qq, o, phis[k], Fs[k], float(E[k]), eps, prec)
+        check_vs_oracle(x, qq, o, phis[k], Fs[k], float(E[k]), eps, prec, c=c, name=f"mixed-batch-{prec}-sys{k}")
     # sequential single-system plans with the same tiles
     tol = 1e-6 if prec == "fp32" else 1e-12
     for k, (x, qq, L, eps, c, o) in enumerate(systems):
@@ -227,4 +232,4 @@ def test_full_ensemble_batched_vs_sequential_and_oracle():
         x, qq = rounded(x, prec), rounded(qq, prec)
         o = oparams.choose(1e-6, L, n=len(qq))
         assert (o.m, o.P) == (params[k].m, params[k].P)
-        check_vs_oracle(x, qq, o, phis[k], Fs[k], float(E[k]), 1e-6, prec)
+        check_vs_oracle(x, qq, o, phis[k], Fs[k], float(E[k]), 1e-6, prec, c=params[k], name=f"ensemble-sys{k}")

@@ -17,6 +17,8 @@ import math
 import numpy as np
 import pytest
 
+import elementwise as EW
+import oracle_pool
 import workloads as W
 from oracle import direct, fast, params as oparams
 
@@ -66,9 +68,13 @@ def test_water_box_vs_direct_sum(prec):
     gerr = -F[idx] / q[idx, None] - gref
     kmax = o.m // 2
     assert np.sqrt(np.mean(np.sum(gerr ** 2, axis=1))) < 3 * (2 * math.pi * kmax / L) * eps
-    # every particle against the float64 fast oracle: arithmetic error of the path only
-    rphi, rg = fast.fast_longrange(x, q, o)
+    # every particle against the float64 fast oracle, phi and forces, particle by particle:
+    # arithmetic error of the path only
+    rphi, rg, grids = fast.fast_longrange(x, q, o, return_grids=True)
     assert np.sqrt(np.mean((phi - rphi) ** 2)) < (1e-10 if prec == "fp64" else 0.3 * eps)
+    far = rphi - direct.self_term(q, o.rc, o.cs)
+    EW.check(f"water_box_n30000-{prec}", phi, F, q, rphi, rg, far, grids["b"], np.mod(x, L), o,
+             pw.host_tables(c, prec)["coef"], eps, prec)
     Eref = 0.5 * float(np.dot(q, rphi))
     assert abs(E - Eref) < (1e-9 if prec == "fp64" else 1e-6) * abs(Eref)
 
@@ -98,6 +104,49 @@ def test_large_uniform_vs_direct_sum(prec, eps, m, rc):
     gerr = -F[idx] / q[idx, None] - gref
     assert np.sqrt(np.mean(np.sum(gerr ** 2, axis=1))) < 3 * (2 * math.pi * (o.m // 2) / L) * eps * \
         np.sqrt(np.mean(far ** 2))
+
+
+@pytest.mark.slow
+def test_large_uniform_fp32_every_particle_vs_fast_oracle():
+    """n = 1e6 uniform, float32 at eps = 1e-6 on 128^3 (P = 12), the benchmark's plan: phi and
+    forces of every particle against Alg. 2 in float64 (oracle/fast.py), particle by particle."""
+    x, q, L = W.config("uniform_n1e6")
+    x, q = rounded(x, "fp32"), rounded(q, "fp32")
+    eps = 1e-6
+    c = pw.choose_params(eps, L, m=128)
+    o = oparams.choose(eps, L, m=128)
+    phi, F, E = run(x, q, c, "fp32")
+    rphi, rg, grids = oracle_pool.fast_longrange(x, q, o, return_grids=True)
+    far = rphi - direct.self_term(q, o.rc, o.cs)
+    EW.check("uniform_n1e6-fp32-every-particle", phi, F, q, rphi, rg, far, grids["b"], np.mod(x, L), o,
+             pw.host_tables(c, "fp32")["coef"], eps, "fp32")
+    Eref = 0.5 * float(np.dot(q, rphi))
+    assert abs(E - Eref) <= 6 * EW.global_rel(eps, "fp32")[0] * 0.5 * float(np.abs(q) @ np.abs(far)) + 1e-12 * abs(Eref)
+
+
+@pytest.mark.slow
+def test_large_uniform_fp64_sampled_vs_fast_oracle():
+    """n = 1e6 uniform, float64 at eps = 1e-10 with the float32 plan's r_c (216^3, P = 18): the
+    oracle's grid of Alg. 2 steps 1-4 in full, interpolated at 4096 sampled particles (step 5);
+    phi and forces of those particles compared one by one."""
+    x, q, L = W.config("uniform_n1e6")
+    eps = 1e-10
+    rc = oparams.choose(1e-6, L, m=128).rc
+    c = pw.choose_params(eps, L, rc=rc)
+    o = oparams.choose(eps, L, rc=rc)
+    assert (c.m, c.P) == (o.m, o.P)
+    phi, F, E = run(x, q, c, "fp64")
+    xw = np.mod(x, L)
+    a = oracle_pool.spread(xw, q, o)
+    ahat = np.fft.ifftn(a) * o.m ** 3
+    b = np.fft.fftn(fast.scaling(o, ball=True) * ahat).real
+    del a, ahat
+    idx = sample(len(q), 4096, 5)
+    rphi, rg = fast.interpolate(b, xw[idx], o)
+    far = rphi
+    rphi = rphi + direct.self_term(q[idx], o.rc, o.cs)
+    EW.check("uniform_n1e6-fp64-4096-sampled", phi[idx], F[idx], q, rphi, rg, far, b, xw, o,
+             pw.host_tables(c, "fp64")["coef"], eps, "fp64", idx=idx)
 
 
 def test_clustered_vs_direct_sum():
