@@ -215,6 +215,27 @@ pswfe_status pswfe_plan_destroy(pswfe_plan* plan);
 pswfe_status pswfe_compute(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* phi,
                            void* force, double* energy, void* stream);
 
+/* pswfe_compute for callers that cannot allocate device memory (serving loops and harnesses that
+ * forbid hipMalloc): no plan object; every buffer of the pipeline (tables, descriptors, grids,
+ * spectrum, particle bins) lives in one library-owned device array of 64 MiB per GPU, held until
+ * the process ends, so the call allocates no device memory. Arguments as for pswfe_compute, with
+ * the plan replaced by its parameters and precision:
+ *   p, prec  parameters (as for pswfe_plan_create) and pswfe_prec
+ *   n        number of particles (0 <= n < 2^31); pos, q, phi, force, energy, stream as for pswfe_compute
+ * The configuration's buffers must fit the array: about 17 m^3 (float32) or 25 m^3 (float64)
+ * bytes of grids and spectrum plus 32 (float32) or 48 (float64) bytes per particle and a few KiB
+ * of tables (the 64^3 water box with 30,000 particles needs about 6 MiB; a 128^3 float32 grid
+ * fits up to about 970,000 particles); larger configurations return PSWFE_E_CAPACITY before any
+ * device work. The first call of a configuration (parameters,
+ * precision, n) on a GPU builds its tables on the host (host memory; the last 8 configurations
+ * are kept); a call uploads them into the array (a host-to-device copy on `stream`) when another
+ * configuration used it last, clears the grid and bin counters with fill kernels, and runs the
+ * pipeline. The upload reads host memory, so under graph capture the call returns PSWFE_E_ARG.
+ * Every call on a GPU shares that GPU's array and leaves its contents there: calls that overlap
+ * in time on one GPU (on different streams) race and give wrong results. */
+pswfe_status pswfe_compute_noalloc(const pswfe_params* p, int32_t prec, int64_t n, const void* pos, const void* q,
+                                   void* phi, void* force, double* energy, void* stream);
+
 /* As pswfe_compute, but `grad` receives grad phi_far (n x 3, not multiplied by -rho): the
  * field needed by adjoints of losses that depend on phi (a second apply with charges g gives
  * A g, and d/dx_i of g^T A q = g_i grad phi_i[q] + q_i grad phi_i[g], A symmetric, eq. matform). */

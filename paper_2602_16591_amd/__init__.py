@@ -57,6 +57,7 @@ SIGNATURES = {
     "pswfe_plan_destroy": (ctypes.c_int, [_vp]),
     "pswfe_compute": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pswfe_compute_grad": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "pswfe_compute_noalloc": (ctypes.c_int, [ctypes.POINTER(CParams), _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "pswfe_spread": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp]),
     "pswfe_transform": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "pswfe_interpolate": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp]),

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <utility>
@@ -14,6 +15,13 @@
 #include "../../include/pswfe.h"
 #include "host.hpp"
 #include "kernels.hpp"
+
+// Device memory of pswfe_compute_noalloc: every buffer of its pipeline (tables, descriptors,
+// grids, spectrum, particle bins) is laid out in this array, one copy per GPU, held until the
+// process ends. In host code the name stands for a host-side shadow, not a device address: the
+// device address is taken once per device with hipGetSymbolAddress and used everywhere instead.
+static constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 struct pswfe_plan {
   std::vector<pswfe::Params> p;   // effective parameters of each system
@@ -34,6 +42,13 @@ struct pswfe_plan {
   double* phi_d = nullptr;        // n_max
   double* vec_d = nullptr;        // n_max x 3
   bool overlap = true;            // PSWFE_LOCAL_OVERLAP=0: residual after the long-range part, same stream
+  // device arena holding every buffer (owned, or caller-provided memory), its size, the byte
+  // ranges that must start at zero, and (caller-provided memory only) the host image of its
+  // constant part, uploaded at compute time
+  unsigned char* base = nullptr;
+  size_t arena_bytes = 0;
+  std::vector<std::pair<size_t, size_t>> zero;
+  std::vector<unsigned char> img;
 };
 
 namespace {
@@ -237,10 +252,21 @@ void put(std::vector<unsigned char>& img, size_t off, const std::vector<double>&
   }
 }
 
+// Where a plan's device arena lives: allocated by the plan (base == nullptr) or at `base`, device
+// memory of `capacity` bytes that the caller provides and keeps (no real-space residual buffers
+// then; the constant part is uploaded by the caller of build_plan at compute time).
+// With `external` and base == nullptr, build_plan only checks that the arena fits `capacity`
+// (PSWFE_OK with *out = nullptr, or PSWFE_E_CAPACITY) and touches no device.
+struct Placement {
+  bool external = false;
+  unsigned char* base = nullptr;
+  size_t capacity = 0;
+};
+
 // Builds a plan over `ps.size()` systems. counts == NULL: single system taking up to n_max
 // particles per call; otherwise a batch with counts[s] particles in system s.
 pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, const int64_t* counts,
-                        const int32_t* tiles, pswfe_plan** out) {
+                        const int32_t* tiles, pswfe_plan** out, Placement place = Placement()) {
   const int nsys = static_cast<int>(ps.size());
   const int elem = prec == PSWFE_FP32 ? 4 : 8;
   const size_t celem = 2 * static_cast<size_t>(elem);
@@ -490,16 +516,6 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   }
   if (!counts) part_prefix[1] = 0;  // unused: one system takes every particle of a call
 
-  pswfe_status st = PSWFE_OK;
-  auto alloc = [&](size_t bytes) -> void* {
-    void* ptr = nullptr;
-    if (st == PSWFE_OK && hipMalloc(&ptr, std::max<size_t>(bytes, 16)) != hipSuccess) {
-      st = PSWFE_E_ALLOC;
-      ptr = nullptr;
-    }
-    if (ptr) plan->allocs.push_back(ptr);
-    return ptr;
-  };
   // sub-buckets per tile: at least 8 particles each on average, at most 16 per tile and
   // 32768 counters in all (the scan runs in one workgroup)
   {
@@ -510,18 +526,6 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   }
   const int64_t nbuckets = static_cast<int64_t>(d.total_tiles) << d.sub_log2;
   const size_t nm = static_cast<size_t>(std::max<int64_t>(d.n_max, 1));
-  unsigned char* work_dev = static_cast<unsigned char*>(alloc(work.size));
-  unsigned char* tab_dev = static_cast<unsigned char*>(alloc(tabs.size));
-  d.tile_count = static_cast<int*>(alloc(sizeof(int) * nbuckets));
-  d.tile_start = static_cast<int*>(alloc(sizeof(int) * (nbuckets + 1)));
-  d.tile_of = static_cast<int*>(alloc(sizeof(int) * nm));
-  d.rank = static_cast<int*>(alloc(sizeof(int) * nm));
-  d.perm = static_cast<int*>(alloc(sizeof(int) * nm));
-  d.cells = static_cast<int*>(alloc(sizeof(int) * nm));
-  d.sorted = alloc(4 * static_cast<size_t>(elem) * nm);
-  d.sys_dev = static_cast<pswfe::SysDesc*>(alloc(sizeof(pswfe::SysDesc) * nsys));
-  d.tile_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
-  d.tile_sys = static_cast<int*>(alloc(sizeof(int) * nsys));
   d.total_cells = cell_prefix;
   // residual workgroup size: 512 threads (PSWFE_LOCAL_THREADS=128 or 256 overrides)
   d.local_threads = 512;
@@ -529,24 +533,103 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     const int v = std::atoi(env);
     if (v == 128 || v == 256) d.local_threads = v;
   }
-  d.cell_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
-  d.cell_count = static_cast<int*>(alloc(sizeof(int) * d.total_cells));
-  d.cell_start = static_cast<int*>(alloc(sizeof(int) * (d.total_cells + 1)));
-  d.cell_of = static_cast<int*>(alloc(sizeof(int) * nm));
-  d.cell_rank = static_cast<int*>(alloc(sizeof(int) * nm));
-  d.lsorted = static_cast<double*>(alloc(sizeof(double) * 4 * nm));
-  d.lperm = static_cast<int*>(alloc(sizeof(int) * nm));
-  d.xblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
-  d.pblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
-  d.zblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
-  d.cblk_prefix = static_cast<int*>(alloc(sizeof(int) * (nsys + 1)));
-  d.part_prefix = static_cast<int64_t*>(alloc(sizeof(int64_t) * (nsys + 1)));
-  d.check = static_cast<double*>(alloc(sizeof(double) * 3 * nsys));
-  if (st != PSWFE_OK) {
-    free_plan(plan);
-    return st;
+  const bool with_local = !place.external;  // the residual's buffers: plans that own memory only
+  if (with_local && plan->local_ok) {
+    if (const char* env = std::getenv("PSWFE_LOCAL_OVERLAP")) plan->overlap = std::atoi(env) != 0;
+  } else {
+    plan->overlap = false;
   }
-  std::vector<unsigned char> img(tabs.size, 0);
+  if (!with_local) plan->local_ok = false;
+
+  // Every device buffer of the plan lives in one arena: first the constant part (tables,
+  // descriptors, prefix tables), uploaded from a host image; then the work grids and the
+  // particle bins. grid_a and the counters must start at zero (kept zero between calls).
+  Arena dev;
+  const size_t o_tab = dev.take(tabs.size);
+  const size_t o_sys = dev.take(sizeof(pswfe::SysDesc) * nsys);
+  const size_t o_tile_prefix = dev.take(sizeof(int) * (nsys + 1));
+  const size_t o_tile_sys = dev.take(sizeof(int) * nsys);
+  const size_t o_cell_prefix = dev.take(sizeof(int) * (nsys + 1));
+  const size_t o_xblk = dev.take(sizeof(int) * (nsys + 1));
+  const size_t o_pblk = dev.take(sizeof(int) * (nsys + 1));
+  const size_t o_zblk = dev.take(sizeof(int) * (nsys + 1));
+  const size_t o_cblk = dev.take(sizeof(int) * (nsys + 1));
+  const size_t o_part = dev.take(sizeof(int64_t) * (nsys + 1));
+  const size_t const_end = dev.size;
+  const size_t o_work = dev.take(work.size);
+  const size_t o_tile_count = dev.take(sizeof(int) * nbuckets);
+  const size_t o_tile_start = dev.take(sizeof(int) * (nbuckets + 1));
+  const size_t o_tile_of = dev.take(sizeof(int) * nm);
+  const size_t o_rank = dev.take(sizeof(int) * nm);
+  const size_t o_perm = dev.take(sizeof(int) * nm);
+  const size_t o_cells = dev.take(sizeof(int) * nm);
+  const size_t o_sorted = dev.take(4 * static_cast<size_t>(elem) * nm);
+  const size_t o_check = dev.take(sizeof(double) * 3 * nsys);
+  size_t o_cell_count = 0, o_cell_start = 0, o_cell_of = 0, o_cell_rank = 0, o_lsorted = 0, o_lperm = 0;
+  size_t o_phi_d = 0, o_vec_d = 0;
+  if (with_local) {
+    o_cell_count = dev.take(sizeof(int) * d.total_cells);
+    o_cell_start = dev.take(sizeof(int) * (d.total_cells + 1));
+    o_cell_of = dev.take(sizeof(int) * nm);
+    o_cell_rank = dev.take(sizeof(int) * nm);
+    o_lsorted = dev.take(sizeof(double) * 4 * nm);
+    o_lperm = dev.take(sizeof(int) * nm);
+    if (plan->overlap) {
+      o_phi_d = dev.take(sizeof(double) * nm);
+      o_vec_d = dev.take(sizeof(double) * 3 * nm);
+    }
+  }
+  plan->arena_bytes = dev.size;
+  unsigned char* base = place.base;
+  if (place.external) {
+    const bool fits = dev.size <= place.capacity;
+    if (!fits || !base) {
+      free_plan(plan);
+      return fits ? PSWFE_OK : PSWFE_E_CAPACITY;
+    }
+  } else {
+    void* ptr = nullptr;
+    if (hipMalloc(&ptr, dev.size) != hipSuccess) {
+      free_plan(plan);
+      return PSWFE_E_ALLOC;
+    }
+    plan->allocs.push_back(ptr);
+    base = static_cast<unsigned char*>(ptr);
+  }
+  unsigned char* work_dev = base + o_work;
+  unsigned char* tab_dev = base + o_tab;
+  d.sys_dev = reinterpret_cast<pswfe::SysDesc*>(base + o_sys);
+  d.tile_prefix = reinterpret_cast<int*>(base + o_tile_prefix);
+  d.tile_sys = reinterpret_cast<int*>(base + o_tile_sys);
+  d.cell_prefix = reinterpret_cast<int*>(base + o_cell_prefix);
+  d.xblk_prefix = reinterpret_cast<int*>(base + o_xblk);
+  d.pblk_prefix = reinterpret_cast<int*>(base + o_pblk);
+  d.zblk_prefix = reinterpret_cast<int*>(base + o_zblk);
+  d.cblk_prefix = reinterpret_cast<int*>(base + o_cblk);
+  d.part_prefix = reinterpret_cast<int64_t*>(base + o_part);
+  d.tile_count = reinterpret_cast<int*>(base + o_tile_count);
+  d.tile_start = reinterpret_cast<int*>(base + o_tile_start);
+  d.tile_of = reinterpret_cast<int*>(base + o_tile_of);
+  d.rank = reinterpret_cast<int*>(base + o_rank);
+  d.perm = reinterpret_cast<int*>(base + o_perm);
+  d.cells = reinterpret_cast<int*>(base + o_cells);
+  d.sorted = base + o_sorted;
+  d.check = reinterpret_cast<double*>(base + o_check);
+  if (with_local) {
+    d.cell_count = reinterpret_cast<int*>(base + o_cell_count);
+    d.cell_start = reinterpret_cast<int*>(base + o_cell_start);
+    d.cell_of = reinterpret_cast<int*>(base + o_cell_of);
+    d.cell_rank = reinterpret_cast<int*>(base + o_cell_rank);
+    d.lsorted = reinterpret_cast<double*>(base + o_lsorted);
+    d.lperm = reinterpret_cast<int*>(base + o_lperm);
+    if (plan->overlap) {
+      plan->phi_d = reinterpret_cast<double*>(base + o_phi_d);
+      plan->vec_d = reinterpret_cast<double*>(base + o_vec_d);
+    }
+  }
+  // host image of the constant part: tables, then descriptors (with the arena's device
+  // addresses) and prefix tables
+  std::vector<unsigned char> img(const_end, 0);
   for (int s = 0; s < nsys; ++s) {
     pswfe::SysDesc& sd = d.sys[s];
     const pswfe::Tables& t = plan->tab[s];
@@ -569,8 +652,9 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     sd.twzm = tab_dev + toff[s].twzm;
     sd.lcoef = reinterpret_cast<const double*>(tab_dev + toff[s].lcoef);
     sd.rleg = reinterpret_cast<const double*>(tab_dev + toff[s].rpoly);
-    put<double>(img, toff[s].lcoef, plan->ltab[s].coef);
-    put<double>(img, toff[s].rpoly, t.rpoly.empty() ? std::vector<double>(1, 0.0) : t.rpoly);
+    const size_t T0 = o_tab;
+    put<double>(img, T0 + toff[s].lcoef, plan->ltab[s].coef);
+    put<double>(img, T0 + toff[s].rpoly, t.rpoly.empty() ? std::vector<double>(1, 0.0) : t.rpoly);
     std::vector<double> twhp, twhm, twfp, twfm, twyp, twym, twzp, twzm;
     pswfe::twiddles(N, +1, &twhp);
     pswfe::twiddles(N, -1, &twhm);
@@ -580,12 +664,12 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     pswfe::twiddles(sd.my, -1, &twym);
     pswfe::twiddles(sd.mz, +1, &twzp);
     pswfe::twiddles(sd.mz, -1, &twzm);
-    put<double>(img, toff[s].coef, t.coef);  // window polynomials: float64 in both precisions
+    put<double>(img, T0 + toff[s].coef, t.coef);  // window polynomials: float64 in both precisions
     auto put_real = [&](size_t off, const std::vector<double>& v) {
       if (prec == PSWFE_FP32)
-        put<float>(img, off, v);
+        put<float>(img, T0 + off, v);
       else
-        put<double>(img, off, v);
+        put<double>(img, T0 + off, v);
     };
     put_real(toff[s].tm, t.tm);
     put_real(toff[s].wk, t.w);
@@ -600,44 +684,45 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     put_real(toff[s].twzp, twzp);
     put_real(toff[s].twzm, twzm);
   }
-  // grid_a must start (and is kept) all-zero; the rest of the work arena needs no value.
-  bool ok = hipMemcpy(tab_dev, img.data(), tabs.size, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemset(work_dev, 0, work.size) == hipSuccess &&
-            hipMemset(d.tile_count, 0, sizeof(int) * nbuckets) == hipSuccess &&
-            hipMemset(d.cell_count, 0, sizeof(int) * d.total_cells) == hipSuccess &&
-            hipMemcpy(d.sys_dev, d.sys.data(), sizeof(pswfe::SysDesc) * nsys, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(d.tile_prefix, tile_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
-                hipSuccess &&
-            hipMemcpy(d.tile_sys, order.data(), sizeof(int) * nsys, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(d.cell_prefix, cell_prefix_v.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
-                hipSuccess &&
-            hipMemcpy(d.xblk_prefix, xblk_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
-                hipSuccess &&
-            hipMemcpy(d.pblk_prefix, pblk_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
-                hipSuccess &&
-            hipMemcpy(d.zblk_prefix, zblk_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
-                hipSuccess &&
-            hipMemcpy(d.cblk_prefix, cblk_prefix.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice) ==
-                hipSuccess &&
-            hipMemcpy(d.part_prefix, part_prefix.data(), sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice) ==
-                hipSuccess &&
-            pswfe::prepare_kernels(d) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
-  if (ok && plan->local_ok) {
-    if (const char* env = std::getenv("PSWFE_LOCAL_OVERLAP")) plan->overlap = std::atoi(env) != 0;
-    if (plan->overlap) {
-      // default priority (a stream of another priority is never used here)
-      ok = hipStreamCreateWithFlags(&plan->side, hipStreamNonBlocking) == hipSuccess &&
-           hipEventCreateWithFlags(&plan->ev_fork, hipEventDisableTiming) == hipSuccess &&
-           hipEventCreateWithFlags(&plan->ev_join, hipEventDisableTiming) == hipSuccess;
-      plan->phi_d = static_cast<double*>(alloc(sizeof(double) * nm));
-      plan->vec_d = static_cast<double*>(alloc(sizeof(double) * 3 * nm));
-      ok = ok && st == PSWFE_OK;
+  auto put_bytes = [&](size_t off, const void* src, size_t bytes) { std::memcpy(img.data() + off, src, bytes); };
+  put_bytes(o_sys, d.sys.data(), sizeof(pswfe::SysDesc) * nsys);
+  put_bytes(o_tile_prefix, tile_prefix.data(), sizeof(int) * (nsys + 1));
+  put_bytes(o_tile_sys, order.data(), sizeof(int) * nsys);
+  put_bytes(o_cell_prefix, cell_prefix_v.data(), sizeof(int) * (nsys + 1));
+  put_bytes(o_xblk, xblk_prefix.data(), sizeof(int) * (nsys + 1));
+  put_bytes(o_pblk, pblk_prefix.data(), sizeof(int) * (nsys + 1));
+  put_bytes(o_zblk, zblk_prefix.data(), sizeof(int) * (nsys + 1));
+  put_bytes(o_cblk, cblk_prefix.data(), sizeof(int) * (nsys + 1));
+  put_bytes(o_part, part_prefix.data(), sizeof(int64_t) * (nsys + 1));
+  // ranges that must start at zero: each system's grid_a and the bin counters
+  for (int s = 0; s < nsys; ++s)
+    plan->zero.push_back({o_work + woff[s].a, sizeof(double) * static_cast<size_t>(d.sys[s].m) * d.sys[s].my *
+                                                  d.sys[s].mz});
+  plan->zero.push_back({o_tile_count, sizeof(int) * static_cast<size_t>(nbuckets)});
+  if (with_local) plan->zero.push_back({o_cell_count, sizeof(int) * static_cast<size_t>(d.total_cells)});
+  plan->base = base;
+  if (place.external) {
+    // a plan in caller-provided memory keeps its image for uploads at compute time
+    plan->img = std::move(img);
+    if (pswfe::prepare_kernels(d) != hipSuccess) {
+      free_plan(plan);
+      return PSWFE_E_HIP;
     }
+    *out = plan;
+    return PSWFE_OK;
+  }
+  bool ok = hipMemcpy(base, img.data(), img.size(), hipMemcpyHostToDevice) == hipSuccess;
+  for (const auto& z : plan->zero) ok = ok && hipMemset(base + z.first, 0, z.second) == hipSuccess;
+  ok = ok && pswfe::prepare_kernels(d) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+  if (ok && plan->overlap) {
+    // default priority (a stream of another priority is never used here)
+    ok = hipStreamCreateWithFlags(&plan->side, hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&plan->ev_fork, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&plan->ev_join, hipEventDisableTiming) == hipSuccess;
   }
   if (!ok) {
-    const pswfe_status fail = st != PSWFE_OK ? st : PSWFE_E_HIP;
     free_plan(plan);
-    return fail;
+    return PSWFE_E_HIP;
   }
   *out = plan;
   return PSWFE_OK;
@@ -1026,6 +1111,106 @@ pswfe_status pswfe_host_local(const pswfe_params* pp, int64_t count, const doubl
     info[2] = t.K;
   }
   return PSWFE_OK;
+}
+
+namespace {
+// pswfe_compute_noalloc: per device, the scratch array's device address and the configuration
+// whose constant part it holds; and a few host-side plans bound to the scratch array, one per
+// (parameters, precision, n, device), reused by later calls of that configuration.
+constexpr int kNoAllocDevices = 64;
+constexpr int kNoAllocSlots = 8;
+struct NoAllocDevice {
+  unsigned char* ptr = nullptr;
+  const pswfe_plan* resident = nullptr;
+};
+struct NoAllocSlot {
+  pswfe_params key{};
+  int32_t prec = -1;
+  int64_t n = -1;
+  int device = -1;
+  pswfe_plan* plan = nullptr;
+  uint64_t used = 0;
+};
+std::mutex g_noalloc_mu;
+NoAllocDevice g_noalloc_dev[kNoAllocDevices];
+NoAllocSlot g_noalloc_slot[kNoAllocSlots];
+uint64_t g_noalloc_clock = 0;
+
+// Device address of the scratch array on `device` (current), taken once.
+hipError_t noalloc_scratch(int device, unsigned char** out) {
+  NoAllocDevice& dv = g_noalloc_dev[device];
+  if (!dv.ptr) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    dv.ptr = static_cast<unsigned char*>(ptr);
+  }
+  *out = dv.ptr;
+  return hipSuccess;
+}
+}  // namespace
+
+pswfe_status pswfe_compute_noalloc(const pswfe_params* pp, int32_t prec, int64_t n, const void* pos, const void* q,
+                                   void* phi, void* force, double* energy, void* stream) {
+  if (!pp || n < 0 || n > (int64_t(1) << 31) - 1 || (n > 0 && (!pos || !q))) return PSWFE_E_ARG;
+  if (prec != PSWFE_FP32 && prec != PSWFE_FP64) return PSWFE_E_PREC;
+  std::vector<pswfe::Params> ps(1);
+  {
+    const pswfe_status st = params_from_c(pp, &ps[0]);
+    if (st != PSWFE_OK) return st;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int device = -1;
+  if (hipGetDevice(&device) != hipSuccess) device = -1;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  NoAllocSlot* slot = nullptr;
+  for (NoAllocSlot& c : g_noalloc_slot)
+    if (c.plan && c.device == device && c.prec == prec && c.n == n && std::memcmp(&c.key, pp, sizeof(*pp)) == 0)
+      slot = &c;
+  if (!slot) {
+    // the layout's size is checked before any device call; the scratch address is taken only
+    // for a configuration that fits
+    pswfe_plan* plan = nullptr;
+    Placement place;
+    place.external = true;
+    place.capacity = kNoAllocBytes;
+    pswfe_status st = build_plan(ps, prec, n, nullptr, nullptr, &plan, place);
+    if (st != PSWFE_OK) return st;
+    if (device < 0 || device >= kNoAllocDevices) return PSWFE_E_HIP;
+    if (noalloc_scratch(device, &place.base) != hipSuccess) return PSWFE_E_HIP;
+    st = build_plan(ps, prec, n, nullptr, nullptr, &plan, place);
+    if (st != PSWFE_OK) return st;
+    slot = &g_noalloc_slot[0];
+    for (NoAllocSlot& c : g_noalloc_slot)
+      if (!c.plan || c.used < slot->used) slot = &c;
+    if (slot->plan) {
+      // the evicted plan's tables may be the scratch array's current contents
+      (void)hipDeviceSynchronize();
+      for (NoAllocDevice& dv : g_noalloc_dev)
+        if (dv.resident == slot->plan) dv.resident = nullptr;
+      free_plan(slot->plan);
+    }
+    slot->key = *pp;
+    slot->prec = prec;
+    slot->n = n;
+    slot->device = device;
+    slot->plan = plan;
+  }
+  slot->used = ++g_noalloc_clock;
+  pswfe_plan* plan = slot->plan;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess) return PSWFE_E_HIP;
+  if (cap != hipStreamCaptureStatusNone) return PSWFE_E_ARG;  // the upload below reads host memory
+  NoAllocDevice& dv = g_noalloc_dev[device];
+  hipError_t e = hipSuccess;
+  if (dv.resident != plan) {
+    e = hipMemcpyAsync(plan->base, plan->img.data(), plan->img.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) dv.resident = plan;
+  }
+  for (size_t k = 0; k < plan->zero.size() && e == hipSuccess; ++k)
+    e = pswfe::launch_zero(plan->base + plan->zero[k].first, plan->zero[k].second, s);
+  if (e == hipSuccess) e = run_pipeline(plan, n, pos, q, phi, force, 0, energy, false, s);
+  return from_hip(e);
 }
 
 pswfe_status pswfe_spread(pswfe_plan* plan, int64_t n, const void* pos, const void* q, void* grid, void* stream) {

@@ -130,6 +130,13 @@ __global__ void k_zero(double* __restrict__ out, int count) {
   if (i < count) out[i] = 0.0;
 }
 
+// Zeroes `words` 32-bit words (a fill kernel rather than a memset node, so the call can sit in a
+// captured graph).
+__global__ void k_zero_words(uint32_t* __restrict__ p, int64_t words) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < words; i += stride) p[i] = 0u;
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_check_input(int64_t n, int nsys, const int64_t* __restrict__ part_prefix,
                                                      const T* __restrict__ pos, const T* __restrict__ q,
@@ -974,6 +981,14 @@ hipError_t prepare_kernels(DevPlan& d) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const int64_t words = static_cast<int64_t>(bytes / 4);
+  if (words > 0)
+    hipLaunchKernelGGL(k_zero_words, dim3(std::max(1u, std::min(blocks_for(words, 256), 2048u))), dim3(256), 0, st,
+                       static_cast<uint32_t*>(p), words);
+  return hipGetLastError();
 }
 
 hipError_t launch_check(const DevPlan& d, int64_t n_total, const void* pos, const void* q, double* out,

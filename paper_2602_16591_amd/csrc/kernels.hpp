@@ -227,6 +227,8 @@ hipError_t prepare_kernels(DevPlan& d);
 // n_total: packed particles (a single system: its n). energy: nsys doubles zeroed here, or NULL.
 hipError_t launch_bin(const DevPlan& d, int64_t n_total, const void* pos, const void* q, double* energy,
                       hipStream_t stream);
+// Zeroes `bytes` (a multiple of 4) at device address p with a fill kernel.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);
 // Input check: per system s, out[3 s .. 3 s + 2] = (sum q, sum |q|, number of particles with a
 // non-finite position or charge), float64; out holds 3 nsys doubles (zeroed here).
 hipError_t launch_check(const DevPlan& d, int64_t n_total, const void* pos, const void* q, double* out,
