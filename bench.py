@@ -1,14 +1,17 @@
 """Benchmark: long-range PSWF fast Ewald (potentials + forces + energy) on one MI355X.
 
-Workload: water-like box of 10,000 rigid 3-site molecules (n = 30,000 charges, L = 6.688 nm,
-1 g/cm^3, SPC/E-like charges), eps = 1e-6 absolute RMS with the parameters of Alg. 3 on a 64^3
-grid (P = 13). One step = one full pass of the pipeline (binning, spreading, FFT with fused
-scaling, inverse FFT, interpolation of phi and forces, self term and energy) on inputs resident
-in HBM. The headline value is the float32 path; the float64 path is timed on the same system,
-and a batch of 256 independent systems is timed batched (one HIP graph) and sequentially.
+Headline workload: water-like box of 10,000 rigid 3-site molecules (n = 30,000 charges,
+L = 6.688 nm, 1 g/cm^3, SPC/E-like charges), eps = 1e-6 absolute RMS with the parameters of
+Alg. 3 on a 64^3 grid (P = 13). One step = one full pass of the pipeline (binning, spreading,
+FFT with fused scaling, inverse FFT, interpolation of phi and forces, self term and energy) on
+inputs resident in HBM. The headline value is the float32 path; the float64 path is timed on the
+same system. Alongside: the n = 1e6 uniform system (float32 at eps = 1e-6 on 128^3, float64 at
+eps = 1e-10 on 216^3), a batch of 256 independent systems timed batched (one HIP graph) and
+sequentially, the paper's split/window comparison configurations, and the float64 oracle on the
+host's cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
-                       [--no-comparison]
+                       [--no-comparison] [--no-large] [--workload water_box_n30000|uniform_n1e6]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -63,27 +66,8 @@ STAGE_KERNEL = {"spread": ("k_spread", "k_spread_cols", "k_spread_mfma"), "gathe
                 "ifft_x": ("k_fft_x_c2r",), "bin": ("k_bin_count",)}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_water_box_n30000.md")
 TRAFFIC_FILE_N1E6 = os.path.join(ROOT, "profiles", "traffic_uniform_n1e6.md")
-# the device code whose counters the traffic file holds; any change to the code voids them
-KERNEL_SOURCES = ("kernels.hip", "kernels.hpp", "particles.hip", "device_common.hpp")
-
-
-def code_only(text: str) -> str:
-    """C++ source with comments removed and every run of blank space made one space (string
-    and character literals kept), so that editing a comment leaves the hash unchanged."""
-    import re
-    token = re.compile(r'"(?:\\.|[^"\\])*"|\'(?:\\.|[^\'\\])*\'|//[^\n]*|/\*.*?\*/', re.S)
-    stripped = token.sub(lambda m: " " if m.group(0).startswith("/") else m.group(0), text)
-    return " ".join(stripped.split())
-
-
-def kernel_source_sha256() -> str:
-    import hashlib
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2602_16591_amd", "csrc", f), encoding="utf-8") as fh:
-            h.update(code_only(fh.read()).encode())
-    return h.hexdigest()
-
+# the device code whose counters a summary holds, and its hash (comments and blank space aside)
+from paper_2602_16591_amd.profile_summary import KERNEL_SOURCES, code_only, kernel_source_sha256  # noqa: E402,F401
 
 LDS_FILE = os.path.join(ROOT, "profiles", "lds_water_box_n30000.md")
 
@@ -164,26 +148,62 @@ def kernel_rooflines(stage_ms: dict, n: int, m: int, P: int, deg: int, elem: int
     return out
 
 
-def cpu_baseline(x, q, L, eps, m, tol_mode="abs", sample=None, label="full water box"):
-    """The float64 oracle of the same computation (Alg. 2 in NumPy, oracle/fast.py), single-
-    threaded, timed on this host: on the full system, or on its first `sample` particles with
-    the full system's parameters (grid and window), when the whole would take minutes."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(x, q, L, eps, m, tol_mode="abs", label="full water box"):
+    """The float64 oracle of the same computation (Alg. 2 in NumPy, oracle/fast.py), timed on this
+    host: on all cores (the oracle's spreading and interpolation over particle chunks in one
+    worker process per core, oracle/pool.py; the pool is started before the timed region) and on
+    one thread; plus the single-core time of the plain n = 1000 system (m = 32, eps = 1e-6), by
+    Alg. 2 and by the oracle's direct-sum route R2."""
     import numpy as np
     from threadpoolctl import threadpool_limits
-    from oracle import fast, params
+    import workloads as W
+    from oracle import direct, fast, params, pool as opool
     if tol_mode == "abs":
         p = params.choose(eps, L, m=m, q_l2=float(np.linalg.norm(q)), tol_mode="abs")
     else:
         p = params.choose(eps, L, m=m)
-    xs, qs = (x, q) if sample is None else (x[:sample], q[:sample])
+    cores = os.cpu_count() or 1
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        fast.fast_longrange(xs, qs, p, grad=True)
-        dt = time.perf_counter() - t0
-    what = f"{label} (n={len(qs)})" if sample is None else f"first {len(qs)} of the n={len(q)} {label} particles, same m and P"
-    return {"value": len(qs) / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": f"{what}, one evaluation of oracle/fast.py (Alg. 2, float64 NumPy, phi and gradients) "
-                      f"taking {dt:.2f} s on 1 thread"}
+        fast.fast_longrange(x, q, p, grad=True)
+        dt1 = time.perf_counter() - t0
+        ex = opool._pool(cores)
+        try:
+            list(ex.map(abs, range(cores)))          # workers started and idle
+            t0 = time.perf_counter()
+            opool.fast_longrange(x, q, p, pool=ex, nchunks=4 * cores)
+            dtn = time.perf_counter() - t0
+        finally:
+            ex.shutdown()
+        xc, qc, Lc = W.config("plain_fp64_n1000")
+        pc = params.choose(1e-6, Lc, m=32)
+        t0 = time.perf_counter()
+        fast.fast_longrange(xc, qc, pc, grad=True)
+        c1_fast = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        direct.longrange_r2(xc, qc, Lc, pc.rc, pc.cs)
+        c1_r2 = time.perf_counter() - t0
+    n = len(q)
+    return {"value": n / dtn, "unit": "particles/s", "cores": cores, "kind": "oracle",
+            "sample": f"{label} (n={n}), one evaluation of oracle/fast.py (Alg. 2, float64 NumPy, phi and "
+                      f"gradients) with its particle steps in {cores} worker processes, {dtn:.2f} s",
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": n / dt1, "unit": "particles/s", "seconds": dt1},
+            "plain_n1000_single_core": {"alg2_seconds": c1_fast, "direct_r2_seconds": c1_r2,
+                                        "note": "n = 1000 uniform +-1, L = 1, eps = 1e-6, m = 32: oracle/fast.py "
+                                                "and the direct route R2 of oracle/direct.py, one thread"}}
 
 
 def bench_ensemble(steps: int, warmup: int):
@@ -342,18 +362,126 @@ def bench_comparison(steps: int, warmup: int, n: int = 100_000):
     return {"workload": f"uniform_n{n}_unit_box_rc0.1", "prec": "fp32", "rows": rows, "oversampled_eps1e-6": over}
 
 
+def time_precisions(x, q, params_of, steps: int, warmup: int, with_total: bool, workload: str):
+    """Both precisions of one workload: plan creation time, the timed steps, per-stage event
+    times (a calibration pass before the timed region), the dominant stage's average launch time
+    measured with events on the compute stream during the timed steps, and (with_total) the full
+    Ewald sum with the real-space residual."""
+    import numpy as np
+    import torch
+    import paper_2602_16591_amd as pw
+    dev = torch.device("cuda:0")
+    n = len(q)
+    out = {}
+    for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        X = torch.as_tensor(x, dtype=dt, device=dev).contiguous()
+        Q = torch.as_tensor(q, dtype=dt, device=dev).contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = pw.Plan(params_of[prec], prec, n_max=n)
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t0
+        phi = torch.empty(n, dtype=dt, device=dev)
+        F = torch.empty((n, 3), dtype=dt, device=dev)
+        E = torch.empty(1, dtype=torch.float64, device=dev)
+
+        def step():
+            plan.compute(X, Q, phi=phi, force=F, energy=E)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        # untimed calibration: average duration of every stage and of the whole call
+        stage_ms = {}
+        for st in STAGES + ["all"]:
+            plan.timing_enable(st, 16)
+            for _ in range(8):
+                step()
+            ms, calls = plan.timing_read()
+            stage_ms[st] = ms / max(calls, 1)
+        plan.timing_enable(None)
+        dom = max(STAGES, key=stage_ms.get)
+        plan.timing_enable(dom, steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        dom_ms_total, dom_calls = plan.timing_read()
+        plan.timing_enable(None)
+        p = params_of[prec]
+        r = dict(elapsed=elapsed, dom=dom, dom_ms=dom_ms_total / max(dom_calls, 1), stage_ms=stage_ms, plan_s=plan_s,
+                 phi=phi.double().cpu().numpy(), F=F.double().cpu().numpy(), E=float(E.cpu()[0]),
+                 deg=pw.host_tables(p, prec)["deg"], elem=4 if prec == "fp32" else 8, m=p.m, P=p.P)
+        if with_total:
+            def step_total():
+                plan.compute(X, Q, phi=phi, force=F, energy=E, total=True)
+
+            for _ in range(5):
+                step_total()
+            plan.timing_enable("local", 16)
+            for _ in range(8):
+                step_total()
+            lms, lcalls = plan.timing_read()
+            plan.timing_enable(None)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ksteps = max(10, steps // 4)
+            for _ in range(ksteps):
+                step_total()
+            torch.cuda.synchronize()
+            total_s = (time.perf_counter() - t1) / ksteps
+            r["total"] = {"value": n / total_s, "unit": "particles/s", "ms_per_step": total_s * 1e3,
+                          "local_overlapped_us": lms / max(lcalls, 1) * 1e3}
+        plan.close()
+        out[prec] = r
+    return out
+
+
+def leg_summary(r, n, steps, workload, prec_ctype):
+    """A precision's figures for the JSON line."""
+    ms = r["elapsed"] / steps * 1e3
+    return {"value": n * steps / r["elapsed"], "unit": "particles/s", "ms_per_step": ms,
+            "ms_per_step_excl_bin": ms - r["stage_ms"]["bin"],
+            "call_us_event_timed": r["stage_ms"]["all"] * 1e3, "plan_create_s": r["plan_s"], "m": r["m"], "P": r["P"],
+            "stage_us": {k: v * 1e3 for k, v in r["stage_ms"].items() if k != "all"},
+            "kernels": kernel_rooflines(r["stage_ms"], n, r["m"], r["P"], r["deg"], r["elem"], prec_ctype, workload)}
+
+
+def roofline_of(r, n, workload):
+    kind, work = stage_work(r["dom"], n, r["m"], r["P"], r["deg"], r["elem"])
+    secs = r["dom_ms"] * 1e-3
+    if kind in ("alu", "mfma"):
+        # the particle kernels compute window values, products and sums in float64 in both
+        # precisions; the spread's sums run on the matrix cores, whose float64 peak on MI355X
+        # equals the float64 vector rate
+        achieved = work / secs / 1e12
+        roof = {"bound": kind, "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS}
+    else:
+        achieved = work / secs / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS}
+    roof["traffic"] = measured_traffic(r["dom"], "float", workload)
+    roof.update({"kernel": r["dom"], "avg_launch_us": r["dom_ms"] * 1e3, "work_per_launch": work})
+    return roof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", choices=("water_box_n30000", "uniform_n1e6"), default="water_box_n30000",
-                    help="water box (default, the headline) or n = 1e6 uniform (float32 at eps 1e-6 on 128^3, "
-                         "float64 at eps 1e-10 with the same r_c)")
+                    help="the headline workload: the water box (default) or n = 1e6 uniform (float32 at eps 1e-6 "
+                         "on 128^3, float64 at eps 1e-10 with the same r_c)")
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-sequential ensemble")
     ap.add_argument("--no-comparison", action="store_true",
                     help="skip the split/window comparison at the paper's resolutions")
+    ap.add_argument("--no-large", action="store_true",
+                    help="with the water box as headline: skip the n = 1e6 legs")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the measurement, copy a device buffer of this many MiB three times (a kernel of "
                          "known traffic, to calibrate profiler byte counters); not part of the result")
@@ -369,123 +497,48 @@ def main():
     import workloads as W
 
     dev = torch.device("cuda:0")
-    water = args.workload == "water_box_n30000"
-    if water:
+
+    def water_inputs():
         x, q, L = W.config("water_n30000")
-        eps, m = 1e-6, 64
-        params = pw.choose_params(eps, L, m=m, q_l2=float(np.linalg.norm(q)), tol_mode="abs")
-        params_of = {"fp32": params, "fp64": params}
-    else:
+        p = pw.choose_params(1e-6, L, m=64, q_l2=float(np.linalg.norm(q)), tol_mode="abs")
+        return x, q, L, {"fp32": p, "fp64": p}
+
+    def large_inputs():
         x, q, L = W.config("uniform_n1e6")
-        eps, m = 1e-6, 128
-        params = pw.choose_params(eps, L, m=m)
-        params_of = {"fp32": params, "fp64": pw.choose_params(1e-10, L, rc=params.rc)}
-    n = len(q)
-    # both precisions see the same float32-representable inputs, so the float32/float64
-    # comparison below isolates arithmetic error from input quantisation
+        p = pw.choose_params(1e-6, L, m=128)
+        return x, q, L, {"fp32": p, "fp64": pw.choose_params(1e-10, L, rc=p.rc)}
+
+    water = args.workload == "water_box_n30000"
+    x, q, L, params_of = water_inputs() if water else large_inputs()
+    # both precisions get the same float32-representable inputs, so the float32/float64
+    # comparison isolates arithmetic error from input quantisation
     x = x.astype(np.float32).astype(np.float64)
     q = q.astype(np.float32).astype(np.float64)
-    P = params.P
-    results = {}
-    for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
-        plan = pw.Plan(params_of[prec], prec, n_max=n)
-        X = torch.as_tensor(x, dtype=dt, device=dev).contiguous()
-        Q = torch.as_tensor(q, dtype=dt, device=dev).contiguous()
-        phi = torch.empty(n, dtype=dt, device=dev)
-        F = torch.empty((n, 3), dtype=dt, device=dev)
-        E = torch.empty(1, dtype=torch.float64, device=dev)
-
-        def step():
-            plan.compute(X, Q, phi=phi, force=F, energy=E)
-
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        # untimed calibration: average duration of every stage, to pick the dominant kernel
-        stage_ms = {}
-        for st in STAGES:
-            plan.timing_enable(st, 16)
-            for _ in range(8):
-                step()
-            ms, calls = plan.timing_read()
-            stage_ms[st] = ms / max(calls, 1)
-        plan.timing_enable(None)
-        dom = max(stage_ms, key=stage_ms.get)
-        plan.timing_enable(dom, args.steps)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t0
-        dom_ms_total, dom_calls = plan.timing_read()
-        plan.timing_enable(None)
-        results[prec] = dict(elapsed=elapsed, dom=dom, dom_ms=dom_ms_total / max(dom_calls, 1), stage_ms=stage_ms,
-                             phi=phi.double().cpu().numpy(), F=F.double().cpu().numpy(), E=float(E.cpu()[0]),
-                             deg=pw.host_tables(params_of[prec], prec)["deg"], elem=4 if prec == "fp32" else 8)
-        if not water:
-            plan.close()
-            continue
-        # the full Ewald sum (real-space residual added), same inputs, outside the headline
-        def step_total():
-            plan.compute(X, Q, phi=phi, force=F, energy=E, total=True)
-
-        for _ in range(5):
-            step_total()
-        plan.timing_enable("local", 16)
-        for _ in range(8):
-            step_total()
-        lms, lcalls = plan.timing_read()
-        plan.timing_enable(None)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ksteps = max(10, args.steps // 4)
-        for _ in range(ksteps):
-            step_total()
-        torch.cuda.synchronize()
-        total_s = (time.perf_counter() - t1) / ksteps
-        results[prec + "_total"] = {"value": n / total_s, "unit": "particles/s", "ms_per_step": total_s * 1e3,
-                                    "local_overlapped_us": lms / max(lcalls, 1) * 1e3}
-        plan.close()
-
-    r = results["fp32"]
-    value = n * args.steps / r["elapsed"]
-    kind, work = stage_work(r["dom"], n, m, P, r["deg"], r["elem"])
-    secs = r["dom_ms"] * 1e-3
-    if kind in ("alu", "mfma"):
-        # the particle kernels compute window values, products and sums in float64 in both
-        # precisions; the spread's sums run on the matrix cores, whose float64 peak on MI355X
-        # equals the float64 vector rate
-        achieved = work / secs / 1e12
-        roof = {"bound": kind, "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}
-    else:
-        achieved = work / secs / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None}
-    roof["traffic"] = measured_traffic(r["dom"], "float", args.workload)
-    roof.update({"kernel": r["dom"], "avg_launch_us": r["dom_ms"] * 1e3, "work_per_launch": work})
-    r64 = results["fp64"]
-    p64 = params_of["fp64"]
+    n = len(q)
+    res = time_precisions(x, q, params_of, args.steps, args.warmup, with_total=water, workload=args.workload)
+    r, r64 = res["fp32"], res["fp64"]
+    p32, p64 = params_of["fp32"], params_of["fp64"]
     if water:
-        config = {"workload": "water_box_n30000", "n": n, "L_nm": L, "eps": eps, "tol_mode": "abs", "m": m, "P": P,
-                  "rc_nm": params.rc, "parallelism": "single GPU"}
+        config = {"workload": "water_box_n30000", "n": n, "L_nm": L, "eps": 1e-6, "tol_mode": "abs", "m": p32.m,
+                  "P": p32.P, "rc_nm": p32.rc, "parallelism": "single GPU"}
     else:
-        config = {"workload": "uniform_n1e6", "n": n, "L": L, "eps": eps, "tol_mode": "rel", "m": m, "P": P,
-                  "rc": params.rc, "fp64": {"eps": 1e-10, "m": p64.m, "P": p64.P}, "parallelism": "single GPU"}
+        config = {"workload": "uniform_n1e6", "n": n, "L": L, "eps": 1e-6, "tol_mode": "rel", "m": p32.m, "P": p32.P,
+                  "rc": p32.rc, "fp64": {"eps": 1e-10, "m": p64.m, "P": p64.P}, "parallelism": "single GPU"}
+    leg32 = leg_summary(r, n, args.steps, args.workload, "float")
+    leg64 = leg_summary(r64, n, args.steps, args.workload, "double")
     out = {
-        "metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": r["elapsed"] / args.steps * 1e3, "higher_is_better": True,
+        "metric": METRIC, "value": leg32["value"], "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": leg32["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": config,
-        "roofline": roof,
-        "stage_us_fp32": {k: v * 1e3 for k, v in r["stage_ms"].items()},
-        "fp64": {"value": n * args.steps / r64["elapsed"], "unit": "particles/s",
-                 "ms_per_step": r64["elapsed"] / args.steps * 1e3,
-                 "stage_us": {k: v * 1e3 for k, v in r64["stage_ms"].items()}},
-        "kernels_fp32": kernel_rooflines(r["stage_ms"], n, m, P, r["deg"], r["elem"], "float", args.workload),
-        "kernels_fp64": kernel_rooflines(r64["stage_ms"], n, p64.m, p64.P, r64["deg"], r64["elem"], "double",
-                                         args.workload),
+        "roofline": roofline_of(r, n, args.workload),
+        "ms_per_step_excl_bin": leg32["ms_per_step_excl_bin"],
+        "plan_create_s": {"fp32": r["plan_s"], "fp64": r64["plan_s"]},
+        "stage_us_fp32": leg32["stage_us"],
+        "fp64": {k: leg64[k] for k in ("value", "unit", "ms_per_step", "ms_per_step_excl_bin", "stage_us",
+                                       "plan_create_s", "m", "P")},
+        "kernels_fp32": leg32["kernels"],
+        "kernels_fp64": leg64["kernels"],
     }
     if water:
         phi_diff = float(np.linalg.norm(r["phi"] - r64["phi"]) / np.linalg.norm(r64["phi"]))
@@ -496,17 +549,33 @@ def main():
         out["total_ewald"] = {"note": "phi_far + phi_local + phi_self (real-space residual on the GPU), same workload; "
                                       "local_overlapped_us: the residual's span on its own stream, which it shares "
                                       "with the long-range kernels running at the same time",
-                              "fp32": results["fp32_total"], "fp64": results["fp64_total"]}
+                              "fp32": r["total"], "fp64": r64["total"]}
+        if not args.no_large:
+            # the n = 1e6 system, both precisions, as extra keys (the headline stays the water box)
+            xl, ql, Ll, pl = large_inputs()
+            xl = xl.astype(np.float32).astype(np.float64)
+            ql = ql.astype(np.float32).astype(np.float64)
+            ksteps = max(10, min(args.steps, 50))
+            resl = time_precisions(xl, ql, pl, ksteps, max(2, min(args.warmup, 5)), with_total=False,
+                                   workload="uniform_n1e6")
+            out["uniform_n1e6"] = {
+                "note": "n = 1e6 uniform charges U[-1,1] minus the mean, L = 1; float32 at eps = 1e-6 (relative) on "
+                        "128^3, float64 at eps = 1e-10 with the same r_c; phi + forces + energy",
+                "steps": ksteps, "rc": pl["fp32"].rc,
+                "fp32": leg_summary(resl["fp32"], len(ql), ksteps, "uniform_n1e6", "float"),
+                "fp64": leg_summary(resl["fp64"], len(ql), ksteps, "uniform_n1e6", "double"),
+                "roofline_fp32": roofline_of(resl["fp32"], len(ql), "uniform_n1e6"),
+            }
+            del xl, ql
     if not args.no_batched:
         out["batched"] = bench_ensemble(max(5, min(args.steps, 50)), max(2, min(args.warmup, 5)))
     if not args.no_comparison:
         out["comparison"] = bench_comparison(max(5, min(args.steps, 30)), max(2, min(args.warmup, 5)))
     if not args.no_cpu_baseline:
         if water:
-            out["cpu_baseline"] = cpu_baseline(x, q, L, eps, m)
+            out["cpu_baseline"] = cpu_baseline(x, q, L, 1e-6, p32.m)
         else:
-            out["cpu_baseline"] = cpu_baseline(x, q, L, eps, m, tol_mode="rel", sample=200_000,
-                                               label="uniform")
+            out["cpu_baseline"] = cpu_baseline(x, q, L, 1e-6, p32.m, tol_mode="rel", label="uniform n = 1e6")
     if args.copy_mib > 0:
         src = torch.ones(args.copy_mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

@@ -13,4 +13,6 @@ params  parameter selection (Alg. 3, Sec. 6) with the rounding rules of the desi
 direct  direct Ewald sums: Fourier-space sum (Alg. 1), real-space residual (Sec. 3.1.1),
         self term (Sec. 3.1), Gaussian Ewald (Example 1), energy and forces (Remark in 3.1)
 fast    fast Fourier-space summation (Alg. 2) in float64, step by step in the paper's order
+pool    the same steps of ``fast`` over particle chunks in worker processes (no arithmetic of
+        its own), for systems of a million particles
 """
