@@ -104,7 +104,7 @@ size_t spread_lds_bytes(int S, int P, int D, int threads) {
   return sizeof(double) * (static_cast<size_t>(S) * S * S + (threads / 16) * 3 * P) + coef_lds_bytes(P, D);
 }
 size_t gather_lds_bytes(int S, int P, int D, int elem, int threads) {
-  return static_cast<size_t>(elem) * S * S * S + sizeof(double) * (threads / 16) * 6 * P + coef_lds_bytes(P, D);
+  return static_cast<size_t>(elem) * S * S * S + sizeof(double) * (16 + (threads / 16) * 6 * P) + coef_lds_bytes(P, D);
 }
 // LDS tile edge of interpolation and LDS-atomic spreading: the halo block B + P - 1 (supports
 // start at o in [0, B-1]), made odd so that the 16 lanes of a particle, reading or adding lines
@@ -491,14 +491,19 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   // turns it off)
   bool mfma_ok = true;
   if (const char* env = std::getenv("PSWFE_SPREAD_MFMA")) mfma_ok = std::atoi(env) != 0;
+  // float32 arithmetic in the matrix-core spreading of float32 plans (PSWFE_SPREAD_ACC=fp32);
+  // float64 window values, products and tile sums otherwise
+  bool acc32 = false;
+  if (const char* env = std::getenv("PSWFE_SPREAD_ACC")) acc32 = std::strcmp(env, "fp32") == 0;
   for (pswfe::PGroup& g : d.groups) {
     const int S = static_cast<int>(g.lds_spread), P = g.P, D = g.D;
     g.mfma = g.col_tile && mfma_ok ? 1 : 0;
+    g.acc32 = g.mfma && acc32 && prec == PSWFE_FP32 ? 1 : 0;
     g.spread_threads = g.mfma       ? pswfe::mfma_threads_host(P, g.col_tile)
                        : g.col_tile ? pswfe::col_threads_host(P, g.col_tile)
                                     : particle_threads(P, [&](int t) { return spread_lds_bytes(S, P, D, t); }, true);
     g.gather_threads = particle_threads(P, [&](int t) { return gather_lds_bytes(S, P, D, elem, t); }, false);
-    g.lds_spread = g.mfma       ? pswfe::mfma_lds_bytes(P, D, g.col_tile)
+    g.lds_spread = g.mfma       ? pswfe::mfma_lds_bytes(P, D, g.col_tile, g.acc32 ? sizeof(float) : sizeof(double))
                    : g.col_tile ? pswfe::col_lds_bytes(P, D, g.col_tile)
                                 : spread_lds_bytes(S, P, D, g.spread_threads);
     g.lds_gather = gather_lds_bytes(S, P, D, elem, g.gather_threads);

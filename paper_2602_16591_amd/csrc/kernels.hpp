@@ -113,6 +113,7 @@ struct PGroup {
   int spread_threads = 256, gather_threads = 256;  // workgroup sizes (multiples of 64, <= 1024)
   int col_tile = 0;  // spreading in registers when the group's tiles all have this edge (4, 6, 8)
   int mfma = 0;      // ... as a matrix product on the matrix cores (k_spread_mfma) rather than by y-columns
+  int acc32 = 0;     // ... with float32 window values, products and tile sums (float32 plans only)
   int parts = 1;     // workgroups per tile, each taking an equal slice of the tile's particles
   int xcd_spread = 0, xcd_gather = 0;  // XCD-aware tile order (set at plan creation)
   size_t lds_spread = 0, lds_gather = 0;  // maxima over the group's systems
@@ -131,10 +132,15 @@ inline int mfma_threads_host(int P, int B) {
   const int S = col_edge_host(P, B), pieces = (S * S + 15) / 16;
   return 64 * ((pieces + 3) / 4);
 }
-inline size_t mfma_lds_bytes(int P, int D, int B) {
+// Matrix-core spreading by two column slices: the block is wider than one 16-column piece
+// (S > 16), and every particle's x-support fits the columns [0, 16) (o_x <= 16 - P) or
+// [S - 16, S) (o_x >= S - 16), o_x in [0, B): B + 2 P <= 34.
+constexpr bool mfma_sliced_host(int P, int B) { return B + P - 1 > 16 && B + 2 * P <= 34; }
+constexpr int kMfmaRecordsHost = kColBatchHost + 8;  // a batch plus the padding of two slices
+inline size_t mfma_lds_bytes(int P, int D, int B, size_t acc_bytes) {
   const size_t S = static_cast<size_t>(col_edge_host(P, B));
-  const size_t batch = sizeof(double) * (static_cast<size_t>(P) * coef_stride(D) + kColBatchHost * (3 * S + 4)) +
-                       sizeof(int) * kColBatchHost * 4;
+  const size_t batch = sizeof(double) * (static_cast<size_t>(P) * coef_stride(D) + kMfmaRecordsHost * 4) +
+                       sizeof(int) * kMfmaRecordsHost * 4 + acc_bytes * kMfmaRecordsHost * 3 * S + 16;
   return std::max(batch, sizeof(double) * S * S * S);  // the records, then the block
 }
 inline size_t col_lds_bytes(int P, int D, int B) {

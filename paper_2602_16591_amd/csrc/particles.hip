@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 #ifndef PSWFE_PREC
 #error "PSWFE_PREC must be defined (0 float, 1 double)"
@@ -328,15 +329,42 @@ __global__ __launch_bounds__((col_threads<P, B>())) void k_spread_cols(
 // same sums as k_spread). Over a tile's particles the S^3 block is
 //   C[(z, y), x] = sum_p U[(z, y), p] V[p, x],  U = q_p w_z,p[z] w_y,p[y],  V = w_x,p[x],
 // a product of an S^2 x K and a K x S matrix (K = the tile's particles). The block is cut into
-// 16 x 16 pieces of C held in the accumulators of v_mfma_f64_16x16x4f64, kMfmaPieces row
-// pieces (all column pieces) per wave; each instruction takes 4 particles. Particles are taken
-// kColBatch at a time: their window values are written to LDS as S-long arrays per dimension
-// (zero outside the support, the z-values multiplied by the charge); per 4 particles a lane
-// reads one value of V per column piece and two of U per row piece. The block is then written
-// to LDS and added to the grid with lanes of consecutive x on consecutive addresses.
-// Accumulator layout of the instruction: item r of lane l holds row l / 16 + 4 r, column l % 16;
-// operand a of lane l is A[l % 16][l / 16], operand b is B[l / 16][l % 16].
-typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+// 16 x 16 pieces of C held in the accumulators of v_mfma_f64_16x16x4f64 (or, with A = float, of
+// v_mfma_f32_16x16x4f32), kMfmaPieces row pieces per wave; each instruction takes 4 particles.
+// Particles are taken kColBatch at a time: their window values are written to LDS as S-long arrays
+// per dimension (zero outside the support, the z-values multiplied by the charge).
+// Column slices: when S exceeds 16 but a particle's x-support (P points from o_x in [0, B)) fits
+// one 16-column piece starting at column 0 (o_x <= 16 - P) or at column S - 16 (o_x >= S - 16),
+// every particle is assigned to one of these two slices, each batch is ordered by slice (each
+// slice padded to whole groups of 4 with zero records), and a group's instructions use only its
+// slice's 16 columns: one column piece per row piece instead of two, half the matrix work (tile
+// edge 8 with P = 10-13). The two slices' accumulators are added in LDS at the end.
+// The block is then written to LDS and added to the grid with lanes of consecutive x on
+// consecutive addresses.
+// Accumulator layouts (checked on the GPU): float64, item r of lane l at row l / 16 + 4 r,
+// column l % 16; float32, item r of lane l at row 4 (l / 16) + r, column l % 16. Operand a of lane
+// l is A[l % 16][l / 16], operand b is B[l / 16][l % 16].
+// A = float keeps window values, products and the tile's sums in float32 on the matrix cores
+// (the float32 arithmetic path of float32 plans); the block is flushed into the float64 grid.
+template <class A>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mfma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+};
+template <>
+struct MfmaAcc<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mfma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+};
+
 constexpr int kMfmaPieces = 4;
 template <int P, int B>
 constexpr int mfma_row_pieces() { return (col_edge<P, B>() * col_edge<P, B>() + 15) / 16; }
@@ -344,17 +372,26 @@ template <int P, int B>
 constexpr int mfma_col_pieces() { return (col_edge<P, B>() + 15) / 16; }
 template <int P, int B>
 constexpr int mfma_threads() { return 64 * ((mfma_row_pieces<P, B>() + kMfmaPieces - 1) / kMfmaPieces); }
+template <int P, int B>
+constexpr bool mfma_sliced() { return mfma_sliced_host(P, B); }
+constexpr int kMfmaRecords = kColBatch + 8;  // a batch plus the padding of two slices
 
-template <class T, int P, int D, int B>
+template <class T, int P, int D, int B, class A>
 __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
     const typename Vec4<T>::type* __restrict__ sorted, const int* __restrict__ cells,
     const int* __restrict__ tile_start, int sub_log2, int nsys, const SysDesc* __restrict__ sys,
     const int* __restrict__ tile_prefix, const int* __restrict__ tile_sys, int tile_offset, int parts, int xcd) {
   constexpr int S = col_edge<P, B>();
   constexpr int MR = mfma_row_pieces<P, B>();
-  constexpr int NC = mfma_col_pieces<P, B>();
+  constexpr bool SL = mfma_sliced<P, B>();
+  constexpr int NC = SL ? 2 : mfma_col_pieces<P, B>();  // column pieces, or the two slices
+  constexpr int X1 = S - 16;                              // first column of slice 1
   constexpr int CS = coef_stride(D);
   constexpr int RS = 3 * S;
+  using M = MfmaAcc<A>;
+  typedef typename M::v4 acc_t;
+  // dynamic LDS only: a static array beside a large dynamic allocation measured 2.8x slower
+  // (P = 18, 125 KB of LDS per workgroup)
   extern __shared__ unsigned char smem_raw[];
   const int wgid = tile_order_block(xcd);
   const int gtile = tile_offset + wgid / parts;
@@ -364,41 +401,45 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
   const SysDesc& sd = sys[tile_sys[find_sys(tile_prefix, nsys, gtile)]];
   const int m = sd.m, Tn = sd.Tn;
   double* __restrict__ grid = sd.grid_a;
-  double* lcoef = reinterpret_cast<double*>(smem_raw);  // P * CS
-  double* recs = lcoef + P * CS;                        // kColBatch * RS
-  double* pg = recs + kColBatch * RS;                   // kColBatch * 4: g_x, g_y, g_z, q
-  int* po = reinterpret_cast<int*>(pg + kColBatch * 4); // kColBatch * 4: o_x, o_y, o_z
+  double* lcoef = reinterpret_cast<double*>(smem_raw);     // P * CS
+  double* pg = lcoef + P * CS;                             // kMfmaRecords * 4: g_x, g_y, g_z, q
+  int* po = reinterpret_cast<int*>(pg + kMfmaRecords * 4); // kMfmaRecords * 4: o_x, o_y, o_z, valid
+  A* recs = reinterpret_cast<A*>(po + kMfmaRecords * 4);   // kMfmaRecords * RS
+  // groups of 4: slice 0 in [0, s_split[0]), slice 1 up to s_split[1]
+  int* s_split = reinterpret_cast<int*>(recs + kMfmaRecords * RS);
   const int tile = gtile - sd.tile_base;
   const int tx = tile % Tn, ty = (tile / Tn) % sd.Tny, tz = tile / (Tn * sd.Tny);
   const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
   stage_coefficients<P, D>(sd.coef, sd.deg, lcoef);
   const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6;
+  const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int lr = lane & 15, lk = lane >> 4;
-  // this lane's rows of U (one per row piece) and columns of V (one per column piece)
+  // waves whose row pieces are all inside the block run the group loop without per-piece checks
+  const bool full_wave = (wave + 1) * kMfmaPieces <= MR;
+  // this lane's rows of U (one per row piece) and columns of V (one per column piece or slice)
   int zo[kMfmaPieces], yo[kMfmaPieces];
-  double rmask[kMfmaPieces];
+  A rmask[kMfmaPieces];
 #pragma unroll
   for (int u = 0; u < kMfmaPieces; ++u) {
     const int row = (wave * kMfmaPieces + u) * 16 + lr;
     const bool ok = row < S * S;
     zo[u] = 2 * S + (ok ? row / S : 0);
     yo[u] = S + (ok ? row % S : 0);
-    rmask[u] = ok ? 1.0 : 0.0;
+    rmask[u] = ok ? A(1) : A(0);
   }
   int xo[NC];
-  double cmask[NC];
+  A cmask[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const int x = c * 16 + lr;
+    const int x = SL ? (c == 0 ? lr : X1 + lr) : c * 16 + lr;
     xo[c] = x < S ? x : 0;
-    cmask[c] = x < S ? 1.0 : 0.0;
+    cmask[c] = x < S ? A(1) : A(0);
   }
-  mfma_d4 acc[kMfmaPieces][NC];
+  acc_t acc[kMfmaPieces][NC];
 #pragma unroll
   for (int u = 0; u < kMfmaPieces; ++u)
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[u][c] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < NC; ++c) acc[u][c] = acc_t{0, 0, 0, 0};
   auto r_next = sorted[min(p0 + t, p1 - 1)];
   int c_next = cells[min(p0 + t, p1 - 1)];
   for (int b0 = p0; b0 < p1; b0 += kColBatch) {
@@ -409,27 +450,47 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
       r_next = sorted[min(b0 + kColBatch + t, p1 - 1)];
       c_next = cells[min(b0 + kColBatch + t, p1 - 1)];
     }
-    if (t < nb) {
-      int o0, o1, o2;
-      pg[4 * t + 0] = static_cast<double>(r.x);
-      o0 = cell_x(cp) - T0x;
-      pg[4 * t + 1] = static_cast<double>(r.y);
-      o1 = cell_y(cp) - T0y;
-      pg[4 * t + 2] = static_cast<double>(r.z);
-      o2 = cell_z(cp) - T0z;
-      pg[4 * t + 3] = static_cast<double>(r.w);
-      po[4 * t + 0] = o0;
-      po[4 * t + 1] = o1;
-      po[4 * t + 2] = o2;
+    if (t < 64) {  // wave 0 holds the batch (kColBatch <= 64): record slots, ordered by slice
+      const bool act = t < nb;
+      const int ox = cell_x(cp) - T0x;
+      int pos = t, ng0 = (nb + 3) >> 2, ng = ng0;
+      if constexpr (SL) {
+        const bool s1 = act && ox > 16 - P;
+        const uint64_t m1 = __ballot(s1), m0 = __ballot(act && !s1);
+        const uint64_t below = (uint64_t(1) << t) - 1;
+        const int n0 = __popcll(m0), n0p = (n0 + 3) & ~3, n1 = __popcll(m1);
+        pos = s1 ? n0p + __popcll(m1 & below) : __popcll(m0 & below);
+        ng0 = n0p >> 2;
+        ng = ng0 + ((n1 + 3) >> 2);
+        // slots of the padding: [n0, n0p) and [n0p + n1, 4 ng)
+        if (t < 4 * ng && !((t < n0) || (t >= n0p && t < n0p + n1))) po[4 * t + 3] = 0;
+      } else {
+        if (t >= nb && t < 4 * ng) po[4 * t + 3] = 0;
+      }
+      if (act) {
+        pg[4 * pos + 0] = static_cast<double>(r.x);
+        pg[4 * pos + 1] = static_cast<double>(r.y);
+        pg[4 * pos + 2] = static_cast<double>(r.z);
+        pg[4 * pos + 3] = static_cast<double>(r.w);
+        po[4 * pos + 0] = ox;
+        po[4 * pos + 1] = cell_y(cp) - T0y;
+        po[4 * pos + 2] = cell_z(cp) - T0z;
+        po[4 * pos + 3] = 1;
+      }
+      if (t == 0) {
+        s_split[0] = 4 * ng0;
+        s_split[1] = 4 * ng;
+      }
     }
     __syncthreads();
-    const int nb4 = (nb + 3) & ~3;  // whole groups of 4 particles; the padding records are zero
+    const int nrec = s_split[1];
     // the P window values of each particle and dimension (Horner), then the S - P zeros around
-    // them, so that no lane runs Horner for a zero
-    for (int e = t; e < nb4 * 3 * P; e += blockDim.x) {
+    // them, so that no lane runs Horner for a zero; padding slots are all zero
+    for (int e = t; e < nrec * 3 * P; e += blockDim.x) {
       const int k = e / (3 * P), rr = e - k * (3 * P), d = rr / P, j = rr - d * P;
+      const bool ok = po[4 * k + 3] != 0;
       double v = 0.0;
-      if (k < nb) {
+      if (ok) {
         const double g = pg[4 * k + d];
         const double* c = lcoef + j * CS;
         v = c[D];
@@ -437,43 +498,100 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
         for (int kk = D - 1; kk >= 0; --kk) v = fma(v, g, c[kk]);
         if (d == 2) v *= pg[4 * k + 3];
       }
-      recs[k * RS + d * S + (k < nb ? po[4 * k + d] : 0) + j] = v;
+      recs[k * RS + d * S + (ok ? po[4 * k + d] : 0) + j] = static_cast<A>(v);
     }
-    for (int e = t; e < nb4 * 3 * (S - P); e += blockDim.x) {
+    for (int e = t; e < nrec * 3 * (S - P); e += blockDim.x) {
       const int k = e / (3 * (S - P)), rr = e - k * (3 * (S - P)), d = rr / (S - P), jj = rr - d * (S - P);
-      const int o = k < nb ? po[4 * k + d] : 0;
-      recs[k * RS + d * S + (jj < o ? jj : jj + P)] = 0.0;
+      const int o = po[4 * k + 3] != 0 ? po[4 * k + d] : 0;
+      recs[k * RS + d * S + (jj < o ? jj : jj + P)] = A(0);
     }
     __syncthreads();
-    for (int k4 = 0; k4 < nb4; k4 += 4) {
-      const double* R = recs + (k4 + lk) * RS;
-      // every piece takes every group: skipping the pieces outside the group's z-range (the
-      // particles are ordered by z) measured slower, as the branches break up the chain of
-      // matrix instructions
-      double bv[NC];
+    // every piece takes every group of its slice: skipping the pieces outside a group's z-range
+    // (the particles are ordered by z) measured slower, as the branches break up the chain of
+    // matrix instructions
+    auto groups = [&](int k_begin, int k_end, auto slice, auto full) {
+      constexpr int s = decltype(slice)::value;
+      constexpr bool all_pieces = decltype(full)::value;
+      for (int k4 = k_begin; k4 < k_end; k4 += 4) {
+        const A* R = recs + (k4 + lk) * RS;
+        A bv[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) bv[c] = R[xo[c]] * cmask[c];
+        for (int c = 0; c < NC; ++c)
+          if (!SL || c == s) bv[c] = R[xo[c]] * cmask[c];
+        if constexpr (sizeof(A) == sizeof(float)) {
+          // float32: the row operands of all pieces are read first (registers allow it)
+          A av[kMfmaPieces];
 #pragma unroll
-      for (int u = 0; u < kMfmaPieces; ++u) {
-        if (wave * kMfmaPieces + u < MR) {
-          const double av = R[zo[u]] * R[yo[u]] * rmask[u];
+          for (int u = 0; u < kMfmaPieces; ++u) av[u] = R[zo[u]] * R[yo[u]] * rmask[u];
 #pragma unroll
-          for (int c = 0; c < NC; ++c) acc[u][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[c], acc[u][c], 0, 0, 0);
+          for (int u = 0; u < kMfmaPieces; ++u) {
+            if (all_pieces || wave * kMfmaPieces + u < MR) {
+#pragma unroll
+              for (int c = 0; c < NC; ++c)
+                if (!SL || c == s) acc[u][c] = M::mfma(av[u], bv[c], acc[u][c]);
+            }
+          }
+        } else {
+          // float64: one piece's operand at a time, which keeps the kernel within 128 VGPRs
+          // (reading all four first took 160 and lost a workgroup per compute unit)
+#pragma unroll
+          for (int u = 0; u < kMfmaPieces; ++u) {
+            if (all_pieces || wave * kMfmaPieces + u < MR) {
+              const A av = R[zo[u]] * R[yo[u]] * rmask[u];
+#pragma unroll
+              for (int c = 0; c < NC; ++c)
+                if (!SL || c == s) acc[u][c] = M::mfma(av, bv[c], acc[u][c]);
+            }
+          }
         }
       }
+    };
+    auto slices = [&](auto full) {
+      if constexpr (SL) {
+        groups(0, s_split[0], std::integral_constant<int, 0>(), full);
+        groups(s_split[0], nrec, std::integral_constant<int, 1>(), full);
+      } else {
+        groups(0, nrec, std::integral_constant<int, 0>(), full);
+      }
+    };
+    if constexpr (sizeof(A) == sizeof(float)) {
+      if (full_wave)
+        slices(std::true_type());
+      else
+        slices(std::false_type());
+    } else {
+      slices(std::false_type());  // one copy of the loop: a second one took 150+ VGPRs
     }
     __syncthreads();
   }
   double* blk = reinterpret_cast<double*>(smem_raw);  // S^3, over the coefficients and records
+  // column piece c (or slice 0) first; with slices, the columns only slice 1 reaches are zeroed
+  // and slice 1 is added after a barrier
 #pragma unroll
   for (int u = 0; u < kMfmaPieces; ++u) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
+    for (int c = 0; c < (SL ? 1 : NC); ++c) {
       const int x = c * 16 + lr;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int row = (wave * kMfmaPieces + u) * 16 + lk + 4 * q;
-        if (row < S * S && x < S) blk[row * S + x] = acc[u][c][q];
+        const int row = (wave * kMfmaPieces + u) * 16 + M::row(lk, q);
+        if (row < S * S && x < S) blk[row * S + x] = static_cast<double>(acc[u][c][q]);
+      }
+    }
+  }
+  if constexpr (SL) {
+    for (int i = t; i < S * S * (S - 16); i += blockDim.x) {
+      const int row = i / (S - 16);
+      blk[row * S + 16 + (i - row * (S - 16))] = 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kMfmaPieces; ++u) {
+      const int x = X1 + lr;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = (wave * kMfmaPieces + u) * 16 + M::row(lk, q);
+        if (row < S * S) blk[row * S + x] += static_cast<double>(acc[u][1][q]);
       }
     }
   }
@@ -505,8 +623,8 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
                                                 const double* __restrict__ vec_add) {
   constexpr int REC = 6 * P;  // values x, y, z then derivatives x, y, z (d/dg)
   constexpr int CS = coef_stride(D);
+  // dynamic LDS only (see k_spread_mfma)
   extern __shared__ unsigned char smem_raw[];
-  __shared__ double s_red[16];
   const int wgid = tile_order_block(xcd);
   const int gtile = tile_offset + wgid / parts;
   int p0, p1;
@@ -518,7 +636,8 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
   const global_ptr<T> grid = as_global(grid_override ? grid_override : static_cast<const T*>(sd.grid_b));
   const double inv_hx = sd.inv_h, inv_hy = sd.inv_hy, inv_hz = sd.inv_hz, self_coef = sd.self_coef;
   const int nslots = blockDim.x / kLanesPerParticle;
-  double* recs = reinterpret_cast<double*>(smem_raw);              // nslots * REC
+  double* s_red = reinterpret_cast<double*>(smem_raw);             // 16: the energy's per-wave sums
+  double* recs = s_red + 16;                                       // nslots * REC
   double* lcoef = recs + nslots * REC;                             // P * CS
   T* tb = reinterpret_cast<T*>(lcoef + P * CS);
   const int tile = gtile - sd.tile_base;
@@ -670,13 +789,24 @@ hipError_t spread_impl(const DevPlan& d, const PGroup& g, hipStream_t st) {
                        static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.tile_start, d.sub_log2, d.nsys,
                        d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin, g.parts, g.xcd_spread);
   };
-  if (g.mfma && g.col_tile == 4)
-    cols(k_spread_mfma<T, P, D, 4>, mfma_threads<P, 4>());
-  else if (g.mfma && g.col_tile == 6)
-    cols(k_spread_mfma<T, P, D, 6>, mfma_threads<P, 6>());
-  else if (g.mfma && g.col_tile == 8)
-    cols(k_spread_mfma<T, P, D, 8>, mfma_threads<P, 8>());
-  else if (g.col_tile == 4)
+  if (g.mfma) {
+    auto mf = [&](auto acc) {
+      using A = decltype(acc);
+      if (g.col_tile == 4)
+        cols(k_spread_mfma<T, P, D, 4, A>, mfma_threads<P, 4>());
+      else if (g.col_tile == 6)
+        cols(k_spread_mfma<T, P, D, 6, A>, mfma_threads<P, 6>());
+      else
+        cols(k_spread_mfma<T, P, D, 8, A>, mfma_threads<P, 8>());
+    };
+    if constexpr (std::is_same_v<T, float>) {
+      if (g.acc32) {
+        mf(float());
+        return hipGetLastError();
+      }
+    }
+    mf(double());
+  } else if (g.col_tile == 4)
     cols(k_spread_cols<T, P, D, 4>, col_threads<P, 4>());
   else if (g.col_tile == 6)
     cols(k_spread_cols<T, P, D, 6>, col_threads<P, 6>());
@@ -705,11 +835,23 @@ hipError_t gather_impl(const DevPlan& d, const PGroup& g, const void* grid, void
 // Raises the dynamic-LDS limit of the particle kernels of one group where needed, and turns on
 // the XCD-aware tile order for a kernel whose whole grid is resident at once.
 template <class T, int P, int D>
+const void* mfma_fn(const PGroup& g) {
+  auto pick = [&](auto acc) -> const void* {
+    using A = decltype(acc);
+    return g.col_tile == 4   ? reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 4, A>)
+           : g.col_tile == 6 ? reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 6, A>)
+                             : reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 8, A>);
+  };
+  if constexpr (std::is_same_v<T, float>) {
+    if (g.acc32) return pick(float());
+  }
+  return pick(double());
+}
+
+template <class T, int P, int D>
 hipError_t prepare_impl(PGroup& g) {
   const void* spread_fn =
-      g.mfma && g.col_tile == 4   ? reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 4>)
-      : g.mfma && g.col_tile == 6 ? reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 6>)
-      : g.mfma && g.col_tile == 8 ? reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 8>)
+      g.mfma                      ? mfma_fn<T, P, D>(g)
       : g.col_tile == 4           ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 4>)
       : g.col_tile == 6           ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 6>)
       : g.col_tile == 8           ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 8>)

@@ -119,10 +119,27 @@ SPREAD_KERNEL_CASES = [
     ("clustered_m24_tile8", lambda: W.clustered(800, seed=23, L=0.9), 1e-6, dict(m=24), 8),
     ("high_precision_m48_tile8", lambda: W.uniform_pm1(500, seed=24), 1e-10, dict(m=48), 8),
     ("uniform_m30_tile6", lambda: W.uniform_pm1(600, seed=25, L=1.3), 1e-6, dict(m=30), 6),
+    # a halo block wider than the grid (it wraps onto itself)
+    ("uniform_m16_tile8", lambda: W.uniform_pm1(900, seed=28), 1e-6, dict(m=16), 8),
+    # ragged tiles (5 tiles per dimension), several batches per tile, both column slices
+    ("paper_m40_tile8", lambda: W.paper_default(6000, seed=30, L=1.1), 1e-6, dict(m=40), 8),
+    # P = 10 .. 13 at tile edge 8 take the column slices; P = 12 here, and P = 13 at m = 64
+    ("uniform_m64_tile8", lambda: W.uniform_pm1(9000, seed=31), 1e-6, dict(m=64), 8),
 ]
 
 
-SPREAD_KERNELS = {"mfma": ("1", "1"), "columns": ("1", "0"), "lds": ("0", "0")}
+# spreading kernels by their launch switches (PSWFE_SPREAD_COLUMNS, PSWFE_SPREAD_MFMA,
+# PSWFE_SPREAD_ACC): matrix cores with float64 or float32 arithmetic (tile edges 4, 6, 8; column
+# slices where they apply), register columns, LDS atomics
+SPREAD_KERNELS = {"mfma": ("1", "1", "fp64"), "mfma_acc32": ("1", "1", "fp32"),
+                  "columns": ("1", "0", "fp64"), "lds": ("0", "0", "fp64")}
+
+
+def use_spread_kernel(monkeypatch, kernel):
+    columns, mfma, acc = SPREAD_KERNELS[kernel]
+    monkeypatch.setenv("PSWFE_SPREAD_COLUMNS", columns)
+    monkeypatch.setenv("PSWFE_SPREAD_MFMA", mfma)
+    monkeypatch.setenv("PSWFE_SPREAD_ACC", acc)
 
 
 @pytest.mark.parametrize("kernel", list(SPREAD_KERNELS))
@@ -135,9 +152,9 @@ def test_every_spreading_kernel_matches_oracle(case, prec, kernel, monkeypatch):
     _, gen, eps, kw, tile = case
     if prec == "fp32" and eps < 1e-6:
         pytest.skip("fp32 path is for eps >= 1e-6")
-    columns, mfma = SPREAD_KERNELS[kernel]
-    monkeypatch.setenv("PSWFE_SPREAD_COLUMNS", columns)
-    monkeypatch.setenv("PSWFE_SPREAD_MFMA", mfma)
+    if kernel == "mfma_acc32" and prec == "fp64":
+        pytest.skip("float32 accumulation is for float32 plans")
+    use_spread_kernel(monkeypatch, kernel)
     x, q, L, kw = _sys(gen, eps, kw, prec)
     c, o = both_params(eps, L, **kw)
     plan = pw.Plan(c, prec, n_max=len(q), tile=tile)
@@ -182,6 +199,7 @@ def test_xcd_tile_order_gives_the_same_results(prec, monkeypatch):
 
 DENSE_CASES = [
     # (name, generator, eps, params kwargs, tile, spreading kernel): many particles per tile, few tiles
+    ("dense_m24_tile8_acc32", lambda: W.uniform_pm1(24000, seed=26), 1e-6, dict(m=24), 8, "mfma_acc32"),
     ("dense_m24_tile8_mfma", lambda: W.uniform_pm1(24000, seed=26), 1e-6, dict(m=24), 8, "mfma"),
     ("dense_m24_tile8_cols", lambda: W.uniform_pm1(24000, seed=26), 1e-6, dict(m=24), 8, "columns"),
     ("dense_m20_tile5_lds", lambda: W.paper_default(9000, seed=27, L=1.1), 1e-6, dict(m=20), 5, "lds"),
@@ -196,9 +214,7 @@ def test_dense_tiles_shared_by_workgroups(case, prec, parts, monkeypatch):
     particles into its own partial block, or interpolating its slice): the same results as the
     oracle, whatever the number of parts (automatic: 1024 / tiles, here 2 to 16)."""
     _, gen, eps, kw, tile, kernel = case
-    columns, mfma = SPREAD_KERNELS[kernel]
-    monkeypatch.setenv("PSWFE_SPREAD_COLUMNS", columns)
-    monkeypatch.setenv("PSWFE_SPREAD_MFMA", mfma)
+    use_spread_kernel(monkeypatch, kernel)
     if parts != "auto":
         monkeypatch.setenv("PSWFE_TILE_PARTS", parts)
     x, q, L, kw = _sys(gen, eps, kw, prec)
