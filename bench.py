@@ -30,6 +30,15 @@ if ROOT not in sys.path:
 METRIC = "long-range particles/s (φ+forces) at ε=1e-6 FP32 vs FP64; % HBM roofline"
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6    # float64 vector FMA (256 CU x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz); the float64 MFMA peak is the same
+PEAK_FP32_TFLOPS = 157.3   # float32 vector FMA (256 CU x 4 SIMD x 64 lanes x 2 flops x 2.4 GHz) and dense float32 MFMA
+# plan precisions timed: float32 storage with float32 arithmetic in spreading and interpolation
+# (the headline float32 path), float32 storage with float64 arithmetic, float64
+PRECISIONS = ("fp32_arith", "fp32", "fp64")
+
+
+def peak_tflops(prec: str) -> float:
+    """Peak of the arithmetic the particle kernels of a plan precision run in."""
+    return PEAK_FP32_TFLOPS if prec == "fp32_arith" else PEAK_FP64_TFLOPS
 STAGES = ["bin", "spread", "fft_x", "fft_y", "fft_z_scale", "ifft_y", "ifft_x", "gather"]
 
 
@@ -122,18 +131,20 @@ def measured_lds(stage: str, prec_ctype: str, workload: str = "water_box_n30000"
 
 
 def kernel_rooflines(stage_ms: dict, n: int, m: int, P: int, deg: int, elem: int, prec_ctype: str,
-                     workload: str = "water_box_n30000"):
-    """Per stage: event-timed duration, the algorithmic work and its roofline fraction, the HBM
-    traffic the counters measured (GB/s against 8 TB/s) and the LDS bank-conflict share of the
-    compute units' cycles (2.4 GHz x 256 CUs)."""
+                     workload: str = "water_box_n30000", prec: str = "fp32"):
+    """Per stage: event-timed duration, the algorithmic work and its roofline fraction (against the
+    peak of the arithmetic the kernel runs in), the HBM traffic the counters measured (GB/s
+    against 8 TB/s) and the LDS bank-conflict share of the compute units' cycles (2.4 GHz x 256
+    CUs)."""
     out = {}
     for st in STAGES:
         us = stage_ms[st] * 1e3
         kind, work = stage_work(st, n, m, P, deg, elem)
         row = {"us": us}
         if kind in ("alu", "mfma"):
-            peak = PEAK_FP64_TFLOPS
-            row.update({"bound": kind, "flops": work, "tflops": work / us * 1e-6, "frac_fp64_peak": work / us * 1e-6 / peak})
+            peak = peak_tflops(prec)
+            row.update({"bound": kind, "flops": work, "tflops": work / us * 1e-6, "peak_tflops": peak,
+                        "frac_peak": work / us * 1e-6 / peak})
         else:
             row.update({"bound": "hbm", "algorithmic_bytes": work, "gbs": work / us * 1e-3,
                         "frac_hbm_peak": work / us * 1e-3 / PEAK_HBM_GBS})
@@ -373,7 +384,8 @@ def time_precisions(x, q, params_of, steps: int, warmup: int, with_total: bool, 
     dev = torch.device("cuda:0")
     n = len(q)
     out = {}
-    for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+    for prec in PRECISIONS:
+        dt = torch.float64 if prec == "fp64" else torch.float32
         X = torch.as_tensor(x, dtype=dt, device=dev).contiguous()
         Q = torch.as_tensor(q, dtype=dt, device=dev).contiguous()
         torch.cuda.synchronize()
@@ -413,7 +425,7 @@ def time_precisions(x, q, params_of, steps: int, warmup: int, with_total: bool, 
         p = params_of[prec]
         r = dict(elapsed=elapsed, dom=dom, dom_ms=dom_ms_total / max(dom_calls, 1), stage_ms=stage_ms, plan_s=plan_s,
                  phi=phi.double().cpu().numpy(), F=F.double().cpu().numpy(), E=float(E.cpu()[0]),
-                 deg=pw.host_tables(p, prec)["deg"], elem=4 if prec == "fp32" else 8, m=p.m, P=p.P)
+                 deg=pw.host_tables(p, prec)["deg"], elem=8 if prec == "fp64" else 4, m=p.m, P=p.P)
         if with_total:
             def step_total():
                 plan.compute(X, Q, phi=phi, force=F, energy=E, total=True)
@@ -439,26 +451,27 @@ def time_precisions(x, q, params_of, steps: int, warmup: int, with_total: bool, 
     return out
 
 
-def leg_summary(r, n, steps, workload, prec_ctype):
+def leg_summary(r, n, steps, workload, prec):
     """A precision's figures for the JSON line."""
     ms = r["elapsed"] / steps * 1e3
+    ctype = "double" if prec == "fp64" else "float"
     return {"value": n * steps / r["elapsed"], "unit": "particles/s", "ms_per_step": ms,
             "ms_per_step_excl_bin": ms - r["stage_ms"]["bin"],
             "call_us_event_timed": r["stage_ms"]["all"] * 1e3, "plan_create_s": r["plan_s"], "m": r["m"], "P": r["P"],
             "stage_us": {k: v * 1e3 for k, v in r["stage_ms"].items() if k != "all"},
-            "kernels": kernel_rooflines(r["stage_ms"], n, r["m"], r["P"], r["deg"], r["elem"], prec_ctype, workload)}
+            "kernels": kernel_rooflines(r["stage_ms"], n, r["m"], r["P"], r["deg"], r["elem"], ctype, workload, prec)}
 
 
-def roofline_of(r, n, workload):
+def roofline_of(r, n, workload, prec):
     kind, work = stage_work(r["dom"], n, r["m"], r["P"], r["deg"], r["elem"])
     secs = r["dom_ms"] * 1e-3
     if kind in ("alu", "mfma"):
-        # the particle kernels compute window values, products and sums in float64 in both
-        # precisions; the spread's sums run on the matrix cores, whose float64 peak on MI355X
-        # equals the float64 vector rate
+        # the particle kernels' arithmetic: float32 on the float32 arithmetic path (the spread on
+        # the float32 matrix cores), float64 otherwise (the float64 matrix-core peak on MI355X
+        # equals the float64 vector rate)
+        peak = peak_tflops(prec)
         achieved = work / secs / 1e12
-        roof = {"bound": kind, "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS}
+        roof = {"bound": kind, "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak}
     else:
         achieved = work / secs / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -515,8 +528,9 @@ def main():
     x = x.astype(np.float32).astype(np.float64)
     q = q.astype(np.float32).astype(np.float64)
     n = len(q)
+    params_of["fp32_arith"] = params_of["fp32"]
     res = time_precisions(x, q, params_of, args.steps, args.warmup, with_total=water, workload=args.workload)
-    r, r64 = res["fp32"], res["fp64"]
+    r, rmix, r64 = res["fp32_arith"], res["fp32"], res["fp64"]
     p32, p64 = params_of["fp32"], params_of["fp64"]
     if water:
         config = {"workload": "water_box_n30000", "n": n, "L_nm": L, "eps": 1e-6, "tol_mode": "abs", "m": p32.m,
@@ -524,35 +538,46 @@ def main():
     else:
         config = {"workload": "uniform_n1e6", "n": n, "L": L, "eps": 1e-6, "tol_mode": "rel", "m": p32.m, "P": p32.P,
                   "rc": p32.rc, "fp64": {"eps": 1e-10, "m": p64.m, "P": p64.P}, "parallelism": "single GPU"}
-    leg32 = leg_summary(r, n, args.steps, args.workload, "float")
-    leg64 = leg_summary(r64, n, args.steps, args.workload, "double")
+    leg32 = leg_summary(r, n, args.steps, args.workload, "fp32_arith")
+    legmix = leg_summary(rmix, n, args.steps, args.workload, "fp32")
+    leg64 = leg_summary(r64, n, args.steps, args.workload, "fp64")
+    keys = ("value", "unit", "ms_per_step", "ms_per_step_excl_bin", "stage_us", "plan_create_s", "m", "P")
+
+    def diff(a, b):
+        return {"phi_rel_l2": float(np.linalg.norm(a["phi"] - b["phi"]) / np.linalg.norm(b["phi"])),
+                "phi_abs_rms": float(np.sqrt(np.mean((a["phi"] - b["phi"]) ** 2))),
+                "force_rel_l2": float(np.linalg.norm(a["F"] - b["F"]) / np.linalg.norm(b["F"])),
+                "energy_rel": abs(a["E"] - b["E"]) / abs(b["E"])}
+
     out = {
         "metric": METRIC, "value": leg32["value"], "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": leg32["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": config,
-        "roofline": roofline_of(r, n, args.workload),
+        "roofline": roofline_of(r, n, args.workload, "fp32_arith"),
+        "precision_note": "headline: float32 inputs, grids and outputs with float32 window values, products and sums in "
+                          "spreading (float32 matrix cores) and interpolation (plan precision fp32_arith); fp32_mixed: "
+                          "float32 storage with float64 arithmetic; fp64: float64 throughout",
         "ms_per_step_excl_bin": leg32["ms_per_step_excl_bin"],
-        "plan_create_s": {"fp32": r["plan_s"], "fp64": r64["plan_s"]},
+        "plan_create_s": {"fp32_arith": r["plan_s"], "fp32_mixed": rmix["plan_s"], "fp64": r64["plan_s"]},
         "stage_us_fp32": leg32["stage_us"],
-        "fp64": {k: leg64[k] for k in ("value", "unit", "ms_per_step", "ms_per_step_excl_bin", "stage_us",
-                                       "plan_create_s", "m", "P")},
+        "fp32_mixed": {k: legmix[k] for k in keys},
+        "fp64": {k: leg64[k] for k in keys},
         "kernels_fp32": leg32["kernels"],
+        "kernels_fp32_mixed": legmix["kernels"],
         "kernels_fp64": leg64["kernels"],
+        "fp32_vs_fp64": diff(r, r64),
+        "fp32_mixed_vs_fp64": diff(rmix, r64),
     }
     if water:
-        phi_diff = float(np.linalg.norm(r["phi"] - r64["phi"]) / np.linalg.norm(r64["phi"]))
-        phi_abs = float(np.sqrt(np.mean((r["phi"] - r64["phi"]) ** 2)))
-        F_diff = float(np.linalg.norm(r["F"] - r64["F"]) / np.linalg.norm(r64["F"]))
-        out["fp32_vs_fp64"] = {"phi_rel_l2": phi_diff, "phi_abs_rms": phi_abs, "force_rel_l2": F_diff,
-                               "energy_rel": abs(r["E"] - r64["E"]) / abs(r64["E"])}
         out["total_ewald"] = {"note": "phi_far + phi_local + phi_self (real-space residual on the GPU), same workload; "
                                       "local_overlapped_us: the residual's span on its own stream, which it shares "
                                       "with the long-range kernels running at the same time",
-                              "fp32": r["total"], "fp64": r64["total"]}
+                              "fp32": r["total"], "fp32_mixed": rmix["total"], "fp64": r64["total"]}
         if not args.no_large:
             # the n = 1e6 system, both precisions, as extra keys (the headline stays the water box)
             xl, ql, Ll, pl = large_inputs()
+            pl["fp32_arith"] = pl["fp32"]
             xl = xl.astype(np.float32).astype(np.float64)
             ql = ql.astype(np.float32).astype(np.float64)
             ksteps = max(10, min(args.steps, 50))
@@ -562,9 +587,12 @@ def main():
                 "note": "n = 1e6 uniform charges U[-1,1] minus the mean, L = 1; float32 at eps = 1e-6 (relative) on "
                         "128^3, float64 at eps = 1e-10 with the same r_c; phi + forces + energy",
                 "steps": ksteps, "rc": pl["fp32"].rc,
-                "fp32": leg_summary(resl["fp32"], len(ql), ksteps, "uniform_n1e6", "float"),
-                "fp64": leg_summary(resl["fp64"], len(ql), ksteps, "uniform_n1e6", "double"),
-                "roofline_fp32": roofline_of(resl["fp32"], len(ql), "uniform_n1e6"),
+                "fp32": leg_summary(resl["fp32_arith"], len(ql), ksteps, "uniform_n1e6", "fp32_arith"),
+                "fp32_mixed": leg_summary(resl["fp32"], len(ql), ksteps, "uniform_n1e6", "fp32"),
+                "fp64": leg_summary(resl["fp64"], len(ql), ksteps, "uniform_n1e6", "fp64"),
+                "roofline_fp32": roofline_of(resl["fp32_arith"], len(ql), "uniform_n1e6", "fp32_arith"),
+                "fp32_mixed_vs_fp32_rel_l2_phi": float(np.linalg.norm(resl["fp32_arith"]["phi"] - resl["fp32"]["phi"]) /
+                                                        np.linalg.norm(resl["fp32"]["phi"])),
             }
             del xl, ql
     if not args.no_batched:

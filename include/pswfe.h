@@ -29,8 +29,8 @@
  *    instead of being moved silently into the box, as a non-finite charge does; and a system
  *    whose charges do not sum to zero carries the uniform neutralising background implied by
  *    dropping the k = 0 mode (Sec. 3.1.2).
- *  - Floating-point arrays are in the plan's precision: float for PSWFE_FP32, double for
- *    PSWFE_FP64. The energy is always a double.
+ *  - Floating-point arrays are in the plan's precision: float for PSWFE_FP32 and
+ *    PSWFE_FP32_ARITH, double for PSWFE_FP64. The energy is always a double.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream). Every compute
  *    entry point only enqueues work: it performs no allocation and no host synchronisation
  *    (except with PSWFE_CHECK_INPUT), so it may be captured into a HIP graph. Calls on one plan must not overlap in time
@@ -63,7 +63,13 @@ typedef enum {
   PSWFE_TOL_ABS = 1       /* c_s = W0(2 (B_s/eps)^2)/2: absolute RMS target (eq. cs_dimless) */
 } pswfe_tolmode;
 
-typedef enum { PSWFE_FP32 = 0, PSWFE_FP64 = 1 } pswfe_prec;
+/* Plan precision. PSWFE_FP32: float32 inputs, grids and outputs, with window values, products and
+ * per-tile sums in float64 (error about 1e-8 relative from the arithmetic). PSWFE_FP32_ARITH: the
+ * same float32 storage, with window values, products and sums in float32 in spreading (on the
+ * float32 matrix cores) and interpolation; tiles are still added into a float64 grid, and the self
+ * term and energy are float64 (for eps >= 1e-6: about 3e-7 relative on systems of neutral
+ * molecules, where grid values cancel). PSWFE_FP64: float64 throughout. */
+typedef enum { PSWFE_FP32 = 0, PSWFE_FP64 = 1, PSWFE_FP32_ARITH = 2 } pswfe_prec;
 
 /* Flags of the *_ex compute entry points (bitwise or). */
 typedef enum {

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libpswfe.so")
 
 OK, E_ARG, E_EPS_RANGE, E_GRID, E_ALLOC, E_HIP, E_CAPACITY, E_PREC, E_NONNEUTRAL, E_NONFINITE = range(10)
 TOL_REL, TOL_ABS = 0, 1
-FP32, FP64 = 0, 1
+FP32, FP64, FP32_ARITH = 0, 1, 2
+PRECISIONS = {"fp32": FP32, "fp64": FP64, "fp32_arith": FP32_ARITH}
 VEC_GRAD, TOTAL, CHECK_INPUT = 1, 2, 4
 
 
@@ -163,7 +164,7 @@ def host_pswf(c: float, x: float):
 def host_tables(params: CParams, prec: int | str = FP32):
     """The plan's float64 host tables: dict(tm, w, coef (P, deg+1), deg, fit_err, fit_err_deriv, self_coef)."""
     import numpy as np
-    prec = {"fp32": FP32, "fp64": FP64}.get(prec, prec)
+    prec = PRECISIONS.get(prec, prec)
     m, P = params.m, params.P
     tm = np.zeros(3 * (m // 2) ** 2 + 1)
     w = np.zeros(m // 2 + 1)
@@ -229,8 +230,8 @@ def _stream_ptr(stream):
 
 
 def _prec(prec):
-    p = {"fp32": FP32, "fp64": FP64}.get(prec, prec)
-    if p not in (FP32, FP64):
+    p = PRECISIONS.get(prec, prec)
+    if p not in (FP32, FP64, FP32_ARITH):
         raise ValueError(f"unknown precision {prec!r}")
     return p
 
@@ -241,7 +242,7 @@ class _PlanBase:
     def _init_common(self, prec):
         import torch
         self.prec = _prec(prec)
-        self.dtype = torch.float32 if self.prec == FP32 else torch.float64
+        self.dtype = torch.float64 if self.prec == FP64 else torch.float32
         self._h = ctypes.c_void_p()
 
     def system(self, s: int):

@@ -103,8 +103,9 @@ size_t coef_lds_bytes(int P, int D) { return sizeof(double) * P * pswfe::coef_st
 size_t spread_lds_bytes(int S, int P, int D, int threads) {
   return sizeof(double) * (static_cast<size_t>(S) * S * S + (threads / 16) * 3 * P) + coef_lds_bytes(P, D);
 }
-size_t gather_lds_bytes(int S, int P, int D, int elem, int threads) {
-  return static_cast<size_t>(elem) * S * S * S + sizeof(double) * (16 + (threads / 16) * 6 * P) + coef_lds_bytes(P, D);
+size_t gather_lds_bytes(int S, int P, int D, int elem, int threads, size_t gbytes = sizeof(double)) {
+  return static_cast<size_t>(elem) * S * S * S + sizeof(double) * 16 + gbytes * (threads / 16) * 6 * P +
+         coef_lds_bytes(P, D);
 }
 // LDS tile edge of interpolation and LDS-atomic spreading: the halo block B + P - 1 (supports
 // start at o in [0, B-1]), made odd so that the 16 lanes of a particle, reading or adding lines
@@ -267,6 +268,9 @@ struct Placement {
 // particles per call; otherwise a batch with counts[s] particles in system s.
 pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, const int64_t* counts,
                         const int32_t* tiles, pswfe_plan** out, Placement place = Placement()) {
+  // float32 arithmetic path: float32 storage, as PSWFE_FP32, with float32 particle arithmetic
+  const bool arith32 = prec == PSWFE_FP32_ARITH;
+  if (arith32) prec = PSWFE_FP32;
   const int nsys = static_cast<int>(ps.size());
   const int elem = prec == PSWFE_FP32 ? 4 : 8;
   const size_t celem = 2 * static_cast<size_t>(elem);
@@ -491,22 +495,20 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   // turns it off)
   bool mfma_ok = true;
   if (const char* env = std::getenv("PSWFE_SPREAD_MFMA")) mfma_ok = std::atoi(env) != 0;
-  // float32 arithmetic in the matrix-core spreading of float32 plans (PSWFE_SPREAD_ACC=fp32);
-  // float64 window values, products and tile sums otherwise
-  bool acc32 = false;
-  if (const char* env = std::getenv("PSWFE_SPREAD_ACC")) acc32 = std::strcmp(env, "fp32") == 0;
   for (pswfe::PGroup& g : d.groups) {
     const int S = static_cast<int>(g.lds_spread), P = g.P, D = g.D;
     g.mfma = g.col_tile && mfma_ok ? 1 : 0;
-    g.acc32 = g.mfma && acc32 && prec == PSWFE_FP32 ? 1 : 0;
+    // float32 window values, products and sums in spreading (matrix cores) and interpolation
+    g.acc32 = arith32 ? 1 : 0;
     g.spread_threads = g.mfma       ? pswfe::mfma_threads_host(P, g.col_tile)
                        : g.col_tile ? pswfe::col_threads_host(P, g.col_tile)
                                     : particle_threads(P, [&](int t) { return spread_lds_bytes(S, P, D, t); }, true);
-    g.gather_threads = particle_threads(P, [&](int t) { return gather_lds_bytes(S, P, D, elem, t); }, false);
+    const size_t gbytes = g.acc32 ? sizeof(float) : sizeof(double);
+    g.gather_threads = particle_threads(P, [&](int t) { return gather_lds_bytes(S, P, D, elem, t, gbytes); }, false);
     g.lds_spread = g.mfma       ? pswfe::mfma_lds_bytes(P, D, g.col_tile, g.acc32 ? sizeof(float) : sizeof(double))
                    : g.col_tile ? pswfe::col_lds_bytes(P, D, g.col_tile)
                                 : spread_lds_bytes(S, P, D, g.spread_threads);
-    g.lds_gather = gather_lds_bytes(S, P, D, elem, g.gather_threads);
+    g.lds_gather = gather_lds_bytes(S, P, D, elem, g.gather_threads, gbytes);
   }
   d.total_tiles = tile_prefix[nsys];
   d.total_xblk = xblk_prefix[nsys];
@@ -834,12 +836,12 @@ pswfe_status pswfe_host_pswf(double c, double x, double* psi, double* dpsi, doub
 pswfe_status pswfe_host_tables(const pswfe_params* pp, int32_t prec, double* tm, int64_t tm_len, double* w,
                                int64_t w_len, double* coef, int64_t coef_len, double* info) {
   if (!pp) return PSWFE_E_ARG;
-  if (prec != PSWFE_FP32 && prec != PSWFE_FP64) return PSWFE_E_PREC;
+  if (prec != PSWFE_FP32 && prec != PSWFE_FP64 && prec != PSWFE_FP32_ARITH) return PSWFE_E_PREC;
   pswfe::Params p{};
   const pswfe_status st = params_from_c(pp, &p);
   if (st != PSWFE_OK) return st;
   pswfe::Tables t;
-  pswfe::build_tables(p, 0, fit_tolerance(p.eps, prec), &t);
+  pswfe::build_tables(p, 0, fit_tolerance(p.eps, prec == PSWFE_FP32_ARITH ? PSWFE_FP32 : prec), &t);
   if ((tm && tm_len < static_cast<int64_t>(t.tm.size())) || (w && w_len < static_cast<int64_t>(t.w.size())) ||
       (coef && coef_len < static_cast<int64_t>(t.coef.size())))
     return PSWFE_E_ARG;
@@ -884,7 +886,7 @@ pswfe_status pswfe_plan_create_tiled(const pswfe_params* pp, int32_t prec, int64
   if (!out) return PSWFE_E_ARG;
   *out = nullptr;
   if (!pp || n_max < 0 || n_max > (int64_t(1) << 31) - 1) return PSWFE_E_ARG;
-  if (prec != PSWFE_FP32 && prec != PSWFE_FP64) return PSWFE_E_PREC;
+  if (prec != PSWFE_FP32 && prec != PSWFE_FP64 && prec != PSWFE_FP32_ARITH) return PSWFE_E_PREC;
   std::vector<pswfe::Params> ps(1);
   const pswfe_status st = params_from_c(pp, &ps[0]);
   if (st != PSWFE_OK) return st;
@@ -896,7 +898,7 @@ pswfe_status pswfe_batch_plan_create(int32_t nsys, const pswfe_params* params, c
   if (!out) return PSWFE_E_ARG;
   *out = nullptr;
   if (nsys < 1 || nsys > (1 << 20) || !params || !counts) return PSWFE_E_ARG;
-  if (prec != PSWFE_FP32 && prec != PSWFE_FP64) return PSWFE_E_PREC;
+  if (prec != PSWFE_FP32 && prec != PSWFE_FP64 && prec != PSWFE_FP32_ARITH) return PSWFE_E_PREC;
   std::vector<pswfe::Params> ps(nsys);
   int64_t total = 0;
   for (int s = 0; s < nsys; ++s) {
@@ -1158,7 +1160,7 @@ hipError_t noalloc_scratch(int device, unsigned char** out) {
 pswfe_status pswfe_compute_noalloc(const pswfe_params* pp, int32_t prec, int64_t n, const void* pos, const void* q,
                                    void* phi, void* force, double* energy, void* stream) {
   if (!pp || n < 0 || n > (int64_t(1) << 31) - 1 || (n > 0 && (!pos || !q))) return PSWFE_E_ARG;
-  if (prec != PSWFE_FP32 && prec != PSWFE_FP64) return PSWFE_E_PREC;
+  if (prec != PSWFE_FP32 && prec != PSWFE_FP64 && prec != PSWFE_FP32_ARITH) return PSWFE_E_PREC;
   std::vector<pswfe::Params> ps(1);
   {
     const pswfe_status st = params_from_c(pp, &ps[0]);

@@ -610,8 +610,9 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
 // nested sums: each lane runs the x-sums of its lines for the value and the x-derivative,
 // weights them with the y/z windows and derivatives, and the 16 lanes of a particle reduce.
 // grid_override (single system) replaces the system's grid_b; energy holds one double per
-// system.
-template <class T, int P, int D>
+// system. G is the arithmetic of the window values and sums: float64, or float32 for the float32
+// arithmetic path (the potential, self term and energy are then still formed in float64).
+template <class T, int P, int D, class G>
 __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const typename Vec4<T>::type* __restrict__ sorted,
                                                 const int* __restrict__ cells, const int* __restrict__ perm,
                                                 const int* __restrict__ tile_start, int sub_log2, int nsys,
@@ -637,9 +638,9 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
   const double inv_hx = sd.inv_h, inv_hy = sd.inv_hy, inv_hz = sd.inv_hz, self_coef = sd.self_coef;
   const int nslots = blockDim.x / kLanesPerParticle;
   double* s_red = reinterpret_cast<double*>(smem_raw);             // 16: the energy's per-wave sums
-  double* recs = s_red + 16;                                       // nslots * REC
-  double* lcoef = recs + nslots * REC;                             // P * CS
-  T* tb = reinterpret_cast<T*>(lcoef + P * CS);
+  double* lcoef = s_red + 16;                                      // P * CS
+  G* recs = reinterpret_cast<G*>(lcoef + P * CS);                  // nslots * REC
+  T* tb = reinterpret_cast<T*>(recs + nslots * REC);
   const int tile = gtile - sd.tile_base;
   const int tx = tile % Tn, ty = (tile / Tn) % sd.Tny, tz = tile / (Tn * sd.Tny);
   const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
@@ -656,7 +657,7 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
   const int lane = threadIdx.x & 63;
   const int slot = threadIdx.x >> 4;
   const int li = lane & (kLanesPerParticle - 1);
-  double* rec = recs + slot * REC;
+  G* rec = recs + slot * REC;
   const int nt = p1 - p0;
   double esum = 0.0;
   auto r_next = sorted[min(p0 + slot, p1 - 1)];
@@ -696,17 +697,17 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
         v1 = fma(v1, g[1], c[k]);
         v2 = fma(v2, g[2], c[k]);
       }
-      rec[j] = v0;
-      rec[P + j] = v1;
-      rec[2 * P + j] = v2;
-      rec[3 * P + j] = d0;
-      rec[4 * P + j] = d1;
-      rec[5 * P + j] = d2;
+      rec[j] = static_cast<G>(v0);
+      rec[P + j] = static_cast<G>(v1);
+      rec[2 * P + j] = static_cast<G>(v2);
+      rec[3 * P + j] = static_cast<G>(d0);
+      rec[4 * P + j] = static_cast<G>(d1);
+      rec[5 * P + j] = static_cast<G>(d2);
     }
     wave_lds_sync();
-    double ph = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    G ph = 0, gx = 0, gy = 0, gz = 0;
     if (active) {
-      double wx[P], dx[P];
+      G wx[P], dx[P];
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         wx[j] = rec[j];
@@ -716,23 +717,23 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
       for (int e = li; e < P * P; e += kLanesPerParticle) {
         const int jz = e / P, jy = e - jz * P;
         const T* row = tb + ((o[2] + jz) * S + (o[1] + jy)) * S + o[0];
-        double sx0 = 0.0, sx1 = 0.0, sd0 = 0.0, sd1 = 0.0;
+        G sx0 = 0, sx1 = 0, sd0 = 0, sd1 = 0;
 #pragma unroll
         for (int jx = 0; jx + 1 < P; jx += 2) {
-          const double b0 = static_cast<double>(row[jx]), b1 = static_cast<double>(row[jx + 1]);
+          const G b0 = static_cast<G>(row[jx]), b1 = static_cast<G>(row[jx + 1]);
           sx0 = fma(b0, wx[jx], sx0);
           sd0 = fma(b0, dx[jx], sd0);
           sx1 = fma(b1, wx[jx + 1], sx1);
           sd1 = fma(b1, dx[jx + 1], sd1);
         }
         if constexpr (P % 2 == 1) {
-          const double b = static_cast<double>(row[P - 1]);
+          const G b = static_cast<G>(row[P - 1]);
           sx0 = fma(b, wx[P - 1], sx0);
           sd0 = fma(b, dx[P - 1], sd0);
         }
-        const double sx = sx0 + sx1, sdx = sd0 + sd1;
-        const double wy = rec[P + jy], dy = rec[4 * P + jy], wz = rec[2 * P + jz], dz = rec[5 * P + jz];
-        const double wyz = wy * wz;
+        const G sx = sx0 + sx1, sdx = sd0 + sd1;
+        const G wy = rec[P + jy], dy = rec[4 * P + jy], wz = rec[2 * P + jz], dz = rec[5 * P + jz];
+        const G wyz = wy * wz;
         ph = fma(sx, wyz, ph);
         gx = fma(sdx, wyz, gx);
         gy = fma(sx, dy * wz, gy);
@@ -748,14 +749,15 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
     }
     if (active && li == 0) {
       const double qd = static_cast<double>(r.w);
-      if (qd != qd) ph = gx = gy = gz = qd;  // binning marks a non-finite position with a NaN charge
-      double phd = ph;
+      if (qd != qd) ph = gx = gy = gz = static_cast<G>(qd);  // binning marks a non-finite position with a NaN charge
+      double phd = static_cast<double>(ph);
       if (add_self) phd -= self_coef * qd;
       if (phi_add) phd += phi_add[idx];  // the real-space residual, computed alongside (float64)
       if (phi) phi[idx] = static_cast<T>(phd);
       if (vec) {
         const double sc = vec_mode == 0 ? -qd : 1.0;  // d/dx_d = (1 / h_d) d/dg_d
-        double v0 = sc * inv_hx * gx, v1 = sc * inv_hy * gy, v2 = sc * inv_hz * gz;
+        double v0 = sc * inv_hx * static_cast<double>(gx), v1 = sc * inv_hy * static_cast<double>(gy),
+               v2 = sc * inv_hz * static_cast<double>(gz);
         if (vec_add) {
           v0 += vec_add[3 * idx + 0];
           v1 += vec_add[3 * idx + 1];
@@ -824,11 +826,20 @@ template <class T, int P, int D>
 hipError_t gather_impl(const DevPlan& d, const PGroup& g, const void* grid, void* phi, void* vec, int vec_mode,
                        bool add_self, double* energy, const double* phi_add, const double* vec_add,
                        hipStream_t st) {
-  hipLaunchKernelGGL((k_gather<T, P, D>), dim3((g.tile_end - g.tile_begin) * g.parts), dim3(g.gather_threads),
-                     g.lds_gather, st, static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.perm,
-                     d.tile_start, d.sub_log2, d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin, g.parts,
-                     g.xcd_gather, static_cast<const T*>(grid),
-                     static_cast<T*>(phi), static_cast<T*>(vec), vec_mode, add_self ? 1 : 0, energy, phi_add, vec_add);
+  auto launch = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((g.tile_end - g.tile_begin) * g.parts), dim3(g.gather_threads), g.lds_gather, st,
+                       static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.perm, d.tile_start, d.sub_log2,
+                       d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin, g.parts, g.xcd_gather,
+                       static_cast<const T*>(grid), static_cast<T*>(phi), static_cast<T*>(vec), vec_mode,
+                       add_self ? 1 : 0, energy, phi_add, vec_add);
+  };
+  if constexpr (std::is_same_v<T, float>) {
+    if (g.acc32) {
+      launch(k_gather<T, P, D, float>);
+      return hipGetLastError();
+    }
+  }
+  launch(k_gather<T, P, D, double>);
   return hipGetLastError();
 }
 
@@ -856,14 +867,17 @@ hipError_t prepare_impl(PGroup& g) {
       : g.col_tile == 6           ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 6>)
       : g.col_tile == 8           ? reinterpret_cast<const void*>(&k_spread_cols<T, P, D, 8>)
                                   : reinterpret_cast<const void*>(&k_spread<T, P, D>);
-  const void* gather_fn = reinterpret_cast<const void*>(&k_gather<T, P, D>);
+  const void* gather_fn = reinterpret_cast<const void*>(&k_gather<T, P, D, double>);
+  if constexpr (std::is_same_v<T, float>) {
+    if (g.acc32) gather_fn = reinterpret_cast<const void*>(&k_gather<T, P, D, float>);
+  }
   if (g.lds_spread > 64 * 1024) {
     const hipError_t e =
         hipFuncSetAttribute(spread_fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(g.lds_spread));
     if (e != hipSuccess) return e;
   }
   if (g.lds_gather > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gather<T, P, D>),
+    const hipError_t e = hipFuncSetAttribute(gather_fn,
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
                                              static_cast<int>(g.lds_gather));
     if (e != hipSuccess) return e;

@@ -24,6 +24,11 @@ and 1e-10 + 100 delta). Over n samples the largest value of such a field stays b
 sqrt(2 ln n) (<= 5.3 for n <= 1e6) times its RMS: 6 is allowed. A single particle whose support,
 offset or window were wrong would be off by O(|phi_i|) and fail.
 
+The float32 arithmetic path (fp32_arith) also rounds inside the interpolation sums: the local
+rounding term grows from 4 u S_i to (4 + P/2 + P^2/16 + 4) u S_i (recursive summation bounds
+the error of a sum of k terms by about k u times the sum of their magnitudes); its grid stage
+is within the same norm bounds as the float32 path's.
+
 Each check returns the largest err/tol ratio and records it for the session summary.
 """
 from __future__ import annotations
@@ -33,18 +38,18 @@ import numpy as np
 from oracle import fast
 from oracle.pswf import PSWF, window_1d, window_1d_deriv
 
-U = {"fp32": 6e-8, "fp64": 1.2e-16}
+U = {"fp32": 6e-8, "fp32_arith": 6e-8, "fp64": 1.2e-16}
 RATIOS: list[tuple[str, float]] = []
 
 
 def fit_tol(eps, prec):
-    return max(0.01 * eps, 5e-9 if prec == "fp32" else 1e-15)
+    return max(0.01 * eps, 1e-15 if prec == "fp64" else 5e-9)
 
 
 def global_rel(eps, prec):
     """(g_phi, g_grad): relative l2 bounds of the grid-stage error reaching phi and grad phi."""
     d = fit_tol(eps, prec)
-    if prec == "fp32":
+    if prec != "fp64":
         return 2e-6 + 10 * d, 2e-5 + 100 * d
     return 1e-11 + 10 * d, 1e-10 + 100 * d
 
@@ -97,6 +102,11 @@ def check(name, phi, vec, q, ref_phi, ref_grad, far, b_xyz, x, o, coef, eps, pre
     global part). idx: the particles compared, when only a sample is (x and q are then the full
     system's, phi, vec, ref_*, far those of the sample). Returns (max ratio phi, max ratio grad)."""
     u = U[prec]
+    # rounding of the interpolation sums, in units of u times S_i: a float64 sum rounded once to
+    # float32 (4); with float32 arithmetic the recursive sums themselves (an x-line of P terms in two
+    # accumulators, about P^2 / 16 lines per lane, 4 levels of the 16-lane reduction) add
+    # P / 2 + P^2 / 16 + 4 more
+    r_sum = 4 + ((o.P / 2 + o.P ** 2 / 16 + 4) if prec == "fp32_arith" else 0)
     delta, ddelta, D1, D2 = window_bounds(coef, o)
     xs = x if idx is None else x[idx]
     qs = q if idx is None else q[idx]
@@ -108,14 +118,14 @@ def check(name, phi, vec, q, ref_phi, ref_grad, far, b_xyz, x, o, coef, eps, pre
     g_phi, g_grad = global_rel(eps, prec) if global_part else (0.0, 0.0)
     ref_phi = np.asarray(ref_phi, dtype=np.float64)
     rms_phi = float(np.sqrt(np.mean(np.asarray(far, dtype=np.float64) ** 2))) if len(far) else 0.0
-    tol_phi = 6 * g_phi * rms_phi + (3 * delta + 3 * u * D1 + 4 * u) * S + u * np.abs(ref_phi) + 1e-300
+    tol_phi = 6 * g_phi * rms_phi + (3 * delta + 3 * u * D1 + r_sum * u) * S + u * np.abs(ref_phi) + 1e-300
     err_phi = np.abs(np.asarray(phi, dtype=np.float64) - ref_phi)
     r_phi = float(np.max(err_phi / tol_phi)) if len(err_phi) else 0.0
     r_g = 0.0
     if vec is not None:
         ref_g = np.asarray(ref_grad, dtype=np.float64)
         rms_g = float(np.sqrt(np.mean(np.sum(ref_g ** 2, axis=1)))) if len(ref_g) else 0.0
-        tol_g = (6 * g_grad * rms_g + (ddelta + 3 * delta * D1 + 3 * u * (D1 + D2) + 4 * u * D1) * S / o.h
+        tol_g = (6 * g_grad * rms_g + (ddelta + 3 * delta * D1 + 3 * u * (D1 + D2) + r_sum * u * D1) * S / o.h
                  + u * np.max(np.abs(ref_g), axis=1) + 1e-300)
         v = np.asarray(vec, dtype=np.float64)
         if vec_is_force:   # F = -q grad phi: the bound scales with |q_i|

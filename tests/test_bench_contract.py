@@ -77,7 +77,7 @@ def test_roofline_fractions_are_fractions():
     stage_ms = {st: 0.05 for st in bench.STAGES}
     rows = bench.kernel_rooflines(stage_ms, 30000, 64, 13, 9, 4, "float")
     for st, row in rows.items():
-        frac = row.get("frac_fp64_peak", row.get("frac_hbm_peak"))
+        frac = row.get("frac_peak", row.get("frac_hbm_peak"))
         assert frac is not None and 0.0 < frac < 1.0, (st, row)
 
 

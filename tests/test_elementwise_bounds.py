@@ -14,7 +14,7 @@ pw = pytest.importorskip("paper_2602_16591_amd")
 
 def _system(prec, eps=1e-6, m=24, n=400, seed=41):
     x, q, L = W.uniform_pm1(n, seed=seed)
-    dt = np.float32 if prec == "fp32" else np.float64
+    dt = np.float64 if prec == "fp64" else np.float32
     x = x.astype(dt).astype(np.float64)
     q = q.astype(dt).astype(np.float64)
     c = pw.choose_params(eps, L, m=m)
@@ -26,10 +26,10 @@ def _system(prec, eps=1e-6, m=24, n=400, seed=41):
 
 
 def _round(a, prec):
-    return np.asarray(a, dtype=np.float32 if prec == "fp32" else np.float64).astype(np.float64)
+    return np.asarray(a, dtype=np.float64 if prec == "fp64" else np.float32).astype(np.float64)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp32_arith", "fp64"])
 def test_bounds_accept_the_rounded_oracle(prec):
     x, q, o, rphi, rg, far, b, coef, eps = _system(prec)
     F = direct.forces(q, rg)
@@ -38,7 +38,7 @@ def test_bounds_accept_the_rounded_oracle(prec):
     assert r_phi < 0.2 and r_g < 0.2
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp32_arith", "fp64"])
 def test_bounds_reject_one_bad_potential(prec):
     x, q, o, rphi, rg, far, b, coef, eps = _system(prec)
     F = direct.forces(q, rg)

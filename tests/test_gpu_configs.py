@@ -35,7 +35,7 @@ def dev():
 
 
 def run(x, q, c, prec):
-    dt = torch.float32 if prec == "fp32" else torch.float64
+    dt = torch.float64 if prec == "fp64" else torch.float32
     plan = pw.Plan(c, prec, n_max=len(q))
     phi, F, E = plan.compute(torch.as_tensor(x, dtype=dt, device=dev()), torch.as_tensor(q, dtype=dt, device=dev()))
     out = phi.double().cpu().numpy(), F.double().cpu().numpy(), float(E.cpu()[0])
@@ -44,14 +44,22 @@ def run(x, q, c, prec):
 
 
 def rounded(a, prec):
-    return np.asarray(a, dtype=np.float32 if prec == "fp32" else np.float64).astype(np.float64)
+    return np.asarray(a, dtype=np.float64 if prec == "fp64" else np.float32).astype(np.float64)
 
 
 def sample(n, k, seed):
     return np.sort(np.random.Generator(np.random.PCG64(seed)).choice(n, k, replace=False))
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+# RMS of phi against the float64 fast oracle (the path's arithmetic error): float64 rounding;
+# float32 storage with float64 arithmetic (rounding of inputs, grid and outputs, about 3e-7 here);
+# float32 arithmetic, whose window products in spreading alone add about 4e-7 on this system of
+# neutral molecules (measured by rounding the oracle's products to float32 on the CPU), and the
+# interpolation sums a similar amount
+FAST_ORACLE_RMS = {"fp64": 1e-10, "fp32": 0.3e-6, "fp32_arith": 0.8e-6}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "fp32_arith"])
 def test_water_box_vs_direct_sum(prec):
     """10,000 rigid 3-site waters (n = 30,000), eps = 1e-6 absolute (Alg. 3), grid 64^3."""
     x, q, L = W.config("water_n30000")
@@ -71,12 +79,14 @@ def test_water_box_vs_direct_sum(prec):
     # every particle against the float64 fast oracle, phi and forces, particle by particle:
     # arithmetic error of the path only
     rphi, rg, grids = fast.fast_longrange(x, q, o, return_grids=True)
-    assert np.sqrt(np.mean((phi - rphi) ** 2)) < (1e-10 if prec == "fp64" else 0.3 * eps)
+    rms = float(np.sqrt(np.mean((phi - rphi) ** 2)))
+    EW.RATIOS.append((f"water_box_n30000-{prec}-rms-vs-fast-oracle/bound", rms / FAST_ORACLE_RMS[prec]))
+    assert rms < FAST_ORACLE_RMS[prec], rms
     far = rphi - direct.self_term(q, o.rc, o.cs)
     EW.check(f"water_box_n30000-{prec}", phi, F, q, rphi, rg, far, grids["b"], np.mod(x, L), o,
              pw.host_tables(c, prec)["coef"], eps, prec)
     Eref = 0.5 * float(np.dot(q, rphi))
-    assert abs(E - Eref) < (1e-9 if prec == "fp64" else 1e-6) * abs(Eref)
+    assert abs(E - Eref) < (1e-9 if prec == "fp64" else 2e-6) * abs(Eref)
 
 
 @pytest.mark.slow
@@ -108,20 +118,23 @@ def test_large_uniform_vs_direct_sum(prec, eps, m, rc):
 
 @pytest.mark.slow
 def test_large_uniform_fp32_every_particle_vs_fast_oracle():
-    """n = 1e6 uniform, float32 at eps = 1e-6 on 128^3 (P = 12), the benchmark's plan: phi and
-    forces of every particle against Alg. 2 in float64 (oracle/fast.py), particle by particle."""
+    """n = 1e6 uniform, float32 at eps = 1e-6 on 128^3 (P = 12), the benchmark's plans (float32
+    storage with float64 and with float32 arithmetic): phi and forces of every particle against
+    Alg. 2 in float64 (oracle/fast.py), particle by particle."""
     x, q, L = W.config("uniform_n1e6")
     x, q = rounded(x, "fp32"), rounded(q, "fp32")
     eps = 1e-6
     c = pw.choose_params(eps, L, m=128)
     o = oparams.choose(eps, L, m=128)
-    phi, F, E = run(x, q, c, "fp32")
     rphi, rg, grids = oracle_pool.fast_longrange(x, q, o, return_grids=True)
     far = rphi - direct.self_term(q, o.rc, o.cs)
-    EW.check("uniform_n1e6-fp32-every-particle", phi, F, q, rphi, rg, far, grids["b"], np.mod(x, L), o,
-             pw.host_tables(c, "fp32")["coef"], eps, "fp32")
     Eref = 0.5 * float(np.dot(q, rphi))
-    assert abs(E - Eref) <= 6 * EW.global_rel(eps, "fp32")[0] * 0.5 * float(np.abs(q) @ np.abs(far)) + 1e-12 * abs(Eref)
+    for prec in ("fp32", "fp32_arith"):
+        phi, F, E = run(x, q, c, prec)
+        EW.check(f"uniform_n1e6-{prec}-every-particle", phi, F, q, rphi, rg, far, grids["b"], np.mod(x, L), o,
+                 pw.host_tables(c, prec)["coef"], eps, prec)
+        assert abs(E - Eref) <= 6 * EW.global_rel(eps, prec)[0] * 0.5 * float(np.abs(q) @ np.abs(far)) + \
+            1e-12 * abs(Eref)
 
 
 @pytest.mark.slow

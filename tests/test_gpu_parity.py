@@ -23,7 +23,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 pw = pytest.importorskip("paper_2602_16591_amd")
 
-U = {"fp32": 6e-8, "fp64": 1.2e-16}
+U = {"fp32": 6e-8, "fp32_arith": 6e-8, "fp64": 1.2e-16}
 
 
 def dev():
@@ -33,12 +33,12 @@ def dev():
 
 
 def tdev(a, prec):
-    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32 if prec == "fp32" else torch.float64,
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64 if prec == "fp64" else torch.float32,
                            device=dev())
 
 
 def fit_tol(eps, prec):
-    return max(0.01 * eps, 5e-9 if prec == "fp32" else 1e-15)
+    return max(0.01 * eps, 1e-15 if prec == "fp64" else 5e-9)
 
 
 def both_params(eps, L, **kw):
@@ -86,7 +86,7 @@ def spread_tol(x, q, o, eps, prec, A):
 
 def rounded(a, prec):
     """The values the device sees: inputs rounded to the working precision, as float64."""
-    return np.asarray(a, dtype=np.float32 if prec == "fp32" else np.float64).astype(np.float64)
+    return np.asarray(a, dtype=np.float64 if prec == "fp64" else np.float32).astype(np.float64)
 
 
 def _sys(gen, eps, kw, prec):
@@ -96,7 +96,7 @@ def _sys(gen, eps, kw, prec):
     return rounded(x, prec), rounded(q, prec), L, kw
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_arith"])
 @pytest.mark.parametrize("case", SMALL, ids=[c[0] for c in SMALL])
 def test_spread_matches_oracle(case, prec):
     _, gen, eps, kw = case
@@ -128,32 +128,28 @@ SPREAD_KERNEL_CASES = [
 ]
 
 
-# spreading kernels by their launch switches (PSWFE_SPREAD_COLUMNS, PSWFE_SPREAD_MFMA,
-# PSWFE_SPREAD_ACC): matrix cores with float64 or float32 arithmetic (tile edges 4, 6, 8; column
-# slices where they apply), register columns, LDS atomics
-SPREAD_KERNELS = {"mfma": ("1", "1", "fp64"), "mfma_acc32": ("1", "1", "fp32"),
-                  "columns": ("1", "0", "fp64"), "lds": ("0", "0", "fp64")}
+# spreading kernels by their launch switches (PSWFE_SPREAD_COLUMNS, PSWFE_SPREAD_MFMA): matrix
+# cores (tile edges 4, 6, 8; column slices where they apply; float32 arithmetic in fp32_arith
+# plans), register columns, LDS atomics
+SPREAD_KERNELS = {"mfma": ("1", "1"), "columns": ("1", "0"), "lds": ("0", "0")}
 
 
 def use_spread_kernel(monkeypatch, kernel):
-    columns, mfma, acc = SPREAD_KERNELS[kernel]
+    columns, mfma = SPREAD_KERNELS[kernel]
     monkeypatch.setenv("PSWFE_SPREAD_COLUMNS", columns)
     monkeypatch.setenv("PSWFE_SPREAD_MFMA", mfma)
-    monkeypatch.setenv("PSWFE_SPREAD_ACC", acc)
 
 
 @pytest.mark.parametrize("kernel", list(SPREAD_KERNELS))
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_arith"])
 @pytest.mark.parametrize("case", SPREAD_KERNEL_CASES, ids=[c[0] for c in SPREAD_KERNEL_CASES])
 def test_every_spreading_kernel_matches_oracle(case, prec, kernel, monkeypatch):
     """Spreading by LDS atomics (any tile), by register columns and as a matrix product on the
     matrix cores (tiles of edge 4, 6, 8): the grid against the oracle's spreading, and the whole
     pipeline against Alg. 2 in float64."""
     _, gen, eps, kw, tile = case
-    if prec == "fp32" and eps < 1e-6:
+    if prec != "fp64" and eps < 1e-6:
         pytest.skip("fp32 path is for eps >= 1e-6")
-    if kernel == "mfma_acc32" and prec == "fp64":
-        pytest.skip("float32 accumulation is for float32 plans")
     use_spread_kernel(monkeypatch, kernel)
     x, q, L, kw = _sys(gen, eps, kw, prec)
     c, o = both_params(eps, L, **kw)
@@ -199,7 +195,6 @@ def test_xcd_tile_order_gives_the_same_results(prec, monkeypatch):
 
 DENSE_CASES = [
     # (name, generator, eps, params kwargs, tile, spreading kernel): many particles per tile, few tiles
-    ("dense_m24_tile8_acc32", lambda: W.uniform_pm1(24000, seed=26), 1e-6, dict(m=24), 8, "mfma_acc32"),
     ("dense_m24_tile8_mfma", lambda: W.uniform_pm1(24000, seed=26), 1e-6, dict(m=24), 8, "mfma"),
     ("dense_m24_tile8_cols", lambda: W.uniform_pm1(24000, seed=26), 1e-6, dict(m=24), 8, "columns"),
     ("dense_m20_tile5_lds", lambda: W.paper_default(9000, seed=27, L=1.1), 1e-6, dict(m=20), 5, "lds"),
@@ -207,7 +202,7 @@ DENSE_CASES = [
 
 
 @pytest.mark.parametrize("parts", ["auto", "1", "3", "16"])
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_arith"])
 @pytest.mark.parametrize("case", DENSE_CASES, ids=[c[0] for c in DENSE_CASES])
 def test_dense_tiles_shared_by_workgroups(case, prec, parts, monkeypatch):
     """Dense tiles split over several workgroups (each spreading its slice of the tile's
@@ -234,7 +229,7 @@ def test_dense_tiles_shared_by_workgroups(case, prec, parts, monkeypatch):
     assert abs(float(E.cpu()[0]) - Eref) <= tol_phi * 0.5 * float(np.abs(q) @ np.abs(far)) + 1e-12 * abs(Eref)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "fp32_arith"])
 def test_single_charge_window_precision(prec):
     """One unit charge far from the origin (x/h ~ m): every grid value of its support within a few
     units of roundoff of the oracle's window product. Guards the compensated x/h of the binning
@@ -270,7 +265,7 @@ def test_transform_matches_oracle(m, eps, prec, plane, monkeypatch):
     plane=0 (the default) runs the separate x and y passes.
     """
     from oracle.pswf import PSWF, window_hat_1d
-    if prec == "fp32" and eps < 1e-8:
+    if prec != "fp64" and eps < 1e-8:
         pytest.skip("fp32 path is for eps >= 1e-6")
     monkeypatch.setenv("PSWFE_PLANE_FFT", plane)
     L = 1.0
@@ -288,7 +283,7 @@ def test_transform_matches_oracle(m, eps, prec, plane, monkeypatch):
     assert rel < (1e-12 if prec == "fp64" else 2e-6), rel
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_arith"])
 @pytest.mark.parametrize("case", SMALL, ids=[c[0] for c in SMALL])
 def test_interpolate_matches_oracle(case, prec):
     _, gen, eps, kw = case
@@ -307,12 +302,12 @@ def test_interpolate_matches_oracle(case, prec):
              coef, eps, prec, vec_is_force=False, global_part=False)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_arith"])
 @pytest.mark.parametrize("case", SMALL, ids=[c[0] for c in SMALL])
 def test_compute_matches_fast_oracle(case, prec):
     """Whole pipeline against Alg. 2 in float64: phi, forces and energy."""
     _, gen, eps, kw = case
-    if prec == "fp32" and eps < 1e-6:
+    if prec != "fp64" and eps < 1e-6:
         pytest.skip("fp32 path is for eps >= 1e-6")
     x, q, L, kw = _sys(gen, eps, kw, prec)
     c, o = both_params(eps, L, **kw)
@@ -334,7 +329,7 @@ def test_compute_matches_fast_oracle(case, prec):
     assert abs(E - 0.5 * float(np.dot(q, phi))) <= 1e-6 * abs(E) + 1e-12
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_arith"])
 def test_plain_config_vs_direct_sum(prec):
     """n = 1000 uniform +-1 charges, L = 1, eps = 1e-6, grid 32^3: relative l2 error of phi_far
     against the direct Ewald sum below eps (relative-tolerance parameters)."""
