@@ -95,15 +95,26 @@ def _profile_blob(path, workload: str = "water_box_n30000"):
     return blob if blob.get("kernel_source_sha256") == kernel_source_sha256() else None
 
 
-def _stage_kernels(blob_keys, stage: str, prec_ctype: str):
-    prefixes = tuple(f"{name}<{prec_ctype}" for name in STAGE_KERNEL[stage])
-    hits = [k for k in blob_keys if k.startswith(prefixes)]
+# kernels whose last template argument is the type of their window arithmetic
+ARITH_KERNELS = ("k_spread_mfma", "k_gather")
+
+
+def _stage_kernels(blob_keys, stage: str, prec: str):
+    """Names of the kernels that run a stage at a plan precision ("fp32_arith", "fp32", "fp64")."""
+    ctype = "double" if prec == "fp64" else "float"
+    arith = "float" if prec == "fp32_arith" else "double"
+    hits = []
+    for k in blob_keys:
+        name = k.split("<", 1)[0]
+        if name in STAGE_KERNEL[stage] and k.startswith(f"{name}<{ctype}"):
+            if name not in ARITH_KERNELS or k.endswith(f", {arith}>"):
+                hits.append(k)
     if stage == "bin":   # the counting sort is three launches: count, scan, scatter
-        hits += [k for k in blob_keys if k == "k_scan" or k.startswith(f"k_bin_scatter<{prec_ctype}")]
+        hits += [k for k in blob_keys if k == "k_scan" or k.startswith(f"k_bin_scatter<{ctype}")]
     return hits
 
 
-def measured_traffic(stage: str, prec_ctype: str, workload: str = "water_box_n30000"):
+def measured_traffic(stage: str, prec: str, workload: str = "water_box_n30000"):
     """HBM bytes per launch of the stage's kernel(s) from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE runs, calibrated against a plain copy), or None when the summary
     is missing or was taken on other kernel sources."""
@@ -111,27 +122,27 @@ def measured_traffic(stage: str, prec_ctype: str, workload: str = "water_box_n30
     if blob is None:
         return None
     per = blob.get("bytes_per_launch", {})
-    hits = _stage_kernels(per.keys(), stage, prec_ctype)
+    hits = _stage_kernels(per.keys(), stage, prec)
     if not hits or (stage != "bin" and len(hits) != 1):
         return None
     return sum(per[k] for k in hits)
 
 
-def measured_lds(stage: str, prec_ctype: str, workload: str = "water_box_n30000"):
+def measured_lds(stage: str, prec: str, workload: str = "water_box_n30000"):
     """LDS instructions and LDS bank-conflict cycles per launch of the stage's kernel(s) from the
     committed counter summary, or None."""
     blob = _profile_blob(LDS_FILE, workload)
     if blob is None:
         return None
     per = blob.get("per_launch", {})
-    hits = _stage_kernels(per.keys(), stage, prec_ctype)
+    hits = _stage_kernels(per.keys(), stage, prec)
     if not hits or (stage != "bin" and len(hits) != 1):
         return None
     return {c: sum(per[k][c] for k in hits) for c in ("lds_instr", "lds_bank_conflict_cycles", "valu_instr")}
 
 
-def kernel_rooflines(stage_ms: dict, n: int, m: int, P: int, deg: int, elem: int, prec_ctype: str,
-                     workload: str = "water_box_n30000", prec: str = "fp32"):
+def kernel_rooflines(stage_ms: dict, n: int, m: int, P: int, deg: int, elem: int, prec: str,
+                     workload: str = "water_box_n30000"):
     """Per stage: event-timed duration, the algorithmic work and its roofline fraction (against the
     peak of the arithmetic the kernel runs in), the HBM traffic the counters measured (GB/s
     against 8 TB/s) and the LDS bank-conflict share of the compute units' cycles (2.4 GHz x 256
@@ -148,10 +159,10 @@ def kernel_rooflines(stage_ms: dict, n: int, m: int, P: int, deg: int, elem: int
         else:
             row.update({"bound": "hbm", "algorithmic_bytes": work, "gbs": work / us * 1e-3,
                         "frac_hbm_peak": work / us * 1e-3 / PEAK_HBM_GBS})
-        t = measured_traffic(st, prec_ctype, workload)
+        t = measured_traffic(st, prec, workload)
         if t is not None:
             row.update({"measured_bytes": t, "measured_gbs": t / us * 1e-3, "measured_frac_hbm_peak": t / us * 1e-3 / PEAK_HBM_GBS})
-        lds = measured_lds(st, prec_ctype, workload)
+        lds = measured_lds(st, prec, workload)
         if lds is not None:
             row.update({"lds_instr": lds["lds_instr"],
                         "lds_conflict_share": lds["lds_bank_conflict_cycles"] / (us * 2400.0 * 256)})
@@ -454,12 +465,11 @@ def time_precisions(x, q, params_of, steps: int, warmup: int, with_total: bool, 
 def leg_summary(r, n, steps, workload, prec):
     """A precision's figures for the JSON line."""
     ms = r["elapsed"] / steps * 1e3
-    ctype = "double" if prec == "fp64" else "float"
     return {"value": n * steps / r["elapsed"], "unit": "particles/s", "ms_per_step": ms,
             "ms_per_step_excl_bin": ms - r["stage_ms"]["bin"],
             "call_us_event_timed": r["stage_ms"]["all"] * 1e3, "plan_create_s": r["plan_s"], "m": r["m"], "P": r["P"],
             "stage_us": {k: v * 1e3 for k, v in r["stage_ms"].items() if k != "all"},
-            "kernels": kernel_rooflines(r["stage_ms"], n, r["m"], r["P"], r["deg"], r["elem"], ctype, workload, prec)}
+            "kernels": kernel_rooflines(r["stage_ms"], n, r["m"], r["P"], r["deg"], r["elem"], prec, workload)}
 
 
 def roofline_of(r, n, workload, prec):
@@ -476,7 +486,7 @@ def roofline_of(r, n, workload, prec):
         achieved = work / secs / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS}
-    roof["traffic"] = measured_traffic(r["dom"], "float", workload)
+    roof["traffic"] = measured_traffic(r["dom"], prec, workload)
     roof.update({"kernel": r["dom"], "avg_launch_us": r["dom_ms"] * 1e3, "work_per_launch": work})
     return roof
 

@@ -24,13 +24,15 @@ def test_more_than_one_gpu_is_refused_with_a_message(extra):
 
 def test_water_box_counter_summaries_are_not_used_for_other_workloads(tmp_path, monkeypatch):
     blob = {"kernel_source_sha256": bench.kernel_source_sha256(), "workload": "water_box_n30000",
-            "bytes_per_launch": {"k_spread_mfma<float, 13, 11, 8>": 41_000_000}}
+            "bytes_per_launch": {"k_spread_mfma<float, 13, 11, 8, float>": 41_000_000, "k_spread_mfma<float, 13, 11, 8, double>": 52_000_000}}
     p = tmp_path / "summary.md"
     p.write_text("```json\n" + json.dumps(blob) + "\n```\n")
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(p))
     monkeypatch.setattr(bench, "TRAFFIC_FILE_N1E6", str(p))   # a water-box summary where the n = 1e6 one belongs
-    assert bench.measured_traffic("spread", "float") == 41_000_000
-    assert bench.measured_traffic("spread", "float", "uniform_n1e6") is None
+    assert bench.measured_traffic("spread", "fp32_arith") == 41_000_000
+    assert bench.measured_traffic("spread", "fp32") == 52_000_000
+    assert bench.measured_traffic("spread", "fp64") is None
+    assert bench.measured_traffic("spread", "fp32_arith", "uniform_n1e6") is None
 
 
 def test_spread_and_gather_work_per_launch():
@@ -55,7 +57,7 @@ def test_fft_pass_bytes(elem):
 
 
 def _summary(tmp_path, sha):
-    blob = {"kernel_source_sha256": sha, "bytes_per_launch": {"k_spread_mfma<float, 13, 11, 8>": 41_000_000}}
+    blob = {"kernel_source_sha256": sha, "bytes_per_launch": {"k_spread_mfma<float, 13, 11, 8, float>": 41_000_000, "k_spread_mfma<float, 13, 11, 8, double>": 52_000_000}}
     p = tmp_path / "summary.md"
     p.write_text("# summary\n\n```json\n" + json.dumps(blob) + "\n```\n")
     return str(p)
@@ -68,14 +70,14 @@ def test_counter_summaries_apply_only_to_their_kernel_sources(tmp_path, monkeypa
     assert bench._profile_blob(_summary(tmp_path, "0" * 64)) is None
     assert bench._profile_blob(str(tmp_path / "missing.md")) is None
     monkeypatch.setattr(bench, "TRAFFIC_FILE", _summary(tmp_path, current))
-    assert bench.measured_traffic("spread", "float") == 41_000_000
+    assert bench.measured_traffic("spread", "fp32_arith") == 41_000_000
     monkeypatch.setattr(bench, "TRAFFIC_FILE", _summary(tmp_path, "0" * 64))
-    assert bench.measured_traffic("spread", "float") is None
+    assert bench.measured_traffic("spread", "fp32_arith") is None
 
 
 def test_roofline_fractions_are_fractions():
     stage_ms = {st: 0.05 for st in bench.STAGES}
-    rows = bench.kernel_rooflines(stage_ms, 30000, 64, 13, 9, 4, "float")
+    rows = bench.kernel_rooflines(stage_ms, 30000, 64, 13, 9, 4, "fp32_arith")
     for st, row in rows.items():
         frac = row.get("frac_peak", row.get("frac_hbm_peak"))
         assert frac is not None and 0.0 < frac < 1.0, (st, row)
