@@ -524,7 +524,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   if (!counts) part_prefix[1] = 0;  // unused: one system takes every particle of a call
 
   // sub-buckets per tile: at least 8 particles each on average, at most 16 per tile and
-  // 32768 counters in all (the scan runs in one workgroup)
+  // 32768 buckets in all
   {
     const double per_tile = static_cast<double>(d.n_max) / std::max(d.total_tiles, 1);
     while (d.sub_log2 < 4 && 8.0 * (1 << d.sub_log2) <= per_tile &&
@@ -532,6 +532,22 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
       ++d.sub_log2;
   }
   const int64_t nbuckets = static_cast<int64_t>(d.total_tiles) << d.sub_log2;
+  // two-level sort: the fewest buckets per coarse bucket (a power of two) that leave at most
+  // kCoarse coarse buckets; particles per thread so that about 512 workgroups share the passes
+  while (((nbuckets + (int64_t(1) << d.bin_shift) - 1) >> d.bin_shift) > pswfe::kCoarse) ++d.bin_shift;
+  d.bin_ncoarse = static_cast<int>((nbuckets + (int64_t(1) << d.bin_shift) - 1) >> d.bin_shift);
+  if ((1 << d.bin_shift) > pswfe::kBinMaxFine) {
+    free_plan(plan);
+    return PSWFE_E_GRID;
+  }
+  // the one-level sort below 200,000 particles (PSWFE_BIN_LEVELS=1 or 2 overrides)
+  d.bin_levels = d.n_max < 200000 ? 1 : 2;
+  if (const char* env = std::getenv("PSWFE_BIN_LEVELS")) {
+    const int v = std::atoi(env);
+    if (v == 1 || v == 2) d.bin_levels = v;
+  }
+  d.bin_per_thread = static_cast<int>(std::min<int64_t>(
+      pswfe::kBinMaxPerThread, std::max<int64_t>(1, (d.n_max + 256 * 512 - 1) / (256 * 512))));
   const size_t nm = static_cast<size_t>(std::max<int64_t>(d.n_max, 1));
   d.total_cells = cell_prefix;
   // residual workgroup size: 512 threads (PSWFE_LOCAL_THREADS=128 or 256 overrides)
@@ -564,10 +580,13 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   const size_t o_part = dev.take(sizeof(int64_t) * (nsys + 1));
   const size_t const_end = dev.size;
   const size_t o_work = dev.take(work.size);
+  // coarse counts and cursors (kCoarseCopies copies each), then the coarse starts
+  const size_t o_coarse = dev.take(sizeof(int) * (2 * pswfe::kCoarseCopies * pswfe::kCoarse + pswfe::kCoarse + 1));
   const size_t o_tile_count = dev.take(sizeof(int) * nbuckets);
   const size_t o_tile_start = dev.take(sizeof(int) * (nbuckets + 1));
   const size_t o_tile_of = dev.take(sizeof(int) * nm);
-  const size_t o_rank = dev.take(sizeof(int) * nm);
+  const size_t o_bin_tmp = dev.take(4 * static_cast<size_t>(elem) * nm);
+  const size_t o_bin_tmp_ib = dev.take(sizeof(int2) * nm);
   const size_t o_perm = dev.take(sizeof(int) * nm);
   const size_t o_cells = dev.take(sizeof(int) * nm);
   const size_t o_sorted = dev.take(4 * static_cast<size_t>(elem) * nm);
@@ -614,10 +633,15 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   d.zblk_prefix = reinterpret_cast<int*>(base + o_zblk);
   d.cblk_prefix = reinterpret_cast<int*>(base + o_cblk);
   d.part_prefix = reinterpret_cast<int64_t*>(base + o_part);
-  d.tile_count = reinterpret_cast<int*>(base + o_tile_count);
+  d.coarse_count = reinterpret_cast<int*>(base + o_coarse);
+  d.coarse_cursor = d.coarse_count + pswfe::kCoarseCopies * pswfe::kCoarse;
+  d.coarse_start = d.coarse_cursor + pswfe::kCoarseCopies * pswfe::kCoarse;
   d.tile_start = reinterpret_cast<int*>(base + o_tile_start);
   d.tile_of = reinterpret_cast<int*>(base + o_tile_of);
-  d.rank = reinterpret_cast<int*>(base + o_rank);
+  d.bin_tmp = base + o_bin_tmp;
+  d.bin_tmp_ib = reinterpret_cast<int2*>(base + o_bin_tmp_ib);
+  d.bin_rank = reinterpret_cast<int*>(base + o_bin_tmp_ib);
+  d.tile_count = reinterpret_cast<int*>(base + o_tile_count);
   d.perm = reinterpret_cast<int*>(base + o_perm);
   d.cells = reinterpret_cast<int*>(base + o_cells);
   d.sorted = base + o_sorted;
@@ -705,6 +729,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   for (int s = 0; s < nsys; ++s)
     plan->zero.push_back({o_work + woff[s].a, sizeof(double) * static_cast<size_t>(d.sys[s].m) * d.sys[s].my *
                                                   d.sys[s].mz});
+  plan->zero.push_back({o_coarse, sizeof(int) * 2 * static_cast<size_t>(pswfe::kCoarseCopies * pswfe::kCoarse)});
   plan->zero.push_back({o_tile_count, sizeof(int) * static_cast<size_t>(nbuckets)});
   if (with_local) plan->zero.push_back({o_cell_count, sizeof(int) * static_cast<size_t>(d.total_cells)});
   plan->base = base;

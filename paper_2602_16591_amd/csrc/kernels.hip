@@ -14,52 +14,356 @@
 namespace pswfe {
 namespace {
 // ------------------------------------------------------------------------------------
-// Binning: particles are grouped by tiles of B^3 grid cells (counting sort over the global
-// tile index of the batch, each tile split into sub-buckets). Packed particle i belongs to the system whose range
-// [part_prefix[s], part_prefix[s+1]) holds it.
+// Binning: a counting sort of the particles by bucket (the tile of B^3 grid cells that holds
+// the particle's support anchor, split into z sub-buckets; packed particle i belongs to the
+// system whose range [part_prefix[s], part_prefix[s+1]) holds it). Two levels, so that no step
+// issues one global atomic per particle or scatters lone records across memory:
+//   k_bin_count   each workgroup takes per_thread particles per thread, stores their buckets and
+//                 counts the coarse buckets (bucket >> shift, at most kCoarse of them) in LDS, then
+//                 adds each nonzero count to the global coarse counts with one atomic;
+//   k_bin_coarse  moves the particles into coarse-bucket order: a workgroup ranks its particles
+//                 per coarse bucket in LDS and reserves its range in each coarse bucket with one
+//                 atomic, so its particles of one coarse bucket land next to each other;
+//   k_bin_fine    one workgroup per coarse bucket counts its particles per bucket in LDS, writes
+//                 the bucket starts, and writes each particle's record, cell and original index in
+//                 bucket order.
+// The coarse counters are zero between calls: k_bin_fine clears them after their last use.
 // ------------------------------------------------------------------------------------
+constexpr int kBinThreads = 256;
+constexpr int kFineThreads = 1024;
+
+// Tile bucket of a particle at (x, y, z) (the anchor's tile, and within it the sub-bucket of the
+// z-cell: a tile's particles come out ordered by z, so the slices of a tile shared by several
+// workgroups cover narrow z-ranges and their partial blocks flush fewer nonzero points); the
+// packed anchor and the centred offsets g go to `cell` and `g`.
 template <class T>
-__global__ void k_bin_count(int64_t n, int nsys, const SysDesc* __restrict__ sys,
-                            const int64_t* __restrict__ part_prefix, const T* __restrict__ pos, int sub_log2,
-                            int* __restrict__ tile_count, int* __restrict__ tile_of, int* __restrict__ rank,
-                            double* __restrict__ energy) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+__device__ __forceinline__ int bin_bucket(const SysDesc& sd, int sub_log2, T x, T y, T z, int& cell, T g[3]) {
+  T f[3];
+  const int c0 = grid_coord(x, T(sd.ih_hi), T(sd.ih_lo), T(sd.L), sd.m, f[0]);
+  const int c1 = grid_coord(y, T(sd.ihy_hi), T(sd.ihy_lo), T(sd.Ly), sd.my, f[1]);
+  const int c2 = grid_coord(z, T(sd.ihz_hi), T(sd.ihz_lo), T(sd.Lz), sd.mz, f[2]);
+  const int cx = support_anchor(c0, f[0], sd.P, sd.m, g[0]);
+  const int cy = support_anchor(c1, f[1], sd.P, sd.my, g[1]);
+  const int cz = support_anchor(c2, f[2], sd.P, sd.mz, g[2]);
+  const int B = sd.B;
+  cell = pack_cell(cx, cy, cz);
+  const int tile = sd.tile_base + ((cz / B) * sd.Tny + cy / B) * sd.Tn + cx / B;
+  return (tile << sub_log2) | (((cz % B) << sub_log2) / B);
+}
+
+// Exclusive prefix sum of a[0, count) in LDS, in place, by the whole workgroup; returns the total.
+// Each thread sums a run of consecutive entries, the run sums are scanned across lanes and waves
+// (s_wave: one int per wave), then each thread rewrites its run. Ends with a barrier.
+__device__ __forceinline__ int block_scan_lds(int* a, int count, int* s_wave) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+  const int per = (count + static_cast<int>(blockDim.x) - 1) / static_cast<int>(blockDim.x);
+  const int b0 = min(tid * per, count), b1 = min(b0 + per, count);
+  int sum = 0;
+  for (int i = b0; i < b1; ++i) sum += a[i];
+  int x = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_wave[wid] = x;
+  __syncthreads();
+  int before = 0, total = 0;
+  for (int w = 0; w < nw; ++w) {
+    const int v = s_wave[w];
+    before += w < wid ? v : 0;
+    total += v;
+  }
+  int run = before + x - sum;
+  for (int i = b0; i < b1; ++i) {
+    const int v = a[i];
+    a[i] = run;
+    run += v;
+  }
+  __syncthreads();
+  return total;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t n, int nsys, const SysDesc* __restrict__ sys,
+                                                        const int64_t* __restrict__ part_prefix,
+                                                        const T* __restrict__ pos, int sub_log2, int per_thread,
+                                                        int shift, int ncoarse, int* __restrict__ coarse_count,
+                                                        int* __restrict__ key, double* __restrict__ energy) {
+  __shared__ int hist[kCoarse];
+  const int tid = threadIdx.x;
+  {
+    const int64_t e = blockIdx.x * static_cast<int64_t>(kBinThreads) + tid;
+    if (energy && e < nsys) energy[e] = 0.0;
+  }
+  for (int c = tid; c < kCoarse; c += kBinThreads) hist[c] = 0;
+  __syncthreads();
+  if (n > 0) {
+    const int64_t i0 = blockIdx.x * static_cast<int64_t>(kBinThreads) * per_thread + tid;
+    // every load is issued (at clamped, valid indices) before any position is used
+    T x[kBinMaxPerThread][3];
+#pragma unroll
+    for (int k = 0; k < kBinMaxPerThread; ++k) {
+      const int64_t i = min(i0 + static_cast<int64_t>(min(k, per_thread - 1)) * kBinThreads, n - 1);
+#pragma unroll
+      for (int dd = 0; dd < 3; ++dd) x[k][dd] = pos[3 * i + dd];
+    }
+#pragma unroll
+    for (int k = 0; k < kBinMaxPerThread; ++k) {
+      const int64_t i = i0 + static_cast<int64_t>(k) * kBinThreads;
+      if (k < per_thread && i < n) {
+        const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
+        int cell;
+        T g[3];
+        const int b = bin_bucket(sd, sub_log2, x[k][0], x[k][1], x[k][2], cell, g);
+        key[i] = b;
+        atomicAdd(&hist[b >> shift], 1);
+      }
+    }
+  }
+  __syncthreads();
+  int* __restrict__ mine = coarse_count + (blockIdx.x % kCoarseCopies) * kCoarse;
+  for (int c = tid; c < ncoarse; c += kBinThreads)
+    if (hist[c] > 0) atomicAdd(&mine[c], hist[c]);
+}
+
+template <class T>
+__global__ __launch_bounds__(kBinThreads) void k_bin_coarse(int64_t n, const T* __restrict__ pos,
+                                                         const T* __restrict__ q, int per_thread, int shift,
+                                                         int ncoarse, const int* __restrict__ coarse_count,
+                                                         int* __restrict__ coarse_cursor,
+                                                         int* __restrict__ coarse_start, const int* __restrict__ key,
+                                                         typename Vec4<T>::type* __restrict__ tmp_rec,
+                                                         int2* __restrict__ tmp_ib) {
+  __shared__ int s_start[kCoarse];
+  __shared__ int hist[kCoarse];
+  __shared__ int s_wave[kBinThreads / 64];
+  const int tid = threadIdx.x;
+  const int copy = blockIdx.x % kCoarseCopies;
+  const int64_t i0 = blockIdx.x * static_cast<int64_t>(kBinThreads) * per_thread + tid;
+  // this thread's particles: bucket, position and charge, all loads issued at once
+  int kb[kBinMaxPerThread], lr[kBinMaxPerThread];
+  typename Vec4<T>::type r[kBinMaxPerThread];
+#pragma unroll
+  for (int k = 0; k < kBinMaxPerThread; ++k) {
+    const int64_t i = i0 + static_cast<int64_t>(k) * kBinThreads;
+    const int64_t ic = min(i0 + static_cast<int64_t>(min(k, per_thread - 1)) * kBinThreads, n - 1);
+    kb[k] = key[ic];
+    if (!(k < per_thread && i < n)) kb[k] = -1;
+    r[k].x = pos[3 * ic + 0];
+    r[k].y = pos[3 * ic + 1];
+    r[k].z = pos[3 * ic + 2];
+    r[k].w = q ? q[ic] : T(0);
+  }
+  // coarse starts (the scan over all copies) and this copy's offset within each coarse bucket
+  int own = 0;
+  if (tid < kCoarse) {
+    int tot = 0;
+    if (tid < ncoarse) {
+#pragma unroll
+      for (int k = 0; k < kCoarseCopies; ++k) {
+        const int v = coarse_count[k * kCoarse + tid];
+        own += k < copy ? v : 0;
+        tot += v;
+      }
+    }
+    s_start[tid] = tot;
+    hist[tid] = 0;
+  }
+  __syncthreads();
+  const int total = block_scan_lds(s_start, ncoarse, s_wave);
+  if (blockIdx.x == 0) {
+    for (int c = tid; c < ncoarse; c += kBinThreads) coarse_start[c] = s_start[c];
+    if (tid == 0) coarse_start[ncoarse] = total;
+  }
+#pragma unroll
+  for (int k = 0; k < kBinMaxPerThread; ++k)
+    if (kb[k] >= 0) lr[k] = atomicAdd(&hist[kb[k] >> shift], 1);
+  __syncthreads();
+  // each nonzero count becomes the workgroup's first slot in that coarse bucket
+  if (tid < ncoarse && hist[tid] > 0)
+    hist[tid] = s_start[tid] + own + atomicAdd(&coarse_cursor[copy * kCoarse + tid], hist[tid]);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kBinMaxPerThread; ++k) {
+    if (kb[k] < 0) continue;
+    const int dst = hist[kb[k] >> shift] + lr[k];
+    if (dst >= n) continue;  // only if the coarse counters were not zero at the start
+    tmp_rec[dst] = r[k];
+    tmp_ib[dst] = int2{static_cast<int>(i0 + static_cast<int64_t>(k) * kBinThreads), kb[k]};
+  }
+}
+
+// Sorted record: (g_x, g_y, g_z, q), the centred offsets from the support anchors, and the
+// packed anchor of the particle in its system. A coarse bucket of up to kFineRes items per thread
+// is held in registers from one round of loads; larger ones are read twice.
+constexpr int kFineRes = 8;
+template <class T>
+__global__ __launch_bounds__(kFineThreads) void k_bin_fine(int64_t n, int nsys, const SysDesc* __restrict__ sys,
+                                                        const int64_t* __restrict__ part_prefix, int shift,
+                                                        int ncoarse, int nbuckets, const int* __restrict__ coarse_start,
+                                                        int* __restrict__ coarse_count, int* __restrict__ coarse_cursor,
+                                                        const typename Vec4<T>::type* __restrict__ tmp_rec,
+                                                        const int2* __restrict__ tmp_ib, int* __restrict__ tile_start,
+                                                        typename Vec4<T>::type* __restrict__ sorted,
+                                                        int* __restrict__ cells, int* __restrict__ perm) {
+  using V = typename Vec4<T>::type;
+  extern __shared__ int smem_int[];
+  const int nf = 1 << shift;
+  int* fine = smem_int;             // nf: counts, then cursors
+  int* s_wave = smem_int + nf;      // kFineThreads / 64
+  const int tid = threadIdx.x, c = blockIdx.x;
+  // clamped to [0, n]: the ranges are inside the particle arrays whatever the counters held
+  const int s1 = static_cast<int>(min<int64_t>(max(coarse_start[c + 1], 0), n));
+  const int s0 = min(max(coarse_start[c], 0), s1);
+  const bool resident = s1 - s0 <= kFineRes * kFineThreads;
+  V r[kFineRes];
+  int2 ib[kFineRes];
+  if (resident) {
+#pragma unroll
+    for (int u = 0; u < kFineRes; ++u) {
+      const int j = min(s0 + tid + u * kFineThreads, s1 - 1);
+      if (s1 > s0) {
+        r[u] = tmp_rec[j];
+        ib[u] = tmp_ib[j];
+      }
+    }
+  }
+  for (int f = tid; f < nf; f += kFineThreads) fine[f] = 0;
+  __syncthreads();
+  if (resident) {
+#pragma unroll
+    for (int u = 0; u < kFineRes; ++u)
+      if (s0 + tid + u * kFineThreads < s1) atomicAdd(&fine[ib[u].y & (nf - 1)], 1);
+  } else {
+    for (int j = s0 + tid; j < s1; j += kFineThreads) atomicAdd(&fine[tmp_ib[j].y & (nf - 1)], 1);
+  }
+  __syncthreads();
+  block_scan_lds(fine, nf, s_wave);
+  const int b0 = c << shift;
+  for (int f = tid; f < nf; f += kFineThreads) {
+    const int st = fine[f] + s0;
+    fine[f] = st;
+    if (b0 + f < nbuckets) tile_start[b0 + f] = st;
+  }
+  if (c == ncoarse - 1 && tid == 0) tile_start[nbuckets] = s1;
+  for (int k = tid; k < kCoarseCopies; k += kFineThreads) {
+    coarse_count[k * kCoarse + c] = 0;
+    coarse_cursor[k * kCoarse + c] = 0;
+  }
+  __syncthreads();
+  auto place = [&](const V& rv, int2 iv) {
+    const int dst = atomicAdd(&fine[iv.y & (nf - 1)], 1);
+    if (dst >= s1) return;
+    const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, static_cast<int64_t>(iv.x))];
+    V rec;
+    int cell;
+    T g[3];
+    bin_bucket(sd, 0, rv.x, rv.y, rv.z, cell, g);
+    rec.x = g[0];
+    rec.y = g[1];
+    rec.z = g[2];
+    rec.w = rv.w;
+    // a non-finite position is moved to cell 0 by grid_coord; its NaN charge poisons the outputs
+    // instead (spreading adds NaN into the grid, interpolation returns NaN for it)
+    if (!(isfinite(rv.x) && isfinite(rv.y) && isfinite(rv.z))) rec.w = std::numeric_limits<T>::quiet_NaN();
+    sorted[dst] = rec;
+    cells[dst] = cell;
+    perm[dst] = iv.x;
+  };
+  if (resident) {
+#pragma unroll
+    for (int u = 0; u < kFineRes; ++u)
+      if (s0 + tid + u * kFineThreads < s1) place(r[u], ib[u]);
+  } else {
+    for (int j = s0 + tid; j < s1; j += kFineThreads) place(tmp_rec[j], tmp_ib[j]);
+  }
+}
+
+// One-level counting sort, for small systems (three short launches with no chain of dependent
+// passes): a returning atomic per particle gives its rank within its bucket, one workgroup scans
+// the bucket counts (k_scan), and the scatter writes each particle at its bucket's start plus
+// its rank.
+template <class T>
+__global__ __launch_bounds__(kBinThreads) void k_bin_count1(int64_t n, int nsys, const SysDesc* __restrict__ sys,
+                                                         const int64_t* __restrict__ part_prefix,
+                                                         const T* __restrict__ pos, int sub_log2,
+                                                         int* __restrict__ tile_count, int* __restrict__ key,
+                                                         int* __restrict__ rank, double* __restrict__ energy) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kBinThreads) + threadIdx.x;
   if (energy && i < nsys) energy[i] = 0.0;
   if (i >= n) return;
   const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
-  const int B = sd.B;
-  T f[3], g;
-  const int c0 = grid_coord(pos[3 * i + 0], T(sd.ih_hi), T(sd.ih_lo), T(sd.L), sd.m, f[0]);
-  const int c1 = grid_coord(pos[3 * i + 1], T(sd.ihy_hi), T(sd.ihy_lo), T(sd.Ly), sd.my, f[1]);
-  const int c2 = grid_coord(pos[3 * i + 2], T(sd.ihz_hi), T(sd.ihz_lo), T(sd.Lz), sd.mz, f[2]);
-  const int cx = support_anchor(c0, f[0], sd.P, sd.m, g);
-  const int cy = support_anchor(c1, f[1], sd.P, sd.my, g);
-  const int cz = support_anchor(c2, f[2], sd.P, sd.mz, g);
-  const int tile = sd.tile_base + ((cz / B) * sd.Tny + cy / B) * sd.Tn + cx / B;
-  // sub-bucket: the z-cell within the tile, so a tile's particles come out ordered by z (the
-  // slices of a tile shared by several workgroups then cover narrow z-ranges, and their partial
-  // blocks flush fewer nonzero points)
-  const int bucket = (tile << sub_log2) | (((cz % B) << sub_log2) / B);
-  tile_of[i] = bucket;
-  rank[i] = atomicAdd(&tile_count[bucket], 1);
+  int cell;
+  T g[3];
+  const int b = bin_bucket(sd, sub_log2, pos[3 * i + 0], pos[3 * i + 1], pos[3 * i + 2], cell, g);
+  key[i] = b;
+  rank[i] = atomicAdd(&tile_count[b], 1);
 }
 
-// Exclusive scan of the tile counts (one workgroup); resets the counts to zero.
+template <class T>
+__global__ __launch_bounds__(kBinThreads) void k_bin_scatter1(
+    int64_t n, int nsys, const SysDesc* __restrict__ sys, const int64_t* __restrict__ part_prefix,
+    const T* __restrict__ pos, const T* __restrict__ q, const int* __restrict__ key, const int* __restrict__ rank,
+    const int* __restrict__ tile_start, typename Vec4<T>::type* __restrict__ sorted, int* __restrict__ cells,
+    int* __restrict__ perm) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(kBinThreads) + threadIdx.x;
+  if (i >= n) return;
+  const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
+  const int dst = tile_start[key[i]] + rank[i];
+  const T x = pos[3 * i + 0], y = pos[3 * i + 1], z = pos[3 * i + 2];
+  typename Vec4<T>::type rec;
+  int cell;
+  T g[3];
+  bin_bucket(sd, 0, x, y, z, cell, g);
+  rec.x = g[0];
+  rec.y = g[1];
+  rec.z = g[2];
+  rec.w = q ? q[i] : T(0);
+  // a non-finite position is moved to cell 0 by grid_coord; its NaN charge poisons the outputs
+  // instead (spreading adds NaN into the grid, interpolation returns NaN for it)
+  if (!(isfinite(x) && isfinite(y) && isfinite(z))) rec.w = std::numeric_limits<T>::quiet_NaN();
+  sorted[dst] = rec;
+  cells[dst] = cell;
+  perm[dst] = static_cast<int>(i);
+}
+
+// Exclusive scan of the counts (one workgroup of 1,024 threads, 16 consecutive counts per thread
+// per pass, held in registers from one round of loads); resets the counts to zero.
+constexpr int kScanK = 16;
 __global__ __launch_bounds__(1024) void k_scan(int ntiles, int* __restrict__ count, int* __restrict__ start) {
   __shared__ int s_part[16];
   __shared__ int s_carry;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (tid == 0) s_carry = 0;
   __syncthreads();
-  for (int base = 0; base < ntiles; base += 4096) {
-    const int i0 = base + 4 * tid;
-    int v[4], sum = 0;
+  for (int base = 0; base < ntiles; base += 1024 * kScanK) {
+    const int i0 = base + kScanK * tid;
+    int v[kScanK];
+    if (i0 + kScanK <= ntiles) {
+      // the count and start buffers are 256-byte aligned and i0 is a multiple of 16
+      const int4* c4 = reinterpret_cast<const int4*>(count + i0);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      v[k] = (i0 + k < ntiles) ? count[i0 + k] : 0;
-      if (i0 + k < ntiles) count[i0 + k] = 0;
-      sum += v[k];
+      for (int k = 0; k < kScanK / 4; ++k) {
+        const int4 w = c4[k];
+        v[4 * k] = w.x;
+        v[4 * k + 1] = w.y;
+        v[4 * k + 2] = w.z;
+        v[4 * k + 3] = w.w;
+      }
+      int4* z4 = reinterpret_cast<int4*>(count + i0);
+#pragma unroll
+      for (int k = 0; k < kScanK / 4; ++k) z4[k] = int4{0, 0, 0, 0};
+    } else {
+#pragma unroll
+      for (int k = 0; k < kScanK; ++k) {
+        v[k] = i0 + k < ntiles ? count[i0 + k] : 0;
+        if (i0 + k < ntiles) count[i0 + k] = 0;
+      }
     }
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanK; ++k) sum += v[k];
     int x = sum;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -79,46 +383,26 @@ __global__ __launch_bounds__(1024) void k_scan(int ntiles, int* __restrict__ cou
     }
     __syncthreads();
     int excl = x - sum + (wid > 0 ? s_part[wid - 1] : 0) + s_carry;
+    int e[kScanK];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (i0 + k < ntiles) start[i0 + k] = excl;
+    for (int k = 0; k < kScanK; ++k) {
+      e[k] = excl;
       excl += v[k];
+    }
+    if (i0 + kScanK <= ntiles) {
+      int4* s4 = reinterpret_cast<int4*>(start + i0);
+#pragma unroll
+      for (int k = 0; k < kScanK / 4; ++k) s4[k] = int4{e[4 * k], e[4 * k + 1], e[4 * k + 2], e[4 * k + 3]};
+    } else {
+#pragma unroll
+      for (int k = 0; k < kScanK; ++k)
+        if (i0 + k < ntiles) start[i0 + k] = e[k];
     }
     __syncthreads();
     if (tid == 1023) s_carry = excl;
     __syncthreads();
   }
   if (tid == 0) start[ntiles] = s_carry;
-}
-
-// Sorted record: (g_x, g_y, g_z, q), the centred offsets from the support anchors, and the
-// packed anchor of the particle in its system.
-template <class T>
-__global__ void k_bin_scatter(int64_t n, int nsys, const SysDesc* __restrict__ sys,
-                              const int64_t* __restrict__ part_prefix, const T* __restrict__ pos,
-                              const T* __restrict__ q, const int* __restrict__ tile_of, const int* __restrict__ rank,
-                              const int* __restrict__ tile_start, typename Vec4<T>::type* __restrict__ sorted,
-                              int* __restrict__ cells, int* __restrict__ perm) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i >= n) return;
-  const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
-  const int dst = tile_start[tile_of[i]] + rank[i];
-  typename Vec4<T>::type r;
-  T f[3];
-  const int c0 = grid_coord(pos[3 * i + 0], T(sd.ih_hi), T(sd.ih_lo), T(sd.L), sd.m, f[0]);
-  const int c1 = grid_coord(pos[3 * i + 1], T(sd.ihy_hi), T(sd.ihy_lo), T(sd.Ly), sd.my, f[1]);
-  const int c2 = grid_coord(pos[3 * i + 2], T(sd.ihz_hi), T(sd.ihz_lo), T(sd.Lz), sd.mz, f[2]);
-  const int cx = support_anchor(c0, f[0], sd.P, sd.m, r.x);
-  const int cy = support_anchor(c1, f[1], sd.P, sd.my, r.y);
-  const int cz = support_anchor(c2, f[2], sd.P, sd.mz, r.z);
-  r.w = q ? q[i] : T(0);
-  // a non-finite position is moved to cell 0 by grid_coord; its NaN charge poisons the outputs
-  // instead (spreading adds NaN into the grid, interpolation returns NaN for it)
-  if (!(isfinite(pos[3 * i + 0]) && isfinite(pos[3 * i + 1]) && isfinite(pos[3 * i + 2])))
-    r.w = std::numeric_limits<T>::quiet_NaN();
-  sorted[dst] = r;
-  cells[dst] = pack_cell(cx, cy, cz);
-  perm[dst] = static_cast<int>(i);
 }
 
 // Input check (PSWFE_CHECK_INPUT): per system s, out[3 s] = sum q, out[3 s + 1] = sum |q| (float64)
@@ -508,6 +792,26 @@ __device__ __forceinline__ void staged_copy(int count, Load&& load, Store&& stor
   }
 }
 
+// Twiddle tables copied into LDS: the loads (up to 4 per thread, count <= 4 * blockDim.x) are
+// issued first and written to LDS only after the caller has issued its data loads, so that the
+// two round trips to memory overlap instead of following each other.
+template <class C, class Get>
+__device__ __forceinline__ void table_load(int count, Get&& get, C (&v)[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = threadIdx.x + k * blockDim.x;
+    if (e < count) v[k] = get(e);
+  }
+}
+template <class C, class Put>
+__device__ __forceinline__ void table_store(int count, Put&& put, const C (&v)[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = threadIdx.x + k * blockDim.x;
+    if (e < count) put(e, v[k]);
+  }
+}
+
 // x-direction real-to-complex FFT (sign +) of the m^2 rows of m reals of each system, via an
 // m/2-point complex FFT of (a_2j + i a_2j+1); writes X_k, k = 0..m/2, to the system's spectrum.
 // The input is the float64 grid_a (zeroed after it is read when zero_input is set) or, for a
@@ -528,18 +832,15 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(int nsys, const SysDesc* __re
   C* tw_f = tw_h + N;
   const int row0 = (static_cast<int>(blockIdx.x) - sd.xblk_base) * rpb;
   const int nr = min(rpb, nrows - row0);
-  for (int e = threadIdx.x; e < 2 * N + 1; e += blockDim.x) {
-    if (e < N)
-      tw_h[e] = gload(tw_half + e);
-    else
-      tw_f[e - N] = gload(tw_full + (e - N));
-  }
+  C twv[4];
+  table_load(2 * N + 1, [&](int e) { return e < N ? gload(tw_half + e) : gload(tw_full + (e - N)); }, twv);
   using CI = typename Cplx<TI>::type;  // a pair (a_2j, a_2j+1) of the input row, one vector load
   const TI* grid = in_override ? in_override : reinterpret_cast<const TI*>(sd.grid_a);
   const CI* src = reinterpret_cast<const CI*>(grid + static_cast<int64_t>(row0) * m);
   staged_copy<8>(
       nr * N, [&](int e) { return gload(src + e); },
       [&](int e, CI v) { A[e] = C{static_cast<T>(v.x), static_cast<T>(v.y)}; });
+  table_store(2 * N + 1, [&](int e, C v) { (e < N ? tw_h[e] : tw_f[e - N]) = v; }, twv);
   if (zero_input) {
     CI* zsrc = const_cast<CI*>(src);
     for (int e = threadIdx.x; e < nr * N; e += blockDim.x) gstore(zsrc + e, CI{TI(0), TI(0)});
@@ -578,12 +879,8 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(int nsys, const SysDesc* __re
   C* tw_f = tw_h + N;
   const int row0 = (static_cast<int>(blockIdx.x) - sd.xblk_base) * rpb;
   const int nr = min(rpb, nrows - row0);
-  for (int e = threadIdx.x; e < 2 * N; e += blockDim.x) {
-    if (e < N)
-      tw_h[e] = gload(tw_half + e);
-    else
-      tw_f[e - N] = gload(tw_full + (e - N));
-  }
+  C twv[4];
+  table_load(2 * N, [&](int e) { return e < N ? gload(tw_half + e) : gload(tw_full + (e - N)); }, twv);
   const int sp = sd.spec_pitch;
   const C* in = static_cast<const C*>(sd.spec) + static_cast<int64_t>(row0) * sp;
   staged_copy<8>(
@@ -593,6 +890,7 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(int nsys, const SysDesc* __re
         return gload(in + r * sp + k);
       },
       [&](int e, C v) { A[e] = v; });
+  table_store(2 * N, [&](int e, C v) { (e < N ? tw_h[e] : tw_f[e - N]) = v; }, twv);
   __syncthreads();
   for (int e = threadIdx.x; e < nr * N; e += blockDim.x) {
     const int r = e / N, k = e - r * N;
@@ -773,15 +1071,11 @@ __global__ __launch_bounds__(256) void k_fft_cols(int nsys, const SysDesc* __res
   C* Bf = A + cpb * ss;
   C* tw_p = Bf + cpb * ss;  // twiddles of length len: sign + then sign -
   C* tw_m = tw_p + len;
+  C twv[4];
   {
     const C* __restrict__ gp = static_cast<const C*>(mode == 1 ? sd.twzp : sd.twyp);
     const C* __restrict__ gm = static_cast<const C*>(mode == 1 ? sd.twzm : sd.twym);
-    for (int e = threadIdx.x; e < 2 * len; e += blockDim.x) {
-      if (e < len)
-        tw_p[e] = gload(gp + e);
-      else
-        tw_m[e - len] = gload(gm + (e - len));
-    }
+    table_load(2 * len, [&](int e) { return e < len ? gload(gp + e) : gload(gm + (e - len)); }, twv);
   }
   const C* tw = mode == 2 ? tw_m : tw_p;
   C* base = static_cast<C*>(sd.spec) + outer * ostride + kx0;
@@ -795,6 +1089,7 @@ __global__ __launch_bounds__(256) void k_fft_cols(int nsys, const SysDesc* __res
         const int e = i / nc, c = i - e * nc;
         A[c * ss + e] = v;
       });
+  table_store(2 * len, [&](int e, C v) { (e < len ? tw_p[e] : tw_m[e - len]) = v; }, twv);
   __syncthreads();
   C* R1 = fft_lds(A, Bf, nc, ss, pl, tw);
   if (mode == 1) {
@@ -846,16 +1141,41 @@ inline unsigned blocks_for(int64_t n, int bs) { return static_cast<unsigned>((n 
 template <class T>
 hipError_t bin_impl(const DevPlan& d, int64_t n, const void* pos, const void* q, double* energy, hipStream_t st) {
   stage_begin(d, kStageBin, st);
-  const int64_t nthreads = std::max<int64_t>(n, energy ? d.nsys : 0);
-  if (nthreads > 0)
-    hipLaunchKernelGGL(k_bin_count<T>, dim3(blocks_for(nthreads, 256)), dim3(256), 0, st, n, d.nsys, d.sys_dev,
-                       d.part_prefix, static_cast<const T*>(pos), d.sub_log2, d.tile_count, d.tile_of, d.rank,
-                       energy);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d.total_tiles << d.sub_log2, d.tile_count, d.tile_start);
+  if (d.bin_levels == 1) {
+    const int64_t nthreads = std::max<int64_t>(n, energy ? d.nsys : 0);
+    if (nthreads > 0)
+      hipLaunchKernelGGL(k_bin_count1<T>, dim3(blocks_for(nthreads, kBinThreads)), dim3(kBinThreads), 0, st, n,
+                         d.nsys, d.sys_dev, d.part_prefix, static_cast<const T*>(pos), d.sub_log2, d.tile_count,
+                         d.tile_of, d.bin_rank, energy);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, d.total_tiles << d.sub_log2, d.tile_count, d.tile_start);
+    if (n > 0)
+      hipLaunchKernelGGL(k_bin_scatter1<T>, dim3(blocks_for(n, kBinThreads)), dim3(kBinThreads), 0, st, n, d.nsys,
+                         d.sys_dev, d.part_prefix, static_cast<const T*>(pos), static_cast<const T*>(q), d.tile_of,
+                         d.bin_rank, d.tile_start, static_cast<typename Vec4<T>::type*>(d.sorted), d.cells, d.perm);
+    stage_end(d, kStageBin, st);
+    return hipGetLastError();
+  }
+  // counting: per_thread particles per thread, and at least one thread per system for the energy
+  // reset; then the coarse pass and one workgroup per coarse bucket
+  const int64_t chunk = static_cast<int64_t>(kBinThreads) * d.bin_per_thread;
+  const int64_t blocks = std::max<int64_t>(blocks_for(n, static_cast<int>(chunk)), energy ? blocks_for(d.nsys, kBinThreads) : 0);
+  if (blocks > 0)
+    hipLaunchKernelGGL(k_bin_count<T>, dim3(static_cast<unsigned>(blocks)), dim3(kBinThreads), 0, st, n, d.nsys,
+                       d.sys_dev, d.part_prefix, static_cast<const T*>(pos), d.sub_log2, d.bin_per_thread, d.bin_shift,
+                       d.bin_ncoarse, d.coarse_count, d.tile_of, energy);
   if (n > 0)
-    hipLaunchKernelGGL(k_bin_scatter<T>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, d.nsys, d.sys_dev,
-                       d.part_prefix, static_cast<const T*>(pos), static_cast<const T*>(q), d.tile_of, d.rank,
-                       d.tile_start, static_cast<typename Vec4<T>::type*>(d.sorted), d.cells, d.perm);
+    hipLaunchKernelGGL(k_bin_coarse<T>, dim3(blocks_for(n, static_cast<int>(chunk))), dim3(kBinThreads), 0, st, n,
+                       static_cast<const T*>(pos), static_cast<const T*>(q), d.bin_per_thread, d.bin_shift,
+                       d.bin_ncoarse, d.coarse_count, d.coarse_cursor, d.coarse_start, d.tile_of,
+                       static_cast<typename Vec4<T>::type*>(d.bin_tmp), d.bin_tmp_ib);
+  else
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t*>(d.coarse_start),
+                       static_cast<int64_t>(kCoarse + 1));
+  hipLaunchKernelGGL(k_bin_fine<T>, dim3(d.bin_ncoarse), dim3(kFineThreads),
+                     sizeof(int) * ((size_t(1) << d.bin_shift) + kFineThreads / 64), st, n, d.nsys, d.sys_dev,
+                     d.part_prefix, d.bin_shift, d.bin_ncoarse, d.total_tiles << d.sub_log2, d.coarse_start,
+                     d.coarse_count, d.coarse_cursor, static_cast<const typename Vec4<T>::type*>(d.bin_tmp),
+                     d.bin_tmp_ib, d.tile_start, static_cast<typename Vec4<T>::type*>(d.sorted), d.cells, d.perm);
   stage_end(d, kStageBin, st);
   return hipGetLastError();
 }

@@ -149,6 +149,14 @@ inline size_t col_lds_bytes(int P, int D, int B) {
          sizeof(int) * kColBatchHost * 4;
 }
 
+// binning: at most kCoarse coarse buckets, counted in kCoarseCopies copies (workgroup w adds
+// into copy w % kCoarseCopies, so fewer atomics queue on one address), and at most
+// kBinMaxPerThread particles per thread
+constexpr int kCoarse = 256;
+constexpr int kCoarseCopies = 16;
+constexpr int kBinMaxPerThread = 8;
+constexpr int kBinMaxFine = 16384;  // buckets per coarse bucket (LDS counters of the fine pass)
+
 struct DevPlan {
   int prec = 0;               // 0 float, 1 double
   int nsys = 0;
@@ -169,15 +177,25 @@ struct DevPlan {
   int64_t* part_prefix = nullptr;  // nsys + 1 (batches; a single system takes n per call)
   int total_tiles = 0, total_xblk = 0, total_cblk = 0;
   size_t lds_x = 0, lds_c = 0;     // maxima over the systems
-  // binning, over all systems. Each tile's counter is split into 2^sub_log2 sub-buckets by
-  // the particle's z-cell within the tile, so fewer atomics queue on one address and a tile's
-  // particles come out ordered by z; a tile's particles stay contiguous: tile t owns
-  // [tile_start[t << sub_log2], tile_start[(t+1) << sub_log2]).
+  // binning, over all systems. Each tile is split into 2^sub_log2 buckets by the particle's
+  // z-cell within the tile, so a tile's particles come out ordered by z; a tile's particles stay
+  // contiguous: tile t owns [tile_start[t << sub_log2], tile_start[(t+1) << sub_log2]). The sort
+  // runs in two levels: coarse buckets (bucket >> bin_shift, bin_ncoarse <= kCoarse of them), then
+  // the buckets within each coarse bucket.
   int sub_log2 = 0;
-  int* tile_count = nullptr;   // total_tiles << sub_log2, kept all-zero between calls
+  int bin_levels = 2;          // 1: one-level sort (small systems), 2: two-level sort
+  int* tile_count = nullptr;   // one-level: total_tiles << sub_log2, kept all-zero between calls
+  int* bin_rank = nullptr;     // one-level: n_max ranks within the bucket (over bin_tmp_ib)
+  int bin_shift = 0;
+  int bin_ncoarse = 1;
+  int bin_per_thread = 1;      // particles per thread in the counting and coarse passes
+  int* coarse_count = nullptr; // kCoarseCopies x kCoarse, kept all-zero between calls
+  int* coarse_cursor = nullptr;// kCoarseCopies x kCoarse, kept all-zero between calls
+  int* coarse_start = nullptr; // kCoarse + 1
+  void* bin_tmp = nullptr;     // n_max x 4: (x, y, z, q) in coarse-bucket order
+  int2* bin_tmp_ib = nullptr;  // n_max: (input index, bucket) in coarse-bucket order
   int* tile_start = nullptr;   // (total_tiles << sub_log2) + 1
   int* tile_of = nullptr;      // n_max: bucket of each particle
-  int* rank = nullptr;         // n_max
   int* perm = nullptr;         // n_max: sorted slot -> packed input index
   int* cells = nullptr;        // n_max: packed cell cx + m (cy + m cz) of each sorted particle
   void* sorted = nullptr;      // n_max x 4: (f_x, f_y, f_z, q), fractional cell offsets in [0, 1]

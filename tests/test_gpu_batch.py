@@ -97,8 +97,10 @@ def mixed_systems(prec):
     return out
 
 
+@pytest.mark.parametrize("levels", ["1", "2"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_mixed_batch_matches_oracle_and_sequential(prec):
+def test_mixed_batch_matches_oracle_and_sequential(prec, levels, monkeypatch):
+    monkeypatch.setenv("PSWFE_BIN_LEVELS", levels)   # one-level or two-level binning of the batch
     systems = mixed_systems(prec)
     assert len({s[4].P for s in systems}) >= 2           # several P groups in one plan
     pos, q = pack([(s[0], s[1]) for s in systems], prec)
@@ -112,7 +114,7 @@ def test_mixed_batch_matches_oracle_and_sequential(prec):
     E = E.cpu().numpy()
     phis, Fs = plan.split(phi.cpu().numpy()), plan.split(F.cpu().numpy())
     for k, (x, qq, L, eps, c, o) in enumerate(systems):
-        check_vs_oracle(x, qq, o, phis[k], Fs[k], float(E[k]), eps, prec, c=c, name=f"mixed-batch-{prec}-sys{k}")
+        check_vs_oracle(x, qq, o, phis[k], Fs[k], float(E[k]), eps, prec, c=c, name=f"mixed-batch-{prec}-bin{levels}-sys{k}")
     # sequential single-system plans with the same tiles
     tol = 1e-6 if prec == "fp32" else 1e-12
     for k, (x, qq, L, eps, c, o) in enumerate(systems):

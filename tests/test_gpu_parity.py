@@ -229,6 +229,25 @@ def test_dense_tiles_shared_by_workgroups(case, prec, parts, monkeypatch):
     assert abs(float(E.cpu()[0]) - Eref) <= tol_phi * 0.5 * float(np.abs(q) @ np.abs(far)) + 1e-12 * abs(Eref)
 
 
+@pytest.mark.parametrize("levels", ["1", "2"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_one_crowded_bucket(prec, levels, monkeypatch):
+    """12,000 particles in one grid cell plus 2,000 spread over the box: one bucket holds more
+    particles than the two-level sort keeps in registers per coarse bucket (8 x 1,024), so its
+    fine pass reads the bucket twice; the results match the oracle element by element."""
+    monkeypatch.setenv("PSWFE_BIN_LEVELS", levels)
+    rng = np.random.default_rng(31)
+    L, eps = 1.0, 1e-6
+    x = np.concatenate([0.5 + 0.02 * rng.random((12000, 3)), rng.random((2000, 3))])
+    q = rng.choice([-1.0, 1.0], size=len(x))
+    q -= q.mean()
+    x, q = rounded(x, prec), rounded(q, prec)
+    c, o = both_params(eps, L, m=16)
+    plan = pw.Plan(c, prec, n_max=len(q))
+    phi, F, E = plan.compute(tdev(x, prec), tdev(q, prec))
+    check_elementwise(f"crowded-bucket-{prec}-bin{levels}", phi, F, x, q, c, o, eps, prec)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64", "fp32_arith"])
 def test_single_charge_window_precision(prec):
     """One unit charge far from the origin (x/h ~ m): every grid value of its support within a few
@@ -302,10 +321,13 @@ def test_interpolate_matches_oracle(case, prec):
              coef, eps, prec, vec_is_force=False, global_part=False)
 
 
+@pytest.mark.parametrize("levels", ["1", "2"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_arith"])
 @pytest.mark.parametrize("case", SMALL, ids=[c[0] for c in SMALL])
-def test_compute_matches_fast_oracle(case, prec):
-    """Whole pipeline against Alg. 2 in float64: phi, forces and energy."""
+def test_compute_matches_fast_oracle(case, prec, levels, monkeypatch):
+    """Whole pipeline against Alg. 2 in float64: phi, forces and energy, with either binning
+    (one-level counting sort, or the two-level sort that large systems take)."""
+    monkeypatch.setenv("PSWFE_BIN_LEVELS", levels)
     _, gen, eps, kw = case
     if prec != "fp64" and eps < 1e-6:
         pytest.skip("fp32 path is for eps >= 1e-6")
@@ -313,7 +335,7 @@ def test_compute_matches_fast_oracle(case, prec):
     c, o = both_params(eps, L, **kw)
     plan = pw.Plan(c, prec, n_max=len(q))
     phi, F, E = plan.compute(tdev(x, prec), tdev(q, prec))
-    check_elementwise(f"compute-{case[0]}-{prec}", phi, F, x, q, c, o, eps, prec)
+    check_elementwise(f"compute-{case[0]}-{prec}-bin{levels}", phi, F, x, q, c, o, eps, prec)
     phi, F, E = phi.cpu().numpy(), F.cpu().numpy(), float(E.cpu().numpy()[0])
     rphi, rg = fast.fast_longrange(x, q, o)
     rF = direct.forces(q, rg)
@@ -347,7 +369,9 @@ def test_plain_config_vs_direct_sum(prec):
     assert rel_l2(F, direct.forces(q, gref)) < 1e-5
 
 
-def test_edge_cases():
+@pytest.mark.parametrize("levels", ["1", "2"])
+def test_edge_cases(levels, monkeypatch):
+    monkeypatch.setenv("PSWFE_BIN_LEVELS", levels)
     d = dev()
     c = pw.choose_params(1e-6, 1.0, m=16)
     plan = pw.Plan(c, "fp64", n_max=64)
