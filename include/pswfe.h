@@ -229,9 +229,11 @@ pswfe_status pswfe_compute(pswfe_plan* plan, int64_t n, const void* pos, const v
  *   p, prec  parameters (as for pswfe_plan_create) and pswfe_prec
  *   n        number of particles (0 <= n < 2^31); pos, q, phi, force, energy, stream as for pswfe_compute
  * The configuration's buffers must fit the array: about 17 m^3 (float32) or 25 m^3 (float64)
- * bytes of grids and spectrum plus 32 (float32) or 48 (float64) bytes per particle and a few KiB
- * of tables (the 64^3 water box with 30,000 particles needs about 6 MiB; a 128^3 float32 grid
- * fits up to about 970,000 particles); larger configurations return PSWFE_E_CAPACITY before any
+ * bytes of grids and spectrum plus, per particle, 36 (float32) or 52 (float64) bytes below
+ * 200,000 particles and 52 or 84 bytes from there on (the two-level sort of large systems keeps a
+ * staging copy of the records), and a few KiB of tables (the 64^3 water box with 30,000
+ * particles needs about 6 MiB; a 128^3 float32 grid fits up to about 600,000 particles); larger
+ * configurations return PSWFE_E_CAPACITY before any
  * device work. The first call of a configuration (parameters,
  * precision, n) on a GPU builds its tables on the host (host memory; the last 8 configurations
  * are kept); a call uploads them into the array (a host-to-device copy on `stream`) when another

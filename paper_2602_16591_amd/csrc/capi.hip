@@ -585,7 +585,8 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   const size_t o_tile_count = dev.take(sizeof(int) * nbuckets);
   const size_t o_tile_start = dev.take(sizeof(int) * (nbuckets + 1));
   const size_t o_tile_of = dev.take(sizeof(int) * nm);
-  const size_t o_bin_tmp = dev.take(4 * static_cast<size_t>(elem) * nm);
+  // the two-level sort's staging copy of the records (one-level plans use none)
+  const size_t o_bin_tmp = d.bin_levels == 2 ? dev.take(4 * static_cast<size_t>(elem) * nm) : 0;
   const size_t o_bin_tmp_ib = dev.take(sizeof(int2) * nm);
   const size_t o_perm = dev.take(sizeof(int) * nm);
   const size_t o_cells = dev.take(sizeof(int) * nm);
@@ -638,7 +639,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   d.coarse_start = d.coarse_cursor + pswfe::kCoarseCopies * pswfe::kCoarse;
   d.tile_start = reinterpret_cast<int*>(base + o_tile_start);
   d.tile_of = reinterpret_cast<int*>(base + o_tile_of);
-  d.bin_tmp = base + o_bin_tmp;
+  d.bin_tmp = d.bin_levels == 2 ? base + o_bin_tmp : nullptr;
   d.bin_tmp_ib = reinterpret_cast<int2*>(base + o_bin_tmp_ib);
   d.bin_rank = reinterpret_cast<int*>(base + o_bin_tmp_ib);
   d.tile_count = reinterpret_cast<int*>(base + o_tile_count);
