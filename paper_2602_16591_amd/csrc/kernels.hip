@@ -31,6 +31,8 @@ namespace {
 // ------------------------------------------------------------------------------------
 constexpr int kBinThreads = 256;
 constexpr int kFineThreads = 1024;
+constexpr int kFineStage = 128 * 1024;     // LDS staging of the fine pass's records
+constexpr size_t kFineLdsMax = 160 * 1024; // LDS per workgroup on gfx950
 
 // Tile bucket of a particle at (x, y, z) (the anchor's tile, and within it the sub-bucket of the
 // z-cell: a tile's particles come out ordered by z, so the slices of a tile shared by several
@@ -127,6 +129,13 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t n, int nsys, 
     if (hist[c] > 0) atomicAdd(&mine[c], hist[c]);
 }
 
+// LDS of the coarse pass: coarse starts, counts, local starts, wave sums, then the workgroup's
+// records and (index, bucket) pairs in coarse-bucket order.
+template <class T>
+constexpr size_t coarse_lds_bytes() {
+  return sizeof(int) * (3 * kCoarse + 16) + (sizeof(typename Vec4<T>::type) + sizeof(int2)) * kBinThreads * kBinMaxPerThread;
+}
+
 template <class T>
 __global__ __launch_bounds__(kBinThreads) void k_bin_coarse(int64_t n, const T* __restrict__ pos,
                                                          const T* __restrict__ q, int per_thread, int shift,
@@ -135,15 +144,20 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_coarse(int64_t n, const T* 
                                                          int* __restrict__ coarse_start, const int* __restrict__ key,
                                                          typename Vec4<T>::type* __restrict__ tmp_rec,
                                                          int2* __restrict__ tmp_ib) {
-  __shared__ int s_start[kCoarse];
-  __shared__ int hist[kCoarse];
-  __shared__ int s_wave[kBinThreads / 64];
+  using V = typename Vec4<T>::type;
+  extern __shared__ int smem_int[];
+  int* s_start = smem_int;                 // kCoarse
+  int* hist = s_start + kCoarse;           // kCoarse: counts, then the global slot of each run
+  int* s_lp = hist + kCoarse;              // kCoarse: start of each coarse bucket's run in the stage
+  int* s_wave = s_lp + kCoarse;            // 16
+  V* st_rec = reinterpret_cast<V*>(s_wave + 16);
+  int2* st_ib = reinterpret_cast<int2*>(st_rec + kBinThreads * kBinMaxPerThread);
   const int tid = threadIdx.x;
   const int copy = blockIdx.x % kCoarseCopies;
   const int64_t i0 = blockIdx.x * static_cast<int64_t>(kBinThreads) * per_thread + tid;
   // this thread's particles: bucket, position and charge, all loads issued at once
   int kb[kBinMaxPerThread], lr[kBinMaxPerThread];
-  typename Vec4<T>::type r[kBinMaxPerThread];
+  V r[kBinMaxPerThread];
 #pragma unroll
   for (int k = 0; k < kBinMaxPerThread; ++k) {
     const int64_t i = i0 + static_cast<int64_t>(k) * kBinThreads;
@@ -180,23 +194,38 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_coarse(int64_t n, const T* 
   for (int k = 0; k < kBinMaxPerThread; ++k)
     if (kb[k] >= 0) lr[k] = atomicAdd(&hist[kb[k] >> shift], 1);
   __syncthreads();
+  if (tid < kCoarse) s_lp[tid] = tid < ncoarse ? hist[tid] : 0;
+  __syncthreads();
+  const int cnt = block_scan_lds(s_lp, ncoarse, s_wave);
   // each nonzero count becomes the workgroup's first slot in that coarse bucket
   if (tid < ncoarse && hist[tid] > 0)
     hist[tid] = s_start[tid] + own + atomicAdd(&coarse_cursor[copy * kCoarse + tid], hist[tid]);
-  __syncthreads();
+  // the workgroup's particles in coarse-bucket order in LDS
 #pragma unroll
   for (int k = 0; k < kBinMaxPerThread; ++k) {
     if (kb[k] < 0) continue;
-    const int dst = hist[kb[k] >> shift] + lr[k];
+    const int sp = s_lp[kb[k] >> shift] + lr[k];
+    st_rec[sp] = r[k];
+    st_ib[sp] = int2{static_cast<int>(i0 + static_cast<int64_t>(k) * kBinThreads), kb[k]};
+  }
+  __syncthreads();
+  // then stored run by run: consecutive lanes on consecutive slots of one coarse bucket
+  for (int p = tid; p < cnt; p += kBinThreads) {
+    const int2 iv = st_ib[p];
+    const int cb = iv.y >> shift;
+    const int dst = hist[cb] + (p - s_lp[cb]);
     if (dst >= n) continue;  // only if the coarse counters were not zero at the start
-    tmp_rec[dst] = r[k];
-    tmp_ib[dst] = int2{static_cast<int>(i0 + static_cast<int64_t>(k) * kBinThreads), kb[k]};
+    tmp_rec[dst] = st_rec[p];
+    tmp_ib[dst] = iv;
   }
 }
 
 // Sorted record: (g_x, g_y, g_z, q), the centred offsets from the support anchors, and the
 // packed anchor of the particle in its system. A coarse bucket of up to kFineRes items per thread
-// is held in registers from one round of loads; larger ones are read twice.
+// is held in registers from one round of loads; when `staged`, its records are then put in bucket
+// order in LDS (kFineStage bytes at a time) and stored with consecutive lanes on consecutive
+// addresses, instead of one scattered store per lane. Larger coarse buckets are read twice and
+// stored directly.
 constexpr int kFineRes = 8;
 template <class T>
 __global__ __launch_bounds__(kFineThreads) void k_bin_fine(int64_t n, int nsys, const SysDesc* __restrict__ sys,
@@ -206,12 +235,14 @@ __global__ __launch_bounds__(kFineThreads) void k_bin_fine(int64_t n, int nsys, 
                                                         const typename Vec4<T>::type* __restrict__ tmp_rec,
                                                         const int2* __restrict__ tmp_ib, int* __restrict__ tile_start,
                                                         typename Vec4<T>::type* __restrict__ sorted,
-                                                        int* __restrict__ cells, int* __restrict__ perm) {
+                                                        int* __restrict__ cells, int* __restrict__ perm, int staged) {
   using V = typename Vec4<T>::type;
   extern __shared__ int smem_int[];
   const int nf = 1 << shift;
   int* fine = smem_int;             // nf: counts, then cursors
   int* s_wave = smem_int + nf;      // kFineThreads / 64
+  // staging area, 16-byte aligned, after the counters
+  unsigned char* stage = reinterpret_cast<unsigned char*>(smem_int + ((nf + kFineThreads / 64 + 3) & ~3));
   const int tid = threadIdx.x, c = blockIdx.x;
   // clamped to [0, n]: the ranges are inside the particle arrays whatever the counters held
   const int s1 = static_cast<int>(min<int64_t>(max(coarse_start[c + 1], 0), n));
@@ -252,12 +283,10 @@ __global__ __launch_bounds__(kFineThreads) void k_bin_fine(int64_t n, int nsys, 
     coarse_cursor[k * kCoarse + c] = 0;
   }
   __syncthreads();
-  auto place = [&](const V& rv, int2 iv) {
+  // the final record of one item, and its slot (or -1 when the counters were inconsistent)
+  auto finish = [&](const V rv, int2 iv, V& rec, int& cell) {  // rv by value: rec may be its source
     const int dst = atomicAdd(&fine[iv.y & (nf - 1)], 1);
-    if (dst >= s1) return;
     const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, static_cast<int64_t>(iv.x))];
-    V rec;
-    int cell;
     T g[3];
     bin_bucket(sd, 0, rv.x, rv.y, rv.z, cell, g);
     rec.x = g[0];
@@ -267,16 +296,68 @@ __global__ __launch_bounds__(kFineThreads) void k_bin_fine(int64_t n, int nsys, 
     // a non-finite position is moved to cell 0 by grid_coord; its NaN charge poisons the outputs
     // instead (spreading adds NaN into the grid, interpolation returns NaN for it)
     if (!(isfinite(rv.x) && isfinite(rv.y) && isfinite(rv.z))) rec.w = std::numeric_limits<T>::quiet_NaN();
-    sorted[dst] = rec;
-    cells[dst] = cell;
-    perm[dst] = iv.x;
+    return dst < s1 ? dst : -1;
   };
-  if (resident) {
+  if (!resident) {
+    for (int j = s0 + tid; j < s1; j += kFineThreads) {
+      const int2 iv = tmp_ib[j];
+      V rec;
+      int cell;
+      const int dst = finish(tmp_rec[j], iv, rec, cell);
+      if (dst < 0) continue;
+      sorted[dst] = rec;
+      cells[dst] = cell;
+      perm[dst] = iv.x;
+    }
+    return;
+  }
+  int slot[kFineRes], cl[kFineRes];
 #pragma unroll
-    for (int u = 0; u < kFineRes; ++u)
-      if (s0 + tid + u * kFineThreads < s1) place(r[u], ib[u]);
-  } else {
-    for (int j = s0 + tid; j < s1; j += kFineThreads) place(tmp_rec[j], tmp_ib[j]);
+  for (int u = 0; u < kFineRes; ++u) {
+    slot[u] = -1;
+    if (s0 + tid + u * kFineThreads < s1) {
+      const int dst = finish(r[u], ib[u], r[u], cl[u]);
+      slot[u] = dst < 0 ? -1 : dst - s0;
+    }
+  }
+  if (!staged) {
+#pragma unroll
+    for (int u = 0; u < kFineRes; ++u) {
+      if (slot[u] < 0) continue;
+      sorted[s0 + slot[u]] = r[u];
+      cells[s0 + slot[u]] = cl[u];
+      perm[s0 + slot[u]] = ib[u].x;
+    }
+    return;
+  }
+  const int cnt = s1 - s0;
+  {
+    V* sv = reinterpret_cast<V*>(stage);
+    constexpr int cap = kFineStage / static_cast<int>(sizeof(V));
+    for (int w0 = 0; w0 < cnt; w0 += cap) {
+#pragma unroll
+      for (int u = 0; u < kFineRes; ++u)
+        if (slot[u] >= w0 && slot[u] < w0 + cap) sv[slot[u] - w0] = r[u];
+      __syncthreads();
+      for (int p = tid; p < min(cap, cnt - w0); p += kFineThreads) sorted[s0 + w0 + p] = sv[p];
+      __syncthreads();
+    }
+  }
+  {
+    int2* sv = reinterpret_cast<int2*>(stage);
+    constexpr int cap = kFineStage / static_cast<int>(sizeof(int2));
+    for (int w0 = 0; w0 < cnt; w0 += cap) {
+#pragma unroll
+      for (int u = 0; u < kFineRes; ++u)
+        if (slot[u] >= w0 && slot[u] < w0 + cap) sv[slot[u] - w0] = int2{cl[u], ib[u].x};
+      __syncthreads();
+      for (int p = tid; p < min(cap, cnt - w0); p += kFineThreads) {
+        const int2 v = sv[p];
+        cells[s0 + w0 + p] = v.x;
+        perm[s0 + w0 + p] = v.y;
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -1164,18 +1245,22 @@ hipError_t bin_impl(const DevPlan& d, int64_t n, const void* pos, const void* q,
                        d.sys_dev, d.part_prefix, static_cast<const T*>(pos), d.sub_log2, d.bin_per_thread, d.bin_shift,
                        d.bin_ncoarse, d.coarse_count, d.tile_of, energy);
   if (n > 0)
-    hipLaunchKernelGGL(k_bin_coarse<T>, dim3(blocks_for(n, static_cast<int>(chunk))), dim3(kBinThreads), 0, st, n,
+    hipLaunchKernelGGL(k_bin_coarse<T>, dim3(blocks_for(n, static_cast<int>(chunk))), dim3(kBinThreads),
+                       coarse_lds_bytes<T>(), st, n,
                        static_cast<const T*>(pos), static_cast<const T*>(q), d.bin_per_thread, d.bin_shift,
                        d.bin_ncoarse, d.coarse_count, d.coarse_cursor, d.coarse_start, d.tile_of,
                        static_cast<typename Vec4<T>::type*>(d.bin_tmp), d.bin_tmp_ib);
   else
     hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t*>(d.coarse_start),
                        static_cast<int64_t>(kCoarse + 1));
-  hipLaunchKernelGGL(k_bin_fine<T>, dim3(d.bin_ncoarse), dim3(kFineThreads),
-                     sizeof(int) * ((size_t(1) << d.bin_shift) + kFineThreads / 64), st, n, d.nsys, d.sys_dev,
-                     d.part_prefix, d.bin_shift, d.bin_ncoarse, d.total_tiles << d.sub_log2, d.coarse_start,
-                     d.coarse_count, d.coarse_cursor, static_cast<const typename Vec4<T>::type*>(d.bin_tmp),
-                     d.bin_tmp_ib, d.tile_start, static_cast<typename Vec4<T>::type*>(d.sorted), d.cells, d.perm);
+  // counters, then the staging area (when it fits beside them)
+  const size_t counters = sizeof(int) * (((size_t(1) << d.bin_shift) + kFineThreads / 64 + 3) & ~size_t(3));
+  const bool staged = counters + kFineStage <= kFineLdsMax;
+  hipLaunchKernelGGL(k_bin_fine<T>, dim3(d.bin_ncoarse), dim3(kFineThreads), counters + (staged ? kFineStage : 0), st,
+                     n, d.nsys, d.sys_dev, d.part_prefix, d.bin_shift, d.bin_ncoarse, d.total_tiles << d.sub_log2,
+                     d.coarse_start, d.coarse_count, d.coarse_cursor,
+                     static_cast<const typename Vec4<T>::type*>(d.bin_tmp), d.bin_tmp_ib, d.tile_start,
+                     static_cast<typename Vec4<T>::type*>(d.sorted), d.cells, d.perm, staged ? 1 : 0);
   stage_end(d, kStageBin, st);
   return hipGetLastError();
 }
@@ -1262,6 +1347,9 @@ hipError_t raise_fft_lds(const DevPlan& d) {
   if (e == hipSuccess) e = set(reinterpret_cast<const void*>(&k_fft_x_r2c<T, double>), d.lds_x);
   if (e == hipSuccess) e = set(reinterpret_cast<const void*>(&k_fft_x_c2r<T>), d.lds_x);
   if (e == hipSuccess) e = set(reinterpret_cast<const void*>(&k_fft_cols<T>), d.lds_c);
+  // the binning fine pass stages its records in up to kFineLdsMax bytes
+  if (e == hipSuccess && d.bin_levels == 2) e = set(reinterpret_cast<const void*>(&k_bin_fine<T>), kFineLdsMax);
+  if (e == hipSuccess && d.bin_levels == 2) e = set(reinterpret_cast<const void*>(&k_bin_coarse<T>), coarse_lds_bytes<T>());
   return e;
 }
 
