@@ -92,6 +92,31 @@ __device__ __forceinline__ void stage_coefficients(const double* __restrict__ co
   }
 }
 
+// The same in two halves, so that other loads can be issued in between: coef_load reads this
+// thread's entries (at most kCoefPerThread; P * coef_stride(D) <= kCoefPerThread * blockDim.x)
+// into registers, coef_store writes them to LDS.
+constexpr int kCoefPerThread = 3;
+template <int P, int D>
+__device__ __forceinline__ void coef_load(const double* __restrict__ coef, int deg, double (&v)[kCoefPerThread]) {
+  constexpr int CS = coef_stride(D);
+  const global_ptr<double> gcoef = as_global(coef);
+#pragma unroll
+  for (int u = 0; u < kCoefPerThread; ++u) {
+    const int i = threadIdx.x + u * blockDim.x;
+    const int j = i / CS, k = i - j * CS;
+    v[u] = (i < P * CS && k <= deg) ? gcoef[j * (deg + 1) + k] : 0.0;
+  }
+}
+template <int P, int D>
+__device__ __forceinline__ void coef_store(double* lcoef, const double (&v)[kCoefPerThread]) {
+  constexpr int CS = coef_stride(D);
+#pragma unroll
+  for (int u = 0; u < kCoefPerThread; ++u) {
+    const int i = threadIdx.x + u * blockDim.x;
+    if (i < P * CS) lcoef[i] = v[u];
+  }
+}
+
 // Spreading (Alg. 2 step 1): the tile accumulates q w_x w_y w_z over the supports with LDS
 // float64 atomic adds (on gfx950 about 20x the throughput of float32 LDS atomics), then adds
 // the tile into its system's float64 HBM grid with atomics (a point lies in the halos of up
@@ -117,7 +142,7 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_spread(const type
   int p0, p1;
   tile_slice(tile_start, gtile, sub_log2, wgid % parts, parts, p0, p1);
   if (p0 == p1) return;
-  const SysDesc& sd = sys[tile_sys[find_sys(tile_prefix, nsys, gtile)]];
+  const SysDesc& sd = sys[nsys == 1 ? 0 : tile_sys[find_sys(tile_prefix, nsys, gtile)]];
   const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S;
   double* __restrict__ grid = sd.grid_a;
   double* acc = reinterpret_cast<double*>(smem_raw);
@@ -242,7 +267,7 @@ __global__ __launch_bounds__((col_threads<P, B>())) void k_spread_cols(
   int p0, p1;
   tile_slice(tile_start, gtile, sub_log2, wgid % parts, parts, p0, p1);
   if (p0 == p1) return;
-  const SysDesc& sd = sys[tile_sys[find_sys(tile_prefix, nsys, gtile)]];
+  const SysDesc& sd = sys[nsys == 1 ? 0 : tile_sys[find_sys(tile_prefix, nsys, gtile)]];
   const int m = sd.m, Tn = sd.Tn;
   double* __restrict__ grid = sd.grid_a;
   double* lcoef = reinterpret_cast<double*>(smem_raw);  // P * CS
@@ -398,7 +423,7 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
   int p0, p1;
   tile_slice(tile_start, gtile, sub_log2, wgid % parts, parts, p0, p1);
   if (p0 == p1) return;
-  const SysDesc& sd = sys[tile_sys[find_sys(tile_prefix, nsys, gtile)]];
+  const SysDesc& sd = sys[nsys == 1 ? 0 : tile_sys[find_sys(tile_prefix, nsys, gtile)]];
   const int m = sd.m, Tn = sd.Tn;
   double* __restrict__ grid = sd.grid_a;
   double* lcoef = reinterpret_cast<double*>(smem_raw);     // P * CS
@@ -410,8 +435,12 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
   const int tile = gtile - sd.tile_base;
   const int tx = tile % Tn, ty = (tile / Tn) % sd.Tny, tz = tile / (Tn * sd.Tny);
   const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
-  stage_coefficients<P, D>(sd.coef, sd.deg, lcoef);
   const int t = threadIdx.x;
+  // the first batch's records are loaded before the coefficients are staged: the two round
+  // trips to memory overlap
+  auto r_next = sorted[min(p0 + t, p1 - 1)];
+  int c_next = cells[min(p0 + t, p1 - 1)];
+  stage_coefficients<P, D>(sd.coef, sd.deg, lcoef);
   const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int lr = lane & 15, lk = lane >> 4;
   // waves whose row pieces are all inside the block run the group loop without per-piece checks
@@ -440,8 +469,6 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
   for (int u = 0; u < kMfmaPieces; ++u)
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[u][c] = acc_t{0, 0, 0, 0};
-  auto r_next = sorted[min(p0 + t, p1 - 1)];
-  int c_next = cells[min(p0 + t, p1 - 1)];
   for (int b0 = p0; b0 < p1; b0 += kColBatch) {
     const int nb = min(kColBatch, p1 - b0);
     const auto r = r_next;
@@ -631,7 +658,7 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
   int p0, p1;
   tile_slice(tile_start, gtile, sub_log2, wgid % parts, parts, p0, p1);
   if (p0 == p1) return;
-  const int s = tile_sys[find_sys(tile_prefix, nsys, gtile)];
+  const int s = nsys == 1 ? 0 : tile_sys[find_sys(tile_prefix, nsys, gtile)];
   const SysDesc& sd = sys[s];
   const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S;
   const global_ptr<T> grid = as_global(grid_override ? grid_override : static_cast<const T*>(sd.grid_b));
@@ -646,23 +673,28 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
   const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
   const int half = (P + 1) / 2;
   const int Ox = T0x + 1 - half, Oy = T0y + 1 - half, Oz = T0z + 1 - half;
-  stage_coefficients<P, D>(sd.coef, sd.deg, lcoef);
+  const int slot = threadIdx.x >> 4;
+  // the first particles' records are loaded before the grid block is staged: the two round
+  // trips to memory overlap
+  auto r_next = sorted[min(p0 + slot, p1 - 1)];
+  int c_next = cells[min(p0 + slot, p1 - 1)];
+  int i_next = perm[min(p0 + slot, p1 - 1)];
+  static_assert(P * coef_stride(D) <= kCoefPerThread * 256, "coefficients per thread");
+  double cv[kCoefPerThread];
+  coef_load<P, D>(sd.coef, sd.deg, cv);
   {
     T v[8];
     walk_tile<8>(
         S, m, sd.my, sd.mz, Ox, Oy, Oz, [&](int k, int, int64_t gi) { v[k] = grid[gi]; },
         [&](int k, int li_, int64_t) { tb[li_] = v[k]; });
   }
+  coef_store<P, D>(lcoef, cv);
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int slot = threadIdx.x >> 4;
   const int li = lane & (kLanesPerParticle - 1);
   G* rec = recs + slot * REC;
   const int nt = p1 - p0;
   double esum = 0.0;
-  auto r_next = sorted[min(p0 + slot, p1 - 1)];
-  int c_next = cells[min(p0 + slot, p1 - 1)];
-  int i_next = perm[min(p0 + slot, p1 - 1)];
   for (int base = 0; base < nt; base += nslots) {
     const int pi = p0 + base + slot;
     const bool active = pi < p1;
