@@ -639,62 +639,33 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
 // grid_override (single system) replaces the system's grid_b; energy holds one double per
 // system. G is the arithmetic of the window values and sums: float64, or float32 for the float32
 // arithmetic path (the potential, self term and energy are then still formed in float64).
+//
+// The particles [p0, p1) of one tile against its S^3 block in LDS (tb, x fastest). The first
+// records (at p0 + slot) are passed in, loaded by the caller.
 template <class T, int P, int D, class G>
-__global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const typename Vec4<T>::type* __restrict__ sorted,
-                                                const int* __restrict__ cells, const int* __restrict__ perm,
-                                                const int* __restrict__ tile_start, int sub_log2, int nsys,
-                                                const SysDesc* __restrict__ sys, const int* __restrict__ tile_prefix,
-                                                const int* __restrict__ tile_sys, int tile_offset, int parts, int xcd,
-                                                const T* __restrict__ grid_override, T* __restrict__ phi,
-                                                T* __restrict__ vec, int vec_mode, int add_self,
-                                                double* __restrict__ energy, const double* __restrict__ phi_add,
-                                                const double* __restrict__ vec_add) {
+struct GatherOut {
+  T* phi;
+  T* vec;
+  int vec_mode, add_self;
+  const double* phi_add;
+  const double* vec_add;
+};
+
+template <class T, int P, int D, class G>
+__device__ __forceinline__ void gather_tile(const typename Vec4<T>::type* __restrict__ sorted,
+                                            const int* __restrict__ cells, const int* __restrict__ perm, int p0,
+                                            int p1, int T0x, int T0y, int T0z, int S, const T* tb, G* recs,
+                                            const double* lcoef, const SysDesc& sd,
+                                            const GatherOut<T, P, D, G>& out, typename Vec4<T>::type r_next,
+                                            int c_next, int i_next, double& esum) {
   constexpr int REC = 6 * P;  // values x, y, z then derivatives x, y, z (d/dg)
   constexpr int CS = coef_stride(D);
-  // dynamic LDS only (see k_spread_mfma)
-  extern __shared__ unsigned char smem_raw[];
-  const int wgid = tile_order_block(xcd);
-  const int gtile = tile_offset + wgid / parts;
-  int p0, p1;
-  tile_slice(tile_start, gtile, sub_log2, wgid % parts, parts, p0, p1);
-  if (p0 == p1) return;
-  const int s = nsys == 1 ? 0 : tile_sys[find_sys(tile_prefix, nsys, gtile)];
-  const SysDesc& sd = sys[s];
-  const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S;
-  const global_ptr<T> grid = as_global(grid_override ? grid_override : static_cast<const T*>(sd.grid_b));
-  const double inv_hx = sd.inv_h, inv_hy = sd.inv_hy, inv_hz = sd.inv_hz, self_coef = sd.self_coef;
   const int nslots = blockDim.x / kLanesPerParticle;
-  double* s_red = reinterpret_cast<double*>(smem_raw);             // 16: the energy's per-wave sums
-  double* lcoef = s_red + 16;                                      // P * CS
-  G* recs = reinterpret_cast<G*>(lcoef + P * CS);                  // nslots * REC
-  T* tb = reinterpret_cast<T*>(recs + nslots * REC);
-  const int tile = gtile - sd.tile_base;
-  const int tx = tile % Tn, ty = (tile / Tn) % sd.Tny, tz = tile / (Tn * sd.Tny);
-  const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
-  const int half = (P + 1) / 2;
-  const int Ox = T0x + 1 - half, Oy = T0y + 1 - half, Oz = T0z + 1 - half;
-  const int slot = threadIdx.x >> 4;
-  // the first particles' records are loaded before the grid block is staged: the two round
-  // trips to memory overlap
-  auto r_next = sorted[min(p0 + slot, p1 - 1)];
-  int c_next = cells[min(p0 + slot, p1 - 1)];
-  int i_next = perm[min(p0 + slot, p1 - 1)];
-  static_assert(P * coef_stride(D) <= kCoefPerThread * 256, "coefficients per thread");
-  double cv[kCoefPerThread];
-  coef_load<P, D>(sd.coef, sd.deg, cv);
-  {
-    T v[8];
-    walk_tile<8>(
-        S, m, sd.my, sd.mz, Ox, Oy, Oz, [&](int k, int, int64_t gi) { v[k] = grid[gi]; },
-        [&](int k, int li_, int64_t) { tb[li_] = v[k]; });
-  }
-  coef_store<P, D>(lcoef, cv);
-  __syncthreads();
   const int lane = threadIdx.x & 63;
+  const int slot = threadIdx.x >> 4;
   const int li = lane & (kLanesPerParticle - 1);
   G* rec = recs + slot * REC;
   const int nt = p1 - p0;
-  double esum = 0.0;
   for (int base = 0; base < nt; base += nslots) {
     const int pi = p0 + base + slot;
     const bool active = pi < p1;
@@ -783,37 +754,96 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
       const double qd = static_cast<double>(r.w);
       if (qd != qd) ph = gx = gy = gz = static_cast<G>(qd);  // binning marks a non-finite position with a NaN charge
       double phd = static_cast<double>(ph);
-      if (add_self) phd -= self_coef * qd;
-      if (phi_add) phd += phi_add[idx];  // the real-space residual, computed alongside (float64)
-      if (phi) phi[idx] = static_cast<T>(phd);
-      if (vec) {
-        const double sc = vec_mode == 0 ? -qd : 1.0;  // d/dx_d = (1 / h_d) d/dg_d
-        double v0 = sc * inv_hx * static_cast<double>(gx), v1 = sc * inv_hy * static_cast<double>(gy),
-               v2 = sc * inv_hz * static_cast<double>(gz);
-        if (vec_add) {
-          v0 += vec_add[3 * idx + 0];
-          v1 += vec_add[3 * idx + 1];
-          v2 += vec_add[3 * idx + 2];
+      if (out.add_self) phd -= sd.self_coef * qd;
+      if (out.phi_add) phd += out.phi_add[idx];  // the real-space residual, computed alongside (float64)
+      if (out.phi) out.phi[idx] = static_cast<T>(phd);
+      if (out.vec) {
+        const double sc = out.vec_mode == 0 ? -qd : 1.0;  // d/dx_d = (1 / h_d) d/dg_d
+        double v0 = sc * sd.inv_h * static_cast<double>(gx), v1 = sc * sd.inv_hy * static_cast<double>(gy),
+               v2 = sc * sd.inv_hz * static_cast<double>(gz);
+        if (out.vec_add) {
+          v0 += out.vec_add[3 * idx + 0];
+          v1 += out.vec_add[3 * idx + 1];
+          v2 += out.vec_add[3 * idx + 2];
         }
-        vec[3 * idx + 0] = static_cast<T>(v0);
-        vec[3 * idx + 1] = static_cast<T>(v1);
-        vec[3 * idx + 2] = static_cast<T>(v2);
+        out.vec[3 * idx + 0] = static_cast<T>(v0);
+        out.vec[3 * idx + 1] = static_cast<T>(v1);
+        out.vec[3 * idx + 2] = static_cast<T>(v2);
       }
       esum += qd * phd;
     }
     wave_lds_sync();
   }
-  if (energy) {
+}
+
+// The workgroup's energy sum into energy[s] (one atomic per workgroup).
+__device__ __forceinline__ void gather_energy(double esum, double* s_red, double* energy) {
+  const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) esum += __shfl_xor(esum, off, 64);
-    if (lane == 0) s_red[threadIdx.x >> 6] = esum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double tot = 0.0;
-      for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) tot += s_red[w];
-      safeAtomicAdd(energy + s, 0.5 * tot);  // caller's memory: the CAS form
-    }
+  for (int off = 32; off > 0; off >>= 1) esum += __shfl_xor(esum, off, 64);
+  if (lane == 0) s_red[threadIdx.x >> 6] = esum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < static_cast<int>(blockDim.x >> 6); ++w) tot += s_red[w];
+    safeAtomicAdd(energy, 0.5 * tot);  // caller's memory: the CAS form
   }
+}
+
+template <class T, int P, int D, class G>
+__global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const typename Vec4<T>::type* __restrict__ sorted,
+                                                const int* __restrict__ cells, const int* __restrict__ perm,
+                                                const int* __restrict__ tile_start, int sub_log2, int nsys,
+                                                const SysDesc* __restrict__ sys, const int* __restrict__ tile_prefix,
+                                                const int* __restrict__ tile_sys, int tile_offset, int parts, int xcd,
+                                                const T* __restrict__ grid_override, T* __restrict__ phi,
+                                                T* __restrict__ vec, int vec_mode, int add_self,
+                                                double* __restrict__ energy, const double* __restrict__ phi_add,
+                                                const double* __restrict__ vec_add) {
+  constexpr int REC = 6 * P;
+  constexpr int CS = coef_stride(D);
+  // dynamic LDS only (see k_spread_mfma)
+  extern __shared__ unsigned char smem_raw[];
+  const int wgid = tile_order_block(xcd);
+  const int gtile = tile_offset + wgid / parts;
+  int p0, p1;
+  tile_slice(tile_start, gtile, sub_log2, wgid % parts, parts, p0, p1);
+  if (p0 == p1) return;
+  const int s = nsys == 1 ? 0 : tile_sys[find_sys(tile_prefix, nsys, gtile)];
+  const SysDesc& sd = sys[s];
+  const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S;
+  const global_ptr<T> grid = as_global(grid_override ? grid_override : static_cast<const T*>(sd.grid_b));
+  const int nslots = blockDim.x / kLanesPerParticle;
+  double* s_red = reinterpret_cast<double*>(smem_raw);             // 16: the energy's per-wave sums
+  double* lcoef = s_red + 16;                                      // P * CS
+  G* recs = reinterpret_cast<G*>(lcoef + P * CS);                  // nslots * REC
+  T* tb = reinterpret_cast<T*>(recs + nslots * REC);
+  const int tile = gtile - sd.tile_base;
+  const int tx = tile % Tn, ty = (tile / Tn) % sd.Tny, tz = tile / (Tn * sd.Tny);
+  const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
+  const int half = (P + 1) / 2;
+  const int Ox = T0x + 1 - half, Oy = T0y + 1 - half, Oz = T0z + 1 - half;
+  const int slot = threadIdx.x >> 4;
+  // the first particles' records are loaded before the grid block is staged: the two round
+  // trips to memory overlap
+  const auto r0 = sorted[min(p0 + slot, p1 - 1)];
+  const int c0 = cells[min(p0 + slot, p1 - 1)];
+  const int i0 = perm[min(p0 + slot, p1 - 1)];
+  static_assert(P * coef_stride(D) <= kCoefPerThread * 256, "coefficients per thread");
+  double cv[kCoefPerThread];
+  coef_load<P, D>(sd.coef, sd.deg, cv);
+  {
+    T v[8];
+    walk_tile<8>(
+        S, m, sd.my, sd.mz, Ox, Oy, Oz, [&](int k, int, int64_t gi) { v[k] = grid[gi]; },
+        [&](int k, int li_, int64_t) { tb[li_] = v[k]; });
+  }
+  coef_store<P, D>(lcoef, cv);
+  __syncthreads();
+  double esum = 0.0;
+  const GatherOut<T, P, D, G> out{phi, vec, vec_mode, add_self, phi_add, vec_add};
+  gather_tile<T, P, D, G>(sorted, cells, perm, p0, p1, T0x, T0y, T0z, S, tb, recs, lcoef, sd, out, r0, c0, i0, esum);
+  if (energy) gather_energy(esum, s_red, energy + s);
 }
 
 template <class T, int P, int D>
