@@ -91,6 +91,19 @@ __device__ __forceinline__ int find_sys(const I* __restrict__ prefix, int nsys, 
   return lo;
 }
 
+// The same search restricted to [lo, hi] (a range known to hold i's system).
+template <class I>
+__device__ __forceinline__ int find_sys_in(const I* __restrict__ prefix, int lo, int hi, I i) {
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= i)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 // Cell coordinates (each < m <= 512) packed into 10-bit fields.
 __device__ __forceinline__ int pack_cell(int cx, int cy, int cz) { return cx | (cy << 10) | (cz << 20); }
 __device__ __forceinline__ int cell_x(int c) { return c & 1023; }

@@ -102,6 +102,11 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t n, int nsys, 
   __syncthreads();
   if (n > 0) {
     const int64_t i0 = blockIdx.x * static_cast<int64_t>(kBinThreads) * per_thread + tid;
+    // the systems of the workgroup's particles (one, unless the chunk spans a boundary)
+    const int64_t c0 = min(blockIdx.x * static_cast<int64_t>(kBinThreads) * per_thread, n - 1);
+    const int64_t c1 = min(c0 + static_cast<int64_t>(kBinThreads) * per_thread, n) - 1;
+    const int s_lo = nsys == 1 ? 0 : find_sys(part_prefix, nsys, c0);
+    const int s_hi = nsys == 1 ? 0 : find_sys(part_prefix, nsys, c1);
     // every load is issued (at clamped, valid indices) before any position is used
     T x[kBinMaxPerThread][3];
 #pragma unroll
@@ -114,7 +119,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count(int64_t n, int nsys, 
     for (int k = 0; k < kBinMaxPerThread; ++k) {
       const int64_t i = i0 + static_cast<int64_t>(k) * kBinThreads;
       if (k < per_thread && i < n) {
-        const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
+        const SysDesc& sd = sys[s_lo == s_hi ? s_lo : find_sys_in(part_prefix, s_lo, s_hi, i)];
         int cell;
         T g[3];
         const int b = bin_bucket(sd, sub_log2, x[k][0], x[k][1], x[k][2], cell, g);
@@ -229,7 +234,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_coarse(int64_t n, const T* 
 constexpr int kFineRes = 8;
 template <class T>
 __global__ __launch_bounds__(kFineThreads) void k_bin_fine(int64_t n, int nsys, const SysDesc* __restrict__ sys,
-                                                        const int64_t* __restrict__ part_prefix, int shift,
+                                                        const int* __restrict__ tile_prefix,
+                                                        const int* __restrict__ tile_sys, int sub_log2, int shift,
                                                         int ncoarse, int nbuckets, const int* __restrict__ coarse_start,
                                                         int* __restrict__ coarse_count, int* __restrict__ coarse_cursor,
                                                         const typename Vec4<T>::type* __restrict__ tmp_rec,
@@ -248,6 +254,10 @@ __global__ __launch_bounds__(kFineThreads) void k_bin_fine(int64_t n, int nsys, 
   const int s1 = static_cast<int>(min<int64_t>(max(coarse_start[c + 1], 0), n));
   const int s0 = min(max(coarse_start[c], 0), s1);
   const bool resident = s1 - s0 <= kFineRes * kFineThreads;
+  // the (group-ordered) systems whose tiles this coarse bucket covers: an item's system follows
+  // from its bucket's tile, searched within that range
+  const int k_lo = nsys == 1 ? 0 : find_sys(tile_prefix, nsys, (c << shift) >> sub_log2);
+  const int k_hi = nsys == 1 ? 0 : find_sys(tile_prefix, nsys, (min(nbuckets, (c + 1) << shift) - 1) >> sub_log2);
   V r[kFineRes];
   int2 ib[kFineRes];
   if (resident) {
@@ -286,7 +296,8 @@ __global__ __launch_bounds__(kFineThreads) void k_bin_fine(int64_t n, int nsys, 
   // the final record of one item, and its slot (or -1 when the counters were inconsistent)
   auto finish = [&](const V rv, int2 iv, V& rec, int& cell) {  // rv by value: rec may be its source
     const int dst = atomicAdd(&fine[iv.y & (nf - 1)], 1);
-    const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, static_cast<int64_t>(iv.x))];
+    const SysDesc& sd =
+        sys[nsys == 1 ? 0 : tile_sys[k_lo == k_hi ? k_lo : find_sys_in(tile_prefix, k_lo, k_hi, iv.y >> sub_log2)]];
     T g[3];
     bin_bucket(sd, 0, rv.x, rv.y, rv.z, cell, g);
     rec.x = g[0];
@@ -361,6 +372,17 @@ __global__ __launch_bounds__(kFineThreads) void k_bin_fine(int64_t n, int nsys, 
   }
 }
 
+// System of particle i (i < n) for kernels with one particle per thread: the systems of the
+// workgroup's first and last particles are found once (the same for every thread), and only a
+// workgroup that spans a boundary searches between them per particle.
+__device__ __forceinline__ int block_sys(const int64_t* __restrict__ part_prefix, int nsys, int64_t n, int64_t i) {
+  if (nsys == 1) return 0;
+  const int64_t b0 = blockIdx.x * static_cast<int64_t>(blockDim.x);
+  const int lo = find_sys(part_prefix, nsys, b0);
+  const int hi = find_sys(part_prefix, nsys, min(b0 + static_cast<int64_t>(blockDim.x), n) - 1);
+  return lo == hi ? lo : find_sys_in(part_prefix, lo, hi, i);
+}
+
 // One-level counting sort, for small systems (three short launches with no chain of dependent
 // passes): a returning atomic per particle gives its rank within its bucket, one workgroup scans
 // the bucket counts (k_scan), and the scatter writes each particle at its bucket's start plus
@@ -374,7 +396,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_count1(int64_t n, int nsys,
   const int64_t i = blockIdx.x * static_cast<int64_t>(kBinThreads) + threadIdx.x;
   if (energy && i < nsys) energy[i] = 0.0;
   if (i >= n) return;
-  const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
+  const SysDesc& sd = sys[block_sys(part_prefix, nsys, n, i)];
   int cell;
   T g[3];
   const int b = bin_bucket(sd, sub_log2, pos[3 * i + 0], pos[3 * i + 1], pos[3 * i + 2], cell, g);
@@ -390,7 +412,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_scatter1(
     int* __restrict__ perm) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(kBinThreads) + threadIdx.x;
   if (i >= n) return;
-  const SysDesc& sd = sys[nsys == 1 ? 0 : find_sys(part_prefix, nsys, i)];
+  const SysDesc& sd = sys[block_sys(part_prefix, nsys, n, i)];
   const int dst = tile_start[key[i]] + rank[i];
   const T x = pos[3 * i + 0], y = pos[3 * i + 1], z = pos[3 * i + 2];
   typename Vec4<T>::type rec;
@@ -1257,7 +1279,8 @@ hipError_t bin_impl(const DevPlan& d, int64_t n, const void* pos, const void* q,
   const size_t counters = sizeof(int) * (((size_t(1) << d.bin_shift) + kFineThreads / 64 + 3) & ~size_t(3));
   const bool staged = counters + kFineStage <= kFineLdsMax;
   hipLaunchKernelGGL(k_bin_fine<T>, dim3(d.bin_ncoarse), dim3(kFineThreads), counters + (staged ? kFineStage : 0), st,
-                     n, d.nsys, d.sys_dev, d.part_prefix, d.bin_shift, d.bin_ncoarse, d.total_tiles << d.sub_log2,
+                     n, d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys, d.sub_log2, d.bin_shift, d.bin_ncoarse,
+                     d.total_tiles << d.sub_log2,
                      d.coarse_start, d.coarse_count, d.coarse_cursor,
                      static_cast<const typename Vec4<T>::type*>(d.bin_tmp), d.bin_tmp_ib, d.tile_start,
                      static_cast<typename Vec4<T>::type*>(d.sorted), d.cells, d.perm, staged ? 1 : 0);

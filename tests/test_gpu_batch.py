@@ -29,15 +29,15 @@ def dev():
 
 
 def dt(prec):
-    return torch.float32 if prec == "fp32" else torch.float64
+    return torch.float64 if prec == "fp64" else torch.float32
 
 
 def rounded(a, prec):
-    return np.asarray(a, dtype=np.float32 if prec == "fp32" else np.float64).astype(np.float64)
+    return np.asarray(a, dtype=np.float64 if prec == "fp64" else np.float32).astype(np.float64)
 
 
 def fit_tol(eps, prec):
-    return max(0.01 * eps, 5e-9 if prec == "fp32" else 1e-15)
+    return max(0.01 * eps, 1e-15 if prec == "fp64" else 5e-9)
 
 
 def pack(systems, prec):
@@ -86,7 +86,7 @@ MIXED = [
 def mixed_systems(prec):
     out = []
     for gen, eps, kw in MIXED:
-        if prec == "fp32" and eps < 1e-6:
+        if prec != "fp64" and eps < 1e-6:
             eps = 1e-6
         x, q, L = gen()
         x, q = rounded(x, prec), rounded(q, prec)
@@ -98,7 +98,7 @@ def mixed_systems(prec):
 
 
 @pytest.mark.parametrize("levels", ["1", "2"])
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_arith"])
 def test_mixed_batch_matches_oracle_and_sequential(prec, levels, monkeypatch):
     monkeypatch.setenv("PSWFE_BIN_LEVELS", levels)   # one-level or two-level binning of the batch
     systems = mixed_systems(prec)
@@ -116,7 +116,7 @@ def test_mixed_batch_matches_oracle_and_sequential(prec, levels, monkeypatch):
     for k, (x, qq, L, eps, c, o) in enumerate(systems):
         check_vs_oracle(x, qq, o, phis[k], Fs[k], float(E[k]), eps, prec, c=c, name=f"mixed-batch-{prec}-bin{levels}-sys{k}")
     # sequential single-system plans with the same tiles
-    tol = 1e-6 if prec == "fp32" else 1e-12
+    tol = 1e-12 if prec == "fp64" else 1e-6
     for k, (x, qq, L, eps, c, o) in enumerate(systems):
         single = pw.Plan(c, prec, n_max=len(qq), tile=plan.tiles[k])
         assert single.tile == plan.tiles[k]
@@ -127,7 +127,7 @@ def test_mixed_batch_matches_oracle_and_sequential(prec, levels, monkeypatch):
         sp, sF = sp.cpu().numpy(), sF.cpu().numpy()
         assert np.linalg.norm(phis[k] - sp) <= tol * np.linalg.norm(sp) + 1e-30
         assert np.linalg.norm(Fs[k] - sF) <= tol * np.linalg.norm(sF) + 1e-30
-        assert abs(float(E[k]) - float(sE.cpu()[0])) <= tol * abs(float(sE.cpu()[0])) + 1e-30
+        assert abs(float(E[k]) - float(sE.cpu()[0])) <= tol * 0.5 * float(np.abs(qq) @ np.abs(sp)) + 1e-30
         single.close()
     # grad mode returns grad phi_far: force = -q grad phi (a second call: the float64 atomic
     # additions may round in another order)
@@ -209,23 +209,30 @@ def _ensemble(prec):
     return ens, params
 
 
-def test_full_ensemble_batched_vs_sequential_and_oracle():
-    """256 systems, n log-uniform in [500, 20000], L uniform in [0.5, 2], eps = 1e-6 fp32."""
-    prec = "fp32"
+@pytest.mark.parametrize("prec", ["fp32", "fp32_arith"])
+def test_full_ensemble_batched_vs_sequential_and_oracle(prec):
+    """256 systems, n log-uniform in [500, 20000], L uniform in [0.5, 2], eps = 1e-6, float32
+    storage with float64 or float32 window arithmetic."""
     ens, params = _ensemble(prec)
     counts = [len(q) for _, q, _ in ens]
     pos, q = pack([(x, qq) for x, qq, _ in ens], prec)
     plan = pw.BatchPlan(params, counts, prec)
     phi, F, E = plan.compute(pos, q)
     phis, Fs, E = plan.split(phi.cpu().numpy()), plan.split(F.cpu().numpy()), E.cpu().numpy()
-    # every system against its own sequential plan (same tiles)
+    # every system against its own sequential plan (same tiles): the same arithmetic up to the
+    # order of the tile sums (particles within a bucket come in any order), which float32 sums
+    # feel more
+    tol = 2e-6 if prec == "fp32_arith" else 1e-6
     for k, (x, qq, L) in enumerate(ens):
         single = pw.Plan(params[k], prec, n_max=len(qq), tile=plan.tiles[k])
         sp, sF, sE = single.compute(*pack([(x, qq)], prec))
         sp, sF = sp.cpu().numpy(), sF.cpu().numpy()
-        assert np.linalg.norm(phis[k] - sp) <= 1e-6 * np.linalg.norm(sp), k
-        assert np.linalg.norm(Fs[k] - sF) <= 1e-6 * np.linalg.norm(sF), k
-        assert abs(E[k] - float(sE.cpu()[0])) <= 1e-6 * abs(E[k]), k
+        assert np.linalg.norm(phis[k] - sp) <= tol * np.linalg.norm(sp), k
+        assert np.linalg.norm(Fs[k] - sF) <= tol * np.linalg.norm(sF), k
+        # the energy of a neutral system is a small difference of large terms: its rounding, from
+        # the order in which the float32 (float32 arithmetic) or float64 tile sums are taken, is
+        # relative to the sum of |q_i phi_i|, not to E
+        assert abs(E[k] - float(sE.cpu()[0])) <= tol * 0.5 * float(np.abs(qq) @ np.abs(sp)), k
         single.close()
     # 16 seeded systems against the oracle
     pick = np.random.default_rng(16591).choice(len(ens), 16, replace=False)
