@@ -832,7 +832,44 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
   static_assert(P * coef_stride(D) <= kCoefPerThread * 256, "coefficients per thread");
   double cv[kCoefPerThread];
   coef_load<P, D>(sd.coef, sd.deg, cv);
-  {
+  // the S^3 block: by aligned 16-byte loads of whole row segments where no row wraps around the
+  // grid in x (and rows start on 16 bytes), else point by point
+  constexpr int VW = 16 / static_cast<int>(sizeof(T));  // values per 16-byte load
+  const T* gsrc = grid_override ? grid_override : static_cast<const T*>(sd.grid_b);
+  // the chunks of a row end at or before the row's end: x + S <= m and m is a multiple of VW
+  if (Ox >= 0 && Ox + S <= m && m % VW == 0 && (reinterpret_cast<uintptr_t>(gsrc) & 15) == 0) {
+    using V16 = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    const int a0 = Ox & ~(VW - 1);                         // first aligned x of every row
+    const int nch = (Ox + S - a0 + VW - 1) / VW;           // 16-byte chunks per row
+    const int items = S * S * nch;
+    const int nt = static_cast<int>(blockDim.x);
+    constexpr int K = 4;
+    for (int base = threadIdx.x; base < items; base += nt * K) {
+      V16 v[K];
+      int row[K], ch[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int it = base + k * nt;
+        row[k] = it / nch;
+        ch[k] = it - row[k] * nch;
+        if (it < items) {
+          const int z = row[k] / S, y = row[k] - z * S;
+          const int64_t g0 = (static_cast<int64_t>(fold_index(Oz + z, sd.mz)) * sd.my + fold_index(Oy + y, sd.my)) * m + a0;
+          v[k] = *reinterpret_cast<const V16*>(gsrc + g0 + ch[k] * VW);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (base + k * nt >= items) continue;
+        const T* e = reinterpret_cast<const T*>(&v[k]);
+#pragma unroll
+        for (int j = 0; j < VW; ++j) {
+          const int x = a0 + ch[k] * VW + j - Ox;
+          if (x >= 0 && x < S) tb[row[k] * S + x] = e[j];
+        }
+      }
+    }
+  } else {
     T v[8];
     walk_tile<8>(
         S, m, sd.my, sd.mz, Ox, Oy, Oz, [&](int k, int, int64_t gi) { v[k] = grid[gi]; },
