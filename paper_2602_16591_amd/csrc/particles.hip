@@ -716,21 +716,25 @@ __device__ __forceinline__ void gather_tile(const typename Vec4<T>::type* __rest
         wx[j] = rec[j];
         dx[j] = rec[3 * P + j];
       }
-#pragma unroll 2
-      for (int e = li; e < P * P; e += kLanesPerParticle) {
+      auto load_row = [&](int e, T (&bl)[P]) {
         const int jz = e / P, jy = e - jz * P;
         const T* row = tb + ((o[2] + jz) * S + (o[1] + jy)) * S + o[0];
+#pragma unroll
+        for (int jx = 0; jx < P; ++jx) bl[jx] = row[jx];
+      };
+      auto sum_row = [&](int e, const T (&bl)[P]) {
+        const int jz = e / P, jy = e - jz * P;
         G sx0 = 0, sx1 = 0, sd0 = 0, sd1 = 0;
 #pragma unroll
         for (int jx = 0; jx + 1 < P; jx += 2) {
-          const G b0 = static_cast<G>(row[jx]), b1 = static_cast<G>(row[jx + 1]);
+          const G b0 = static_cast<G>(bl[jx]), b1 = static_cast<G>(bl[jx + 1]);
           sx0 = fma(b0, wx[jx], sx0);
           sd0 = fma(b0, dx[jx], sd0);
           sx1 = fma(b1, wx[jx + 1], sx1);
           sd1 = fma(b1, dx[jx + 1], sd1);
         }
         if constexpr (P % 2 == 1) {
-          const G b = static_cast<G>(row[P - 1]);
+          const G b = static_cast<G>(bl[P - 1]);
           sx0 = fma(b, wx[P - 1], sx0);
           sd0 = fma(b, dx[P - 1], sd0);
         }
@@ -741,6 +745,17 @@ __device__ __forceinline__ void gather_tile(const typename Vec4<T>::type* __rest
         gx = fma(sdx, wyz, gx);
         gy = fma(sx, dy * wz, gy);
         gz = fma(sx, wy * dz, gz);
+      };
+      constexpr int L = kLanesPerParticle;
+      {
+        // one row at a time, its values loaded together before they are summed (two row
+        // buffers, the next row's loads in flight during the sums, measured slower)
+#pragma unroll 2
+        for (int e = li; e < P * P; e += L) {
+          T bl[P];
+          load_row(e, bl);
+          sum_row(e, bl);
+        }
       }
     }
 #pragma unroll
