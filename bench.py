@@ -72,7 +72,9 @@ def stage_work(stage: str, n: int, m: int, P: int, deg: int, elem: int):
 
 STAGE_KERNEL = {"spread": ("k_spread", "k_spread_cols", "k_spread_mfma"), "gather": ("k_gather",), "fft_x": ("k_fft_x_r2c",),
                 "fft_y": ("k_fft_cols",), "fft_z_scale": ("k_fft_cols",), "ifft_y": ("k_fft_cols",),
-                "ifft_x": ("k_fft_x_c2r",), "bin": ("k_bin_count",)}
+                "ifft_x": ("k_fft_x_c2r",),
+                # one-level sort (count, scan, scatter) or two-level sort (count, coarse, fine)
+                "bin": ("k_bin_count1", "k_bin_scatter1", "k_bin_count", "k_bin_coarse", "k_bin_fine")}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_water_box_n30000.md")
 TRAFFIC_FILE_N1E6 = os.path.join(ROOT, "profiles", "traffic_uniform_n1e6.md")
 # the device code whose counters a summary holds, and its hash (comments and blank space aside)
@@ -109,8 +111,8 @@ def _stage_kernels(blob_keys, stage: str, prec: str):
         if name in STAGE_KERNEL[stage] and k.startswith(f"{name}<{ctype}"):
             if name not in ARITH_KERNELS or k.endswith(f", {arith}>"):
                 hits.append(k)
-    if stage == "bin":   # the counting sort is three launches: count, scan, scatter
-        hits += [k for k in blob_keys if k == "k_scan" or k.startswith(f"k_bin_scatter<{ctype}")]
+    if stage == "bin" and any(k.startswith("k_bin_count1<") for k in hits):   # the one-level sort's scan
+        hits += [k for k in blob_keys if k == "k_scan"]
     return hits
 
 

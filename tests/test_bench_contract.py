@@ -90,3 +90,16 @@ def test_kernel_hash_ignores_comments_but_not_code():
     assert bench.code_only(src) == bench.code_only(same)
     assert bench.code_only(src) != bench.code_only(other)
     assert '"// kept"' in bench.code_only(src)
+
+
+def test_binning_traffic_sums_the_sort_kernels_of_either_form(tmp_path, monkeypatch):
+    """The binning stage is three launches: count, scan, scatter (one-level sort) or count,
+    coarse pass, fine pass (two-level sort); its traffic is their sum, per storage type."""
+    one = {"k_bin_count1<float>": 1, "k_scan": 2, "k_bin_scatter1<float>": 4, "k_bin_count1<double>": 100}
+    two = {"k_bin_count<float>": 10, "k_bin_coarse<float>": 20, "k_bin_fine<float>": 40, "k_scan": 1000}
+    for per, want, workload in ((one, 7, "water_box_n30000"), (two, 70, "uniform_n1e6")):
+        blob = {"kernel_source_sha256": bench.kernel_source_sha256(), "workload": workload, "bytes_per_launch": per}
+        p = tmp_path / f"{workload}.md"
+        p.write_text("```json\n" + json.dumps(blob) + "\n```\n")
+        monkeypatch.setattr(bench, "TRAFFIC_FILE_N1E6" if workload == "uniform_n1e6" else "TRAFFIC_FILE", str(p))
+        assert bench.measured_traffic("bin", "fp32_arith", workload) == want
