@@ -116,6 +116,9 @@ struct PGroup {
   int acc32 = 0;     // ... with float32 window values, products and tile sums (float32 plans only)
   int parts = 1;     // workgroups per tile, each taking an equal slice of the tile's particles
   int xcd_spread = 0, xcd_gather = 0;  // XCD-aware tile order (set at plan creation)
+  // matrix-core spreading by columns of tiles with a ring of z-planes in LDS (single systems):
+  // roll_len tiles per workgroup, roll_nseg segments per column, roll_cols columns (0: off)
+  int roll_len = 0, roll_nseg = 0, roll_cols = 0;
   size_t lds_spread = 0, lds_gather = 0;  // maxima over the group's systems
 };
 
@@ -142,6 +145,13 @@ inline size_t mfma_lds_bytes(int P, int D, int B, size_t acc_bytes) {
   const size_t batch = sizeof(double) * (static_cast<size_t>(P) * coef_stride(D) + kMfmaRecordsHost * 4) +
                        sizeof(int) * kMfmaRecordsHost * 4 + acc_bytes * kMfmaRecordsHost * 3 * S + 16;
   return std::max(batch, sizeof(double) * S * S * S);  // the records, then the block
+}
+// The same with the ring of a column of tiles (S^3 float64) ahead of the records.
+inline size_t mfma_roll_lds_bytes(int P, int D, int B, size_t acc_bytes) {
+  const size_t S = static_cast<size_t>(col_edge_host(P, B));
+  const size_t batch = sizeof(double) * (static_cast<size_t>(P) * coef_stride(D) + kMfmaRecordsHost * 4) +
+                       sizeof(int) * kMfmaRecordsHost * 4 + acc_bytes * kMfmaRecordsHost * 3 * S + 16;
+  return sizeof(double) * S * S * S + batch;
 }
 inline size_t col_lds_bytes(int P, int D, int B) {
   const int S = col_edge_host(P, B);

@@ -401,11 +401,12 @@ template <int P, int B>
 constexpr bool mfma_sliced() { return mfma_sliced_host(P, B); }
 constexpr int kMfmaRecords = kColBatch + 8;  // a batch plus the padding of two slices
 
-template <class T, int P, int D, int B, class A>
+template <class T, int P, int D, int B, class A, bool ROLL>
 __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
     const typename Vec4<T>::type* __restrict__ sorted, const int* __restrict__ cells,
     const int* __restrict__ tile_start, int sub_log2, int nsys, const SysDesc* __restrict__ sys,
-    const int* __restrict__ tile_prefix, const int* __restrict__ tile_sys, int tile_offset, int parts, int xcd) {
+    const int* __restrict__ tile_prefix, const int* __restrict__ tile_sys, int tile_offset, int parts, int xcd,
+    int seg_len, int nseg) {
   constexpr int S = col_edge<P, B>();
   constexpr int MR = mfma_row_pieces<P, B>();
   constexpr bool SL = mfma_sliced<P, B>();
@@ -418,29 +419,56 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
   // dynamic LDS only: a static array beside a large dynamic allocation measured 2.8x slower
   // (P = 18, 125 KB of LDS per workgroup)
   extern __shared__ unsigned char smem_raw[];
-  const int wgid = tile_order_block(xcd);
-  const int gtile = tile_offset + wgid / parts;
-  int p0, p1;
-  tile_slice(tile_start, gtile, sub_log2, wgid % parts, parts, p0, p1);
-  if (p0 == p1) return;
-  const SysDesc& sd = sys[nsys == 1 ? 0 : tile_sys[find_sys(tile_prefix, nsys, gtile)]];
+  // ROLL: the workgroup takes tiles z0..z1-1 of column (tx, ty) of a single system in turn,
+  // keeping their S^3 blocks in LDS as a ring of z-planes (plane z of tile z0 + k in slot
+  // (k B + z) mod S) ahead of the records; after each tile only the B planes that no later tile
+  // of the column reaches are added to the grid, the others carry over. Otherwise: one tile (or
+  // one slice of a tile's particles) per workgroup, its block over the records' LDS.
+  const int wgid = ROLL ? static_cast<int>(blockIdx.x) : tile_order_block(xcd);
+  int p0 = 0, p1 = 0, gtile = 0;
+  if constexpr (!ROLL) {
+    gtile = tile_offset + wgid / parts;
+    tile_slice(tile_start, gtile, sub_log2, wgid % parts, parts, p0, p1);
+    if (p0 == p1) return;
+  }
+  const SysDesc& sd = sys[(ROLL || nsys == 1) ? 0 : tile_sys[find_sys(tile_prefix, nsys, gtile)]];
   const int m = sd.m, Tn = sd.Tn;
   double* __restrict__ grid = sd.grid_a;
-  double* lcoef = reinterpret_cast<double*>(smem_raw);     // P * CS
+  double* ring = reinterpret_cast<double*>(smem_raw);      // ROLL: S^3
+  double* lcoef = ring + (ROLL ? S * S * S : 0);           // P * CS
   double* pg = lcoef + P * CS;                             // kMfmaRecords * 4: g_x, g_y, g_z, q
   int* po = reinterpret_cast<int*>(pg + kMfmaRecords * 4); // kMfmaRecords * 4: o_x, o_y, o_z, valid
   A* recs = reinterpret_cast<A*>(po + kMfmaRecords * 4);   // kMfmaRecords * RS
   // groups of 4: slice 0 in [0, s_split[0]), slice 1 up to s_split[1]
   int* s_split = reinterpret_cast<int*>(recs + kMfmaRecords * RS);
-  const int tile = gtile - sd.tile_base;
-  const int tx = tile % Tn, ty = (tile / Tn) % sd.Tny, tz = tile / (Tn * sd.Tny);
-  const int T0x = tx * B, T0y = ty * B, T0z = tz * B;
+  int tx, ty, tz, z1 = 0;
+  if constexpr (ROLL) {
+    const int col = wgid / nseg, seg = wgid - col * nseg;
+    tx = col % Tn;
+    ty = col / Tn;
+    tz = seg * seg_len;
+    z1 = min(sd.Tnz, tz + seg_len);
+    if (tz >= z1) return;
+    const int gt = sd.tile_base + (tz * sd.Tny + ty) * Tn + tx;
+    p0 = tile_start[gt << sub_log2];
+    p1 = tile_start[(gt + 1) << sub_log2];
+  } else {
+    const int tile = gtile - sd.tile_base;
+    tx = tile % Tn;
+    ty = (tile / Tn) % sd.Tny;
+    tz = tile / (Tn * sd.Tny);
+  }
+  const int T0x = tx * B, T0y = ty * B;
+  int T0z = tz * B;
   const int t = threadIdx.x;
   // the first batch's records are loaded before the coefficients are staged: the two round
   // trips to memory overlap
-  auto r_next = sorted[min(p0 + t, p1 - 1)];
-  int c_next = cells[min(p0 + t, p1 - 1)];
+  auto r_next = sorted[min(p0 + t, max(p1 - 1, 0))];
+  int c_next = cells[min(p0 + t, max(p1 - 1, 0))];
   stage_coefficients<P, D>(sd.coef, sd.deg, lcoef);
+  if constexpr (ROLL) {
+    for (int i = t; i < S * S * S; i += blockDim.x) ring[i] = 0.0;
+  }
   const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int lr = lane & 15, lk = lane >> 4;
   // waves whose row pieces are all inside the block run the group loop without per-piece checks
@@ -465,10 +493,13 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
     cmask[c] = x < S ? A(1) : A(0);
   }
   acc_t acc[kMfmaPieces][NC];
+  constexpr int half = (P + 1) / 2;
+  for (int k = 0;; ++k) {
 #pragma unroll
   for (int u = 0; u < kMfmaPieces; ++u)
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[u][c] = acc_t{0, 0, 0, 0};
+  if constexpr (ROLL) __syncthreads();  // the ring's zeros, or the previous tile's flush
   for (int b0 = p0; b0 < p1; b0 += kColBatch) {
     const int nb = min(kColBatch, p1 - b0);
     const auto r = r_next;
@@ -591,6 +622,68 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
     }
     __syncthreads();
   }
+  if constexpr (ROLL) {
+    // the tile's sums into the ring (slot of plane z: (k B + z) mod S); every row belongs to one
+    // wave, so the two slices' additions (one lane after another) need no barrier between them
+#pragma unroll
+    for (int u = 0; u < kMfmaPieces; ++u) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int x = SL ? (c == 0 ? lr : X1 + lr) : c * 16 + lr;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = (wave * kMfmaPieces + u) * 16 + M::row(lk, q);
+          if (row < S * S && x < S) {
+            const int z = row / S, y = row - z * S;
+            int zs = (k * B) % S + z;
+            zs -= zs >= S ? S : 0;
+            ring[(zs * S + y) * S + x] += static_cast<double>(acc[u][c][q]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // the planes no later tile of the column reaches (all S after the last tile) into the grid,
+    // their slots cleared for the planes the next tile adds
+    const bool last = tz + 1 >= z1;
+    const int nplanes = last ? S : B;
+    const int Ox = T0x + 1 - half, Oy = T0y + 1 - half, Oz = T0z + 1 - half;
+    const int S2 = S * S, items = nplanes * S2, nt = static_cast<int>(blockDim.x);
+    for (int base = t; base < items; base += 8 * nt) {
+      double v[8];
+      int li[8];
+      int64_t gi[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int e = base + j * nt;
+        li[j] = -1;
+        if (e < items) {
+          const int z = e / S2, rem = e - z * S2, y = rem / S, x = rem - y * S;
+          int zs = (k * B) % S + z;
+          zs -= zs >= S ? S : 0;
+          li[j] = (zs * S + y) * S + x;
+          gi[j] = (static_cast<int64_t>(fold_index(Oz + z, sd.mz)) * sd.my + fold_index(Oy + y, sd.my)) * m +
+                  fold_index(Ox + x, m);
+          v[j] = ring[li[j]];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (li[j] < 0) continue;
+        if (v[j] != 0.0) atomic_add_global(grid + gi[j], v[j]);
+        ring[li[j]] = 0.0;
+      }
+    }
+    if (last) break;
+    // the next tile of the column
+    ++tz;
+    T0z = tz * B;
+    const int gt = sd.tile_base + (tz * sd.Tny + ty) * Tn + tx;
+    p0 = tile_start[gt << sub_log2];
+    p1 = tile_start[(gt + 1) << sub_log2];
+    r_next = sorted[min(p0 + t, max(p1 - 1, 0))];
+    c_next = cells[min(p0 + t, max(p1 - 1, 0))];
+  } else {
   double* blk = reinterpret_cast<double*>(smem_raw);  // S^3, over the coefficients and records
   // column piece c (or slice 0) first; with slices, the columns only slice 1 reaches are zeroed
   // and slice 1 is added after a barrier
@@ -623,7 +716,6 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
     }
   }
   __syncthreads();
-  constexpr int half = (P + 1) / 2;
   double v[8];
   walk_tile<8>(
       S, m, sd.my, sd.mz, T0x + 1 - half, T0y + 1 - half, T0z + 1 - half,
@@ -631,6 +723,9 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
       [&](int k, int, int64_t gi) {
         if (v[k] != 0.0) atomic_add_global(grid + gi, v[k]);
       });
+  break;
+  }
+  }
 }
 
 // Interpolation (Alg. 2 step 5 and eq. force): phi = sum b w_x w_y w_z and its gradient as
@@ -906,14 +1001,25 @@ hipError_t spread_impl(const DevPlan& d, const PGroup& g, hipStream_t st) {
                        d.sys_dev, d.tile_prefix, d.tile_sys, g.tile_begin, g.parts, g.xcd_spread);
   };
   if (g.mfma) {
+    auto launch = [&](auto kern, int threads) {
+      const bool roll = g.roll_len > 0;
+      hipLaunchKernelGGL(kern, dim3(roll ? g.roll_cols * g.roll_nseg : (g.tile_end - g.tile_begin) * g.parts),
+                         dim3(threads), g.lds_spread, st, static_cast<const typename Vec4<T>::type*>(d.sorted),
+                         d.cells, d.tile_start, d.sub_log2, d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys,
+                         g.tile_begin, g.parts, g.xcd_spread, g.roll_len, g.roll_nseg);
+    };
     auto mf = [&](auto acc) {
       using A = decltype(acc);
+      const bool roll = g.roll_len > 0;
       if (g.col_tile == 4)
-        cols(k_spread_mfma<T, P, D, 4, A>, mfma_threads<P, 4>());
+        roll ? launch(k_spread_mfma<T, P, D, 4, A, true>, mfma_threads<P, 4>())
+             : launch(k_spread_mfma<T, P, D, 4, A, false>, mfma_threads<P, 4>());
       else if (g.col_tile == 6)
-        cols(k_spread_mfma<T, P, D, 6, A>, mfma_threads<P, 6>());
+        roll ? launch(k_spread_mfma<T, P, D, 6, A, true>, mfma_threads<P, 6>())
+             : launch(k_spread_mfma<T, P, D, 6, A, false>, mfma_threads<P, 6>());
       else
-        cols(k_spread_mfma<T, P, D, 8, A>, mfma_threads<P, 8>());
+        roll ? launch(k_spread_mfma<T, P, D, 8, A, true>, mfma_threads<P, 8>())
+             : launch(k_spread_mfma<T, P, D, 8, A, false>, mfma_threads<P, 8>());
     };
     if constexpr (std::is_same_v<T, float>) {
       if (g.acc32) {
@@ -963,9 +1069,13 @@ template <class T, int P, int D>
 const void* mfma_fn(const PGroup& g) {
   auto pick = [&](auto acc) -> const void* {
     using A = decltype(acc);
-    return g.col_tile == 4   ? reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 4, A>)
-           : g.col_tile == 6 ? reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 6, A>)
-                             : reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 8, A>);
+    if (g.roll_len > 0)
+      return g.col_tile == 4   ? reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 4, A, true>)
+             : g.col_tile == 6 ? reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 6, A, true>)
+                               : reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 8, A, true>);
+    return g.col_tile == 4   ? reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 4, A, false>)
+           : g.col_tile == 6 ? reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 6, A, false>)
+                             : reinterpret_cast<const void*>(&k_spread_mfma<T, P, D, 8, A, false>);
   };
   if constexpr (std::is_same_v<T, float>) {
     if (g.acc32) return pick(float());

@@ -351,6 +351,39 @@ def test_compute_matches_fast_oracle(case, prec, levels, monkeypatch):
     assert abs(E - 0.5 * float(np.dot(q, phi))) <= 1e-6 * abs(E) + 1e-12
 
 
+ROLL_CASES = SMALL + [("uniform_m48_tile8", lambda: W.uniform_pm1(3000, seed=12), 1e-6, dict(m=48)),
+                      ("uniform_m40_tile8_p13", lambda: W.uniform_pm1(2500, seed=14), 1e-6, dict(m=40))]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_arith"])
+@pytest.mark.parametrize("case", ROLL_CASES, ids=[c[0] for c in ROLL_CASES])
+def test_spreading_by_columns_of_tiles(case, prec, monkeypatch):
+    """Matrix-core spreading by whole columns of tiles with a ring of z-planes in LDS (the form
+    large single systems take), forced on small systems: the grid against the oracle's, the
+    whole pipeline particle by particle, and both against the tile-by-tile kernel."""
+    _, gen, eps, kw = case
+    if prec != "fp64" and eps < 1e-6:
+        pytest.skip("fp32 path is for eps >= 1e-6")
+    x, q, L, kw = _sys(gen, eps, kw, prec)
+    c, o = both_params(eps, L, **kw)
+    a = fast.spread(np.mod(x, L), q, o).transpose(2, 1, 0)
+    A = fast.spread(np.mod(x, L), np.abs(q), o).transpose(2, 1, 0)
+    outs = {}
+    for roll in ("1", "0"):
+        monkeypatch.setenv("PSWFE_SPREAD_ROLL", roll)
+        plan = pw.Plan(c, prec, n_max=len(q))
+        g = plan.spread(tdev(x, prec), tdev(q, prec)).cpu().numpy()
+        assert np.all(np.abs(g - a) <= spread_tol(x, q, o, eps, prec, A))
+        phi, F, E = plan.compute(tdev(x, prec), tdev(q, prec))
+        outs[roll] = (g, phi.cpu().numpy(), F.cpu().numpy(), float(E.cpu()[0]))
+        if roll == "1":
+            check_elementwise(f"spread-columns-{case[0]}-{prec}", phi, F, x, q, c, o, eps, prec)
+        plan.close()
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    assert rel_l2(outs["1"][1], outs["0"][1]) < tol
+    assert rel_l2(outs["1"][2], outs["0"][2]) < tol
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_arith"])
 def test_plain_config_vs_direct_sum(prec):
     """n = 1000 uniform +-1 charges, L = 1, eps = 1e-6, grid 32^3: relative l2 error of phi_far
