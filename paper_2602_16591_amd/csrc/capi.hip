@@ -514,16 +514,17 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   // so that the columns still fill the GPU): each tile then adds B S^2 points to the grid instead
   // of S^3 (n = 1e6 float64: 2.30 -> 2.20 ms; float32 plans, whose flush is a small share,
   // measured slower: 410 -> 640 us). Segments per column: about 1,024 workgroups.
-  // PSWFE_SPREAD_ROLL=0 turns it off, =1 turns it on wherever it applies (whole columns).
+  // PSWFE_SPREAD_ROLL=0 turns it off, =1 turns it on wherever it applies (whole columns), =2 turns
+  // it on with the automatic segments for any precision and tile count.
   {
     int roll_env = -1;
-    if (const char* env = std::getenv("PSWFE_SPREAD_ROLL")) roll_env = std::atoi(env) != 0 ? 1 : 0;
+    if (const char* env = std::getenv("PSWFE_SPREAD_ROLL")) roll_env = std::max(0, std::min(2, std::atoi(env)));
     if (nsys == 1 && d.groups.size() == 1 && d.groups[0].mfma && d.groups[0].parts == 1 && roll_env != 0) {
       pswfe::PGroup& g = d.groups[0];
       const pswfe::SysDesc& sd = d.sys[0];
       const int cols = sd.Tn * sd.Tny, tiles = cols * sd.Tnz;
       const size_t lds = pswfe::mfma_roll_lds_bytes(g.P, g.D, g.col_tile, g.acc32 ? sizeof(float) : sizeof(double));
-      if ((roll_env == 1 || (tiles >= 2048 && prec == PSWFE_FP64)) && sd.Tnz >= 2 && lds <= kLdsLimit) {
+      if ((roll_env >= 1 || (tiles >= 2048 && prec == PSWFE_FP64)) && sd.Tnz >= 2 && lds <= kLdsLimit) {
         const int nseg0 = roll_env == 1 ? 1 : std::max(1, std::min(sd.Tnz, (1024 + cols - 1) / cols));
         const int len = (sd.Tnz + nseg0 - 1) / nseg0;
         if (len >= 2) {
