@@ -97,8 +97,9 @@ def _profile_blob(path, workload: str = "water_box_n30000"):
     return blob if blob.get("kernel_source_sha256") == kernel_source_sha256() else None
 
 
-# kernels whose last template argument is the type of their window arithmetic
-ARITH_KERNELS = ("k_spread_mfma", "k_gather")
+# kernels with a template argument for the type of their window arithmetic, and its position:
+# k_spread_mfma<T, P, D, B, A, column form>, k_gather<T, P, D, G>
+ARITH_ARG = {"k_spread_mfma": 4, "k_gather": 3}
 
 
 def _stage_kernels(blob_keys, stage: str, prec: str):
@@ -109,7 +110,8 @@ def _stage_kernels(blob_keys, stage: str, prec: str):
     for k in blob_keys:
         name = k.split("<", 1)[0]
         if name in STAGE_KERNEL[stage] and k.startswith(f"{name}<{ctype}"):
-            if name not in ARITH_KERNELS or k.endswith(f", {arith}>"):
+            args = k[len(name) + 1:-1].split(", ")
+            if name not in ARITH_ARG or (len(args) > ARITH_ARG[name] and args[ARITH_ARG[name]] == arith):
                 hits.append(k)
     if stage == "bin" and any(k.startswith("k_bin_count1<") for k in hits):   # the one-level sort's scan
         hits += [k for k in blob_keys if k == "k_scan"]

@@ -24,7 +24,7 @@ def test_more_than_one_gpu_is_refused_with_a_message(extra):
 
 def test_water_box_counter_summaries_are_not_used_for_other_workloads(tmp_path, monkeypatch):
     blob = {"kernel_source_sha256": bench.kernel_source_sha256(), "workload": "water_box_n30000",
-            "bytes_per_launch": {"k_spread_mfma<float, 13, 11, 8, float>": 41_000_000, "k_spread_mfma<float, 13, 11, 8, double>": 52_000_000}}
+            "bytes_per_launch": {"k_spread_mfma<float, 13, 11, 8, float, false>": 41_000_000, "k_spread_mfma<float, 13, 11, 8, double, false>": 52_000_000}}
     p = tmp_path / "summary.md"
     p.write_text("```json\n" + json.dumps(blob) + "\n```\n")
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(p))
@@ -57,7 +57,7 @@ def test_fft_pass_bytes(elem):
 
 
 def _summary(tmp_path, sha):
-    blob = {"kernel_source_sha256": sha, "bytes_per_launch": {"k_spread_mfma<float, 13, 11, 8, float>": 41_000_000, "k_spread_mfma<float, 13, 11, 8, double>": 52_000_000}}
+    blob = {"kernel_source_sha256": sha, "bytes_per_launch": {"k_spread_mfma<float, 13, 11, 8, float, false>": 41_000_000, "k_spread_mfma<float, 13, 11, 8, double, false>": 52_000_000}}
     p = tmp_path / "summary.md"
     p.write_text("# summary\n\n```json\n" + json.dumps(blob) + "\n```\n")
     return str(p)
