@@ -124,10 +124,10 @@ bool tile_fits(int B, int P, int elem) {
 // 16-wave budget of kernels near 128 VGPRs). On ties, spreading takes the larger workgroup
 // (more particle slots share one LDS tile), interpolation the smaller (two workgroups per
 // compute unit overlap one's grid staging with the other's sums: 40 against 44 us on the
-// water box). PSWFE_PARTICLE_THREADS overrides it (if that fits).
-int particle_threads(int P, const std::function<size_t(int)>& lds_of, bool larger_on_ties) {
+// water box), and at most `cap` threads. PSWFE_PARTICLE_THREADS overrides it (if that fits).
+int particle_threads(int P, const std::function<size_t(int)>& lds_of, bool larger_on_ties, int cap = 1024) {
   int best = 256, best_waves = 0;
-  const int tmax = pswfe::particle_max_threads_host(P);
+  const int tmax = std::min(cap, pswfe::particle_max_threads_host(P));
   for (int t = 256; t <= tmax; t *= 2) {
     const size_t lds = lds_of(t);
     if (lds > kLdsLimit) break;
@@ -504,7 +504,10 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
                        : g.col_tile ? pswfe::col_threads_host(P, g.col_tile)
                                     : particle_threads(P, [&](int t) { return spread_lds_bytes(S, P, D, t); }, true);
     const size_t gbytes = g.acc32 ? sizeof(float) : sizeof(double);
-    g.gather_threads = particle_threads(P, [&](int t) { return gather_lds_bytes(S, P, D, elem, t, gbytes); }, false);
+    // interpolation: at most 512 threads (1,024 measured slower on every workload: water box
+    // float64 55.2 against 52.9 us, n = 1e6 float32 468 against 366 us)
+    g.gather_threads =
+        particle_threads(P, [&](int t) { return gather_lds_bytes(S, P, D, elem, t, gbytes); }, false, 512);
     g.lds_spread = g.mfma       ? pswfe::mfma_lds_bytes(P, D, g.col_tile, g.acc32 ? sizeof(float) : sizeof(double))
                    : g.col_tile ? pswfe::col_lds_bytes(P, D, g.col_tile)
                                 : spread_lds_bytes(S, P, D, g.spread_threads);
