@@ -104,7 +104,7 @@ size_t spread_lds_bytes(int S, int P, int D, int threads) {
   return sizeof(double) * (static_cast<size_t>(S) * S * S + (threads / 16) * 3 * P) + coef_lds_bytes(P, D);
 }
 size_t gather_lds_bytes(int S, int P, int D, int elem, int threads, size_t gbytes = sizeof(double)) {
-  return static_cast<size_t>(elem) * S * S * S + sizeof(double) * 16 + gbytes * (threads / 16) * 6 * P +
+  return pswfe::gather_block_bytes(S, elem) + sizeof(double) * 16 + gbytes * (threads / 16) * 6 * P +
          coef_lds_bytes(P, D);
 }
 // LDS tile edge of interpolation and LDS-atomic spreading: the halo block B + P - 1 (supports
@@ -113,6 +113,10 @@ size_t gather_lds_bytes(int S, int P, int D, int elem, int threads, size_t gbyte
 // 42 us in float32 and from 50 to 76 us in float64). The register kernels use B + P - 1.
 int lds_edge(int B, int P) { return (B + P - 1) | 1; }
 constexpr size_t kLdsLimit = 160 * 1024;
+// largest LDS of the fused y/z FFT workgroup
+constexpr size_t kYzLdsMax = kLdsLimit;
+// fewest workgroups (spectrum columns over all systems) for which the fused y/z pass is chosen
+constexpr int kYzMinBlocks = 256;
 
 bool tile_fits(int B, int P, int elem) {
   const int S = lds_edge(B, P);
@@ -286,7 +290,15 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   d.nsys = nsys;
   d.sys.resize(nsys);
   std::vector<int> xblk_prefix(nsys + 1, 0), cblk_prefix(nsys + 1, 0), pblk_prefix(nsys + 1, 0);
-  std::vector<int> zblk_prefix(nsys + 1, 0);
+  std::vector<int> zblk_prefix(nsys + 1, 0), yzblk_prefix(nsys + 1, 0);
+  // y and z passes fused per spectrum column (k_fft_yz) when every system's (y, z) plane, two
+  // padded copies plus twiddles, fits in LDS and the columns of all systems give at least one
+  // workgroup per compute unit (batches of small grids: 256 systems of 16^3-50^3, 206 -> 153 us;
+  // a single 64^3 grid has 33 columns, and the three separate passes over 192 workgroups each
+  // took 30 against 31 us). PSWFE_YZ_FFT=0 turns it off, =1 on wherever it fits.
+  int yz_env = -1;
+  if (const char* env = std::getenv("PSWFE_YZ_FFT")) yz_env = std::atoi(env) != 0 ? 1 : 0;
+  bool yz_ok = yz_env != 0;
   // x and y FFTs fused per z-plane (PSWFE_PLANE_FFT=1) when every system's plane (two padded
   // copies of its half spectrum plus twiddles) fits in LDS. Off by default: measured on MI355X,
   // one workgroup per plane (64-128 of them) costs as much as the two separate passes it saves a
@@ -414,6 +426,14 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
     }
     sd.cblk_base = cblk_prefix[s];
     sd.zblk_base = zblk_prefix[s];
+    sd.yzblk_base = yzblk_prefix[s];
+    yzblk_prefix[s + 1] = yzblk_prefix[s] + nx1;
+    {
+      const size_t cap = std::max(static_cast<size_t>(mz) * (my + 1), static_cast<size_t>(my) * (mz + 1));
+      const size_t lds_yz = (2 * cap + 2 * static_cast<size_t>(my + mz)) * celem;
+      d.lds_yz = std::max(d.lds_yz, lds_yz);
+      if (lds_yz > kYzLdsMax) yz_ok = false;
+    }
     sd.part_base = part_prefix[s];
     const int ncb = (nx1 + sd.cols_per_block - 1) / sd.cols_per_block;
     xblk_prefix[s + 1] = xblk_prefix[s] + (my * mz + rpb - 1) / rpb;
@@ -544,6 +564,8 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   d.total_pblk = pblk_prefix[nsys];
   d.total_zblk = zblk_prefix[nsys];
   d.plane_fft = plane_ok ? 1 : 0;
+  d.yz_fft = yz_ok && !plane_ok && (yz_env == 1 || yzblk_prefix[nsys] >= kYzMinBlocks) ? 1 : 0;
+  d.total_yzblk = yzblk_prefix[nsys];
   d.total_cblk = cblk_prefix[nsys];
   d.n_max = counts ? part_prefix[nsys] : n_max;
   if (d.n_max > (int64_t(1) << 31) - 1) {
@@ -605,6 +627,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   const size_t o_xblk = dev.take(sizeof(int) * (nsys + 1));
   const size_t o_pblk = dev.take(sizeof(int) * (nsys + 1));
   const size_t o_zblk = dev.take(sizeof(int) * (nsys + 1));
+  const size_t o_yzblk = dev.take(sizeof(int) * (nsys + 1));
   const size_t o_cblk = dev.take(sizeof(int) * (nsys + 1));
   const size_t o_part = dev.take(sizeof(int64_t) * (nsys + 1));
   const size_t const_end = dev.size;
@@ -661,6 +684,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   d.xblk_prefix = reinterpret_cast<int*>(base + o_xblk);
   d.pblk_prefix = reinterpret_cast<int*>(base + o_pblk);
   d.zblk_prefix = reinterpret_cast<int*>(base + o_zblk);
+  d.yzblk_prefix = reinterpret_cast<int*>(base + o_yzblk);
   d.cblk_prefix = reinterpret_cast<int*>(base + o_cblk);
   d.part_prefix = reinterpret_cast<int64_t*>(base + o_part);
   d.coarse_count = reinterpret_cast<int*>(base + o_coarse);
@@ -753,6 +777,7 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   put_bytes(o_xblk, xblk_prefix.data(), sizeof(int) * (nsys + 1));
   put_bytes(o_pblk, pblk_prefix.data(), sizeof(int) * (nsys + 1));
   put_bytes(o_zblk, zblk_prefix.data(), sizeof(int) * (nsys + 1));
+  put_bytes(o_yzblk, yzblk_prefix.data(), sizeof(int) * (nsys + 1));
   put_bytes(o_cblk, cblk_prefix.data(), sizeof(int) * (nsys + 1));
   put_bytes(o_part, part_prefix.data(), sizeof(int64_t) * (nsys + 1));
   // ranges that must start at zero: each system's grid_a and the bin counters

@@ -1226,6 +1226,117 @@ __global__ __launch_bounds__(256) void k_fft_cols(int nsys, const SysDesc* __res
   }
 }
 
+// The y and z passes of one column kx of a system's half spectrum in one workgroup: forward y,
+// forward z, the scaling s_k, inverse z and inverse y (Alg. 2 steps 2-4 along y and z) with the
+// column's (y, z) plane of my x mz complex values kept in LDS between them, for grids whose plane
+// fits; one launch and one read and write of the spectrum instead of three. Block b of system s
+// is column kx = b - yzblk_base.
+template <class T>
+__global__ __launch_bounds__(512) void k_fft_yz(int nsys, const SysDesc* __restrict__ sys,
+                                                const int* __restrict__ yzblk_prefix) {
+  using C = typename Cplx<T>::type;
+  extern __shared__ unsigned char smem_raw[];
+  const SysDesc& sd = sys[find_sys(yzblk_prefix, nsys, static_cast<int>(blockIdx.x))];
+  const int my = sd.my, mz = sd.mz;
+  const int kx = static_cast<int>(blockIdx.x) - sd.yzblk_base;
+  const int ssy = my + 1, ssz = mz + 1;  // padded sequence strides: y sequences, then z sequences
+  const int cap = max(mz * ssy, my * ssz);
+  C* A = reinterpret_cast<C*>(smem_raw);
+  C* Bf = A + cap;
+  C* twy_p = Bf + cap;  // twiddles of length my (sign +, then -), then of length mz
+  C* twy_m = twy_p + my;
+  C* twz_p = twy_m + my;
+  C* twz_m = twz_p + mz;
+  const int ntw = 2 * (my + mz);
+  C twv[4];
+  {
+    const C* __restrict__ yp = static_cast<const C*>(sd.twyp);
+    const C* __restrict__ ym = static_cast<const C*>(sd.twym);
+    const C* __restrict__ zp = static_cast<const C*>(sd.twzp);
+    const C* __restrict__ zm = static_cast<const C*>(sd.twzm);
+    table_load(ntw, [&](int e) {
+      if (e < my) return gload(yp + e);
+      if (e < 2 * my) return gload(ym + (e - my));
+      if (e < 2 * my + mz) return gload(zp + (e - 2 * my));
+      return gload(zm + (e - 2 * my - mz));
+    }, twv);
+  }
+  const int64_t sp = sd.spec_pitch, plane = static_cast<int64_t>(my) * sp;
+  C* base = static_cast<C*>(sd.spec) + kx;
+  // sequence z of the y pass: A[z * ssy + y]
+  staged_copy<8>(
+      my * mz,
+      [&](int i) {
+        const int z = i / my, y = i - z * my;
+        return gload(base + z * plane + y * sp);
+      },
+      [&](int i, C v) {
+        const int z = i / my, y = i - z * my;
+        A[z * ssy + y] = v;
+      });
+  table_store(ntw, [&](int e, C v) { twy_p[e] = v; }, twv);
+  __syncthreads();
+  C* R = fft_lds(A, Bf, mz, ssy, sd.ffy, twy_p);  // forward y
+  C* W = (R == A) ? Bf : A;
+  for (int i = threadIdx.x; i < my * mz; i += blockDim.x) {  // sequence y of the z pass: W[y * ssz + z]
+    const int y = i / mz, z = i - y * mz;
+    W[y * ssz + z] = R[z * ssy + y];
+  }
+  __syncthreads();
+  R = fft_lds(W, R, my, ssz, sd.ffz, twz_p);  // forward z
+  {
+    const auto wk = as_global(static_cast<const T*>(sd.wk));
+    const auto wky = as_global(static_cast<const T*>(sd.wky));
+    const auto wkz = as_global(static_cast<const T*>(sd.wkz));
+    const T wx = wk[kx];
+    // K factors per thread computed (their table loads in flight together) before they are applied
+    constexpr int K = 8;
+    const int nt = static_cast<int>(blockDim.x), count = my * mz;
+    for (int i0 = threadIdx.x; i0 < count; i0 += K * nt) {
+      T sc[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = i0 + k * nt;
+        if (i >= count) break;
+        const int y = i / mz, z = i - y * mz;
+        const int ky = y <= (my - 1) / 2 ? y : my - y;
+        const int kz = z <= (mz - 1) / 2 ? z : mz - z;
+        T rad;
+        if (sd.radial == 0) {
+          rad = as_global(static_cast<const T*>(sd.tm))[kx * kx + ky * ky + kz * kz];
+        } else {
+          rad = static_cast<T>(radial_factor(sd, sd.w2x * kx * kx + sd.w2y * ky * ky + sd.w2z * kz * kz));
+        }
+        sc[k] = rad * wx * wky[ky] * wkz[kz];
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = i0 + k * nt;
+        if (i >= count) break;
+        const int y = i / mz, z = i - y * mz;
+        C v = R[y * ssz + z];
+        v.x *= sc[k];
+        v.y *= sc[k];
+        R[y * ssz + z] = v;
+      }
+    }
+  }
+  __syncthreads();
+  C* other = (R == A) ? Bf : A;
+  R = fft_lds(R, other, my, ssz, sd.ffz, twz_m);  // inverse z
+  W = (R == A) ? Bf : A;
+  for (int i = threadIdx.x; i < my * mz; i += blockDim.x) {  // back to sequences along y
+    const int z = i / my, y = i - z * my;
+    W[z * ssy + y] = R[y * ssz + z];
+  }
+  __syncthreads();
+  R = fft_lds(W, R, mz, ssy, sd.ffy, twy_m);  // inverse y
+  for (int i = threadIdx.x; i < my * mz; i += blockDim.x) {
+    const int z = i / my, y = i - z * my;
+    gstore(base + z * plane + y * sp, R[z * ssy + y]);
+  }
+}
+
 // Copies the float64 accumulation grid into a grid of the plan's precision and zeroes it.
 template <class T>
 __global__ void k_drain(double* __restrict__ acc, T* __restrict__ out, int64_t count) {
@@ -1321,15 +1432,29 @@ hipError_t transform_impl(const DevPlan& d, const void* in_override, void* out_o
     hipLaunchKernelGGL((k_fft_x_r2c<T, double>), dim3(d.total_xblk), dim3(256), d.lds_x, st, d.nsys, d.sys_dev,
                        d.xblk_prefix, static_cast<const double*>(nullptr), 1);
   stage_end(d, kStageFftX, st);
-  stage_begin(d, kStageFftY, st);
-  hipLaunchKernelGGL(k_fft_cols<T>, dim3(d.total_cblk), dim3(256), d.lds_c, st, d.nsys, d.sys_dev, d.cblk_prefix, 0);
-  stage_end(d, kStageFftY, st);
-  stage_begin(d, kStageFftZScale, st);
-  hipLaunchKernelGGL(k_fft_cols<T>, dim3(d.total_zblk), dim3(256), d.lds_c, st, d.nsys, d.sys_dev, d.zblk_prefix, 1);
-  stage_end(d, kStageFftZScale, st);
-  stage_begin(d, kStageIfftY, st);
-  hipLaunchKernelGGL(k_fft_cols<T>, dim3(d.total_cblk), dim3(256), d.lds_c, st, d.nsys, d.sys_dev, d.cblk_prefix, 2);
-  stage_end(d, kStageIfftY, st);
+  if (d.yz_fft) {
+    stage_begin(d, kStageFftY, st);  // fused into the z stage: recorded as an empty stage
+    stage_end(d, kStageFftY, st);
+    stage_begin(d, kStageFftZScale, st);
+    hipLaunchKernelGGL(k_fft_yz<T>, dim3(d.total_yzblk), dim3(512), d.lds_yz, st, d.nsys, d.sys_dev,
+                       d.yzblk_prefix);
+    stage_end(d, kStageFftZScale, st);
+    stage_begin(d, kStageIfftY, st);  // fused into the z stage
+    stage_end(d, kStageIfftY, st);
+  } else {
+    stage_begin(d, kStageFftY, st);
+    hipLaunchKernelGGL(k_fft_cols<T>, dim3(d.total_cblk), dim3(256), d.lds_c, st, d.nsys, d.sys_dev, d.cblk_prefix,
+                       0);
+    stage_end(d, kStageFftY, st);
+    stage_begin(d, kStageFftZScale, st);
+    hipLaunchKernelGGL(k_fft_cols<T>, dim3(d.total_zblk), dim3(256), d.lds_c, st, d.nsys, d.sys_dev, d.zblk_prefix,
+                       1);
+    stage_end(d, kStageFftZScale, st);
+    stage_begin(d, kStageIfftY, st);
+    hipLaunchKernelGGL(k_fft_cols<T>, dim3(d.total_cblk), dim3(256), d.lds_c, st, d.nsys, d.sys_dev, d.cblk_prefix,
+                       2);
+    stage_end(d, kStageIfftY, st);
+  }
   stage_begin(d, kStageIfftX, st);
   hipLaunchKernelGGL(k_fft_x_c2r<T>, dim3(d.total_xblk), dim3(256), d.lds_x, st, d.nsys, d.sys_dev, d.xblk_prefix,
                      static_cast<T*>(out_override));
@@ -1370,6 +1495,7 @@ hipError_t raise_fft_lds(const DevPlan& d) {
   if (e == hipSuccess) e = set(reinterpret_cast<const void*>(&k_fft_x_r2c<T, double>), d.lds_x);
   if (e == hipSuccess) e = set(reinterpret_cast<const void*>(&k_fft_x_c2r<T>), d.lds_x);
   if (e == hipSuccess) e = set(reinterpret_cast<const void*>(&k_fft_cols<T>), d.lds_c);
+  if (e == hipSuccess && d.yz_fft) e = set(reinterpret_cast<const void*>(&k_fft_yz<T>), d.lds_yz);
   // the binning fine pass stages its records in up to kFineLdsMax bytes
   if (e == hipSuccess && d.bin_levels == 2) e = set(reinterpret_cast<const void*>(&k_bin_fine<T>), kFineLdsMax);
   if (e == hipSuccess && d.bin_levels == 2) e = set(reinterpret_cast<const void*>(&k_bin_coarse<T>), coarse_lds_bytes<T>());

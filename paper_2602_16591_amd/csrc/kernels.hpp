@@ -58,6 +58,7 @@ struct SysDesc {
   int pblk_base = 0;          // first block (z-plane) of this system in the plane FFT launches
   int cblk_base = 0;          // first block in the y-direction FFT launches
   int zblk_base = 0;          // first block in the z-direction FFT launch
+  int yzblk_base = 0;         // first block (spectrum column kx) in the fused y/z FFT launch
   int64_t part_base = 0;      // first packed particle of this system
   double L = 0, inv_h = 0, ih_hi = 0, ih_lo = 0, self_coef = 0;  // x: box side, 1/h (split in two)
   double Ly = 0, inv_hy = 0, ihy_hi = 0, ihy_lo = 0;
@@ -103,6 +104,11 @@ struct SysDesc {
 inline int degree_bucket(int deg) { return deg <= 11 ? 11 : (deg <= 17 ? 17 : 28); }
 constexpr int coef_stride(int D) { return (D + 1) % 2 ? D + 1 : D + 2; }
 constexpr int kMaxDeg = 28;
+// Bytes of the interpolation's S^3 grid block at the start of its LDS, rounded up to 16 so that
+// the float64 arrays after it stay aligned.
+__host__ __device__ constexpr size_t gather_block_bytes(int S, size_t elem) {
+  return (elem * static_cast<size_t>(S) * S * S + 15) & ~static_cast<size_t>(15);
+}
 
 // Systems sharing one window support P and degree bucket D: their tiles form the contiguous
 // global range [tile_begin, tile_end), covered by one launch of each particle kernel
@@ -179,6 +185,11 @@ struct DevPlan {
   int* xblk_prefix = nullptr;      // nsys + 1, in system order
   int* zblk_prefix = nullptr;      // nsys + 1: blocks of the z-direction pass
   int total_zblk = 0;
+  // y and z passes fused per spectrum column (k_fft_yz) when every system's (y, z) plane fits in LDS
+  int yz_fft = 0;
+  int* yzblk_prefix = nullptr;     // nsys + 1: blocks (columns) of the fused pass
+  int total_yzblk = 0;
+  size_t lds_yz = 0;
   int* pblk_prefix = nullptr;      // nsys + 1: z-planes, for the plane FFT kernels
   int plane_fft = 0;               // x and y FFTs fused per z-plane (every system's plane fits in LDS)
   int total_pblk = 0;

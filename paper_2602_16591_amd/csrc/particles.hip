@@ -811,14 +811,12 @@ __device__ __forceinline__ void gather_tile(const typename Vec4<T>::type* __rest
         wx[j] = rec[j];
         dx[j] = rec[3 * P + j];
       }
-      auto load_row = [&](int e, T (&bl)[P]) {
-        const int jz = e / P, jy = e - jz * P;
-        const T* row = tb + ((o[2] + jz) * S + (o[1] + jy)) * S + o[0];
+      auto load_row = [&](int roff, T (&bl)[P]) {
+        const T* row = tb + roff;
 #pragma unroll
         for (int jx = 0; jx < P; ++jx) bl[jx] = row[jx];
       };
-      auto sum_row = [&](int e, const T (&bl)[P]) {
-        const int jz = e / P, jy = e - jz * P;
+      auto sum_row = [&](int jy, int jz, const T (&bl)[P]) {
         G sx0 = 0, sx1 = 0, sd0 = 0, sd1 = 0;
 #pragma unroll
         for (int jx = 0; jx + 1 < P; jx += 2) {
@@ -844,12 +842,27 @@ __device__ __forceinline__ void gather_tile(const typename Vec4<T>::type* __rest
       constexpr int L = kLanesPerParticle;
       {
         // one row at a time, its values loaded together before they are summed (two row
-        // buffers, the next row's loads in flight during the sums, measured slower)
+        // buffers, the next row's loads in flight during the sums, measured slower). Row e =
+        // (jy, jz) = (e mod P, e / P) of the lane's rows e = li, li + L, ... and its offset in
+        // the block advance by constant steps (one more z-line when jy passes P), without a
+        // division per row.
+        constexpr int DY = L % P, DZ = L / P;
+        int jz = li / P, jy = li - jz * P;
+        int roff = ((o[2] + jz) * S + (o[1] + jy)) * S + o[0];
+        const int step = (DZ * S + DY) * S, wrap = (S - P) * S;
 #pragma unroll 2
         for (int e = li; e < P * P; e += L) {
           T bl[P];
-          load_row(e, bl);
-          sum_row(e, bl);
+          load_row(roff, bl);
+          sum_row(jy, jz, bl);
+          jy += DY;
+          jz += DZ;
+          roff += step;
+          if (jy >= P) {
+            jy -= P;
+            jz += 1;
+            roff += wrap;
+          }
         }
       }
     }
@@ -910,7 +923,6 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
                                                 T* __restrict__ vec, int vec_mode, int add_self,
                                                 double* __restrict__ energy, const double* __restrict__ phi_add,
                                                 const double* __restrict__ vec_add) {
-  constexpr int REC = 6 * P;
   constexpr int CS = coef_stride(D);
   // dynamic LDS only (see k_spread_mfma)
   extern __shared__ unsigned char smem_raw[];
@@ -923,11 +935,13 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
   const SysDesc& sd = sys[s];
   const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S;
   const global_ptr<T> grid = as_global(grid_override ? grid_override : static_cast<const T*>(sd.grid_b));
-  const int nslots = blockDim.x / kLanesPerParticle;
-  double* s_red = reinterpret_cast<double*>(smem_raw);             // 16: the energy's per-wave sums
-  double* lcoef = s_red + 16;                                      // P * CS
-  G* recs = reinterpret_cast<G*>(lcoef + P * CS);                  // nslots * REC
-  T* tb = reinterpret_cast<T*>(recs + nslots * REC);
+  // the S^3 block first, at LDS address 0, so that a row's offsets from its first value fit
+  // the immediate offsets of the LDS loads; then the energy's per-wave sums (16), the
+  // coefficients (P * CS) and one window record per particle slot
+  T* tb = reinterpret_cast<T*>(smem_raw);
+  double* s_red = reinterpret_cast<double*>(smem_raw + gather_block_bytes(S, sizeof(T)));
+  double* lcoef = s_red + 16;
+  G* recs = reinterpret_cast<G*>(lcoef + P * CS);
   const int tile = gtile - sd.tile_base;
   const int tx = tile % Tn, ty = (tile / Tn) % sd.Tny, tz = tile / (Tn * sd.Tny);
   const int T0x = tx * B, T0y = ty * B, T0z = tz * B;

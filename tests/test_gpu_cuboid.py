@@ -126,8 +126,12 @@ def test_doubled_box_equals_cube(axis):
         assert abs(float(Eb.cpu()[0]) - 2 * float(Ea.cpu()[0])) < 1e-10 * abs(float(Ea.cpu()[0]))
 
 
+@pytest.mark.parametrize("yz", ["1", "0"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_batch_mixes_cubes_and_cuboids(prec):
+def test_batch_mixes_cubes_and_cuboids(prec, yz, monkeypatch):
+    """A batch of cubes and cuboids against one plan per system; yz=1 runs the batch's y and z
+    FFT passes and the scaling fused per spectrum column (on cuboid planes), against the
+    separate passes of the single-system plans."""
     systems = [((1.0, 1.3, 0.8), 1500, 83), ((1.0, 1.0, 1.0), 900, 84), ((0.9, 1.5, 1.2), 2000, 85)]
     params, xs, qs = [], [], []
     for sides, n, seed in systems:
@@ -138,7 +142,9 @@ def test_batch_mixes_cubes_and_cuboids(prec):
         xs.append(x)
         qs.append(q)
     counts = [len(q) for q in qs]
+    monkeypatch.setenv("PSWFE_YZ_FFT", yz)
     plan = pw.BatchPlan(params, counts, prec)
+    monkeypatch.setenv("PSWFE_YZ_FFT", "0")
     phi, F, E = plan.compute(tdev(np.concatenate(xs), prec), tdev(np.concatenate(qs), prec), total=True)
     lphi, lF, lE = plan.split(phi.cpu().numpy()), plan.split(F.cpu().numpy()), E.cpu().numpy()
     tol = 1e-12 if prec == "fp64" else 1e-6

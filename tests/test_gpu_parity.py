@@ -266,11 +266,11 @@ def test_single_charge_window_precision(prec):
     assert worst < (4 * fit_tol(1e-6, prec) + 8 * U[prec]), worst
 
 
-@pytest.mark.parametrize("plane", ["1", "0"])
+@pytest.mark.parametrize("fusion", ["plane", "yz", "none"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("m,eps", [(16, 1e-4), (30, 1e-6), (64, 1e-6), (42, 1e-10), (56, 1e-6), (128, 1e-6),
                                    (96, 1e-10), (112, 1e-10)])
-def test_transform_matches_oracle(m, eps, prec, plane, monkeypatch):
+def test_transform_matches_oracle(m, eps, prec, fusion, monkeypatch):
     """Steps 2-4: b = F^-1 (s . F a) against the oracle's s and numpy's FFT, on the oracle's spread
     grid of seeded random charges (the grids this step sees).
 
@@ -279,14 +279,17 @@ def test_transform_matches_oracle(m, eps, prec, plane, monkeypatch):
     noise of relative size u in ahat becomes O(u / eps_w) in the band-edge modes of b itself,
     and interpolation multiplies it by phihat ~ eps_w again. The weighted error is what reaches phi.
 
-    plane=1 lets the plan fuse the x and y FFTs per z-plane where the plane fits in LDS (m <= 128
-    in float32, m <= 98 in float64; m = 112 in float64 takes the separate passes either way);
-    plane=0 (the default) runs the separate x and y passes.
+    fusion=plane lets the plan fuse the x and y FFTs per z-plane where the plane fits in LDS
+    (m <= 128 in float32, m <= 98 in float64; m = 112 in float64 takes the separate passes either
+    way); fusion=yz runs the y and z passes and the scaling in one workgroup per spectrum column
+    where its (y, z) plane fits in LDS (m up to about 100 in float32, 70 in float64), which a single
+    system only takes when asked; fusion=none runs the separate passes.
     """
     from oracle.pswf import PSWF, window_hat_1d
     if prec != "fp64" and eps < 1e-8:
         pytest.skip("fp32 path is for eps >= 1e-6")
-    monkeypatch.setenv("PSWFE_PLANE_FFT", plane)
+    monkeypatch.setenv("PSWFE_PLANE_FFT", "1" if fusion == "plane" else "0")
+    monkeypatch.setenv("PSWFE_YZ_FFT", "1" if fusion == "yz" else "0")
     L = 1.0
     c, o = both_params(eps, L, m=m)
     plan = pw.Plan(c, prec, n_max=1)
