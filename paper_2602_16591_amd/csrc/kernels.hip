@@ -1337,13 +1337,14 @@ __global__ __launch_bounds__(512) void k_fft_yz(int nsys, const SysDesc* __restr
   }
 }
 
-// Copies the float64 accumulation grid into a grid of the plan's precision and zeroes it.
-template <class T>
-__global__ void k_drain(double* __restrict__ acc, T* __restrict__ out, int64_t count) {
+// Copies the accumulation grid (float64, or float32 where the plan accumulates in float32) into
+// a grid of the plan's precision and zeroes it.
+template <class TA, class T>
+__global__ void k_drain(TA* __restrict__ acc, T* __restrict__ out, int64_t count) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < count;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     out[i] = static_cast<T>(acc[i]);
-    acc[i] = 0.0;
+    acc[i] = TA(0);
   }
 }
 
@@ -1428,6 +1429,9 @@ hipError_t transform_impl(const DevPlan& d, const void* in_override, void* out_o
   if (in_override)
     hipLaunchKernelGGL((k_fft_x_r2c<T, T>), dim3(d.total_xblk), dim3(256), d.lds_x, st, d.nsys, d.sys_dev,
                        d.xblk_prefix, static_cast<const T*>(in_override), 0);
+  else if (std::is_same_v<T, float> && d.grid32)
+    hipLaunchKernelGGL((k_fft_x_r2c<T, float>), dim3(d.total_xblk), dim3(256), d.lds_x, st, d.nsys, d.sys_dev,
+                       d.xblk_prefix, static_cast<const float*>(nullptr), 1);
   else
     hipLaunchKernelGGL((k_fft_x_r2c<T, double>), dim3(d.total_xblk), dim3(256), d.lds_x, st, d.nsys, d.sys_dev,
                        d.xblk_prefix, static_cast<const double*>(nullptr), 1);
@@ -1585,10 +1589,15 @@ hipError_t launch_drain(const DevPlan& d, void* out, hipStream_t st) {
   const SysDesc& s0 = d.sys[0];
   const int64_t count = static_cast<int64_t>(s0.m) * s0.my * s0.mz;
   const unsigned nb = std::max(1u, std::min<unsigned>(blocks_for(count, 256), 4096u));
-  if (d.prec == 0)
-    hipLaunchKernelGGL(k_drain<float>, dim3(nb), dim3(256), 0, st, s0.grid_a, static_cast<float*>(out), count);
+  if (d.prec == 0 && d.grid32)
+    hipLaunchKernelGGL((k_drain<float, float>), dim3(nb), dim3(256), 0, st, reinterpret_cast<float*>(s0.grid_a),
+                       static_cast<float*>(out), count);
+  else if (d.prec == 0)
+    hipLaunchKernelGGL((k_drain<double, float>), dim3(nb), dim3(256), 0, st, s0.grid_a, static_cast<float*>(out),
+                       count);
   else
-    hipLaunchKernelGGL(k_drain<double>, dim3(nb), dim3(256), 0, st, s0.grid_a, static_cast<double*>(out), count);
+    hipLaunchKernelGGL((k_drain<double, double>), dim3(nb), dim3(256), 0, st, s0.grid_a, static_cast<double*>(out),
+                       count);
   return hipGetLastError();
 }
 

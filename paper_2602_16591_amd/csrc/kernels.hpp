@@ -187,6 +187,8 @@ struct DevPlan {
   int total_zblk = 0;
   // y and z passes fused per spectrum column (k_fft_yz) when every system's (y, z) plane fits in LDS
   int yz_fft = 0;
+  // float32-arithmetic plans whose spread accumulates into grid_a read as a float32 grid
+  int grid32 = 0;
   int* yzblk_prefix = nullptr;     // nsys + 1: blocks (columns) of the fused pass
   int total_yzblk = 0;
   size_t lds_yz = 0;

@@ -370,7 +370,8 @@ __global__ __launch_bounds__((col_threads<P, B>())) void k_spread_cols(
 // column l % 16; float32, item r of lane l at row 4 (l / 16) + r, column l % 16. Operand a of lane
 // l is A[l % 16][l / 16], operand b is B[l / 16][l % 16].
 // A = float keeps window values, products and the tile's sums in float32 on the matrix cores
-// (the float32 arithmetic path of float32 plans); the block is flushed into the float64 grid.
+// (the float32 arithmetic path of float32 plans); the block is flushed into the float64 grid,
+// or (grid32, A = float only) into the same buffer read as a float32 grid.
 template <class A>
 struct MfmaAcc;
 template <>
@@ -390,6 +391,19 @@ struct MfmaAcc<float> {
   static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
 };
 
+// One value of a tile's block added to the grid: float64, or float32 where the plan
+// accumulates its float32-arithmetic spread in a float32 grid (grid32).
+template <class A>
+__device__ __forceinline__ void flush_add(double* grid, int64_t gi, double v, int grid32) {
+  if constexpr (sizeof(A) == sizeof(float)) {
+    if (grid32) {
+      atomic_add_global(reinterpret_cast<float*>(grid) + gi, static_cast<float>(v));
+      return;
+    }
+  }
+  atomic_add_global(grid + gi, v);
+}
+
 constexpr int kMfmaPieces = 4;
 template <int P, int B>
 constexpr int mfma_row_pieces() { return (col_edge<P, B>() * col_edge<P, B>() + 15) / 16; }
@@ -406,7 +420,7 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
     const typename Vec4<T>::type* __restrict__ sorted, const int* __restrict__ cells,
     const int* __restrict__ tile_start, int sub_log2, int nsys, const SysDesc* __restrict__ sys,
     const int* __restrict__ tile_prefix, const int* __restrict__ tile_sys, int tile_offset, int parts, int xcd,
-    int seg_len, int nseg) {
+    int seg_len, int nseg, int grid32) {
   constexpr int S = col_edge<P, B>();
   constexpr int MR = mfma_row_pieces<P, B>();
   constexpr bool SL = mfma_sliced<P, B>();
@@ -670,7 +684,7 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         if (li[j] < 0) continue;
-        if (v[j] != 0.0) atomic_add_global(grid + gi[j], v[j]);
+        if (v[j] != 0.0) flush_add<A>(grid, gi[j], v[j], grid32);
         ring[li[j]] = 0.0;
       }
     }
@@ -721,7 +735,7 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
       S, m, sd.my, sd.mz, T0x + 1 - half, T0y + 1 - half, T0z + 1 - half,
       [&](int k, int li_, int64_t) { v[k] = blk[li_]; },
       [&](int k, int, int64_t gi) {
-        if (v[k] != 0.0) atomic_add_global(grid + gi, v[k]);
+        if (v[k] != 0.0) flush_add<A>(grid, gi, v[k], grid32);
       });
   break;
   }
@@ -1020,7 +1034,7 @@ hipError_t spread_impl(const DevPlan& d, const PGroup& g, hipStream_t st) {
       hipLaunchKernelGGL(kern, dim3(roll ? g.roll_cols * g.roll_nseg : (g.tile_end - g.tile_begin) * g.parts),
                          dim3(threads), g.lds_spread, st, static_cast<const typename Vec4<T>::type*>(d.sorted),
                          d.cells, d.tile_start, d.sub_log2, d.nsys, d.sys_dev, d.tile_prefix, d.tile_sys,
-                         g.tile_begin, g.parts, g.xcd_spread, g.roll_len, g.roll_nseg);
+                         g.tile_begin, g.parts, g.xcd_spread, g.roll_len, g.roll_nseg, d.grid32);
     };
     auto mf = [&](auto acc) {
       using A = decltype(acc);

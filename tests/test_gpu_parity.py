@@ -112,6 +112,29 @@ def test_spread_matches_oracle(case, prec):
     assert np.all(np.abs(g - a) <= tol), float(np.max(np.abs(g - a) / tol))
 
 
+@pytest.mark.parametrize("case", SMALL, ids=[c[0] for c in SMALL])
+def test_spread_into_float32_grid_matches_oracle(case, monkeypatch):
+    """Float32 arithmetic with the tile blocks added into a float32 grid (float32 atomics; plans
+    take it on grids of 2^20 points and more, forced here). Each grid point is the float32 sum
+    of the blocks of the tiles whose halo covers it, at most ceil(S / B)^3 <= ceil((P + 3) / 4)^3
+    of them (tile edge B >= 4, halo edge S = B + P - 1): recursive summation adds at most that
+    many roundings of the sum of |terms| to the float32-arithmetic bound."""
+    _, gen, eps, kw = case
+    if eps < 1e-6:
+        pytest.skip("fp32 path is for eps >= 1e-6")
+    monkeypatch.setenv("PSWFE_GRID32", "1")
+    prec = "fp32_arith"
+    x, q, L, kw = _sys(gen, eps, kw, prec)
+    c, o = both_params(eps, L, **kw)
+    plan = pw.Plan(c, prec, n_max=len(q))
+    g = plan.spread(tdev(x, prec), tdev(q, prec)).cpu().numpy()       # [z, y, x]
+    a = fast.spread(np.mod(x, L), q, o).transpose(2, 1, 0)
+    A = fast.spread(np.mod(x, L), np.abs(q), o).transpose(2, 1, 0)
+    n_add = math.ceil((o.P + 3) / 4) ** 3
+    tol = spread_tol(x, q, o, eps, prec, A) + n_add * U[prec] * A
+    assert np.all(np.abs(g - a) <= tol), float(np.max(np.abs(g - a) / tol))
+
+
 SPREAD_KERNEL_CASES = [
     # (name, generator, eps, params kwargs, tile): tile 8 can run either spreading kernel
     ("uniform_m32_P11_tile8", lambda: W.uniform_pm1(700, seed=21), 1e-6, dict(m=32), 8),
@@ -325,12 +348,16 @@ def test_interpolate_matches_oracle(case, prec):
 
 
 @pytest.mark.parametrize("levels", ["1", "2"])
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_arith"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_arith", "fp32_arith_grid32"])
 @pytest.mark.parametrize("case", SMALL, ids=[c[0] for c in SMALL])
 def test_compute_matches_fast_oracle(case, prec, levels, monkeypatch):
     """Whole pipeline against Alg. 2 in float64: phi, forces and energy, with either binning
-    (one-level counting sort, or the two-level sort that large systems take)."""
+    (one-level counting sort, or the two-level sort that large systems take); fp32_arith_grid32
+    spreads into a float32 grid (as plans do on grids of 2^20 points and more)."""
     monkeypatch.setenv("PSWFE_BIN_LEVELS", levels)
+    if prec == "fp32_arith_grid32":
+        monkeypatch.setenv("PSWFE_GRID32", "1")
+        prec = "fp32_arith"
     _, gen, eps, kw = case
     if prec != "fp64" and eps < 1e-6:
         pytest.skip("fp32 path is for eps >= 1e-6")
