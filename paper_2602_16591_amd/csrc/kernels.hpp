@@ -145,19 +145,24 @@ inline int mfma_threads_host(int P, int B) {
 // (S > 16), and every particle's x-support fits the columns [0, 16) (o_x <= 16 - P) or
 // [S - 16, S) (o_x >= S - 16), o_x in [0, B): B + 2 P <= 34.
 constexpr bool mfma_sliced_host(int P, int B) { return B + P - 1 > 16 && B + 2 * P <= 34; }
-constexpr int kMfmaRecordsHost = kColBatchHost + 8;  // a batch plus the padding of two slices
+// particles per batch of the matrix-core spread: one tile per workgroup, and by columns of tiles
+constexpr int kMfmaBatchHost = 64, kMfmaRollBatchHost = 32;
+// LDS of a batch's records: coefficients, offsets, window values, and slots for a batch plus the
+// padding of two slices
+inline size_t mfma_batch_lds_bytes(int P, int D, int B, size_t acc_bytes, int batch) {
+  const size_t S = static_cast<size_t>(col_edge_host(P, B)), nrec = static_cast<size_t>(batch) + 8;
+  return sizeof(double) * (static_cast<size_t>(P) * coef_stride(D) + nrec * 4) + sizeof(int) * nrec * 4 +
+         acc_bytes * nrec * 3 * S + 16;
+}
 inline size_t mfma_lds_bytes(int P, int D, int B, size_t acc_bytes) {
   const size_t S = static_cast<size_t>(col_edge_host(P, B));
-  const size_t batch = sizeof(double) * (static_cast<size_t>(P) * coef_stride(D) + kMfmaRecordsHost * 4) +
-                       sizeof(int) * kMfmaRecordsHost * 4 + acc_bytes * kMfmaRecordsHost * 3 * S + 16;
+  const size_t batch = mfma_batch_lds_bytes(P, D, B, acc_bytes, kMfmaBatchHost);
   return std::max(batch, sizeof(double) * S * S * S);  // the records, then the block
 }
 // The same with the ring of a column of tiles (S^3 float64) ahead of the records.
 inline size_t mfma_roll_lds_bytes(int P, int D, int B, size_t acc_bytes) {
   const size_t S = static_cast<size_t>(col_edge_host(P, B));
-  const size_t batch = sizeof(double) * (static_cast<size_t>(P) * coef_stride(D) + kMfmaRecordsHost * 4) +
-                       sizeof(int) * kMfmaRecordsHost * 4 + acc_bytes * kMfmaRecordsHost * 3 * S + 16;
-  return sizeof(double) * S * S * S + batch;
+  return sizeof(double) * S * S * S + mfma_batch_lds_bytes(P, D, B, acc_bytes, kMfmaRollBatchHost);
 }
 inline size_t col_lds_bytes(int P, int D, int B) {
   const int S = col_edge_host(P, B);

@@ -413,7 +413,11 @@ template <int P, int B>
 constexpr int mfma_threads() { return 64 * ((mfma_row_pieces<P, B>() + kMfmaPieces - 1) / kMfmaPieces); }
 template <int P, int B>
 constexpr bool mfma_sliced() { return mfma_sliced_host(P, B); }
-constexpr int kMfmaRecords = kColBatch + 8;  // a batch plus the padding of two slices
+// Particles per batch of the matrix-core spread: 64 (fewer barrier-separated rounds: water box
+// 44.6 -> 43.8 us, n = 1e6 float32 417 -> 391 us against 32), 32 by columns of tiles (float64
+// n = 1e6: 2.19 against 2.33 ms with 64). Record slots: a batch plus the padding of two slices.
+template <bool ROLL>
+constexpr int mfma_batch() { return ROLL ? kMfmaRollBatchHost : kMfmaBatchHost; }
 
 template <class T, int P, int D, int B, class A, bool ROLL>
 __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
@@ -428,6 +432,8 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
   constexpr int X1 = S - 16;                              // first column of slice 1
   constexpr int CS = coef_stride(D);
   constexpr int RS = 3 * S;
+  constexpr int CB = mfma_batch<ROLL>(), NREC = CB + 8;
+  static_assert(CB <= 64 && NREC <= 128, "wave 0 holds a batch and marks its slots");
   using M = MfmaAcc<A>;
   typedef typename M::v4 acc_t;
   // dynamic LDS only: a static array beside a large dynamic allocation measured 2.8x slower
@@ -450,11 +456,11 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
   double* __restrict__ grid = sd.grid_a;
   double* ring = reinterpret_cast<double*>(smem_raw);      // ROLL: S^3
   double* lcoef = ring + (ROLL ? S * S * S : 0);           // P * CS
-  double* pg = lcoef + P * CS;                             // kMfmaRecords * 4: g_x, g_y, g_z, q
-  int* po = reinterpret_cast<int*>(pg + kMfmaRecords * 4); // kMfmaRecords * 4: o_x, o_y, o_z, valid
-  A* recs = reinterpret_cast<A*>(po + kMfmaRecords * 4);   // kMfmaRecords * RS
+  double* pg = lcoef + P * CS;                             // NREC * 4: g_x, g_y, g_z, q
+  int* po = reinterpret_cast<int*>(pg + NREC * 4);         // NREC * 4: o_x, o_y, o_z, valid
+  A* recs = reinterpret_cast<A*>(po + NREC * 4);           // NREC * RS
   // groups of 4: slice 0 in [0, s_split[0]), slice 1 up to s_split[1]
-  int* s_split = reinterpret_cast<int*>(recs + kMfmaRecords * RS);
+  int* s_split = reinterpret_cast<int*>(recs + NREC * RS);
   int tx, ty, tz, z1 = 0;
   if constexpr (ROLL) {
     const int col = wgid / nseg, seg = wgid - col * nseg;
@@ -514,15 +520,15 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[u][c] = acc_t{0, 0, 0, 0};
   if constexpr (ROLL) __syncthreads();  // the ring's zeros, or the previous tile's flush
-  for (int b0 = p0; b0 < p1; b0 += kColBatch) {
-    const int nb = min(kColBatch, p1 - b0);
+  for (int b0 = p0; b0 < p1; b0 += CB) {
+    const int nb = min(CB, p1 - b0);
     const auto r = r_next;
     const int cp = c_next;
-    if (t < kColBatch) {
-      r_next = sorted[min(b0 + kColBatch + t, p1 - 1)];
-      c_next = cells[min(b0 + kColBatch + t, p1 - 1)];
+    if (t < CB) {
+      r_next = sorted[min(b0 + CB + t, p1 - 1)];
+      c_next = cells[min(b0 + CB + t, p1 - 1)];
     }
-    if (t < 64) {  // wave 0 holds the batch (kColBatch <= 64): record slots, ordered by slice
+    if (t < 64) {  // wave 0 holds the batch (CB <= 64): record slots, ordered by slice
       const bool act = t < nb;
       const int ox = cell_x(cp) - T0x;
       int pos = t, ng0 = (nb + 3) >> 2, ng = ng0;
@@ -535,9 +541,18 @@ __global__ __launch_bounds__((mfma_threads<P, B>())) void k_spread_mfma(
         ng0 = n0p >> 2;
         ng = ng0 + ((n1 + 3) >> 2);
         // slots of the padding: [n0, n0p) and [n0p + n1, 4 ng)
+        // (lane t marks slots t and t + 64: a batch of more than 58 particles has slots beyond
+        // the wave's lanes)
         if (t < 4 * ng && !((t < n0) || (t >= n0p && t < n0p + n1))) po[4 * t + 3] = 0;
+        if constexpr (NREC > 64) {
+          const int t2 = t + 64;
+          if (t2 < 4 * ng && !((t2 < n0) || (t2 >= n0p && t2 < n0p + n1))) po[4 * t2 + 3] = 0;
+        }
       } else {
         if (t >= nb && t < 4 * ng) po[4 * t + 3] = 0;
+        if constexpr (NREC > 64) {
+          if (t + 64 < 4 * ng) po[4 * (t + 64) + 3] = 0;  // t + 64 >= nb
+        }
       }
       if (act) {
         pg[4 * pos + 0] = static_cast<double>(r.x);
