@@ -567,6 +567,17 @@ pswfe_status build_plan(std::vector<pswfe::Params> ps, int prec, int64_t n_max, 
   d.total_zblk = zblk_prefix[nsys];
   d.plane_fft = plane_ok ? 1 : 0;
   d.yz_fft = yz_ok && !plane_ok && (yz_env == 1 || yzblk_prefix[nsys] >= kYzMinBlocks) ? 1 : 0;
+  // Interpolation by tile sequences (k_gather_stream) for float64 single systems with at least
+  // 2,048 tiles (n = 1e6: 216^3 2.55 -> 2.50 ms, 128^3 1.88 -> 1.80 ms): PSWFE_GATHER_STREAM=0
+  // turns it off, =1 on for any float64 single system.
+  {
+    int env = -1;
+    if (const char* e = std::getenv("PSWFE_GATHER_STREAM")) env = std::atoi(e) != 0 ? 1 : 0;
+    const int tiles = d.sys[0].Tn * d.sys[0].Tny * d.sys[0].Tnz;
+    if (nsys == 1 && d.groups.size() == 1 && d.groups[0].parts == 1 && prec == PSWFE_FP64 &&
+        (env == 1 || (env != 0 && tiles >= 2048)))
+      d.groups[0].gather_stream = -1;
+  }
   // Float32-arithmetic plans spread into a float32 grid (grid_a's bytes read as float32, summed
   // with float32 atomics) when every group spreads on the matrix cores and the grids hold at
   // least kGrid32MinPoints points in all: 256-system ensemble 1.16 -> 0.95 ms, n = 1e6 on 128^3

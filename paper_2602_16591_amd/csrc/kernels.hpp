@@ -125,6 +125,10 @@ struct PGroup {
   // matrix-core spreading by columns of tiles with a ring of z-planes in LDS (single systems):
   // roll_len tiles per workgroup, roll_nseg segments per column, roll_cols columns (0: off)
   int roll_len = 0, roll_nseg = 0, roll_cols = 0;
+  // interpolation by a fixed grid of workgroups that each take a sequence of tiles, loading the
+  // next tile's block while interpolating the current one: its workgroup count (0: off; the plan
+  // sets -1 to ask for it, and preparing the kernels resolves it)
+  int gather_stream = 0;
   size_t lds_spread = 0, lds_gather = 0;  // maxima over the group's systems
 };
 

@@ -1036,6 +1036,173 @@ __global__ __launch_bounds__(particle_max_threads<P>()) void k_gather(const type
   if (energy) gather_energy(esum, s_red, energy + s);
 }
 
+// Interpolation of one system by a fixed grid of workgroups that each take a sequence of tiles
+// (float64 plans on large grids, where one 125 KB block per compute unit leaves no second
+// workgroup to hide the block's loading). While a tile's particles are interpolated from its
+// block in LDS, the first half of the next tile's block is loaded into registers as aligned
+// 16-byte row segments and written to LDS once the tile is done, with the rest (at most
+// kStreamChunks segments per thread in all); a tile whose rows wrap around the grid in x, or whose
+// block has more segments, is loaded after the tile instead.
+// Workgroup w runs on XCD w mod 8 (the dispatch order): the XCD's workgroups take consecutive
+// tiles of one eighth of the tile range, so neighbouring tiles' overlapping blocks are read
+// through the same L2.
+constexpr int kStreamChunks = 16;
+// segments per thread loaded ahead, during the previous tile (registers held across its
+// interpolation: 16 took 256 VGPRs and spilled)
+constexpr int kStreamAhead = 4;
+
+template <class T>
+struct StreamBlock {
+  int Ox, Oy, Oz, a0, nch, items;
+  bool vec;  // loaded as 16-byte segments
+};
+
+template <class T, int P, int D, class G>
+__global__ __launch_bounds__(particle_max_threads<P>()) void k_gather_stream(
+    const typename Vec4<T>::type* __restrict__ sorted, const int* __restrict__ cells, const int* __restrict__ perm,
+    const int* __restrict__ tile_start, int sub_log2, const SysDesc* __restrict__ sys, int tile_offset, int ntiles,
+    const T* __restrict__ grid_override, T* __restrict__ phi, T* __restrict__ vec, int vec_mode, int add_self,
+    double* __restrict__ energy, const double* __restrict__ phi_add, const double* __restrict__ vec_add) {
+  constexpr int CS = coef_stride(D);
+  constexpr int VW = 16 / static_cast<int>(sizeof(T));
+  using V16 = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+  extern __shared__ unsigned char smem_raw[];
+  const SysDesc& sd = sys[0];
+  const int m = sd.m, B = sd.B, Tn = sd.Tn, S = sd.S;
+  T* tb = reinterpret_cast<T*>(smem_raw);
+  double* s_red = reinterpret_cast<double*>(smem_raw + gather_block_bytes(S, sizeof(T)));
+  double* lcoef = s_red + 16;
+  G* recs = reinterpret_cast<G*>(lcoef + P * CS);
+  const T* gsrc = grid_override ? grid_override : static_cast<const T*>(sd.grid_b);
+  const bool aligned = m % VW == 0 && (reinterpret_cast<uintptr_t>(gsrc) & 15) == 0;
+  const int nt = static_cast<int>(blockDim.x), t = static_cast<int>(threadIdx.x);
+  const int half = (P + 1) / 2;
+  // tile sequence: XCD x = w mod 8 takes tiles [x per, (x + 1) per), its workgroups in turn
+  const int w = static_cast<int>(blockIdx.x), G8 = static_cast<int>(gridDim.x) / 8;
+  const int xcd = w % 8, per = (ntiles + 7) / 8;
+  const int first = xcd * per, last = min(ntiles, first + per);
+  auto block_of = [&](int u) {
+    const int tile = tile_offset + u - sd.tile_base;
+    const int tx = tile % Tn, ty = (tile / Tn) % sd.Tny, tz = tile / (Tn * sd.Tny);
+    StreamBlock<T> b;
+    b.Ox = tx * B + 1 - half;
+    b.Oy = ty * B + 1 - half;
+    b.Oz = tz * B + 1 - half;
+    b.a0 = b.Ox & ~(VW - 1);
+    b.nch = (b.Ox + S - b.a0 + VW - 1) / VW;
+    b.items = S * S * b.nch;
+    b.vec = aligned && b.Ox >= 0 && b.Ox + S <= m && b.items <= kStreamChunks * nt;
+    return b;
+  };
+  auto seg_addr = [&](const StreamBlock<T>& b, int it, int& row, int& ch) {
+    row = it / b.nch;
+    ch = it - row * b.nch;
+    const int z = row / S, y = row - z * S;
+    return (static_cast<int64_t>(fold_index(b.Oz + z, sd.mz)) * sd.my + fold_index(b.Oy + y, sd.my)) * m + b.a0 +
+           ch * VW;
+  };
+  auto seg_store = [&](const StreamBlock<T>& b, int row, int ch, const V16& v) {
+    const T* e = reinterpret_cast<const T*>(&v);
+#pragma unroll
+    for (int j = 0; j < VW; ++j) {
+      const int x = b.a0 + ch * VW + j - b.Ox;
+      if (x >= 0 && x < S) tb[row * S + x] = e[j];
+    }
+  };
+  auto stage_now = [&](const StreamBlock<T>& b) {  // the block loaded and stored in one pass
+    if (b.vec) {
+      V16 v[kStreamChunks];
+#pragma unroll
+      for (int k = 0; k < kStreamChunks; ++k) {
+        const int it = t + k * nt;
+        int row, ch;
+        if (it < b.items) v[k] = *reinterpret_cast<const V16*>(gsrc + seg_addr(b, it, row, ch));
+      }
+#pragma unroll
+      for (int k = 0; k < kStreamChunks; ++k) {
+        const int it = t + k * nt;
+        int row, ch;
+        if (it < b.items) {
+          (void)seg_addr(b, it, row, ch);
+          seg_store(b, row, ch, v[k]);
+        }
+      }
+    } else {
+      const global_ptr<T> grid = as_global(gsrc);
+      T v[8];
+      walk_tile<8>(
+          S, m, sd.my, sd.mz, b.Ox, b.Oy, b.Oz, [&](int k, int, int64_t gi) { v[k] = grid[gi]; },
+          [&](int k, int li_, int64_t) { tb[li_] = v[k]; });
+    }
+  };
+  int u = first + w / 8;
+  if (G8 == 0 || u >= last) return;
+  double cv[kCoefPerThread];
+  coef_load<P, D>(sd.coef, sd.deg, cv);
+  StreamBlock<T> cur = block_of(u);
+  stage_now(cur);
+  coef_store<P, D>(lcoef, cv);
+  __syncthreads();
+  double esum = 0.0;
+  const GatherOut<T, P, D, G> out{phi, vec, vec_mode, add_self, phi_add, vec_add};
+  const int slot = t >> 4;
+  for (;;) {
+    const int un = u + G8;
+    const bool more = un < last;
+    StreamBlock<T> nxt{};
+    V16 pre[kStreamAhead];
+    if (more) {
+      nxt = block_of(un);
+      if (nxt.vec) {
+#pragma unroll
+        for (int k = 0; k < kStreamAhead; ++k) {
+          const int it = t + k * nt;
+          int row, ch;
+          if (it < nxt.items) pre[k] = *reinterpret_cast<const V16*>(gsrc + seg_addr(nxt, it, row, ch));
+        }
+      }
+    }
+    const int gtile = tile_offset + u;
+    const int p0 = tile_start[gtile << sub_log2], p1 = tile_start[(gtile + 1) << sub_log2];
+    if (p1 > p0) {
+      const int tile = gtile - sd.tile_base;
+      const int tx = tile % Tn, ty = (tile / Tn) % sd.Tny, tz = tile / (Tn * sd.Tny);
+      const auto r0 = sorted[min(p0 + slot, p1 - 1)];
+      const int c0 = cells[min(p0 + slot, p1 - 1)];
+      const int i0 = perm[min(p0 + slot, p1 - 1)];
+      gather_tile<T, P, D, G>(sorted, cells, perm, p0, p1, tx * B, ty * B, tz * B, S, tb, recs, lcoef, sd, out, r0,
+                              c0, i0, esum);
+    }
+    __syncthreads();  // every read of this tile's block is done
+    if (!more) break;
+    if (nxt.vec) {
+      // the segments not loaded ahead, their loads issued before the stores of those that were
+      V16 rest[kStreamChunks - kStreamAhead];
+#pragma unroll
+      for (int k = kStreamAhead; k < kStreamChunks; ++k) {
+        const int it = t + k * nt;
+        int row, ch;
+        if (it < nxt.items) rest[k - kStreamAhead] = *reinterpret_cast<const V16*>(gsrc + seg_addr(nxt, it, row, ch));
+      }
+#pragma unroll
+      for (int k = 0; k < kStreamChunks; ++k) {
+        const int it = t + k * nt;
+        int row, ch;
+        if (it < nxt.items) {
+          (void)seg_addr(nxt, it, row, ch);
+          seg_store(nxt, row, ch, k < kStreamAhead ? pre[k] : rest[k - kStreamAhead]);
+        }
+      }
+    } else {
+      stage_now(nxt);
+    }
+    __syncthreads();
+    u = un;
+    cur = nxt;
+  }
+  if (energy) gather_energy(esum, s_red, energy);
+}
+
 template <class T, int P, int D>
 hipError_t spread_impl(const DevPlan& d, const PGroup& g, hipStream_t st) {
   auto cols = [&](auto kern, int threads) {
@@ -1101,6 +1268,15 @@ hipError_t gather_impl(const DevPlan& d, const PGroup& g, const void* grid, void
       launch(k_gather<T, P, D, float>);
       return hipGetLastError();
     }
+  } else {
+    if (g.gather_stream > 0) {
+      hipLaunchKernelGGL((k_gather_stream<T, P, D, double>), dim3(g.gather_stream), dim3(g.gather_threads),
+                         g.lds_gather, st, static_cast<const typename Vec4<T>::type*>(d.sorted), d.cells, d.perm,
+                         d.tile_start, d.sub_log2, d.sys_dev, g.tile_begin, g.tile_end - g.tile_begin,
+                         static_cast<const T*>(grid), static_cast<T*>(phi), static_cast<T*>(vec), vec_mode,
+                         add_self ? 1 : 0, energy, phi_add, vec_add);
+      return hipGetLastError();
+    }
   }
   launch(k_gather<T, P, D, double>);
   return hipGetLastError();
@@ -1164,6 +1340,20 @@ hipError_t prepare_impl(PGroup& g) {
   };
   e = resident(spread_fn, g.spread_threads, g.lds_spread, &g.xcd_spread);
   if (e == hipSuccess) e = resident(gather_fn, g.gather_threads, g.lds_gather, &g.xcd_gather);
+  // the tile-sequence interpolation (float64; asked for by the plan with gather_stream = -1): as
+  // many workgroups as are resident at once, a multiple of the 8 XCDs
+  if (e == hipSuccess && g.gather_stream < 0) {
+    g.gather_stream = 0;
+    if constexpr (std::is_same_v<T, double>) {
+      const void* fn = reinterpret_cast<const void*>(&k_gather_stream<T, P, D, double>);
+      if (g.lds_gather > 64 * 1024)
+        e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(g.lds_gather));
+      int per_cu = 0;
+      if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, g.gather_threads, g.lds_gather);
+      const int64_t resident_wg = static_cast<int64_t>(per_cu) * cus / 8 * 8;
+      if (e == hipSuccess && resident_wg >= 8 && resident_wg < grid) g.gather_stream = static_cast<int>(resident_wg);
+    }
+  }
   return e;
 }
 

@@ -347,6 +347,46 @@ def test_interpolate_matches_oracle(case, prec):
              coef, eps, prec, vec_is_force=False, global_part=False)
 
 
+STREAM_CASES = [
+    # float64 systems of more tiles (512, 729) than workgroups resident at once, so that the
+    # interpolation by tile sequences applies; tiles at the x ends wrap around the grid
+    ("uniform_m64_eps1e-10", lambda: W.uniform_pm1(4000, seed=41), 1e-10, dict(m=64)),
+    ("clustered_m72_eps1e-10", lambda: W.clustered(5000, seed=42, L=1.1), 1e-10, dict(m=72)),
+]
+
+
+@pytest.mark.parametrize("case", STREAM_CASES, ids=[c[0] for c in STREAM_CASES])
+def test_interpolation_by_tile_sequences_matches_oracle(case, monkeypatch):
+    """Step 5 by workgroups that each take a sequence of tiles, loading the next tile's block
+    while interpolating the current one (PSWFE_GATHER_STREAM=1): on a given grid against the
+    oracle (per-particle local bound), and in the whole pipeline equal, particle by particle, to
+    the one-tile-per-workgroup kernel to rounding (the same sums over the same block values; the
+    grids of the two runs differ in the order of the spread's float64 atomic adds, and the
+    energy in its order of summation)."""
+    _, gen, eps, kw = case
+    prec = "fp64"
+    x, q, L, kw = _sys(gen, eps, kw, prec)
+    c, o = both_params(eps, L, **kw)
+    monkeypatch.setenv("PSWFE_GATHER_STREAM", "1")
+    plan = pw.Plan(c, prec, n_max=len(q))
+    rng = np.random.Generator(np.random.PCG64(9))
+    b = rng.standard_normal((o.m, o.m, o.m))                             # [z, y, x]
+    phi, g = plan.interpolate(tdev(x, prec), tdev(b, prec))
+    rphi, rg = fast.interpolate(b.transpose(2, 1, 0), np.mod(x, L), o)
+    coef = pw.host_tables(c, prec)["coef"]
+    EW.check(f"interpolate-stream-{case[0]}", phi.cpu().numpy(), g.cpu().numpy(), q, rphi, rg, rphi,
+             b.transpose(2, 1, 0), np.mod(x, L), o, coef, eps, prec, vec_is_force=False, global_part=False)
+    X, Q = tdev(x, prec), tdev(q, prec)
+    p1, F1, E1 = plan.compute(X, Q)
+    monkeypatch.setenv("PSWFE_GATHER_STREAM", "0")
+    ref = pw.Plan(c, prec, n_max=len(q))
+    p0, F0, E0 = ref.compute(X, Q)
+    p0, p1, F0, F1 = (t.cpu().numpy() for t in (p0, p1, F0, F1))
+    assert np.max(np.abs(p1 - p0)) <= 1e-12 * np.max(np.abs(p0))
+    assert np.max(np.abs(F1 - F0)) <= 1e-12 * np.max(np.abs(F0))
+    assert abs(float(E1.cpu()[0]) - float(E0.cpu()[0])) <= 1e-13 * float(np.abs(q) @ np.abs(p0))
+
+
 @pytest.mark.parametrize("levels", ["1", "2"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp32_arith", "fp32_arith_grid32"])
 @pytest.mark.parametrize("case", SMALL, ids=[c[0] for c in SMALL])
