@@ -70,8 +70,8 @@ def stage_work(stage: str, n: int, m: int, P: int, deg: int, elem: int):
     raise KeyError(stage)
 
 
-STAGE_KERNEL = {"spread": ("k_spread", "k_spread_cols", "k_spread_mfma"), "gather": ("k_gather",), "fft_x": ("k_fft_x_r2c",),
-                "fft_y": ("k_fft_cols",), "fft_z_scale": ("k_fft_cols",), "ifft_y": ("k_fft_cols",),
+STAGE_KERNEL = {"spread": ("k_spread", "k_spread_cols", "k_spread_mfma"), "gather": ("k_gather", "k_gather_stream"), "fft_x": ("k_fft_x_r2c",),
+                "fft_y": ("k_fft_cols",), "fft_z_scale": ("k_fft_cols", "k_fft_yz"), "ifft_y": ("k_fft_cols",),
                 "ifft_x": ("k_fft_x_c2r",),
                 # one-level sort (count, scan, scatter) or two-level sort (count, coarse, fine)
                 "bin": ("k_bin_count1", "k_bin_scatter1", "k_bin_count", "k_bin_coarse", "k_bin_fine")}
@@ -99,7 +99,7 @@ def _profile_blob(path, workload: str = "water_box_n30000"):
 
 # kernels with a template argument for the type of their window arithmetic, and its position:
 # k_spread_mfma<T, P, D, B, A, column form>, k_gather<T, P, D, G>
-ARITH_ARG = {"k_spread_mfma": 4, "k_gather": 3}
+ARITH_ARG = {"k_spread_mfma": 4, "k_gather": 3, "k_gather_stream": 3}
 
 
 def _stage_kernels(blob_keys, stage: str, prec: str):
