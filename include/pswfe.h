@@ -66,7 +66,8 @@ typedef enum {
 /* Plan precision. PSWFE_FP32: float32 inputs, grids and outputs, with window values, products and
  * per-tile sums in float64 (error about 1e-8 relative from the arithmetic). PSWFE_FP32_ARITH: the
  * same float32 storage, with window values, products and sums in float32 in spreading (on the
- * float32 matrix cores) and interpolation; tiles are still added into a float64 grid, and the self
+ * float32 matrix cores) and interpolation; tiles are added into a float64 grid, or, on grids of
+ * 2^20 points and more over all systems, into a float32 grid with float32 atomic adds; the self
  * term and energy are float64 (for eps >= 1e-6: about 3e-7 relative on systems of neutral
  * molecules, where grid values cancel). PSWFE_FP64: float64 throughout. */
 typedef enum { PSWFE_FP32 = 0, PSWFE_FP64 = 1, PSWFE_FP32_ARITH = 2 } pswfe_prec;
